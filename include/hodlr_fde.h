@@ -1,0 +1,203 @@
+/* hodlr_fde.h -- C ABI of the MI355X (gfx950) HODLR solver for space-fractional
+ * diffusion equations (Massei, Mazza, Robol: "Fast solvers for two-dimensional
+ * fractional diffusion equations using rank structured matrices").
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Return value: hodlr_status, 0 == HODLR_OK.  Negative values are
+ *   host-detected errors (nothing was enqueued); positive values are
+ *   numerical conditions reported by the device (valid after the call
+ *   returns, since every entry point that reports them synchronises its
+ *   stream before returning).
+ * - No C++ exception crosses this boundary.
+ * - Pointers documented "device" must point to device memory of the current
+ *   HIP device (e.g. a torch tensor's data_ptr()).  Pointers documented
+ *   "host" are ordinary host memory.
+ * - Matrices are column-major, 0-based.  A "batch" is a set of independent
+ *   problems whose vectors are concatenated: problem i owns rows
+ *   offsets[i] .. offsets[i+1]-1 of every vector argument.
+ * - Ownership: the caller owns every buffer it passes.  Handles own the
+ *   device memory they allocate (tree plan, compressed operator, factors,
+ *   scratch), released by the matching *_destroy.  *_destroy(NULL) is a no-op.
+ * - Streams: a context wraps one hipStream_t supplied by the caller (NULL =
+ *   the legacy default stream); all work is enqueued on it.  One context
+ *   must not be used from two host threads at once.
+ */
+#ifndef HODLR_FDE_H
+#define HODLR_FDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HODLR_OK = 0,
+  HODLR_EINVAL = -1,     /* bad argument; hodlr_last_arg() names it (1-based) */
+  HODLR_ENOMEM = -2,     /* device allocation failed */
+  HODLR_EHIP = -3,       /* a HIP runtime call failed */
+  HODLR_ESTATE = -5,     /* call out of order (e.g. solve before factor) */
+  HODLR_ESINGULAR = 1,   /* zero or non-finite pivot in a leaf LU */
+  HODLR_ENOCONV = 2,     /* refinement missed rtol; the FP64 fallback result is returned */
+  HODLR_ERANK = 3        /* a rank cap truncated above the tolerance */
+} hodlr_status;
+
+typedef enum {
+  HODLR_FP64 = 0,        /* factors stored and applied in FP64 */
+  HODLR_MIXED_FP32 = 1,  /* low-rank factors + leaf inverses stored in FP32, FP64 refinement */
+  HODLR_MIXED_BF16 = 2   /* low-rank factors in BF16, leaf inverses FP32, FP64 refinement */
+} hodlr_precision;
+
+typedef struct hodlr_ctx_s* hodlr_ctx;
+typedef struct hodlr_mat_s* hodlr_mat;
+typedef struct fde2d_plan_s* fde2d_plan;
+
+/* One 1D operator (Sec. 2.2.1, eq. (system_FD)):
+ *   M = shift*I + nu*(D+ T_alpha + D- T_alpha^T),   nu = dt / dx^alpha,
+ * with T_alpha the lower Hessenberg Toeplitz matrix of Grunwald-Letnikov
+ * weights (eq. (toeplitz_FD)).  shift = 1 for the 1D implicit Euler step;
+ * shift = 1/2 (+ an ADI shift) for the coefficients of the 2D Sylvester
+ * step (eq. (sylv-timestepping)). */
+typedef struct {
+  int64_t n;              /* interior grid points N >= 1 (eq. (part)) */
+  double alpha;           /* fractional order, 1 <= alpha <= 2 */
+  double dt, dx;          /* time step and grid spacing; nu = dt/dx^alpha */
+  double shift;           /* identity shift s > 0 */
+  const double* d_plus;   /* device, n samples d+(x_i) >= 0 */
+  const double* d_minus;  /* device, n samples d-(x_i) >= 0 */
+} fde_operator;
+
+typedef struct {
+  int leaf;               /* maximal leaf size b, 16 <= b <= 64 ("minimal dimension", Sec. 3.4.1) */
+  double tol;             /* truncation tolerance eps: blocks are truncated at eps*||M||_2 (Sec. 3.4.1) */
+  int prec;               /* hodlr_precision used by hodlr_solve */
+  int max_rank;           /* cap on every off-diagonal rank, <= 32 */
+  int refine_max;         /* max FP64 refinement sweeps per solve (any precision; 0 = plain solve) */
+  double rtol;            /* refinement target ||b - M x||_2 / ||b||_2 */
+} hodlr_opts;
+
+typedef struct {
+  int status;             /* worst hodlr_status seen by the device */
+  int refine_iters;       /* refinement sweeps taken (max over problems) */
+  double rel_residual;    /* max over problems of ||b - M x||_2/||b||_2 after the call (mixed modes) */
+  int max_rank;           /* largest off-diagonal rank of the factors */
+  int leaf;               /* problem index of a singular leaf (ESINGULAR), else -1 */
+  int row;                /* leaf index of that leaf, else -1 */
+  int used_fallback;      /* 1 if any problem fell back to the FP64 factors */
+} hodlr_info;
+
+typedef struct {
+  int batch;              /* number of operators */
+  int leaf;               /* leaf size b */
+  int max_levels;         /* deepest tree */
+  int64_t total_n;        /* sum of n */
+  int max_rank_A;         /* rank of the compressed off-diagonal blocks of M */
+  int max_rank_factors;   /* rank of the LU factor blocks (0 before hodlr_factor) */
+  size_t bytes_factors;   /* bytes read by one single-RHS solve at the chosen precision */
+  size_t bytes_device;    /* device memory held by the handle */
+} hodlr_mat_info;
+
+/* ---- context ------------------------------------------------------------ */
+hodlr_status hodlr_ctx_create(hodlr_ctx* ctx, void* hip_stream);
+void hodlr_ctx_destroy(hodlr_ctx ctx);
+int hodlr_last_arg(hodlr_ctx ctx);
+const char* hodlr_status_string(hodlr_status s);
+hodlr_status hodlr_default_opts(hodlr_opts* opts);
+
+/* ---- 1D: build, factor, solve (Sec. 3.4, Sec. 3.5) ----------------------
+ * hodlr_build compresses each operator into HODLR form: the Grunwald-
+ * Letnikov weights g_k (recursion of Sec. 3.4.2), an ACA of the top-level
+ * subdiagonal Toeplitz block (diagonally pivoted, which is a partial
+ * Cholesky because that block reversed is a PSD Hankel matrix, Lemma
+ * hadamard-product), every other off-diagonal block by restriction and
+ * diagonal scaling (Sec. 3.4.2), dense leaves straight from g.
+ * ops: host array of `batch` descriptors (their d+/d- pointers are device).
+ * The operators are copied; the caller may free d+/d- after the call.   */
+hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch,
+                         const hodlr_opts* opts, hodlr_mat* out);
+void hodlr_destroy(hodlr_mat m);
+hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info);
+
+/* y = M_H x with the compressed HODLR operator (Sec. 3.4.1).  x, y device,
+ * concatenated over the batch, nrhs columns with leading dimension ld. */
+hodlr_status hodlr_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y,
+                          int nrhs, int64_t ld);
+
+/* y = M x exactly (up to FFT rounding) through circulant embedding of the
+ * Toeplitz matrices (the FFT matrix-vector product of Sec. 3.4.2).  Used as
+ * the refinement residual.  Same layout as hodlr_matvec. */
+hodlr_status hodlr_toeplitz_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y,
+                                   int nrhs, int64_t ld);
+
+/* HODLR LU of every operator (Sec. 3.5): block LU with leaf partial pivoting,
+ * low-rank Schur-complement updates recompressed to the truncation
+ * tolerance, plus the HODLR inverses of both triangular factors. */
+hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info);
+
+/* x <- M^{-1} x for every problem and column (Sec. 3.5 back substitution,
+ * applied through the HODLR inverses of the triangular factors).  With
+ * opts.refine_max > 0 the solve is followed by FP64 iterative refinement whose
+ * residual is hodlr_toeplitz_matvec, until ||b - M x||_2/||b||_2 <= rtol; a
+ * mixed-precision solve that stalls falls back to the FP64 factors (status
+ * HODLR_ENOCONV, info->used_fallback = 1).  x: device, ld >= total n.
+ * info: host, may be NULL. */
+hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_t ld,
+                         hodlr_info* info);
+
+/* Implicit Euler time stepping (eq. (system_FD)):  u <- M^{-1}(u + fscale*f),
+ * `steps` times, for every problem of the batch at once (fscale = dt for the
+ * scheme of eq. (system_FD) with a time-independent source).  u, f device
+ * (concatenated, one column); f may be NULL (f = 0).  The per-step kernel
+ * sequence (right-hand side, low-precision solve, refine_max refinement
+ * sweeps in the mixed modes) is captured once into a HIP graph and replayed.
+ * info->rel_residual reports the last step's ||b - M u||_2/||b||_2. */
+hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const double* f,
+                              double fscale, int steps, hodlr_info* info);
+
+/* ---- 2D: per-step Sylvester equation (Sec. 4.2-4.3) ----------------------
+ * A U + U B^T = C with A = 1/2 I + nu_x(D1+ T + D1- T^T) (x direction),
+ * B = 1/2 I + nu_y(...) (y direction), C = U_m + dt F (eq. (sylv-timestepping)).
+ * Solved by factored ADI with shifted HODLR solves: the plan builds and
+ * factors A + q_j I and B + p_j I for J shift pairs chosen from the spectral
+ * intervals (FP64).  Low-rank matrices are X = Z W^T, device, column-major. */
+typedef struct {
+  int64_t rows;           /* rows of Z (nx) -- W has ny rows */
+  int rank;               /* columns in use */
+  int capacity;           /* allocated columns (outputs: max rank accepted) */
+  int64_t ldz, ldw;       /* leading dimensions */
+  double* Z;              /* device */
+  double* W;              /* device */
+} lr_matrix;
+
+typedef struct {
+  double tol;             /* stop when ||C - A X - X B^T||_F <= tol * ||C||_F */
+  int max_shifts;         /* cap on J */
+  int max_rank;           /* cap on the rank of the solution factors */
+} fde2d_opts;
+
+hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
+                               const hodlr_opts* hopts, const fde2d_opts* opts, fde2d_plan* out);
+void fde2d_plan_destroy(fde2d_plan p);
+int fde2d_plan_shifts(fde2d_plan p, double* p_shifts, double* q_shifts, int cap);
+
+/* One implicit Euler step: U_next = solution of A X + X B^T = U_m + dt F.
+ * U_m, F: inputs (ranks may be 0).  U_next: caller-allocated factors with
+ * `capacity` columns; on return U_next->rank holds the rank used.
+ * X0 (optional, may be NULL): device dense nx x ny warm start (ld = nx);
+ * the step then solves for the correction from the residual of X0 and
+ * returns U_next as the low-rank correction added to X0 in `X0_out`
+ * (device nx x ny, may alias X0).  rel_residual in info reports the exact
+ * low-rank residual ||C - A X - X B^T||_F / ||C||_F. */
+hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* U_m,
+                                  const lr_matrix* F, double dt, lr_matrix* U_next,
+                                  hodlr_info* info);
+hodlr_status fde2d_sylvester_step_dense(hodlr_ctx ctx, fde2d_plan p, const double* X0,
+                                        const double* C, double* X_out, int64_t ld,
+                                        int max_sweeps, double tol, hodlr_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HODLR_FDE_H */

@@ -1,0 +1,780 @@
+// Host side of the C ABI: planning of the HODLR trees, device memory,
+// kernel launches, refinement policy and the graph-captured time loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+
+
+using namespace hfde;
+
+struct hodlr_ctx_s {
+  hipStream_t stream;
+  int last_arg;
+};
+
+namespace {
+
+constexpr int kNCF = 16;     // columns per FFT launch group
+constexpr int kNCS = 16;     // columns per multi-column solve launch
+constexpr int kFftSmallMax = 13;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct hodlr_mat_s {
+  hodlr_ctx ctx = nullptr;
+  hodlr_opts opts{};
+  int batch = 0;
+  int b = 0;
+  int Lmax = 0;
+  int64_t total_n = 0;
+  int64_t total_leaves = 0;
+  int64_t total_nodes = 0;
+  std::vector<Item> items;
+  std::vector<Node> nodes;
+  std::vector<WorkUnit> wu_h;
+  std::vector<NodeUnit> nu_h;
+  DevPtrs P{};
+  std::vector<void*> allocs;
+  size_t bytes_device = 0;
+  WorkUnit* wu = nullptr;
+  NodeUnit* nu = nullptr;
+  int nwu = 0, nnu = 0;
+  // FFT work lists per column count
+  std::vector<int> small_items, big_items;
+  FftUnit* fft_small_units = nullptr;   // (item, col) for col < kNCF
+  int n_fft_small = 0;
+  FftUnit* fft_p1_units = nullptr;
+  int n_fft_p1 = 0;
+  FftUnit* fft_p2_units = nullptr;
+  int n_fft_p2 = 0;
+  // solve scratch
+  double* partL = nullptr;
+  double* partU = nullptr;
+  double* zL = nullptr;
+  double* zU = nullptr;
+  double* ytmp = nullptr;     // total_n x kNCS
+  double* rbuf = nullptr;     // total_n x kNCS
+  double* dbuf = nullptr;
+  double* bbuf = nullptr;
+  double* norms = nullptr;    // batch x kNCS x 2
+  bool factored = false;
+  int max_rank_factors = 0;
+  int max_rank_A = 0;
+  // low precision copies
+  float* IL32 = nullptr;
+  float* IU32 = nullptr;
+  float* LUinv32 = nullptr;
+  bf16* IL16 = nullptr;
+  bf16* IU16 = nullptr;
+  // graph of one time step
+  hipGraphExec_t step_graph = nullptr;
+  const double* graph_u = nullptr;
+  const double* graph_f = nullptr;
+  int graph_sweeps = -1;
+  double graph_fscale = 0.0;
+};
+
+struct fde2d_plan_s {
+  int dummy;
+};
+
+namespace {
+
+hodlr_status set_arg(hodlr_ctx ctx, int idx) {
+  if (ctx) ctx->last_arg = idx;
+  return HODLR_EINVAL;
+}
+
+#define HIP_TRY(expr)                                 \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) {                           \
+      fprintf(stderr, "hodlr_fde: %s failed: %s\n", #expr, hipGetErrorString(e_)); \
+      return HODLR_EHIP;                              \
+    }                                                 \
+  } while (0)
+
+template <typename T>
+hodlr_status dalloc(hodlr_mat m, T** p, size_t count) {
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) return HODLR_ENOMEM;
+  m->allocs.push_back(q);
+  m->bytes_device += bytes;
+  *p = static_cast<T*>(q);
+  return HODLR_OK;
+}
+
+#define TRY(expr)                      \
+  do {                                 \
+    hodlr_status s_ = (expr);          \
+    if (s_ != HODLR_OK) return s_;     \
+  } while (0)
+
+int levels_for(int64_t n, int b) {
+  int L = 0;
+  while ((n + (int64_t(1) << L) - 1) >> L > b) ++L;
+  return L;
+}
+
+void build_nodes(int64_t n, int L, std::vector<Node>& out) {
+  size_t base = out.size();
+  out.resize(base + ((size_t(1) << (L + 1)) - 1));
+  out[base] = Node{0, int32_t(n)};
+  for (int d = 0; d < L; ++d) {
+    for (int64_t j = 0; j < (int64_t(1) << d); ++j) {
+      const Node p = out[base + ((size_t(1) << d) - 1) + j];
+      const int32_t n1 = p.size / 2;
+      out[base + ((size_t(1) << (d + 1)) - 1) + 2 * j] = Node{p.start, n1};
+      out[base + ((size_t(1) << (d + 1)) - 1) + 2 * j + 1] = Node{p.start + n1, p.size - n1};
+    }
+  }
+}
+
+void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int64_t ldy, const double* b,
+                       int64_t ldb, int nc, hipStream_t s) {
+  // columns in groups of kNCF
+  for (int c0 = 0; c0 < nc; c0 += kNCF) {
+    const int cn = std::min(kNCF, nc - c0);
+    const double* xc = x + int64_t(c0) * ldx;
+    double* yc = y + int64_t(c0) * ldy;
+    const double* bc = b ? b + int64_t(c0) * ldb : nullptr;
+    if (m->n_fft_small) {
+      // units are laid out column-major: first all items for col 0, then col 1 ...
+      int cnt = int(m->small_items.size()) * cn;
+      size_t lds = 0;
+      int maxlog = 0;
+      for (int i : m->small_items) maxlog = std::max(maxlog, m->items[i].fftlog);
+      lds = (size_t(1) << maxlog) * sizeof(double2);
+      hipLaunchKernelGGL(k_fft_small, dim3(cnt), dim3(512), lds, s, m->P, m->fft_small_units, 1, xc, ldx, yc,
+                         ldy, bc, ldb);
+    }
+    if (m->n_fft_p1) {
+      const int per_col1 = m->n_fft_p1 / kNCF, per_col2 = m->n_fft_p2 / kNCF;
+      const size_t lds = size_t(8192) * sizeof(double2);
+      hipLaunchKernelGGL(k_fft4_pass1, dim3(per_col1 * cn), dim3(512), lds, s, m->P, m->fft_p1_units, 1, false,
+                         xc, ldx);
+      hipLaunchKernelGGL(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, false,
+                         xc, ldx, yc, ldy, bc, ldb);
+      hipLaunchKernelGGL(k_fft4_pass1, dim3(per_col1 * cn), dim3(512), lds, s, m->P, m->fft_p1_units, 1, true,
+                         xc, ldx);
+      hipLaunchKernelGGL(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, true,
+                         xc, ldx, yc, ldy, bc, ldb);
+    }
+  }
+}
+
+template <typename TF, typename TL, int NC>
+void launch_solve_t(hodlr_mat m, SolveFactors<TF, TL> F, const double* x, int64_t ldx, double* y, int64_t ldy, int nc,
+                    hipStream_t s) {
+  const TF* IL = F.IL;
+  hipLaunchKernelGGL((k_project<TF, NC>), dim3(m->nwu), dim3(64), 0, s, m->P, m->wu, 0, IL, x, ldx, nc, m->partL,
+                     m->Lmax);
+  if (m->nnu) hipLaunchKernelGGL(k_reduce, dim3(m->nnu), dim3(64), 0, s, m->P, m->nu, 0, nc, m->partL, m->zL, m->Lmax);
+  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(m->nwu), dim3(64), 0, s, m->P, F, m->wu, 0, x, ldx, m->ytmp,
+                     m->total_n, nc, m->zL, m->partU, m->Lmax, m->b);
+  if (m->nnu) hipLaunchKernelGGL(k_reduce, dim3(m->nnu), dim3(64), 0, s, m->P, m->nu, 1, nc, m->partU, m->zU, m->Lmax);
+  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(m->nwu), dim3(64), 0, s, m->P, F, m->wu, 1, m->ytmp, m->total_n, y,
+                     ldy, nc, m->zU, (double*)nullptr, m->Lmax, m->b);
+}
+
+// y <- M_low^{-1} x at precision `prec` (x and y may alias: the first
+// expansion writes ytmp, the second reads only ytmp).
+void launch_solve(hodlr_mat m, int prec, const double* x, int64_t ldx, double* y, int64_t ldy, int nc,
+                  hipStream_t s) {
+  for (int c0 = 0; c0 < nc; c0 += kNCS) {
+    const int cn = std::min(kNCS, nc - c0);
+    const double* xc = x + int64_t(c0) * ldx;
+    double* yc = y + int64_t(c0) * ldy;
+    if (prec == HODLR_MIXED_FP32) {
+      SolveFactors<float, float> F{m->IL32, m->IU32, m->LUinv32};
+      if (cn == 1) launch_solve_t<float, float, 1>(m, F, xc, ldx, yc, ldy, cn, s);
+      else launch_solve_t<float, float, kNCS>(m, F, xc, ldx, yc, ldy, cn, s);
+    } else if (prec == HODLR_MIXED_BF16) {
+      SolveFactors<bf16, float> F{m->IL16, m->IU16, m->LUinv32};
+      if (cn == 1) launch_solve_t<bf16, float, 1>(m, F, xc, ldx, yc, ldy, cn, s);
+      else launch_solve_t<bf16, float, kNCS>(m, F, xc, ldx, yc, ldy, cn, s);
+    } else {
+      SolveFactors<double, double> F{m->P.IL, m->P.IU, m->P.LUinv};
+      if (cn == 1) launch_solve_t<double, double, 1>(m, F, xc, ldx, yc, ldy, cn, s);
+      else launch_solve_t<double, double, kNCS>(m, F, xc, ldx, yc, ldy, cn, s);
+    }
+  }
+}
+
+void launch_norms(hodlr_mat m, const double* v, int64_t ld, int nc, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_item_norms, dim3(m->batch, nc), dim3(256), 0, s, m->P, v, ld, nc, out);
+}
+
+void launch_axpby(int64_t nrows, int nc, double a, const double* x, int64_t ldx, double bco, const double* y,
+                  int64_t ldy, double* z, int64_t ldz, hipStream_t s) {
+  const int64_t tot = nrows * nc;
+  const int blocks = int(std::min<int64_t>((tot + 255) / 256, 65535));
+  hipLaunchKernelGGL(k_axpby, dim3(blocks), dim3(256), 0, s, nrows, nc, a, x, ldx, bco, y, ldy, z, ldz);
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+const char* hodlr_status_string(hodlr_status s) {
+  switch (s) {
+    case HODLR_OK: return "ok";
+    case HODLR_EINVAL: return "invalid argument";
+    case HODLR_ENOMEM: return "device allocation failed";
+    case HODLR_EHIP: return "HIP runtime error";
+    case HODLR_ESTATE: return "call out of order";
+    case HODLR_ESINGULAR: return "singular leaf pivot";
+    case HODLR_ENOCONV: return "refinement did not converge (FP64 fallback used)";
+    case HODLR_ERANK: return "rank cap reached above tolerance";
+  }
+  return "unknown status";
+}
+
+hodlr_status hodlr_ctx_create(hodlr_ctx* ctx, void* hip_stream) {
+  if (!ctx) return HODLR_EINVAL;
+  hodlr_ctx c = new (std::nothrow) hodlr_ctx_s;
+  if (!c) return HODLR_ENOMEM;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->last_arg = 0;
+  *ctx = c;
+  return HODLR_OK;
+}
+
+void hodlr_ctx_destroy(hodlr_ctx ctx) { delete ctx; }
+
+int hodlr_last_arg(hodlr_ctx ctx) { return ctx ? ctx->last_arg : 0; }
+
+hodlr_status hodlr_default_opts(hodlr_opts* o) {
+  if (!o) return HODLR_EINVAL;
+  o->leaf = 64;
+  o->tol = 1e-10;
+  o->prec = HODLR_FP64;
+  o->max_rank = 32;
+  o->refine_max = 0;
+  o->rtol = 1e-12;
+  return HODLR_OK;
+}
+
+void hodlr_destroy(hodlr_mat m) {
+  if (!m) return;
+  if (m->step_graph) (void)hipGraphExecDestroy(m->step_graph);
+  for (void* p : m->allocs) (void)hipFree(p);
+  delete m;
+}
+
+static hodlr_status set_lds_limits() {
+  static bool done = false;
+  if (done) return HODLR_OK;
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(kFactorLdsBytes)));
+  const int fl = int(size_t(kFftLds) * sizeof(double2));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_small),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, fl));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft4_pass1),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, fl));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft4_pass2),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, fl));
+  done = true;
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, const hodlr_opts* opts,
+                         hodlr_mat* out) {
+  if (!ctx) return HODLR_EINVAL;
+  TRY(set_lds_limits());
+  if (!ops) return set_arg(ctx, 2);
+  if (batch < 1) return set_arg(ctx, 3);
+  if (!opts) return set_arg(ctx, 4);
+  if (!out) return set_arg(ctx, 5);
+  if (opts->leaf < 16 || opts->leaf > kMaxLeaf) return set_arg(ctx, 4);
+  if (!(opts->tol > 0.0) || opts->max_rank < 1 || opts->max_rank > kRS) return set_arg(ctx, 4);
+  if (opts->prec < HODLR_FP64 || opts->prec > HODLR_MIXED_BF16) return set_arg(ctx, 4);
+  for (int i = 0; i < batch; ++i) {
+    const fde_operator& o = ops[i];
+    if (o.n < 1 || o.n > (int64_t(1) << 30) || !(o.alpha >= 1.0 && o.alpha <= 2.0) || !(o.dt > 0.0) ||
+        !(o.dx > 0.0) || !(o.shift > 0.0) || !o.d_plus || !o.d_minus)
+      return set_arg(ctx, 2);
+  }
+  hodlr_mat m = new (std::nothrow) hodlr_mat_s;
+  if (!m) return HODLR_ENOMEM;
+  m->ctx = ctx;
+  m->opts = *opts;
+  m->batch = batch;
+  m->b = opts->leaf;
+  hipStream_t s = ctx->stream;
+  // ---- plan
+  int64_t row0 = 0, leaf0 = 0, node0 = 0, lvl0 = 0, g0 = 0, w0 = 0, z0 = 0, tw0 = 0, ws0 = 0;
+  for (int i = 0; i < batch; ++i) {
+    const fde_operator& o = ops[i];
+    Item it{};
+    it.n = o.n;
+    it.row0 = row0;
+    it.L = levels_for(o.n, m->b);
+    it.leaf0 = leaf0;
+    it.node0 = node0;
+    it.lvl0 = lvl0;
+    it.g0 = g0;
+    it.nh = (o.n + 1) / 2;
+    it.w0 = w0;
+    it.z0 = z0;
+    it.alpha = o.alpha;
+    it.nu = o.dt / std::pow(o.dx, o.alpha);
+    it.shift = o.shift;
+    int flog = 1;
+    while ((int64_t(1) << flog) < 2 * o.n - 1) ++flog;
+    it.fftlog = flog;
+    it.band = int(std::min<int64_t>(64, o.n - 1));
+    it.tw0 = tw0;
+    it.mu0 = tw0;   // mu shares the offsets of the twiddle table (separate array)
+    it.ws0 = ws0;
+    m->items.push_back(it);
+    build_nodes(o.n, it.L, m->nodes);
+    row0 += o.n;
+    leaf0 += int64_t(1) << it.L;
+    node0 += (int64_t(1) << (it.L + 1)) - 1;
+    lvl0 += int64_t(it.L + 1) * o.n * kRS;
+    g0 += o.n + 8;
+    w0 += it.nh * kRS;
+    z0 += (int64_t(1) << it.L) * kRS * 64;
+    tw0 += int64_t(1) << flog;
+    ws0 += 2 * (int64_t(1) << flog) * kNCF;
+    m->Lmax = std::max(m->Lmax, it.L);
+  }
+  m->total_n = row0;
+  m->total_leaves = leaf0;
+  m->total_nodes = node0;
+  std::vector<int32_t> rowleaf(row0);
+  for (int i = 0; i < batch; ++i) {
+    const Item& it = m->items[i];
+    for (int64_t l = 0; l < (int64_t(1) << it.L); ++l) {
+      const Node nd = m->nodes[node_index(it, it.L, l)];
+      for (int32_t r = 0; r < nd.size; ++r) rowleaf[it.row0 + nd.start + r] = int32_t(l);
+      m->wu_h.push_back(WorkUnit{i, int32_t(l)});
+    }
+    for (int d = 0; d < it.L; ++d)
+      for (int64_t j = 0; j < (int64_t(1) << d); ++j) m->nu_h.push_back(NodeUnit{i, d, int32_t(j), 0});
+  }
+  m->nwu = int(m->wu_h.size());
+  m->nnu = int(m->nu_h.size());
+  const int b = m->b;
+  // ---- allocate
+  DevPtrs& P = m->P;
+  hodlr_status st;
+#define ALLOC(ptr, cnt)                                   \
+  do {                                                    \
+    st = dalloc(m, &(ptr), (cnt));                        \
+    if (st != HODLR_OK) { hodlr_destroy(m); return st; }  \
+  } while (0)
+  ALLOC(P.items, batch);
+  ALLOC(P.nodes, m->nodes.size());
+  ALLOC(P.rowleaf, row0);
+  ALLOC(P.g, g0);
+  ALLOC(P.W, w0);
+  ALLOC(P.dplus, row0);
+  ALLOC(P.dminus, row0);
+  const size_t leafsz = size_t(leaf0) * b * b;
+  ALLOC(P.Aleaf, leafsz);
+  ALLOC(P.LU, leafsz);
+  ALLOC(P.LUinv, leafsz);
+  ALLOC(P.perm, size_t(leaf0) * b);
+  ALLOC(P.perminv, size_t(leaf0) * b);
+  ALLOC(P.XL, lvl0);
+  ALLOC(P.XR, lvl0);
+  ALLOC(P.FL, lvl0);
+  ALLOC(P.FU, lvl0);
+  ALLOC(P.IL, lvl0);
+  ALLOC(P.IU, lvl0);
+  ALLOC(P.T1, std::max<int64_t>(lvl0, w0));
+  ALLOC(P.T2, lvl0);
+  ALLOC(P.PP, lvl0);
+  ALLOC(P.PQ, lvl0);
+  ALLOC(P.Z, z0);
+  ALLOC(P.rankL, node0);
+  ALLOC(P.rankU, node0);
+  ALLOC(P.tw, tw0);
+  ALLOC(P.mu, tw0);
+  ALLOC(P.fws, ws0);
+  ALLOC(P.status, batch);
+  ALLOC(P.diag, 4 * batch);
+  ALLOC(m->wu, m->nwu);
+  ALLOC(m->nu, m->nnu);
+  const int64_t part_sz = leaf0 * std::max(1, m->Lmax) * kRS * kNCS;
+  ALLOC(m->partL, part_sz);
+  ALLOC(m->partU, part_sz);
+  ALLOC(m->zL, 2 * node0 * kRS * kNCS);   // the operator matvec stores two sides per node
+  ALLOC(m->zU, 2 * node0 * kRS * kNCS);
+  ALLOC(m->ytmp, row0 * kNCS);
+  ALLOC(m->rbuf, row0 * kNCS);
+  ALLOC(m->dbuf, row0 * kNCS);
+  ALLOC(m->bbuf, row0 * kNCS);
+  ALLOC(m->norms, batch * kNCS * 2);
+  // FFT work lists
+  {
+    std::vector<FftUnit> us, u1, u2;
+    for (int i = 0; i < batch; ++i) {
+      if (m->items[i].fftlog <= kFftSmallMax) m->small_items.push_back(i);
+      else m->big_items.push_back(i);
+    }
+    for (int c = 0; c < kNCF; ++c)
+      for (int i : m->small_items) us.push_back(FftUnit{i, c, 0, 0});
+    for (int c = 0; c < kNCF; ++c)
+      for (int i : m->big_items) {
+        const int lg = m->items[i].fftlog;
+        const int l2 = lg / 2, l1 = lg - l2;
+        int T = std::min(16, 8192 >> l1);
+        for (int t = 0; t < (1 << l1) / T; ++t) u1.push_back(FftUnit{i, c, t, 0});
+        for (int t = 0; t < (1 << l2) / T; ++t) u2.push_back(FftUnit{i, c, t, 0});
+      }
+    m->n_fft_small = int(m->small_items.size());
+    m->n_fft_p1 = int(u1.size());
+    m->n_fft_p2 = int(u2.size());
+    ALLOC(m->fft_small_units, us.size());
+    ALLOC(m->fft_p1_units, u1.size());
+    ALLOC(m->fft_p2_units, u2.size());
+    if (!us.empty()) HIP_TRY(hipMemcpy(m->fft_small_units, us.data(), us.size() * sizeof(FftUnit), hipMemcpyHostToDevice));
+    if (!u1.empty()) HIP_TRY(hipMemcpy(m->fft_p1_units, u1.data(), u1.size() * sizeof(FftUnit), hipMemcpyHostToDevice));
+    if (!u2.empty()) HIP_TRY(hipMemcpy(m->fft_p2_units, u2.data(), u2.size() * sizeof(FftUnit), hipMemcpyHostToDevice));
+  }
+#undef ALLOC
+  HIP_TRY(hipMemcpy(P.items, m->items.data(), batch * sizeof(Item), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(P.nodes, m->nodes.data(), m->nodes.size() * sizeof(Node), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(P.rowleaf, rowleaf.data(), row0 * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m->wu, m->wu_h.data(), m->nwu * sizeof(WorkUnit), hipMemcpyHostToDevice));
+  if (m->nnu) HIP_TRY(hipMemcpy(m->nu, m->nu_h.data(), m->nnu * sizeof(NodeUnit), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemsetAsync(P.status, 0, batch * sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P.diag, 0, 4 * batch * sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P.rankL, 0, node0 * sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P.rankU, 0, node0 * sizeof(int32_t), s));
+  for (int i = 0; i < batch; ++i) {
+    const Item& it = m->items[i];
+    HIP_TRY(hipMemcpyAsync(P.dplus + it.row0, ops[i].d_plus, it.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(P.dminus + it.row0, ops[i].d_minus, it.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  // ---- device construction
+  hipLaunchKernelGGL(k_gl_weights, dim3(batch), dim3(1024), 0, s, P);
+  hipLaunchKernelGGL(k_hankel_aca, dim3(batch), dim3(512), 0, s, P, opts->tol);
+  for (int i = 0; i < batch; ++i) {
+    const Item& it = m->items[i];
+    if (it.L > 0)
+      hipLaunchKernelGGL(k_assemble_bases, dim3(unsigned((it.n + 255) / 256), it.L), dim3(256), 0, s, P, i);
+    hipLaunchKernelGGL(k_assemble_leaves, dim3(unsigned(int64_t(1) << it.L)), dim3(256), 0, s, P, i, b);
+    hipLaunchKernelGGL(k_twiddles, dim3(unsigned(std::min<int64_t>(((int64_t(1) << it.fftlog) + 255) / 256, 4096))),
+                       dim3(256), 0, s, P, i);
+  }
+  // far-field multipliers mu = FFT(c_far) -> lambda + i conj(lambda)
+  if (m->n_fft_small) {
+    int maxlog = 0;
+    for (int i : m->small_items) maxlog = std::max(maxlog, m->items[i].fftlog);
+    hipLaunchKernelGGL(k_fft_small, dim3(m->n_fft_small), dim3(512), (size_t(1) << maxlog) * sizeof(double2), s,
+                       P, m->fft_small_units, 0, (const double*)nullptr, 0, (double*)nullptr, 0,
+                       (const double*)nullptr, 0);
+  }
+  if (m->n_fft_p1) {
+    const size_t lds = size_t(8192) * sizeof(double2);
+    hipLaunchKernelGGL(k_fft4_pass1, dim3(m->n_fft_p1 / kNCF), dim3(512), lds, s, P, m->fft_p1_units, 0, false,
+                       (const double*)nullptr, 0);
+    hipLaunchKernelGGL(k_fft4_pass2, dim3(m->n_fft_p2 / kNCF), dim3(512), lds, s, P, m->fft_p2_units, 0, false,
+                       (const double*)nullptr, 0, (double*)nullptr, 0, (const double*)nullptr, 0);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(m->items.data(), P.items, batch * sizeof(Item), hipMemcpyDeviceToHost));
+  for (const Item& it : m->items) m->max_rank_A = std::max(m->max_rank_A, it.r);
+  *out = m;
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info) {
+  if (!m || !info) return HODLR_EINVAL;
+  info->batch = m->batch;
+  info->leaf = m->b;
+  info->max_levels = m->Lmax;
+  info->total_n = m->total_n;
+  info->max_rank_A = m->max_rank_A;
+  info->max_rank_factors = m->max_rank_factors;
+  // bytes of one single-RHS solve: leaf inverses (both triangles) + both
+  // families of off-diagonal factors at their actual ranks
+  size_t bytes = 0;
+  if (m->factored) {
+    std::vector<int32_t> rl(m->total_nodes), ru(m->total_nodes);
+    (void)hipMemcpy(rl.data(), m->P.rankL, rl.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+    (void)hipMemcpy(ru.data(), m->P.rankU, ru.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+    const size_t fb = m->opts.prec == HODLR_FP64 ? 8 : (m->opts.prec == HODLR_MIXED_FP32 ? 4 : 4);
+    for (const Item& it : m->items) {
+      for (int d = 0; d < it.L; ++d)
+        for (int64_t j = 0; j < (int64_t(1) << d); ++j) {
+          const Node nd = m->nodes[node_index(it, d, j)];
+          const int64_t idx = node_index(it, d, j);
+          bytes += size_t(nd.size) * (rl[idx] + ru[idx]) * fb;
+        }
+      for (int64_t l = 0; l < (int64_t(1) << it.L); ++l) {
+        const Node nd = m->nodes[node_index(it, it.L, l)];
+        bytes += size_t(nd.size) * nd.size * fb;
+      }
+    }
+  }
+  info->bytes_factors = bytes;
+  info->bytes_device = m->bytes_device;
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y, int nrhs, int64_t ld) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!m) return set_arg(ctx, 2);
+  if (!x) return set_arg(ctx, 3);
+  if (!y) return set_arg(ctx, 4);
+  if (nrhs < 1) return set_arg(ctx, 5);
+  if (ld < m->total_n) return set_arg(ctx, 6);
+  hipStream_t s = ctx->stream;
+  for (int c0 = 0; c0 < nrhs; c0 += kNCS) {
+    const int cn = std::min(kNCS, nrhs - c0);
+    const double* xc = x + int64_t(c0) * ld;
+    double* yc = y + int64_t(c0) * ld;
+    hipLaunchKernelGGL(k_hmatvec_A_project, dim3(m->nwu), dim3(64), 0, s, m->P, m->wu, xc, ld, cn, m->partL,
+                       m->Lmax);
+    if (m->nnu)
+      hipLaunchKernelGGL(k_hmatvec_A_reduce, dim3(m->nnu), dim3(64), 0, s, m->P, m->nu, cn, m->partL, m->zL,
+                         m->Lmax);
+    hipLaunchKernelGGL(k_hmatvec_A_expand, dim3(m->nwu), dim3(64), 0, s, m->P, m->wu, xc, ld, yc, ld, cn, m->zL,
+                       m->b);
+  }
+  HIP_TRY(hipGetLastError());
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_toeplitz_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y, int nrhs, int64_t ld) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!m) return set_arg(ctx, 2);
+  if (!x) return set_arg(ctx, 3);
+  if (!y) return set_arg(ctx, 4);
+  if (nrhs < 1) return set_arg(ctx, 5);
+  if (ld < m->total_n) return set_arg(ctx, 6);
+  if (x == y) return set_arg(ctx, 4);
+  launch_fft_matvec(m, x, ld, y, ld, nullptr, 0, nrhs, ctx->stream);
+  HIP_TRY(hipGetLastError());
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!m) return set_arg(ctx, 2);
+  hipStream_t s = ctx->stream;
+  const size_t lds = kFactorLdsBytes;
+  hipLaunchKernelGGL(k_factor, dim3(m->batch), dim3(kWG), lds, s, m->P, m->b, m->opts.max_rank);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int32_t> stv(m->batch), dg(4 * m->batch);
+  HIP_TRY(hipMemcpy(stv.data(), m->P.status, m->batch * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(dg.data(), m->P.diag, 4 * m->batch * sizeof(int32_t), hipMemcpyDeviceToHost));
+  hodlr_status res = HODLR_OK;
+  int maxr = 0, badp = -1, badl = -1;
+  for (int i = 0; i < m->batch; ++i) {
+    maxr = std::max(maxr, dg[4 * i + 1]);
+    if ((stv[i] & 1) && badp < 0) { badp = i; badl = dg[4 * i]; }
+    if (stv[i] & 1) res = HODLR_ESINGULAR;
+    else if ((stv[i] & 4) && res == HODLR_OK) res = HODLR_ERANK;
+  }
+  m->max_rank_factors = maxr;
+  m->factored = true;
+  // low precision copies
+  if (m->opts.prec != HODLR_FP64) {
+    const int64_t lvl = int64_t(m->allocs.size());
+    (void)lvl;
+    int64_t nlvl = 0;
+    for (const Item& it : m->items) nlvl += int64_t(it.L + 1) * it.n * kRS;
+    const int64_t nleafv = m->total_leaves * m->b * m->b;
+    if (!m->LUinv32) {
+      TRY(dalloc(m, &m->LUinv32, nleafv));
+      TRY(dalloc(m, &m->IL32, nlvl));
+      TRY(dalloc(m, &m->IU32, nlvl));
+      if (m->opts.prec == HODLR_MIXED_BF16) {
+        TRY(dalloc(m, &m->IL16, nlvl));
+        TRY(dalloc(m, &m->IU16, nlvl));
+      }
+    }
+    hipLaunchKernelGGL(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.LUinv, m->LUinv32, nleafv);
+    hipLaunchKernelGGL(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.IL, m->IL32, nlvl);
+    hipLaunchKernelGGL(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.IU, m->IU32, nlvl);
+    if (m->opts.prec == HODLR_MIXED_BF16) {
+      hipLaunchKernelGGL(k_convert<bf16>, dim3(4096), dim3(256), 0, s, m->P.IL, m->IL16, nlvl);
+      hipLaunchKernelGGL(k_convert<bf16>, dim3(4096), dim3(256), 0, s, m->P.IU, m->IU16, nlvl);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->status = res;
+    info->max_rank = maxr;
+    info->leaf = badp;
+    info->row = badl;
+  }
+  return res;
+}
+
+hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_t ld, hodlr_info* info) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!m) return set_arg(ctx, 2);
+  if (!x) return set_arg(ctx, 3);
+  if (nrhs < 1) return set_arg(ctx, 4);
+  if (ld < m->total_n) return set_arg(ctx, 5);
+  if (!m->factored) return HODLR_ESTATE;
+  hipStream_t s = ctx->stream;
+  const int prec = m->opts.prec;
+  hodlr_status res = HODLR_OK;
+  int iters = 0;
+  double worst = 0.0;
+  bool fallback = false;
+  for (int c0 = 0; c0 < nrhs; c0 += kNCS) {
+    const int cn = std::min(kNCS, nrhs - c0);
+    double* xc = x + int64_t(c0) * ld;
+    const int64_t tn = m->total_n;
+    const bool refine = m->opts.refine_max > 0;
+    if (!refine) {
+      launch_solve(m, prec, xc, ld, xc, ld, cn, s);
+      continue;
+    }
+    // keep b
+    HIP_TRY(hipMemcpy2DAsync(m->bbuf, tn * sizeof(double), xc, ld * sizeof(double), tn * sizeof(double), cn,
+                             hipMemcpyDeviceToDevice, s));
+    launch_norms(m, m->bbuf, tn, cn, m->norms + m->batch * kNCS, s);
+    launch_solve(m, prec, m->bbuf, tn, xc, ld, cn, s);
+    std::vector<double> nr(m->batch * cn), nb(m->batch * cn);
+    HIP_TRY(hipMemcpyAsync(nb.data(), m->norms + m->batch * kNCS, nb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    double prev = 1e300;
+    bool conv = false;
+    for (int sweep = 0; sweep <= m->opts.refine_max; ++sweep) {
+      launch_fft_matvec(m, xc, ld, m->rbuf, tn, m->bbuf, tn, cn, s);
+      launch_norms(m, m->rbuf, tn, cn, m->norms, s);
+      HIP_TRY(hipMemcpyAsync(nr.data(), m->norms, nr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double rel = 0.0;
+      for (size_t q = 0; q < nr.size(); ++q) rel = std::max(rel, nb[q] > 0 ? std::sqrt(nr[q] / nb[q]) : 0.0);
+      worst = rel;
+      if (rel <= m->opts.rtol) { conv = true; break; }
+      if (sweep == m->opts.refine_max || rel > 0.9 * prev) break;   // budget spent or stalled
+      prev = rel;
+      launch_solve(m, prec, m->rbuf, tn, m->dbuf, tn, cn, s);
+      launch_axpby(tn, cn, 1.0, xc, ld, 1.0, m->dbuf, tn, xc, ld, s);
+      iters = std::max(iters, sweep + 1);
+    }
+    if (!conv && prec == HODLR_FP64) {
+      res = HODLR_ENOCONV;
+    } else if (!conv) {
+      // FP64 fallback: FP64 factors + refinement with the same residual
+      fallback = true;
+      launch_solve(m, HODLR_FP64, m->bbuf, tn, xc, ld, cn, s);
+      for (int sweep = 0; sweep < 3; ++sweep) {
+        launch_fft_matvec(m, xc, ld, m->rbuf, tn, m->bbuf, tn, cn, s);
+        launch_solve(m, HODLR_FP64, m->rbuf, tn, m->dbuf, tn, cn, s);
+        launch_axpby(tn, cn, 1.0, xc, ld, 1.0, m->dbuf, tn, xc, ld, s);
+      }
+      launch_fft_matvec(m, xc, ld, m->rbuf, tn, m->bbuf, tn, cn, s);
+      launch_norms(m, m->rbuf, tn, cn, m->norms, s);
+      HIP_TRY(hipMemcpyAsync(nr.data(), m->norms, nr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double rel = 0.0;
+      for (size_t q = 0; q < nr.size(); ++q) rel = std::max(rel, nb[q] > 0 ? std::sqrt(nr[q] / nb[q]) : 0.0);
+      worst = rel;
+      res = HODLR_ENOCONV;
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->status = res;
+    info->refine_iters = iters;
+    info->rel_residual = worst;
+    info->max_rank = m->max_rank_factors;
+    info->leaf = -1;
+    info->row = -1;
+    info->used_fallback = fallback ? 1 : 0;
+  }
+  return res;
+}
+
+static void record_step(hodlr_mat m, double* u, const double* f, double fscale, int sweeps, hipStream_t s) {
+  const int64_t tn = m->total_n;
+  const int prec = m->opts.prec;
+  // b = u + fscale * f
+  if (f) launch_axpby(tn, 1, 1.0, u, tn, fscale, f, tn, m->bbuf, tn, s);
+  else launch_axpby(tn, 1, 1.0, u, tn, 0.0, u, tn, m->bbuf, tn, s);
+  launch_solve(m, prec, m->bbuf, tn, u, tn, 1, s);
+  for (int q = 0; q < sweeps; ++q) {
+    launch_fft_matvec(m, u, tn, m->rbuf, tn, m->bbuf, tn, 1, s);
+    launch_solve(m, prec, m->rbuf, tn, m->dbuf, tn, 1, s);
+    launch_axpby(tn, 1, 1.0, u, tn, 1.0, m->dbuf, tn, u, tn, s);
+  }
+}
+
+hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const double* f, double fscale, int steps,
+                              hodlr_info* info) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!m) return set_arg(ctx, 2);
+  if (!u) return set_arg(ctx, 3);
+  if (steps < 0) return set_arg(ctx, 5);
+  if (!m->factored) return HODLR_ESTATE;
+  hipStream_t s = ctx->stream;
+  const int64_t tn = m->total_n;
+  const int sweeps = m->opts.refine_max;
+  if (s == nullptr) {
+    // the legacy null stream cannot be captured: launch the steps directly
+    for (int k = 0; k < steps; ++k) record_step(m, u, f, fscale, sweeps, s);
+  } else if (!m->step_graph || m->graph_u != u || m->graph_f != f || m->graph_sweeps != sweeps ||
+             m->graph_fscale != fscale) {
+    if (m->step_graph) {
+      (void)hipGraphExecDestroy(m->step_graph);
+      m->step_graph = nullptr;
+    }
+    hipGraph_t g;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    record_step(m, u, f, fscale, sweeps, s);
+    HIP_TRY(hipStreamEndCapture(s, &g));
+    HIP_TRY(hipGraphInstantiate(&m->step_graph, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    m->graph_u = u;
+    m->graph_f = f;
+    m->graph_sweeps = sweeps;
+    m->graph_fscale = fscale;
+  }
+  if (s != nullptr)
+    for (int k = 0; k < steps; ++k) HIP_TRY(hipGraphLaunch(m->step_graph, s));
+  HIP_TRY(hipGetLastError());
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->refine_iters = sweeps;
+    info->max_rank = m->max_rank_factors;
+    info->leaf = -1;
+    info->row = -1;
+    // residual of the last step against its right-hand side (still in bbuf)
+    launch_fft_matvec(m, u, tn, m->rbuf, tn, m->bbuf, tn, 1, s);
+    launch_norms(m, m->rbuf, tn, 1, m->norms, s);
+    launch_norms(m, m->bbuf, tn, 1, m->norms + m->batch * kNCS, s);
+    std::vector<double> nr(m->batch), nb(m->batch);
+    HIP_TRY(hipMemcpyAsync(nr.data(), m->norms, nr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(nb.data(), m->norms + m->batch * kNCS, nb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double rel = 0.0;
+    for (int q = 0; q < m->batch; ++q) rel = std::max(rel, nb[q] > 0 ? std::sqrt(nr[q] / nb[q]) : 0.0);
+    info->rel_residual = rel;
+    info->status = (sweeps > 0 && rel > m->opts.rtol) ? HODLR_ENOCONV : HODLR_OK;
+    return hodlr_status(info->status);
+  }
+  return HODLR_OK;
+}
+
+// ---- 2D (factored ADI): implemented in adi.hip
+}  // extern "C"

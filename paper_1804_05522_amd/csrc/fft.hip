@@ -1,0 +1,294 @@
+// Exact matrix-vector product with M = s I + nu (D+ T + D- T^T) (eq. (system_FD))
+// for the refinement residual, on gfx950.
+//
+// Sec. 3.4.2 applies T with the FFT (circulant embedding).  Here T is split
+//   T = T_near + T_far,  T_near = entries with -1 <= i-j <= w (band),
+//                        T_far  = entries with i-j > w  (the slowly decaying tail),
+// T_near x and T_near^T x are summed directly in double-double (TwoSum /
+// TwoProd with fma), and only the far tail goes through a circulant of
+// length M >= 2N-1 (power of two):
+//   c[k] = -g_{k+1} for w < k < N, 0 elsewhere,  lambda = FFT(c),
+//   T_far x = Re IFFT(mu . FFT(x)),  T_far^T x = Im IFFT(mu . FFT(x)),
+//   mu = lambda + i conj(lambda)
+// (C^T is the circulant with eigenvalues conj(lambda) because c is real, and
+// both products are real, so one complex inverse transform returns both).
+// The far tail is small (|g_k| ~ k^{-alpha-1}), so the FFT's rounding error
+// is scaled down by the same factor, and the residual is accurate to a few
+// units of roundoff of |r| plus a far smaller FFT term.
+//
+// FFT: radix-2 in LDS after a bit-reversed load (lengths <= 8192); longer
+// lengths use the four-step split M = M1 * M2 (two LDS passes with a twiddle
+// multiply between them), each pass moving tiles of T adjacent sub-transforms
+// so global accesses stay 256-byte contiguous.
+#include "internal.hpp"
+
+namespace hfde {
+
+constexpr int kFftWG = 512;
+constexpr int kFftLds = 8192;          // complex values held in LDS
+
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// In-place radix-2 DIT on `ntile` transforms of length m = 2^logm stored
+// back to back in LDS (already in bit-reversed order).  tw: the M-th roots
+// e^{-2 pi i j / M} of the problem, M = 2^logM >= m.
+__device__ void lds_fft(double2* buf, int ntile, int logm, const double2* tw, int logM, bool inverse) {
+  const int m = 1 << logm;
+  const int half_total = ntile * (m >> 1);
+  for (int lh = 0; lh < logm; ++lh) {
+    const int h = 1 << lh;
+    const int shift = logM - lh - 1;          // w = omega_{2h}^k = tw[k << shift]
+    for (int b = threadIdx.x; b < half_total; b += blockDim.x) {
+      const int t = b >> (logm - 1);
+      const int q = b & ((m >> 1) - 1);
+      const int k = q & (h - 1);
+      const int i0 = t * m + ((q >> lh) << (lh + 1)) + k;
+      const int i1 = i0 + h;
+      double2 w = tw[int64_t(k) << shift];
+      if (inverse) w = cconj(w);
+      const double2 a = buf[i0];
+      const double2 c = cmul(buf[i1], w);
+      buf[i0] = make_double2(a.x + c.x, a.y + c.y);
+      buf[i1] = make_double2(a.x - c.x, a.y - c.y);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ inline int bitrev(int v, int logm) {
+  return logm == 0 ? 0 : int(__brev(uint32_t(v)) >> (32 - logm));
+}
+
+// --------------------------------------------------------- double-double
+struct dd {
+  double hi, lo;
+};
+__device__ inline dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  return dd{s, (a - (s - bb)) + (b - bb)};
+}
+__device__ inline dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  return two_sum(s.hi, s.lo + a.lo + b.lo);
+}
+__device__ inline dd dd_prod(double a, double b) {
+  double p = a * b;
+  return dd{p, fma(a, b, -p)};
+}
+__device__ inline dd dd_mul_d(dd a, double b) {
+  dd p = dd_prod(a.hi, b);
+  p.lo += a.lo * b;
+  return two_sum(p.hi, p.lo);
+}
+
+// Output of the exact product for row i: y_i = s x_i + nu (d+ (Tn x + far_re) + d- (Tn^T x + far_im)),
+// or the residual b_i - y_i.  Near band in double-double.
+__device__ inline double exact_row(const DevPtrs& P, const Item& it, const double* x, int64_t i, double far_re,
+                                   double far_im, const double* bvec) {
+  const double* g = P.g + it.g0;
+  const int64_t n = it.n;
+  const int w = it.band;
+  dd sp{0.0, 0.0}, sm{0.0, 0.0};
+  // (T x)_i = -sum_{j <= i+1} g_{i-j+1} x_j ;  near: i - j in [-1, w]
+  for (int k = -1; k <= w; ++k) {
+    const int64_t j = i - k;
+    if (j < 0 || j >= n) continue;
+    sp = dd_add(sp, dd_prod(-g[k + 1], x[j]));
+  }
+  // (T^T x)_i = -sum_{j >= i-1} g_{j-i+1} x_j ;  near: j - i in [-1, w]
+  for (int k = -1; k <= w; ++k) {
+    const int64_t j = i + k;
+    if (j < 0 || j >= n) continue;
+    sm = dd_add(sm, dd_prod(-g[k + 1], x[j]));
+  }
+  sp = dd_add(sp, dd{far_re, 0.0});
+  sm = dd_add(sm, dd{far_im, 0.0});
+  const int64_t gi = it.row0 + i;
+  dd tsum = dd_add(dd_mul_d(sp, P.dplus[gi]), dd_mul_d(sm, P.dminus[gi]));
+  tsum = dd_mul_d(tsum, it.nu);
+  dd y = dd_add(dd_prod(it.shift, x[i]), tsum);
+  if (bvec != nullptr) {
+    dd r = dd_add(dd{bvec[i], 0.0}, dd{-y.hi, -y.lo});
+    return r.hi + r.lo;
+  }
+  return y.hi + y.lo;
+}
+
+// ---------------------------------------------------------------- setup
+__global__ void k_twiddles(DevPtrs P, int item) {
+  const Item it = P.items[item];
+  const int64_t M = int64_t(1) << it.fftlog;
+  double2* tw = P.tw + it.tw0;
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < M; j += int64_t(gridDim.x) * blockDim.x) {
+    // e^{-2 pi i j/M}: the argument 2j/M is exact in binary
+    double s, c;
+    sincospi(-2.0 * double(j) / double(M), &s, &c);
+    tw[j] = make_double2(c, s);
+  }
+}
+
+// value of the far circulant's first column at position k (length M)
+__device__ inline double cfar(const DevPtrs& P, const Item& it, int64_t k) {
+  if (k > it.band && k < it.n) return -P.g[it.g0 + k + 1];
+  return 0.0;
+}
+
+// modes of the FFT kernels
+enum { kModeSetup = 0, kModeMatvec = 1 };
+
+// Single work-group path (M <= kFftLds): setup builds mu, matvec does the
+// whole product for one (problem, column).
+__global__ void __launch_bounds__(kFftWG) k_fft_small(DevPtrs P, const FftUnit* units, int mode, const double* x,
+                                                     int64_t ldx, double* y, int64_t ldy, const double* b,
+                                                     int64_t ldb) {
+  extern __shared__ double2 buf[];
+  const FftUnit u = units[blockIdx.x];
+  const Item it = P.items[u.item];
+  const int logM = it.fftlog;
+  const int M = 1 << logM;
+  const double2* tw = P.tw + it.tw0;
+  const double* xc = x ? x + it.row0 + int64_t(u.col) * ldx : nullptr;
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    double v = 0.0;
+    if (mode == kModeSetup) v = cfar(P, it, j);
+    else if (j < it.n) v = xc[j];
+    buf[bitrev(j, logM)] = make_double2(v, 0.0);
+  }
+  __syncthreads();
+  lds_fft(buf, 1, logM, tw, logM, false);
+  double2* mu = P.mu + it.mu0;
+  if (mode == kModeSetup) {
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+      const double2 l = buf[j];
+      mu[j] = make_double2(l.x + l.y, l.y + l.x);   // lambda + i conj(lambda)
+    }
+    return;
+  }
+  // multiply, store bit-reversed for the inverse pass
+  __syncthreads();
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    const double2 v = cmul(buf[j], mu[j]);
+    buf[j] = v;
+  }
+  __syncthreads();
+  // bit-reverse permutation in place (swap pairs once)
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    const int r = bitrev(j, logM);
+    if (r > j) {
+      const double2 a = buf[j];
+      buf[j] = buf[r];
+      buf[r] = a;
+    }
+  }
+  __syncthreads();
+  lds_fft(buf, 1, logM, tw, logM, true);
+  const double inv = 1.0 / double(M);
+  double* yc = y + it.row0 + int64_t(u.col) * ldy;
+  const double* bc = b ? b + it.row0 + int64_t(u.col) * ldb : nullptr;
+  for (int64_t i = threadIdx.x; i < it.n; i += blockDim.x) {
+    const double2 w = buf[i];
+    yc[i] = exact_row(P, it, xc, i, w.x * inv, w.y * inv, bc);
+  }
+}
+
+// Four-step split: M = M1 * M2, n = n1 + M1 n2, k = k2 + M2 k1.
+__device__ inline void four_step_dims(int logM, int& l1, int& l2, int& tile) {
+  l2 = logM / 2;
+  l1 = logM - l2;
+  tile = kFftLds >> l1;
+  if (tile > 16) tile = 16;
+}
+
+// Pass 1: transforms over n2 (length M2) for `tile` adjacent n1, then the
+// twiddle omega_M^{n1 k2}; output Y[k2 * M1 + n1].
+// forward/setup: input c (setup) or x (matvec, real); inverse: input W.
+__global__ void __launch_bounds__(kFftWG) k_fft4_pass1(DevPtrs P, const FftUnit* units, int mode, bool inverse,
+                                                      const double* x, int64_t ldx) {
+  extern __shared__ double2 buf[];
+  const FftUnit u = units[blockIdx.x];
+  const Item it = P.items[u.item];
+  const int logM = it.fftlog;
+  int l1, l2, T;
+  four_step_dims(logM, l1, l2, T);
+  const int M1 = 1 << l1, M2 = 1 << l2;
+  const double2* tw = P.tw + it.tw0;
+  double2* ws = P.fws + it.ws0 + int64_t(u.col) * 2 * (int64_t(1) << logM);
+  double2* Y = ws;                               // first half: Y
+  const double2* Win = ws + (int64_t(1) << logM);   // second half: W (inverse input)
+  const int n1base = u.tile * T;
+  const double* xc = x ? x + it.row0 + int64_t(u.col) * ldx : nullptr;
+  for (int e = threadIdx.x; e < T * M2; e += blockDim.x) {
+    const int t = e % T, n2 = e / T;
+    const int64_t nidx = int64_t(n1base + t) + int64_t(M1) * n2;
+    double2 v;
+    if (inverse) {
+      v = Win[nidx];
+    } else if (mode == kModeSetup) {
+      v = make_double2(cfar(P, it, nidx), 0.0);
+    } else {
+      v = make_double2(nidx < it.n ? xc[nidx] : 0.0, 0.0);
+    }
+    buf[t * M2 + bitrev(n2, l2)] = v;
+  }
+  __syncthreads();
+  lds_fft(buf, T, l2, tw, logM, inverse);
+  const int64_t Mmask = (int64_t(1) << logM) - 1;
+  for (int e = threadIdx.x; e < T * M2; e += blockDim.x) {
+    const int t = e % T, k2 = e / T;
+    const int n1 = n1base + t;
+    double2 w = tw[(int64_t(n1) * k2) & Mmask];
+    if (inverse) w = cconj(w);
+    Y[int64_t(k2) * M1 + n1] = cmul(buf[t * M2 + k2], w);
+  }
+}
+
+// Pass 2: transforms over n1 (length M1) for `tile` adjacent k2; output index
+// k = k2 + M2 k1.  setup: mu; forward matvec: W = mu . X (second half of the
+// scratch); inverse: the final product rows.
+__global__ void __launch_bounds__(kFftWG) k_fft4_pass2(DevPtrs P, const FftUnit* units, int mode, bool inverse,
+                                                      const double* x, int64_t ldx, double* y, int64_t ldy,
+                                                      const double* b, int64_t ldb) {
+  extern __shared__ double2 buf[];
+  const FftUnit u = units[blockIdx.x];
+  const Item it = P.items[u.item];
+  const int logM = it.fftlog;
+  int l1, l2, T;
+  four_step_dims(logM, l1, l2, T);
+  const int M1 = 1 << l1, M2 = 1 << l2;
+  const int64_t M = int64_t(1) << logM;
+  const double2* tw = P.tw + it.tw0;
+  double2* ws = P.fws + it.ws0 + int64_t(u.col) * 2 * M;
+  const double2* Y = ws;
+  double2* Wout = ws + M;
+  const int k2base = u.tile * T;
+  for (int e = threadIdx.x; e < T * M1; e += blockDim.x) {
+    const int n1 = e % M1, t = e / M1;
+    buf[t * M1 + bitrev(n1, l1)] = Y[int64_t(k2base + t) * M1 + n1];
+  }
+  __syncthreads();
+  lds_fft(buf, T, l1, tw, logM, inverse);
+  double2* mu = P.mu + it.mu0;
+  const double inv = 1.0 / double(M);
+  const double* xc = x ? x + it.row0 + int64_t(u.col) * ldx : nullptr;
+  double* yc = y ? y + it.row0 + int64_t(u.col) * ldy : nullptr;
+  const double* bc = b ? b + it.row0 + int64_t(u.col) * ldb : nullptr;
+  for (int e = threadIdx.x; e < T * M1; e += blockDim.x) {
+    const int t = e % T, k1 = e / T;
+    const int64_t k = int64_t(k2base + t) + int64_t(M2) * k1;
+    const double2 v = buf[t * M1 + k1];
+    if (mode == kModeSetup) {
+      mu[k] = make_double2(v.x + v.y, v.y + v.x);
+    } else if (!inverse) {
+      Wout[k] = cmul(v, mu[k]);
+    } else if (k < it.n) {
+      yc[k] = exact_row(P, it, xc, k, v.x * inv, v.y * inv, bc);
+    }
+  }
+}
+
+}  // namespace hfde

@@ -1,0 +1,9 @@
+// Single translation unit of the HIP library (gfx950): every kernel and the
+// C ABI are compiled together so kernels and their launch sites share one
+// code object.
+#include "internal.hpp"
+#include "build.hip"
+#include "factor.hip"
+#include "solve.hip"
+#include "fft.hip"
+#include "api.hip"

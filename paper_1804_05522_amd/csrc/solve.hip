@@ -1,0 +1,300 @@
+// Per-step HODLR solve x = U^{-1} L^{-1} b (Sec. 3.5) on gfx950, batched over
+// problems, leaves and right-hand sides.
+//
+// With the HODLR inverses of the triangular factors (see factor.hip), each
+// triangular solve is one HODLR matrix product, which is fully parallel:
+//   z_node = B[src rows]^T x[src rows]           (projection, per node)
+//   y[row] = leaf^{-1} x[leaf] + sum over levels B[row] z_node(row)   (expansion)
+// L^{-1}: src = child c1, dst = child c2 (lower blocks);
+// U^{-1}: src = c2, dst = c1 (upper blocks).
+// Kernels (one work unit = one leaf of one problem, 64 threads = its rows):
+//   k_project   per-leaf partial projections for every level,
+//   k_reduce    per-node sums of the partials (fixed order: deterministic),
+//   k_expand    leaf block + expansions; optionally also the next product's
+//               per-leaf projections of the freshly computed rows (fusion of
+//               the L^{-1} expansion with the U^{-1} projection).
+// Factors may be stored in FP64, FP32 or BF16 (TF); vectors and every
+// accumulation stay FP64.
+#include "internal.hpp"
+
+namespace hfde {
+
+
+__device__ inline double ld(const double* p) { return *p; }
+__device__ inline double ld(const float* p) { return double(*p); }
+__device__ inline double ld(const bf16* p) {
+  uint32_t u = uint32_t(p->v) << 16;
+  return double(__uint_as_float(u));
+}
+
+
+// Partial projection of v (rows of this leaf) onto the basis B at every
+// level where the leaf lies in the source child.
+template <typename TF>
+__device__ void leaf_project(const DevPtrs& P, const Item& it, int leaf, const Node& lf, const TF* Bb,
+                             const int32_t* ranks, int src_side, const double* vl /*LDS m x nc, ld 64*/,
+                             int nc, double* part, int Lmax, double* sh /*LDS 32*65*/, int vst) {
+  const int t = threadIdx.x;
+  const int m = lf.size;
+  const int64_t gl = it.leaf0 + leaf;
+  for (int d = 0; d < it.L; ++d) {
+    const int side = (leaf >> (it.L - d - 1)) & 1;
+    if (side != src_side) continue;
+    const int64_t nidx = node_index(it, d, leaf >> (it.L - d));
+    const int r = ranks[nidx];
+    const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start;
+    double* pout = part + (gl * Lmax + d) * int64_t(kRS) * nc;
+    for (int c = 0; c < nc; ++c) {
+      if (t < m) {
+        const double xv = vl[t + c * vst];
+        for (int s = 0; s < r; ++s) sh[s * 65 + t] = ld(Bd + t + int64_t(s) * it.n) * xv;
+      }
+      __syncthreads();
+      if (t < r) {
+        double acc = 0;
+        for (int i = 0; i < m; ++i) acc += sh[t * 65 + i];
+        pout[t + c * kRS] = acc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename TF, int NC>
+__global__ void __launch_bounds__(64) k_project(DevPtrs P, const WorkUnit* wu, int which, const TF* Bb,
+                                                const double* x, int64_t ldx, int nc, double* part,
+                                                int Lmax) {
+  __shared__ double vl[64 * NC];
+  __shared__ double sh[kRS * 65];
+  const WorkUnit w = wu[blockIdx.x];
+  const Item it = P.items[w.item];
+  const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
+  const int t = threadIdx.x;
+  const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
+  const int src_side = which == 0 ? 0 : 1;
+  for (int c = 0; c < nc; ++c)
+    if (t < lf.size) vl[t + c * 64] = x[it.row0 + lf.start + t + c * ldx];
+  __syncthreads();
+  leaf_project<TF>(P, it, w.leaf, lf, Bb, ranks, src_side, vl, nc, part, Lmax, sh, 64);
+}
+
+// z[node] = sum of the per-leaf partials over the leaves of the node's source child.
+__global__ void k_reduce(DevPtrs P, const NodeUnit* nu, int which, int nc, const double* part,
+                         double* z, int Lmax) {
+  const NodeUnit u = nu[blockIdx.x];
+  const Item it = P.items[u.item];
+  const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
+  const int64_t nidx = node_index(it, u.level, u.j);
+  const int r = ranks[nidx];
+  const int src_side = which == 0 ? 0 : 1;
+  const int64_t span = int64_t(1) << (it.L - u.level - 1);     // leaves per child
+  const int64_t first = (int64_t(u.j) * 2 + src_side) * span;
+  for (int e = threadIdx.x; e < r * nc; e += blockDim.x) {
+    const int s = e % r, c = e / r;
+    double acc = 0;
+    for (int64_t l = 0; l < span; ++l)
+      acc += part[((it.leaf0 + first + l) * Lmax + u.level) * int64_t(kRS) * nc + s + c * kRS];
+    z[nidx * int64_t(kRS) * nc + s + c * kRS] = acc;
+  }
+}
+
+// y = F x on this leaf's rows, F = L^{-1} (which = 0) or U^{-1} (which = 1),
+// x read from xin (global), result written to yout; if `next_part` is set,
+// also the per-leaf projections of y for U^{-1}.
+template <typename TF, typename TL, int NC>
+__global__ void __launch_bounds__(64) k_expand(DevPtrs P, SolveFactors<TF, TL> F, const WorkUnit* wu, int which,
+                                               const double* xin, int64_t ldx, double* yout, int64_t ldy,
+                                               int nc, const double* z, double* next_part, int Lmax, int b) {
+  __shared__ double vl[64 * NC];
+  __shared__ double yl[64 * NC];
+  __shared__ double sh[kRS * 65];
+  __shared__ int pm[64];
+  const WorkUnit w = wu[blockIdx.x];
+  const Item it = P.items[w.item];
+  const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
+  const int t = threadIdx.x;
+  const int m = lf.size;
+  const int64_t gl = it.leaf0 + w.leaf;
+  const TL* Fi = F.LUinv + gl * int64_t(b) * b;
+  const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
+  const TF* Bb = which == 0 ? F.IL : F.IU;
+  const int dst_side = which == 0 ? 1 : 0;
+  for (int c = 0; c < nc; ++c)
+    if (t < m) vl[t + c * 64] = xin[it.row0 + lf.start + t + c * ldx];
+  if (t < m) pm[t] = P.perm[gl * b + t];
+  __syncthreads();
+  if (t < m) {
+    for (int c = 0; c < nc; ++c) {
+      const double* x = vl + c * 64;
+      double acc = 0;
+      if (which == 0) {
+        acc = x[pm[t]];
+        for (int j = 0; j < t; ++j) acc += ld(Fi + t + j * b) * x[pm[j]];
+      } else {
+        for (int j = t; j < m; ++j) acc += ld(Fi + t + j * b) * x[j];
+      }
+      yl[t + c * 64] = acc;
+    }
+    for (int d = 0; d < it.L; ++d) {
+      const int side = (w.leaf >> (it.L - d - 1)) & 1;
+      if (side != dst_side) continue;
+      const int64_t nidx = node_index(it, d, w.leaf >> (it.L - d));
+      const int r = ranks[nidx];
+      const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + t;
+      const double* zn = z + nidx * int64_t(kRS) * nc;
+      double bv[kRS];
+      for (int s = 0; s < r; ++s) bv[s] = ld(Bd + int64_t(s) * it.n);
+      for (int c = 0; c < nc; ++c) {
+        double acc = 0;
+        for (int s = 0; s < r; ++s) acc += bv[s] * zn[s + c * kRS];
+        yl[t + c * 64] += acc;
+      }
+    }
+    for (int c = 0; c < nc; ++c) yout[it.row0 + lf.start + t + c * ldy] = yl[t + c * 64];
+  }
+  __syncthreads();
+  if (next_part != nullptr)
+    leaf_project<TF>(P, it, w.leaf, lf, F.IU, P.rankU, 1, yl, nc, next_part, Lmax, sh, 64);
+}
+
+// ---------------------------------------------------------------- helpers
+// out[col * batch + item] = sum of squares of v over the rows of `item`.
+__global__ void k_item_norms(DevPtrs P, const double* v, int64_t ld, int nc, double* out) {
+  const int item = blockIdx.x, col = blockIdx.y;
+  const Item it = P.items[item];
+  __shared__ double red[256];
+  double acc = 0.0;
+  const double* vc = v + it.row0 + int64_t(col) * ld;
+  for (int64_t i = threadIdx.x; i < it.n; i += blockDim.x) acc += vc[i] * vc[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[int64_t(col) * gridDim.x + item] = red[0];
+}
+
+// z = a x + b y (column blocks), z may alias x or y.
+__global__ void k_axpby(int64_t nrows, int nc, double a, const double* x, int64_t ldx, double bco,
+                        const double* y, int64_t ldy, double* z, int64_t ldz) {
+  const int64_t tot = nrows * nc;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = e % nrows, c = e / nrows;
+    const double yv = bco != 0.0 ? bco * y[i + c * ldy] : 0.0;
+    z[i + c * ldz] = a * x[i + c * ldx] + yv;
+  }
+}
+
+template <typename TF>
+__global__ void k_convert(const double* src, TF* dst, int64_t count);
+
+template <>
+__global__ void k_convert<float>(const double* src, float* dst, int64_t count) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x)
+    dst[i] = float(src[i]);
+}
+
+template <>
+__global__ void k_convert<bf16>(const double* src, bf16* dst, int64_t count) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    float f = float(src[i]);
+    uint32_t u = __float_as_uint(f);
+    uint32_t rounding = 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+    if ((u & 0x7F800000u) == 0x7F800000u) rounding = 0;  // keep inf/nan
+    dst[i].v = uint16_t((u + rounding) >> 16);
+  }
+}
+
+// y = M_H x for the compressed operator itself (leaves dense + off-diagonal
+// blocks of every level), one leaf per work unit; used to check the build.
+__global__ void __launch_bounds__(64) k_hmatvec_A_project(DevPtrs P, const WorkUnit* wu, const double* x,
+                                                          int64_t ldx, int nc, double* part, int Lmax) {
+  // partial projections for both the lower (src c1, basis XR) and upper
+  // (src c2, basis XR) blocks: z = XR[src]^T x[src]; slot layout like k_project.
+  __shared__ double vl[64 * 64];
+  __shared__ double sh[kRS * 65];
+  const WorkUnit w = wu[blockIdx.x];
+  const Item it = P.items[w.item];
+  const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
+  const int t = threadIdx.x;
+  const int m = lf.size;
+  const int64_t gl = it.leaf0 + w.leaf;
+  for (int c = 0; c < nc; ++c)
+    if (t < m) vl[t + c * 64] = x[it.row0 + lf.start + t + c * ldx];
+  __syncthreads();
+  for (int d = 0; d < it.L; ++d) {
+    const double* Bd = P.XR + it.lvl0 + int64_t(d) * it.n * kRS + lf.start;
+    const int r = it.r;
+    double* pout = part + (gl * Lmax + d) * int64_t(kRS) * nc;
+    for (int c = 0; c < nc; ++c) {
+      if (t < m) {
+        const double xv = vl[t + c * 64];
+        for (int s = 0; s < r; ++s) sh[s * 65 + t] = Bd[t + int64_t(s) * it.n] * xv;
+      }
+      __syncthreads();
+      if (t < r) {
+        double acc = 0;
+        for (int i = 0; i < m; ++i) acc += sh[t * 65 + i];
+        pout[t + c * kRS] = acc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_hmatvec_A_reduce(DevPtrs P, const NodeUnit* nu, int nc, const double* part, double* z,
+                                   int Lmax) {
+  // z layout: [node][side][s + c*kRS] where side 0 = projection of c1 (feeds A21),
+  // side 1 = projection of c2 (feeds A12)
+  const NodeUnit u = nu[blockIdx.x];
+  const Item it = P.items[u.item];
+  const int64_t nidx = node_index(it, u.level, u.j);
+  const int r = it.r;
+  const int64_t span = int64_t(1) << (it.L - u.level - 1);
+  for (int e = threadIdx.x; e < 2 * r * nc; e += blockDim.x) {
+    const int side = e / (r * nc);
+    const int q = e % (r * nc);
+    const int s = q % r, c = q / r;
+    const int64_t first = (int64_t(u.j) * 2 + side) * span;
+    double acc = 0;
+    for (int64_t l = 0; l < span; ++l)
+      acc += part[((it.leaf0 + first + l) * Lmax + u.level) * int64_t(kRS) * nc + s + c * kRS];
+    z[(nidx * 2 + side) * int64_t(kRS) * nc + s + c * kRS] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_hmatvec_A_expand(DevPtrs P, const WorkUnit* wu, const double* x,
+                                                         int64_t ldx, double* y, int64_t ldy, int nc,
+                                                         const double* z, int b) {
+  __shared__ double vl[64 * 64];
+  const WorkUnit w = wu[blockIdx.x];
+  const Item it = P.items[w.item];
+  const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
+  const int t = threadIdx.x;
+  const int m = lf.size;
+  const int64_t gl = it.leaf0 + w.leaf;
+  for (int c = 0; c < nc; ++c)
+    if (t < m) vl[t + c * 64] = x[it.row0 + lf.start + t + c * ldx];
+  __syncthreads();
+  if (t >= m) return;
+  const double* A = P.Aleaf + gl * int64_t(b) * b;
+  for (int c = 0; c < nc; ++c) {
+    double acc = 0;
+    for (int j = 0; j < m; ++j) acc += A[t + j * b] * vl[j + c * 64];
+    for (int d = 0; d < it.L; ++d) {
+      const int side = (w.leaf >> (it.L - d - 1)) & 1;
+      const int64_t nidx = node_index(it, d, w.leaf >> (it.L - d));
+      // row in c2 receives A21 (XL on c2 rows) times the projection of c1 (side 0);
+      // row in c1 receives A12 (XL on c1 rows) times the projection of c2 (side 1)
+      const double* zn = z + (nidx * 2 + (1 - side)) * int64_t(kRS) * nc + c * kRS;
+      const double* Bd = P.XL + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + t;
+      for (int s = 0; s < it.r; ++s) acc += Bd[int64_t(s) * it.n] * zn[s];
+    }
+    y[it.row0 + lf.start + t + c * ldy] = acc;
+  }
+}
+
+}  // namespace hfde

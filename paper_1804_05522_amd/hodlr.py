@@ -1,0 +1,220 @@
+"""ctypes binding of the HIP library ``libhodlr_fde.so`` (C ABI in include/hodlr_fde.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  torch supplies device memory (``data_ptr()``) and the stream.
+The binding fails loudly if the library was not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhodlr_fde.so")
+
+HODLR_OK, HODLR_EINVAL, HODLR_ENOMEM, HODLR_EHIP, HODLR_ESTATE = 0, -1, -2, -3, -5
+HODLR_ESINGULAR, HODLR_ENOCONV, HODLR_ERANK = 1, 2, 3
+FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16": MIXED_BF16}
+
+# every exported symbol of include/hodlr_fde.h
+EXPORTS = [
+    "hodlr_ctx_create", "hodlr_ctx_destroy", "hodlr_last_arg", "hodlr_status_string",
+    "hodlr_default_opts", "hodlr_build", "hodlr_destroy", "hodlr_get_info", "hodlr_matvec",
+    "hodlr_toeplitz_matvec", "hodlr_factor", "hodlr_solve", "hodlr_time_steps",
+    "fde2d_plan_create", "fde2d_plan_destroy", "fde2d_plan_shifts", "fde2d_sylvester_step",
+    "fde2d_sylvester_step_dense",
+]
+
+
+class FdeOperator(C.Structure):
+    _fields_ = [("n", C.c_int64), ("alpha", C.c_double), ("dt", C.c_double), ("dx", C.c_double),
+                ("shift", C.c_double), ("d_plus", C.c_void_p), ("d_minus", C.c_void_p)]
+
+
+class HodlrOpts(C.Structure):
+    _fields_ = [("leaf", C.c_int), ("tol", C.c_double), ("prec", C.c_int), ("max_rank", C.c_int),
+                ("refine_max", C.c_int), ("rtol", C.c_double)]
+
+
+class HodlrInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("refine_iters", C.c_int), ("rel_residual", C.c_double),
+                ("max_rank", C.c_int), ("leaf", C.c_int), ("row", C.c_int),
+                ("used_fallback", C.c_int)]
+
+
+class HodlrMatInfo(C.Structure):
+    _fields_ = [("batch", C.c_int), ("leaf", C.c_int), ("max_levels", C.c_int),
+                ("total_n", C.c_int64), ("max_rank_A", C.c_int), ("max_rank_factors", C.c_int),
+                ("bytes_factors", C.c_size_t), ("bytes_device", C.c_size_t)]
+
+
+class LrMatrix(C.Structure):
+    _fields_ = [("rows", C.c_int64), ("rank", C.c_int), ("capacity", C.c_int),
+                ("ldz", C.c_int64), ("ldw", C.c_int64), ("Z", C.c_void_p), ("W", C.c_void_p)]
+
+
+class Fde2dOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_shifts", C.c_int), ("max_rank", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+        L.hodlr_ctx_create.argtypes = [C.POINTER(vp), vp]
+        L.hodlr_ctx_destroy.argtypes = [vp]
+        L.hodlr_ctx_destroy.restype = None
+        L.hodlr_last_arg.argtypes = [vp]
+        L.hodlr_status_string.argtypes = [i32]
+        L.hodlr_status_string.restype = C.c_char_p
+        L.hodlr_default_opts.argtypes = [C.POINTER(HodlrOpts)]
+        L.hodlr_build.argtypes = [vp, C.POINTER(FdeOperator), i32, C.POINTER(HodlrOpts), C.POINTER(vp)]
+        L.hodlr_destroy.argtypes = [vp]
+        L.hodlr_destroy.restype = None
+        L.hodlr_get_info.argtypes = [vp, C.POINTER(HodlrMatInfo)]
+        L.hodlr_matvec.argtypes = [vp, vp, vp, vp, i32, i64]
+        L.hodlr_toeplitz_matvec.argtypes = [vp, vp, vp, vp, i32, i64]
+        L.hodlr_factor.argtypes = [vp, vp, C.POINTER(HodlrInfo)]
+        L.hodlr_solve.argtypes = [vp, vp, vp, i32, i64, C.POINTER(HodlrInfo)]
+        L.hodlr_time_steps.argtypes = [vp, vp, vp, vp, dbl, i32, C.POINTER(HodlrInfo)]
+        if hasattr(L, "fde2d_plan_create"):
+            L.fde2d_plan_create.argtypes = [vp, C.POINTER(FdeOperator), C.POINTER(FdeOperator),
+                                            C.POINTER(HodlrOpts), C.POINTER(Fde2dOpts), C.POINTER(vp)]
+            L.fde2d_plan_destroy.argtypes = [vp]
+            L.fde2d_plan_destroy.restype = None
+            L.fde2d_plan_shifts.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), i32]
+            L.fde2d_sylvester_step.argtypes = [vp, vp, C.POINTER(LrMatrix), C.POINTER(LrMatrix), dbl,
+                                               C.POINTER(LrMatrix), C.POINTER(HodlrInfo)]
+            L.fde2d_sylvester_step_dense.argtypes = [vp, vp, vp, vp, vp, i64, i32, dbl,
+                                                     C.POINTER(HodlrInfo)]
+        _lib = L
+    return _lib
+
+
+class HodlrError(RuntimeError):
+    def __init__(self, status, where, ctx=None):
+        msg = lib().hodlr_status_string(status).decode()
+        arg = lib().hodlr_last_arg(ctx) if (ctx and status == HODLR_EINVAL) else 0
+        super().__init__(f"{where}: {msg} (status {status}{', argument %d' % arg if arg else ''})")
+        self.status = status
+
+
+def check(status, where, ctx=None, ok=(HODLR_OK,)):
+    if status not in ok:
+        raise HodlrError(status, where, ctx)
+    return status
+
+
+def _stream_handle(torch_stream=None):
+    import torch
+    s = torch_stream if torch_stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A library context bound to one HIP stream (torch's current stream by default)."""
+
+    def __init__(self, stream=None):
+        self.h = C.c_void_p()
+        check(lib().hodlr_ctx_create(C.byref(self.h), _stream_handle(stream)), "hodlr_ctx_create")
+
+    def close(self):
+        if self.h:
+            lib().hodlr_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_opts(**kw) -> HodlrOpts:
+    o = HodlrOpts()
+    lib().hodlr_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if k == "prec" and isinstance(v, str):
+            v = PRECISIONS[v]
+        setattr(o, k, v)
+    return o
+
+
+class HodlrMatrix:
+    """A batch of HODLR-compressed operators M = s I + nu (D+ T + D- T^T)."""
+
+    def __init__(self, ctx: Context, ops, opts: HodlrOpts):
+        """ops: list of dicts n, alpha, dt, dx, shift, d_plus, d_minus (torch CUDA float64)."""
+        self.ctx = ctx
+        self._keep = []
+        arr = (FdeOperator * len(ops))()
+        for i, o in enumerate(ops):
+            dp, dm = o["d_plus"], o["d_minus"]
+            self._keep += [dp, dm]
+            arr[i] = FdeOperator(int(o["n"]), float(o["alpha"]), float(o["dt"]), float(o["dx"]),
+                                 float(o.get("shift", 1.0)), C.c_void_p(dp.data_ptr()),
+                                 C.c_void_p(dm.data_ptr()))
+        self.h = C.c_void_p()
+        self.opts = opts
+        self.sizes = [int(o["n"]) for o in ops]
+        self.total_n = sum(self.sizes)
+        check(lib().hodlr_build(ctx.h, arr, len(ops), C.byref(opts), C.byref(self.h)), "hodlr_build", ctx.h)
+        self._keep = []
+
+    def info(self) -> HodlrMatInfo:
+        i = HodlrMatInfo()
+        check(lib().hodlr_get_info(self.h, C.byref(i)), "hodlr_get_info")
+        return i
+
+    def factor(self, allow=(HODLR_OK,)) -> HodlrInfo:
+        info = HodlrInfo()
+        check(lib().hodlr_factor(self.ctx.h, self.h, C.byref(info)), "hodlr_factor", self.ctx.h, allow)
+        return info
+
+    def matvec(self, x, y, nrhs=1, ld=None):
+        ld = self.total_n if ld is None else ld
+        check(lib().hodlr_matvec(self.ctx.h, self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                 nrhs, ld), "hodlr_matvec", self.ctx.h)
+
+    def toeplitz_matvec(self, x, y, nrhs=1, ld=None):
+        ld = self.total_n if ld is None else ld
+        check(lib().hodlr_toeplitz_matvec(self.ctx.h, self.h, C.c_void_p(x.data_ptr()),
+                                          C.c_void_p(y.data_ptr()), nrhs, ld),
+              "hodlr_toeplitz_matvec", self.ctx.h)
+
+    def solve(self, x, nrhs=1, ld=None, allow=(HODLR_OK,)) -> HodlrInfo:
+        ld = self.total_n if ld is None else ld
+        info = HodlrInfo()
+        check(lib().hodlr_solve(self.ctx.h, self.h, C.c_void_p(x.data_ptr()), nrhs, ld, C.byref(info)),
+              "hodlr_solve", self.ctx.h, allow)
+        return info
+
+    def time_steps(self, u, f=None, fscale=0.0, steps=1, allow=(HODLR_OK,)) -> HodlrInfo:
+        info = HodlrInfo()
+        fp = C.c_void_p(f.data_ptr()) if f is not None else C.c_void_p()
+        check(lib().hodlr_time_steps(self.ctx.h, self.h, C.c_void_p(u.data_ptr()), fp, float(fscale),
+                                     int(steps), C.byref(info)), "hodlr_time_steps", self.ctx.h, allow)
+        return info
+
+    def close(self):
+        if self.h:
+            lib().hodlr_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def operator_dict(n, alpha, dt, dx, d_plus, d_minus, shift=1.0):
+    return dict(n=n, alpha=alpha, dt=dt, dx=dx, d_plus=d_plus, d_minus=d_minus, shift=shift)
