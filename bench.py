@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of the HODLR implicit-Euler solver on one MI355X.
+
+Workload (the 1D variable-coefficient configuration): N = 65536 interior
+points on [0,1], alpha in {1.2, 1.8} (the two problems form one batch),
+d+ = 1 + x^2, d- = 1 + (1-x)^2, dt = 1/256, 256 implicit Euler steps,
+source = seeded sum of 8 Gaussians, u0 = x^2 (1-x)^2, HODLR leaf 64,
+truncation eps = 1e-10.  Inputs are synthetic (workloads.py).
+
+One bench "step" is one whole job: build the HODLR operators (weights, ACA
+compression, assembly), factor them (HODLR LU + inverse factors), and run the
+256 time steps, each solved to a relative forward-error estimate <= 1e-10
+(FP64 refinement sweeps with the exact near/far-field Toeplitz residual).
+value = problem-steps per second of the whole job (2 problems x 256 steps /
+job time), at the headline precision (FP32 factors by default); the FP64
+factor path is measured the same way for comparison.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_HBM = 8.0e12           # bytes/s
+MI355X_FP64 = 78.6e12         # flop/s, vector and matrix
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed jobs")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed jobs")
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--euler-steps", type=int, default=256)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--target", type=float, default=1e-10)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the batched "
+              "problems shard across GPUs as independent units, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1804_05522_amd as H
+    import workloads as W
+
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = H.Context(stream)
+    probs = [W.var_1d(1.2, n=args.n), W.var_1d(1.8, n=args.n)]
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    dps = [dev(p.d_plus) for p in probs]
+    dms = [dev(p.d_minus) for p in probs]
+    ops = [H.operator_dict(p.n, p.alpha, p.dt, p.h, a, b) for p, a, b in zip(probs, dps, dms)]
+    u0 = dev(np.concatenate([p.u0 for p in probs]))
+    f = dev(np.concatenate([p.f for p in probs]))
+    dt = probs[0].dt
+    K = args.euler_steps
+
+    def job(prec, sweeps, timing=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        A = H.HodlrMatrix(ctx, ops, H.default_opts(tol=1e-10, prec=prec, refine_max=sweeps, rtol=args.target))
+        ev[1].record(stream)
+        A.factor(allow=(0, 3))
+        ev[2].record(stream)
+        u = u0.clone()
+        info = A.time_steps(u, f, dt, K, allow=(0, 2))
+        ev[3].record(stream)
+        if timing is not None:
+            stream.synchronize()
+            timing.append([ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])])
+        return A, u, info
+
+    def calibrate(prec):
+        """Fewest refinement sweeps per step whose last correction is <= target."""
+        for sweeps in range(0, 9):
+            A, u, info = job(prec, sweeps)
+            ok = sweeps > 0 and info.rel_correction <= args.target and info.rel_correction == info.rel_correction
+            A.close()
+            if ok:
+                return sweeps, info
+        return None, info
+
+    def measure(prec):
+        sweeps, cinfo = calibrate(prec)
+        if sweeps is None:
+            return None
+        for _ in range(args.warmup):
+            A, _, _ = job(prec, sweeps)
+            A.close()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        parts = []
+        last = None
+        for _ in range(args.steps):
+            A, u, info = job(prec, sweeps, parts)
+            last = (A, u, info)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        A, u, info = last
+        mi = A.info()
+        # live per-launch timing of the two dominant kernels' calls on the same stream
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        reps = 20
+        x = u.clone()
+        A2 = H.HodlrMatrix(ctx, ops, H.default_opts(tol=1e-10, prec=prec, refine_max=0))
+        e0.record(stream)
+        A2.factor(allow=(0, 3))
+        e1.record(stream)
+        for _ in range(reps):
+            A2.solve(x, allow=(0, 2))
+        e2.record(stream)
+        stream.synchronize()
+        t_factor = e0.elapsed_time(e1) / 1e3
+        t_solve = e1.elapsed_time(e2) / 1e3 / reps
+        mi2 = A2.info()
+        A2.close()
+        res = dict(prec=prec, sweeps=sweeps, job_s=(t1 - t0) / args.steps,
+                   build_ms=float(np.mean([p[0] for p in parts])), factor_ms=float(np.mean([p[1] for p in parts])),
+                   steps_ms=float(np.mean([p[2] for p in parts])), rel_correction=info.rel_correction,
+                   rel_residual=info.rel_residual, rank_A=mi.max_rank_A, rank_factors=mi.max_rank_factors,
+                   solve_bytes=mi2.bytes_factors, factor_flops=mi2.factor_flops, t_factor=t_factor, t_solve=t_solve)
+        A.close()
+        return res
+
+    main_res = measure(args.prec)
+    if main_res is None:
+        print(json.dumps({"metric": "HODLR solve steps/s", "error": f"{args.prec} did not reach {args.target}"}))
+        sys.exit(1)
+    cmp_res = None if (args.no_compare or args.prec == "fp64") else measure("fp64")
+
+    problem_steps = len(probs) * K
+    value = problem_steps / main_res["job_s"]
+    # dominant kernel of the job: the factorisation (one launch of k_factor per job)
+    # or the per-step solve kernels, whichever takes more of the job
+    fact_share = main_res["factor_ms"] / (1e3 * main_res["job_s"])
+    if fact_share >= 0.5:
+        achieved = main_res["factor_flops"] / main_res["t_factor"]
+        roof = {"kernel": "k_factor", "bound": "alu", "achieved": achieved / 1e12, "peak": MI355X_FP64 / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / MI355X_FP64, "traffic": None,
+                "algorithmic": f"{main_res['factor_flops']:.3e} flop per launch (flop model of the HODLR LU)",
+                "launch_ms": 1e3 * main_res["t_factor"]}
+    else:
+        vec_bytes = 8.0 * sum(p.n for p in probs) * 6
+        byts = main_res["solve_bytes"] + vec_bytes
+        achieved = byts / main_res["t_solve"]
+        roof = {"kernel": "hodlr_solve (project/reduce/expand)", "bound": "hbm", "achieved": achieved / 1e9,
+                "peak": MI355X_HBM / 1e9, "unit": "GB/s", "frac": achieved / MI355X_HBM, "traffic": None,
+                "algorithmic": f"{byts:.3e} bytes per solve (factors at their ranks + 6 vector passes)",
+                "launch_ms": 1e3 * main_res["t_solve"]}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args, probs)
+
+    out = {
+        "metric": "HODLR solve steps/s (1D N=65536) at rel.err 1e-10",
+        "value": value,
+        "unit": "problem-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * main_res["job_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "factor_storage": {"fp64": "f64", "fp32": "f32", "bf16": "bf16+f32"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": f"var_1d N={args.n} alpha={{1.2,1.8}} batch=2 euler_steps={K} dt=1/256 "
+                               f"leaf=64 eps=1e-10 target={args.target}",
+                   "global_batch": len(probs), "parallelism": "single GPU"},
+        "phases_ms": {"build": main_res["build_ms"], "factor": main_res["factor_ms"], "time_steps": main_res["steps_ms"]},
+        "per_step_us": 1e3 * main_res["steps_ms"] / K,
+        "refine_sweeps_per_step": main_res["sweeps"],
+        "rel_correction_last": main_res["rel_correction"],
+        "rank_A": main_res["rank_A"], "rank_factors": main_res["rank_factors"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if cmp_res is not None:
+        out["fp64_path"] = {"value": problem_steps / cmp_res["job_s"], "per_step_us": 1e3 * cmp_res["steps_ms"] / K,
+                            "factor_ms": cmp_res["factor_ms"], "sweeps": cmp_res["sweeps"],
+                            "solve_us": 1e6 * cmp_res["t_solve"]}
+        out["mixed_vs_fp64"] = {"whole_job": out["fp64_path"]["value"] and value / out["fp64_path"]["value"],
+                                "per_step": cmp_res["steps_ms"] / main_res["steps_ms"]}
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(args, probs):
+    """The oracle as it stands (dense LU + double-double refined steps) on a
+    bounded sample: N = 4096 of the same workload, both alphas, 8 steps; the
+    whole-workload rate is extrapolated with the oracle's own cost model
+    (LU ~ N^3, a refined step ~ N^2)."""
+    import numpy as np
+    import workloads as W
+    from oracle import fde1d as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    n0, steps0 = 4096, 8
+    t_lu = t_step = 0.0
+    for p in probs:
+        q = W.var_1d(p.alpha, n=n0)
+        t0 = time.perf_counter()
+        S = O.DenseSolver(q.alpha, q.n, q.nu, q.d_plus, q.d_minus)
+        t1 = time.perf_counter()
+        u = q.u0.copy()
+        for _ in range(steps0):
+            u = S.solve(u + q.dt * q.f)
+        t2 = time.perf_counter()
+        t_lu += t1 - t0
+        t_step += (t2 - t1) / steps0
+    scale = args.n / n0
+    t_full = t_lu * scale ** 3 + args.euler_steps * t_step * scale ** 2
+    return {"value": len(probs) * args.euler_steps / t_full, "unit": "problem-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"N={n0}, alpha=1.2 and 1.8, dense LU + {steps0} double-double refined steps "
+                      f"(LU {t_lu:.2f} s, {1e3 * t_step:.1f} ms/step for both); extrapolated to N={args.n}, "
+                      f"{args.euler_steps} steps with LU ~ N^3 and a step ~ N^2",
+            "sample_problem_steps_per_s": len(probs) / t_step}
+
+
+if __name__ == "__main__":
+    main()

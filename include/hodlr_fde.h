@@ -75,7 +75,7 @@ typedef struct {
   int prec;               /* hodlr_precision used by hodlr_solve */
   int max_rank;           /* cap on every off-diagonal rank, <= 32 */
   int refine_max;         /* max FP64 refinement sweeps per solve (any precision; 0 = plain solve) */
-  double rtol;            /* refinement target ||b - M x||_2 / ||b||_2 */
+  double rtol;            /* refinement target ||d||_2 / ||x||_2 for the last correction d */
 } hodlr_opts;
 
 typedef struct {
@@ -86,6 +86,8 @@ typedef struct {
   int leaf;               /* problem index of a singular leaf (ESINGULAR), else -1 */
   int row;                /* leaf index of that leaf, else -1 */
   int used_fallback;      /* 1 if any problem fell back to the FP64 factors */
+  double rel_correction;  /* max over problems of ||d||_2/||x||_2, d = last refinement correction
+                             (estimates the forward error; 0 without refinement) */
 } hodlr_info;
 
 typedef struct {
@@ -97,6 +99,7 @@ typedef struct {
   int max_rank_factors;   /* rank of the LU factor blocks (0 before hodlr_factor) */
   size_t bytes_factors;   /* bytes read by one single-RHS solve at the chosen precision */
   size_t bytes_device;    /* device memory held by the handle */
+  double factor_flops;    /* algorithmic FP64 flops of hodlr_factor (model from the final ranks) */
 } hodlr_mat_info;
 
 /* ---- context ------------------------------------------------------------ */
@@ -139,7 +142,8 @@ hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info);
 /* x <- M^{-1} x for every problem and column (Sec. 3.5 back substitution,
  * applied through the HODLR inverses of the triangular factors).  With
  * opts.refine_max > 0 the solve is followed by FP64 iterative refinement whose
- * residual is hodlr_toeplitz_matvec, until ||b - M x||_2/||b||_2 <= rtol; a
+ * residual is hodlr_toeplitz_matvec, until the correction satisfies
+ * ||d||_2 <= rtol ||x||_2 (the residual of a stiff M floors near u ||M|| ||x||); a
  * mixed-precision solve that stalls falls back to the FP64 factors (status
  * HODLR_ENOCONV, info->used_fallback = 1).  x: device, ld >= total n.
  * info: host, may be NULL. */

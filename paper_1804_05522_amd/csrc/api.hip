@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <array>
+#include <cstdlib>
 #include <vector>
 
 
@@ -58,6 +60,9 @@ struct hodlr_mat_s {
   int n_fft_p1 = 0;
   FftUnit* fft_p2_units = nullptr;
   int n_fft_p2 = 0;
+  FftUnit* fft_row_units = nullptr;
+  int n_fft_rows = 0;
+  size_t fft4_lds = 0;
   // solve scratch
   double* partL = nullptr;
   double* partU = nullptr;
@@ -77,6 +82,24 @@ struct hodlr_mat_s {
   float* LUinv32 = nullptr;
   bf16* IL16 = nullptr;
   bf16* IU16 = nullptr;
+  // multi-work-group factorisation schedule
+  bool mwg_planned = false;
+  std::vector<int> mwg_kind;                 // launch kind per record
+  std::vector<int> mwg_grid;                 // grid size
+  std::vector<int64_t> mwg_off;              // offset into the unit array of its kind
+  std::vector<int64_t> mwg_off2;             // secondary offset (tasks / jobs)
+  NodeTask* d_tasks = nullptr;
+  GramUnit* d_gram = nullptr;
+  ReduceUnit* d_red = nullptr;
+  int2* d_core = nullptr;
+  FormUnit* d_form = nullptr;
+  ProdJob* d_jobs = nullptr;
+  ProdUnit* d_punits = nullptr;
+  double* d_gpart = nullptr;
+  double* d_G = nullptr;
+  double* d_M = nullptr;
+  double* d_ppart = nullptr;
+  double* d_pz = nullptr;
   // graph of one time step
   hipGraphExec_t step_graph = nullptr;
   const double* graph_u = nullptr;
@@ -162,7 +185,7 @@ void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int
     }
     if (m->n_fft_p1) {
       const int per_col1 = m->n_fft_p1 / kNCF, per_col2 = m->n_fft_p2 / kNCF;
-      const size_t lds = size_t(8192) * sizeof(double2);
+      const size_t lds = m->fft4_lds;
       hipLaunchKernelGGL(k_fft4_pass1, dim3(per_col1 * cn), dim3(512), lds, s, m->P, m->fft_p1_units, 1, false,
                          xc, ldx);
       hipLaunchKernelGGL(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, false,
@@ -171,6 +194,9 @@ void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int
                          xc, ldx);
       hipLaunchKernelGGL(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, true,
                          xc, ldx, yc, ldy, bc, ldb);
+      const int per_colr = m->n_fft_rows / kNCF;
+      hipLaunchKernelGGL(k_exact_rows, dim3(per_colr * cn), dim3(256), 0, s, m->P, m->fft_row_units, xc, ldx, yc, ldy,
+                         bc, ldb);
     }
   }
 }
@@ -179,14 +205,14 @@ template <typename TF, typename TL, int NC>
 void launch_solve_t(hodlr_mat m, SolveFactors<TF, TL> F, const double* x, int64_t ldx, double* y, int64_t ldy, int nc,
                     hipStream_t s) {
   const TF* IL = F.IL;
-  hipLaunchKernelGGL((k_project<TF, NC>), dim3(m->nwu), dim3(64), 0, s, m->P, m->wu, 0, IL, x, ldx, nc, m->partL,
-                     m->Lmax);
-  if (m->nnu) hipLaunchKernelGGL(k_reduce, dim3(m->nnu), dim3(64), 0, s, m->P, m->nu, 0, nc, m->partL, m->zL, m->Lmax);
-  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(m->nwu), dim3(64), 0, s, m->P, F, m->wu, 0, x, ldx, m->ytmp,
-                     m->total_n, nc, m->zL, m->partU, m->Lmax, m->b);
-  if (m->nnu) hipLaunchKernelGGL(k_reduce, dim3(m->nnu), dim3(64), 0, s, m->P, m->nu, 1, nc, m->partU, m->zU, m->Lmax);
-  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(m->nwu), dim3(64), 0, s, m->P, F, m->wu, 1, m->ytmp, m->total_n, y,
-                     ldy, nc, m->zU, (double*)nullptr, m->Lmax, m->b);
+  const int64_t lv = m->total_leaves;
+  hipLaunchKernelGGL((k_project<TF, NC>), dim3(m->nwu), dim3(256), 0, s, m->P, m->wu, 0, IL, x, ldx, nc, m->partL, lv);
+  if (m->nnu) hipLaunchKernelGGL(k_reduce, dim3(m->nnu), dim3(256), 0, s, m->P, m->nu, 0, nc, m->partL, m->zL, lv);
+  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(m->nwu), dim3(256), 0, s, m->P, F, m->wu, 0, x, ldx, m->ytmp,
+                     m->total_n, nc, m->zL, m->partU, lv, m->b);
+  if (m->nnu) hipLaunchKernelGGL(k_reduce, dim3(m->nnu), dim3(256), 0, s, m->P, m->nu, 1, nc, m->partU, m->zU, lv);
+  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(m->nwu), dim3(256), 0, s, m->P, F, m->wu, 1, m->ytmp, m->total_n, y,
+                     ldy, nc, m->zU, (double*)nullptr, lv, m->b);
 }
 
 // y <- M_low^{-1} x at precision `prec` (x and y may alias: the first
@@ -225,6 +251,232 @@ void launch_axpby(int64_t nrows, int nc, double a, const double* x, int64_t ldx,
 }
 
 }  // namespace
+
+
+// ------------------------------------------------------------------
+// Multi-work-group factorisation: host schedule (post-order, lock-step
+// over the problems of the batch, which must share one tree shape).
+enum MwgKind { KL_LEAF = 0, KL_GRAM, KL_REDUCE, KL_CORE, KL_FORM, KL_SPP, KL_SPR, KL_SPE };
+
+static bool same_tree(hodlr_mat m) {
+  for (const Item& it : m->items)
+    if (it.n != m->items[0].n || it.L != m->items[0].L) return false;
+  return true;
+}
+
+static hodlr_status plan_mwg(hodlr_mat m) {
+  if (m->mwg_planned) return HODLR_OK;
+  const int B = m->batch;
+  const int L = m->items[0].L;
+  std::vector<NodeTask> tasks;
+  std::vector<GramUnit> grams;
+  std::vector<ReduceUnit> reds;
+  std::vector<int2> cores;
+  std::vector<FormUnit> forms;
+  std::vector<ProdJob> jobs;
+  std::vector<ProdUnit> punits;
+  size_t max_gpart = 1, max_ppart = 1, max_pz = 1;
+  auto node = [&](int d, int64_t j) { return m->nodes[node_index(m->items[0], d, j)]; };
+  auto rec = [&](int kind, int grid, int64_t off, int64_t off2) {
+    m->mwg_kind.push_back(kind);
+    m->mwg_grid.push_back(grid);
+    m->mwg_off.push_back(off);
+    m->mwg_off2.push_back(off2);
+  };
+  auto add_tasks = [&](int d, int64_t j) {
+    const int64_t t0 = int64_t(tasks.size());
+    for (int i = 0; i < B; ++i) tasks.push_back(NodeTask{i, d, int32_t(j), i});
+    return t0;
+  };
+  // grams (x^T y) over `rows` rows for each listed pair, then reduce into G[slot*9 + dst]
+  auto add_grams = [&](int64_t t0, int64_t rows, std::vector<std::array<int, 3>> pairs) {
+    const int64_t g0 = int64_t(grams.size());
+    const int64_t r0 = int64_t(reds.size());
+    const int chunks = int((rows + 1023) / 1024);
+    int32_t outi = 0;
+    for (int i = 0; i < B; ++i)
+      for (auto& p : pairs) {
+        reds.push_back(ReduceUnit{outi, chunks, int32_t(i * 9 + p[2]), 0});
+        for (int c = 0; c < chunks; ++c) grams.push_back(GramUnit{int32_t(i), int16_t(p[0]), int16_t(p[1]), c, outi++});
+      }
+    max_gpart = std::max(max_gpart, size_t(outi));
+    rec(KL_GRAM, int(grams.size() - g0), g0, t0);
+    rec(KL_REDUCE, int(reds.size() - r0), r0, t0);
+  };
+  auto add_core = [&](int64_t t0, std::vector<int> whiches) {
+    const int64_t c0 = int64_t(cores.size());
+    for (int i = 0; i < B; ++i)
+      for (int w : whiches) cores.push_back(make_int2(i, w));
+    rec(KL_CORE, int(cores.size() - c0), c0, t0);
+  };
+  auto add_form = [&](int64_t t0, std::vector<std::pair<int, int64_t>> outs) {
+    const int64_t f0 = int64_t(forms.size());
+    for (int i = 0; i < B; ++i)
+      for (auto& o : outs)
+        for (int64_t c = 0; c < (o.second + 255) / 256; ++c)
+          forms.push_back(FormUnit{int32_t(i), o.first, int32_t(c), 0});
+    rec(KL_FORM, int(forms.size() - f0), f0, t0);
+  };
+  // products: one job per (item, spec); spec = {child (0/1), which, trans, xarr, yarr, rk, sign}
+  struct Spec { int child, which, trans, xarr, yarr, rk; double sign; };
+  auto add_prods = [&](int d, int64_t j, std::vector<Spec> specs) {
+    const int64_t j0i = int64_t(jobs.size());
+    std::vector<ProdUnit> leafu, nodeu;
+    for (int i = 0; i < B; ++i)
+      for (auto& sp : specs) {
+        ProdJob jb{};
+        jb.item = i;
+        jb.d0 = int16_t(d + 1);
+        jb.j0 = int32_t(2 * j + sp.child);
+        jb.which = int16_t(sp.which);
+        jb.trans = int16_t(sp.trans);
+        jb.xarr = int8_t(sp.xarr);
+        jb.yarr = int8_t(sp.yarr);
+        jb.xlev = int16_t(d);
+        jb.ylev = int16_t(d);
+        jb.rd = int16_t(d);
+        jb.rj = int32_t(j);
+        jb.rk = int16_t(sp.rk);
+        jb.sign = sp.sign;
+        jb.unit0 = int32_t(leafu.size());
+        jb.node0 = int32_t(nodeu.size());
+        const int jid = int(jobs.size() - j0i);
+        const int64_t lo = int64_t(jb.j0) << (L - jb.d0), cnt = int64_t(1) << (L - jb.d0);
+        for (int64_t l = 0; l < cnt; ++l) leafu.push_back(ProdUnit{jid, int32_t(lo + l), 0, 0});
+        for (int dd = jb.d0; dd < L; ++dd)
+          for (int64_t q = 0; q < (int64_t(1) << (dd - jb.d0)); ++q)
+            nodeu.push_back(ProdUnit{jid, dd, int32_t((int64_t(jb.j0) << (dd - jb.d0)) + q), 0});
+        jobs.push_back(jb);
+      }
+    const int64_t lu0 = int64_t(punits.size());
+    punits.insert(punits.end(), leafu.begin(), leafu.end());
+    const int64_t nu0 = int64_t(punits.size());
+    punits.insert(punits.end(), nodeu.begin(), nodeu.end());
+    max_ppart = std::max(max_ppart, leafu.size());
+    max_pz = std::max(max_pz, nodeu.size());
+    rec(KL_SPP, int(leafu.size()), lu0, j0i);
+    if (!nodeu.empty()) rec(KL_SPR, int(nodeu.size()), nu0, j0i);
+    rec(KL_SPE, int(leafu.size()), lu0, j0i);
+  };
+  // post-order walk
+  std::vector<int> state(L + 2, 0);
+  int d = 0;
+  int64_t j = 0;
+  for (;;) {
+    if (d == L) {
+      const int64_t t0 = add_tasks(d, j);
+      rec(KL_LEAF, B, t0, t0);
+      if (d == 0) break;
+      --d;
+      j >>= 1;
+      continue;
+    }
+    if (state[d] == 0) {
+      state[d] = 1;
+      state[d + 1] = 0;
+      ++d;
+      j = 2 * j;
+      continue;
+    }
+    const Node nd = node(d, j);
+    const int64_t n1 = nd.size / 2, n2 = nd.size - n1;
+    if (state[d] == 1) {
+      int64_t t0 = add_tasks(d, j);
+      add_grams(t0, std::max(n1, n2), {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {3, 3, 3}});
+      add_core(t0, {0, 1});
+      add_form(t0, {{0, n1}, {1, n2}, {2, n2}, {3, n1}});
+      add_prods(d, j, {{0, 0, 0, A_T1, A_FU, 0, 1.0}, {0, 1, 1, A_T2, A_FL, 1, 1.0}});
+      add_grams(t0, n1, {{4, 7, 4}});
+      add_form(t0, {{4, n2}});
+      add_grams(t0, n2, {{5, 5, 5}, {6, 6, 6}});
+      add_core(t0, {2});
+      add_form(t0, {{5, n2}, {6, n2}});
+      state[d] = 2;
+      state[d + 1] = 0;
+      ++d;
+      j = 2 * j + 1;
+      continue;
+    }
+    add_prods(d, j, {{1, 0, 0, A_FL, A_IL, 1, -1.0}, {0, 0, 1, A_FL, A_IL, 1, 1.0},
+                     {0, 1, 0, A_FU, A_IU, 0, -1.0}, {1, 1, 1, A_FU, A_IU, 0, 1.0}});
+    if (d == 0) break;
+    --d;
+    j >>= 1;
+  }
+  TRY(dalloc(m, &m->d_tasks, tasks.size()));
+  TRY(dalloc(m, &m->d_gram, grams.size()));
+  TRY(dalloc(m, &m->d_red, reds.size()));
+  TRY(dalloc(m, &m->d_core, cores.size()));
+  TRY(dalloc(m, &m->d_form, forms.size()));
+  TRY(dalloc(m, &m->d_jobs, jobs.size()));
+  TRY(dalloc(m, &m->d_punits, punits.size()));
+  TRY(dalloc(m, &m->d_gpart, max_gpart * kG2));
+  TRY(dalloc(m, &m->d_G, size_t(B) * 9 * kG2));
+  TRY(dalloc(m, &m->d_M, size_t(B) * 3 * 2 * kMaxCat * kRS));
+  TRY(dalloc(m, &m->d_ppart, max_ppart * std::max(1, L) * kRS * kPNC));
+  TRY(dalloc(m, &m->d_pz, max_pz * kRS * kPNC));
+  auto up = [](void* dst, const void* src, size_t bytes) -> hodlr_status {
+    if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return HODLR_OK;
+  };
+  TRY(up(m->d_tasks, tasks.data(), tasks.size() * sizeof(NodeTask)));
+  TRY(up(m->d_gram, grams.data(), grams.size() * sizeof(GramUnit)));
+  TRY(up(m->d_red, reds.data(), reds.size() * sizeof(ReduceUnit)));
+  TRY(up(m->d_core, cores.data(), cores.size() * sizeof(int2)));
+  TRY(up(m->d_form, forms.data(), forms.size() * sizeof(FormUnit)));
+  TRY(up(m->d_jobs, jobs.data(), jobs.size() * sizeof(ProdJob)));
+  TRY(up(m->d_punits, punits.data(), punits.size() * sizeof(ProdUnit)));
+  m->mwg_planned = true;
+  return HODLR_OK;
+}
+
+static int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v ? atoi(v) : dflt;
+}
+
+static void enqueue_mwg(hodlr_mat m, hipStream_t s) {
+  const DevPtrs& P = m->P;
+  // block sizes of the latency-bound single-group kernels (512 measured fastest);
+  // the leaf kernel splits its dot products over blockDim/128 threads, so it needs >= 128
+  auto pick = [](int v) { return v >= 512 ? 512 : (v >= 256 ? 256 : 128); };
+  const int core_threads = pick(env_int("HODLR_CORE_THREADS", 512));
+  const int leaf_threads = pick(env_int("HODLR_LEAF_THREADS", 512));
+  const int Lmax = std::max(1, m->Lmax);
+  for (size_t q = 0; q < m->mwg_kind.size(); ++q) {
+    const int g = m->mwg_grid[q];
+    if (g <= 0) continue;
+    const int64_t off = m->mwg_off[q], off2 = m->mwg_off2[q];
+    switch (m->mwg_kind[q]) {
+      case KL_LEAF:
+        hipLaunchKernelGGL(k_leaf_task, dim3(g), dim3(leaf_threads), kFactorLdsBytes, s, P, m->d_tasks + off, m->b);
+        break;
+      case KL_GRAM:
+        hipLaunchKernelGGL(k_gram_partial, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_gram + off, m->d_gpart);
+        break;
+      case KL_REDUCE:
+        hipLaunchKernelGGL(k_gram_reduce, dim3(g), dim3(256), 0, s, m->d_red + off, m->d_gpart, m->d_G);
+        break;
+      case KL_CORE:
+        hipLaunchKernelGGL(k_core, dim3(g), dim3(core_threads), kFactorLdsBytes, s, P, m->d_tasks + off2, m->d_core + off, m->d_G,
+                           m->d_M, m->opts.max_rank);
+        break;
+      case KL_FORM:
+        hipLaunchKernelGGL(k_form, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_form + off, m->d_G, m->d_M);
+        break;
+      case KL_SPP:
+        hipLaunchKernelGGL(k_sp_project, dim3(g), dim3(256), 0, s, P, m->d_jobs + off2, m->d_punits + off, m->d_ppart, Lmax);
+        break;
+      case KL_SPR:
+        hipLaunchKernelGGL(k_sp_reduce, dim3(g), dim3(256), 0, s, P, m->d_jobs + off2, m->d_punits + off, m->d_ppart,
+                           m->d_pz, Lmax);
+        break;
+      default:
+        hipLaunchKernelGGL(k_sp_expand, dim3(g), dim3(128), 0, s, P, m->d_jobs + off2, m->d_punits + off, m->d_pz, m->b);
+        break;
+    }
+  }
+}
 
 // ===================================================================== ABI
 extern "C" {
@@ -279,6 +531,10 @@ static hodlr_status set_lds_limits() {
   static bool done = false;
   if (done) return HODLR_OK;
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(kFactorLdsBytes)));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_task),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(kFactorLdsBytes)));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_core),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(kFactorLdsBytes)));
   const int fl = int(size_t(kFftLds) * sizeof(double2));
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_small),
@@ -404,6 +660,7 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   ALLOC(P.Z, z0);
   ALLOC(P.rankL, node0);
   ALLOC(P.rankU, node0);
+  ALLOC(P.rankP, node0);
   ALLOC(P.tw, tw0);
   ALLOC(P.mu, tw0);
   ALLOC(P.fws, ws0);
@@ -420,10 +677,10 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   ALLOC(m->rbuf, row0 * kNCS);
   ALLOC(m->dbuf, row0 * kNCS);
   ALLOC(m->bbuf, row0 * kNCS);
-  ALLOC(m->norms, batch * kNCS * 2);
+  ALLOC(m->norms, batch * kNCS * 4);
   // FFT work lists
   {
-    std::vector<FftUnit> us, u1, u2;
+    std::vector<FftUnit> us, u1, u2, ur;
     for (int i = 0; i < batch; ++i) {
       if (m->items[i].fftlog <= kFftSmallMax) m->small_items.push_back(i);
       else m->big_items.push_back(i);
@@ -434,13 +691,18 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
       for (int i : m->big_items) {
         const int lg = m->items[i].fftlog;
         const int l2 = lg / 2, l1 = lg - l2;
-        int T = std::min(16, 8192 >> l1);
+        int T = std::min(4, 8192 >> l1);
+        m->fft4_lds = std::max(m->fft4_lds, size_t(T) * (size_t(1) << l1) * sizeof(double2));
         for (int t = 0; t < (1 << l1) / T; ++t) u1.push_back(FftUnit{i, c, t, 0});
         for (int t = 0; t < (1 << l2) / T; ++t) u2.push_back(FftUnit{i, c, t, 0});
+        for (int64_t t = 0; t < (m->items[i].n + 255) / 256; ++t) ur.push_back(FftUnit{i, c, int32_t(t), 0});
       }
     m->n_fft_small = int(m->small_items.size());
     m->n_fft_p1 = int(u1.size());
     m->n_fft_p2 = int(u2.size());
+    m->n_fft_rows = int(ur.size());
+    ALLOC(m->fft_row_units, ur.size());
+    if (!ur.empty()) HIP_TRY(hipMemcpy(m->fft_row_units, ur.data(), ur.size() * sizeof(FftUnit), hipMemcpyHostToDevice));
     ALLOC(m->fft_small_units, us.size());
     ALLOC(m->fft_p1_units, u1.size());
     ALLOC(m->fft_p2_units, u2.size());
@@ -458,6 +720,7 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   HIP_TRY(hipMemsetAsync(P.diag, 0, 4 * batch * sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(P.rankL, 0, node0 * sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(P.rankU, 0, node0 * sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P.rankP, 0, node0 * sizeof(int32_t), s));
   for (int i = 0; i < batch; ++i) {
     const Item& it = m->items[i];
     HIP_TRY(hipMemcpyAsync(P.dplus + it.row0, ops[i].d_plus, it.n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -483,7 +746,7 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
                        (const double*)nullptr, 0);
   }
   if (m->n_fft_p1) {
-    const size_t lds = size_t(8192) * sizeof(double2);
+    const size_t lds = m->fft4_lds;
     hipLaunchKernelGGL(k_fft4_pass1, dim3(m->n_fft_p1 / kNCF), dim3(512), lds, s, P, m->fft_p1_units, 0, false,
                        (const double*)nullptr, 0);
     hipLaunchKernelGGL(k_fft4_pass2, dim3(m->n_fft_p2 / kNCF), dim3(512), lds, s, P, m->fft_p2_units, 0, false,
@@ -495,6 +758,54 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   for (const Item& it : m->items) m->max_rank_A = std::max(m->max_rank_A, it.r);
   *out = m;
   return HODLR_OK;
+}
+
+// Algorithmic FP64 flops of the factorisation of Sec. 3.5 as carried out
+// (ranks read back from the device): per internal node the two
+// recompressions of the off-diagonal Schur blocks and the one of the pending
+// update (Gram matrices 2 m R^2, factor formation 2 m R r), the projections
+// that form U~12, V~21 and the four inverse-factor blocks (one HODLR product
+// of a child subtree on r columns each: 2 r (n b + 2 n sum of child ranks)),
+// C and W (2 n1 r^2, 2 n2 r^2); per leaf the Schur update 2 m^2 rp, the LU
+// (2/3) m^3 and the two triangular inverses (2/3) m^3.
+static double factor_flop_model(hodlr_mat m) {
+  std::vector<int32_t> rl(m->total_nodes), ru(m->total_nodes), rp(m->total_nodes);
+  (void)hipMemcpy(rl.data(), m->P.rankL, rl.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+  (void)hipMemcpy(ru.data(), m->P.rankU, ru.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+  (void)hipMemcpy(rp.data(), m->P.rankP, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+  double fl = 0.0;
+  for (const Item& it : m->items) {
+    // subtree product cost per column: leaves (m^2) + 2 * rows * rank per level below
+    std::vector<double> sub(size_t(1) << (it.L + 1), 0.0);   // per node (depth-major index)
+    auto idx = [&](int d, int64_t j) { return size_t((int64_t(1) << d) - 1 + j); };
+    for (int d = it.L; d >= 0; --d)
+      for (int64_t j = 0; j < (int64_t(1) << d); ++j) {
+        const Node nd = m->nodes[node_index(it, d, j)];
+        if (d == it.L) { sub[idx(d, j)] = double(nd.size) * nd.size; continue; }
+        const int64_t ni = node_index(it, d, j);
+        const double rr = 0.5 * (rl[ni] + ru[ni]);
+        sub[idx(d, j)] = sub[idx(d + 1, 2 * j)] + sub[idx(d + 1, 2 * j + 1)] + 4.0 * nd.size * rr;
+      }
+    for (int d = 0; d <= it.L; ++d)
+      for (int64_t j = 0; j < (int64_t(1) << d); ++j) {
+        const int64_t ni = node_index(it, d, j);
+        const Node nd = m->nodes[ni];
+        const double n = nd.size, pr = rp[ni];
+        if (d == it.L) {
+          fl += 2.0 * n * n * pr + (4.0 / 3.0) * n * n * n;
+          continue;
+        }
+        const double n1 = double(nd.size / 2), n2 = n - n1;
+        const double r = it.r, R = r + pr, r12 = ru[ni], r21 = rl[ni];
+        fl += 2 * (2.0 * n * R * R) + 2.0 * n * R * (r12 + r21);              // S12, S21 recompression
+        fl += 2.0 * n2 * (pr + r12) * (pr + r12) * 2 + 2.0 * n2 * (pr + r12) * r12;  // pending recompression
+        fl += 2.0 * n1 * r12 * r21 + 2.0 * n2 * r21 * r12;                      // C and W
+        const double s1 = sub[idx(d + 1, 2 * j)], s2 = sub[idx(d + 1, 2 * j + 1)];
+        fl += 2.0 * (r12 + r21) * s1;                                           // U~12, V~21
+        fl += 2.0 * r21 * (s1 + s2) + 2.0 * r12 * (s1 + s2);                    // inverse blocks
+      }
+  }
+  return fl;
 }
 
 hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info) {
@@ -528,6 +839,7 @@ hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info) {
   }
   info->bytes_factors = bytes;
   info->bytes_device = m->bytes_device;
+  info->factor_flops = m->factored ? factor_flop_model(m) : 0.0;
   return HODLR_OK;
 }
 
@@ -573,7 +885,14 @@ hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
   if (!m) return set_arg(ctx, 2);
   hipStream_t s = ctx->stream;
   const size_t lds = kFactorLdsBytes;
-  hipLaunchKernelGGL(k_factor, dim3(m->batch), dim3(kWG), lds, s, m->P, m->b, m->opts.max_rank);
+  const char* env = getenv("HODLR_FACTOR_PATH");
+  const bool single = (env && env[0] == 's') || !same_tree(m);
+  if (single) {
+    hipLaunchKernelGGL(k_factor, dim3(m->batch), dim3(kWG), lds, s, m->P, m->b, m->opts.max_rank);
+  } else {
+    TRY(plan_mwg(m));
+    enqueue_mwg(m, s);
+  }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   std::vector<int32_t> stv(m->batch), dg(4 * m->batch);
@@ -636,7 +955,7 @@ hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_
   const int prec = m->opts.prec;
   hodlr_status res = HODLR_OK;
   int iters = 0;
-  double worst = 0.0;
+  double worst = 0.0, worst_d = 0.0;
   bool fallback = false;
   for (int c0 = 0; c0 < nrhs; c0 += kNCS) {
     const int cn = std::min(kNCS, nrhs - c0);
@@ -647,50 +966,51 @@ hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_
       launch_solve(m, prec, xc, ld, xc, ld, cn, s);
       continue;
     }
-    // keep b
+    // keep b; x0 = M_low^{-1} b; then sweeps r = b - M x (exact), d = M_low^{-1} r,
+    // x += d, until ||d|| <= rtol ||x|| (the correction estimates the forward
+    // error; the residual of a stiff M floors near u ||M|| ||x||).
     HIP_TRY(hipMemcpy2DAsync(m->bbuf, tn * sizeof(double), xc, ld * sizeof(double), tn * sizeof(double), cn,
                              hipMemcpyDeviceToDevice, s));
-    launch_norms(m, m->bbuf, tn, cn, m->norms + m->batch * kNCS, s);
-    launch_solve(m, prec, m->bbuf, tn, xc, ld, cn, s);
-    std::vector<double> nr(m->batch * cn), nb(m->batch * cn);
-    HIP_TRY(hipMemcpyAsync(nb.data(), m->norms + m->batch * kNCS, nb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    double prev = 1e300;
-    bool conv = false;
-    for (int sweep = 0; sweep <= m->opts.refine_max; ++sweep) {
-      launch_fft_matvec(m, xc, ld, m->rbuf, tn, m->bbuf, tn, cn, s);
-      launch_norms(m, m->rbuf, tn, cn, m->norms, s);
-      HIP_TRY(hipMemcpyAsync(nr.data(), m->norms, nr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      double rel = 0.0;
-      for (size_t q = 0; q < nr.size(); ++q) rel = std::max(rel, nb[q] > 0 ? std::sqrt(nr[q] / nb[q]) : 0.0);
-      worst = rel;
-      if (rel <= m->opts.rtol) { conv = true; break; }
-      if (sweep == m->opts.refine_max || rel > 0.9 * prev) break;   // budget spent or stalled
-      prev = rel;
-      launch_solve(m, prec, m->rbuf, tn, m->dbuf, tn, cn, s);
-      launch_axpby(tn, cn, 1.0, xc, ld, 1.0, m->dbuf, tn, xc, ld, s);
-      iters = std::max(iters, sweep + 1);
-    }
-    if (!conv && prec == HODLR_FP64) {
-      res = HODLR_ENOCONV;
-    } else if (!conv) {
-      // FP64 fallback: FP64 factors + refinement with the same residual
-      fallback = true;
-      launch_solve(m, HODLR_FP64, m->bbuf, tn, xc, ld, cn, s);
-      for (int sweep = 0; sweep < 3; ++sweep) {
+    const int nb_off = m->batch * kNCS;
+    double* nrm = m->norms;   // [0]: ||r||^2  [1]: ||b||^2  [2]: ||d||^2  [3]: ||x||^2 (each batch x kNCS)
+    launch_norms(m, m->bbuf, tn, cn, nrm + nb_off, s);
+    auto sweep_loop = [&](int p, int maxsw, double& rel_r, double& rel_d) -> bool {
+      launch_solve(m, p, m->bbuf, tn, xc, ld, cn, s);
+      double prev = 1e300;
+      std::vector<double> h(4 * nb_off);
+      rel_r = rel_d = 1e300;
+      for (int sweep = 0; sweep < maxsw; ++sweep) {
         launch_fft_matvec(m, xc, ld, m->rbuf, tn, m->bbuf, tn, cn, s);
-        launch_solve(m, HODLR_FP64, m->rbuf, tn, m->dbuf, tn, cn, s);
+        launch_solve(m, p, m->rbuf, tn, m->dbuf, tn, cn, s);
         launch_axpby(tn, cn, 1.0, xc, ld, 1.0, m->dbuf, tn, xc, ld, s);
+        launch_norms(m, m->rbuf, tn, cn, nrm, s);
+        launch_norms(m, m->dbuf, tn, cn, nrm + 2 * nb_off, s);
+        launch_norms(m, xc, ld, cn, nrm + 3 * nb_off, s);
+        HIP_TRY(hipMemcpyAsync(h.data(), nrm, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        rel_r = rel_d = 0.0;
+        for (int q = 0; q < m->batch * cn; ++q) {
+          const double bq = h[nb_off + q], xq = h[3 * nb_off + q];
+          rel_r = std::max(rel_r, bq > 0 ? std::sqrt(h[q] / bq) : 0.0);
+          rel_d = std::max(rel_d, xq > 0 ? std::sqrt(h[2 * nb_off + q] / xq) : 0.0);
+        }
+        iters = std::max(iters, sweep + 1);
+        if (!(rel_d == rel_d)) return false;   // NaN
+        if (rel_d <= m->opts.rtol) return true;
+        if (rel_d > 0.9 * prev) return false;  // stalled or diverging
+        prev = rel_d;
       }
-      launch_fft_matvec(m, xc, ld, m->rbuf, tn, m->bbuf, tn, cn, s);
-      launch_norms(m, m->rbuf, tn, cn, m->norms, s);
-      HIP_TRY(hipMemcpyAsync(nr.data(), m->norms, nr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      double rel = 0.0;
-      for (size_t q = 0; q < nr.size(); ++q) rel = std::max(rel, nb[q] > 0 ? std::sqrt(nr[q] / nb[q]) : 0.0);
-      worst = rel;
-      res = HODLR_ENOCONV;
+      return false;
+    };
+    double rr = 0, rd = 0;
+    bool conv = sweep_loop(prec, m->opts.refine_max, rr, rd);
+    if (!conv && prec != HODLR_FP64) {
+      fallback = true;
+      conv = sweep_loop(HODLR_FP64, std::max(4, m->opts.refine_max), rr, rd);
     }
+    if (!conv) res = HODLR_ENOCONV;
+    worst = std::max(worst, rr);
+    worst_d = std::max(worst_d, rd);
   }
   HIP_TRY(hipGetLastError());
   if (info) {
@@ -702,6 +1022,7 @@ hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_
     info->leaf = -1;
     info->row = -1;
     info->used_fallback = fallback ? 1 : 0;
+    info->rel_correction = worst_d;
   }
   return res;
 }
@@ -770,7 +1091,19 @@ hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const doubl
     double rel = 0.0;
     for (int q = 0; q < m->batch; ++q) rel = std::max(rel, nb[q] > 0 ? std::sqrt(nr[q] / nb[q]) : 0.0);
     info->rel_residual = rel;
-    info->status = (sweeps > 0 && rel > m->opts.rtol) ? HODLR_ENOCONV : HODLR_OK;
+    info->rel_correction = 0.0;
+    if (sweeps > 0) {
+      // size of the last correction of the last step relative to u
+      launch_norms(m, m->dbuf, tn, 1, m->norms, s);
+      launch_norms(m, u, tn, 1, m->norms + m->batch * kNCS, s);
+      HIP_TRY(hipMemcpyAsync(nr.data(), m->norms, nr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(nb.data(), m->norms + m->batch * kNCS, nb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double rd = 0.0;
+      for (int q = 0; q < m->batch; ++q) rd = std::max(rd, nb[q] > 0 ? std::sqrt(nr[q] / nb[q]) : 0.0);
+      info->rel_correction = rd;
+    }
+    info->status = (sweeps > 0 && info->rel_correction > m->opts.rtol) ? HODLR_ENOCONV : HODLR_OK;
     return hodlr_status(info->status);
   }
   return HODLR_OK;

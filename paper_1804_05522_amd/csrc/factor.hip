@@ -150,51 +150,77 @@ __device__ void wg_copy_cols(const double* X, int64_t ldx, int64_t m, int nc, do
   wg_sync();
 }
 
+// Wave-level reductions (wave64).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline void wave_argmax(double& v, int& idx) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o);
+    const int oi = __shfl_xor(idx, o);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
 // Pivoted Cholesky of the R x R PSD matrix G (LDS, ld kLdG):  G ~ Lc Lc^T,
-// Lc (LDS, R x k, ld kLdG) in original row order.  Stops when the largest
+// Lc (LDS, R x k, ld kLdG) in original row order.  Right-looking: each step
+// takes the largest remaining diagonal entry (wave argmax), forms the column
+// and subtracts its outer product from G in parallel.  Stops when the largest
 // remaining diagonal entry falls below delta * (largest initial one).
+// G is overwritten by the Schur complement.
 __device__ int wg_pchol(double* G, int R, double* Lc, double* dv, int* done, double delta) {
   const int t = threadIdx.x;
-  __shared__ double s_piv;
+  __shared__ double s_piv, s_dmax;
   __shared__ int s_p, s_stop;
-  for (int i = t; i < R; i += kWG) {
+  for (int i = t; i < R; i += blockDim.x) {
     dv[i] = G[i + i * kLdG];
     done[i] = 0;
   }
   wg_sync();
-  double dmax0 = 0;
-  for (int i = 0; i < R; ++i) dmax0 = fmax(dmax0, dv[i]);
+  if (t < 64) {
+    double v = t < R ? dv[t] : -1.0;
+    int ix = t;
+    wave_argmax(v, ix);
+    if (t == 0) s_dmax = v;
+  }
+  wg_sync();
+  const double dmax0 = s_dmax;
   int k = 0;
   for (; k < R; ++k) {
-    if (t == 0) {
-      int p = -1;
-      double v = -1.0;
-      for (int i = 0; i < R; ++i)
-        if (!done[i] && dv[i] > v) { v = dv[i]; p = i; }
-      s_stop = (p < 0 || !(v > delta * dmax0) || !(v > 0.0)) ? 1 : 0;
-      s_p = p;
-      s_piv = s_stop ? 1.0 : sqrt(v);
-      if (!s_stop) done[p] = 1;
+    if (t < 64) {
+      double v = (t < R && !done[t]) ? dv[t] : -1.0;
+      int ix = t;
+      wave_argmax(v, ix);
+      if (t == 0) {
+        s_stop = (!(v > delta * dmax0) || !(v > 0.0)) ? 1 : 0;
+        s_p = ix;
+        s_piv = s_stop ? 1.0 : sqrt(v);
+        if (!s_stop) done[ix] = 1;
+      }
     }
     wg_sync();
     if (s_stop) break;
     const int p = s_p;
     const double piv = s_piv;
-    for (int i = t; i < R; i += kWG) {
+    for (int i = t; i < R; i += blockDim.x) {
       double c;
-      if (i == p) {
-        c = piv;
-      } else if (done[i]) {
-        c = 0.0;
-      } else {
-        c = G[i + p * kLdG];
-        for (int s = 0; s < k; ++s) c -= Lc[i + s * kLdG] * Lc[p + s * kLdG];
-        c /= piv;
-      }
+      if (i == p) c = piv;
+      else if (done[i]) c = 0.0;
+      else c = G[i + p * kLdG] / piv;
       Lc[i + k * kLdG] = c;
     }
     wg_sync();
-    for (int i = t; i < R; i += kWG) {
+    for (int e = t; e < R * R; e += blockDim.x) {
+      const int i = e % R, j = e / R;
+      G[i + j * kLdG] -= Lc[i + k * kLdG] * Lc[j + k * kLdG];
+    }
+    for (int i = t; i < R; i += blockDim.x) {
       const double c = Lc[i + k * kLdG];
       if (!done[i]) dv[i] -= c * c;
     }
@@ -207,79 +233,107 @@ __device__ int wg_pchol(double* G, int R, double* Lc, double* dv, int* done, dou
 // when the Frobenius norm of the trailing block is <= tau.  On return the
 // upper triangle holds R, the Householder vectors sit below the diagonal
 // (unit leading entry implicit), tv holds their scalars, perm the column order.
+// Column norms are recomputed exactly every step (one wave per column, lanes =
+// rows), so tiny trailing norms are not lost to cancellation.
 __device__ int wg_qrcp(double* K, int kA, int kB, double tau, int* perm, double* tv, double* cn) {
   const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+  const int nwaves = blockDim.x >> 6;
   __shared__ int s_p, s_stop;
   __shared__ double s_beta, s_tau, s_sc;
-  for (int j = t; j < kB; j += kWG) perm[j] = j;
+  for (int j = t; j < kB; j += blockDim.x) perm[j] = j;
   wg_sync();
   const int kmax = kA < kB ? kA : kB;
   int step = 0;
   for (; step < kmax; ++step) {
-    for (int j = t; j < kB; j += kWG) {
-      if (j >= step) {
-        double s = 0;
-        for (int i = step; i < kA; ++i) s += K[i + j * kLdG] * K[i + j * kLdG];
-        cn[j] = s;
-      }
+    for (int j = step + wave; j < kB; j += nwaves) {
+      const double x = (lane >= step && lane < kA) ? K[lane + j * kLdG] : 0.0;
+      const double s = wave_sum(x * x);
+      if (lane == 0) cn[j] = s;
     }
     wg_sync();
-    if (t == 0) {
-      double tot = 0, best = -1;
-      int p = step;
-      for (int j = step; j < kB; ++j) {
-        tot += cn[j];
-        if (cn[j] > best) { best = cn[j]; p = j; }
+    if (t < 64) {
+      double v = (t >= step && t < kB) ? cn[t] : -1.0;
+      const double tot = wave_sum((t >= step && t < kB) ? cn[t] : 0.0);
+      int ix = t;
+      wave_argmax(v, ix);
+      if (t == 0) {
+        s_stop = (tot <= tau * tau) ? 1 : 0;
+        s_p = ix;
       }
-      s_stop = (tot <= tau * tau) ? 1 : 0;
-      s_p = p;
     }
     wg_sync();
     if (s_stop) break;
     const int p = s_p;
     if (p != step) {
-      for (int i = t; i < kA; i += kWG) {
-        double a = K[i + step * kLdG];
+      for (int i = t; i < kA; i += blockDim.x) {
+        const double a = K[i + step * kLdG];
         K[i + step * kLdG] = K[i + p * kLdG];
         K[i + p * kLdG] = a;
       }
       if (t == 0) {
-        int q = perm[step]; perm[step] = perm[p]; perm[p] = q;
+        const int q = perm[step];
+        perm[step] = perm[p];
+        perm[p] = q;
+      }
+      wg_sync();
+    }
+    if (t < 64) {
+      const double x0 = K[step + step * kLdG];
+      const double xi = (t > step && t < kA) ? K[t + step * kLdG] : 0.0;
+      const double s = wave_sum(xi * xi);
+      if (t == 0) {
+        const double nrm = sqrt(x0 * x0 + s);
+        if (nrm == 0.0) {
+          s_beta = 0.0; s_tau = 0.0; s_sc = 0.0;
+        } else {
+          const double beta = x0 >= 0 ? -nrm : nrm;
+          s_beta = beta;
+          s_tau = (beta - x0) / beta;
+          s_sc = 1.0 / (x0 - beta);
+        }
       }
     }
     wg_sync();
-    if (t == 0) {
-      double x0 = K[step + step * kLdG];
-      double s = 0;
-      for (int i = step + 1; i < kA; ++i) s += K[i + step * kLdG] * K[i + step * kLdG];
-      double nrm = sqrt(x0 * x0 + s);
-      if (nrm == 0.0) {
-        s_beta = 0.0; s_tau = 0.0; s_sc = 0.0;
-      } else {
-        double beta = x0 >= 0 ? -nrm : nrm;
-        s_beta = beta;
-        s_tau = (beta - x0) / beta;
-        s_sc = 1.0 / (x0 - beta);
-      }
-    }
-    wg_sync();
-    for (int i = step + 1 + t; i < kA; i += kWG) K[i + step * kLdG] *= s_sc;
-    wg_sync();
+    for (int i = step + 1 + t; i < kA; i += blockDim.x) K[i + step * kLdG] *= s_sc;
     if (t == 0) {
       K[step + step * kLdG] = s_beta;
       tv[step] = s_tau;
     }
+    wg_sync();
     const double tq = s_tau;
-    for (int j = step + 1 + t; j < kB; j += kWG) {
-      double w = K[step + j * kLdG];
-      for (int i = step + 1; i < kA; ++i) w += K[i + step * kLdG] * K[i + j * kLdG];
-      w *= tq;
-      K[step + j * kLdG] -= w;
-      for (int i = step + 1; i < kA; ++i) K[i + j * kLdG] -= w * K[i + step * kLdG];
+    for (int j = step + 1 + wave; j < kB; j += nwaves) {
+      const double v = (lane == step) ? 1.0 : ((lane > step && lane < kA) ? K[lane + step * kLdG] : 0.0);
+      const double kij = (lane >= step && lane < kA) ? K[lane + j * kLdG] : 0.0;
+      const double w = tq * wave_sum(v * kij);
+      if (lane >= step && lane < kA) K[lane + j * kLdG] = kij - w * v;
     }
     wg_sync();
   }
   return step;
+}
+
+// Q = H_0 ... H_{r-1} [I_r; 0] (kA x r) into Q (LDS, ld kLdG) from the vectors
+// left in K by wg_qrcp; one wave per column.
+__device__ void wg_form_q(const double* K, int kA, int r, const double* tv, double* Q) {
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+  const int nwaves = blockDim.x >> 6;
+  for (int e = t; e < kA * r; e += blockDim.x) {
+    const int i = e % kA, j = e / kA;
+    Q[i + j * kLdG] = (i == j) ? 1.0 : 0.0;
+  }
+  wg_sync();
+  for (int s = r - 1; s >= 0; --s) {
+    const double ts = tv[s];
+    for (int c = wave; c < r; c += nwaves) {
+      const double v = (lane == s) ? 1.0 : ((lane > s && lane < kA) ? K[lane + s * kLdG] : 0.0);
+      const double q = (lane >= s && lane < kA) ? Q[lane + c * kLdG] : 0.0;
+      const double w = ts * wave_sum(v * q);
+      if (lane >= s && lane < kA) Q[lane + c * kLdG] = q - w * v;
+    }
+    wg_sync();
+  }
 }
 
 struct RecompressOut {
@@ -321,7 +375,7 @@ __device__ __noinline__ RecompressOut wg_recompress(const Cat& A, int64_t m, con
     KC[i + j * kLdG] = (zi || zj) ? 0.0 : KC[i + j * kLdG] / (di * dj);
   }
   wg_sync();
-  const double delta = 1e-28;
+  const double delta = 1e-15 * R;
   const int kA = wg_pchol(G, R, LA, vec + 192, ivec, delta);
   const int kB = wg_pchol(KC, R, LB, vec + 192, ivec, delta);
   if (kA == 0 || kB == 0) return out;
@@ -342,22 +396,7 @@ __device__ __noinline__ RecompressOut wg_recompress(const Cat& A, int64_t m, con
   out.rank = r;
   if (r == 0) return out;
   // Q = H_0 ... H_{r-1} [I_r; 0]  (kA x r) into G
-  for (int e = t; e < kA * r; e += kWG) {
-    const int i = e % kA, j = e / kA;
-    G[i + j * kLdG] = (i == j) ? 1.0 : 0.0;
-  }
-  wg_sync();
-  for (int s = r - 1; s >= 0; --s) {
-    const double ts = vec[256 + s];
-    for (int c = t; c < r; c += kWG) {
-      double w = G[s + c * kLdG];
-      for (int i = s + 1; i < kA; ++i) w += KC[i + s * kLdG] * G[i + c * kLdG];
-      w *= ts;
-      G[s + c * kLdG] -= w;
-      for (int i = s + 1; i < kA; ++i) G[i + c * kLdG] -= w * KC[i + s * kLdG];
-    }
-    wg_sync();
-  }
+  wg_form_q(KC, kA, r, vec + 256, G);
   // M_U = D * LB[:, perm[0:r]] * R11^{-1}  (R x r) into red
   for (int i = t; i < R; i += kWG) {
     for (int j = 0; j < r; ++j) {
@@ -509,7 +548,7 @@ __device__ __noinline__ bool wg_leaf(const DevPtrs& P, const Item& it, int b, in
   __shared__ int s_p;
   __shared__ int s_bad;
   __shared__ int s_perm[kMaxLeaf];
-  for (int e = t; e < m * rp; e += kWG) {
+  for (int e = t; e < m * rp; e += blockDim.x) {
     const int i = e % m, s = e / m;
     PL[i + s * kMaxLeaf] = PP[lf.start + i + int64_t(s) * it.n];
     QL[i + s * kMaxLeaf] = PQ[lf.start + i + int64_t(s) * it.n];
@@ -518,7 +557,7 @@ __device__ __noinline__ bool wg_leaf(const DevPtrs& P, const Item& it, int b, in
   if (t == 0) s_bad = 0;
   wg_sync();
   const double* A = P.Aleaf + gl * int64_t(b) * b;
-  for (int e = t; e < b * b; e += kWG) {
+  for (int e = t; e < b * b; e += blockDim.x) {
     const int i = e % b, j = e / b;
     double v = A[e];
     if (i < m && j < m)
@@ -527,21 +566,22 @@ __device__ __noinline__ bool wg_leaf(const DevPtrs& P, const Item& it, int b, in
   }
   wg_sync();
   for (int j = 0; j < b; ++j) {
-    if (t == 0) {
-      int p = j;
-      double best = fabs(S[j + j * kLdsLeaf]);
-      for (int i = j + 1; i < b; ++i) {
-        double v = fabs(S[i + j * kLdsLeaf]);
-        if (v > best) { best = v; p = i; }
+    if (t < 64) {
+      double v = (t >= j && t < b) ? fabs(S[t + j * kLdsLeaf]) : -1.0;
+      if (v != v) v = 1e308;   // a NaN pivot candidate is picked and flagged
+      int ix = t;
+      wave_argmax(v, ix);
+      if (t == 0) {
+        const double pv = S[ix + j * kLdsLeaf];
+        if (!(fabs(pv) > 0.0) || !isfinite(pv)) s_bad = 1;
+        s_p = ix;
+        if (ix != j) { int q = s_perm[j]; s_perm[j] = s_perm[ix]; s_perm[ix] = q; }
       }
-      if (!(best > 0.0) || !isfinite(best)) s_bad = 1;
-      s_p = p;
-      if (p != j) { int q = s_perm[j]; s_perm[j] = s_perm[p]; s_perm[p] = q; }
     }
     wg_sync();
     const int p = s_p;
     if (p != j) {
-      for (int c = t; c < b; c += kWG) {
+      for (int c = t; c < b; c += blockDim.x) {
         double a = S[j + c * kLdsLeaf];
         S[j + c * kLdsLeaf] = S[p + c * kLdsLeaf];
         S[p + c * kLdsLeaf] = a;
@@ -550,39 +590,52 @@ __device__ __noinline__ bool wg_leaf(const DevPtrs& P, const Item& it, int b, in
     }
     const double piv = S[j + j * kLdsLeaf];
     const double ip = (piv != 0.0) ? 1.0 / piv : 0.0;
-    for (int i = j + 1 + t; i < b; i += kWG) S[i + j * kLdsLeaf] *= ip;
+    for (int i = j + 1 + t; i < b; i += blockDim.x) S[i + j * kLdsLeaf] *= ip;
     wg_sync();
     const int rem = b - j - 1;
-    for (int e = t; e < rem * rem; e += kWG) {
+    for (int e = t; e < rem * rem; e += blockDim.x) {
       const int i = j + 1 + e % rem, c = j + 1 + e / rem;
       S[i + c * kLdsLeaf] -= S[i + j * kLdsLeaf] * S[j + c * kLdsLeaf];
     }
     wg_sync();
   }
-  // inverses: thread c < b builds column c of L^{-1}; thread b + c column c of U^{-1}
-  if (t < b) {
-    const int c = t;
-    for (int i = 0; i < b; ++i) LI[i + c * kLdsLeaf] = 0.0;
-    LI[c + c * kLdsLeaf] = 1.0;
-    for (int i = c + 1; i < b; ++i) {
-      double s = 0;
-      for (int k = c; k < i; ++k) s -= S[i + k * kLdsLeaf] * LI[k + c * kLdsLeaf];
-      LI[i + c * kLdsLeaf] = s;
+  // inverses, row by row with 4 threads per dot product: L^{-1} by forward
+  // substitution (threads 0..255: column c = t/4), U^{-1} by backward
+  // substitution (threads 256..511), one row of each per step.
+  {
+    const int nt = blockDim.x, half = nt >> 1;
+    const int tpd = half >= 64 ? half / 64 : 1;   // threads per dot product: 1, 2 or 4 (blockDim >= 128)
+    const int grp = t / half, loc = t % half, c = loc / tpd, q = loc % tpd;
+    for (int e = t; e < b * b; e += nt) {
+      const int i = e % b, jj = e / b;
+      LI[i + jj * kLdsLeaf] = (i == jj) ? 1.0 : 0.0;
+      UI[i + jj * kLdsLeaf] = 0.0;
     }
-  } else if (t < 2 * b) {
-    const int c = t - b;
-    for (int i = 0; i < b; ++i) UI[i + c * kLdsLeaf] = 0.0;
-    UI[c + c * kLdsLeaf] = 1.0 / S[c + c * kLdsLeaf];
-    for (int i = c - 1; i >= 0; --i) {
-      double s = 0;
-      for (int k = i + 1; k <= c; ++k) s -= S[i + k * kLdsLeaf] * UI[k + c * kLdsLeaf];
-      UI[i + c * kLdsLeaf] = s / S[i + i * kLdsLeaf];
+    wg_sync();
+    for (int step = 0; step < b; ++step) {
+      if (grp == 0) {
+        const int i = step;                      // row of L^{-1}
+        double s = 0.0;
+        if (c < i)
+          for (int k = c + q; k < i; k += tpd) s -= S[i + k * kLdsLeaf] * LI[k + c * kLdsLeaf];
+        if (tpd > 1) s += __shfl_xor(s, 1);
+        if (tpd > 2) s += __shfl_xor(s, 2);
+        if (c < i && q == 0) LI[i + c * kLdsLeaf] = s;
+      } else {
+        const int i = b - 1 - step;              // row of U^{-1}
+        double s = 0.0;
+        if (c > i && c < b)
+          for (int k = i + 1 + q; k <= c; k += tpd) s -= S[i + k * kLdsLeaf] * UI[k + c * kLdsLeaf];
+        if (tpd > 1) s += __shfl_xor(s, 1);
+        if (tpd > 2) s += __shfl_xor(s, 2);
+        if (q == 0 && c >= i && c < b) UI[i + c * kLdsLeaf] = (c == i ? 1.0 : s) / S[i + i * kLdsLeaf];
+      }
+      wg_sync();
     }
   }
-  wg_sync();
   double* LUo = P.LU + gl * int64_t(b) * b;
   double* LUi = P.LUinv + gl * int64_t(b) * b;
-  for (int e = t; e < b * b; e += kWG) {
+  for (int e = t; e < b * b; e += blockDim.x) {
     const int i = e % b, j = e / b;
     LUo[e] = S[i + j * kLdsLeaf];
     LUi[e] = (i > j) ? LI[i + j * kLdsLeaf] : UI[i + j * kLdsLeaf];
@@ -615,6 +668,7 @@ __global__ void __launch_bounds__(kWG) k_factor(DevPtrs P, int b, int rmax) {
   prank[0] = 0;
   const double tau = it.tau;
   for (;;) {
+    if (t == 0 && (d == it.L || state[d] == 0)) P.rankP[node_index(it, d, j)] = prank[d];
     if (d == it.L) {
       const double* PPs = lvl_ptr(P.PP, it, psrc[d]);
       const double* PQs = lvl_ptr(P.PQ, it, psrc[d]);

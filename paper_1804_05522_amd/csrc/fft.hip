@@ -201,7 +201,7 @@ __device__ inline void four_step_dims(int logM, int& l1, int& l2, int& tile) {
   l2 = logM / 2;
   l1 = logM - l2;
   tile = kFftLds >> l1;
-  if (tile > 16) tile = 16;
+  if (tile > 4) tile = 4;   // 64-byte contiguous segments, many work-groups per pass
 }
 
 // Pass 1: transforms over n2 (length M2) for `tile` adjacent n1, then the
@@ -249,7 +249,8 @@ __global__ void __launch_bounds__(kFftWG) k_fft4_pass1(DevPtrs P, const FftUnit*
 
 // Pass 2: transforms over n1 (length M1) for `tile` adjacent k2; output index
 // k = k2 + M2 k1.  setup: mu; forward matvec: W = mu . X (second half of the
-// scratch); inverse: the final product rows.
+// scratch); inverse: the far-field products (scaled by 1/M) in natural order
+// into the first half of the scratch, for k_exact_rows.
 __global__ void __launch_bounds__(kFftWG) k_fft4_pass2(DevPtrs P, const FftUnit* units, int mode, bool inverse,
                                                       const double* x, int64_t ldx, double* y, int64_t ldy,
                                                       const double* b, int64_t ldb) {
@@ -286,9 +287,25 @@ __global__ void __launch_bounds__(kFftWG) k_fft4_pass2(DevPtrs P, const FftUnit*
     } else if (!inverse) {
       Wout[k] = cmul(v, mu[k]);
     } else if (k < it.n) {
-      yc[k] = exact_row(P, it, xc, k, v.x * inv, v.y * inv, bc);
+      ws[k] = make_double2(v.x * inv, v.y * inv);
     }
   }
+  (void)xc; (void)yc; (void)bc;
+}
+
+// Near-field rows (double-double) plus the far-field values left by the
+// inverse pass 2; one thread per row.
+__global__ void __launch_bounds__(256) k_exact_rows(DevPtrs P, const FftUnit* units, const double* x, int64_t ldx,
+                                                    double* y, int64_t ldy, const double* b, int64_t ldb) {
+  const FftUnit u = units[blockIdx.x];
+  const Item it = P.items[u.item];
+  const int64_t i = int64_t(u.tile) * blockDim.x + threadIdx.x;
+  if (i >= it.n) return;
+  const int64_t M = int64_t(1) << it.fftlog;
+  const double2 w = P.fws[it.ws0 + int64_t(u.col) * 2 * M + i];
+  const double* xc = x + it.row0 + int64_t(u.col) * ldx;
+  const double* bc = b ? b + it.row0 + int64_t(u.col) * ldb : nullptr;
+  y[it.row0 + int64_t(u.col) * ldy + i] = exact_row(P, it, xc, i, w.x, w.y, bc);
 }
 
 }  // namespace hfde

@@ -4,6 +4,7 @@
 #include "internal.hpp"
 #include "build.hip"
 #include "factor.hip"
+#include "factor_mwg.hip"
 #include "solve.hip"
 #include "fft.hip"
 #include "api.hip"

@@ -78,6 +78,7 @@ struct DevPtrs {
   double* Z;             // hmatvec scratch
   int32_t* rankL;        // per node: rank of the L-factor block (and of IL)
   int32_t* rankU;        // per node: rank of the U-factor block (and of IU)
+  int32_t* rankP;        // per node: rank of the pending Schur update it was factored with
   double2* tw;           // FFT twiddles
   double2* mu;           // far-field circulant multipliers
   double2* fws;          // FFT scratch

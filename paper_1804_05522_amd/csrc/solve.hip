@@ -28,133 +28,185 @@ __device__ inline double ld(const bf16* p) {
 }
 
 
-// Partial projection of v (rows of this leaf) onto the basis B at every
-// level where the leaf lies in the source child.
-template <typename TF>
+// Partial projections of the leaf's rows v (LDS, m x nc, ld 64) onto the
+// basis B of every level where the leaf lies in the source child.  The 256
+// threads are (level slot, rank index) pairs: slot = t / 32 takes levels
+// slot, slot + 8, ...; each thread walks the leaf's rows down one basis
+// column (a contiguous 512-byte run), so loads are independent and many are
+// in flight.  Partials are level-major: part[(d * leaves + gl) * kRS * nc + s + c kRS].
+template <typename TF, int NC>
 __device__ void leaf_project(const DevPtrs& P, const Item& it, int leaf, const Node& lf, const TF* Bb,
-                             const int32_t* ranks, int src_side, const double* vl /*LDS m x nc, ld 64*/,
-                             int nc, double* part, int Lmax, double* sh /*LDS 32*65*/, int vst) {
+                             const int32_t* ranks, int src_side, const double* vl, int nc, double* part,
+                             int64_t leaves) {
   const int t = threadIdx.x;
+  const int slot = t >> 5, s = t & 31;
   const int m = lf.size;
   const int64_t gl = it.leaf0 + leaf;
-  for (int d = 0; d < it.L; ++d) {
+  for (int d = slot; d < it.L; d += 8) {
     const int side = (leaf >> (it.L - d - 1)) & 1;
     if (side != src_side) continue;
     const int64_t nidx = node_index(it, d, leaf >> (it.L - d));
     const int r = ranks[nidx];
-    const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start;
-    double* pout = part + (gl * Lmax + d) * int64_t(kRS) * nc;
-    for (int c = 0; c < nc; ++c) {
-      if (t < m) {
-        const double xv = vl[t + c * vst];
-        for (int s = 0; s < r; ++s) sh[s * 65 + t] = ld(Bd + t + int64_t(s) * it.n) * xv;
-      }
-      __syncthreads();
-      if (t < r) {
-        double acc = 0;
-        for (int i = 0; i < m; ++i) acc += sh[t * 65 + i];
-        pout[t + c * kRS] = acc;
-      }
-      __syncthreads();
+    if (s >= r) continue;
+    const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + int64_t(s) * it.n;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double bv = ld(Bd + i);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c < nc) acc[c] += bv * vl[i + c * 64];
     }
+    double* pout = part + (int64_t(d) * leaves + gl) * int64_t(kRS) * nc + s;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < nc) pout[c * kRS] = acc[c];
   }
 }
 
 template <typename TF, int NC>
-__global__ void __launch_bounds__(64) k_project(DevPtrs P, const WorkUnit* wu, int which, const TF* Bb,
-                                                const double* x, int64_t ldx, int nc, double* part,
-                                                int Lmax) {
+__global__ void __launch_bounds__(256) k_project(DevPtrs P, const WorkUnit* wu, int which, const TF* Bb,
+                                                 const double* x, int64_t ldx, int nc, double* part,
+                                                 int64_t leaves) {
   __shared__ double vl[64 * NC];
-  __shared__ double sh[kRS * 65];
   const WorkUnit w = wu[blockIdx.x];
   const Item it = P.items[w.item];
   const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
   const int t = threadIdx.x;
   const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
   const int src_side = which == 0 ? 0 : 1;
-  for (int c = 0; c < nc; ++c)
-    if (t < lf.size) vl[t + c * 64] = x[it.row0 + lf.start + t + c * ldx];
+  for (int e = t; e < lf.size * nc; e += blockDim.x) {
+    const int i = e % lf.size, c = e / lf.size;
+    vl[i + c * 64] = x[it.row0 + lf.start + i + c * ldx];
+  }
   __syncthreads();
-  leaf_project<TF>(P, it, w.leaf, lf, Bb, ranks, src_side, vl, nc, part, Lmax, sh, 64);
+  leaf_project<TF, NC>(P, it, w.leaf, lf, Bb, ranks, src_side, vl, nc, part, leaves);
 }
 
-// z[node] = sum of the per-leaf partials over the leaves of the node's source child.
-__global__ void k_reduce(DevPtrs P, const NodeUnit* nu, int which, int nc, const double* part,
-                         double* z, int Lmax) {
+// z[node] = sum of the per-leaf partials over the leaves of the node's source
+// child.  256 threads = groups x (rank, column) entries; each group sums a
+// strided subset of the leaves, groups are combined in a fixed order.
+__global__ void __launch_bounds__(256) k_reduce(DevPtrs P, const NodeUnit* nu, int which, int nc,
+                                                const double* part, double* z, int64_t leaves) {
+  __shared__ double red[256];
   const NodeUnit u = nu[blockIdx.x];
   const Item it = P.items[u.item];
   const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
   const int64_t nidx = node_index(it, u.level, u.j);
   const int r = ranks[nidx];
   const int src_side = which == 0 ? 0 : 1;
-  const int64_t span = int64_t(1) << (it.L - u.level - 1);     // leaves per child
-  const int64_t first = (int64_t(u.j) * 2 + src_side) * span;
-  for (int e = threadIdx.x; e < r * nc; e += blockDim.x) {
-    const int s = e % r, c = e / r;
-    double acc = 0;
-    for (int64_t l = 0; l < span; ++l)
-      acc += part[((it.leaf0 + first + l) * Lmax + u.level) * int64_t(kRS) * nc + s + c * kRS];
-    z[nidx * int64_t(kRS) * nc + s + c * kRS] = acc;
+  const int64_t span = int64_t(1) << (it.L - u.level - 1);
+  const int64_t first = it.leaf0 + (int64_t(u.j) * 2 + src_side) * span;
+  const int E = r * nc;
+  if (E == 0) return;
+  for (int e0 = 0; e0 < E; e0 += 256) {
+    const int ecnt = min(256, E - e0);
+    const int groups = 256 / ecnt;
+    const int t = threadIdx.x;
+    const int g = t / ecnt, e = e0 + t % ecnt;
+    double acc = 0.0;
+    if (g < groups) {
+      const int s = e % r, c = e / r;
+      const double* pp = part + (int64_t(u.level) * leaves + first) * int64_t(kRS) * nc + s + c * kRS;
+      for (int64_t l = g; l < span; l += groups) acc += pp[l * int64_t(kRS) * nc];
+    }
+    red[t] = acc;
+    __syncthreads();
+    if (t < ecnt) {
+      double sum = 0.0;
+      for (int q = 0; q < groups; ++q) sum += red[q * ecnt + t];
+      const int ee = e0 + t;
+      const int s = ee % r, c = ee / r;
+      z[nidx * int64_t(kRS) * nc + s + c * kRS] = sum;
+    }
+    __syncthreads();
   }
 }
 
 // y = F x on this leaf's rows, F = L^{-1} (which = 0) or U^{-1} (which = 1),
 // x read from xin (global), result written to yout; if `next_part` is set,
-// also the per-leaf projections of y for U^{-1}.
+// also the per-leaf projections of y for U^{-1}.  256 threads = 4 slots x 64
+// rows: slot 0 applies the leaf block, slots 1..3 the expansions of levels
+// 0, 3, 6, ... / 1, 4, 7, ... / 2, 5, 8, ...; slot sums meet in LDS.
 template <typename TF, typename TL, int NC>
-__global__ void __launch_bounds__(64) k_expand(DevPtrs P, SolveFactors<TF, TL> F, const WorkUnit* wu, int which,
-                                               const double* xin, int64_t ldx, double* yout, int64_t ldy,
-                                               int nc, const double* z, double* next_part, int Lmax, int b) {
+__global__ void __launch_bounds__(256) k_expand(DevPtrs P, SolveFactors<TF, TL> F, const WorkUnit* wu, int which,
+                                                const double* xin, int64_t ldx, double* yout, int64_t ldy,
+                                                int nc, const double* z, double* next_part, int64_t leaves, int b) {
   __shared__ double vl[64 * NC];
-  __shared__ double yl[64 * NC];
-  __shared__ double sh[kRS * 65];
+  __shared__ double yl[4][64 * NC];
   __shared__ int pm[64];
   const WorkUnit w = wu[blockIdx.x];
   const Item it = P.items[w.item];
   const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
   const int t = threadIdx.x;
+  const int slot = t >> 6, row = t & 63;
   const int m = lf.size;
   const int64_t gl = it.leaf0 + w.leaf;
   const TL* Fi = F.LUinv + gl * int64_t(b) * b;
   const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
   const TF* Bb = which == 0 ? F.IL : F.IU;
   const int dst_side = which == 0 ? 1 : 0;
-  for (int c = 0; c < nc; ++c)
-    if (t < m) vl[t + c * 64] = xin[it.row0 + lf.start + t + c * ldx];
+  for (int e = t; e < m * nc; e += blockDim.x) {
+    const int i = e % m, c = e / m;
+    vl[i + c * 64] = xin[it.row0 + lf.start + i + c * ldx];
+  }
   if (t < m) pm[t] = P.perm[gl * b + t];
   __syncthreads();
-  if (t < m) {
-    for (int c = 0; c < nc; ++c) {
-      const double* x = vl + c * 64;
-      double acc = 0;
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  if (row < m) {
+    if (slot == 0) {
       if (which == 0) {
-        acc = x[pm[t]];
-        for (int j = 0; j < t; ++j) acc += ld(Fi + t + j * b) * x[pm[j]];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (c < nc) acc[c] = vl[pm[row] + c * 64];
+        for (int j = 0; j < row; ++j) {
+          const double f = ld(Fi + row + j * b);
+          const int pj = pm[j];
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            if (c < nc) acc[c] += f * vl[pj + c * 64];
+        }
       } else {
-        for (int j = t; j < m; ++j) acc += ld(Fi + t + j * b) * x[j];
+        for (int j = row; j < m; ++j) {
+          const double f = ld(Fi + row + j * b);
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            if (c < nc) acc[c] += f * vl[j + c * 64];
+        }
       }
-      yl[t + c * 64] = acc;
-    }
-    for (int d = 0; d < it.L; ++d) {
-      const int side = (w.leaf >> (it.L - d - 1)) & 1;
-      if (side != dst_side) continue;
-      const int64_t nidx = node_index(it, d, w.leaf >> (it.L - d));
-      const int r = ranks[nidx];
-      const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + t;
-      const double* zn = z + nidx * int64_t(kRS) * nc;
-      double bv[kRS];
-      for (int s = 0; s < r; ++s) bv[s] = ld(Bd + int64_t(s) * it.n);
-      for (int c = 0; c < nc; ++c) {
-        double acc = 0;
-        for (int s = 0; s < r; ++s) acc += bv[s] * zn[s + c * kRS];
-        yl[t + c * 64] += acc;
+    } else {
+      for (int d = slot - 1; d < it.L; d += 3) {
+        const int side = (w.leaf >> (it.L - d - 1)) & 1;
+        if (side != dst_side) continue;
+        const int64_t nidx = node_index(it, d, w.leaf >> (it.L - d));
+        const int r = ranks[nidx];
+        const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + row;
+        const double* zn = z + nidx * int64_t(kRS) * nc;
+        for (int s = 0; s < r; ++s) {
+          const double bv = ld(Bd + int64_t(s) * it.n);
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            if (c < nc) acc[c] += bv * zn[s + c * kRS];
+        }
       }
     }
-    for (int c = 0; c < nc; ++c) yout[it.row0 + lf.start + t + c * ldy] = yl[t + c * 64];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (c < nc) yl[slot][row + c * 64] = acc[c];
+  __syncthreads();
+  for (int e = t; e < m * nc; e += blockDim.x) {
+    const int i = e % m, c = e / m;
+    const double v = (yl[0][i + c * 64] + yl[1][i + c * 64]) + (yl[2][i + c * 64] + yl[3][i + c * 64]);
+    vl[i + c * 64] = v;
+    yout[it.row0 + lf.start + i + c * ldy] = v;
   }
   __syncthreads();
   if (next_part != nullptr)
-    leaf_project<TF>(P, it, w.leaf, lf, F.IU, P.rankU, 1, yl, nc, next_part, Lmax, sh, 64);
+    leaf_project<TF, NC>(P, it, w.leaf, lf, F.IU, P.rankU, 1, vl, nc, next_part, leaves);
 }
 
 // ---------------------------------------------------------------- helpers

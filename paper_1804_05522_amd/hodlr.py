@@ -40,13 +40,14 @@ class HodlrOpts(C.Structure):
 class HodlrInfo(C.Structure):
     _fields_ = [("status", C.c_int), ("refine_iters", C.c_int), ("rel_residual", C.c_double),
                 ("max_rank", C.c_int), ("leaf", C.c_int), ("row", C.c_int),
-                ("used_fallback", C.c_int)]
+                ("used_fallback", C.c_int), ("rel_correction", C.c_double)]
 
 
 class HodlrMatInfo(C.Structure):
     _fields_ = [("batch", C.c_int), ("leaf", C.c_int), ("max_levels", C.c_int),
                 ("total_n", C.c_int64), ("max_rank_A", C.c_int), ("max_rank_factors", C.c_int),
-                ("bytes_factors", C.c_size_t), ("bytes_device", C.c_size_t)]
+                ("bytes_factors", C.c_size_t), ("bytes_device", C.c_size_t),
+                ("factor_flops", C.c_double)]
 
 
 class LrMatrix(C.Structure):
