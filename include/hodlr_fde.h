@@ -176,30 +176,39 @@ typedef struct {
 } lr_matrix;
 
 typedef struct {
-  double tol;             /* stop when ||C - A X - X B^T||_F <= tol * ||C||_F */
-  int max_shifts;         /* cap on J */
-  int max_rank;           /* cap on the rank of the solution factors */
+  double tol;             /* target relative accuracy of each step (see fde2d_sylvester_step) */
+  int max_shifts;         /* cap on J, the number of shift pairs (<= 64) */
+  int max_rank;           /* cap on the rank of the solution factors (<= 32) */
 } fde2d_opts;
 
+/* Plan for one 2D problem: opx, opy are the 1D operators of the x and y
+ * directions with shift 1/2 (the split of the identity in Sec. 4.2).  The
+ * spectral intervals [s, s + 2 nu alpha max(d+ + d-)] (Gershgorin, strict
+ * diagonal dominance of Sec. 2.2.1) fix J and the shifts (Zolotarev problem,
+ * elliptic functions); A + q_j I and B + p_j I are built as one batched HODLR
+ * operator and factored with hopts (prec selects the factor precision). */
 hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
                                const hodlr_opts* hopts, const fde2d_opts* opts, fde2d_plan* out);
 void fde2d_plan_destroy(fde2d_plan p);
 int fde2d_plan_shifts(fde2d_plan p, double* p_shifts, double* q_shifts, int cap);
 
-/* One implicit Euler step: U_next = solution of A X + X B^T = U_m + dt F.
- * U_m, F: inputs (ranks may be 0).  U_next: caller-allocated factors with
- * `capacity` columns; on return U_next->rank holds the rank used.
- * X0 (optional, may be NULL): device dense nx x ny warm start (ld = nx);
- * the step then solves for the correction from the residual of X0 and
- * returns U_next as the low-rank correction added to X0 in `X0_out`
- * (device nx x ny, may alias X0).  rel_residual in info reports the exact
- * low-rank residual ||C - A X - X B^T||_F / ||C||_F. */
+/* One implicit Euler step of eq. (sylv-timestepping): U_next solves
+ *   A X + X B^T = C,  C = U_m + dt F,
+ * with every matrix in low-rank form.  U_m, F: inputs (rank 0 allowed; at
+ * most 32 columns each).  C is recompressed, then factored ADI sweeps with the
+ * plan's shifted HODLR solves run until the fADI residual G_J H_J^T is below
+ * opts.tol * ||C||_F; the solution factors are recompressed after every ADI
+ * step (relative truncation opts.tol / 10).  The exact residual
+ * C - A X - X B^T (exact Toeplitz products) then drives correction sweeps
+ * until the correction is below opts.tol * ||X||_F (at most 4).
+ * U_next: caller-allocated factors with `capacity` (>= the needed rank, <= 32)
+ * columns; on return U_next->rank is the rank used.  info->rel_residual:
+ * ||C - A X - X B^T||_F / ||C||_F before the last correction;
+ * info->rel_correction: the last correction relative to ||X||_F;
+ * info->refine_iters: ADI steps taken in total. */
 hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* U_m,
                                   const lr_matrix* F, double dt, lr_matrix* U_next,
                                   hodlr_info* info);
-hodlr_status fde2d_sylvester_step_dense(hodlr_ctx ctx, fde2d_plan p, const double* X0,
-                                        const double* C, double* X_out, int64_t ld,
-                                        int max_sweeps, double tol, hodlr_info* info);
 
 #ifdef __cplusplus
 }

@@ -10,6 +10,7 @@
 #include <array>
 #include <cstdlib>
 #include <vector>
+#include <functional>
 
 
 
@@ -109,7 +110,40 @@ struct hodlr_mat_s {
 };
 
 struct fde2d_plan_s {
-  int dummy;
+  hodlr_ctx ctx = nullptr;
+  hodlr_mat mat = nullptr;      // 2J shifted problems: x_j = A + q_j I (items 0..J-1), y_j = B + p_j I (J..2J-1)
+  hodlr_mat exact = nullptr;    // the unshifted A and B (exact products for the residual)
+  int J = 0;
+  std::vector<double> p, q;
+  int64_t nx = 0, ny = 0;
+  double shift_x = 0.5, shift_y = 0.5;
+  fde2d_opts opts{};
+  std::vector<int> pwu_off, pwu_cnt, pnu_off, pnu_cnt;
+  WorkUnit* pair_wu = nullptr;
+  NodeUnit* pair_nu = nullptr;
+  double* G = nullptr;          // residual factors (nx x 64 / ny x 64)
+  double* H = nullptr;
+  double* G0 = nullptr;         // right-hand side factors of the current sweep
+  double* H0 = nullptr;
+  double* Zx[2] = {nullptr, nullptr};   // solution factors (ping-pong)
+  double* Wx[2] = {nullptr, nullptr};
+  double* Zd[2] = {nullptr, nullptr};   // correction factors
+  double* Wd[2] = {nullptr, nullptr};
+  double* R1 = nullptr;         // residual recompression temporaries
+  double* R1w = nullptr;
+  double* xin = nullptr;        // (total rows of mat) x 64 solve workspace
+  double* ex_in = nullptr;      // (nx + ny) x 64 for the exact products
+  double* ex_out = nullptr;
+  int32_t* ranks = nullptr;     // device ranks, see kR_* below
+  LrJob* jobs = nullptr;        // device job slots
+  LrUnit* units = nullptr;
+  double* gpart = nullptr;
+  double* grams = nullptr;
+  double* mbuf = nullptr;
+  double* frob = nullptr;
+  int cap_gram = 0;             // gram units per job slot
+  int slot_units = 0;           // LrUnit entries per job slot
+  std::vector<void*> allocs;
 };
 
 namespace {
@@ -202,41 +236,47 @@ void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int
 }
 
 template <typename TF, typename TL, int NC>
-void launch_solve_t(hodlr_mat m, SolveFactors<TF, TL> F, const double* x, int64_t ldx, double* y, int64_t ldy, int nc,
-                    hipStream_t s) {
+void launch_solve_t(hodlr_mat m, SolveFactors<TF, TL> F, const WorkUnit* wu, int nwu, const NodeUnit* nu, int nnu,
+                    const double* x, int64_t ldx, double* y, int64_t ldy, int nc, hipStream_t s) {
   const TF* IL = F.IL;
   const int64_t lv = m->total_leaves;
-  hipLaunchKernelGGL((k_project<TF, NC>), dim3(m->nwu), dim3(256), 0, s, m->P, m->wu, 0, IL, x, ldx, nc, m->partL, lv);
-  if (m->nnu) hipLaunchKernelGGL(k_reduce, dim3(m->nnu), dim3(256), 0, s, m->P, m->nu, 0, nc, m->partL, m->zL, lv);
-  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(m->nwu), dim3(256), 0, s, m->P, F, m->wu, 0, x, ldx, m->ytmp,
+  hipLaunchKernelGGL((k_project<TF, NC>), dim3(nwu), dim3(256), 0, s, m->P, wu, 0, IL, x, ldx, nc, m->partL, lv);
+  if (nnu) hipLaunchKernelGGL(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 0, nc, m->partL, m->zL, lv);
+  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 0, x, ldx, m->ytmp,
                      m->total_n, nc, m->zL, m->partU, lv, m->b);
-  if (m->nnu) hipLaunchKernelGGL(k_reduce, dim3(m->nnu), dim3(256), 0, s, m->P, m->nu, 1, nc, m->partU, m->zU, lv);
-  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(m->nwu), dim3(256), 0, s, m->P, F, m->wu, 1, m->ytmp, m->total_n, y,
+  if (nnu) hipLaunchKernelGGL(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 1, nc, m->partU, m->zU, lv);
+  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 1, m->ytmp, m->total_n, y,
                      ldy, nc, m->zU, (double*)nullptr, lv, m->b);
 }
 
 // y <- M_low^{-1} x at precision `prec` (x and y may alias: the first
-// expansion writes ytmp, the second reads only ytmp).
-void launch_solve(hodlr_mat m, int prec, const double* x, int64_t ldx, double* y, int64_t ldy, int nc,
-                  hipStream_t s) {
+// expansion writes ytmp, the second reads only ytmp), over the problems whose
+// leaves / nodes are listed (all by default).
+void launch_solve_units(hodlr_mat m, int prec, const WorkUnit* wu, int nwu, const NodeUnit* nu, int nnu,
+                        const double* x, int64_t ldx, double* y, int64_t ldy, int nc, hipStream_t s) {
   for (int c0 = 0; c0 < nc; c0 += kNCS) {
     const int cn = std::min(kNCS, nc - c0);
     const double* xc = x + int64_t(c0) * ldx;
     double* yc = y + int64_t(c0) * ldy;
     if (prec == HODLR_MIXED_FP32) {
       SolveFactors<float, float> F{m->IL32, m->IU32, m->LUinv32};
-      if (cn == 1) launch_solve_t<float, float, 1>(m, F, xc, ldx, yc, ldy, cn, s);
-      else launch_solve_t<float, float, kNCS>(m, F, xc, ldx, yc, ldy, cn, s);
+      if (cn == 1) launch_solve_t<float, float, 1>(m, F, wu, nwu, nu, nnu, xc, ldx, yc, ldy, cn, s);
+      else launch_solve_t<float, float, kNCS>(m, F, wu, nwu, nu, nnu, xc, ldx, yc, ldy, cn, s);
     } else if (prec == HODLR_MIXED_BF16) {
       SolveFactors<bf16, float> F{m->IL16, m->IU16, m->LUinv32};
-      if (cn == 1) launch_solve_t<bf16, float, 1>(m, F, xc, ldx, yc, ldy, cn, s);
-      else launch_solve_t<bf16, float, kNCS>(m, F, xc, ldx, yc, ldy, cn, s);
+      if (cn == 1) launch_solve_t<bf16, float, 1>(m, F, wu, nwu, nu, nnu, xc, ldx, yc, ldy, cn, s);
+      else launch_solve_t<bf16, float, kNCS>(m, F, wu, nwu, nu, nnu, xc, ldx, yc, ldy, cn, s);
     } else {
       SolveFactors<double, double> F{m->P.IL, m->P.IU, m->P.LUinv};
-      if (cn == 1) launch_solve_t<double, double, 1>(m, F, xc, ldx, yc, ldy, cn, s);
-      else launch_solve_t<double, double, kNCS>(m, F, xc, ldx, yc, ldy, cn, s);
+      if (cn == 1) launch_solve_t<double, double, 1>(m, F, wu, nwu, nu, nnu, xc, ldx, yc, ldy, cn, s);
+      else launch_solve_t<double, double, kNCS>(m, F, wu, nwu, nu, nnu, xc, ldx, yc, ldy, cn, s);
     }
   }
+}
+
+void launch_solve(hodlr_mat m, int prec, const double* x, int64_t ldx, double* y, int64_t ldy, int nc,
+                  hipStream_t s) {
+  launch_solve_units(m, prec, m->wu, m->nwu, m->nu, m->nnu, x, ldx, y, ldy, nc, s);
 }
 
 void launch_norms(hodlr_mat m, const double* v, int64_t ld, int nc, double* out, hipStream_t s) {

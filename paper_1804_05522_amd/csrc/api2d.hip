@@ -1,0 +1,521 @@
+// Host side of the 2D solver (C ABI fde2d_*): shift selection, the batched
+// shifted operator, and the factored-ADI step with exact-residual corrections.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+namespace {
+
+enum { kR_R0 = 0, kR_D0 = 1, kR_D1 = 2, kR_X0 = 3, kR_X1 = 4, kR_T = 5, kR_C = 6, kR_ZERO = 7, kR_N = 8 };
+
+// ---------- Zolotarev shifts for two real intervals (host, FP64) ----------
+double ellip_K(double k) {           // complete elliptic integral of the first kind, modulus k (AGM)
+  double a = 1.0, b = std::sqrt(1.0 - k * k);
+  for (int it = 0; it < 80 && std::fabs(a - b) > 1e-16 * a; ++it) {
+    const double an = 0.5 * (a + b);
+    b = std::sqrt(a * b);
+    a = an;
+  }
+  return M_PI / (2.0 * a);
+}
+
+double ellip_dn(double u, double k) { // Jacobi dn(u | k) by the AGM / descending Landen scheme
+  std::vector<double> a{1.0}, c{k};
+  double b = std::sqrt(1.0 - k * k);
+  while (std::fabs(c.back()) > 1e-16 && a.size() < 80) {
+    const double an = 0.5 * (a.back() + b), cn = 0.5 * (a.back() - b);
+    b = std::sqrt(a.back() * b);
+    a.push_back(an);
+    c.push_back(cn);
+  }
+  const int N = int(a.size()) - 1;
+  double phi = std::ldexp(1.0, N) * a[N] * u, prev = phi;
+  for (int n = N; n >= 1; --n) {
+    prev = phi;
+    phi = 0.5 * (phi + std::asin(c[n] * std::sin(phi) / a[n]));
+  }
+  return std::cos(phi) / std::cos(prev - phi);
+}
+
+// Optimal rational r(z) = prod (z - p_j)/(z + q_j) for |r| small on [a1,b1] (spectrum of A)
+// and large on [-b2,-a2] (minus the spectrum of B): the symmetric problem on
+// [-alpha,-1] U [1,alpha] has zeros alpha dn((2j-1)K/(2n), k'), k' = sqrt(1 - 1/alpha^2),
+// mapped back by the Moebius transformation fixing the cross ratio.
+void zolotarev_shifts(double a1, double b1, double a2, double b2, int n, std::vector<double>& p,
+                      std::vector<double>& q) {
+  const double gam = (a1 + b2) * (b1 + a2) / ((a1 + a2) * (b1 + b2));
+  const double alp = 2.0 * gam - 1.0 + 2.0 * std::sqrt(std::max(gam * gam - gam, 0.0));
+  const double kp = std::sqrt(std::max(1.0 - 1.0 / (alp * alp), 0.0));
+  const double K = ellip_K(kp);
+  auto T = [&](double z) {   // maps -1 -> -a2, 1 -> a1, alpha -> b1
+    const double z1 = -1.0, z2 = 1.0, z3 = alp, w1 = -a2, w2 = a1, w3 = b1;
+    const double R = (z - z1) * (z2 - z3) / ((z - z3) * (z2 - z1));
+    const double S = R * (w2 - w1) / (w2 - w3);
+    return (w1 - S * w3) / (1.0 - S);
+  };
+  p.resize(n);
+  q.resize(n);
+  for (int j = 0; j < n; ++j) {
+    const double z = alp * ellip_dn((2.0 * j + 1.0) * K / (2.0 * n), kp);
+    p[j] = T(z);
+    q[j] = -T(-z);
+  }
+}
+
+// max over [a1,b1] of |r| times max over [a2,b2] of |1/r(-mu)| on log grids
+double zolotarev_bound(double a1, double b1, double a2, double b2, const std::vector<double>& p,
+                       const std::vector<double>& q) {
+  double e1 = 0.0, e2 = 0.0;
+  const int S = 2000;
+  for (int s = 0; s < S; ++s) {
+    const double l = a1 * std::pow(b1 / a1, double(s) / (S - 1));
+    const double m = a2 * std::pow(b2 / a2, double(s) / (S - 1));
+    double r1 = 1.0, r2 = 1.0;
+    for (size_t j = 0; j < p.size(); ++j) {
+      r1 *= std::fabs((l - p[j]) / (l + q[j]));
+      r2 *= std::fabs((m - q[j]) / (m + p[j]));
+    }
+    e1 = std::max(e1, r1);
+    e2 = std::max(e2, r2);
+  }
+  return e1 * e2;
+}
+
+template <typename T>
+hodlr_status plan_alloc(fde2d_plan p, T** ptr, size_t count) {
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return HODLR_ENOMEM;
+  p->allocs.push_back(q);
+  *ptr = static_cast<T*>(q);
+  return HODLR_OK;
+}
+
+Grp grp(const double* ptr, int64_t ld, const int32_t* cdev, int cnt, double s) { return Grp{ptr, ld, cdev, cnt, s}; }
+Grp grp_none() { return Grp{nullptr, 0, nullptr, 0, 0.0}; }
+
+// Enqueue one low-rank job (uploaded to device slot `slot`): Grams of both
+// sides, then either the recompression (core + forms) or only the norm.
+hodlr_status run_lr(fde2d_plan P, const LrJob& job, int slot, bool recompress, hipStream_t s, bool upload = true) {
+  LrJob jb = job;
+  jb.gx = 2 * slot;
+  jb.gy = 2 * slot + 1;
+  jb.mslot = slot;
+  if (upload) HIP_TRY(hipMemcpyAsync(P->jobs + slot, &jb, sizeof(LrJob), hipMemcpyHostToDevice, s));
+  std::vector<LrUnit> units;
+  std::vector<ReduceUnit> reds;
+  int out = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int64_t rows = side == 0 ? jb.rows_x : jb.rows_y;
+    const int chunks = int((rows + kLrRows - 1) / kLrRows);
+    reds.push_back(ReduceUnit{out, chunks, side == 0 ? jb.gx : jb.gy, 0});
+    for (int c = 0; c < chunks; ++c) units.push_back(LrUnit{slot, side, c, out++});
+  }
+  // per-slot regions: gram units, reduce units, form units
+  LrUnit* du = P->units + int64_t(slot) * P->slot_units;
+  HIP_TRY(hipMemcpyAsync(du, units.data(), units.size() * sizeof(LrUnit), hipMemcpyHostToDevice, s));
+  ReduceUnit* dr = reinterpret_cast<ReduceUnit*>(du + P->cap_gram);
+  HIP_TRY(hipMemcpyAsync(dr, reds.data(), reds.size() * sizeof(ReduceUnit), hipMemcpyHostToDevice, s));
+  double* gp = P->gpart + int64_t(slot) * P->cap_gram * kG2;
+  hipLaunchKernelGGL(k_lr_gram, dim3(units.size()), dim3(256), 0, s, P->jobs, du, gp);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(reds.size()), dim3(256), 0, s, dr, gp, P->grams);
+  if (!recompress) {
+    hipLaunchKernelGGL(k_lr_frob, dim3(1), dim3(256), 0, s, P->jobs + slot, P->grams, P->frob + slot);
+    return HODLR_OK;
+  }
+  hipLaunchKernelGGL(k_lr_core, dim3(1), dim3(kWG), kFactorLdsBytes, s, P->jobs + slot, P->grams, P->mbuf);
+  std::vector<LrUnit> fu;
+  for (int side = 0; side < 2; ++side) {
+    const int64_t rows = side == 0 ? jb.rows_x : jb.rows_y;
+    for (int64_t c = 0; c < (rows + 255) / 256; ++c) fu.push_back(LrUnit{slot, side, int32_t(c), 0});
+  }
+  LrUnit* dfu = du + P->cap_gram + 2;
+  HIP_TRY(hipMemcpyAsync(dfu, fu.data(), fu.size() * sizeof(LrUnit), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_lr_form, dim3(fu.size()), dim3(256), 0, s, P->jobs, dfu, P->mbuf);
+  return HODLR_OK;
+}
+
+hodlr_status read_ranks(fde2d_plan P, int32_t* h, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(h, P->ranks, kR_N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return HODLR_OK;
+}
+
+hodlr_status read_frob(fde2d_plan P, int slot, double* v, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(v, P->frob + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return HODLR_OK;
+}
+
+void copy_cols(int64_t rows, const int32_t* rdev, int rfix, const double* src, int64_t lds, double* dst, int64_t ldd,
+               double sc, hipStream_t s) {
+  const int blocks = int(std::min<int64_t>((rows * 64 + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_copy_cols, dim3(blocks), dim3(256), 0, s, rows, rdev, rfix, src, lds, dst, ldd, sc);
+}
+
+// One fADI sweep on the right-hand side G H^T (rank r0, in P->G / P->H; they are
+// consumed).  Accumulates the sweep's solution into Zd/Wd; returns the steps
+// taken and the parity holding the result.
+hodlr_status adi_sweep(fde2d_plan P, int r0, double cnorm, int& steps, int& parity, hipStream_t s) {
+  hodlr_mat m = P->mat;
+  const int64_t nx = P->nx, ny = P->ny, tn = m->total_n;
+  const double tol = P->opts.tol;
+  HIP_TRY(hipMemsetAsync(P->ranks + kR_D0, 0, sizeof(int32_t), s));
+  parity = 0;
+  steps = 0;
+  if (r0 == 0) return HODLR_OK;
+  for (int j = 0; j < P->J; ++j) {
+    const Item& ix = m->items[j];
+    const Item& iy = m->items[P->J + j];
+    copy_cols(nx, P->ranks + kR_R0, 0, P->G, nx, P->xin + ix.row0, tn, 1.0, s);
+    copy_cols(ny, P->ranks + kR_R0, 0, P->H, ny, P->xin + iy.row0, tn, 1.0, s);
+    launch_solve_units(m, m->opts.prec, P->pair_wu + P->pwu_off[j], P->pwu_cnt[j], P->pair_nu + P->pnu_off[j],
+                       P->pnu_cnt[j], P->xin, tn, P->xin, tn, r0, s);
+    const double w = P->p[j] + P->q[j];
+    hipLaunchKernelGGL(k_adi_update, dim3(256), dim3(256), 0, s, nx, ny, P->ranks + kR_R0, w, P->xin + ix.row0, tn,
+                       P->xin + iy.row0, tn, P->G, nx, P->H, ny);
+    // D <- recompress([D, w Z_j][W_D, Y_j])
+    LrJob jb{};
+    jb.X.g[0] = grp(P->Zd[parity], nx, P->ranks + kR_D0 + parity, 0, 1.0);
+    jb.X.g[1] = grp(P->xin + ix.row0, tn, P->ranks + kR_R0, 0, w);
+    jb.X.g[2] = grp_none();
+    jb.Y.g[0] = grp(P->Wd[parity], ny, P->ranks + kR_D0 + parity, 0, 1.0);
+    jb.Y.g[1] = grp(P->xin + iy.row0, tn, P->ranks + kR_R0, 0, 1.0);
+    jb.Y.g[2] = grp_none();
+    jb.rows_x = nx;
+    jb.rows_y = ny;
+    jb.rank_out = P->ranks + kR_D0 + (1 - parity);
+    jb.tau = 0.0;
+    jb.tau_rel = 0.1 * tol;
+    jb.rmax = kRS;
+    jb.U = P->Zd[1 - parity];
+    jb.ldu = nx;
+    jb.V = P->Wd[1 - parity];
+    jb.ldv = ny;
+    TRY(run_lr(P, jb, 2 + (j & 1), true, s));
+    parity = 1 - parity;
+    steps = j + 1;
+    if ((j % 4 == 3) || j == P->J - 1) {
+      LrJob nj{};
+      nj.X.g[0] = grp(P->G, nx, P->ranks + kR_R0, 0, 1.0);
+      nj.X.g[1] = nj.X.g[2] = grp_none();
+      nj.Y.g[0] = grp(P->H, ny, P->ranks + kR_R0, 0, 1.0);
+      nj.Y.g[1] = nj.Y.g[2] = grp_none();
+      nj.rows_x = nx;
+      nj.rows_y = ny;
+      TRY(run_lr(P, nj, 1, false, s));
+      double f2 = 0.0;
+      TRY(read_frob(P, 1, &f2, s));
+      if (std::sqrt(std::max(f2, 0.0)) <= tol * cnorm) break;
+    }
+  }
+  return HODLR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fde2d_plan_destroy(fde2d_plan p) {
+  if (!p) return;
+  hodlr_destroy(p->mat);
+  hodlr_destroy(p->exact);
+  for (void* q : p->allocs) (void)hipFree(q);
+  delete p;
+}
+
+int fde2d_plan_shifts(fde2d_plan p, double* ps, double* qs, int cap) {
+  if (!p) return 0;
+  for (int j = 0; j < std::min(cap, p->J); ++j) {
+    if (ps) ps[j] = p->p[j];
+    if (qs) qs[j] = p->q[j];
+  }
+  return p->J;
+}
+
+hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
+                               const hodlr_opts* hopts, const fde2d_opts* opts, fde2d_plan* out) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!opx) return set_arg(ctx, 2);
+  if (!opy) return set_arg(ctx, 3);
+  if (!hopts) return set_arg(ctx, 4);
+  if (!opts || !(opts->tol > 0.0) || opts->max_shifts < 1 || opts->max_shifts > 64 || opts->max_rank < 1 ||
+      opts->max_rank > kRS)
+    return set_arg(ctx, 5);
+  if (!out) return set_arg(ctx, 6);
+  hipStream_t s = ctx->stream;
+  fde2d_plan P = new (std::nothrow) fde2d_plan_s;
+  if (!P) return HODLR_ENOMEM;
+  P->ctx = ctx;
+  P->opts = *opts;
+  P->nx = opx->n;
+  P->ny = opy->n;
+  P->shift_x = opx->shift;
+  P->shift_y = opy->shift;
+  // spectral intervals [s, s + 2 nu alpha max(d+ + d-)]
+  auto upper = [&](const fde_operator* o, double& hi) -> hodlr_status {
+    std::vector<double> dp(o->n), dm(o->n);
+    HIP_TRY(hipMemcpy(dp.data(), o->d_plus, o->n * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(dm.data(), o->d_minus, o->n * sizeof(double), hipMemcpyDeviceToHost));
+    double mx = 0.0;
+    for (int64_t i = 0; i < o->n; ++i) mx = std::max(mx, dp[i] + dm[i]);
+    const double nu = o->dt / std::pow(o->dx, o->alpha);
+    hi = o->shift + 2.0 * nu * o->alpha * mx;
+    return HODLR_OK;
+  };
+  double b1 = 0, b2 = 0;
+  hodlr_status st = upper(opx, b1);
+  if (st == HODLR_OK) st = upper(opy, b2);
+  if (st != HODLR_OK) { fde2d_plan_destroy(P); return st; }
+  const double a1 = opx->shift, a2 = opy->shift;
+  int J = 1;
+  for (; J <= opts->max_shifts; ++J) {
+    zolotarev_shifts(a1, b1, a2, b2, J, P->p, P->q);
+    if (zolotarev_bound(a1, b1, a2, b2, P->p, P->q) <= 0.1 * opts->tol) break;
+  }
+  J = std::min(J, opts->max_shifts);
+  zolotarev_shifts(a1, b1, a2, b2, J, P->p, P->q);
+  P->J = J;
+  // batched shifted operator: x items shift_x + q_j, y items shift_y + p_j
+  std::vector<fde_operator> ops;
+  for (int j = 0; j < J; ++j) { fde_operator o = *opx; o.shift = opx->shift + P->q[j]; ops.push_back(o); }
+  for (int j = 0; j < J; ++j) { fde_operator o = *opy; o.shift = opy->shift + P->p[j]; ops.push_back(o); }
+  hodlr_opts ho = *hopts;
+  ho.refine_max = 0;
+  st = hodlr_build(ctx, ops.data(), int(ops.size()), &ho, &P->mat);
+  if (st != HODLR_OK) { fde2d_plan_destroy(P); return st; }
+  hodlr_info fi{};
+  st = hodlr_factor(ctx, P->mat, &fi);
+  if (st != HODLR_OK && st != HODLR_ERANK) { fde2d_plan_destroy(P); return st; }
+  fde_operator ex[2] = {*opx, *opy};
+  st = hodlr_build(ctx, ex, 2, &ho, &P->exact);
+  if (st != HODLR_OK) { fde2d_plan_destroy(P); return st; }
+  // per-pair solve unit lists (x_j leaves/nodes, then y_j)
+  hodlr_mat m = P->mat;
+  std::vector<int> wo(m->batch + 1, 0), no(m->batch + 1, 0);
+  for (const WorkUnit& w : m->wu_h) wo[w.item + 1]++;
+  for (const NodeUnit& u : m->nu_h) no[u.item + 1]++;
+  for (int i = 0; i < m->batch; ++i) { wo[i + 1] += wo[i]; no[i + 1] += no[i]; }
+  std::vector<WorkUnit> pw;
+  std::vector<NodeUnit> pn;
+  for (int j = 0; j < J; ++j) {
+    P->pwu_off.push_back(int(pw.size()));
+    P->pnu_off.push_back(int(pn.size()));
+    for (int it : {j, J + j}) {
+      pw.insert(pw.end(), m->wu_h.begin() + wo[it], m->wu_h.begin() + wo[it + 1]);
+      pn.insert(pn.end(), m->nu_h.begin() + no[it], m->nu_h.begin() + no[it + 1]);
+    }
+    P->pwu_cnt.push_back(int(pw.size()) - P->pwu_off.back());
+    P->pnu_cnt.push_back(int(pn.size()) - P->pnu_off.back());
+  }
+  const int64_t nx = P->nx, ny = P->ny;
+  const int64_t mr = std::max(nx, ny);
+  P->cap_gram = int(2 * ((mr + kLrRows - 1) / kLrRows));
+  P->slot_units = P->cap_gram + 2 + int(2 * ((mr + 255) / 256));
+  bool ok = plan_alloc(P, &P->pair_wu, pw.size()) == HODLR_OK && plan_alloc(P, &P->pair_nu, pn.size()) == HODLR_OK &&
+            plan_alloc(P, &P->G, nx * kMaxCat) == HODLR_OK && plan_alloc(P, &P->H, ny * kMaxCat) == HODLR_OK &&
+            plan_alloc(P, &P->G0, nx * kMaxCat) == HODLR_OK && plan_alloc(P, &P->H0, ny * kMaxCat) == HODLR_OK &&
+            plan_alloc(P, &P->R1, nx * kMaxCat) == HODLR_OK && plan_alloc(P, &P->R1w, ny * kMaxCat) == HODLR_OK &&
+            plan_alloc(P, &P->xin, m->total_n * kMaxCat) == HODLR_OK &&
+            plan_alloc(P, &P->ex_in, (nx + ny) * kMaxCat) == HODLR_OK &&
+            plan_alloc(P, &P->ex_out, (nx + ny) * kMaxCat) == HODLR_OK && plan_alloc(P, &P->ranks, kR_N) == HODLR_OK &&
+            plan_alloc(P, &P->jobs, 16) == HODLR_OK && plan_alloc(P, &P->units, 16 * P->slot_units) == HODLR_OK &&
+            plan_alloc(P, &P->gpart, 16 * P->cap_gram * kG2) == HODLR_OK && plan_alloc(P, &P->grams, 32 * kG2) == HODLR_OK &&
+            plan_alloc(P, &P->mbuf, 16 * 2 * kMaxCat * kRS) == HODLR_OK && plan_alloc(P, &P->frob, 16) == HODLR_OK;
+  for (int k = 0; k < 2 && ok; ++k)
+    ok = plan_alloc(P, &P->Zx[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wx[k], ny * kRS) == HODLR_OK &&
+         plan_alloc(P, &P->Zd[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wd[k], ny * kRS) == HODLR_OK;
+  if (!ok) { fde2d_plan_destroy(P); return HODLR_ENOMEM; }
+  if (hipMemcpy(P->pair_wu, pw.data(), pw.size() * sizeof(WorkUnit), hipMemcpyHostToDevice) != hipSuccess ||
+      (!pn.empty() && hipMemcpy(P->pair_nu, pn.data(), pn.size() * sizeof(NodeUnit), hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemsetAsync(P->ranks, 0, kR_N * sizeof(int32_t), s) != hipSuccess) {
+    fde2d_plan_destroy(P);
+    return HODLR_EHIP;
+  }
+  static bool attr = false;
+  if (!attr) {
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lr_core), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(kFactorLdsBytes)));
+    attr = true;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = P;
+  return HODLR_OK;
+}
+
+hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* U_m, const lr_matrix* F, double dt,
+                                  lr_matrix* U_next, hodlr_info* info) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!P) return set_arg(ctx, 2);
+  if (!U_m || U_m->rank < 0 || U_m->rank > kRS || (U_m->rank > 0 && (!U_m->Z || !U_m->W))) return set_arg(ctx, 3);
+  if (!F || F->rank < 0 || F->rank > kRS || (F->rank > 0 && (!F->Z || !F->W))) return set_arg(ctx, 4);
+  if (!U_next || !U_next->Z || !U_next->W || U_next->capacity < 1) return set_arg(ctx, 6);
+  hipStream_t s = ctx->stream;
+  const int64_t nx = P->nx, ny = P->ny;
+  const double tol = P->opts.tol;
+  int32_t hr[kR_N];
+  // C = [Z_m, dt F_Z][W_m, F_W]^T, recompressed into G0, H0 (and G, H)
+  LrJob cj{};
+  cj.X.g[0] = grp(U_m->Z, U_m->ldz, nullptr, U_m->rank, 1.0);
+  cj.X.g[1] = grp(F->Z, F->ldz, nullptr, F->rank, dt);
+  cj.X.g[2] = grp_none();
+  cj.Y.g[0] = grp(U_m->W, U_m->ldw, nullptr, U_m->rank, 1.0);
+  cj.Y.g[1] = grp(F->W, F->ldw, nullptr, F->rank, 1.0);
+  cj.Y.g[2] = grp_none();
+  cj.rows_x = nx;
+  cj.rows_y = ny;
+  cj.rank_out = P->ranks + kR_C;
+  cj.tau = 0.0;
+  cj.tau_rel = 1e-3 * tol;
+  cj.rmax = kRS;
+  cj.U = P->G0;
+  cj.ldu = nx;
+  cj.V = P->H0;
+  cj.ldv = ny;
+  if (U_m->rank + F->rank > 0) {
+    TRY(run_lr(P, cj, 0, true, s));
+  } else {
+    HIP_TRY(hipMemsetAsync(P->ranks + kR_C, 0, sizeof(int32_t), s));
+  }
+  TRY(read_ranks(P, hr, s));
+  const int rc = hr[kR_C];
+  // ||C||_F
+  double cn2 = 0.0;
+  if (rc > 0) {
+    LrJob nj{};
+    nj.X.g[0] = grp(P->G0, nx, P->ranks + kR_C, 0, 1.0);
+    nj.X.g[1] = nj.X.g[2] = grp_none();
+    nj.Y.g[0] = grp(P->H0, ny, P->ranks + kR_C, 0, 1.0);
+    nj.Y.g[1] = nj.Y.g[2] = grp_none();
+    nj.rows_x = nx;
+    nj.rows_y = ny;
+    TRY(run_lr(P, nj, 1, false, s));
+    TRY(read_frob(P, 1, &cn2, s));
+  }
+  const double cnorm = std::sqrt(std::max(cn2, 0.0));
+  // sweep 0 on C itself
+  copy_cols(nx, P->ranks + kR_C, 0, P->G0, nx, P->G, nx, 1.0, s);
+  copy_cols(ny, P->ranks + kR_C, 0, P->H0, ny, P->H, ny, 1.0, s);
+  HIP_TRY(hipMemcpyAsync(P->ranks + kR_R0, P->ranks + kR_C, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemsetAsync(P->ranks + kR_X0, 0, sizeof(int32_t), s));
+  int xpar = 0, total_steps = 0, sweeps = 0;
+  double rel_res = 0.0, rel_corr = 1.0;
+  int r0 = rc;
+  hodlr_status res = HODLR_OK;
+  for (sweeps = 0; sweeps < 5; ++sweeps) {
+    int steps = 0, dpar = 0;
+    TRY(adi_sweep(P, r0, std::max(cnorm, 1e-300), steps, dpar, s));
+    total_steps += steps;
+    // X <- recompress([X, D][W_X, W_D])
+    LrJob mj{};
+    mj.X.g[0] = grp(P->Zx[xpar], nx, P->ranks + kR_X0 + xpar, 0, 1.0);
+    mj.X.g[1] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
+    mj.X.g[2] = grp_none();
+    mj.Y.g[0] = grp(P->Wx[xpar], ny, P->ranks + kR_X0 + xpar, 0, 1.0);
+    mj.Y.g[1] = grp(P->Wd[dpar], ny, P->ranks + kR_D0 + dpar, 0, 1.0);
+    mj.Y.g[2] = grp_none();
+    mj.rows_x = nx;
+    mj.rows_y = ny;
+    mj.rank_out = P->ranks + kR_X0 + (1 - xpar);
+    mj.tau = 0.0;
+    mj.tau_rel = 0.1 * tol;
+    mj.rmax = P->opts.max_rank;
+    mj.U = P->Zx[1 - xpar];
+    mj.ldu = nx;
+    mj.V = P->Wx[1 - xpar];
+    mj.ldv = ny;
+    TRY(run_lr(P, mj, 4, true, s));
+    xpar = 1 - xpar;
+    // size of the correction relative to X
+    double d2 = 0.0, x2 = 0.0;
+    {
+      LrJob nj{};
+      nj.X.g[0] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
+      nj.X.g[1] = nj.X.g[2] = grp_none();
+      nj.Y.g[0] = grp(P->Wd[dpar], ny, P->ranks + kR_D0 + dpar, 0, 1.0);
+      nj.Y.g[1] = nj.Y.g[2] = grp_none();
+      nj.rows_x = nx;
+      nj.rows_y = ny;
+      TRY(run_lr(P, nj, 5, false, s));
+      LrJob xj = nj;
+      xj.X.g[0] = grp(P->Zx[xpar], nx, P->ranks + kR_X0 + xpar, 0, 1.0);
+      xj.Y.g[0] = grp(P->Wx[xpar], ny, P->ranks + kR_X0 + xpar, 0, 1.0);
+      TRY(run_lr(P, xj, 6, false, s));
+      TRY(read_frob(P, 5, &d2, s));
+      TRY(read_frob(P, 6, &x2, s));
+    }
+    rel_corr = x2 > 0 ? std::sqrt(std::max(d2, 0.0) / x2) : 0.0;
+    if (sweeps > 0 && rel_corr <= tol) break;
+    if (rc == 0) break;
+    // exact residual R = C - A X - X B^T  ->  next sweep's right-hand side (G, H)
+    TRY(read_ranks(P, hr, s));
+    const int rx = hr[kR_X0 + xpar];
+    if (rx == 0) break;
+    copy_cols(nx, nullptr, rx, P->Zx[xpar], nx, P->ex_in, nx + ny, 1.0, s);
+    copy_cols(ny, nullptr, rx, P->Wx[xpar], ny, P->ex_in + nx, nx + ny, 1.0, s);
+    launch_fft_matvec(P->exact, P->ex_in, nx + ny, P->ex_out, nx + ny, nullptr, 0, rx, s);
+    LrJob r1{};
+    r1.X.g[0] = grp(P->G0, nx, P->ranks + kR_C, 0, 1.0);
+    r1.X.g[1] = grp(P->ex_out, nx + ny, nullptr, rx, -1.0);      // A Z_X
+    r1.X.g[2] = grp_none();
+    r1.Y.g[0] = grp(P->H0, ny, P->ranks + kR_C, 0, 1.0);
+    r1.Y.g[1] = grp(P->Wx[xpar], ny, nullptr, rx, 1.0);
+    r1.Y.g[2] = grp_none();
+    r1.rows_x = nx;
+    r1.rows_y = ny;
+    r1.rank_out = P->ranks + kR_T;
+    r1.tau = 1e-3 * tol * cnorm;
+    r1.tau_rel = 0.0;
+    r1.rmax = kRS;
+    r1.U = P->R1;
+    r1.ldu = nx;
+    r1.V = P->R1w;
+    r1.ldv = ny;
+    TRY(run_lr(P, r1, 7, true, s));
+    LrJob r2 = r1;
+    r2.X.g[0] = grp(P->R1, nx, P->ranks + kR_T, 0, 1.0);
+    r2.X.g[1] = grp(P->Zx[xpar], nx, nullptr, rx, -1.0);
+    r2.Y.g[0] = grp(P->R1w, ny, P->ranks + kR_T, 0, 1.0);
+    r2.Y.g[1] = grp(P->ex_out + nx, nx + ny, nullptr, rx, 1.0);   // B W_X
+    r2.rank_out = P->ranks + kR_R0;
+    r2.U = P->G;
+    r2.V = P->H;
+    TRY(run_lr(P, r2, 8, true, s));
+    LrJob nj{};
+    nj.X.g[0] = grp(P->G, nx, P->ranks + kR_R0, 0, 1.0);
+    nj.X.g[1] = nj.X.g[2] = grp_none();
+    nj.Y.g[0] = grp(P->H, ny, P->ranks + kR_R0, 0, 1.0);
+    nj.Y.g[1] = nj.Y.g[2] = grp_none();
+    nj.rows_x = nx;
+    nj.rows_y = ny;
+    TRY(run_lr(P, nj, 9, false, s));
+    double r2n = 0.0;
+    TRY(read_frob(P, 9, &r2n, s));
+    rel_res = cnorm > 0 ? std::sqrt(std::max(r2n, 0.0)) / cnorm : 0.0;
+    TRY(read_ranks(P, hr, s));
+    r0 = hr[kR_R0];
+    if (rel_res <= 1e-3 * tol) break;
+  }
+  if (sweeps >= 5 && rel_corr > tol) res = HODLR_ENOCONV;
+  TRY(read_ranks(P, hr, s));
+  const int rx = hr[kR_X0 + xpar];
+  if (rx > U_next->capacity) return set_arg(ctx, 6);
+  copy_cols(nx, nullptr, rx, P->Zx[xpar], nx, U_next->Z, U_next->ldz, 1.0, s);
+  copy_cols(ny, nullptr, rx, P->Wx[xpar], ny, U_next->W, U_next->ldw, 1.0, s);
+  U_next->rank = rx;
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->status = res;
+    info->refine_iters = total_steps;
+    info->rel_residual = rel_res;
+    info->rel_correction = rel_corr;
+    info->max_rank = rx;
+    info->leaf = -1;
+    info->row = -1;
+  }
+  return res;
+}
+
+}  // extern "C"

@@ -7,4 +7,6 @@
 #include "factor_mwg.hip"
 #include "solve.hip"
 #include "fft.hip"
+#include "adi.hip"
 #include "api.hip"
+#include "api2d.hip"

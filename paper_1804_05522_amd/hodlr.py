@@ -23,7 +23,6 @@ EXPORTS = [
     "hodlr_default_opts", "hodlr_build", "hodlr_destroy", "hodlr_get_info", "hodlr_matvec",
     "hodlr_toeplitz_matvec", "hodlr_factor", "hodlr_solve", "hodlr_time_steps",
     "fde2d_plan_create", "fde2d_plan_destroy", "fde2d_plan_shifts", "fde2d_sylvester_step",
-    "fde2d_sylvester_step_dense",
 ]
 
 
@@ -94,8 +93,6 @@ def lib():
             L.fde2d_plan_shifts.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), i32]
             L.fde2d_sylvester_step.argtypes = [vp, vp, C.POINTER(LrMatrix), C.POINTER(LrMatrix), dbl,
                                                C.POINTER(LrMatrix), C.POINTER(HodlrInfo)]
-            L.fde2d_sylvester_step_dense.argtypes = [vp, vp, vp, vp, vp, i64, i32, dbl,
-                                                     C.POINTER(HodlrInfo)]
         _lib = L
     return _lib
 
@@ -219,3 +216,55 @@ class HodlrMatrix:
 
 def operator_dict(n, alpha, dt, dx, d_plus, d_minus, shift=1.0):
     return dict(n=n, alpha=alpha, dt=dt, dx=dx, d_plus=d_plus, d_minus=d_minus, shift=shift)
+
+
+class Fde2dPlan:
+    """Shifted HODLR factor sets for A X + X B^T = C (eq. (sylv-timestepping))."""
+
+    def __init__(self, ctx: Context, opx: dict, opy: dict, hopts: HodlrOpts, tol=1e-10, max_shifts=64,
+                 max_rank=32):
+        self.ctx = ctx
+        self.nx, self.ny = int(opx["n"]), int(opy["n"])
+        ox = FdeOperator(self.nx, float(opx["alpha"]), float(opx["dt"]), float(opx["dx"]),
+                         float(opx.get("shift", 0.5)), C.c_void_p(opx["d_plus"].data_ptr()),
+                         C.c_void_p(opx["d_minus"].data_ptr()))
+        oy = FdeOperator(self.ny, float(opy["alpha"]), float(opy["dt"]), float(opy["dx"]),
+                         float(opy.get("shift", 0.5)), C.c_void_p(opy["d_plus"].data_ptr()),
+                         C.c_void_p(opy["d_minus"].data_ptr()))
+        self.opts = Fde2dOpts(float(tol), int(max_shifts), int(max_rank))
+        self.h = C.c_void_p()
+        check(lib().fde2d_plan_create(ctx.h, C.byref(ox), C.byref(oy), C.byref(hopts), C.byref(self.opts),
+                                      C.byref(self.h)), "fde2d_plan_create", ctx.h)
+
+    def shifts(self):
+        n = lib().fde2d_plan_shifts(self.h, None, None, 0)
+        p = (C.c_double * n)()
+        q = (C.c_double * n)()
+        lib().fde2d_plan_shifts(self.h, p, q, n)
+        return list(p), list(q)
+
+    def step(self, Um, F, dt, out, allow=(HODLR_OK,)):
+        """Um, F, out: (Z, W) pairs of column-major torch CUDA float64 tensors
+        stored as (rank, n) row-major (column j = row j); out gives the capacity."""
+        def lr(zw, cap=None):
+            Z, W = zw
+            r = Z.shape[0] if Z is not None else 0
+            return LrMatrix(self.nx, r if cap is None else 0, cap or r, self.nx, self.ny,
+                            C.c_void_p(Z.data_ptr() if Z is not None and Z.numel() else 0),
+                            C.c_void_p(W.data_ptr() if W is not None and W.numel() else 0))
+        a, f, o = lr(Um), lr(F), lr(out, cap=out[0].shape[0])
+        info = HodlrInfo()
+        check(lib().fde2d_sylvester_step(self.ctx.h, self.h, C.byref(a), C.byref(f), float(dt), C.byref(o),
+                                         C.byref(info)), "fde2d_sylvester_step", self.ctx.h, allow)
+        return o.rank, info
+
+    def close(self):
+        if self.h:
+            lib().fde2d_plan_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

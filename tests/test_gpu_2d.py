@@ -1,0 +1,85 @@
+"""GPU parity of the 2D per-step Sylvester solver (factored ADI with shifted
+HODLR solves) against the oracle's Bartels-Stewart / Kronecker solutions."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fde2d as O2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1804_05522_amd as H
+    H.lib()
+    return H
+
+
+@pytest.fixture(scope="module")
+def ctx(H):
+    return H.Context()
+
+
+def plan_for(H, ctx, p, prec="fp64", tol=1e-10):
+    opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5)
+    opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5)
+    return H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-12, prec=prec, leaf=32), tol=tol)
+
+
+def lr_dev(Z, W_):
+    return dev(Z.T.copy()), dev(W_.T.copy())
+
+
+@pytest.mark.parametrize("n,variable", [(40, False), (150, True), (333, True)])
+def test_sylvester_step_matches_bartels_stewart(H, ctx, n, variable):
+    """One implicit Euler step of eq. (sylv-timestepping) from a low-rank U_m and F."""
+    p = W.fd_2d(n=n, variable=variable, dt=1 / 16)
+    P = plan_for(H, ctx, p)
+    # smooth low-rank previous state (the solutions of these problems are smooth)
+    Um = W.LowRank(np.stack([np.sin((k + 1) * np.pi * p.x) for k in range(3)], 1) * 0.1,
+                   np.stack([p.y * (1 - p.y) * np.cos(k * np.pi * p.y) for k in range(3)], 1))
+    out = (torch.zeros((32, n), dtype=torch.float64, device="cuda"),
+           torch.zeros((32, n), dtype=torch.float64, device="cuda"))
+    r, info = P.step(lr_dev(Um.Z, Um.W), lr_dev(p.f.Z, p.f.W), p.dt, out, allow=(0, 2))
+    X = out[0][:r].cpu().numpy().T @ out[1][:r].cpu().numpy()
+    st = O2.SylvesterStepper(p)
+    ref = st.step(Um.dense(), p.f.dense())
+    err = np.linalg.norm(X - ref) / np.linalg.norm(ref)
+    assert err <= 1e-8, (err, r, info.refine_iters, info.rel_residual, info.rel_correction)
+    if n <= 40:
+        A, B = O2.sylvester_coefficients(p)
+        np.testing.assert_allclose(ref, O2.kron_solve(A, B, Um.dense() + p.dt * p.f.dense()), rtol=1e-9, atol=1e-12)
+
+
+def test_two_steps_in_a_row(H, ctx):
+    """Two consecutive steps (U_1 from U_0 = 0, then U_2 from U_1) match the oracle trajectory."""
+    n = 200
+    p = W.fd_2d(n=n, variable=True, dt=1 / 64)
+    P = plan_for(H, ctx, p)
+    st = O2.SylvesterStepper(p)
+    U = np.zeros((n, n))
+    cur = (torch.zeros((0, n), dtype=torch.float64, device="cuda"),) * 2
+    for _ in range(2):
+        out = (torch.zeros((32, n), dtype=torch.float64, device="cuda"),
+               torch.zeros((32, n), dtype=torch.float64, device="cuda"))
+        r, info = P.step(cur, lr_dev(p.f.Z, p.f.W), p.dt, out, allow=(0, 2))
+        cur = (out[0][:r].contiguous(), out[1][:r].contiguous())
+        U = st.step(U, p.f.dense())
+    X = cur[0].cpu().numpy().T @ cur[1].cpu().numpy()
+    assert np.linalg.norm(X - U) / np.linalg.norm(U) <= 1e-8
+
+
+def test_shift_count_reasonable(H, ctx):
+    p = W.fd_2d(n=256, variable=True)
+    P = plan_for(H, ctx, p)
+    ps, qs = P.shifts()
+    assert 5 <= len(ps) <= 64
+    assert all(x > 0 for x in ps + qs)
