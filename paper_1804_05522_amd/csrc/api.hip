@@ -168,6 +168,10 @@ hodlr_status dalloc(hodlr_mat m, T** p, size_t count) {
   void* q = nullptr;
   if (hipMalloc(&q, bytes) != hipSuccess) return HODLR_ENOMEM;
   m->allocs.push_back(q);
+  // HODLR_POISON=1 fills new device memory with NaN bytes, so that a read of
+  // memory no kernel has written shows up in the results
+  static const bool poison = getenv("HODLR_POISON") && getenv("HODLR_POISON")[0] == '1';
+  if (poison && hipMemset(q, 0xff, bytes) != hipSuccess) return HODLR_EHIP;
   m->bytes_device += bytes;
   *p = static_cast<T*>(q);
   return HODLR_OK;
@@ -298,16 +302,9 @@ void launch_axpby(int64_t nrows, int nc, double a, const double* x, int64_t ldx,
 // over the problems of the batch, which must share one tree shape).
 enum MwgKind { KL_LEAF = 0, KL_GRAM, KL_REDUCE, KL_CORE, KL_FORM, KL_SPP, KL_SPR, KL_SPE };
 
-static bool same_tree(hodlr_mat m) {
-  for (const Item& it : m->items)
-    if (it.n != m->items[0].n || it.L != m->items[0].L) return false;
-  return true;
-}
-
 static hodlr_status plan_mwg(hodlr_mat m) {
   if (m->mwg_planned) return HODLR_OK;
   const int B = m->batch;
-  const int L = m->items[0].L;
   std::vector<NodeTask> tasks;
   std::vector<GramUnit> grams;
   std::vector<ReduceUnit> reds;
@@ -316,66 +313,95 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   std::vector<ProdJob> jobs;
   std::vector<ProdUnit> punits;
   size_t max_gpart = 1, max_ppart = 1, max_pz = 1;
-  auto node = [&](int d, int64_t j) { return m->nodes[node_index(m->items[0], d, j)]; };
   auto rec = [&](int kind, int grid, int64_t off, int64_t off2) {
     m->mwg_kind.push_back(kind);
     m->mwg_grid.push_back(grid);
     m->mwg_off.push_back(off);
     m->mwg_off2.push_back(off2);
   };
-  auto add_tasks = [&](int d, int64_t j) {
+  struct Ev { int type, d; int64_t j; };   // type 0: leaf, 1: phase A, 2: phase B
+  std::vector<std::vector<Ev>> evs(B);
+  for (int i = 0; i < B; ++i) {
+    const int L = m->items[i].L;
+    std::vector<int> state(L + 2, 0);
+    int d = 0;
+    int64_t j = 0;
+    for (;;) {
+      if (d == L) {
+        evs[i].push_back(Ev{0, d, j});
+        if (d == 0) break;
+        --d; j >>= 1;
+        continue;
+      }
+      if (state[d] == 0) { state[d] = 1; state[d + 1] = 0; ++d; j = 2 * j; continue; }
+      if (state[d] == 1) {
+        evs[i].push_back(Ev{1, d, j});
+        state[d] = 2; state[d + 1] = 0; ++d; j = 2 * j + 1;
+        continue;
+      }
+      evs[i].push_back(Ev{2, d, j});
+      if (d == 0) break;
+      --d; j >>= 1;
+    }
+  }
+  size_t steps = 0;
+  for (auto& e : evs) steps = std::max(steps, e.size());
+  struct TaskSpec { int item, d; int64_t j; int64_t n1, n2; };
+  auto add_tasks = [&](const std::vector<TaskSpec>& ts) {
     const int64_t t0 = int64_t(tasks.size());
-    for (int i = 0; i < B; ++i) tasks.push_back(NodeTask{i, d, int32_t(j), i});
+    for (size_t k = 0; k < ts.size(); ++k) tasks.push_back(NodeTask{ts[k].item, ts[k].d, int32_t(ts[k].j), int32_t(k)});
     return t0;
   };
-  // grams (x^T y) over `rows` rows for each listed pair, then reduce into G[slot*9 + dst]
-  auto add_grams = [&](int64_t t0, int64_t rows, std::vector<std::array<int, 3>> pairs) {
-    const int64_t g0 = int64_t(grams.size());
-    const int64_t r0 = int64_t(reds.size());
-    const int chunks = int((rows + 1023) / 1024);
+  auto rows_of = [](const TaskSpec& t, int type) { return (type == 0 || type == 3 || type == 4 || type == 7) ? t.n1 : t.n2; };
+  auto add_grams = [&](int64_t t0, const std::vector<TaskSpec>& ts, std::vector<std::array<int, 3>> pairs) {
+    const int64_t g0 = int64_t(grams.size()), r0 = int64_t(reds.size());
     int32_t outi = 0;
-    for (int i = 0; i < B; ++i)
+    for (size_t k = 0; k < ts.size(); ++k)
       for (auto& p : pairs) {
-        reds.push_back(ReduceUnit{outi, chunks, int32_t(i * 9 + p[2]), 0});
-        for (int c = 0; c < chunks; ++c) grams.push_back(GramUnit{int32_t(i), int16_t(p[0]), int16_t(p[1]), c, outi++});
+        const int chunks = int((rows_of(ts[k], p[0]) + 1023) / 1024);
+        reds.push_back(ReduceUnit{outi, std::max(chunks, 1), int32_t(k * 9 + p[2]), 0});
+        for (int c = 0; c < std::max(chunks, 1); ++c)
+          grams.push_back(GramUnit{int32_t(k), int16_t(p[0]), int16_t(p[1]), c, outi++});
       }
     max_gpart = std::max(max_gpart, size_t(outi));
     rec(KL_GRAM, int(grams.size() - g0), g0, t0);
     rec(KL_REDUCE, int(reds.size() - r0), r0, t0);
   };
-  auto add_core = [&](int64_t t0, std::vector<int> whiches) {
+  auto add_core = [&](int64_t t0, size_t nt, std::vector<int> whiches) {
     const int64_t c0 = int64_t(cores.size());
-    for (int i = 0; i < B; ++i)
-      for (int w : whiches) cores.push_back(make_int2(i, w));
+    for (size_t k = 0; k < nt; ++k)
+      for (int w : whiches) cores.push_back(make_int2(int(k), w));
     rec(KL_CORE, int(cores.size() - c0), c0, t0);
   };
-  auto add_form = [&](int64_t t0, std::vector<std::pair<int, int64_t>> outs) {
+  auto add_form = [&](int64_t t0, const std::vector<TaskSpec>& ts, std::vector<int> outs) {
     const int64_t f0 = int64_t(forms.size());
-    for (int i = 0; i < B; ++i)
-      for (auto& o : outs)
-        for (int64_t c = 0; c < (o.second + 255) / 256; ++c)
-          forms.push_back(FormUnit{int32_t(i), o.first, int32_t(c), 0});
+    static const int src_type[7] = {0, 1, 2, 3, 8, 5, 6};
+    for (size_t k = 0; k < ts.size(); ++k)
+      for (int o : outs) {
+        const int64_t rows = rows_of(ts[k], src_type[o]);
+        for (int64_t c = 0; c < (rows + 255) / 256; ++c) forms.push_back(FormUnit{int32_t(k), o, int32_t(c), 0});
+      }
     rec(KL_FORM, int(forms.size() - f0), f0, t0);
   };
-  // products: one job per (item, spec); spec = {child (0/1), which, trans, xarr, yarr, rk, sign}
   struct Spec { int child, which, trans, xarr, yarr, rk; double sign; };
-  auto add_prods = [&](int d, int64_t j, std::vector<Spec> specs) {
+  auto add_prods = [&](const std::vector<TaskSpec>& ts, std::vector<Spec> specs) {
     const int64_t j0i = int64_t(jobs.size());
     std::vector<ProdUnit> leafu, nodeu;
-    for (int i = 0; i < B; ++i)
+    for (const TaskSpec& t : ts) {
+      const int L = m->items[t.item].L;
       for (auto& sp : specs) {
         ProdJob jb{};
-        jb.item = i;
-        jb.d0 = int16_t(d + 1);
-        jb.j0 = int32_t(2 * j + sp.child);
+        jb.item = t.item;
+        jb.d0 = int16_t(t.d + 1);
+        jb.j0 = int32_t(2 * t.j + sp.child);
         jb.which = int16_t(sp.which);
         jb.trans = int16_t(sp.trans);
         jb.xarr = int8_t(sp.xarr);
         jb.yarr = int8_t(sp.yarr);
-        jb.xlev = int16_t(d);
-        jb.ylev = int16_t(d);
-        jb.rd = int16_t(d);
-        jb.rj = int32_t(j);
+        jb.xlev = int16_t(t.d);
+        jb.ylev = int16_t(t.d);
+        jb.rd = int16_t(t.d);
+        jb.rj = int32_t(t.j);
         jb.rk = int16_t(sp.rk);
         jb.sign = sp.sign;
         jb.unit0 = int32_t(leafu.size());
@@ -388,6 +414,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
             nodeu.push_back(ProdUnit{jid, dd, int32_t((int64_t(jb.j0) << (dd - jb.d0)) + q), 0});
         jobs.push_back(jb);
       }
+    }
     const int64_t lu0 = int64_t(punits.size());
     punits.insert(punits.end(), leafu.begin(), leafu.end());
     const int64_t nu0 = int64_t(punits.size());
@@ -398,51 +425,36 @@ static hodlr_status plan_mwg(hodlr_mat m) {
     if (!nodeu.empty()) rec(KL_SPR, int(nodeu.size()), nu0, j0i);
     rec(KL_SPE, int(leafu.size()), lu0, j0i);
   };
-  // post-order walk
-  std::vector<int> state(L + 2, 0);
-  int d = 0;
-  int64_t j = 0;
-  for (;;) {
-    if (d == L) {
-      const int64_t t0 = add_tasks(d, j);
-      rec(KL_LEAF, B, t0, t0);
-      if (d == 0) break;
-      --d;
-      j >>= 1;
-      continue;
+  for (size_t g = 0; g < steps; ++g) {
+    std::vector<TaskSpec> lt, at, bt;
+    for (int i = 0; i < B; ++i) {
+      if (g >= evs[i].size()) continue;
+      const Ev e = evs[i][g];
+      const Node nd = m->nodes[node_index(m->items[i], e.d, e.j)];
+      TaskSpec t{i, e.d, e.j, nd.size / 2, nd.size - nd.size / 2};
+      (e.type == 0 ? lt : (e.type == 1 ? at : bt)).push_back(t);
     }
-    if (state[d] == 0) {
-      state[d] = 1;
-      state[d + 1] = 0;
-      ++d;
-      j = 2 * j;
-      continue;
+    if (!lt.empty()) {
+      const int64_t t0 = add_tasks(lt);
+      rec(KL_LEAF, int(lt.size()), t0, t0);
     }
-    const Node nd = node(d, j);
-    const int64_t n1 = nd.size / 2, n2 = nd.size - n1;
-    if (state[d] == 1) {
-      int64_t t0 = add_tasks(d, j);
-      add_grams(t0, std::max(n1, n2), {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {3, 3, 3}});
-      add_core(t0, {0, 1});
-      add_form(t0, {{0, n1}, {1, n2}, {2, n2}, {3, n1}});
-      add_prods(d, j, {{0, 0, 0, A_T1, A_FU, 0, 1.0}, {0, 1, 1, A_T2, A_FL, 1, 1.0}});
-      add_grams(t0, n1, {{4, 7, 4}});
-      add_form(t0, {{4, n2}});
-      add_grams(t0, n2, {{5, 5, 5}, {6, 6, 6}});
-      add_core(t0, {2});
-      add_form(t0, {{5, n2}, {6, n2}});
-      state[d] = 2;
-      state[d + 1] = 0;
-      ++d;
-      j = 2 * j + 1;
-      continue;
+    if (!at.empty()) {
+      const int64_t t0 = add_tasks(at);
+      add_grams(t0, at, {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {3, 3, 3}});
+      add_core(t0, at.size(), {0, 1});
+      add_form(t0, at, {0, 1, 2, 3});
+      add_prods(at, {{0, 0, 0, A_T1, A_FU, 0, 1.0}, {0, 1, 1, A_T2, A_FL, 1, 1.0}});
+      add_grams(t0, at, {{4, 7, 4}});
+      add_form(t0, at, {4});
+      add_grams(t0, at, {{5, 5, 5}, {6, 6, 6}});
+      add_core(t0, at.size(), {2});
+      add_form(t0, at, {5, 6});
     }
-    add_prods(d, j, {{1, 0, 0, A_FL, A_IL, 1, -1.0}, {0, 0, 1, A_FL, A_IL, 1, 1.0},
+    if (!bt.empty())
+      add_prods(bt, {{1, 0, 0, A_FL, A_IL, 1, -1.0}, {0, 0, 1, A_FL, A_IL, 1, 1.0},
                      {0, 1, 0, A_FU, A_IU, 0, -1.0}, {1, 1, 1, A_FU, A_IU, 0, 1.0}});
-    if (d == 0) break;
-    --d;
-    j >>= 1;
   }
+  const int Lmax = std::max(1, m->Lmax);
   TRY(dalloc(m, &m->d_tasks, tasks.size()));
   TRY(dalloc(m, &m->d_gram, grams.size()));
   TRY(dalloc(m, &m->d_red, reds.size()));
@@ -453,7 +465,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   TRY(dalloc(m, &m->d_gpart, max_gpart * kG2));
   TRY(dalloc(m, &m->d_G, size_t(B) * 9 * kG2));
   TRY(dalloc(m, &m->d_M, size_t(B) * 3 * 2 * kMaxCat * kRS));
-  TRY(dalloc(m, &m->d_ppart, max_ppart * std::max(1, L) * kRS * kPNC));
+  TRY(dalloc(m, &m->d_ppart, max_ppart * Lmax * kRS * kPNC));
   TRY(dalloc(m, &m->d_pz, max_pz * kRS * kPNC));
   auto up = [](void* dst, const void* src, size_t bytes) -> hodlr_status {
     if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
@@ -926,7 +938,7 @@ hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
   hipStream_t s = ctx->stream;
   const size_t lds = kFactorLdsBytes;
   const char* env = getenv("HODLR_FACTOR_PATH");
-  const bool single = (env && env[0] == 's') || !same_tree(m);
+  const bool single = (env && env[0] == 's');
   if (single) {
     hipLaunchKernelGGL(k_factor, dim3(m->batch), dim3(kWG), lds, s, m->P, m->b, m->opts.max_rank);
   } else {

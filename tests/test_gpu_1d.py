@@ -104,11 +104,12 @@ def test_factor_solve_fp64(H, ctx, n, alpha, refine):
 
 
 @pytest.mark.parametrize("path,sizes", [("single", [(300, 1.3), (1024, 1.7), (77, 1.5)]),
-                                        ("multi", [(1000, 1.3), (1000, 1.7), (1000, 1.5)])])
+                                        ("multi", [(1000, 1.3), (1000, 1.7), (1000, 1.5)]),
+                                        ("multi", [(300, 1.3), (1024, 1.7), (77, 1.5), (1, 1.2), (2500, 1.9)])])
 def test_batched_equals_separate(H, ctx, path, sizes):
-    """A batch gives the same solutions as the problems run one by one: a ragged
-    batch on the one-work-group-per-problem walk, a same-tree batch on the
-    lock-step multi-work-group schedule."""
+    """A batch gives the same solutions as the problems run one by one, on the
+    one-work-group-per-problem walk and on the multi-work-group schedule (same
+    trees, and ragged trees of different depths merged step by step)."""
     import os
     os.environ["HODLR_FACTOR_PATH"] = path
     try:
@@ -171,7 +172,11 @@ def test_time_steps_plain_config(H, ctx):
 @pytest.mark.parametrize("n,alpha", [(700, 1.4), (2049, 1.8)])
 def test_factor_paths_agree(H, ctx, n, alpha):
     """The one-work-group-per-problem walk and the multi-work-group schedule
-    carry out the same factorisation (different summation orders)."""
+    carry out the same factorisation (different summation orders).  Without
+    refinement the error of the factors is bounded by about eps * cond(M) and,
+    in the Gram-based recompression, by sqrt(u) times the norm of each updated
+    block; the stiff alpha = 1.8 case (cond ~ 1e5) therefore takes FP64
+    refinement sweeps with the exact residual."""
     import os
     p = var_problem(n, alpha, dt=1 / 32)
     b = np.cos(5 * p.x) + p.x
@@ -179,15 +184,35 @@ def test_factor_paths_agree(H, ctx, n, alpha):
     for path in ("single", "multi"):
         os.environ["HODLR_FACTOR_PATH"] = path
         try:
-            A = build(H, ctx, [p], tol=1e-10)
+            A = build(H, ctx, [p], tol=1e-10, refine_max=0 if alpha < 1.5 else 3, rtol=1e-12)
             A.factor()
             x = dev(b)
-            A.solve(x)
+            A.solve(x, allow=(0, 2))
             sols.append(x.cpu().numpy())
         finally:
             del os.environ["HODLR_FACTOR_PATH"]
     ref = O.DenseSolver(alpha, n, p.nu, p.d_plus, p.d_minus).solve(b)
-    for s in sols:      # both within the truncation error of eps = 1e-10
-        assert np.linalg.norm(s - ref) / np.linalg.norm(ref) <= 1e-8
+    errs = [np.linalg.norm(s - ref) / np.linalg.norm(ref) for s in sols]
+    assert max(errs) <= 1e-8, errs     # both within the truncation error of eps = 1e-10
     # they differ only where Gram rounding moves a rank decision at the margin
     assert np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(ref) <= 1e-8
+
+
+def test_ragged_batch_time_steps(H, ctx):
+    """Ragged batch (the batched workload's recipe at small sizes: N log-uniform,
+    alpha uniform in (1.1, 1.9), one operator per problem): every problem's
+    implicit Euler trajectory matches the oracle's, from one batched factor and
+    one batched time-step loop."""
+    probs = W.batched_1d(count=10, nmin=100, nmax=6000, steps=6)
+    A = build(H, ctx, probs, tol=1e-10, refine_max=2, rtol=1e-12)
+    A.factor()
+    u = dev(np.concatenate([p.u0 for p in probs]))
+    f = dev(np.concatenate([p.f for p in probs]))
+    A.time_steps(u, f, probs[0].dt, probs[0].steps, allow=(0, 2))
+    u = u.cpu().numpy()
+    off = 0
+    for p in probs:
+        ref = O.euler_1d(p)
+        err = np.linalg.norm(u[off:off + p.n] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-9, (p.name, err)
+        off += p.n
