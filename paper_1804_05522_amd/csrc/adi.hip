@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) k_lr_form(const LrJob* jobs, const LrUnit
   const int R = A.cols();
   const int r = *jb.rank_out;
   const double* M = Mbuf + int64_t(jb.mslot) * 2 * kMaxCat * kRS + (u.which ? kMaxCat * kRS : 0);
-  for (int e = threadIdx.x; e < R * r; e += 256) Ms[(e % R) + (e / R) * kMaxCat] = M[(e % R) + (e / R) * kMaxCat];
+  g2l(M, kMaxCat, Ms, kMaxCat, R, r);
   __syncthreads();
   const int64_t rows = u.which == 0 ? jb.rows_x : jb.rows_y;
   const int64_t i = int64_t(u.chunk) * 256 + threadIdx.x;

@@ -244,6 +244,18 @@ void launch_solve_t(hodlr_mat m, SolveFactors<TF, TL> F, const WorkUnit* wu, int
                     const double* x, int64_t ldx, double* y, int64_t ldy, int nc, hipStream_t s) {
   const TF* IL = F.IL;
   const int64_t lv = m->total_leaves;
+  if (NC == 1) {                        // one right-hand side: row-per-lane kernels
+    hipLaunchKernelGGL((k_project1<TF>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, wu, 0, IL, x, m->partL, lv);
+    if (nnu) hipLaunchKernelGGL(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 0, 1, m->partL, m->zL, lv);
+    hipLaunchKernelGGL((k_expand1<TF, TL>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, F, wu, 0, x, m->ytmp, m->zL,
+                       m->partU, lv, m->b);
+    if (nnu) hipLaunchKernelGGL(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 1, 1, m->partU, m->zU, lv);
+    hipLaunchKernelGGL((k_expand1<TF, TL>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, F, wu, 1, m->ytmp, y, m->zU,
+                       (double*)nullptr, lv, m->b);
+    (void)ldx;
+    (void)ldy;
+    return;
+  }
   hipLaunchKernelGGL((k_project<TF, NC>), dim3(nwu), dim3(256), 0, s, m->P, wu, 0, IL, x, ldx, nc, m->partL, lv);
   if (nnu) hipLaunchKernelGGL(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 0, nc, m->partL, m->zL, lv);
   hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 0, x, ldx, m->ytmp,
@@ -358,7 +370,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
     int32_t outi = 0;
     for (size_t k = 0; k < ts.size(); ++k)
       for (auto& p : pairs) {
-        const int chunks = int((rows_of(ts[k], p[0]) + 1023) / 1024);
+        const int chunks = int((rows_of(ts[k], p[0]) + kGramRows - 1) / kGramRows);
         reds.push_back(ReduceUnit{outi, std::max(chunks, 1), int32_t(k * 9 + p[2]), 0});
         for (int c = 0; c < std::max(chunks, 1); ++c)
           grams.push_back(GramUnit{int32_t(k), int16_t(p[0]), int16_t(p[1]), c, outi++});
@@ -492,8 +504,8 @@ static void enqueue_mwg(hodlr_mat m, hipStream_t s) {
   // block sizes of the latency-bound single-group kernels (512 measured fastest);
   // the leaf kernel splits its dot products over blockDim/128 threads, so it needs >= 128
   auto pick = [](int v) { return v >= 512 ? 512 : (v >= 256 ? 256 : 128); };
-  const int core_threads = pick(env_int("HODLR_CORE_THREADS", 512));
-  const int leaf_threads = pick(env_int("HODLR_LEAF_THREADS", 512));
+  const int core_threads = std::max(256, pick(env_int("HODLR_CORE_THREADS", 512)));
+  const int leaf_threads = std::max(256, pick(env_int("HODLR_LEAF_THREADS", 512)));
   const int Lmax = std::max(1, m->Lmax);
   for (size_t q = 0; q < m->mwg_kind.size(); ++q) {
     const int g = m->mwg_grid[q];
@@ -517,14 +529,14 @@ static void enqueue_mwg(hodlr_mat m, hipStream_t s) {
         hipLaunchKernelGGL(k_form, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_form + off, m->d_G, m->d_M);
         break;
       case KL_SPP:
-        hipLaunchKernelGGL(k_sp_project, dim3(g), dim3(256), 0, s, P, m->d_jobs + off2, m->d_punits + off, m->d_ppart, Lmax);
+        hipLaunchKernelGGL(k_sp_project, dim3(g), dim3(256), kSpProjLds, s, P, m->d_jobs + off2, m->d_punits + off, m->d_ppart, Lmax);
         break;
       case KL_SPR:
         hipLaunchKernelGGL(k_sp_reduce, dim3(g), dim3(256), 0, s, P, m->d_jobs + off2, m->d_punits + off, m->d_ppart,
                            m->d_pz, Lmax);
         break;
       default:
-        hipLaunchKernelGGL(k_sp_expand, dim3(g), dim3(128), 0, s, P, m->d_jobs + off2, m->d_punits + off, m->d_pz, m->b);
+        hipLaunchKernelGGL(k_sp_expand, dim3(g), dim3(256), kSpExpLds, s, P, m->d_jobs + off2, m->d_punits + off, m->d_pz, m->b);
         break;
     }
   }
@@ -588,6 +600,19 @@ static hodlr_status set_lds_limits() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(kFactorLdsBytes)));
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_core),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(kFactorLdsBytes)));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sp_project),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(kSpProjLds)));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sp_expand),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(kSpExpLds)));
+#define HFDE_LDS1(kern) HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&kern), \
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(kSolve1Lds)))
+  HFDE_LDS1(k_project1<double>);
+  HFDE_LDS1(k_project1<float>);
+  HFDE_LDS1(k_project1<bf16>);
+  HFDE_LDS1((k_expand1<double, double>));
+  HFDE_LDS1((k_expand1<float, float>));
+  HFDE_LDS1((k_expand1<bf16, float>));
+#undef HFDE_LDS1
   const int fl = int(size_t(kFftLds) * sizeof(double2));
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_small),
                               hipFuncAttributeMaxDynamicSharedMemorySize, fl));

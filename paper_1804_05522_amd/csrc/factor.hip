@@ -70,6 +70,72 @@ __device__ inline Cat cat1(const double* p, int64_t ld, int c) {
   return Cat{p, ld, c, 1.0, p, ld, 0, 0.0};
 }
 
+// Copies a rows x cols column-major block from global memory (ld lsrc) into
+// LDS (ld ldst), keeping `kBatch` loads in flight per thread: the loads of a
+// batch are issued before any of its LDS stores, so a thread waits for one
+// memory round trip per batch instead of one per element.
+constexpr int kBatch = 8;
+__device__ inline void g2l(const double* src, int64_t lsrc, double* dst, int ldst, int rows, int cols) {
+  const int tot = rows * cols, nt = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += nt * kBatch) {
+    double v[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int e = e0 + q * nt;
+      v[q] = e < tot ? src[(e % rows) + int64_t(e / rows) * lsrc] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int e = e0 + q * nt;
+      if (e < tot) dst[(e % rows) + (e / rows) * ldst] = v[q];
+    }
+  }
+}
+
+// As g2l, and zero-fills the rest of the rows_pad x cols_pad destination, so
+// that unrolled loops can run over the padded size without guards.
+__device__ inline void g2l_pad(const double* src, int64_t lsrc, double* dst, int ldst, int rows, int cols,
+                               int rows_pad, int cols_pad) {
+  const int tot = rows_pad * cols_pad, nt = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += nt * kBatch) {
+    double v[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int e = e0 + q * nt, i = e % rows_pad, c = e / rows_pad;
+      v[q] = (e < tot && i < rows && c < cols) ? src[i + int64_t(c) * lsrc] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int e = e0 + q * nt;
+      if (e < tot) dst[(e % rows_pad) + (e / rows_pad) * ldst] = v[q];
+    }
+  }
+}
+
+// sum_{q = lo}^{hi - 1} A[q SA] B[q SB] over LDS operands (constant strides, so
+// that the loads of a batch use immediate offsets from one base address):
+// eight loads of each operand are issued before their products are added into
+// four partial sums (q mod 4), combined at the end in a fixed order.  Reads up
+// to seven entries past hi (inside the work-group's LDS; their products are
+// discarded).
+template <int SA, int SB>
+__device__ inline double lds_dot(const double* A, const double* B, int lo, int hi) {
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int q0 = lo; q0 < hi; q0 += 8) {
+    const double* a = A + q0 * SA;
+    const double* b = B + q0 * SB;
+    double x[8], y[8];
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      x[w] = a[w * SA];
+      y[w] = b[w * SB];
+    }
+#pragma unroll
+    for (int w = 0; w < 8; ++w) s4[w & 3] += (q0 + w < hi) ? x[w] * y[w] : 0.0;
+  }
+  return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+}
+
 __device__ inline void wg_sync() {
   __threadfence_block();
   __syncthreads();
@@ -168,172 +234,221 @@ __device__ inline void wave_argmax(double& v, int& idx) {
   }
 }
 
-// Pivoted Cholesky of the R x R PSD matrix G (LDS, ld kLdG):  G ~ Lc Lc^T,
-// Lc (LDS, R x k, ld kLdG) in original row order.  Right-looking: each step
-// takes the largest remaining diagonal entry (wave argmax), forms the column
-// and subtracts its outer product from G in parallel.  Stops when the largest
-// remaining diagonal entry falls below delta * (largest initial one).
-// G is overwritten by the Schur complement.
-__device__ int wg_pchol(double* G, int R, double* Lc, double* dv, int* done, double delta) {
-  const int t = threadIdx.x;
-  __shared__ double s_piv, s_dmax;
-  __shared__ int s_p, s_stop;
-  for (int i = t; i < R; i += blockDim.x) {
-    dv[i] = G[i + i * kLdG];
-    done[i] = 0;
-  }
-  wg_sync();
-  if (t < 64) {
-    double v = t < R ? dv[t] : -1.0;
-    int ix = t;
-    wave_argmax(v, ix);
-    if (t == 0) s_dmax = v;
-  }
-  wg_sync();
-  const double dmax0 = s_dmax;
+// Pivot searches inside one wave: lane-wise maximum of a 32-bit key, returned to every lane (DPP butterflies
+// inside each row of 16 lanes, then the four row maxima by readlane).
+__device__ inline unsigned wave_max_u32(unsigned v) {
+  v = max(v, unsigned(__builtin_amdgcn_update_dpp(0, int(v), 0xB1, 0xF, 0xF, false)));   // quad_perm 1,0,3,2
+  v = max(v, unsigned(__builtin_amdgcn_update_dpp(0, int(v), 0x4E, 0xF, 0xF, false)));   // quad_perm 2,3,0,1
+  v = max(v, unsigned(__builtin_amdgcn_update_dpp(0, int(v), 0x141, 0xF, 0xF, false)));  // row_half_mirror
+  v = max(v, unsigned(__builtin_amdgcn_update_dpp(0, int(v), 0x140, 0xF, 0xF, false)));  // row_mirror
+  const unsigned a = unsigned(__builtin_amdgcn_readlane(int(v), 0)), b = unsigned(__builtin_amdgcn_readlane(int(v), 16));
+  const unsigned c = unsigned(__builtin_amdgcn_readlane(int(v), 32)), d = unsigned(__builtin_amdgcn_readlane(int(v), 48));
+  return max(max(a, b), max(c, d));
+}
+
+// Orders LDS accesses of one wave against each other (lanes exchange data
+// through LDS inside the wave, without a work-group barrier).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+// Sum over the 64 lanes of a wave, in a fixed order, returned to every lane.
+__device__ inline double wave_sum_fixed(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+// Pivot key of a non-negative value: its leading 26 bits, ties to the lowest
+// lane; NaN ranks first, lanes that do not take part rank last.
+__device__ inline unsigned pivot_key(double a, bool part, int lane) {
+  if (!part) return 0u;
+  const unsigned hi = (a == a) ? unsigned(__double2hiint(a)) : 0xFFFFFFFFu;
+  return (max(hi, 0x40u) & ~0x3Fu) | unsigned(63 - lane);
+}
+__device__ inline int pivot_lane(unsigned key) { return 63 - int(wave_max_u32(key) & 63u); }
+
+// Pivoted Cholesky of the R x R PSD matrix G (LDS, ld kLdG), by one wave:
+// G ~ Lc Lc^T with Lc (LDS, R x k, ld kLdG) in original row order.  Lane i
+// owns row i; each step takes the largest remaining diagonal entry and forms
+// the new column left-looking from the columns already made.  Stops when the
+// largest remaining diagonal entry falls below delta * (largest initial one).
+// G is read only.
+__device__ int wave_pchol(const double* G, int R, double* Lc, double delta) {
+  const int lane = threadIdx.x & 63;
+  double dv = lane < R ? G[lane + lane * kLdG] : 0.0;
+  bool done = lane >= R;
+  double dmax0 = 0.0;
   int k = 0;
   for (; k < R; ++k) {
-    if (t < 64) {
-      double v = (t < R && !done[t]) ? dv[t] : -1.0;
-      int ix = t;
-      wave_argmax(v, ix);
-      if (t == 0) {
-        s_stop = (!(v > delta * dmax0) || !(v > 0.0)) ? 1 : 0;
-        s_p = ix;
-        s_piv = s_stop ? 1.0 : sqrt(v);
-        if (!s_stop) done[ix] = 1;
-      }
-    }
-    wg_sync();
-    if (s_stop) break;
-    const int p = s_p;
-    const double piv = s_piv;
-    for (int i = t; i < R; i += blockDim.x) {
-      double c;
-      if (i == p) c = piv;
-      else if (done[i]) c = 0.0;
-      else c = G[i + p * kLdG] / piv;
-      Lc[i + k * kLdG] = c;
-    }
-    wg_sync();
-    for (int e = t; e < R * R; e += blockDim.x) {
-      const int i = e % R, j = e / R;
-      G[i + j * kLdG] -= Lc[i + k * kLdG] * Lc[j + k * kLdG];
-    }
-    for (int i = t; i < R; i += blockDim.x) {
-      const double c = Lc[i + k * kLdG];
-      if (!done[i]) dv[i] -= c * c;
-    }
-    wg_sync();
+    const int p = pivot_lane(pivot_key(dv, !done, lane));
+    const double dp = readlane_d(dv, p);
+    if (k == 0) dmax0 = dp;
+    if (!(dp > delta * dmax0) || !(dp > 0.0)) break;
+    const double piv = sqrt(dp);
+    double sum = lane < R ? G[lane + p * kLdG] : 0.0;
+    sum -= lds_dot<kLdG, kLdG>(Lc + lane, Lc + p, 0, k);
+    double c = sum / piv;
+    if (lane == p) c = piv;
+    if (done) c = 0.0;
+    if (lane < R) Lc[lane + k * kLdG] = c;
+    if (lane == p) done = true;
+    else if (!done) dv -= c * c;
+    wave_lds_sync();
   }
   return k;
 }
 
-// Householder QR with column pivoting of K (kA x kB, LDS, ld kLdG), stopping
-// when the Frobenius norm of the trailing block is <= tau.  On return the
-// upper triangle holds R, the Householder vectors sit below the diagonal
-// (unit leading entry implicit), tv holds their scalars, perm the column order.
-// Column norms are recomputed exactly every step (one wave per column, lanes =
-// rows), so tiny trailing norms are not lost to cancellation.
-__device__ int wg_qrcp(double* K, int kA, int kB, double tau, int* perm, double* tv, double* cn) {
-  const int t = threadIdx.x;
-  const int wave = t >> 6, lane = t & 63;
-  const int nwaves = blockDim.x >> 6;
-  __shared__ int s_p, s_stop;
-  __shared__ double s_beta, s_tau, s_sc;
-  for (int j = t; j < kB; j += blockDim.x) perm[j] = j;
-  wg_sync();
-  const int kmax = kA < kB ? kA : kB;
-  int step = 0;
-  for (; step < kmax; ++step) {
-    for (int j = step + wave; j < kB; j += nwaves) {
-      const double x = (lane >= step && lane < kA) ? K[lane + j * kLdG] : 0.0;
-      const double s = wave_sum(x * x);
-      if (lane == 0) cn[j] = s;
-    }
-    wg_sync();
-    if (t < 64) {
-      double v = (t >= step && t < kB) ? cn[t] : -1.0;
-      const double tot = wave_sum((t >= step && t < kB) ? cn[t] : 0.0);
-      int ix = t;
-      wave_argmax(v, ix);
-      if (t == 0) {
-        s_stop = (tot <= tau * tau) ? 1 : 0;
-        s_p = ix;
-      }
-    }
-    wg_sync();
-    if (s_stop) break;
-    const int p = s_p;
-    if (p != step) {
-      for (int i = t; i < kA; i += blockDim.x) {
-        const double a = K[i + step * kLdG];
-        K[i + step * kLdG] = K[i + p * kLdG];
-        K[i + p * kLdG] = a;
-      }
-      if (t == 0) {
-        const int q = perm[step];
-        perm[step] = perm[p];
-        perm[p] = q;
-      }
-      wg_sync();
-    }
-    if (t < 64) {
-      const double x0 = K[step + step * kLdG];
-      const double xi = (t > step && t < kA) ? K[t + step * kLdG] : 0.0;
-      const double s = wave_sum(xi * xi);
-      if (t == 0) {
-        const double nrm = sqrt(x0 * x0 + s);
-        if (nrm == 0.0) {
-          s_beta = 0.0; s_tau = 0.0; s_sc = 0.0;
-        } else {
-          const double beta = x0 >= 0 ? -nrm : nrm;
-          s_beta = beta;
-          s_tau = (beta - x0) / beta;
-          s_sc = 1.0 / (x0 - beta);
-        }
-      }
-    }
-    wg_sync();
-    for (int i = step + 1 + t; i < kA; i += blockDim.x) K[i + step * kLdG] *= s_sc;
-    if (t == 0) {
-      K[step + step * kLdG] = s_beta;
-      tv[step] = s_tau;
-    }
-    wg_sync();
-    const double tq = s_tau;
-    for (int j = step + 1 + wave; j < kB; j += nwaves) {
-      const double v = (lane == step) ? 1.0 : ((lane > step && lane < kA) ? K[lane + step * kLdG] : 0.0);
-      const double kij = (lane >= step && lane < kA) ? K[lane + j * kLdG] : 0.0;
-      const double w = tq * wave_sum(v * kij);
-      if (lane >= step && lane < kA) K[lane + j * kLdG] = kij - w * v;
-    }
-    wg_sync();
+// Householder QR with column pivoting of K (kA x kB <= 64 x 64, LDS, ld
+// kLdG), by waves 0..3 of the work-group (blockDim >= 256; the other waves
+// only take part in the barriers).  Lane j owns column j; wave w keeps rows
+// 16w..16w+15 of every column in registers.  Columns are not moved: perm[s]
+// is the column taken at step s.  Stops when the Frobenius norm of the
+// trailing block is <= tau; the trailing column norms are recomputed from the
+// updated entries at every step (no downdating, so small trailing norms are
+// not lost to cancellation).  On return column perm[s] holds R(0:s, s) in
+// rows 0..s and the Householder vector (unit leading entry implicit) below
+// row s; tv[s] is its scalar.  Two work-group barriers per step: one to add
+// up the column norms (and publish row s), one to add up the reflector dots.
+// scr: 576 doubles of LDS scratch.
+__device__ int wg_qrcp(double* K, int kA, int kB, double tau, int* perm, double* tv, double* scr) {
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const bool mine = wave < 4;
+  const int r0 = (mine ? wave : 0) * 16;
+  double* s_nb = scr;              // 4 x 64 partial norms
+  double* s_db = scr + 256;        // 4 x 64 partial dots
+  double* s_row = scr + 512;       // row s
+  double kr[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) kr[k] = (mine && r0 + k < kA && lane < kB) ? K[r0 + k + lane * kLdG] : 0.0;
+  bool done = lane >= kB;
+  double pn;
+  {
+    double p4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) p4[k & 3] += kr[k] * kr[k];
+    pn = (p4[0] + p4[1]) + (p4[2] + p4[3]);
   }
-  return step;
+  const int kmax = kA < kB ? kA : kB;
+  int s = 0;
+  for (; s < kmax; ++s) {
+    if (mine) {
+      s_nb[wave * 64 + lane] = pn;
+      if (wave == (s >> 4)) {
+        double x = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (r0 + k == s) x = kr[k];
+        s_row[lane] = x;
+      }
+    }
+    __syncthreads();
+    const double n2 = ((s_nb[lane] + s_nb[64 + lane]) + s_nb[128 + lane]) + s_nb[192 + lane];
+    const double tot = wave_sum_fixed(done ? 0.0 : n2);
+    if (tot <= tau * tau) break;                 // same value in every wave
+    const int p = pivot_lane(pivot_key(n2, !done, lane));
+    const double nrm = sqrt(readlane_d(n2, p));
+    const double x0 = s_row[p];
+    double beta = 0.0, tq = 0.0, sc = 0.0;
+    if (nrm > 0.0) {
+      beta = x0 >= 0 ? -nrm : nrm;
+      tq = (beta - x0) / beta;
+      sc = 1.0 / (x0 - beta);
+    }
+    double v[16];
+    double d4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double pk = readlane_d(kr[k], p);
+      v[k] = (r0 + k > s) ? pk * sc : ((r0 + k == s) ? 1.0 : 0.0);
+      d4[k & 3] += v[k] * kr[k];
+    }
+    const double pd = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+    if (mine) s_db[wave * 64 + lane] = pd;
+    if (t == 0) {
+      perm[s] = p;
+      tv[s] = tq;
+    }
+    __syncthreads();
+    const double dot = ((s_db[lane] + s_db[64 + lane]) + s_db[128 + lane]) + s_db[192 + lane];
+    const double wj = tq * dot;
+    if (lane == p) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (r0 + k >= s) kr[k] = (r0 + k == s) ? beta : v[k];
+      done = true;
+    } else if (!done) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) kr[k] -= wj * v[k];
+    }
+    {
+      double p4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (r0 + k > s) p4[k & 3] += kr[k] * kr[k];
+      pn = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+    }
+  }
+  __syncthreads();
+  if (mine && lane < kB) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (r0 + k < kA) K[r0 + k + lane * kLdG] = kr[k];
+  }
+  __syncthreads();
+  return s;
 }
 
-// Q = H_0 ... H_{r-1} [I_r; 0] (kA x r) into Q (LDS, ld kLdG) from the vectors
-// left in K by wg_qrcp; one wave per column.
-__device__ void wg_form_q(const double* K, int kA, int r, const double* tv, double* Q) {
-  const int t = threadIdx.x;
-  const int wave = t >> 6, lane = t & 63;
-  const int nwaves = blockDim.x >> 6;
-  for (int e = t; e < kA * r; e += blockDim.x) {
-    const int i = e % kA, j = e / kA;
-    Q[i + j * kLdG] = (i == j) ? 1.0 : 0.0;
-  }
-  wg_sync();
+// Q = H_0 ... H_{r-1} [I_r; 0] (kA x r <= 64 x 32, LDS, ld kLdG) from the
+// Householder vectors of Vp (column s holds vector s, unit leading entry
+// implicit), by waves 0..3 (blockDim >= 256): lane c forms column c, wave w
+// keeps rows 16w..16w+15 in registers; one barrier per reflector to add up
+// the four partial dots.  scr: 512 doubles of LDS scratch.
+__device__ void wg_form_q(const double* Vp, int kA, int r, const double* tv, double* Q, double* scr) {
+  const int t = threadIdx.x, wave = t >> 6, c = t & 63;
+  const bool mine = wave < 4;
+  const int r0 = (mine ? wave : 0) * 16;
+  double (*s_pd)[4 * 64] = reinterpret_cast<double (*)[4 * 64]>(scr);   // 2 x 4 x 64 partial dots
+  double q[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) q[k] = (r0 + k == c) ? 1.0 : 0.0;
   for (int s = r - 1; s >= 0; --s) {
-    const double ts = tv[s];
-    for (int c = wave; c < r; c += nwaves) {
-      const double v = (lane == s) ? 1.0 : ((lane > s && lane < kA) ? K[lane + s * kLdG] : 0.0);
-      const double q = (lane >= s && lane < kA) ? Q[lane + c * kLdG] : 0.0;
-      const double w = ts * wave_sum(v * q);
-      if (lane >= s && lane < kA) Q[lane + c * kLdG] = q - w * v;
-    }
-    wg_sync();
+    double v[16];
+    const double* vs = Vp + s * kLdG + r0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = vs[k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = (r0 + k > s && r0 + k < kA) ? v[k] : ((r0 + k == s) ? 1.0 : 0.0);
+    double d4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) d4[k & 3] += v[k] * q[k];
+    if (mine) s_pd[s & 1][wave * 64 + c] = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+    __syncthreads();
+    const double* pd = s_pd[s & 1];
+    const double w = tv[s] * (((pd[c] + pd[64 + c]) + pd[128 + c]) + pd[192 + c]);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) q[k] -= w * v[k];
   }
+  if (mine && c < r) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (r0 + k < kA) Q[r0 + k + c * kLdG] = q[k];
+  }
+  __syncthreads();
 }
 
 struct RecompressOut {
@@ -341,33 +456,34 @@ struct RecompressOut {
   bool capped;
 };
 
-// Truncated recompression of A B^T (see the file header).  Outputs
-// U (m x r, ldu) and V (n x r, ldv) with r <= rmax.
-__device__ __noinline__ RecompressOut wg_recompress(const Cat& A, int64_t m, const Cat& B, int64_t n, double tau,
-                                       int rmax, double* U, int64_t ldu, double* V, int64_t ldv,
-                                       double* L) {
+// From the Grams G = A^T A (lds::G) and KC = B^T B (lds::KC), R x R: balance
+// the columns (A D, B D^{-1}, D_j = (|b_j| / |a_j|)^{1/2}), factor both Grams by
+// pivoted Cholesky (LA, LB), truncate K = LA^T LB by QR with column pivoting
+// at tau, and leave the transfer matrices M_U = D LB(:, perm(1:r)) R11^{-1}
+// (R x r, ld kMaxCat) in lds::RED and M_V = D^{-1} LA Q1 (R x r, ld kLdG) in
+// lds::LB, so that U' = A M_U, V' = B M_V and U' V'^T = A B^T up to the
+// discarded trailing block of K.  Waves 0 and 1 factor the two Grams
+// concurrently; wave 0 runs the QR; the rest is work-group parallel.
+__device__ RecompressOut wg_core_grams(double* L, int R, double tau, int rmax) {
   const int t = threadIdx.x;
-  const int R = A.cols();
+  const int wave = t >> 6, lane = t & 63;
   RecompressOut out{0, false};
-  if (R == 0 || m == 0 || n == 0) return out;
   double* G = L + lds::G;
   double* LA = L + lds::LA;
   double* LB = L + lds::LB;
   double* KC = L + lds::KC;
   double* red = L + lds::RED;
-  double* vec = L + lds::VEC;     // [0,64) dA  [64,128) dB  [128,192) D  [192,256) dv  [256,320) tv  [320,384) cn
-  int* ivec = reinterpret_cast<int*>(L + lds::IVEC);   // [0,64) done [64,128) perm
-  wg_atb(A, A, m, G, kLdG, red);
-  wg_atb(B, B, n, KC, kLdG, red);
-  for (int j = t; j < R; j += kWG) {
-    double a = G[j + j * kLdG], b = KC[j + j * kLdG];
-    double Dj = (a > 0.0 && b > 0.0) ? sqrt(sqrt(b / a)) : 1.0;
-    vec[128 + j] = Dj;
+  double* vec = L + lds::VEC;     // [0,64) dA  [64,128) dB  [128,192) D  [256,320) tv
+  int* perm = reinterpret_cast<int*>(L + lds::IVEC) + 64;
+  __shared__ int s_k[3];
+  for (int j = t; j < R; j += blockDim.x) {
+    const double a = G[j + j * kLdG], b = KC[j + j * kLdG];
+    vec[128 + j] = (a > 0.0 && b > 0.0) ? sqrt(sqrt(b / a)) : 1.0;
     vec[j] = a;
     vec[64 + j] = b;
   }
   wg_sync();
-  for (int e = t; e < R * R; e += kWG) {
+  for (int e = t; e < R * R; e += blockDim.x) {
     const int i = e % R, j = e / R;
     const double di = vec[128 + i], dj = vec[128 + j];
     const bool zi = !(vec[i] > 0.0 && vec[64 + i] > 0.0), zj = !(vec[j] > 0.0 && vec[64 + j] > 0.0);
@@ -376,45 +492,69 @@ __device__ __noinline__ RecompressOut wg_recompress(const Cat& A, int64_t m, con
   }
   wg_sync();
   const double delta = 1e-15 * R;
-  const int kA = wg_pchol(G, R, LA, vec + 192, ivec, delta);
-  const int kB = wg_pchol(KC, R, LB, vec + 192, ivec, delta);
-  if (kA == 0 || kB == 0) return out;
-  // K = LA^T LB (kA x kB)
-  for (int e = t; e < kA * kB; e += kWG) {
-    const int i = e % kA, j = e / kA;
-    double s = 0;
-    for (int q = 0; q < R; ++q) s += LA[q + i * kLdG] * LB[q + j * kLdG];
-    KC[i + j * kLdG] = s;
+  if (wave == 0) {
+    const int k = wave_pchol(G, R, LA, delta);
+    if (lane == 0) s_k[0] = k;
+  } else if (wave == 1) {
+    const int k = wave_pchol(KC, R, LB, delta);
+    if (lane == 0) s_k[1] = k;
   }
   wg_sync();
-  int* perm = ivec + 64;
-  int r = wg_qrcp(KC, kA, kB, tau, perm, vec + 256, vec + 320);
+  const int kA = s_k[0], kB = s_k[1];
+  if (kA == 0 || kB == 0) return out;
+  for (int e = t; e < kA * kB; e += blockDim.x) {
+    const int i = e % kA, j = e / kA;
+    KC[i + j * kLdG] = lds_dot<1, 1>(LA + i * kLdG, LB + j * kLdG, 0, R);
+  }
+  wg_sync();
+  const int rq = wg_qrcp(KC, kA, kB, tau, perm, vec + 256, red);   // RED is free until M_U
+  const int rr = rq < rmax ? rq : rmax;
+  for (int e = t; e < kA * rr; e += blockDim.x) {   // R factor and vectors in pivot order
+    const int i = e % kA, c = e / kA;
+    G[i + c * kLdG] = KC[i + perm[c] * kLdG];
+  }
+  wg_sync();
+  wg_form_q(G, kA, rr, vec + 256, KC, red);
+  if (t == 0) s_k[2] = rq;
+  wg_sync();
+  int r = s_k[2];
   if (r > rmax) {
     r = rmax;
     out.capped = true;
   }
   out.rank = r;
   if (r == 0) return out;
-  // Q = H_0 ... H_{r-1} [I_r; 0]  (kA x r) into G
-  wg_form_q(KC, kA, r, vec + 256, G);
-  // M_U = D * LB[:, perm[0:r]] * R11^{-1}  (R x r) into red
-  for (int i = t; i < R; i += kWG) {
+  for (int i = t; i < R; i += blockDim.x) {
     for (int j = 0; j < r; ++j) {
-      double x = LB[i + perm[j] * kLdG];
-      for (int l = 0; l < j; ++l) x -= red[i + l * kMaxCat] * KC[l + j * kLdG];
-      red[i + j * kMaxCat] = x / KC[j + j * kLdG];
+      const double x = LB[i + perm[j] * kLdG] - lds_dot<kMaxCat, 1>(red + i, G + j * kLdG, 0, j);
+      red[i + j * kMaxCat] = x / G[j + j * kLdG];
     }
     for (int j = 0; j < r; ++j) red[i + j * kMaxCat] *= vec[128 + i];
   }
   wg_sync();
-  // M_V = D^{-1} * LA * Q  (R x r) into LB
-  for (int e = t; e < R * r; e += kWG) {
+  for (int e = t; e < R * r; e += blockDim.x) {
     const int i = e % R, j = e / R;
-    double s = 0;
-    for (int q = 0; q < kA; ++q) s += LA[i + q * kLdG] * G[q + j * kLdG];
-    LB[i + j * kLdG] = s / vec[128 + i];
+    LB[i + j * kLdG] = lds_dot<kLdG, 1>(LA + i, KC + j * kLdG, 0, kA) / vec[128 + i];
   }
   wg_sync();
+  return out;
+}
+
+// Truncated recompression of A B^T (see the file header).  Outputs
+// U (m x r, ldu) and V (n x r, ldv) with r <= rmax.
+__device__ __noinline__ RecompressOut wg_recompress(const Cat& A, int64_t m, const Cat& B, int64_t n, double tau,
+                                       int rmax, double* U, int64_t ldu, double* V, int64_t ldv,
+                                       double* L) {
+  const int R = A.cols();
+  RecompressOut out{0, false};
+  if (R == 0 || m == 0 || n == 0) return out;
+  double* red = L + lds::RED;
+  wg_atb(A, A, m, L + lds::G, kLdG, red);
+  wg_atb(B, B, n, L + lds::KC, kLdG, red);
+  out = wg_core_grams(L, R, tau, rmax);
+  const int r = out.rank;
+  if (r == 0) return out;
+  double* LB = L + lds::LB;
   wg_a_times_small(A, m, red, kMaxCat, r, U, ldu, 1.0);
   wg_a_times_small(B, n, LB, kLdG, r, V, ldv, 1.0);
   return out;
@@ -534,9 +674,27 @@ __device__ __noinline__ void wg_hmatvec(const DevPtrs& P, const Item& it, int b,
 // ------------------------------------------------------------ leaf LU
 // S = A_leaf - P Q^T, partial-pivoted LU in LDS, inverses of both
 // triangular factors.  Returns false on a zero or non-finite pivot.
-__device__ __noinline__ bool wg_leaf(const DevPtrs& P, const Item& it, int b, int64_t leaf, const double* PP,
-                        const double* PQ, int rp, double* L) {
+// Dense leaf of the HODLR LU (Sec. 3.4.1: the diagonal blocks at the finest
+// level are factored densely).  S = A_leaf - P Q^T (pending Schur update) is
+// factored by Gaussian elimination with partial pivoting, then the inverses of
+// its unit lower and upper factors are formed for the solve.  Needs blockDim
+// >= 256.
+//   elimination: waves 0..3 hold 16 columns each in registers (lane i: row i).
+//     At step j the wave owning column j picks the pivot row p (largest
+//     |S(i,j)| over rows not yet chosen, compared on its leading 26 bits, ties
+//     to the lowest row: within a factor 1 + 2^-14 of the largest, which keeps
+//     the growth bound of partial pivoting), forms the multipliers and updates
+//     its own later columns; after one work-group barrier the waves to its
+//     right update theirs with the pivot row read by readlane.  Rows are not
+//     moved: the row chosen at step j is written to position j at the end.
+//   inverses: blocked, L^{-1} by one half of the work-group and U^{-1} by the
+//     other: 8 x 8 diagonal blocks by substitution, then for block sizes 8, 16,
+//     32 the off-diagonal block of each pair, (L^{-1})_21 = -L22^{-1} L21
+//     L11^{-1} and (U^{-1})_12 = -U11^{-1} U12 U22^{-1}, by two small products.
+__device__ inline bool wg_leaf(const DevPtrs& P, const Item& it, int b, int64_t leaf, const double* PP,
+                               const double* PQ, int rp, double* L) {
   const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
   const Node lf = P.nodes[node_index(it, it.L, leaf)];
   const int m = lf.size;
   const int64_t gl = it.leaf0 + leaf;
@@ -545,90 +703,143 @@ __device__ __noinline__ bool wg_leaf(const DevPtrs& P, const Item& it, int b, in
   double* UI = L + lds::UI;
   double* PL = L + lds::PL;
   double* QL = L + lds::QL;
-  __shared__ int s_p;
-  __shared__ int s_bad;
   __shared__ int s_perm[kMaxLeaf];
-  for (int e = t; e < m * rp; e += blockDim.x) {
-    const int i = e % m, s = e / m;
-    PL[i + s * kMaxLeaf] = PP[lf.start + i + int64_t(s) * it.n];
-    QL[i + s * kMaxLeaf] = PQ[lf.start + i + int64_t(s) * it.n];
+  __shared__ int s_pp[2];
+  __shared__ int s_badw[4];
+  __shared__ double s_l[2 * 64];
+  if (rp > 0) {
+    g2l(PP + lf.start, it.n, PL, kMaxLeaf, m, rp);
+    g2l(PQ + lf.start, it.n, QL, kMaxLeaf, m, rp);
   }
-  if (t < b) s_perm[t] = t;
-  if (t == 0) s_bad = 0;
+  g2l(P.Aleaf + gl * int64_t(b) * b, b, S, kLdsLeaf, b, b);
   wg_sync();
-  const double* A = P.Aleaf + gl * int64_t(b) * b;
-  for (int e = t; e < b * b; e += blockDim.x) {
-    const int i = e % b, j = e / b;
-    double v = A[e];
-    if (i < m && j < m)
-      for (int s = 0; s < rp; ++s) v -= PL[i + s * kMaxLeaf] * QL[j + s * kMaxLeaf];
-    S[i + j * kLdsLeaf] = v;
-  }
-  wg_sync();
-  for (int j = 0; j < b; ++j) {
-    if (t < 64) {
-      double v = (t >= j && t < b) ? fabs(S[t + j * kLdsLeaf]) : -1.0;
-      if (v != v) v = 1e308;   // a NaN pivot candidate is picked and flagged
-      int ix = t;
-      wave_argmax(v, ix);
-      if (t == 0) {
-        const double pv = S[ix + j * kLdsLeaf];
-        if (!(fabs(pv) > 0.0) || !isfinite(pv)) s_bad = 1;
-        s_p = ix;
-        if (ix != j) { int q = s_perm[j]; s_perm[j] = s_perm[ix]; s_perm[ix] = q; }
-      }
+  if (rp > 0) {
+    for (int e = t; e < m * m; e += blockDim.x) {
+      const int i = e % m, j = e / m;
+      S[i + j * kLdsLeaf] -= lds_dot<kMaxLeaf, kMaxLeaf>(PL + i, QL + j, 0, rp);
     }
     wg_sync();
-    const int p = s_p;
-    if (p != j) {
-      for (int c = t; c < b; c += blockDim.x) {
-        double a = S[j + c * kLdsLeaf];
-        S[j + c * kLdsLeaf] = S[p + c * kLdsLeaf];
-        S[p + c * kLdsLeaf] = a;
+  }
+  // ---- elimination
+  {
+    const bool mine = wave < 4;
+    const int c0 = (mine ? wave : 0) * 16;
+    double a[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)                // rows and columns past b: identity
+      a[k] = (mine && lane < b && c0 + k < b) ? S[lane + (c0 + k) * kLdsLeaf] : (lane == c0 + k ? 1.0 : 0.0);
+    bool done = lane >= b;
+    int order = lane;
+    int bad = 0;
+    for (int jp = 0; jp < 4; ++jp) {
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = jp * 16 + jj;
+        if (j < b) {
+          double* lb = s_l + (j & 1) * 64;
+          if (wave == jp) {
+            const int p = pivot_lane(pivot_key(fabs(a[jj]), !done, lane));
+            const double pv = readlane_d(a[jj], p);
+            if (!(fabs(pv) > 0.0) || !isfinite(pv)) bad = 1;
+            const double ip = 1.0 / pv;
+            if (lane == p) {
+              done = true;
+              order = j;
+            }
+            const double l = done ? 0.0 : a[jj] * ip;
+            if (!done) a[jj] = l;
+#pragma unroll
+            for (int k = jj + 1; k < 16; ++k) a[k] -= l * readlane_d(a[k], p);
+            lb[lane] = l;
+            if (lane == 0) {
+              s_pp[j & 1] = p;
+              s_perm[j] = p;
+            }
+          }
+          __syncthreads();
+          if (mine && wave != jp) {              // every wave tracks where each row goes
+            const int p = __builtin_amdgcn_readfirstlane(s_pp[j & 1]);
+            if (lane == p) {
+              done = true;
+              order = j;
+            }
+            if (wave > jp) {
+              const double l = lb[lane];
+#pragma unroll
+              for (int k = 0; k < 16; ++k) a[k] -= l * readlane_d(a[k], p);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (mine) {                              // row chosen at step j goes to position j
+#pragma unroll
+      for (int k = 0; k < 16; ++k) S[order + (c0 + k) * kLdsLeaf] = a[k];
+    }
+    if (mine && lane == 0) s_badw[wave] = bad;
+  }
+  for (int e = t; e < 64 * kLdsLeaf; e += blockDim.x) {
+    LI[e] = 0.0;
+    UI[e] = 0.0;
+  }
+  wg_sync();
+  // ---- inverses (S now holds L\U in pivot order)
+  {
+    const int half = blockDim.x >> 1;
+    const int grp = t / half, loc = t % half;
+    double* X = grp == 0 ? LI : UI;
+    double* T = grp == 0 ? PL : QL;            // s x s products of a level (<= 32 * 32 per pair set)
+    if (loc < 64) {                            // 8 x 8 diagonal blocks, one column per thread
+      const int bb = loc >> 3, c = loc & 7, o = bb * 8;
+      double x[8];
+      if (grp == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          double v = (k == c) ? 1.0 : 0.0;
+#pragma unroll
+          for (int q = 0; q < k; ++q) v -= S[(o + k) + (o + q) * kLdsLeaf] * x[q];
+          x[k] = k < c ? 0.0 : v;
+        }
+      } else {
+#pragma unroll
+        for (int k = 7; k >= 0; --k) {
+          double v = (k == c) ? 1.0 : 0.0;
+#pragma unroll
+          for (int q = k + 1; q < 8; ++q) v -= S[(o + k) + (o + q) * kLdsLeaf] * x[q];
+          x[k] = k > c ? 0.0 : v / S[(o + k) + (o + k) * kLdsLeaf];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) X[(o + k) + (o + c) * kLdsLeaf] = x[k];
+    }
+    wg_sync();
+    for (int sz = 8; sz < 64; sz *= 2) {
+      const int pairs = 64 / (2 * sz), tot = pairs * sz * sz;
+      // T = L21 X11 (lower) or U12 X22 (upper), per pair, sz x sz
+      for (int e = loc; e < tot; e += half) {
+        const int pi = e / (sz * sz), r = e % (sz * sz), i = r % sz, c = r / sz, o = pi * 2 * sz;
+        double v = 0.0;
+        if (grp == 0) {
+          for (int q = c; q < sz; ++q) v += S[(o + sz + i) + (o + q) * kLdsLeaf] * X[(o + q) + (o + c) * kLdsLeaf];
+        } else {
+          for (int q = 0; q <= c; ++q) v += S[(o + i) + (o + sz + q) * kLdsLeaf] * X[(o + sz + q) + (o + sz + c) * kLdsLeaf];
+        }
+        T[e] = v;
       }
       wg_sync();
-    }
-    const double piv = S[j + j * kLdsLeaf];
-    const double ip = (piv != 0.0) ? 1.0 / piv : 0.0;
-    for (int i = j + 1 + t; i < b; i += blockDim.x) S[i + j * kLdsLeaf] *= ip;
-    wg_sync();
-    const int rem = b - j - 1;
-    for (int e = t; e < rem * rem; e += blockDim.x) {
-      const int i = j + 1 + e % rem, c = j + 1 + e / rem;
-      S[i + c * kLdsLeaf] -= S[i + j * kLdsLeaf] * S[j + c * kLdsLeaf];
-    }
-    wg_sync();
-  }
-  // inverses, row by row with 4 threads per dot product: L^{-1} by forward
-  // substitution (threads 0..255: column c = t/4), U^{-1} by backward
-  // substitution (threads 256..511), one row of each per step.
-  {
-    const int nt = blockDim.x, half = nt >> 1;
-    const int tpd = half >= 64 ? half / 64 : 1;   // threads per dot product: 1, 2 or 4 (blockDim >= 128)
-    const int grp = t / half, loc = t % half, c = loc / tpd, q = loc % tpd;
-    for (int e = t; e < b * b; e += nt) {
-      const int i = e % b, jj = e / b;
-      LI[i + jj * kLdsLeaf] = (i == jj) ? 1.0 : 0.0;
-      UI[i + jj * kLdsLeaf] = 0.0;
-    }
-    wg_sync();
-    for (int step = 0; step < b; ++step) {
-      if (grp == 0) {
-        const int i = step;                      // row of L^{-1}
-        double s = 0.0;
-        if (c < i)
-          for (int k = c + q; k < i; k += tpd) s -= S[i + k * kLdsLeaf] * LI[k + c * kLdsLeaf];
-        if (tpd > 1) s += __shfl_xor(s, 1);
-        if (tpd > 2) s += __shfl_xor(s, 2);
-        if (c < i && q == 0) LI[i + c * kLdsLeaf] = s;
-      } else {
-        const int i = b - 1 - step;              // row of U^{-1}
-        double s = 0.0;
-        if (c > i && c < b)
-          for (int k = i + 1 + q; k <= c; k += tpd) s -= S[i + k * kLdsLeaf] * UI[k + c * kLdsLeaf];
-        if (tpd > 1) s += __shfl_xor(s, 1);
-        if (tpd > 2) s += __shfl_xor(s, 2);
-        if (q == 0 && c >= i && c < b) UI[i + c * kLdsLeaf] = (c == i ? 1.0 : s) / S[i + i * kLdsLeaf];
+      // X21 = -X22 T (lower) or X12 = -X11 T (upper)
+      for (int e = loc; e < tot; e += half) {
+        const int pi = e / (sz * sz), r = e % (sz * sz), i = r % sz, c = r / sz, o = pi * 2 * sz;
+        const double* Tp = T + pi * sz * sz;
+        double v = 0.0;
+        if (grp == 0) {
+          for (int q = 0; q <= i; ++q) v += X[(o + sz + i) + (o + sz + q) * kLdsLeaf] * Tp[q + c * sz];
+          X[(o + sz + i) + (o + c) * kLdsLeaf] = -v;
+        } else {
+          for (int q = i; q < sz; ++q) v += X[(o + i) + (o + q) * kLdsLeaf] * Tp[q + c * sz];
+          X[(o + i) + (o + sz + c) * kLdsLeaf] = -v;
+        }
       }
       wg_sync();
     }
@@ -644,8 +855,9 @@ __device__ __noinline__ bool wg_leaf(const DevPtrs& P, const Item& it, int b, in
     P.perm[gl * b + t] = s_perm[t];
     P.perminv[gl * b + s_perm[t]] = t;
   }
+  const bool ok = (s_badw[0] | s_badw[1] | s_badw[2] | s_badw[3]) == 0;
   wg_sync();
-  return s_bad == 0;
+  return ok;
 }
 
 // ------------------------------------------------------------ driver

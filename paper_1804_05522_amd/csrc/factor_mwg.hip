@@ -105,8 +105,9 @@ __device__ inline OpRef op_ref(const DevPtrs& P, const Item& it, int d, int64_t 
   }
 }
 
-constexpr int kGramRows = 1024;     // rows per partial
+constexpr int kGramRows = 256;      // rows per partial
 constexpr int kGramSub = 32;        // rows staged in LDS at a time
+constexpr int kGramLd = 66;         // LDS row stride (16-byte aligned rows, spread banks)
 constexpr int kG2 = kMaxCat * kMaxCat;   // one 64 x 64 matrix
 
 // A gram unit: task, pair of operand types (x, y), chunk.
@@ -117,11 +118,13 @@ struct GramUnit {
   int32_t out;       // output slot (partial index)
 };
 
-// partial[out] = X[chunk rows]^T Y[chunk rows]  (64 x 64, zero padded)
+// partial[out] = X[chunk rows]^T Y[chunk rows]  (64 x 64, zero padded).
+// Slabs of 32 rows are staged row-major in LDS; the next slab is fetched into
+// registers while the current one is multiplied.
 __global__ void __launch_bounds__(256) k_gram_partial(DevPtrs P, const NodeTask* tasks, const GramUnit* units,
                                                       double* partial) {
-  __shared__ double xs[kGramSub * kMaxCat];
-  __shared__ double ys[kGramSub * kMaxCat];
+  __shared__ __align__(16) double xs[kGramSub * kGramLd];
+  __shared__ __align__(16) double ys[kGramSub * kGramLd];
   const GramUnit u = units[blockIdx.x];
   const NodeTask tk = tasks[u.task];
   const Item it = P.items[tk.item];
@@ -129,8 +132,7 @@ __global__ void __launch_bounds__(256) k_gram_partial(DevPtrs P, const NodeTask*
   const OpRef Y = op_ref(P, it, tk.d, tk.j, u.ty);
   const int M = X.cat.cols(), N = Y.cat.cols();
   const int t = threadIdx.x;
-  // thread tile: 4x4 outputs of the 64x64 result
-  const int ti = (t % 16) * 4, tj = (t / 16) * 4;
+  const int ti = (t % 16) * 4, tj = (t / 16) * 4;   // 4 x 4 outputs per thread
   double acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -138,22 +140,37 @@ __global__ void __launch_bounds__(256) k_gram_partial(DevPtrs P, const NodeTask*
     for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
   const int64_t r0 = int64_t(u.chunk) * kGramRows;
   const int64_t r1 = min<int64_t>(X.rows, r0 + kGramRows);
+  constexpr int kPer = kGramSub * kMaxCat / 256;      // elements per thread per slab
+  double px[kPer], py[kPer];
+  auto fetch = [&](int64_t s0) {
+    const int sr = int(min<int64_t>(kGramSub, r1 - s0));
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = t + q * 256, i = e % kGramSub, c = e / kGramSub;
+      px[q] = (i < sr && c < M) ? X.cat.at(s0 + i, c) : 0.0;
+      py[q] = (i < sr && c < N) ? Y.cat.at(s0 + i, c) : 0.0;
+    }
+  };
+  if (r0 < r1) fetch(r0);
   for (int64_t s0 = r0; s0 < r1; s0 += kGramSub) {
     const int sr = int(min<int64_t>(kGramSub, r1 - s0));
     __syncthreads();
-    for (int e = t; e < kGramSub * kMaxCat; e += 256) {
-      const int i = e % kGramSub, c = e / kGramSub;
-      xs[e] = (i < sr && c < M) ? X.cat.at(s0 + i, c) : 0.0;
-      ys[e] = (i < sr && c < N) ? Y.cat.at(s0 + i, c) : 0.0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = t + q * 256, i = e % kGramSub, c = e / kGramSub;
+      xs[i * kGramLd + c] = px[q];
+      ys[i * kGramLd + c] = py[q];
     }
     __syncthreads();
+    if (s0 + kGramSub < r1) fetch(s0 + kGramSub);
     if (ti < M && tj < N) {
       for (int i = 0; i < sr; ++i) {
-        double xv[4], yv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) xv[a] = xs[i + (ti + a) * kGramSub];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) yv[b] = ys[i + (tj + b) * kGramSub];
+        const double2 x01 = *reinterpret_cast<const double2*>(xs + i * kGramLd + ti);
+        const double2 x23 = *reinterpret_cast<const double2*>(xs + i * kGramLd + ti + 2);
+        const double2 y01 = *reinterpret_cast<const double2*>(ys + i * kGramLd + tj);
+        const double2 y23 = *reinterpret_cast<const double2*>(ys + i * kGramLd + tj + 2);
+        const double xv[4] = {x01.x, x01.y, x23.x, x23.y};
+        const double yv[4] = {y01.x, y01.y, y23.x, y23.y};
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -178,11 +195,20 @@ struct ReduceUnit {
 
 __global__ void __launch_bounds__(256) k_gram_reduce(const ReduceUnit* units, const double* partial, double* G) {
   const ReduceUnit u = units[blockIdx.x];
-  for (int e = threadIdx.x; e < kG2; e += 256) {
-    double s = 0.0;
-    for (int q = 0; q < u.count; ++q) s += partial[int64_t(u.first + q) * kG2 + e];
-    G[int64_t(u.dst) * kG2 + e] = s;
+  constexpr int kPer = kG2 / 256;
+  double acc[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) acc[k] = 0.0;
+  for (int q = 0; q < u.count; ++q) {          // one round trip per partial
+    const double* src = partial + int64_t(u.first + q) * kG2 + threadIdx.x;
+    double v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) v[k] = src[k * 256];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) acc[k] += v[k];
   }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) G[int64_t(u.dst) * kG2 + threadIdx.x + k * 256] = acc[k];
 }
 
 // Recompression core from two Grams (see wg_recompress): G_A, G_B -> transfer
@@ -191,70 +217,19 @@ __device__ RecompressOut wg_recompress_core(const double* GAg, const double* GBg
                                             double* MU, double* MV, double* L) {
   const int t = threadIdx.x;
   RecompressOut out{0, false};
-  double* G = L + lds::G;
-  double* LA = L + lds::LA;
-  double* LB = L + lds::LB;
-  double* KC = L + lds::KC;
-  double* red = L + lds::RED;
-  double* vec = L + lds::VEC;
-  int* ivec = reinterpret_cast<int*>(L + lds::IVEC);
   if (R == 0) return out;
-  for (int e = t; e < R * R; e += blockDim.x) {
-    const int i = e % R, j = e / R;
-    G[i + j * kLdG] = GAg[i + j * kMaxCat];
-    KC[i + j * kLdG] = GBg[i + j * kMaxCat];
-  }
+  g2l(GAg, kMaxCat, L + lds::G, kLdG, R, R);
+  g2l(GBg, kMaxCat, L + lds::KC, kLdG, R, R);
   wg_sync();
-  for (int j = t; j < R; j += blockDim.x) {
-    double a = G[j + j * kLdG], b = KC[j + j * kLdG];
-    vec[128 + j] = (a > 0.0 && b > 0.0) ? sqrt(sqrt(b / a)) : 1.0;
-    vec[j] = a;
-    vec[64 + j] = b;
-  }
-  wg_sync();
-  for (int e = t; e < R * R; e += blockDim.x) {
-    const int i = e % R, j = e / R;
-    const double di = vec[128 + i], dj = vec[128 + j];
-    const bool zi = !(vec[i] > 0.0 && vec[64 + i] > 0.0), zj = !(vec[j] > 0.0 && vec[64 + j] > 0.0);
-    G[i + j * kLdG] = (zi || zj) ? 0.0 : G[i + j * kLdG] * di * dj;
-    KC[i + j * kLdG] = (zi || zj) ? 0.0 : KC[i + j * kLdG] / (di * dj);
-  }
-  wg_sync();
-  const double delta = 1e-15 * R;
-  const int kA = wg_pchol(G, R, LA, vec + 192, ivec, delta);
-  const int kB = wg_pchol(KC, R, LB, vec + 192, ivec, delta);
-  if (kA == 0 || kB == 0) return out;
-  for (int e = t; e < kA * kB; e += blockDim.x) {
-    const int i = e % kA, j = e / kA;
-    double s = 0;
-    for (int q = 0; q < R; ++q) s += LA[q + i * kLdG] * LB[q + j * kLdG];
-    KC[i + j * kLdG] = s;
-  }
-  wg_sync();
-  int* perm = ivec + 64;
-  int r = wg_qrcp(KC, kA, kB, tau, perm, vec + 256, vec + 320);
-  if (r > rmax) {
-    r = rmax;
-    out.capped = true;
-  }
-  out.rank = r;
-  if (r == 0) return out;
-  wg_form_q(KC, kA, r, vec + 256, G);
-  for (int i = t; i < R; i += blockDim.x) {
-    for (int j = 0; j < r; ++j) {
-      double x = LB[i + perm[j] * kLdG];
-      for (int l = 0; l < j; ++l) x -= red[i + l * kMaxCat] * KC[l + j * kLdG];
-      red[i + j * kMaxCat] = x / KC[j + j * kLdG];
-    }
-    for (int j = 0; j < r; ++j) MU[i + j * kMaxCat] = red[i + j * kMaxCat] * vec[128 + i];
-  }
+  out = wg_core_grams(L, R, tau, rmax);
+  const int r = out.rank;
+  const double* red = L + lds::RED;
+  const double* LB = L + lds::LB;
   for (int e = t; e < R * r; e += blockDim.x) {
     const int i = e % R, j = e / R;
-    double s = 0;
-    for (int q = 0; q < kA; ++q) s += LA[i + q * kLdG] * G[q + j * kLdG];
-    MV[i + j * kMaxCat] = s / vec[128 + i];
+    MU[i + j * kMaxCat] = red[i + j * kMaxCat];
+    MV[i + j * kMaxCat] = LB[i + j * kLdG];
   }
-  wg_sync();
   return out;
 }
 
@@ -317,10 +292,7 @@ __global__ void __launch_bounds__(256) k_form(DevPtrs P, const NodeTask* tasks, 
   else { r = P.rankP[node_index(it, tk.d + 1, 2 * int64_t(tk.j) + 1)];
          M = Mbuf + int64_t(tk.slot * 3 + 2) * 2 * kMaxCat * kRS + (fu.out == 6 ? kMaxCat * kRS : 0); }
   // M: R x r with ld kMaxCat (G for C has ld kMaxCat too)
-  for (int e = threadIdx.x; e < R * r; e += 256) {
-    const int i = e % R, c = e / R;
-    Ms[i + c * kMaxCat] = M[i + c * kMaxCat];
-  }
+  g2l(M, kMaxCat, Ms, kMaxCat, R, r);
   __syncthreads();
   double* Y;
   int64_t row0;
@@ -380,10 +352,20 @@ __device__ inline int prod_cols(const DevPtrs& P, const Item& it, const ProdJob&
 
 constexpr int kPNC = kRS;   // columns of a subtree product
 
-// partial projections of the leaf's X rows for every subtree level where the leaf is on the source side
+constexpr int kSpWaves = 4;          // waves of the subtree-product kernels (256 threads)
+constexpr int kSpLd = 65;            // LDS stride of staged 64-row blocks
+constexpr size_t kSpProjLds = size_t(64 * kPNC + kSpWaves * kSpLd * kRS) * sizeof(double);
+constexpr size_t kSpExpLds = size_t(64 * kPNC + 64 * kSpLd + (kSpWaves - 1) * (kSpLd * kRS + kRS * kPNC)) * sizeof(double);
+
+// Partial projections B_d(leaf rows)^T X(leaf rows) for every subtree level d
+// where the leaf is on the source side.  The source levels are dealt
+// round-robin to the waves; a wave stages its level's leaf rows of B_d in its
+// own LDS slice (one round trip of r loads per lane) and forms the r x nc
+// block (lane: row s of the block, half of its columns).
 __global__ void __launch_bounds__(256) k_sp_project(DevPtrs P, const ProdJob* jobs, const ProdUnit* units,
                                                     double* part, int Lmax) {
-  __shared__ double xl[64 * kPNC];
+  extern __shared__ double sm[];
+  double* xl = sm;
   const ProdUnit u = units[blockIdx.x];
   const ProdJob jb = jobs[u.job];
   const Item it = P.items[jb.item];
@@ -391,35 +373,44 @@ __global__ void __launch_bounds__(256) k_sp_project(DevPtrs P, const ProdJob* jo
   const Node lf = P.nodes[node_index(it, it.L, leaf)];
   const int m = lf.size, nc = prod_cols(P, it, jb);
   const double* X = lvl_ptr(arr_base(P, jb.xarr), it, jb.xlev) + lf.start;
-  const int t = threadIdx.x;
-  for (int e = t; e < m * nc; e += 256) {
-    const int i = e % m, c = e / m;
-    xl[i + c * 64] = X[i + int64_t(c) * it.n];
-  }
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  double* Bl = sm + 64 * kPNC + wave * kSpLd * kRS;
+  g2l_pad(X, it.n, xl, 64, m, nc, 64, kPNC);
   __syncthreads();
   const bool src_c1 = (jb.which == 0) ? !jb.trans : jb.trans;
   const double* Bb = jb.which == 0 ? P.IL : P.IU;
   const int32_t* ranks = jb.which == 0 ? P.rankL : P.rankU;
-  const int slot = t >> 5, s = t & 31;
-  for (int d = jb.d0 + slot; d < it.L; d += 8) {
+  int cnt = 0;
+  for (int d = jb.d0; d < it.L; ++d) {
     const int side = (leaf >> (it.L - d - 1)) & 1;
     if (side != (src_c1 ? 0 : 1)) continue;
+    if ((cnt++ % kSpWaves) != wave) continue;
     const int r = ranks[node_index(it, d, leaf >> (it.L - d))];
-    if (s >= r) continue;
-    const double* Bd = lvl_ptr(const_cast<double*>(Bb), it, d) + lf.start + int64_t(s) * it.n;
-    double acc[kPNC];
+    const double* Bd = lvl_ptr(const_cast<double*>(Bb), it, d) + lf.start;
+    if (lane < m) {
+      double v[kRS];
 #pragma unroll
-    for (int c = 0; c < kPNC; ++c) acc[c] = 0.0;
-    for (int i = 0; i < m; ++i) {
-      const double bv = Bd[i];
+      for (int q = 0; q < kRS; ++q) v[q] = q < r ? Bd[lane + int64_t(q) * it.n] : 0.0;
 #pragma unroll
-      for (int c = 0; c < kPNC; ++c)
-        if (c < nc) acc[c] += bv * xl[i + c * 64];
+      for (int q = 0; q < kRS; ++q) Bl[lane + q * kSpLd] = v[q];
     }
-    double* po = part + (int64_t(blockIdx.x) * Lmax + d) * kRS * kPNC + s;
+    wave_lds_sync();
+    const int srow = lane & 31, cp = lane >> 5;
+    if (srow < r) {
+      double acc[kPNC / 2];
 #pragma unroll
-    for (int c = 0; c < kPNC; ++c)
-      if (c < nc) po[c * kRS] = acc[c];
+      for (int k = 0; k < kPNC / 2; ++k) acc[k] = 0.0;
+      for (int i = 0; i < m; ++i) {
+        const double bv = Bl[i + srow * kSpLd];
+#pragma unroll
+        for (int k = 0; k < kPNC / 2; ++k) acc[k] += bv * xl[i + (cp + 2 * k) * 64];
+      }
+      double* po = part + (int64_t(blockIdx.x) * Lmax + d) * kRS * kPNC + srow;
+#pragma unroll
+      for (int k = 0; k < kPNC / 2; ++k)
+        if (cp + 2 * k < nc) po[(cp + 2 * k) * kRS] = acc[k];
+    }
+    wave_lds_sync();
   }
 }
 
@@ -465,11 +456,19 @@ __global__ void __launch_bounds__(256) k_sp_reduce(DevPtrs P, const ProdJob* job
   }
 }
 
-// Y rows of the leaf = sign * (leaf op X + sum over destination levels B z)
-__global__ void __launch_bounds__(128) k_sp_expand(DevPtrs P, const ProdJob* jobs, const ProdUnit* units,
+// Y rows of the leaf = sign * (leaf op X + sum over destination levels B_d z_d).
+// All operands of the leaf op (X rows, the leaf's inverse factors, pivots)
+// are staged in one round trip; wave 0 applies the leaf op while waves 1..3
+// take the destination levels round-robin (a wave stages z_d in its LDS slice
+// and keeps its lane's row of B_d in registers); the four partial sums are
+// added in a fixed order.
+__global__ void __launch_bounds__(256) k_sp_expand(DevPtrs P, const ProdJob* jobs, const ProdUnit* units,
                                                    const double* z, int b) {
-  __shared__ double xl[64 * kPNC];
-  __shared__ double yl[64 * kPNC];
+  extern __shared__ double sm[];
+  double* xl = sm;                                   // 64 x kPNC
+  double* Fl = xl + 64 * kPNC;                       // 64 x 64, ld kSpLd
+  double* ww = Fl + 64 * kSpLd;                      // per level wave: B rows (64 x kRS, ld kSpLd), z_d
+  constexpr int kSlice = kSpLd * kRS + kRS * kPNC;   // then its partial sum (64 x kPNC) over the B rows
   __shared__ int pm[64], pmi[64];
   const ProdUnit u = units[blockIdx.x];
   const ProdJob jb = jobs[u.job];
@@ -479,92 +478,107 @@ __global__ void __launch_bounds__(128) k_sp_expand(DevPtrs P, const ProdJob* job
   const int m = lf.size, nc = prod_cols(P, it, jb);
   const double* X = lvl_ptr(arr_base(P, jb.xarr), it, jb.xlev) + lf.start;
   double* Y = lvl_ptr(arr_base(P, jb.yarr), it, jb.ylev) + lf.start;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int64_t gl = it.leaf0 + leaf;
   const double* Fi = P.LUinv + gl * int64_t(b) * b;
-  for (int e = t; e < m * nc; e += 128) {
-    const int i = e % m, c = e / m;
-    xl[i + c * 64] = X[i + int64_t(c) * it.n];
-  }
+  g2l_pad(X, it.n, xl, 64, m, nc, 64, kPNC);
+  g2l(Fi, b, Fl, kSpLd, m, m);
   if (t < m) {
     pm[t] = P.perm[gl * b + t];
     pmi[t] = P.perminv[gl * b + t];
   }
   __syncthreads();
-  const int row = t & 63, half = t >> 6;
+  const int row = lane;
   double acc[kPNC];
 #pragma unroll
   for (int c = 0; c < kPNC; ++c) acc[c] = 0.0;
-  if (row < m) {
-    if (half == 0) {
+  if (wave == 0) {
+    if (row < m) {
       if (jb.which == 0 && !jb.trans) {            // L^{-1} P^T x
 #pragma unroll
-        for (int c = 0; c < kPNC; ++c)
-          if (c < nc) acc[c] = xl[pm[row] + c * 64];
+        for (int c = 0; c < kPNC; ++c) acc[c] = xl[pm[row] + c * 64];
         for (int jj = 0; jj < row; ++jj) {
-          const double f = Fi[row + jj * b];
+          const double f = Fl[row + jj * kSpLd];
           const int pj = pm[jj];
 #pragma unroll
-          for (int c = 0; c < kPNC; ++c)
-            if (c < nc) acc[c] += f * xl[pj + c * 64];
+          for (int c = 0; c < kPNC; ++c) acc[c] += f * xl[pj + c * 64];
         }
       } else if (jb.which == 0) {                   // P L^{-T} x
         const int q = pmi[row];
 #pragma unroll
-        for (int c = 0; c < kPNC; ++c)
-          if (c < nc) acc[c] = xl[q + c * 64];
+        for (int c = 0; c < kPNC; ++c) acc[c] = xl[q + c * 64];
         for (int jj = q + 1; jj < m; ++jj) {
-          const double f = Fi[jj + q * b];
+          const double f = Fl[jj + q * kSpLd];
 #pragma unroll
-          for (int c = 0; c < kPNC; ++c)
-            if (c < nc) acc[c] += f * xl[jj + c * 64];
+          for (int c = 0; c < kPNC; ++c) acc[c] += f * xl[jj + c * 64];
         }
       } else if (!jb.trans) {                       // U^{-1} x
         for (int jj = row; jj < m; ++jj) {
-          const double f = Fi[row + jj * b];
+          const double f = Fl[row + jj * kSpLd];
 #pragma unroll
-          for (int c = 0; c < kPNC; ++c)
-            if (c < nc) acc[c] += f * xl[jj + c * 64];
+          for (int c = 0; c < kPNC; ++c) acc[c] += f * xl[jj + c * 64];
         }
       } else {                                      // U^{-T} x
         for (int jj = 0; jj <= row; ++jj) {
-          const double f = Fi[jj + row * b];
+          const double f = Fl[jj + row * kSpLd];
 #pragma unroll
-          for (int c = 0; c < kPNC; ++c)
-            if (c < nc) acc[c] += f * xl[jj + c * 64];
-        }
-      }
-    } else {
-      const bool src_c1 = (jb.which == 0) ? !jb.trans : jb.trans;
-      const double* Bb = jb.which == 0 ? P.IL : P.IU;
-      const int32_t* ranks = jb.which == 0 ? P.rankL : P.rankU;
-      for (int d = jb.d0; d < it.L; ++d) {
-        const int side = (leaf >> (it.L - d - 1)) & 1;
-        if (side != (src_c1 ? 1 : 0)) continue;
-        const int64_t jn = leaf >> (it.L - d);
-        const int r = ranks[node_index(it, d, jn)];
-        const int64_t slot = ((int64_t(1) << (d - jb.d0)) - 1) + (jn - (int64_t(jb.j0) << (d - jb.d0)));
-        const double* zn = z + (int64_t(jb.node0) + slot) * kRS * kPNC;
-        const double* Bd = lvl_ptr(const_cast<double*>(Bb), it, d) + lf.start + row;
-        for (int s = 0; s < r; ++s) {
-          const double bv = Bd[int64_t(s) * it.n];
-#pragma unroll
-          for (int c = 0; c < kPNC; ++c)
-            if (c < nc) acc[c] += bv * zn[s + c * kRS];
+          for (int c = 0; c < kPNC; ++c) acc[c] += f * xl[jj + c * 64];
         }
       }
     }
-  }
-  if (half == 1) {
+  } else {
+    const bool src_c1 = (jb.which == 0) ? !jb.trans : jb.trans;
+    const double* Bb = jb.which == 0 ? P.IL : P.IU;
+    const int32_t* ranks = jb.which == 0 ? P.rankL : P.rankU;
+    double* Bl = ww + (wave - 1) * kSlice;
+    double* zl = Bl + kSpLd * kRS;
+    int cnt = 0;
+    for (int d = jb.d0; d < it.L; ++d) {
+      const int side = (leaf >> (it.L - d - 1)) & 1;
+      if (side != (src_c1 ? 1 : 0)) continue;
+      if ((cnt++ % (kSpWaves - 1)) != wave - 1) continue;
+      const int64_t jn = leaf >> (it.L - d);
+      const int r = ranks[node_index(it, d, jn)];
+      const int64_t slot = ((int64_t(1) << (d - jb.d0)) - 1) + (jn - (int64_t(jb.j0) << (d - jb.d0)));
+      const double* zn = z + (int64_t(jb.node0) + slot) * kRS * kPNC;
+      const double* Bd = lvl_ptr(const_cast<double*>(Bb), it, d) + lf.start + row;
+      {
+        double bv[kRS];
 #pragma unroll
-    for (int c = 0; c < kPNC; ++c)
-      if (c < nc && row < m) yl[row + c * 64] = acc[c];
+        for (int q = 0; q < kRS; ++q) bv[q] = (q < r && row < m) ? Bd[int64_t(q) * it.n] : 0.0;
+        double zv[kRS * kPNC / 64];
+#pragma unroll
+        for (int k = 0; k < kRS * kPNC / 64; ++k) {
+          const int e = lane + 64 * k, q = e % kRS, c = e / kRS;
+          zv[k] = (q < r && c < nc) ? zn[q + c * kRS] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kRS; ++q) Bl[row + q * kSpLd] = bv[q];
+#pragma unroll
+        for (int k = 0; k < kRS * kPNC / 64; ++k) zl[lane + 64 * k] = zv[k];
+      }
+      wave_lds_sync();
+      for (int q = 0; q < r; ++q) {
+        const double bq = Bl[row + q * kSpLd];
+#pragma unroll
+        for (int c = 0; c < kPNC; ++c) acc[c] += bq * zl[q + c * kRS];
+      }
+      wave_lds_sync();
+    }
+    double* yo = Bl;                                 // 64 x kPNC partial over this wave's levels
+#pragma unroll
+    for (int c = 0; c < kPNC; ++c) yo[row + c * 64] = acc[c];
   }
   __syncthreads();
-  if (half == 0 && row < m) {
+  if (wave == 0 && row < m) {
 #pragma unroll
     for (int c = 0; c < kPNC; ++c)
-      if (c < nc) Y[row + int64_t(c) * it.n] = jb.sign * (acc[c] + yl[row + c * 64]);
+      if (c < nc) {
+        double v = acc[c];
+#pragma unroll
+        for (int w = 0; w < kSpWaves - 1; ++w) v += ww[w * kSlice + row + c * 64];
+        Y[row + int64_t(c) * it.n] = jb.sign * v;
+      }
   }
 }
 

@@ -26,6 +26,9 @@ __device__ inline double ld(const bf16* p) {
   uint32_t u = uint32_t(p->v) << 16;
   return double(__uint_as_float(u));
 }
+__device__ inline double cvt(double v) { return v; }
+__device__ inline double cvt(float v) { return double(v); }
+__device__ inline double cvt(bf16 v) { return double(__uint_as_float(uint32_t(v.v) << 16)); }
 
 
 // Partial projections of the leaf's rows v (LDS, m x nc, ld 64) onto the
@@ -207,6 +210,150 @@ __global__ void __launch_bounds__(256) k_expand(DevPtrs P, SolveFactors<TF, TL> 
   __syncthreads();
   if (next_part != nullptr)
     leaf_project<TF, NC>(P, it, w.leaf, lf, F.IU, P.rankU, 1, vl, nc, next_part, leaves);
+}
+
+// ------------------------------------------------ single right-hand side
+// The time-step solves carry one right-hand side.  There each lane owns one
+// row of the leaf, so every basis load is coalesced across the wave and all
+// ranks of a level are loaded at once; the row products are summed across
+// the leaf by a transpose through LDS (stride 65: conflict-free), with four
+// partial sums combined in a fixed order.  Levels are dealt round-robin to the
+// four waves of the work-group.
+constexpr int kP1Ld = 65;
+constexpr size_t kSolve1Lds = size_t(4) * kRS * kP1Ld * sizeof(double);
+
+template <typename TF>
+__device__ void leaf_project1(const DevPtrs& P, const Item& it, int leaf, const Node& lf, const TF* Bb,
+                              const int32_t* ranks, int src_side, double xv, double* part, int64_t leaves,
+                              double* sm) {
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int m = lf.size;
+  double* pw = sm + wave * (kRS * kP1Ld);
+  const int64_t gl = it.leaf0 + leaf;
+  int cnt = 0;
+  for (int d = 0; d < it.L; ++d) {
+    const int side = (leaf >> (it.L - d - 1)) & 1;
+    if (side != src_side) continue;
+    if ((cnt++ & 3) != wave) continue;
+    const int64_t nidx = node_index(it, d, leaf >> (it.L - d));
+    const int r = ranks[nidx];
+    // columns are loaded in groups of eight up to the rank with no use in
+    // between (all kRS columns are allocated; rows past the leaf read its last
+    // row), so the loads are issued together; the guard is applied after the
+    // conversion
+    const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + min(lane, m - 1);
+    TF raw[kRS] = {};
+#pragma unroll
+    for (int g8 = 0; g8 < kRS / 8; ++g8)      // groups of 8 columns up to the rank (uniform branch)
+      if (8 * g8 < r)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) raw[8 * g8 + k] = Bd[int64_t(8 * g8 + k) * it.n];
+#pragma unroll
+    for (int q = 0; q < kRS; ++q) pw[q * kP1Ld + lane] = (q < r && lane < m) ? cvt(raw[q]) * xv : 0.0;
+    wave_lds_sync();
+    const int q = lane & 31, h = lane >> 5;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 32; ++k) a4[k & 3] += pw[q * kP1Ld + h * 32 + k];
+    double v = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    v += __shfl_xor(v, 32);
+    if (h == 0 && q < r) part[(int64_t(d) * leaves + gl) * kRS + q] = v;
+    wave_lds_sync();
+  }
+}
+
+template <typename TF>
+__global__ void __launch_bounds__(256) k_project1(DevPtrs P, const WorkUnit* wu, int which, const TF* Bb,
+                                                  const double* x, double* part, int64_t leaves) {
+  extern __shared__ double sm[];
+  const WorkUnit w = wu[blockIdx.x];
+  const Item it = P.items[w.item];
+  const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
+  const int lane = threadIdx.x & 63;
+  const double xv = lane < lf.size ? x[it.row0 + lf.start + lane] : 0.0;
+  leaf_project1<TF>(P, it, w.leaf, lf, Bb, which == 0 ? P.rankL : P.rankU, which == 0 ? 0 : 1, xv, part, leaves,
+                    sm);
+}
+
+// y = F x on one leaf's rows (F = L^{-1} for which = 0, U^{-1} for which = 1):
+// wave 0 applies the leaf block (64 coalesced loads per lane, 16 in flight,
+// four partial sums), waves 1..3 the destination levels round-robin (basis
+// row loads of all ranks at once; z_node broadcast from lane s by readlane).
+// If next_part is set, the rows of y are projected for U^{-1} in the same
+// launch.
+template <typename TF, typename TL>
+__global__ void __launch_bounds__(256) k_expand1(DevPtrs P, SolveFactors<TF, TL> F, const WorkUnit* wu, int which,
+                                                 const double* xin, double* yout, const double* z,
+                                                 double* next_part, int64_t leaves, int b) {
+  extern __shared__ double sm[];
+  __shared__ double vl[64];
+  __shared__ double yl[4][64];
+  __shared__ int pm[64];
+  const WorkUnit w = wu[blockIdx.x];
+  const Item it = P.items[w.item];
+  const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, row = lane;
+  const int m = lf.size;
+  const int64_t gl = it.leaf0 + w.leaf;
+  if (t < 64) {
+    vl[t] = t < m ? xin[it.row0 + lf.start + t] : 0.0;
+    pm[t] = t < m ? P.perm[gl * b + t] : 0;
+  }
+  __syncthreads();
+  double acc = 0.0;
+  if (wave == 0) {
+    const TL* Fi = F.LUinv + gl * int64_t(b) * b + row;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    if (row < m) {
+      if (which == 0) a4[0] = vl[pm[row]];
+      for (int j0 = 0; j0 < m; j0 += 16) {      // columns j0..j0+15 < b are inside the leaf block
+        TL raw[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) raw[q] = Fi[(j0 + q) * b];
+        double f[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) f[q] = j0 + q < m ? cvt(raw[q]) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int j = j0 + q;
+          const bool use = which == 0 ? (j < row) : (j >= row && j < m);
+          const double xv = which == 0 ? vl[pm[min(j, m - 1)]] : vl[min(j, m - 1)];
+          a4[q & 3] += use ? f[q] * xv : 0.0;
+        }
+      }
+    }
+    acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  } else {
+    const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
+    const TF* Bb = which == 0 ? F.IL : F.IU;
+    const int dst_side = which == 0 ? 1 : 0;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    int cnt = 0;
+    for (int d = 0; d < it.L; ++d) {
+      const int side = (w.leaf >> (it.L - d - 1)) & 1;
+      if (side != dst_side) continue;
+      if ((cnt++ % 3) != wave - 1) continue;
+      const int64_t nidx = node_index(it, d, w.leaf >> (it.L - d));
+      const int r = ranks[nidx];
+      const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + min(row, m - 1);
+      const double zs = lane < r ? z[nidx * int64_t(kRS) + lane] : 0.0;
+      TF raw[kRS] = {};
+#pragma unroll
+      for (int g8 = 0; g8 < kRS / 8; ++g8)
+        if (8 * g8 < r)
+#pragma unroll
+          for (int k = 0; k < 8; ++k) raw[8 * g8 + k] = Bd[int64_t(8 * g8 + k) * it.n];
+#pragma unroll
+      for (int q = 0; q < kRS; ++q) a4[q & 3] += (q < r && row < m) ? cvt(raw[q]) * readlane_d(zs, q) : 0.0;
+    }
+    acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  }
+  yl[wave][row] = acc;
+  __syncthreads();
+  const double y = (yl[0][row] + yl[1][row]) + (yl[2][row] + yl[3][row]);
+  if (wave == 0 && row < m) yout[it.row0 + lf.start + row] = y;
+  if (next_part != nullptr)
+    leaf_project1<TF>(P, it, w.leaf, lf, F.IU, P.rankU, 1, row < m ? y : 0.0, next_part, leaves, sm);
 }
 
 // ---------------------------------------------------------------- helpers
