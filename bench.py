@@ -118,27 +118,21 @@ def main():
         t1 = time.perf_counter()
         A, u, info = last
         mi = A.info()
-        # live per-launch timing of the two dominant kernels' calls on the same stream
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        reps = 20
-        x = u.clone()
-        A2 = H.HodlrMatrix(ctx, ops, H.default_opts(tol=1e-10, prec=prec, refine_max=0))
-        e0.record(stream)
-        A2.factor(allow=(0, 3))
-        e1.record(stream)
-        for _ in range(reps):
-            A2.solve(x, allow=(0, 2))
-        e2.record(stream)
-        stream.synchronize()
-        t_factor = e0.elapsed_time(e1) / 1e3
-        t_solve = e1.elapsed_time(e2) / 1e3 / reps
-        mi2 = A2.info()
-        A2.close()
+        # live per-launch timing of every kernel of one more (untimed) job: each
+        # launch is bracketed by HIP events on the stream the kernels run on
+        ctx.reset_timing()
+        ctx.set_timing(True)
+        At, _, _ = job(prec, sweeps)
+        ctx.set_timing(False)
+        kstats = ctx.timing()
+        ctx.reset_timing()
+        mit = At.info()
+        At.close()
         res = dict(prec=prec, sweeps=sweeps, job_s=(t1 - t0) / args.steps,
                    build_ms=float(np.mean([p[0] for p in parts])), factor_ms=float(np.mean([p[1] for p in parts])),
                    steps_ms=float(np.mean([p[2] for p in parts])), rel_correction=info.rel_correction,
                    rel_residual=info.rel_residual, rank_A=mi.max_rank_A, rank_factors=mi.max_rank_factors,
-                   solve_bytes=mi2.bytes_factors, factor_flops=mi2.factor_flops, t_factor=t_factor, t_solve=t_solve)
+                   kstats=kstats, info=mit)
         A.close()
         return res
 
@@ -150,23 +144,7 @@ def main():
 
     problem_steps = len(probs) * K
     value = problem_steps / main_res["job_s"]
-    # dominant kernel of the job: the factorisation (one launch of k_factor per job)
-    # or the per-step solve kernels, whichever takes more of the job
-    fact_share = main_res["factor_ms"] / (1e3 * main_res["job_s"])
-    if fact_share >= 0.5:
-        achieved = main_res["factor_flops"] / main_res["t_factor"]
-        roof = {"kernel": "k_factor", "bound": "alu", "achieved": achieved / 1e12, "peak": MI355X_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / MI355X_FP64, "traffic": None,
-                "algorithmic": f"{main_res['factor_flops']:.3e} flop per launch (flop model of the HODLR LU)",
-                "launch_ms": 1e3 * main_res["t_factor"]}
-    else:
-        vec_bytes = 8.0 * sum(p.n for p in probs) * 6
-        byts = main_res["solve_bytes"] + vec_bytes
-        achieved = byts / main_res["t_solve"]
-        roof = {"kernel": "hodlr_solve (project/reduce/expand)", "bound": "hbm", "achieved": achieved / 1e9,
-                "peak": MI355X_HBM / 1e9, "unit": "GB/s", "frac": achieved / MI355X_HBM, "traffic": None,
-                "algorithmic": f"{byts:.3e} bytes per solve (factors at their ranks + 6 vector passes)",
-                "launch_ms": 1e3 * main_res["t_solve"]}
+    roof = roofline(main_res, sum(p.n for p in probs), args.prec)
 
     cpu = None
     if not args.no_cpu:
@@ -199,11 +177,54 @@ def main():
     }
     if cmp_res is not None:
         out["fp64_path"] = {"value": problem_steps / cmp_res["job_s"], "per_step_us": 1e3 * cmp_res["steps_ms"] / K,
-                            "factor_ms": cmp_res["factor_ms"], "sweeps": cmp_res["sweeps"],
-                            "solve_us": 1e6 * cmp_res["t_solve"]}
+                            "factor_ms": cmp_res["factor_ms"], "sweeps": cmp_res["sweeps"]}
         out["mixed_vs_fp64"] = {"whole_job": out["fp64_path"]["value"] and value / out["fp64_path"]["value"],
                                 "per_step": cmp_res["steps_ms"] / main_res["steps_ms"]}
     print(json.dumps(out), flush=True)
+
+
+def roofline(res, total_n, prec):
+    """Roofline of the kernel with the largest summed duration in the
+    instrumented job.  Algorithmic work per launch:
+      factorisation kernels (FP64 ALU): the flop model of the factorisation,
+        split by kernel (recompression cores, Gram matrices, leaves), over the
+        kernel's launches;
+      single right-hand-side solve kernels (HBM): every factor value is read
+        once per solve; the projection reads a quarter of the off-diagonal
+        factors, the two expansions the rest and the leaf inverses, plus the
+        vector passes (8 bytes a row in and out)."""
+    ks, mi = res["kstats"], res["info"]
+    name, (launches, total_ms) = max(ks.items(), key=lambda kv: kv[1][1])
+    avg_s = total_ms / launches / 1e3
+    vsize = {"fp64": 8, "fp32": 4, "bf16": 4}[prec]
+    leaf_bytes = 64 * total_n * vsize
+    off_bytes = max(mi.bytes_factors - leaf_bytes, 0)
+    solves = ks.get("(k_project1<TF>)", (0, 0))[0]
+    flop_kernels = {"k_core": mi.core_flops, "k_gram_partial": mi.gram_flops, "k_leaf_task": mi.leaf_flops}
+    out = {"kernel": name, "launches": launches, "launch_us": 1e6 * avg_s}
+    if name in flop_kernels:
+        factorisations = 1
+        per_launch = flop_kernels[name] / max(launches / factorisations, 1)
+        achieved = per_launch / avg_s
+        out.update(bound="alu", achieved=achieved / 1e12, peak=MI355X_FP64 / 1e12, unit="TFLOP/s",
+                   frac=achieved / MI355X_FP64, traffic=None,
+                   algorithmic=f"{per_launch:.3e} flop per launch (flop model of this kernel's share of the "
+                               f"HODLR LU at the final ranks, {flop_kernels[name]:.3e} flop over {launches} launches)")
+    elif name in ("(k_expand1<TF, TL>)", "(k_project1<TF>)") and solves:
+        if name == "(k_project1<TF>)":
+            per_launch = off_bytes / 4 + 8.0 * total_n
+        else:
+            per_launch = (0.75 * off_bytes + leaf_bytes) / 2 + 16.0 * total_n
+        achieved = per_launch / avg_s
+        out.update(bound="hbm", achieved=achieved / 1e9, peak=MI355X_HBM / 1e9, unit="GB/s",
+                   frac=achieved / MI355X_HBM, traffic=None,
+                   algorithmic=f"{per_launch:.3e} bytes per launch (factor values read once per solve at "
+                               f"{vsize}-byte storage, {mi.bytes_factors:.3e} bytes a solve, plus vectors)")
+    else:
+        out.update(bound="latency", achieved=None, peak=None, unit=None, frac=None, traffic=None,
+                   algorithmic="no algorithmic model for this kernel")
+    out["top_kernels_ms"] = {k: round(v[1], 3) for k, v in sorted(ks.items(), key=lambda kv: -kv[1][1])[:8]}
+    return out
 
 
 def cpu_baseline(args, probs):

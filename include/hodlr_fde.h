@@ -100,12 +100,31 @@ typedef struct {
   size_t bytes_factors;   /* bytes read by one single-RHS solve at the chosen precision */
   size_t bytes_device;    /* device memory held by the handle */
   double factor_flops;    /* algorithmic FP64 flops of hodlr_factor (model from the final ranks) */
+  double core_flops;      /* part of factor_flops in the small recompression cores (k x k Gram work) */
+  double gram_flops;      /* part of factor_flops in forming Gram matrices of tall factors */
+  double leaf_flops;      /* part of factor_flops in the dense leaves (update, LU, inverses) */
 } hodlr_mat_info;
 
 /* ---- context ------------------------------------------------------------ */
 hodlr_status hodlr_ctx_create(hodlr_ctx* ctx, void* hip_stream);
 void hodlr_ctx_destroy(hodlr_ctx ctx);
 int hodlr_last_arg(hodlr_ctx ctx);
+
+/* Per-kernel timing, for measurement runs (the caller that needs kernel
+ * durations, e.g. a roofline report or an autotuner).  With timing on, every
+ * kernel the library launches for calls made through ctx is bracketed by two
+ * HIP events on ctx's stream, and each entry point waits for its kernels
+ * before returning; captured time-step graphs are replaced by direct launches.
+ * Launch counts and summed durations accumulate per kernel (named by its
+ * launch expression) until hodlr_ctx_timing_reset.  Timing perturbs the
+ * timings of the calls it brackets only by the event records between launches.
+ * hodlr_ctx_timing_entry: i in [0, hodlr_ctx_timing_count); name points into
+ * ctx and stays valid until the next reset or ctx destruction. */
+hodlr_status hodlr_ctx_set_timing(hodlr_ctx ctx, int enable);
+int hodlr_ctx_timing_count(hodlr_ctx ctx);
+hodlr_status hodlr_ctx_timing_entry(hodlr_ctx ctx, int i, const char** name, int64_t* launches,
+                                    double* total_ms);
+void hodlr_ctx_timing_reset(hodlr_ctx ctx);
 const char* hodlr_status_string(hodlr_status s);
 hodlr_status hodlr_default_opts(hodlr_opts* opts);
 

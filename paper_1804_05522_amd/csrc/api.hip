@@ -9,6 +9,7 @@
 #include <new>
 #include <array>
 #include <cstdlib>
+#include <string>
 #include <vector>
 #include <functional>
 
@@ -16,9 +17,102 @@
 
 using namespace hfde;
 
+// Per-kernel timing for measurement runs: when a context has timing on,
+// every kernel launched through it is bracketed by two HIP events on the
+// context's stream, and counts and durations accumulate per kernel until
+// read or reset.  The events are resolved when the entry point returns.
+struct KTimer {
+  hipStream_t stream = nullptr;
+  struct Pend {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pend> pend;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::string> names;
+  std::vector<int64_t> counts;
+  std::vector<double> ms;
+  hipEvent_t ev() {
+    if (pool.empty()) {
+      hipEvent_t e = nullptr;
+      (void)hipEventCreate(&e);
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  int kind(const char* n) {
+    for (size_t i = 0; i < names.size(); ++i)
+      if (names[i] == n) return int(i);
+    names.emplace_back(n);
+    counts.push_back(0);
+    ms.push_back(0.0);
+    return int(names.size()) - 1;
+  }
+  void flush() {
+    if (pend.empty()) return;
+    (void)hipEventSynchronize(pend.back().b);
+    for (const Pend& q : pend) {
+      float t = 0.0f;
+      (void)hipEventElapsedTime(&t, q.a, q.b);
+      counts[q.kind] += 1;
+      ms[q.kind] += t;
+      pool.push_back(q.a);
+      pool.push_back(q.b);
+    }
+    pend.clear();
+  }
+  void reset() {
+    flush();
+    names.clear();
+    counts.clear();
+    ms.clear();
+  }
+  ~KTimer() {
+    flush();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct hodlr_ctx_s {
-  hipStream_t stream;
-  int last_arg;
+  hipStream_t stream = nullptr;
+  int last_arg = 0;
+  bool timing = false;
+  KTimer timer;
+};
+
+static thread_local KTimer* g_timer = nullptr;
+
+// Launch, bracketed by timing events when the calling entry point's context
+// has timing on.  Kernel names are the launch expressions.
+#define HFDE_LAUNCH(K, ...)                                   \
+  do {                                                        \
+    KTimer* t_ = g_timer;                                     \
+    hipEvent_t a_ = nullptr, b_ = nullptr;                    \
+    if (t_) {                                                 \
+      a_ = t_->ev();                                          \
+      b_ = t_->ev();                                          \
+      (void)hipEventRecord(a_, t_->stream);                   \
+    }                                                         \
+    hipLaunchKernelGGL(K, __VA_ARGS__);                       \
+    if (t_) {                                                 \
+      (void)hipEventRecord(b_, t_->stream);                   \
+      t_->pend.push_back(KTimer::Pend{t_->kind(#K), a_, b_}); \
+    }                                                         \
+  } while (0)
+
+// Makes the context's timer current for the duration of an entry point.
+struct TimerScope {
+  KTimer* prev;
+  explicit TimerScope(hodlr_ctx c) : prev(g_timer) {
+    g_timer = (c && c->timing) ? &c->timer : nullptr;
+    if (g_timer) g_timer->stream = c->stream;
+  }
+  ~TimerScope() {
+    if (g_timer) g_timer->flush();
+    g_timer = prev;
+  }
 };
 
 namespace {
@@ -218,22 +312,22 @@ void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int
       int maxlog = 0;
       for (int i : m->small_items) maxlog = std::max(maxlog, m->items[i].fftlog);
       lds = (size_t(1) << maxlog) * sizeof(double2);
-      hipLaunchKernelGGL(k_fft_small, dim3(cnt), dim3(512), lds, s, m->P, m->fft_small_units, 1, xc, ldx, yc,
+      HFDE_LAUNCH(k_fft_small, dim3(cnt), dim3(512), lds, s, m->P, m->fft_small_units, 1, xc, ldx, yc,
                          ldy, bc, ldb);
     }
     if (m->n_fft_p1) {
       const int per_col1 = m->n_fft_p1 / kNCF, per_col2 = m->n_fft_p2 / kNCF;
       const size_t lds = m->fft4_lds;
-      hipLaunchKernelGGL(k_fft4_pass1, dim3(per_col1 * cn), dim3(512), lds, s, m->P, m->fft_p1_units, 1, false,
+      HFDE_LAUNCH(k_fft4_pass1, dim3(per_col1 * cn), dim3(512), lds, s, m->P, m->fft_p1_units, 1, false,
                          xc, ldx);
-      hipLaunchKernelGGL(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, false,
+      HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, false,
                          xc, ldx, yc, ldy, bc, ldb);
-      hipLaunchKernelGGL(k_fft4_pass1, dim3(per_col1 * cn), dim3(512), lds, s, m->P, m->fft_p1_units, 1, true,
+      HFDE_LAUNCH(k_fft4_pass1, dim3(per_col1 * cn), dim3(512), lds, s, m->P, m->fft_p1_units, 1, true,
                          xc, ldx);
-      hipLaunchKernelGGL(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, true,
+      HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, true,
                          xc, ldx, yc, ldy, bc, ldb);
       const int per_colr = m->n_fft_rows / kNCF;
-      hipLaunchKernelGGL(k_exact_rows, dim3(per_colr * cn), dim3(256), 0, s, m->P, m->fft_row_units, xc, ldx, yc, ldy,
+      HFDE_LAUNCH(k_exact_rows, dim3(per_colr * cn), dim3(256), 0, s, m->P, m->fft_row_units, xc, ldx, yc, ldy,
                          bc, ldb);
     }
   }
@@ -245,23 +339,23 @@ void launch_solve_t(hodlr_mat m, SolveFactors<TF, TL> F, const WorkUnit* wu, int
   const TF* IL = F.IL;
   const int64_t lv = m->total_leaves;
   if (NC == 1) {                        // one right-hand side: row-per-lane kernels
-    hipLaunchKernelGGL((k_project1<TF>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, wu, 0, IL, x, m->partL, lv);
-    if (nnu) hipLaunchKernelGGL(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 0, 1, m->partL, m->zL, lv);
-    hipLaunchKernelGGL((k_expand1<TF, TL>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, F, wu, 0, x, m->ytmp, m->zL,
+    HFDE_LAUNCH((k_project1<TF>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, wu, 0, IL, x, m->partL, lv);
+    if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 0, 1, m->partL, m->zL, lv);
+    HFDE_LAUNCH((k_expand1<TF, TL>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, F, wu, 0, x, m->ytmp, m->zL,
                        m->partU, lv, m->b);
-    if (nnu) hipLaunchKernelGGL(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 1, 1, m->partU, m->zU, lv);
-    hipLaunchKernelGGL((k_expand1<TF, TL>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, F, wu, 1, m->ytmp, y, m->zU,
+    if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 1, 1, m->partU, m->zU, lv);
+    HFDE_LAUNCH((k_expand1<TF, TL>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, F, wu, 1, m->ytmp, y, m->zU,
                        (double*)nullptr, lv, m->b);
     (void)ldx;
     (void)ldy;
     return;
   }
-  hipLaunchKernelGGL((k_project<TF, NC>), dim3(nwu), dim3(256), 0, s, m->P, wu, 0, IL, x, ldx, nc, m->partL, lv);
-  if (nnu) hipLaunchKernelGGL(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 0, nc, m->partL, m->zL, lv);
-  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 0, x, ldx, m->ytmp,
+  HFDE_LAUNCH((k_project<TF, NC>), dim3(nwu), dim3(256), 0, s, m->P, wu, 0, IL, x, ldx, nc, m->partL, lv);
+  if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 0, nc, m->partL, m->zL, lv);
+  HFDE_LAUNCH((k_expand<TF, TL, NC>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 0, x, ldx, m->ytmp,
                      m->total_n, nc, m->zL, m->partU, lv, m->b);
-  if (nnu) hipLaunchKernelGGL(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 1, nc, m->partU, m->zU, lv);
-  hipLaunchKernelGGL((k_expand<TF, TL, NC>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 1, m->ytmp, m->total_n, y,
+  if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 1, nc, m->partU, m->zU, lv);
+  HFDE_LAUNCH((k_expand<TF, TL, NC>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 1, m->ytmp, m->total_n, y,
                      ldy, nc, m->zU, (double*)nullptr, lv, m->b);
 }
 
@@ -296,14 +390,14 @@ void launch_solve(hodlr_mat m, int prec, const double* x, int64_t ldx, double* y
 }
 
 void launch_norms(hodlr_mat m, const double* v, int64_t ld, int nc, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_item_norms, dim3(m->batch, nc), dim3(256), 0, s, m->P, v, ld, nc, out);
+  HFDE_LAUNCH(k_item_norms, dim3(m->batch, nc), dim3(256), 0, s, m->P, v, ld, nc, out);
 }
 
 void launch_axpby(int64_t nrows, int nc, double a, const double* x, int64_t ldx, double bco, const double* y,
                   int64_t ldy, double* z, int64_t ldz, hipStream_t s) {
   const int64_t tot = nrows * nc;
   const int blocks = int(std::min<int64_t>((tot + 255) / 256, 65535));
-  hipLaunchKernelGGL(k_axpby, dim3(blocks), dim3(256), 0, s, nrows, nc, a, x, ldx, bco, y, ldy, z, ldz);
+  HFDE_LAUNCH(k_axpby, dim3(blocks), dim3(256), 0, s, nrows, nc, a, x, ldx, bco, y, ldy, z, ldz);
 }
 
 }  // namespace
@@ -513,30 +607,30 @@ static void enqueue_mwg(hodlr_mat m, hipStream_t s) {
     const int64_t off = m->mwg_off[q], off2 = m->mwg_off2[q];
     switch (m->mwg_kind[q]) {
       case KL_LEAF:
-        hipLaunchKernelGGL(k_leaf_task, dim3(g), dim3(leaf_threads), kFactorLdsBytes, s, P, m->d_tasks + off, m->b);
+        HFDE_LAUNCH(k_leaf_task, dim3(g), dim3(leaf_threads), kFactorLdsBytes, s, P, m->d_tasks + off, m->b);
         break;
       case KL_GRAM:
-        hipLaunchKernelGGL(k_gram_partial, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_gram + off, m->d_gpart);
+        HFDE_LAUNCH(k_gram_partial, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_gram + off, m->d_gpart);
         break;
       case KL_REDUCE:
-        hipLaunchKernelGGL(k_gram_reduce, dim3(g), dim3(256), 0, s, m->d_red + off, m->d_gpart, m->d_G);
+        HFDE_LAUNCH(k_gram_reduce, dim3(g), dim3(256), 0, s, m->d_red + off, m->d_gpart, m->d_G);
         break;
       case KL_CORE:
-        hipLaunchKernelGGL(k_core, dim3(g), dim3(core_threads), kFactorLdsBytes, s, P, m->d_tasks + off2, m->d_core + off, m->d_G,
+        HFDE_LAUNCH(k_core, dim3(g), dim3(core_threads), kFactorLdsBytes, s, P, m->d_tasks + off2, m->d_core + off, m->d_G,
                            m->d_M, m->opts.max_rank);
         break;
       case KL_FORM:
-        hipLaunchKernelGGL(k_form, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_form + off, m->d_G, m->d_M);
+        HFDE_LAUNCH(k_form, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_form + off, m->d_G, m->d_M);
         break;
       case KL_SPP:
-        hipLaunchKernelGGL(k_sp_project, dim3(g), dim3(256), kSpProjLds, s, P, m->d_jobs + off2, m->d_punits + off, m->d_ppart, Lmax);
+        HFDE_LAUNCH(k_sp_project, dim3(g), dim3(256), kSpProjLds, s, P, m->d_jobs + off2, m->d_punits + off, m->d_ppart, Lmax);
         break;
       case KL_SPR:
-        hipLaunchKernelGGL(k_sp_reduce, dim3(g), dim3(256), 0, s, P, m->d_jobs + off2, m->d_punits + off, m->d_ppart,
+        HFDE_LAUNCH(k_sp_reduce, dim3(g), dim3(256), 0, s, P, m->d_jobs + off2, m->d_punits + off, m->d_ppart,
                            m->d_pz, Lmax);
         break;
       default:
-        hipLaunchKernelGGL(k_sp_expand, dim3(g), dim3(256), kSpExpLds, s, P, m->d_jobs + off2, m->d_punits + off, m->d_pz, m->b);
+        HFDE_LAUNCH(k_sp_expand, dim3(g), dim3(256), kSpExpLds, s, P, m->d_jobs + off2, m->d_punits + off, m->d_pz, m->b);
         break;
     }
   }
@@ -564,7 +658,6 @@ hodlr_status hodlr_ctx_create(hodlr_ctx* ctx, void* hip_stream) {
   hodlr_ctx c = new (std::nothrow) hodlr_ctx_s;
   if (!c) return HODLR_ENOMEM;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  c->last_arg = 0;
   *ctx = c;
   return HODLR_OK;
 }
@@ -572,6 +665,28 @@ hodlr_status hodlr_ctx_create(hodlr_ctx* ctx, void* hip_stream) {
 void hodlr_ctx_destroy(hodlr_ctx ctx) { delete ctx; }
 
 int hodlr_last_arg(hodlr_ctx ctx) { return ctx ? ctx->last_arg : 0; }
+
+hodlr_status hodlr_ctx_set_timing(hodlr_ctx ctx, int enable) {
+  if (!ctx) return HODLR_EINVAL;
+  ctx->timer.flush();
+  ctx->timing = enable != 0;
+  return HODLR_OK;
+}
+
+int hodlr_ctx_timing_count(hodlr_ctx ctx) { return ctx ? int(ctx->timer.names.size()) : 0; }
+
+hodlr_status hodlr_ctx_timing_entry(hodlr_ctx ctx, int i, const char** name, int64_t* launches, double* total_ms) {
+  if (!ctx) return HODLR_EINVAL;
+  if (i < 0 || i >= int(ctx->timer.names.size())) return set_arg(ctx, 2);
+  if (name) *name = ctx->timer.names[i].c_str();
+  if (launches) *launches = ctx->timer.counts[i];
+  if (total_ms) *total_ms = ctx->timer.ms[i];
+  return HODLR_OK;
+}
+
+void hodlr_ctx_timing_reset(hodlr_ctx ctx) {
+  if (ctx) ctx->timer.reset();
+}
 
 hodlr_status hodlr_default_opts(hodlr_opts* o) {
   if (!o) return HODLR_EINVAL;
@@ -627,6 +742,7 @@ static hodlr_status set_lds_limits() {
 hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, const hodlr_opts* opts,
                          hodlr_mat* out) {
   if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
   TRY(set_lds_limits());
   if (!ops) return set_arg(ctx, 2);
   if (batch < 1) return set_arg(ctx, 3);
@@ -804,29 +920,29 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
     HIP_TRY(hipMemcpyAsync(P.dminus + it.row0, ops[i].d_minus, it.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   // ---- device construction
-  hipLaunchKernelGGL(k_gl_weights, dim3(batch), dim3(1024), 0, s, P);
-  hipLaunchKernelGGL(k_hankel_aca, dim3(batch), dim3(512), 0, s, P, opts->tol);
+  HFDE_LAUNCH(k_gl_weights, dim3(batch), dim3(1024), 0, s, P);
+  HFDE_LAUNCH(k_hankel_aca, dim3(batch), dim3(512), 0, s, P, opts->tol);
   for (int i = 0; i < batch; ++i) {
     const Item& it = m->items[i];
     if (it.L > 0)
-      hipLaunchKernelGGL(k_assemble_bases, dim3(unsigned((it.n + 255) / 256), it.L), dim3(256), 0, s, P, i);
-    hipLaunchKernelGGL(k_assemble_leaves, dim3(unsigned(int64_t(1) << it.L)), dim3(256), 0, s, P, i, b);
-    hipLaunchKernelGGL(k_twiddles, dim3(unsigned(std::min<int64_t>(((int64_t(1) << it.fftlog) + 255) / 256, 4096))),
+      HFDE_LAUNCH(k_assemble_bases, dim3(unsigned((it.n + 255) / 256), it.L), dim3(256), 0, s, P, i);
+    HFDE_LAUNCH(k_assemble_leaves, dim3(unsigned(int64_t(1) << it.L)), dim3(256), 0, s, P, i, b);
+    HFDE_LAUNCH(k_twiddles, dim3(unsigned(std::min<int64_t>(((int64_t(1) << it.fftlog) + 255) / 256, 4096))),
                        dim3(256), 0, s, P, i);
   }
   // far-field multipliers mu = FFT(c_far) -> lambda + i conj(lambda)
   if (m->n_fft_small) {
     int maxlog = 0;
     for (int i : m->small_items) maxlog = std::max(maxlog, m->items[i].fftlog);
-    hipLaunchKernelGGL(k_fft_small, dim3(m->n_fft_small), dim3(512), (size_t(1) << maxlog) * sizeof(double2), s,
+    HFDE_LAUNCH(k_fft_small, dim3(m->n_fft_small), dim3(512), (size_t(1) << maxlog) * sizeof(double2), s,
                        P, m->fft_small_units, 0, (const double*)nullptr, 0, (double*)nullptr, 0,
                        (const double*)nullptr, 0);
   }
   if (m->n_fft_p1) {
     const size_t lds = m->fft4_lds;
-    hipLaunchKernelGGL(k_fft4_pass1, dim3(m->n_fft_p1 / kNCF), dim3(512), lds, s, P, m->fft_p1_units, 0, false,
+    HFDE_LAUNCH(k_fft4_pass1, dim3(m->n_fft_p1 / kNCF), dim3(512), lds, s, P, m->fft_p1_units, 0, false,
                        (const double*)nullptr, 0);
-    hipLaunchKernelGGL(k_fft4_pass2, dim3(m->n_fft_p2 / kNCF), dim3(512), lds, s, P, m->fft_p2_units, 0, false,
+    HFDE_LAUNCH(k_fft4_pass2, dim3(m->n_fft_p2 / kNCF), dim3(512), lds, s, P, m->fft_p2_units, 0, false,
                        (const double*)nullptr, 0, (double*)nullptr, 0, (const double*)nullptr, 0);
   }
   HIP_TRY(hipGetLastError());
@@ -845,7 +961,20 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
 // of a child subtree on r columns each: 2 r (n b + 2 n sum of child ranks)),
 // C and W (2 n1 r^2, 2 n2 r^2); per leaf the Schur update 2 m^2 rp, the LU
 // (2/3) m^3 and the two triangular inverses (2/3) m^3.
-static double factor_flop_model(hodlr_mat m) {
+struct FlopSplit {
+  double total = 0.0;   // whole factorisation
+  double core = 0.0;    // recompression cores (k_core): per recompression of R columns to rank r,
+                        // two pivoted Cholesky ~2 R^3, K ~2 R^3, QRCP ~4 R^2 r, Q 4 R r^2, M_U, M_V ~R r^2 + 2 R^2 r
+  double gram = 0.0;    // Gram matrices (k_gram_partial): 2 rows x cols x cols each
+  double leaf = 0.0;    // leaves (k_leaf_task): pending update, LU, both inverses
+};
+
+static FlopSplit factor_flop_split(hodlr_mat m);
+
+static double factor_flop_model(hodlr_mat m) { return factor_flop_split(m).total; }
+
+static FlopSplit factor_flop_split(hodlr_mat m) {
+  FlopSplit out;
   std::vector<int32_t> rl(m->total_nodes), ru(m->total_nodes), rp(m->total_nodes);
   (void)hipMemcpy(rl.data(), m->P.rankL, rl.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
   (void)hipMemcpy(ru.data(), m->P.rankU, ru.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
@@ -870,10 +999,14 @@ static double factor_flop_model(hodlr_mat m) {
         const double n = nd.size, pr = rp[ni];
         if (d == it.L) {
           fl += 2.0 * n * n * pr + (4.0 / 3.0) * n * n * n;
+          out.leaf += 2.0 * n * n * pr + (4.0 / 3.0) * n * n * n;
           continue;
         }
         const double n1 = double(nd.size / 2), n2 = n - n1;
         const double r = it.r, R = r + pr, r12 = ru[ni], r21 = rl[ni];
+        auto core = [](double Rc, double rc) { return 4.0 * Rc * Rc * Rc + 6.0 * Rc * Rc * rc + 5.0 * Rc * rc * rc; };
+        out.core += core(R, r12) + core(R, r21) + core(pr + r12, rp[node_index(it, d + 1, 2 * j + 1)]);
+        out.gram += 4.0 * n * R * R + 2.0 * n1 * r21 * r12 + 4.0 * n2 * (pr + r12) * (pr + r12);
         fl += 2 * (2.0 * n * R * R) + 2.0 * n * R * (r12 + r21);              // S12, S21 recompression
         fl += 2.0 * n2 * (pr + r12) * (pr + r12) * 2 + 2.0 * n2 * (pr + r12) * r12;  // pending recompression
         fl += 2.0 * n1 * r12 * r21 + 2.0 * n2 * r21 * r12;                      // C and W
@@ -882,7 +1015,8 @@ static double factor_flop_model(hodlr_mat m) {
         fl += 2.0 * r21 * (s1 + s2) + 2.0 * r12 * (s1 + s2);                    // inverse blocks
       }
   }
-  return fl;
+  out.total = fl;
+  return out;
 }
 
 hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info) {
@@ -916,12 +1050,17 @@ hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info) {
   }
   info->bytes_factors = bytes;
   info->bytes_device = m->bytes_device;
-  info->factor_flops = m->factored ? factor_flop_model(m) : 0.0;
+  const FlopSplit fs = m->factored ? factor_flop_split(m) : FlopSplit{};
+  info->factor_flops = fs.total;
+  info->core_flops = fs.core;
+  info->gram_flops = fs.gram;
+  info->leaf_flops = fs.leaf;
   return HODLR_OK;
 }
 
 hodlr_status hodlr_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y, int nrhs, int64_t ld) {
   if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
   if (!m) return set_arg(ctx, 2);
   if (!x) return set_arg(ctx, 3);
   if (!y) return set_arg(ctx, 4);
@@ -932,12 +1071,12 @@ hodlr_status hodlr_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y
     const int cn = std::min(kNCS, nrhs - c0);
     const double* xc = x + int64_t(c0) * ld;
     double* yc = y + int64_t(c0) * ld;
-    hipLaunchKernelGGL(k_hmatvec_A_project, dim3(m->nwu), dim3(64), 0, s, m->P, m->wu, xc, ld, cn, m->partL,
+    HFDE_LAUNCH(k_hmatvec_A_project, dim3(m->nwu), dim3(64), 0, s, m->P, m->wu, xc, ld, cn, m->partL,
                        m->Lmax);
     if (m->nnu)
-      hipLaunchKernelGGL(k_hmatvec_A_reduce, dim3(m->nnu), dim3(64), 0, s, m->P, m->nu, cn, m->partL, m->zL,
+      HFDE_LAUNCH(k_hmatvec_A_reduce, dim3(m->nnu), dim3(64), 0, s, m->P, m->nu, cn, m->partL, m->zL,
                          m->Lmax);
-    hipLaunchKernelGGL(k_hmatvec_A_expand, dim3(m->nwu), dim3(64), 0, s, m->P, m->wu, xc, ld, yc, ld, cn, m->zL,
+    HFDE_LAUNCH(k_hmatvec_A_expand, dim3(m->nwu), dim3(64), 0, s, m->P, m->wu, xc, ld, yc, ld, cn, m->zL,
                        m->b);
   }
   HIP_TRY(hipGetLastError());
@@ -946,6 +1085,7 @@ hodlr_status hodlr_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y
 
 hodlr_status hodlr_toeplitz_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y, int nrhs, int64_t ld) {
   if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
   if (!m) return set_arg(ctx, 2);
   if (!x) return set_arg(ctx, 3);
   if (!y) return set_arg(ctx, 4);
@@ -959,13 +1099,14 @@ hodlr_status hodlr_toeplitz_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, 
 
 hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
   if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
   if (!m) return set_arg(ctx, 2);
   hipStream_t s = ctx->stream;
   const size_t lds = kFactorLdsBytes;
   const char* env = getenv("HODLR_FACTOR_PATH");
   const bool single = (env && env[0] == 's');
   if (single) {
-    hipLaunchKernelGGL(k_factor, dim3(m->batch), dim3(kWG), lds, s, m->P, m->b, m->opts.max_rank);
+    HFDE_LAUNCH(k_factor, dim3(m->batch), dim3(kWG), lds, s, m->P, m->b, m->opts.max_rank);
   } else {
     TRY(plan_mwg(m));
     enqueue_mwg(m, s);
@@ -1001,12 +1142,12 @@ hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
         TRY(dalloc(m, &m->IU16, nlvl));
       }
     }
-    hipLaunchKernelGGL(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.LUinv, m->LUinv32, nleafv);
-    hipLaunchKernelGGL(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.IL, m->IL32, nlvl);
-    hipLaunchKernelGGL(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.IU, m->IU32, nlvl);
+    HFDE_LAUNCH(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.LUinv, m->LUinv32, nleafv);
+    HFDE_LAUNCH(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.IL, m->IL32, nlvl);
+    HFDE_LAUNCH(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.IU, m->IU32, nlvl);
     if (m->opts.prec == HODLR_MIXED_BF16) {
-      hipLaunchKernelGGL(k_convert<bf16>, dim3(4096), dim3(256), 0, s, m->P.IL, m->IL16, nlvl);
-      hipLaunchKernelGGL(k_convert<bf16>, dim3(4096), dim3(256), 0, s, m->P.IU, m->IU16, nlvl);
+      HFDE_LAUNCH(k_convert<bf16>, dim3(4096), dim3(256), 0, s, m->P.IL, m->IL16, nlvl);
+      HFDE_LAUNCH(k_convert<bf16>, dim3(4096), dim3(256), 0, s, m->P.IU, m->IU16, nlvl);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
@@ -1023,6 +1164,7 @@ hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
 
 hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_t ld, hodlr_info* info) {
   if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
   if (!m) return set_arg(ctx, 2);
   if (!x) return set_arg(ctx, 3);
   if (nrhs < 1) return set_arg(ctx, 4);
@@ -1121,6 +1263,7 @@ static void record_step(hodlr_mat m, double* u, const double* f, double fscale, 
 hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const double* f, double fscale, int steps,
                               hodlr_info* info) {
   if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
   if (!m) return set_arg(ctx, 2);
   if (!u) return set_arg(ctx, 3);
   if (steps < 0) return set_arg(ctx, 5);
@@ -1128,8 +1271,9 @@ hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const doubl
   hipStream_t s = ctx->stream;
   const int64_t tn = m->total_n;
   const int sweeps = m->opts.refine_max;
-  if (s == nullptr) {
-    // the legacy null stream cannot be captured: launch the steps directly
+  if (s == nullptr || ctx->timing) {
+    // the legacy null stream cannot be captured, and timed runs bracket every
+    // launch with events: launch the steps directly
     for (int k = 0; k < steps; ++k) record_step(m, u, f, fscale, sweeps, s);
   } else if (!m->step_graph || m->graph_u != u || m->graph_f != f || m->graph_sweeps != sweeps ||
              m->graph_fscale != fscale) {
@@ -1148,7 +1292,7 @@ hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const doubl
     m->graph_sweeps = sweeps;
     m->graph_fscale = fscale;
   }
-  if (s != nullptr)
+  if (s != nullptr && !ctx->timing)
     for (int k = 0; k < steps; ++k) HIP_TRY(hipGraphLaunch(m->step_graph, s));
   HIP_TRY(hipGetLastError());
   if (info) {

@@ -117,13 +117,13 @@ hodlr_status run_lr(fde2d_plan P, const LrJob& job, int slot, bool recompress, h
   ReduceUnit* dr = reinterpret_cast<ReduceUnit*>(du + P->cap_gram);
   HIP_TRY(hipMemcpyAsync(dr, reds.data(), reds.size() * sizeof(ReduceUnit), hipMemcpyHostToDevice, s));
   double* gp = P->gpart + int64_t(slot) * P->cap_gram * kG2;
-  hipLaunchKernelGGL(k_lr_gram, dim3(units.size()), dim3(256), 0, s, P->jobs, du, gp);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(reds.size()), dim3(256), 0, s, dr, gp, P->grams);
+  HFDE_LAUNCH(k_lr_gram, dim3(units.size()), dim3(256), 0, s, P->jobs, du, gp);
+  HFDE_LAUNCH(k_gram_reduce, dim3(reds.size()), dim3(256), 0, s, dr, gp, P->grams);
   if (!recompress) {
-    hipLaunchKernelGGL(k_lr_frob, dim3(1), dim3(256), 0, s, P->jobs + slot, P->grams, P->frob + slot);
+    HFDE_LAUNCH(k_lr_frob, dim3(1), dim3(256), 0, s, P->jobs + slot, P->grams, P->frob + slot);
     return HODLR_OK;
   }
-  hipLaunchKernelGGL(k_lr_core, dim3(1), dim3(kWG), kFactorLdsBytes, s, P->jobs + slot, P->grams, P->mbuf);
+  HFDE_LAUNCH(k_lr_core, dim3(1), dim3(kWG), kFactorLdsBytes, s, P->jobs + slot, P->grams, P->mbuf);
   std::vector<LrUnit> fu;
   for (int side = 0; side < 2; ++side) {
     const int64_t rows = side == 0 ? jb.rows_x : jb.rows_y;
@@ -131,7 +131,7 @@ hodlr_status run_lr(fde2d_plan P, const LrJob& job, int slot, bool recompress, h
   }
   LrUnit* dfu = du + P->cap_gram + 2;
   HIP_TRY(hipMemcpyAsync(dfu, fu.data(), fu.size() * sizeof(LrUnit), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_lr_form, dim3(fu.size()), dim3(256), 0, s, P->jobs, dfu, P->mbuf);
+  HFDE_LAUNCH(k_lr_form, dim3(fu.size()), dim3(256), 0, s, P->jobs, dfu, P->mbuf);
   return HODLR_OK;
 }
 
@@ -150,7 +150,7 @@ hodlr_status read_frob(fde2d_plan P, int slot, double* v, hipStream_t s) {
 void copy_cols(int64_t rows, const int32_t* rdev, int rfix, const double* src, int64_t lds, double* dst, int64_t ldd,
                double sc, hipStream_t s) {
   const int blocks = int(std::min<int64_t>((rows * 64 + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_copy_cols, dim3(blocks), dim3(256), 0, s, rows, rdev, rfix, src, lds, dst, ldd, sc);
+  HFDE_LAUNCH(k_copy_cols, dim3(blocks), dim3(256), 0, s, rows, rdev, rfix, src, lds, dst, ldd, sc);
 }
 
 // One fADI sweep on the right-hand side G H^T (rank r0, in P->G / P->H; they are
@@ -172,7 +172,7 @@ hodlr_status adi_sweep(fde2d_plan P, int r0, double cnorm, int& steps, int& pari
     launch_solve_units(m, m->opts.prec, P->pair_wu + P->pwu_off[j], P->pwu_cnt[j], P->pair_nu + P->pnu_off[j],
                        P->pnu_cnt[j], P->xin, tn, P->xin, tn, r0, s);
     const double w = P->p[j] + P->q[j];
-    hipLaunchKernelGGL(k_adi_update, dim3(256), dim3(256), 0, s, nx, ny, P->ranks + kR_R0, w, P->xin + ix.row0, tn,
+    HFDE_LAUNCH(k_adi_update, dim3(256), dim3(256), 0, s, nx, ny, P->ranks + kR_R0, w, P->xin + ix.row0, tn,
                        P->xin + iy.row0, tn, P->G, nx, P->H, ny);
     // D <- recompress([D, w Z_j][W_D, Y_j])
     LrJob jb{};
@@ -236,6 +236,7 @@ int fde2d_plan_shifts(fde2d_plan p, double* ps, double* qs, int cap) {
 hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
                                const hodlr_opts* hopts, const fde2d_opts* opts, fde2d_plan* out) {
   if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
   if (!opx) return set_arg(ctx, 2);
   if (!opy) return set_arg(ctx, 3);
   if (!hopts) return set_arg(ctx, 4);
@@ -346,6 +347,7 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
 hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* U_m, const lr_matrix* F, double dt,
                                   lr_matrix* U_next, hodlr_info* info) {
   if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
   if (!P) return set_arg(ctx, 2);
   if (!U_m || U_m->rank < 0 || U_m->rank > kRS || (U_m->rank > 0 && (!U_m->Z || !U_m->W))) return set_arg(ctx, 3);
   if (!F || F->rank < 0 || F->rank > kRS || (F->rank > 0 && (!F->Z || !F->W))) return set_arg(ctx, 4);

@@ -23,6 +23,7 @@ EXPORTS = [
     "hodlr_default_opts", "hodlr_build", "hodlr_destroy", "hodlr_get_info", "hodlr_matvec",
     "hodlr_toeplitz_matvec", "hodlr_factor", "hodlr_solve", "hodlr_time_steps",
     "fde2d_plan_create", "fde2d_plan_destroy", "fde2d_plan_shifts", "fde2d_sylvester_step",
+    "hodlr_ctx_set_timing", "hodlr_ctx_timing_count", "hodlr_ctx_timing_entry", "hodlr_ctx_timing_reset",
 ]
 
 
@@ -46,7 +47,8 @@ class HodlrMatInfo(C.Structure):
     _fields_ = [("batch", C.c_int), ("leaf", C.c_int), ("max_levels", C.c_int),
                 ("total_n", C.c_int64), ("max_rank_A", C.c_int), ("max_rank_factors", C.c_int),
                 ("bytes_factors", C.c_size_t), ("bytes_device", C.c_size_t),
-                ("factor_flops", C.c_double)]
+                ("factor_flops", C.c_double), ("core_flops", C.c_double), ("gram_flops", C.c_double),
+                ("leaf_flops", C.c_double)]
 
 
 class LrMatrix(C.Structure):
@@ -85,6 +87,11 @@ def lib():
         L.hodlr_factor.argtypes = [vp, vp, C.POINTER(HodlrInfo)]
         L.hodlr_solve.argtypes = [vp, vp, vp, i32, i64, C.POINTER(HodlrInfo)]
         L.hodlr_time_steps.argtypes = [vp, vp, vp, vp, dbl, i32, C.POINTER(HodlrInfo)]
+        L.hodlr_ctx_set_timing.argtypes = [vp, i32]
+        L.hodlr_ctx_timing_count.argtypes = [vp]
+        L.hodlr_ctx_timing_entry.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(i64), C.POINTER(dbl)]
+        L.hodlr_ctx_timing_reset.argtypes = [vp]
+        L.hodlr_ctx_timing_reset.restype = None
         if hasattr(L, "fde2d_plan_create"):
             L.fde2d_plan_create.argtypes = [vp, C.POINTER(FdeOperator), C.POINTER(FdeOperator),
                                             C.POINTER(HodlrOpts), C.POINTER(Fde2dOpts), C.POINTER(vp)]
@@ -123,6 +130,23 @@ class Context:
     def __init__(self, stream=None):
         self.h = C.c_void_p()
         check(lib().hodlr_ctx_create(C.byref(self.h), _stream_handle(stream)), "hodlr_ctx_create")
+
+    def set_timing(self, enable: bool):
+        """Bracket every kernel launched through this context with HIP events."""
+        check(lib().hodlr_ctx_set_timing(self.h, int(bool(enable))), "hodlr_ctx_set_timing")
+
+    def timing(self) -> dict:
+        """{kernel launch expression: (launches, total_ms)} accumulated so far."""
+        out = {}
+        for i in range(lib().hodlr_ctx_timing_count(self.h)):
+            name, n, ms = C.c_char_p(), C.c_int64(), C.c_double()
+            check(lib().hodlr_ctx_timing_entry(self.h, i, C.byref(name), C.byref(n), C.byref(ms)),
+                  "hodlr_ctx_timing_entry")
+            out[name.value.decode()] = (n.value, ms.value)
+        return out
+
+    def reset_timing(self):
+        lib().hodlr_ctx_timing_reset(self.h)
 
     def close(self):
         if self.h:
