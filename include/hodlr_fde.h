@@ -229,6 +229,64 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* 
                                   const lr_matrix* F, double dt, lr_matrix* U_next,
                                   hodlr_info* info);
 
+/* As fde2d_sylvester_step, starting from a first guess X0 of the solution
+ * (low-rank, rank <= opts.max_rank; NULL or rank 0: no guess).  The exact
+ * residual R = C - A X0 - X0 B^T becomes the right-hand side of the first
+ * sweep, whose result corrects X0; if ||R||_F >= ||C||_F the guess is dropped
+ * and the plain step runs (info->used_fallback = 1).  The ADI sweeps apply the
+ * shift pairs in an interleaved order and stop once the fADI residual is below
+ * opts.tol * ||C||_F, so a guess with a small residual takes fewer ADI steps
+ * (info->refine_iters).  Argument 7 is U_next.  The learned warm start of the
+ * 2D time stepper (a network's prediction of U^{m+1}, compressed by
+ * fde2d_compress_field) is what this entry point is for. */
+hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* U_m,
+                                        const lr_matrix* F, double dt, const lr_matrix* X0,
+                                        lr_matrix* U_next, hodlr_info* info);
+
+/* Dense field out[i + j nx] = (X)(i, j) for X = Z W^T (FP32, device, nx x ny
+ * column-major, nx, ny of the plan). */
+hodlr_status fde2d_field_from_lr(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* X, float* out);
+
+/* Low-rank approximation of a dense field (FP32, device, nx x ny column-major)
+ * by a randomized range finder: a 32-column sketch X Om with uniform random Om
+ * (counter-based generator, `seed`), two orthonormalising passes, then X^T Q,
+ * truncated at tol ||X||_F and at min(out->capacity, opts.max_rank) columns.
+ * out: caller-allocated factors; out->rank is set. */
+hodlr_status fde2d_compress_field(hodlr_ctx ctx, fde2d_plan p, const float* X, double tol,
+                                  uint64_t seed, lr_matrix* out);
+
+/* ---- learned warm start: the network --------------------------------------
+ * Not part of the paper: a four-layer 3x3 convolutional network predicts
+ * u_{k+1} ~ u + net(u) from u = u_k on the 2D grid (zero padding = the
+ * absorbing boundary); channels 1 -> 32 -> 32 -> 32 -> 1, ReLU after the first
+ * three layers.  Parameters (FP32, fde_net_param_count() of them, in this
+ * order): w1[32][1][3][3], b1[32], w2[32][32][3][3], b2[32], w3[32][32][3][3],
+ * b3[32], w4[1][32][3][3], b4[1]; w[o][c][p][q] multiplies input channel c at
+ * the neighbour (i + p - 1, j + q - 1) for output channel o.  Hidden
+ * activations are stored in BF16 (act_bf16 = 1: the 32 -> 32 layers run on
+ * BF16 matrix cores with FP32 accumulation) or FP32 (act_bf16 = 0); weights,
+ * gradients and Adam state are FP32.  Images: n x h x w row-major FP32, device;
+ * n*h*w <= max_pixels. */
+typedef struct fde_net_s* fde_net;
+int fde_net_param_count(void);
+hodlr_status fde_net_create(hodlr_ctx ctx, int act_bf16, int64_t max_pixels, fde_net* out);
+void fde_net_destroy(fde_net net);
+/* host arrays of fde_net_param_count() floats; set_params also clears the Adam state */
+hodlr_status fde_net_set_params(hodlr_ctx ctx, fde_net net, const float* params, int count);
+hodlr_status fde_net_get_params(hodlr_ctx ctx, fde_net net, float* params, int count);
+/* gradients of the last fde_net_train_step */
+hodlr_status fde_net_get_grads(hodlr_ctx ctx, fde_net net, float* grads, int count);
+/* pred = u + net(u) */
+hodlr_status fde_net_forward(hodlr_ctx ctx, fde_net net, const float* u, int n, int h, int w,
+                             float* pred);
+/* One step on the batch: loss = mean over the interior (margin pixels left out
+ * on every side) of (pred - target)^2, its gradients, and, if update != 0, an
+ * Adam step (beta1 = 0.9, beta2 = 0.999, eps = 1e-8) with learning rate lr.
+ * loss (host, may be NULL) is written after the device work completes. */
+hodlr_status fde_net_train_step(hodlr_ctx ctx, fde_net net, const float* u, const float* target,
+                                int n, int h, int w, int margin, float lr, int update,
+                                double* loss);
+
 #ifdef __cplusplus
 }
 #endif

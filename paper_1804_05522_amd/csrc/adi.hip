@@ -219,4 +219,89 @@ __global__ void k_copy_cols(int64_t rows, const int32_t* rdev, int rfix, const d
   }
 }
 
+// ---------------------------------------------------- dense fields
+// Uniform(-1, 1) numbers from a counter-based generator (splitmix64 of
+// seed + index), for the random sketch of a dense field.
+__global__ void k_fill_uniform(double* out, int64_t count, uint64_t seed) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += int64_t(gridDim.x) * blockDim.x) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * uint64_t(e + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    out[e] = double(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
+__global__ void k_set_identity(double* out, int n, int ld) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n * n) out[(e % n) + (e / n) * ld] = (e % n == e / n) ? 1.0 : 0.0;
+}
+
+// Y = X Om: X dense nx x ny (FP32, column-major), Om ny x k (ld ny), Y nx x k
+// (ld nx), k <= 32.  A thread per row of X; Om is staged in LDS in tiles.
+__global__ void __launch_bounds__(256) k_field_times(int64_t nx, int64_t ny, const float* X, const double* Om, int k,
+                                                     double* Y) {
+  constexpr int kT = 64;
+  __shared__ double om[kT * 32];
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  double acc[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) acc[c] = 0.0;
+  for (int64_t j0 = 0; j0 < ny; j0 += kT) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kT * 32; e += 256) {
+      const int jj = e % kT, c = e / kT;
+      om[jj * 32 + c] = (j0 + jj < ny && c < k) ? Om[j0 + jj + int64_t(c) * ny] : 0.0;
+    }
+    __syncthreads();
+    if (i < nx) {
+      const int jn = int(min<int64_t>(kT, ny - j0));
+      for (int jj = 0; jj < jn; ++jj) {
+        const double x = double(X[i + (j0 + jj) * nx]);
+#pragma unroll
+        for (int c = 0; c < 32; ++c) acc[c] += x * om[jj * 32 + c];
+      }
+    }
+  }
+  if (i < nx)
+    for (int c = 0; c < k; ++c) Y[i + int64_t(c) * nx] = acc[c];
+}
+
+// B = X^T Q: X nx x ny (FP32), Q nx x k (ld nx, k = *kdev <= 32), B ny x k
+// (ld ny).  A block takes 256 columns of X; 32-row tiles of X are staged
+// (coalesced down the columns) and transposed in LDS with Q's rows.
+__global__ void __launch_bounds__(256) k_field_t_times(int64_t nx, int64_t ny, const float* X, const double* Q,
+                                                       const int32_t* kdev, double* B) {
+  constexpr int kR = 32;
+  __shared__ float xt[kR * 257];
+  __shared__ double qs[kR * 32];
+  const int k = *kdev;
+  const int64_t j0 = int64_t(blockIdx.x) * 256;
+  const int t = threadIdx.x;
+  double acc[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) acc[c] = 0.0;
+  for (int64_t i0 = 0; i0 < nx; i0 += kR) {
+    __syncthreads();
+    for (int e = t; e < kR * 256; e += 256) {
+      const int r = e % kR, cl = e / kR;
+      const int64_t i = i0 + r, j = j0 + cl;
+      xt[r * 257 + cl] = (i < nx && j < ny) ? X[i + j * nx] : 0.0f;
+    }
+    for (int e = t; e < kR * 32; e += 256) {
+      const int r = e % kR, c = e / kR;
+      qs[r * 32 + c] = (i0 + r < nx && c < k) ? Q[i0 + r + int64_t(c) * nx] : 0.0;
+    }
+    __syncthreads();
+    for (int r = 0; r < kR; ++r) {
+      const double x = double(xt[r * 257 + t]);
+#pragma unroll
+      for (int c = 0; c < 32; ++c) acc[c] += x * qs[r * 32 + c];
+    }
+  }
+  const int64_t j = j0 + t;
+  if (j < ny)
+    for (int c = 0; c < k; ++c) B[j + int64_t(c) * ny] = acc[c];
+}
+
 }  // namespace hfde

@@ -209,6 +209,7 @@ struct fde2d_plan_s {
   hodlr_mat exact = nullptr;    // the unshifted A and B (exact products for the residual)
   int J = 0;
   std::vector<double> p, q;
+  std::vector<int> order;   // application order of the shift pairs (interleaved)
   int64_t nx = 0, ny = 0;
   double shift_x = 0.5, shift_y = 0.5;
   fde2d_opts opts{};

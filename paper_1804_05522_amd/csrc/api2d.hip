@@ -164,7 +164,8 @@ hodlr_status adi_sweep(fde2d_plan P, int r0, double cnorm, int& steps, int& pari
   parity = 0;
   steps = 0;
   if (r0 == 0) return HODLR_OK;
-  for (int j = 0; j < P->J; ++j) {
+  for (int jo = 0; jo < P->J; ++jo) {
+    const int j = P->order[jo];
     const Item& ix = m->items[j];
     const Item& iy = m->items[P->J + j];
     copy_cols(nx, P->ranks + kR_R0, 0, P->G, nx, P->xin + ix.row0, tn, 1.0, s);
@@ -192,10 +193,10 @@ hodlr_status adi_sweep(fde2d_plan P, int r0, double cnorm, int& steps, int& pari
     jb.ldu = nx;
     jb.V = P->Wd[1 - parity];
     jb.ldv = ny;
-    TRY(run_lr(P, jb, 2 + (j & 1), true, s));
+    TRY(run_lr(P, jb, 2 + (jo & 1), true, s));
     parity = 1 - parity;
-    steps = j + 1;
-    if ((j % 4 == 3) || j == P->J - 1) {
+    steps = jo + 1;
+    if ((jo % 4 == 3) || jo == P->J - 1) {
       LrJob nj{};
       nj.X.g[0] = grp(P->G, nx, P->ranks + kR_R0, 0, 1.0);
       nj.X.g[1] = nj.X.g[2] = grp_none();
@@ -277,6 +278,37 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
   J = std::min(J, opts->max_shifts);
   zolotarev_shifts(a1, b1, a2, b2, J, P->p, P->q);
   P->J = J;
+  // Shift pairs are applied in an interleaved order (the two ends of the
+  // sorted list, then midpoints breadth first), so that every prefix of the
+  // sweep spreads over both spectral intervals: the sweep can stop as soon as
+  // the residual meets the target, which a first guess with a small residual
+  // reaches early.
+  {
+    std::vector<int> ord;
+    std::vector<char> used(J, 0);
+    auto take = [&](int i) {
+      if (i >= 0 && i < J && !used[i]) {
+        used[i] = 1;
+        ord.push_back(i);
+      }
+    };
+    take(0);
+    take(J - 1);
+    std::vector<std::pair<int, int>> seg{{0, J - 1}};
+    while (!seg.empty()) {
+      std::vector<std::pair<int, int>> next;
+      for (auto [lo, hi] : seg) {
+        if (hi - lo < 2) continue;
+        const int mid = (lo + hi) / 2;
+        take(mid);
+        next.push_back({lo, mid});
+        next.push_back({mid, hi});
+      }
+      seg.swap(next);
+    }
+    for (int i = 0; i < J; ++i) take(i);
+    P->order = ord;
+  }
   // batched shifted operator: x items shift_x + q_j, y items shift_y + p_j
   std::vector<fde_operator> ops;
   for (int j = 0; j < J; ++j) { fde_operator o = *opx; o.shift = opx->shift + P->q[j]; ops.push_back(o); }
@@ -344,14 +376,16 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
   return HODLR_OK;
 }
 
-hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* U_m, const lr_matrix* F, double dt,
-                                  lr_matrix* U_next, hodlr_info* info) {
+hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* U_m, const lr_matrix* F,
+                                        double dt, const lr_matrix* X0, lr_matrix* U_next, hodlr_info* info) {
   if (!ctx) return HODLR_EINVAL;
   TimerScope ts_(ctx);
   if (!P) return set_arg(ctx, 2);
   if (!U_m || U_m->rank < 0 || U_m->rank > kRS || (U_m->rank > 0 && (!U_m->Z || !U_m->W))) return set_arg(ctx, 3);
   if (!F || F->rank < 0 || F->rank > kRS || (F->rank > 0 && (!F->Z || !F->W))) return set_arg(ctx, 4);
-  if (!U_next || !U_next->Z || !U_next->W || U_next->capacity < 1) return set_arg(ctx, 6);
+  if (X0 && (X0->rank < 0 || X0->rank > P->opts.max_rank || (X0->rank > 0 && (!X0->Z || !X0->W))))
+    return set_arg(ctx, 6);
+  if (!U_next || !U_next->Z || !U_next->W || U_next->capacity < 1) return set_arg(ctx, 7);
   hipStream_t s = ctx->stream;
   const int64_t nx = P->nx, ny = P->ny;
   const double tol = P->opts.tol;
@@ -395,73 +429,19 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* 
     TRY(read_frob(P, 1, &cn2, s));
   }
   const double cnorm = std::sqrt(std::max(cn2, 0.0));
-  // sweep 0 on C itself
-  copy_cols(nx, P->ranks + kR_C, 0, P->G0, nx, P->G, nx, 1.0, s);
-  copy_cols(ny, P->ranks + kR_C, 0, P->H0, ny, P->H, ny, 1.0, s);
-  HIP_TRY(hipMemcpyAsync(P->ranks + kR_R0, P->ranks + kR_C, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  HIP_TRY(hipMemsetAsync(P->ranks + kR_X0, 0, sizeof(int32_t), s));
-  int xpar = 0, total_steps = 0, sweeps = 0;
-  double rel_res = 0.0, rel_corr = 1.0;
-  int r0 = rc;
-  hodlr_status res = HODLR_OK;
-  for (sweeps = 0; sweeps < 5; ++sweeps) {
-    int steps = 0, dpar = 0;
-    TRY(adi_sweep(P, r0, std::max(cnorm, 1e-300), steps, dpar, s));
-    total_steps += steps;
-    // X <- recompress([X, D][W_X, W_D])
-    LrJob mj{};
-    mj.X.g[0] = grp(P->Zx[xpar], nx, P->ranks + kR_X0 + xpar, 0, 1.0);
-    mj.X.g[1] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
-    mj.X.g[2] = grp_none();
-    mj.Y.g[0] = grp(P->Wx[xpar], ny, P->ranks + kR_X0 + xpar, 0, 1.0);
-    mj.Y.g[1] = grp(P->Wd[dpar], ny, P->ranks + kR_D0 + dpar, 0, 1.0);
-    mj.Y.g[2] = grp_none();
-    mj.rows_x = nx;
-    mj.rows_y = ny;
-    mj.rank_out = P->ranks + kR_X0 + (1 - xpar);
-    mj.tau = 0.0;
-    mj.tau_rel = 0.1 * tol;
-    mj.rmax = P->opts.max_rank;
-    mj.U = P->Zx[1 - xpar];
-    mj.ldu = nx;
-    mj.V = P->Wx[1 - xpar];
-    mj.ldv = ny;
-    TRY(run_lr(P, mj, 4, true, s));
-    xpar = 1 - xpar;
-    // size of the correction relative to X
-    double d2 = 0.0, x2 = 0.0;
-    {
-      LrJob nj{};
-      nj.X.g[0] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
-      nj.X.g[1] = nj.X.g[2] = grp_none();
-      nj.Y.g[0] = grp(P->Wd[dpar], ny, P->ranks + kR_D0 + dpar, 0, 1.0);
-      nj.Y.g[1] = nj.Y.g[2] = grp_none();
-      nj.rows_x = nx;
-      nj.rows_y = ny;
-      TRY(run_lr(P, nj, 5, false, s));
-      LrJob xj = nj;
-      xj.X.g[0] = grp(P->Zx[xpar], nx, P->ranks + kR_X0 + xpar, 0, 1.0);
-      xj.Y.g[0] = grp(P->Wx[xpar], ny, P->ranks + kR_X0 + xpar, 0, 1.0);
-      TRY(run_lr(P, xj, 6, false, s));
-      TRY(read_frob(P, 5, &d2, s));
-      TRY(read_frob(P, 6, &x2, s));
-    }
-    rel_corr = x2 > 0 ? std::sqrt(std::max(d2, 0.0) / x2) : 0.0;
-    if (sweeps > 0 && rel_corr <= tol) break;
-    if (rc == 0) break;
-    // exact residual R = C - A X - X B^T  ->  next sweep's right-hand side (G, H)
-    TRY(read_ranks(P, hr, s));
-    const int rx = hr[kR_X0 + xpar];
-    if (rx == 0) break;
-    copy_cols(nx, nullptr, rx, P->Zx[xpar], nx, P->ex_in, nx + ny, 1.0, s);
-    copy_cols(ny, nullptr, rx, P->Wx[xpar], ny, P->ex_in + nx, nx + ny, 1.0, s);
+  // R = C - A X - X B^T for X = Zx[xp] Wx[xp]^T (rank rx) with the exact
+  // near/far Toeplitz products, recompressed into G, H (rank at kR_R0);
+  // returns ||R||_F / ||C||_F.
+  auto exact_residual = [&](int xp, int rx, double& rel) -> hodlr_status {
+    copy_cols(nx, nullptr, rx, P->Zx[xp], nx, P->ex_in, nx + ny, 1.0, s);
+    copy_cols(ny, nullptr, rx, P->Wx[xp], ny, P->ex_in + nx, nx + ny, 1.0, s);
     launch_fft_matvec(P->exact, P->ex_in, nx + ny, P->ex_out, nx + ny, nullptr, 0, rx, s);
     LrJob r1{};
     r1.X.g[0] = grp(P->G0, nx, P->ranks + kR_C, 0, 1.0);
     r1.X.g[1] = grp(P->ex_out, nx + ny, nullptr, rx, -1.0);      // A Z_X
     r1.X.g[2] = grp_none();
     r1.Y.g[0] = grp(P->H0, ny, P->ranks + kR_C, 0, 1.0);
-    r1.Y.g[1] = grp(P->Wx[xpar], ny, nullptr, rx, 1.0);
+    r1.Y.g[1] = grp(P->Wx[xp], ny, nullptr, rx, 1.0);
     r1.Y.g[2] = grp_none();
     r1.rows_x = nx;
     r1.rows_y = ny;
@@ -476,7 +456,7 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* 
     TRY(run_lr(P, r1, 7, true, s));
     LrJob r2 = r1;
     r2.X.g[0] = grp(P->R1, nx, P->ranks + kR_T, 0, 1.0);
-    r2.X.g[1] = grp(P->Zx[xpar], nx, nullptr, rx, -1.0);
+    r2.X.g[1] = grp(P->Zx[xp], nx, nullptr, rx, -1.0);
     r2.Y.g[0] = grp(P->R1w, ny, P->ranks + kR_T, 0, 1.0);
     r2.Y.g[1] = grp(P->ex_out + nx, nx + ny, nullptr, rx, 1.0);   // B W_X
     r2.rank_out = P->ranks + kR_R0;
@@ -493,15 +473,100 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* 
     TRY(run_lr(P, nj, 9, false, s));
     double r2n = 0.0;
     TRY(read_frob(P, 9, &r2n, s));
-    rel_res = cnorm > 0 ? std::sqrt(std::max(r2n, 0.0)) / cnorm : 0.0;
+    rel = cnorm > 0 ? std::sqrt(std::max(r2n, 0.0)) / cnorm : 0.0;
+    return HODLR_OK;
+  };
+  int xpar = 0, total_steps = 0, sweeps = 0;
+  double rel_res = 0.0, rel_corr = 1.0;
+  int r0 = rc;
+  bool warm = false, fallback = false;
+  if (X0 && X0->rank > 0 && rc > 0) {
+    // first guess: X = X0, right-hand side of the first sweep = its exact residual
+    copy_cols(nx, nullptr, X0->rank, X0->Z, X0->ldz, P->Zx[0], nx, 1.0, s);
+    copy_cols(ny, nullptr, X0->rank, X0->W, X0->ldw, P->Wx[0], ny, 1.0, s);
+    const int32_t rk = X0->rank;
+    HIP_TRY(hipMemcpyAsync(P->ranks + kR_X0, &rk, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    double rel0 = 0.0;
+    TRY(exact_residual(0, X0->rank, rel0));
     TRY(read_ranks(P, hr, s));
-    r0 = hr[kR_R0];
-    if (rel_res <= 1e-3 * tol) break;
+    if (rel0 < 1.0) {
+      warm = true;
+      rel_res = rel0;
+      r0 = hr[kR_R0];
+    } else {
+      fallback = true;          // the guess is no better than zero: plain solve
+    }
   }
-  if (sweeps >= 5 && rel_corr > tol) res = HODLR_ENOCONV;
+  if (!warm) {                  // sweep 0 on C itself
+    copy_cols(nx, P->ranks + kR_C, 0, P->G0, nx, P->G, nx, 1.0, s);
+    copy_cols(ny, P->ranks + kR_C, 0, P->H0, ny, P->H, ny, 1.0, s);
+    HIP_TRY(hipMemcpyAsync(P->ranks + kR_R0, P->ranks + kR_C, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemsetAsync(P->ranks + kR_X0, 0, sizeof(int32_t), s));
+    r0 = rc;
+  }
+  hodlr_status res = HODLR_OK;
+  if (!(warm && rel_res <= 1e-3 * tol)) {
+    for (sweeps = 0; sweeps < 5; ++sweeps) {
+      int steps = 0, dpar = 0;
+      TRY(adi_sweep(P, r0, std::max(cnorm, 1e-300), steps, dpar, s));
+      total_steps += steps;
+      // X <- recompress([X, D][W_X, W_D])
+      LrJob mj{};
+      mj.X.g[0] = grp(P->Zx[xpar], nx, P->ranks + kR_X0 + xpar, 0, 1.0);
+      mj.X.g[1] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
+      mj.X.g[2] = grp_none();
+      mj.Y.g[0] = grp(P->Wx[xpar], ny, P->ranks + kR_X0 + xpar, 0, 1.0);
+      mj.Y.g[1] = grp(P->Wd[dpar], ny, P->ranks + kR_D0 + dpar, 0, 1.0);
+      mj.Y.g[2] = grp_none();
+      mj.rows_x = nx;
+      mj.rows_y = ny;
+      mj.rank_out = P->ranks + kR_X0 + (1 - xpar);
+      mj.tau = 0.0;
+      mj.tau_rel = 0.1 * tol;
+      mj.rmax = P->opts.max_rank;
+      mj.U = P->Zx[1 - xpar];
+      mj.ldu = nx;
+      mj.V = P->Wx[1 - xpar];
+      mj.ldv = ny;
+      TRY(run_lr(P, mj, 4, true, s));
+      xpar = 1 - xpar;
+      // size of the correction relative to X
+      double d2 = 0.0, x2 = 0.0;
+      {
+        LrJob nj{};
+        nj.X.g[0] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
+        nj.X.g[1] = nj.X.g[2] = grp_none();
+        nj.Y.g[0] = grp(P->Wd[dpar], ny, P->ranks + kR_D0 + dpar, 0, 1.0);
+        nj.Y.g[1] = nj.Y.g[2] = grp_none();
+        nj.rows_x = nx;
+        nj.rows_y = ny;
+        TRY(run_lr(P, nj, 5, false, s));
+        LrJob xj = nj;
+        xj.X.g[0] = grp(P->Zx[xpar], nx, P->ranks + kR_X0 + xpar, 0, 1.0);
+        xj.Y.g[0] = grp(P->Wx[xpar], ny, P->ranks + kR_X0 + xpar, 0, 1.0);
+        TRY(run_lr(P, xj, 6, false, s));
+        TRY(read_frob(P, 5, &d2, s));
+        TRY(read_frob(P, 6, &x2, s));
+      }
+      rel_corr = x2 > 0 ? std::sqrt(std::max(d2, 0.0) / x2) : 0.0;
+      // a sweep from zero is not a correction; sweeps from a residual are
+      if ((sweeps > 0 || warm) && rel_corr <= tol) break;
+      if (rc == 0) break;
+      TRY(read_ranks(P, hr, s));
+      const int rx = hr[kR_X0 + xpar];
+      if (rx == 0) break;
+      TRY(exact_residual(xpar, rx, rel_res));
+      TRY(read_ranks(P, hr, s));
+      r0 = hr[kR_R0];
+      if (rel_res <= 1e-3 * tol) break;
+    }
+    if (sweeps >= 5 && rel_corr > tol) res = HODLR_ENOCONV;
+  } else {
+    rel_corr = 0.0;
+  }
   TRY(read_ranks(P, hr, s));
   const int rx = hr[kR_X0 + xpar];
-  if (rx > U_next->capacity) return set_arg(ctx, 6);
+  if (rx > U_next->capacity) return set_arg(ctx, 7);
   copy_cols(nx, nullptr, rx, P->Zx[xpar], nx, U_next->Z, U_next->ldz, 1.0, s);
   copy_cols(ny, nullptr, rx, P->Wx[xpar], ny, U_next->W, U_next->ldw, 1.0, s);
   U_next->rank = rx;
@@ -516,8 +581,90 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* 
     info->max_rank = rx;
     info->leaf = -1;
     info->row = -1;
+    info->used_fallback = fallback ? 1 : 0;
   }
   return res;
+}
+
+hodlr_status fde2d_field_from_lr(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* X, float* out) {
+  if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
+  if (!P) return set_arg(ctx, 2);
+  if (!X || X->rank < 0 || (X->rank > 0 && (!X->Z || !X->W))) return set_arg(ctx, 3);
+  if (!out) return set_arg(ctx, 4);
+  const int64_t tot = P->nx * P->ny;
+  HFDE_LAUNCH(k_lr_to_dense, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, ctx->stream, P->nx, P->ny, X->rank, X->Z,
+              X->ldz, X->W, X->ldw, out);
+  HIP_TRY(hipGetLastError());
+  return HODLR_OK;
+}
+
+hodlr_status fde2d_compress_field(hodlr_ctx ctx, fde2d_plan P, const float* X, double tol, uint64_t seed,
+                                  lr_matrix* out) {
+  if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
+  if (!P) return set_arg(ctx, 2);
+  if (!X) return set_arg(ctx, 3);
+  if (!(tol > 0.0)) return set_arg(ctx, 4);
+  if (!out || !out->Z || !out->W || out->capacity < 1) return set_arg(ctx, 6);
+  hipStream_t s = ctx->stream;
+  const int64_t nx = P->nx, ny = P->ny;
+  constexpr int kSk = 32;                       // sketch columns
+  // scratch between steps: R1w = Om (ny x 32), R1 = Y (nx x 32), G = Q1, G0 = Q2,
+  // H = B (ny x 32), ex_in = the 32 x 32 identity
+  HFDE_LAUNCH(k_fill_uniform, dim3(256), dim3(256), 0, s, P->R1w, ny * kSk, seed);
+  HFDE_LAUNCH(k_field_times, dim3(unsigned((nx + 255) / 256)), dim3(256), 0, s, nx, ny, X, P->R1w, kSk, P->R1);
+  HFDE_LAUNCH(k_set_identity, dim3((kSk * kSk + 255) / 256), dim3(256), 0, s, P->ex_in, kSk, kSk);
+  // two orthonormalising passes: Q1 Q1'^T = Y I^T, then Q2 from Q1
+  for (int pass = 0; pass < 2; ++pass) {
+    LrJob oj{};
+    oj.X.g[0] = pass == 0 ? grp(P->R1, nx, nullptr, kSk, 1.0) : grp(P->G, nx, P->ranks + kR_T, 0, 1.0);
+    oj.X.g[1] = oj.X.g[2] = grp_none();
+    oj.Y.g[0] = pass == 0 ? grp(P->ex_in, kSk, nullptr, kSk, 1.0) : grp(P->ex_in, kSk, P->ranks + kR_T, 0, 1.0);
+    oj.Y.g[1] = oj.Y.g[2] = grp_none();
+    oj.rows_x = nx;
+    oj.rows_y = kSk;
+    oj.rank_out = P->ranks + (pass == 0 ? kR_T : kR_D0);
+    oj.tau = 0.0;
+    oj.tau_rel = 1e-15;
+    oj.rmax = kSk;
+    oj.U = pass == 0 ? P->G : P->G0;
+    oj.ldu = nx;
+    oj.V = P->R1w + ny * kSk;                   // unused right factor (32 x r)
+    oj.ldv = kSk;
+    TRY(run_lr(P, oj, 10 + pass, true, s));
+  }
+  HFDE_LAUNCH(k_field_t_times, dim3(unsigned((ny + 255) / 256)), dim3(256), 0, s, nx, ny, X, P->G0, P->ranks + kR_D0,
+              P->H);
+  // X ~ Q2 (X^T Q2)^T, truncated at tol ||X||_F
+  LrJob tj{};
+  tj.X.g[0] = grp(P->G0, nx, P->ranks + kR_D0, 0, 1.0);
+  tj.X.g[1] = tj.X.g[2] = grp_none();
+  tj.Y.g[0] = grp(P->H, ny, P->ranks + kR_D0, 0, 1.0);
+  tj.Y.g[1] = tj.Y.g[2] = grp_none();
+  tj.rows_x = nx;
+  tj.rows_y = ny;
+  tj.rank_out = P->ranks + kR_D1;
+  tj.tau = 0.0;
+  tj.tau_rel = tol;
+  tj.rmax = std::min(out->capacity, P->opts.max_rank);
+  tj.U = out->Z;
+  tj.ldu = out->ldz;
+  tj.V = out->W;
+  tj.ldv = out->ldw;
+  TRY(run_lr(P, tj, 12, true, s));
+  int32_t hr[kR_N];
+  TRY(read_ranks(P, hr, s));
+  out->rank = hr[kR_D1];
+  HIP_TRY(hipGetLastError());
+  return HODLR_OK;
+}
+
+hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* U_m, const lr_matrix* F, double dt,
+                                  lr_matrix* U_next, hodlr_info* info) {
+  const hodlr_status st = fde2d_sylvester_step_guess(ctx, P, U_m, F, dt, nullptr, U_next, info);
+  if (st == HODLR_EINVAL && ctx && ctx->last_arg == 7) ctx->last_arg = 6;
+  return st;
 }
 
 }  // extern "C"

@@ -53,7 +53,7 @@ __device__ inline bf16 from_f<bf16>(float f) {
 
 struct NetImg {
   int n, H, W;
-  __device__ inline int64_t pixels() const { return int64_t(n) * H * W; }
+  __host__ __device__ inline int64_t pixels() const { return int64_t(n) * H * W; }
   // neighbour of pixel p at offset (s*dp, s*dq), or -1 outside the image
   __device__ inline int64_t nb(int64_t p, int dp, int dq) const {
     const int64_t img = p / (int64_t(H) * W);

@@ -8,5 +8,7 @@
 #include "solve.hip"
 #include "fft.hip"
 #include "adi.hip"
+#include "convnet.hip"
 #include "api.hip"
 #include "api2d.hip"
+#include "apinet.hip"

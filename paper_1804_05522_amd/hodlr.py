@@ -24,6 +24,9 @@ EXPORTS = [
     "hodlr_toeplitz_matvec", "hodlr_factor", "hodlr_solve", "hodlr_time_steps",
     "fde2d_plan_create", "fde2d_plan_destroy", "fde2d_plan_shifts", "fde2d_sylvester_step",
     "hodlr_ctx_set_timing", "hodlr_ctx_timing_count", "hodlr_ctx_timing_entry", "hodlr_ctx_timing_reset",
+    "fde2d_sylvester_step_guess", "fde2d_field_from_lr", "fde2d_compress_field",
+    "fde_net_param_count", "fde_net_create", "fde_net_destroy", "fde_net_set_params", "fde_net_get_params",
+    "fde_net_get_grads", "fde_net_forward", "fde_net_train_step",
 ]
 
 
@@ -100,6 +103,22 @@ def lib():
             L.fde2d_plan_shifts.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), i32]
             L.fde2d_sylvester_step.argtypes = [vp, vp, C.POINTER(LrMatrix), C.POINTER(LrMatrix), dbl,
                                                C.POINTER(LrMatrix), C.POINTER(HodlrInfo)]
+            L.fde2d_sylvester_step_guess.argtypes = [vp, vp, C.POINTER(LrMatrix), C.POINTER(LrMatrix), dbl,
+                                                     C.POINTER(LrMatrix), C.POINTER(LrMatrix), C.POINTER(HodlrInfo)]
+            L.fde2d_field_from_lr.argtypes = [vp, vp, C.POINTER(LrMatrix), vp]
+            L.fde2d_compress_field.argtypes = [vp, vp, vp, dbl, C.c_uint64, C.POINTER(LrMatrix)]
+        if hasattr(L, "fde_net_create"):
+            L.fde_net_param_count.argtypes = []
+            L.fde_net_create.argtypes = [vp, i32, i64, C.POINTER(vp)]
+            L.fde_net_destroy.argtypes = [vp]
+            L.fde_net_destroy.restype = None
+            fp = C.POINTER(C.c_float)
+            L.fde_net_set_params.argtypes = [vp, vp, fp, i32]
+            L.fde_net_get_params.argtypes = [vp, vp, fp, i32]
+            L.fde_net_get_grads.argtypes = [vp, vp, fp, i32]
+            L.fde_net_forward.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+            L.fde_net_train_step.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, C.c_float, i32,
+                                             C.POINTER(dbl)]
         _lib = L
     return _lib
 
@@ -267,24 +286,122 @@ class Fde2dPlan:
         lib().fde2d_plan_shifts(self.h, p, q, n)
         return list(p), list(q)
 
-    def step(self, Um, F, dt, out, allow=(HODLR_OK,)):
-        """Um, F, out: (Z, W) pairs of column-major torch CUDA float64 tensors
-        stored as (rank, n) row-major (column j = row j); out gives the capacity."""
-        def lr(zw, cap=None):
-            Z, W = zw
-            r = Z.shape[0] if Z is not None else 0
-            return LrMatrix(self.nx, r if cap is None else 0, cap or r, self.nx, self.ny,
-                            C.c_void_p(Z.data_ptr() if Z is not None and Z.numel() else 0),
-                            C.c_void_p(W.data_ptr() if W is not None and W.numel() else 0))
-        a, f, o = lr(Um), lr(F), lr(out, cap=out[0].shape[0])
+    def _lr(self, zw, cap=None, rank=None):
+        Z, W = zw
+        r = (Z.shape[0] if Z is not None else 0) if rank is None else rank
+        return LrMatrix(self.nx, r if cap is None else 0, cap or r, self.nx, self.ny,
+                        C.c_void_p(Z.data_ptr() if Z is not None and Z.numel() else 0),
+                        C.c_void_p(W.data_ptr() if W is not None and W.numel() else 0))
+
+    def step(self, Um, F, dt, out, allow=(HODLR_OK,), guess=None, guess_rank=None):
+        """Um, F, out, guess: (Z, W) pairs of column-major torch CUDA float64
+        tensors stored as (rank, n) row-major (column j = row j); out gives the
+        capacity.  guess: optional first guess of the solution (its first
+        guess_rank columns)."""
+        a, f, o = self._lr(Um), self._lr(F), self._lr(out, cap=out[0].shape[0])
         info = HodlrInfo()
-        check(lib().fde2d_sylvester_step(self.ctx.h, self.h, C.byref(a), C.byref(f), float(dt), C.byref(o),
-                                         C.byref(info)), "fde2d_sylvester_step", self.ctx.h, allow)
+        if guess is None:
+            check(lib().fde2d_sylvester_step(self.ctx.h, self.h, C.byref(a), C.byref(f), float(dt), C.byref(o),
+                                             C.byref(info)), "fde2d_sylvester_step", self.ctx.h, allow)
+        else:
+            g = self._lr(guess, rank=guess_rank)
+            check(lib().fde2d_sylvester_step_guess(self.ctx.h, self.h, C.byref(a), C.byref(f), float(dt),
+                                                   C.byref(g), C.byref(o), C.byref(info)),
+                  "fde2d_sylvester_step_guess", self.ctx.h, allow)
         return o.rank, info
+
+    def to_field(self, zw, out, rank=None):
+        """Dense FP32 field of X = Z W^T into out, a (ny, nx) torch CUDA float32
+        tensor (row j = grid line y_j)."""
+        x = self._lr(zw, rank=rank)
+        check(lib().fde2d_field_from_lr(self.ctx.h, self.h, C.byref(x), C.c_void_p(out.data_ptr())),
+              "fde2d_field_from_lr", self.ctx.h)
+
+    def compress_field(self, field, tol, out, seed=1):
+        """Low-rank (Z, W) of a dense (ny, nx) FP32 field; out gives the capacity; returns the rank."""
+        o = self._lr(out, cap=out[0].shape[0])
+        check(lib().fde2d_compress_field(self.ctx.h, self.h, C.c_void_p(field.data_ptr()), float(tol), int(seed),
+                                         C.byref(o)), "fde2d_compress_field", self.ctx.h)
+        return o.rank
 
     def close(self):
         if self.h:
             lib().fde2d_plan_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ConvNet:
+    """The learned warm start's network (four 3x3 convolutions, 1 -> 32 -> 32 ->
+    32 -> 1, residual output u + net(u)), trained and run by the library's
+    kernels.  Parameters use the layout of fde_net_set_params."""
+
+    def __init__(self, ctx: Context, bf16=True, max_pixels=1 << 22):
+        self.ctx = ctx
+        self.h = C.c_void_p()
+        self.count = lib().fde_net_param_count()
+        check(lib().fde_net_create(ctx.h, int(bool(bf16)), int(max_pixels), C.byref(self.h)), "fde_net_create",
+              ctx.h)
+
+    @staticmethod
+    def flatten(params):
+        """[[w1, b1], ..., [w4, b4]] (numpy, oracle layout) -> float32 vector."""
+        import numpy as np
+        return np.concatenate([np.asarray(a, dtype=np.float32).ravel() for wb in params for a in wb])
+
+    @staticmethod
+    def unflatten(flat, channels=32):
+        import numpy as np
+        shapes = [(channels, 1, 3, 3), (channels,), (channels, channels, 3, 3), (channels,),
+                  (channels, channels, 3, 3), (channels,), (1, channels, 3, 3), (1,)]
+        out, off = [], 0
+        for s in shapes:
+            n = int(np.prod(s))
+            out.append(np.asarray(flat[off:off + n], dtype=np.float64).reshape(s))
+            off += n
+        return [out[0:2], out[2:4], out[4:6], out[6:8]]
+
+    def set_params(self, params):
+        import numpy as np
+        flat = params if isinstance(params, np.ndarray) else self.flatten(params)
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        check(lib().fde_net_set_params(self.ctx.h, self.h, flat.ctypes.data_as(C.POINTER(C.c_float)), self.count),
+              "fde_net_set_params", self.ctx.h)
+
+    def _get(self, fn, name):
+        import numpy as np
+        out = np.zeros(self.count, dtype=np.float32)
+        check(fn(self.ctx.h, self.h, out.ctypes.data_as(C.POINTER(C.c_float)), self.count), name, self.ctx.h)
+        return out
+
+    def get_params(self):
+        return self._get(lib().fde_net_get_params, "fde_net_get_params")
+
+    def get_grads(self):
+        return self._get(lib().fde_net_get_grads, "fde_net_get_grads")
+
+    def forward(self, u, pred):
+        """u, pred: (n, h, w) torch CUDA float32 tensors."""
+        n, hh, ww = u.shape
+        check(lib().fde_net_forward(self.ctx.h, self.h, C.c_void_p(u.data_ptr()), n, hh, ww,
+                                    C.c_void_p(pred.data_ptr())), "fde_net_forward", self.ctx.h)
+
+    def train_step(self, u, target, margin=4, lr=1e-3, update=True):
+        n, hh, ww = u.shape
+        loss = C.c_double()
+        check(lib().fde_net_train_step(self.ctx.h, self.h, C.c_void_p(u.data_ptr()), C.c_void_p(target.data_ptr()),
+                                       n, hh, ww, int(margin), float(lr), int(bool(update)), C.byref(loss)),
+              "fde_net_train_step", self.ctx.h)
+        return loss.value
+
+    def close(self):
+        if self.h:
+            lib().fde_net_destroy(self.h)
             self.h = C.c_void_p()
 
     def __del__(self):
