@@ -88,6 +88,12 @@ def main():
             timing.append([ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])])
         return A, u, info
 
+    # launch shapes of the factorisation, tuned once on this workload's tree
+    # (untimed; later matrices of the same shape use them)
+    At = H.HodlrMatrix(ctx, ops, H.default_opts(tol=1e-10, prec=args.prec))
+    tuned = At.autotune()
+    At.close()
+
     def calibrate(prec):
         """Fewest refinement sweeps per step whose last correction is <= target."""
         for sweeps in range(0, 9):
@@ -173,6 +179,8 @@ def main():
         "rel_correction_last": main_res["rel_correction"],
         "rank_A": main_res["rank_A"], "rank_factors": main_res["rank_factors"],
         "roofline": roof,
+        "autotuned": {"core_threads": tuned.core_threads, "leaf_threads": tuned.leaf_threads,
+                      "gram_rows": tuned.gram_rows, "fuse_rows": tuned.fuse_rows, "factor_ms": tuned.factor_ms},
         "cpu_baseline": cpu,
     }
     if cmp_res is not None:

@@ -158,6 +158,32 @@ hodlr_status hodlr_toeplitz_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, 
  * tolerance, plus the HODLR inverses of both triangular factors. */
 hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info);
 
+/* Launch-shape autotuner of the factorisation (a production pattern, not part
+ * of the paper).  Times the factorisation kernels of m (HIP events, best of two
+ * runs) in a coordinate search over: the largest child size (rows) of a node
+ * whose phase A runs as fused single-work-group kernels (0, 128, 256, 512,
+ * 1024; 0 = never), rows per Gram partial of the other nodes (128, 256, 512),
+ * and the work-group sizes of the recompression cores and of the leaves (256
+ * or 512 threads).  Keeps the fastest for m and for every matrix of the same
+ * tree signature (batch, total rows, depth, leaf size) built later in the
+ * process.  The trial runs overwrite m's factors: call hodlr_factor afterwards.
+ * best (may be NULL): the chosen shapes and their factorisation time. */
+typedef struct {
+  int core_threads;
+  int leaf_threads;
+  int gram_rows;
+  int fuse_rows;
+  double factor_ms;
+} hodlr_tuning;
+hodlr_status hodlr_autotune(hodlr_ctx ctx, hodlr_mat m, hodlr_tuning* best);
+
+/* Sets m's factorisation launch shapes (core_threads, leaf_threads: 256 or
+ * 512; gram_rows: 32 .. 65536, a multiple of 32; fuse_rows >= 0; factor_ms is
+ * ignored), for instance ones found by hodlr_autotune on another matrix.  Any
+ * other value: HODLR_EINVAL (argument 3).  The factors computed with any valid
+ * shape agree up to the rounding order of the Gram sums. */
+hodlr_status hodlr_set_tuning(hodlr_ctx ctx, hodlr_mat m, const hodlr_tuning* t);
+
 /* x <- M^{-1} x for every problem and column (Sec. 3.5 back substitution,
  * applied through the HODLR inverses of the triangular factors).  With
  * opts.refine_max > 0 the solve is followed by FP64 iterative refinement whose
@@ -232,8 +258,11 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* 
 /* As fde2d_sylvester_step, starting from a first guess X0 of the solution
  * (low-rank, rank <= opts.max_rank; NULL or rank 0: no guess).  The exact
  * residual R = C - A X0 - X0 B^T becomes the right-hand side of the first
- * sweep, whose result corrects X0; if ||R||_F >= ||C||_F the guess is dropped
- * and the plain step runs (info->used_fallback = 1).  The ADI sweeps apply the
+ * sweep, whose result corrects X0.  The J shift pairs of the plan reduce a
+ * residual by about (0.1 opts.tol)^(1/J) per shift; if ||R||_F / ||C||_F
+ * exceeds (0.1 opts.tol)^(4/J) (the guess would save less than one block of
+ * four shifts), or R needs more than 31 columns to meet its tolerance, the
+ * guess is dropped and the plain step runs (info->used_fallback = 1).  The ADI sweeps apply the
  * shift pairs in an interleaved order and stop once the fADI residual is below
  * opts.tol * ||C||_F, so a guess with a small residual takes fewer ADI steps
  * (info->refine_iters).  Argument 7 is U_next.  The learned warm start of the

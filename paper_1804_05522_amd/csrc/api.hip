@@ -11,6 +11,9 @@
 #include <cstdlib>
 #include <string>
 #include <vector>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <functional>
 
 
@@ -179,6 +182,10 @@ struct hodlr_mat_s {
   bf16* IU16 = nullptr;
   // multi-work-group factorisation schedule
   bool mwg_planned = false;
+  int core_threads = 512;                    // launch shapes of the factorisation (tunable)
+  int leaf_threads = 512;
+  int gram_rows = kGramRows;
+  int fuse_rows = kFuseRows;                 // phase A of nodes with children up to this many rows: fused kernels
   std::vector<int> mwg_kind;                 // launch kind per record
   std::vector<int> mwg_grid;                 // grid size
   std::vector<int64_t> mwg_off;              // offset into the unit array of its kind
@@ -407,7 +414,12 @@ void launch_axpby(int64_t nrows, int nc, double a, const double* x, int64_t ldx,
 // ------------------------------------------------------------------
 // Multi-work-group factorisation: host schedule (post-order, lock-step
 // over the problems of the batch, which must share one tree shape).
-enum MwgKind { KL_LEAF = 0, KL_GRAM, KL_REDUCE, KL_CORE, KL_FORM, KL_SPP, KL_SPR, KL_SPE };
+enum MwgKind { KL_LEAF = 0, KL_GRAM, KL_REDUCE, KL_CORE, KL_FORM, KL_SPP, KL_SPR, KL_SPE, KL_NODE_REC, KL_NODE_PEND };
+
+static int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v ? atoi(v) : dflt;
+}
 
 static hodlr_status plan_mwg(hodlr_mat m) {
   if (m->mwg_planned) return HODLR_OK;
@@ -453,6 +465,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   }
   size_t steps = 0;
   for (auto& e : evs) steps = std::max(steps, e.size());
+  const int fuse_rows = env_int("HODLR_FUSE_ROWS", m->fuse_rows);
   struct TaskSpec { int item, d; int64_t j; int64_t n1, n2; };
   auto add_tasks = [&](const std::vector<TaskSpec>& ts) {
     const int64_t t0 = int64_t(tasks.size());
@@ -465,7 +478,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
     int32_t outi = 0;
     for (size_t k = 0; k < ts.size(); ++k)
       for (auto& p : pairs) {
-        const int chunks = int((rows_of(ts[k], p[0]) + kGramRows - 1) / kGramRows);
+        const int chunks = int((rows_of(ts[k], p[0]) + m->gram_rows - 1) / m->gram_rows);
         reds.push_back(ReduceUnit{outi, std::max(chunks, 1), int32_t(k * 9 + p[2]), 0});
         for (int c = 0; c < std::max(chunks, 1); ++c)
           grams.push_back(GramUnit{int32_t(k), int16_t(p[0]), int16_t(p[1]), c, outi++});
@@ -545,7 +558,14 @@ static hodlr_status plan_mwg(hodlr_mat m) {
       const int64_t t0 = add_tasks(lt);
       rec(KL_LEAF, int(lt.size()), t0, t0);
     }
-    if (!at.empty()) {
+    bool fuse = !at.empty();
+    for (const TaskSpec& t : at) fuse = fuse && std::max(t.n1, t.n2) <= fuse_rows;
+    if (fuse) {
+      const int64_t t0 = add_tasks(at);
+      rec(KL_NODE_REC, int(2 * at.size()), t0, t0);
+      add_prods(at, {{0, 0, 0, A_T1, A_FU, 0, 1.0}, {0, 1, 1, A_T2, A_FL, 1, 1.0}});
+      rec(KL_NODE_PEND, int(at.size()), t0, t0);
+    } else if (!at.empty()) {
       const int64_t t0 = add_tasks(at);
       add_grams(t0, at, {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {3, 3, 3}});
       add_core(t0, at.size(), {0, 1});
@@ -589,18 +609,32 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   return HODLR_OK;
 }
 
-static int env_int(const char* name, int dflt) {
-  const char* v = getenv(name);
-  return v ? atoi(v) : dflt;
-}
+// Launch shapes chosen by hodlr_autotune, per tree signature (batch, total
+// rows, depth, leaf size), applied to matrices built later in the process.
+struct TuneKey {
+  int batch;
+  int64_t total_n;
+  int levels, leaf;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(batch, total_n, levels, leaf) < std::tie(o.batch, o.total_n, o.levels, o.leaf);
+  }
+};
+struct TuneVal {
+  int core_threads, leaf_threads, gram_rows, fuse_rows;
+};
+static std::map<TuneKey, TuneVal> g_tuned;
+static std::mutex g_tuned_mu;
+
+static TuneKey tune_key(hodlr_mat m) { return TuneKey{m->batch, m->total_n, m->Lmax, m->b}; }
+
 
 static void enqueue_mwg(hodlr_mat m, hipStream_t s) {
   const DevPtrs& P = m->P;
   // block sizes of the latency-bound single-group kernels (512 measured fastest);
   // the leaf kernel splits its dot products over blockDim/128 threads, so it needs >= 128
   auto pick = [](int v) { return v >= 512 ? 512 : (v >= 256 ? 256 : 128); };
-  const int core_threads = std::max(256, pick(env_int("HODLR_CORE_THREADS", 512)));
-  const int leaf_threads = std::max(256, pick(env_int("HODLR_LEAF_THREADS", 512)));
+  const int core_threads = std::max(256, pick(env_int("HODLR_CORE_THREADS", m->core_threads)));
+  const int leaf_threads = std::max(256, pick(env_int("HODLR_LEAF_THREADS", m->leaf_threads)));
   const int Lmax = std::max(1, m->Lmax);
   for (size_t q = 0; q < m->mwg_kind.size(); ++q) {
     const int g = m->mwg_grid[q];
@@ -611,7 +645,8 @@ static void enqueue_mwg(hodlr_mat m, hipStream_t s) {
         HFDE_LAUNCH(k_leaf_task, dim3(g), dim3(leaf_threads), kFactorLdsBytes, s, P, m->d_tasks + off, m->b);
         break;
       case KL_GRAM:
-        HFDE_LAUNCH(k_gram_partial, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_gram + off, m->d_gpart);
+        HFDE_LAUNCH(k_gram_partial, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_gram + off, m->d_gpart,
+                    m->gram_rows);
         break;
       case KL_REDUCE:
         HFDE_LAUNCH(k_gram_reduce, dim3(g), dim3(256), 0, s, m->d_red + off, m->d_gpart, m->d_G);
@@ -629,6 +664,13 @@ static void enqueue_mwg(hodlr_mat m, hipStream_t s) {
       case KL_SPR:
         HFDE_LAUNCH(k_sp_reduce, dim3(g), dim3(256), 0, s, P, m->d_jobs + off2, m->d_punits + off, m->d_ppart,
                            m->d_pz, Lmax);
+        break;
+      case KL_NODE_REC:
+        HFDE_LAUNCH(k_node_recompress, dim3(g), dim3(core_threads), kFactorLdsBytes, s, P, m->d_tasks + off,
+                    m->opts.max_rank);
+        break;
+      case KL_NODE_PEND:
+        HFDE_LAUNCH(k_node_pending, dim3(g), dim3(core_threads), kFactorLdsBytes, s, P, m->d_tasks + off);
         break;
       default:
         HFDE_LAUNCH(k_sp_expand, dim3(g), dim3(256), kSpExpLds, s, P, m->d_jobs + off2, m->d_punits + off, m->d_pz, m->b);
@@ -715,6 +757,10 @@ static hodlr_status set_lds_limits() {
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_task),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(kFactorLdsBytes)));
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_core),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(kFactorLdsBytes)));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_node_recompress),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(kFactorLdsBytes)));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_node_pending),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(kFactorLdsBytes)));
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sp_project),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(kSpProjLds)));
@@ -950,6 +996,16 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipMemcpy(m->items.data(), P.items, batch * sizeof(Item), hipMemcpyDeviceToHost));
   for (const Item& it : m->items) m->max_rank_A = std::max(m->max_rank_A, it.r);
+  {  // launch shapes tuned earlier in the process for this tree signature
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto f = g_tuned.find(tune_key(m));
+    if (f != g_tuned.end()) {
+      m->core_threads = f->second.core_threads;
+      m->leaf_threads = f->second.leaf_threads;
+      m->gram_rows = f->second.gram_rows;
+      m->fuse_rows = f->second.fuse_rows;
+    }
+  }
   *out = m;
   return HODLR_OK;
 }
@@ -1098,12 +1154,110 @@ hodlr_status hodlr_toeplitz_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, 
   return HODLR_OK;
 }
 
+hodlr_status hodlr_set_tuning(hodlr_ctx ctx, hodlr_mat m, const hodlr_tuning* t) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!m) return set_arg(ctx, 2);
+  if (!t || (t->core_threads != 256 && t->core_threads != 512) || (t->leaf_threads != 256 && t->leaf_threads != 512) ||
+      t->gram_rows < 32 || t->gram_rows > 65536 || t->gram_rows % 32 != 0 || t->fuse_rows < 0)
+    return set_arg(ctx, 3);
+  if (t->gram_rows != m->gram_rows || t->fuse_rows != m->fuse_rows) {
+    m->gram_rows = t->gram_rows;
+    m->fuse_rows = t->fuse_rows;
+    m->mwg_planned = false;
+    m->mwg_kind.clear();
+    m->mwg_grid.clear();
+    m->mwg_off.clear();
+    m->mwg_off2.clear();
+  }
+  m->core_threads = t->core_threads;
+  m->leaf_threads = t->leaf_threads;
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_autotune(hodlr_ctx ctx, hodlr_mat m, hodlr_tuning* best) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!m) return set_arg(ctx, 2);
+  hipStream_t s = ctx->stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto replan = [&](int g, int f) -> hodlr_status {
+    if (g == m->gram_rows && f == m->fuse_rows && m->mwg_planned) return HODLR_OK;
+    m->gram_rows = g;
+    m->fuse_rows = f;
+    m->mwg_planned = false;
+    m->mwg_kind.clear();
+    m->mwg_grid.clear();
+    m->mwg_off.clear();
+    m->mwg_off2.clear();
+    return plan_mwg(m);
+  };
+  // factorisation time of one launch-shape choice: best of two runs
+  auto trial = [&](const TuneVal& v, double& ms) -> hodlr_status {
+    TRY(replan(v.gram_rows, v.fuse_rows));
+    m->core_threads = v.core_threads;
+    m->leaf_threads = v.leaf_threads;
+    ms = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIP_TRY(hipEventRecord(e0, s));
+      enqueue_mwg(m, s);
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float t = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+      ms = std::min(ms, double(t));
+    }
+    return HODLR_OK;
+  };
+  // coordinate search: fused-node threshold, then Gram chunk rows, then the
+  // work-group sizes of the cores and leaves
+  TuneVal bestv{m->core_threads, m->leaf_threads, m->gram_rows, m->fuse_rows};
+  double best_ms = 1e300;
+  auto consider = [&](TuneVal v) -> hodlr_status {
+    double ms = 0.0;
+    TRY(trial(v, ms));
+    if (ms < best_ms) {
+      best_ms = ms;
+      bestv = v;
+    }
+    return HODLR_OK;
+  };
+  for (int f : {0, 128, 256, 512, 1024}) TRY(consider(TuneVal{bestv.core_threads, bestv.leaf_threads, bestv.gram_rows, f}));
+  for (int g : {128, 256, 512})
+    if (g != bestv.gram_rows) TRY(consider(TuneVal{bestv.core_threads, bestv.leaf_threads, g, bestv.fuse_rows}));
+  const TuneVal base = bestv;
+  for (int ct : {256, 512})
+    for (int lt : {256, 512})
+      if (ct != base.core_threads || lt != base.leaf_threads)
+        TRY(consider(TuneVal{ct, lt, base.gram_rows, base.fuse_rows}));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  TRY(replan(bestv.gram_rows, bestv.fuse_rows));
+  m->core_threads = bestv.core_threads;
+  m->leaf_threads = bestv.leaf_threads;
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned[tune_key(m)] = bestv;
+  }
+  if (best) {
+    best->core_threads = bestv.core_threads;
+    best->leaf_threads = bestv.leaf_threads;
+    best->gram_rows = bestv.gram_rows;
+    best->fuse_rows = bestv.fuse_rows;
+    best->factor_ms = best_ms;
+  }
+  HIP_TRY(hipGetLastError());
+  return HODLR_OK;
+}
+
 hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
   if (!ctx) return HODLR_EINVAL;
   TimerScope ts_(ctx);
   if (!m) return set_arg(ctx, 2);
   hipStream_t s = ctx->stream;
   const size_t lds = kFactorLdsBytes;
+  HIP_TRY(hipMemsetAsync(m->P.status, 0, m->batch * sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(m->P.diag, 0, 4 * m->batch * sizeof(int32_t), s));
   const char* env = getenv("HODLR_FACTOR_PATH");
   const bool single = (env && env[0] == 's');
   if (single) {

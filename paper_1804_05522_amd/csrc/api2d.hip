@@ -489,7 +489,14 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
     double rel0 = 0.0;
     TRY(exact_residual(0, X0->rank, rel0));
     TRY(read_ranks(P, hr, s));
-    if (rel0 < 1.0) {
+    // The J shifts reduce a residual by about 0.1 tol, i.e. by
+    // (0.1 tol)^(1/J) per shift.  The guess is worth taking only if its
+    // residual saves at least one block of four shifts (the sweep tests for
+    // convergence every four), and the residual must be represented to its
+    // tolerance (rank below the cap) for the correction to be the solution's
+    // error.  Otherwise the plain step runs, so a guess never costs ADI steps.
+    const double accept = std::pow(0.1 * tol, 4.0 / std::max(P->J, 4));
+    if (rel0 <= accept && hr[kR_R0] < kRS) {
       warm = true;
       rel_res = rel0;
       r0 = hr[kR_R0];

@@ -478,7 +478,8 @@ __device__ RecompressOut wg_core_grams(double* L, int R, double tau, int rmax) {
   __shared__ int s_k[3];
   for (int j = t; j < R; j += blockDim.x) {
     const double a = G[j + j * kLdG], b = KC[j + j * kLdG];
-    vec[128 + j] = (a > 0.0 && b > 0.0) ? sqrt(sqrt(b / a)) : 1.0;
+    // (b / a)^(1/4) from the two fourth roots: no overflow for tiny a
+    vec[128 + j] = (a > 0.0 && b > 0.0) ? sqrt(sqrt(b)) / sqrt(sqrt(a)) : 1.0;
     vec[j] = a;
     vec[64 + j] = b;
   }

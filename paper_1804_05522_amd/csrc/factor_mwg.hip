@@ -105,7 +105,8 @@ __device__ inline OpRef op_ref(const DevPtrs& P, const Item& it, int d, int64_t 
   }
 }
 
-constexpr int kGramRows = 256;      // rows per partial
+constexpr int kGramRows = 256;      // default rows per partial (a per-matrix tunable)
+constexpr int kFuseRows = 256;      // default largest child of a node whose phase A runs fused (tunable)
 constexpr int kGramSub = 32;        // rows staged in LDS at a time
 constexpr int kGramLd = 66;         // LDS row stride (16-byte aligned rows, spread banks)
 constexpr int kG2 = kMaxCat * kMaxCat;   // one 64 x 64 matrix
@@ -118,71 +119,152 @@ struct GramUnit {
   int32_t out;       // output slot (partial index)
 };
 
+// ------------------------------------------------ Grams on the matrix cores
+typedef double hfde_d4 __attribute__((ext_vector_type(4)));
+constexpr int kStLd = kGramSub + 1;    // column stride (rows) of a staged window in LDS
+constexpr int kMaxTW = 5;              // Gram tiles per wave (20 tiles over 4 waves)
+
+// FP64 16x16x4 matrix-core product: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; element v of the result of lane l is D[4v + l/16][l%16].
+__device__ inline hfde_d4 mfma64(double a, double b, hfde_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// (ti, tj), ti <= tj, of upper-triangle tile s in tj-major order
+__device__ inline void sym_tile(int s, int& ti, int& tj) {
+  tj = 0;
+  while ((tj + 1) * (tj + 2) / 2 <= s) ++tj;
+  ti = s - tj * (tj + 1) / 2;
+}
+
+// Gram matrices with FP64 matrix-core products.  kTwo: out0 = S0^T S0 and
+// out1 = S1^T S1; otherwise out0 = S0^T S1 (symmetric when `same`: S1 is S0).
+// Rows [row0, row0 + rows0) of S0 and [row0, row0 + rows1) of S1 enter.  The
+// work-group stages windows of kGramSub rows of both operands column-major
+// in LDS (st0, st1: kMaxCat x kStLd each), fetching the next window into
+// registers while the current one is multiplied; wave w owns the 16 x 16
+// output tiles w, w + waves, ... (upper triangle only for a symmetric Gram,
+// mirrored on output).  out: ld ldo; zero_rest: zeros over the rest of the
+// 64 x 64 block.  Work-groups of 256 or 512 threads.
+template <bool kTwo>
+__device__ void wg_gram_mfma(const Cat& S0, const Cat& S1, int64_t row0, int64_t rows0, int64_t rows1, bool same,
+                             double* out0, double* out1, int ldo, bool zero_rest, double* st0, double* st1) {
+  const int nt = blockDim.x, t = threadIdx.x;
+  const int l = t & 63, wave = t >> 6, waves = nt >> 6;
+  const int c0 = S0.cols(), c1 = S1.cols();
+  const int t0 = (c0 + 15) >> 4, t1 = (c1 + 15) >> 4;
+  const bool sym0 = kTwo || same;
+  const int T0 = sym0 ? t0 * (t0 + 1) / 2 : t0 * t1;
+  const int T = kTwo ? T0 + t1 * (t1 + 1) / 2 : T0;
+  const bool stage1 = kTwo || !same;
+  if (!stage1) rows1 = 0;
+  const int64_t most = max(rows0, rows1);
+  // this thread stages window row si of columns sc + cstep q
+  constexpr int kQ = kGramSub * kMaxCat / 256;
+  const int si = t % kGramSub, sc = t / kGramSub, cstep = nt / kGramSub;
+  const double* q0[kQ];
+  const double* q1[kQ];
+  double f0[kQ], f1[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int c = sc + cstep * q;
+    const bool a1 = c < S0.c1, b1 = c < S1.c1;
+    q0[q] = c < c0 ? (a1 ? S0.p1 + int64_t(c) * S0.ld1 : S0.p2 + int64_t(c - S0.c1) * S0.ld2) + row0 : nullptr;
+    q1[q] = (stage1 && c < c1) ? (b1 ? S1.p1 + int64_t(c) * S1.ld1 : S1.p2 + int64_t(c - S1.c1) * S1.ld2) + row0
+                               : nullptr;
+    f0[q] = a1 ? S0.s1 : S0.s2;
+    f1[q] = b1 ? S1.s1 : S1.s2;
+  }
+  double v0[kQ], v1[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    v0[q] = (q0[q] && si < rows0) ? f0[q] * q0[q][si] : 0.0;
+    v1[q] = (q1[q] && si < rows1) ? f1[q] * q1[q][si] : 0.0;
+  }
+  hfde_d4 acc[kMaxTW];
+#pragma unroll
+  for (int q = 0; q < kMaxTW; ++q) acc[q] = hfde_d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t w0 = 0; w0 < most; w0 += kGramSub) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int c = sc + cstep * q;
+      if (c < kMaxCat) {
+        st0[c * kStLd + si] = v0[q];
+        if (stage1) st1[c * kStLd + si] = v1[q];
+      }
+    }
+    __syncthreads();
+    if (w0 + kGramSub < most) {
+      const int64_t nr = w0 + kGramSub + si;
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        v0[q] = (q0[q] && nr < rows0) ? f0[q] * q0[q][nr] : 0.0;
+        v1[q] = (q1[q] && nr < rows1) ? f1[q] * q1[q][nr] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxTW; ++q) {
+      const int tau = wave + q * waves;
+      if (tau < T) {
+        int ti, tj;
+        const bool g1 = kTwo && tau >= T0;
+        if (g1) sym_tile(tau - T0, ti, tj);
+        else if (sym0) sym_tile(tau, ti, tj);
+        else { ti = tau % t0; tj = tau / t0; }
+        const double* A = (g1 ? st1 : st0) + (ti * 16 + (l & 15)) * kStLd + (l >> 4);
+        const double* B = (kTwo ? (g1 ? st1 : st0) : (same ? st0 : st1)) + (tj * 16 + (l & 15)) * kStLd + (l >> 4);
+#pragma unroll
+        for (int s4 = 0; s4 < kGramSub; s4 += 4) acc[q] = mfma64(A[s4], B[s4], acc[q]);
+      }
+    }
+  }
+  if (zero_rest && !kTwo) {
+    const int N0 = same ? c0 : c1;
+    for (int e = t; e < kMaxCat * kMaxCat; e += nt) {
+      const int i = e % kMaxCat, j = e / kMaxCat;
+      if (i >= c0 || j >= N0) out0[i + j * ldo] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxTW; ++q) {
+    const int tau = wave + q * waves;
+    if (tau < T) {
+      int ti, tj;
+      const bool g1 = kTwo && tau >= T0;
+      if (g1) sym_tile(tau - T0, ti, tj);
+      else if (sym0) sym_tile(tau, ti, tj);
+      else { ti = tau % t0; tj = tau / t0; }
+      double* out = g1 ? out1 : out0;
+      const int M = g1 ? c1 : c0, N = (g1 || sym0) ? M : c1;
+      const bool mirror = (g1 || sym0) && ti != tj;
+      const int j = tj * 16 + (l & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ti * 16 + 4 * v + (l >> 4);
+        if (i < M && j < N) {
+          out[i + j * ldo] = acc[q][v];
+          if (mirror) out[j + i * ldo] = acc[q][v];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // partial[out] = X[chunk rows]^T Y[chunk rows]  (64 x 64, zero padded).
-// Slabs of 32 rows are staged row-major in LDS; the next slab is fetched into
-// registers while the current one is multiplied.
 __global__ void __launch_bounds__(256) k_gram_partial(DevPtrs P, const NodeTask* tasks, const GramUnit* units,
-                                                      double* partial) {
-  __shared__ __align__(16) double xs[kGramSub * kGramLd];
-  __shared__ __align__(16) double ys[kGramSub * kGramLd];
+                                                      double* partial, int grows) {
+  __shared__ __align__(16) double st[2 * kMaxCat * kStLd];
   const GramUnit u = units[blockIdx.x];
   const NodeTask tk = tasks[u.task];
   const Item it = P.items[tk.item];
   const OpRef X = op_ref(P, it, tk.d, tk.j, u.tx);
   const OpRef Y = op_ref(P, it, tk.d, tk.j, u.ty);
-  const int M = X.cat.cols(), N = Y.cat.cols();
-  const int t = threadIdx.x;
-  const int ti = (t % 16) * 4, tj = (t / 16) * 4;   // 4 x 4 outputs per thread
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  const int64_t r0 = int64_t(u.chunk) * kGramRows;
-  const int64_t r1 = min<int64_t>(X.rows, r0 + kGramRows);
-  constexpr int kPer = kGramSub * kMaxCat / 256;      // elements per thread per slab
-  double px[kPer], py[kPer];
-  auto fetch = [&](int64_t s0) {
-    const int sr = int(min<int64_t>(kGramSub, r1 - s0));
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = t + q * 256, i = e % kGramSub, c = e / kGramSub;
-      px[q] = (i < sr && c < M) ? X.cat.at(s0 + i, c) : 0.0;
-      py[q] = (i < sr && c < N) ? Y.cat.at(s0 + i, c) : 0.0;
-    }
-  };
-  if (r0 < r1) fetch(r0);
-  for (int64_t s0 = r0; s0 < r1; s0 += kGramSub) {
-    const int sr = int(min<int64_t>(kGramSub, r1 - s0));
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = t + q * 256, i = e % kGramSub, c = e / kGramSub;
-      xs[i * kGramLd + c] = px[q];
-      ys[i * kGramLd + c] = py[q];
-    }
-    __syncthreads();
-    if (s0 + kGramSub < r1) fetch(s0 + kGramSub);
-    if (ti < M && tj < N) {
-      for (int i = 0; i < sr; ++i) {
-        const double2 x01 = *reinterpret_cast<const double2*>(xs + i * kGramLd + ti);
-        const double2 x23 = *reinterpret_cast<const double2*>(xs + i * kGramLd + ti + 2);
-        const double2 y01 = *reinterpret_cast<const double2*>(ys + i * kGramLd + tj);
-        const double2 y23 = *reinterpret_cast<const double2*>(ys + i * kGramLd + tj + 2);
-        const double xv[4] = {x01.x, x01.y, x23.x, x23.y};
-        const double yv[4] = {y01.x, y01.y, y23.x, y23.y};
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] += xv[a] * yv[b];
-      }
-    }
-  }
-  double* out = partial + int64_t(u.out) * kG2;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) out[(ti + a) + (tj + b) * kMaxCat] = acc[a][b];
+  const int64_t r0 = int64_t(u.chunk) * grows;
+  const int64_t rows = max<int64_t>(0, min<int64_t>(X.rows, r0 + grows) - r0);
+  wg_gram_mfma<false>(X.cat, Y.cat, r0, rows, rows, u.tx == u.ty, partial + int64_t(u.out) * kG2, nullptr, kMaxCat,
+                      true, st, st + kMaxCat * kStLd);
 }
 
 // G[dst] = sum of partials [first, first + count) in order.
@@ -261,6 +343,9 @@ __global__ void __launch_bounds__(kWG) k_core(DevPtrs P, const NodeTask* tasks, 
   }
 }
 
+__device__ void wg_form_mfma(const Cat& A, int64_t rows, const double* M, int ldm, int r, double* Y, int64_t ldy,
+                             int64_t row0);
+
 // Form unit: rows [chunk*256, +256) of one output of one task.
 //   out 0: T1(c1) = A12 M_U12    1: FU(c2) = B12 M_V12    2: FL(c2) = A21 M_U21
 //       3: T2(c1) = B21 M_V21    4: T1(c2) = FL(c2) C     5: PP_{d+1}(c2) = Ap M_Up
@@ -305,17 +390,142 @@ __global__ void __launch_bounds__(256) k_form(DevPtrs P, const NodeTask* tasks, 
     case 5: Y = lvl_ptr(P.PP, it, tk.d + 1); row0 = o + n1; break;
     default: Y = lvl_ptr(P.PQ, it, tk.d + 1); row0 = o + n1; break;
   }
-  const int64_t i = int64_t(fu.chunk) * 256 + threadIdx.x;
-  if (i >= A.rows) return;
-  double a[kMaxCat];
+  const int64_t c0 = int64_t(fu.chunk) * 256;
+  wg_form_mfma(A.cat, min<int64_t>(256, A.rows - c0), Ms, kMaxCat, r, Y + row0, n, c0);
+}
+
+// ------------------------------------------------ fused small-node steps
+// For a node whose children hold at most a few hundred rows the Gram chunks,
+// their reduction, the core and the forms of a recompression are one
+// work-group's job: the group computes both Grams into LDS, runs the core and
+// writes the new factors straight from the transfer matrices in LDS.  Phase A
+// of such a node is then two launches (plus the subtree products) instead of
+// eleven.  Grams and forms run on the FP64 matrix cores in both paths; only
+// their summation order differs.
+
+// Y[row0 + i + c ldy] = sum_{k < A.cols()} A(row0 + i, k) M[k + c ldm] for
+// i < rows and c < r <= 32, with M in LDS: 16-row tiles of Y (both column
+// tiles at once)
+// as Y^T = M^T A^T with FP64 matrix-core products.  The M^T operands are the
+// same for every tile and stay in registers; the 16 A values of a tile are
+// loaded (coalesced over rows) before its products.
+__device__ void wg_form_mfma(const Cat& A, int64_t rows, const double* M, int ldm, int r, double* Y, int64_t ldy,
+                             int64_t row0) {
+  const int R = A.cols();
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int ks = (R + 3) / 4;
+  const bool two = r > 16;
+  double ma[kMaxCat / 4], mb[kMaxCat / 4];
 #pragma unroll
-  for (int k = 0; k < kMaxCat; ++k) a[k] = k < R ? A.cat.at(i, k) : 0.0;
-  for (int c = 0; c < r; ++c) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < kMaxCat; ++k) s += a[k] * Ms[k + c * kMaxCat];
-    Y[row0 + i + int64_t(c) * n] = s;
+  for (int s4 = 0; s4 < kMaxCat / 4; ++s4) {
+    const int k = 4 * s4 + (l >> 4);
+    ma[s4] = k < R ? M[k + (l & 15) * ldm] : 0.0;
+    mb[s4] = (two && k < R) ? M[k + (16 + (l & 15)) * ldm] : 0.0;
   }
+  for (int64_t rt = wave; rt * 16 < rows; rt += waves) {
+    const int64_t i = rt * 16 + (l & 15);
+    double av[kMaxCat / 4];
+#pragma unroll
+    for (int s4 = 0; s4 < kMaxCat / 4; ++s4) {
+      const int k = 4 * s4 + (l >> 4);
+      av[s4] = (s4 < ks && k < R && i < rows) ? A.at(row0 + i, k) : 0.0;
+    }
+    hfde_d4 d0{0.0, 0.0, 0.0, 0.0}, d1{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < kMaxCat / 4; ++s4)
+      if (s4 < ks) {
+        d0 = mfma64(ma[s4], av[s4], d0);
+        if (two) d1 = mfma64(mb[s4], av[s4], d1);
+      }
+    if (i < rows) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 4 * v + (l >> 4);
+        if (c < r) Y[row0 + i + int64_t(c) * ldy] = d0[v];
+        if (16 + c < r) Y[row0 + i + int64_t(16 + c) * ldy] = d1[v];
+      }
+    }
+  }
+}
+
+// Staging windows of wg_gram_mfma inside the factorisation LDS (region LA,
+// which the core only writes after both Grams are in G and KC).
+static_assert(2 * kMaxCat * kStLd <= 2 * kMaxCat * kLdG, "gram staging in LA/LB");
+
+__device__ inline void record_rank(const DevPtrs& P, const Item& it, int item, int32_t* slot, RecompressOut res) {
+  if (threadIdx.x == 0) {
+    *slot = res.rank;
+    if (res.capped) atomicOr(&P.status[item], 4);
+    atomicMax(&P.diag[4 * item + 1], res.rank);
+  }
+}
+
+// Phase A, first part, of one node: unit 2k + w recompresses S12 (w = 0:
+// U12' -> T1(c1), V12' -> FU(c2)) or S21 (w = 1: U21' -> FL(c2),
+// V21' -> T2(c1)) of task k.
+__global__ void __launch_bounds__(kWG) k_node_recompress(DevPtrs P, const NodeTask* tasks, int rmax) {
+  extern __shared__ __align__(16) double Lf[];
+  const NodeTask tk = tasks[blockIdx.x >> 1];
+  const int which = blockIdx.x & 1;
+  const Item it = P.items[tk.item];
+  const int64_t nidx = node_index(it, tk.d, tk.j);
+  const Node nd = P.nodes[nidx];
+  const int64_t o = nd.start, n1 = nd.size / 2, n = it.n;
+  const OpRef A = op_ref(P, it, tk.d, tk.j, 2 * which);
+  const OpRef B = op_ref(P, it, tk.d, tk.j, 2 * which + 1);
+  const int R = A.cat.cols();
+  if (R > 0)
+    wg_gram_mfma<true>(A.cat, B.cat, 0, A.rows, B.rows, false, Lf + lds::G, Lf + lds::KC, kLdG, false,
+                       Lf + lds::LA, Lf + lds::LA + kMaxCat * kStLd);
+  RecompressOut res{0, false};
+  if (R > 0) res = wg_core_grams(Lf, R, it.tau, rmax);
+  record_rank(P, it, tk.item, which == 0 ? &P.rankU[nidx] : &P.rankL[nidx], res);
+  const int r = res.rank;
+  if (r == 0) return;
+  double* YA = which == 0 ? lvl_ptr(P.T1, it, tk.d) + o : lvl_ptr(P.FL, it, tk.d) + o + n1;
+  double* YB = which == 0 ? lvl_ptr(P.FU, it, tk.d) + o + n1 : lvl_ptr(P.T2, it, tk.d) + o;
+  wg_form_mfma(A.cat, A.rows, Lf + lds::RED, kMaxCat, r, YA, n, 0);
+  wg_form_mfma(B.cat, B.rows, Lf + lds::LB, kLdG, r, YB, n, 0);
+}
+
+// Phase A, last part, of one node (after the products U~12, V~21):
+// C = V~21^T U~12, W = U21' C -> T1(c2), then the recompression of the
+// pending update [P(c2), W][Q(c2), V12']^T of c2 -> PP, PQ at depth d + 1.
+__global__ void __launch_bounds__(kWG) k_node_pending(DevPtrs P, const NodeTask* tasks) {
+  extern __shared__ __align__(16) double Lf[];
+  const NodeTask tk = tasks[blockIdx.x];
+  const Item it = P.items[tk.item];
+  const int64_t nidx = node_index(it, tk.d, tk.j);
+  const Node nd = P.nodes[nidx];
+  const int64_t o = nd.start, n1 = nd.size / 2, n = it.n;
+  const OpRef F4 = op_ref(P, it, tk.d, tk.j, 4);
+  const OpRef F7 = op_ref(P, it, tk.d, tk.j, 7);
+  const OpRef F8 = op_ref(P, it, tk.d, tk.j, 8);
+  const int r12 = P.rankU[nidx];
+  const int c = (F4.cat.cols() > 0 && r12 > 0) ? 1 : 0;
+  if (c) {
+    wg_gram_mfma<false>(F4.cat, F7.cat, 0, F4.rows, F7.rows, false, Lf + lds::G, nullptr, kLdG, false, Lf + lds::LA,
+                        Lf + lds::LA + kMaxCat * kStLd);
+    wg_form_mfma(F8.cat, F8.rows, Lf + lds::G, kLdG, r12, lvl_ptr(P.T1, it, tk.d) + o + n1, n, 0);
+  }
+  else if (r12 > 0) {       // C = 0: W = 0
+    double* W = lvl_ptr(P.T1, it, tk.d) + o + n1;
+    for (int64_t e = threadIdx.x; e < F8.rows * r12; e += blockDim.x) W[e % F8.rows + (e / F8.rows) * n] = 0.0;
+  }
+  __syncthreads();          // W is read back below by other threads of the group
+  const OpRef Ap = op_ref(P, it, tk.d, tk.j, 5);
+  const OpRef Bp = op_ref(P, it, tk.d, tk.j, 6);
+  const int R = Ap.cat.cols();
+  if (R > 0)
+    wg_gram_mfma<true>(Ap.cat, Bp.cat, 0, Ap.rows, Bp.rows, false, Lf + lds::G, Lf + lds::KC, kLdG, false,
+                       Lf + lds::LA, Lf + lds::LA + kMaxCat * kStLd);
+  RecompressOut res{0, false};
+  if (R > 0) res = wg_core_grams(Lf, R, it.tau, kRS);
+  record_rank(P, it, tk.item, &P.rankP[node_index(it, tk.d + 1, 2 * int64_t(tk.j) + 1)], res);
+  const int r = res.rank;
+  if (r == 0) return;
+  wg_form_mfma(Ap.cat, Ap.rows, Lf + lds::RED, kMaxCat, r, lvl_ptr(P.PP, it, tk.d + 1) + o + n1, n, 0);
+  wg_form_mfma(Bp.cat, Bp.rows, Lf + lds::LB, kLdG, r, lvl_ptr(P.PQ, it, tk.d + 1) + o + n1, n, 0);
 }
 
 // --------------------------------------------------- subtree products

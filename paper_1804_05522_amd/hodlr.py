@@ -24,7 +24,8 @@ EXPORTS = [
     "hodlr_toeplitz_matvec", "hodlr_factor", "hodlr_solve", "hodlr_time_steps",
     "fde2d_plan_create", "fde2d_plan_destroy", "fde2d_plan_shifts", "fde2d_sylvester_step",
     "hodlr_ctx_set_timing", "hodlr_ctx_timing_count", "hodlr_ctx_timing_entry", "hodlr_ctx_timing_reset",
-    "fde2d_sylvester_step_guess", "fde2d_field_from_lr", "fde2d_compress_field",
+    "fde2d_sylvester_step_guess", "fde2d_field_from_lr", "fde2d_compress_field", "hodlr_autotune",
+    "hodlr_set_tuning",
     "fde_net_param_count", "fde_net_create", "fde_net_destroy", "fde_net_set_params", "fde_net_get_params",
     "fde_net_get_grads", "fde_net_forward", "fde_net_train_step",
 ]
@@ -52,6 +53,11 @@ class HodlrMatInfo(C.Structure):
                 ("bytes_factors", C.c_size_t), ("bytes_device", C.c_size_t),
                 ("factor_flops", C.c_double), ("core_flops", C.c_double), ("gram_flops", C.c_double),
                 ("leaf_flops", C.c_double)]
+
+
+class HodlrTuning(C.Structure):
+    _fields_ = [("core_threads", C.c_int), ("leaf_threads", C.c_int), ("gram_rows", C.c_int),
+                ("fuse_rows", C.c_int), ("factor_ms", C.c_double)]
 
 
 class LrMatrix(C.Structure):
@@ -90,6 +96,8 @@ def lib():
         L.hodlr_factor.argtypes = [vp, vp, C.POINTER(HodlrInfo)]
         L.hodlr_solve.argtypes = [vp, vp, vp, i32, i64, C.POINTER(HodlrInfo)]
         L.hodlr_time_steps.argtypes = [vp, vp, vp, vp, dbl, i32, C.POINTER(HodlrInfo)]
+        L.hodlr_autotune.argtypes = [vp, vp, C.POINTER(HodlrTuning)]
+        L.hodlr_set_tuning.argtypes = [vp, vp, C.POINTER(HodlrTuning)]
         L.hodlr_ctx_set_timing.argtypes = [vp, i32]
         L.hodlr_ctx_timing_count.argtypes = [vp]
         L.hodlr_ctx_timing_entry.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(i64), C.POINTER(dbl)]
@@ -219,6 +227,18 @@ class HodlrMatrix:
         info = HodlrInfo()
         check(lib().hodlr_factor(self.ctx.h, self.h, C.byref(info)), "hodlr_factor", self.ctx.h, allow)
         return info
+
+    def autotune(self) -> "HodlrTuning":
+        """Pick the factorisation's launch shapes by timing them on this matrix
+        (also used for later matrices of the same shape); factor afterwards."""
+        t = HodlrTuning()
+        check(lib().hodlr_autotune(self.ctx.h, self.h, C.byref(t)), "hodlr_autotune", self.ctx.h)
+        return t
+
+    def set_tuning(self, core_threads=512, leaf_threads=512, gram_rows=256, fuse_rows=256):
+        """Fix the factorisation's launch shapes (see hodlr_set_tuning)."""
+        t = HodlrTuning(core_threads, leaf_threads, gram_rows, fuse_rows, 0.0)
+        check(lib().hodlr_set_tuning(self.ctx.h, self.h, C.byref(t)), "hodlr_set_tuning", self.ctx.h)
 
     def matvec(self, x, y, nrhs=1, ld=None):
         ld = self.total_n if ld is None else ld

@@ -60,7 +60,7 @@ def test_host_only_entry_points(lib_path):
     assert lib.hodlr_default_opts(None) != 0
 
 
-STRUCTS = ["fde_operator", "hodlr_opts", "hodlr_info", "hodlr_mat_info", "lr_matrix", "fde2d_opts"]
+STRUCTS = ["fde_operator", "hodlr_opts", "hodlr_info", "hodlr_mat_info", "lr_matrix", "fde2d_opts", "hodlr_tuning"]
 
 
 def test_struct_layout_matches_c(tmp_path):
@@ -73,6 +73,7 @@ def test_struct_layout_matches_c(tmp_path):
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     sizes = dict(l.split() for l in out if l)
     py = {"fde_operator": hodlr.FdeOperator, "hodlr_opts": hodlr.HodlrOpts, "hodlr_info": hodlr.HodlrInfo,
-          "hodlr_mat_info": hodlr.HodlrMatInfo, "lr_matrix": hodlr.LrMatrix, "fde2d_opts": hodlr.Fde2dOpts}
+          "hodlr_mat_info": hodlr.HodlrMatInfo, "lr_matrix": hodlr.LrMatrix, "fde2d_opts": hodlr.Fde2dOpts,
+          "hodlr_tuning": hodlr.HodlrTuning}
     for s in STRUCTS:
         assert int(sizes[s]) == ctypes.sizeof(py[s]), s

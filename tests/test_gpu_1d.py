@@ -216,3 +216,56 @@ def test_ragged_batch_time_steps(H, ctx):
         err = np.linalg.norm(u[off:off + p.n] - ref) / np.linalg.norm(ref)
         assert err <= 1e-9, (p.name, err)
         off += p.n
+
+
+def test_autotune_then_factor(H, ctx):
+    """The autotuner picks launch shapes from its candidate set and the
+    factorisation with them solves as accurately as with the defaults (two
+    FP64 refinement sweeps with the exact residual, as for the other cases whose
+    condition number exceeds about 1e4)."""
+    p = var_problem(3000, 1.5, dt=1 / 64)
+    b = np.cos(4 * p.x) + p.x
+    A = build(H, ctx, [p, p], tol=1e-10, refine_max=2, rtol=1e-12)
+    t = A.autotune()
+    assert t.core_threads in (256, 512) and t.leaf_threads in (256, 512) and t.gram_rows in (128, 256, 512)
+    assert t.fuse_rows in (0, 128, 256, 512, 1024)
+    assert t.factor_ms > 0
+    A.factor()
+    x = dev(np.concatenate([b, b]))
+    A.solve(x, allow=(0, 2))
+    ref = O.DenseSolver(1.5, p.n, p.nu, p.d_plus, p.d_minus).solve(b)
+    xs = x.cpu().numpy()
+    for k in range(2):
+        assert np.linalg.norm(xs[k * p.n:(k + 1) * p.n] - ref) / np.linalg.norm(ref) <= 1e-9
+    B = build(H, ctx, [p, p], tol=1e-10, refine_max=2, rtol=1e-12)      # same tree signature: tuned shapes reused
+    B.factor()
+    y = dev(np.concatenate([b, b]))
+    B.solve(y, allow=(0, 2))
+    assert np.linalg.norm(y.cpu().numpy() - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+def test_fused_and_split_node_steps_agree(H, ctx):
+    """Phase A of a node as fused single-work-group kernels (Grams, core and
+    forms in one launch) and as the split multi-work-group kernels compute the
+    same factors up to the rounding order of the Gram sums; a ragged batch
+    exercises both kinds of step in one schedule."""
+    probs = [var_problem(3000, 1.3, dt=1 / 64), var_problem(1700, 1.6, dt=1 / 64)]
+    rng = np.random.default_rng(5)
+    bs = [np.sin(3 * p.x) + 0.1 * rng.standard_normal(p.n) for p in probs]
+    refs = [O.DenseSolver(p.alpha, p.n, p.nu, p.d_plus, p.d_minus).solve(b) for p, b in zip(probs, bs)]
+    sols = []
+    for fuse in (0, 1024, 256):
+        A = build(H, ctx, probs, tol=1e-10, refine_max=2, rtol=1e-12)
+        A.set_tuning(fuse_rows=fuse)
+        A.factor()
+        x = dev(np.concatenate(bs))
+        A.solve(x, allow=(0, 2))
+        xs = x.cpu().numpy()
+        sols.append(xs)
+        off = 0
+        for p, ref in zip(probs, refs):
+            err = np.linalg.norm(xs[off:off + p.n] - ref) / np.linalg.norm(ref)
+            assert err <= 1e-9, (fuse, p.n, err)
+            off += p.n
+    for s in sols[1:]:
+        assert np.linalg.norm(s - sols[0]) <= 1e-9 * np.linalg.norm(sols[0])
