@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 MI355X_HBM = 8.0e12           # bytes/s
 MI355X_FP64 = 78.6e12         # flop/s, vector and matrix
+PMC_SWEEPS = {"fp64": 3, "fp32": 3, "bf16": 4}   # refinement sweeps per step of the counter runs (as calibrated)
 
 
 def parse():
@@ -44,6 +45,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--target", type=float, default=1e-10)
+    ap.add_argument("--pmc-job", action="store_true",
+                    help="for hardware-counter runs: one job of the workload with 8 time steps at the "
+                         "calibrated sweep count, then a plain 256 MiB device-to-device copy (the counters' "
+                         "calibration), and exit")
     return ap.parse_args()
 
 
@@ -73,7 +78,7 @@ def main():
     dt = probs[0].dt
     K = args.euler_steps
 
-    def job(prec, sweeps, timing=None):
+    def job(prec, sweeps, timing=None, steps=None):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
         A = H.HodlrMatrix(ctx, ops, H.default_opts(tol=1e-10, prec=prec, refine_max=sweeps, rtol=args.target))
@@ -81,12 +86,25 @@ def main():
         A.factor(allow=(0, 3))
         ev[2].record(stream)
         u = u0.clone()
-        info = A.time_steps(u, f, dt, K, allow=(0, 2))
+        info = A.time_steps(u, f, dt, K if steps is None else steps, allow=(0, 2))
         ev[3].record(stream)
         if timing is not None:
             stream.synchronize()
             timing.append([ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])])
         return A, u, info
+
+    if args.pmc_job:
+        A, u, info = job(args.prec, PMC_SWEEPS[args.prec], steps=8)
+        A.close()
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        stream.synchronize()
+        dst.copy_(src)
+        stream.synchronize()
+        print(json.dumps({"pmc_job": args.prec, "sweeps": PMC_SWEEPS[args.prec], "copy_bytes": nbytes,
+                          "rel_correction_last": info.rel_correction}), flush=True)
+        return
 
     # launch shapes of the factorisation, tuned once on this workload's tree
     # (untimed; later matrices of the same shape use them)
@@ -219,13 +237,16 @@ def roofline(res, total_n, prec):
                    algorithmic=f"{per_launch:.3e} flop per launch (flop model of this kernel's share of the "
                                f"HODLR LU at the final ranks, {flop_kernels[name]:.3e} flop over {launches} launches)")
     elif name in ("(k_expand1<TF, TL>)", "(k_project1<TF>)") and solves:
+        traffic = measured_traffic(name, prec)
         if name == "(k_project1<TF>)":
             per_launch = off_bytes / 4 + 8.0 * total_n
         else:
             per_launch = (0.75 * off_bytes + leaf_bytes) / 2 + 16.0 * total_n
         achieved = per_launch / avg_s
         out.update(bound="hbm", achieved=achieved / 1e9, peak=MI355X_HBM / 1e9, unit="GB/s",
-                   frac=achieved / MI355X_HBM, traffic=None,
+                   frac=achieved / MI355X_HBM, traffic=traffic,
+                   traffic_unit="HBM bytes per launch (counters scaled by a plain copy)",
+                   traffic_over_algorithmic=traffic / per_launch if traffic else None,
                    algorithmic=f"{per_launch:.3e} bytes per launch (factor values read once per solve at "
                                f"{vsize}-byte storage, {mi.bytes_factors:.3e} bytes a solve, plus vectors)")
     else:
@@ -233,6 +254,29 @@ def roofline(res, total_n, prec):
                    algorithmic="no algorithmic model for this kernel")
     out["top_kernels_ms"] = {k: round(v[1], 3) for k, v in sorted(ks.items(), key=lambda kv: -kv[1][1])[:8]}
     return out
+
+
+def measured_traffic(name, prec):
+    """HBM bytes per launch of the kernel from the hardware-counter summary in
+    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    there is none for this kernel and precision or the kernel's source has
+    changed since the counters were taken."""
+    import hashlib
+    if name != "(k_expand1<TF, TL>)" or prec != "fp32":
+        return None
+    path = os.path.join(ROOT, "profiles", "k_expand1_var_1d_n65536_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.split("(")[0].strip() if k.strip() == "kernel" else (v.split() or [""])[0]
+    src = os.path.join(ROOT, "paper_1804_05522_amd", "csrc", "solve.hip")
+    if fields.get("kernel") != "k_expand1<float, float>" or \
+            hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(args, probs):
