@@ -212,9 +212,11 @@ def main():
 def roofline(res, total_n, prec):
     """Roofline of the kernel with the largest summed duration in the
     instrumented job.  Algorithmic work per launch:
-      factorisation kernels (FP64 ALU): the flop model of the factorisation,
-        split by kernel (recompression cores, Gram matrices, leaves), over the
-        kernel's launches;
+      factorisation kernels (FP64; the cores and leaves on the vector ALU, the
+        Grams and forms on the FP64 matrix cores, both with the same 78.6
+        TFLOP/s peak): the flop model of the factorisation, split by kernel
+        (fused node kernels, split recompression cores, Gram matrices,
+        leaves), over the kernel's launches;
       single right-hand-side solve kernels (HBM): every factor value is read
         once per solve; the projection reads a quarter of the off-diagonal
         factors, the two expansions the rest and the leaf inverses, plus the
@@ -226,7 +228,8 @@ def roofline(res, total_n, prec):
     leaf_bytes = 64 * total_n * vsize
     off_bytes = max(mi.bytes_factors - leaf_bytes, 0)
     solves = ks.get("(k_project1<TF>)", (0, 0))[0]
-    flop_kernels = {"k_core": mi.core_flops, "k_gram_partial": mi.gram_flops, "k_leaf_task": mi.leaf_flops}
+    flop_kernels = {"k_core": mi.core_flops, "k_gram_partial": mi.gram_flops, "k_leaf_task": mi.leaf_flops,
+                    "k_node_recompress": mi.node_rec_flops, "k_node_pending": mi.node_pend_flops}
     out = {"kernel": name, "launches": launches, "launch_us": 1e6 * avg_s}
     if name in flop_kernels:
         factorisations = 1

@@ -61,7 +61,7 @@ typedef struct fde2d_plan_s* fde2d_plan;
  * shift = 1/2 (+ an ADI shift) for the coefficients of the 2D Sylvester
  * step (eq. (sylv-timestepping)). */
 typedef struct {
-  int64_t n;              /* interior grid points N >= 1 (eq. (part)) */
+  int64_t n;              /* interior grid points, 1 <= N <= 2^23 (eq. (part)) */
   double alpha;           /* fractional order, 1 <= alpha <= 2 */
   double dt, dx;          /* time step and grid spacing; nu = dt/dx^alpha */
   double shift;           /* identity shift s > 0 */
@@ -100,9 +100,12 @@ typedef struct {
   size_t bytes_factors;   /* bytes read by one single-RHS solve at the chosen precision */
   size_t bytes_device;    /* device memory held by the handle */
   double factor_flops;    /* algorithmic FP64 flops of hodlr_factor (model from the final ranks) */
-  double core_flops;      /* part of factor_flops in the small recompression cores (k x k Gram work) */
-  double gram_flops;      /* part of factor_flops in forming Gram matrices of tall factors */
+  double core_flops;      /* part of factor_flops in the small recompression cores (k x k Gram work) of
+                             the nodes factored by the split kernels */
+  double gram_flops;      /* part of factor_flops in forming Gram matrices of tall factors (split kernels) */
   double leaf_flops;      /* part of factor_flops in the dense leaves (update, LU, inverses) */
+  double node_rec_flops;  /* part in the fused node kernels' first launch (Grams, cores, forms of S12, S21) */
+  double node_pend_flops; /* part in the fused node kernels' last launch (C, W, pending recompression) */
 } hodlr_mat_info;
 
 /* ---- context ------------------------------------------------------------ */

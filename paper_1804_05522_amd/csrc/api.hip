@@ -186,6 +186,7 @@ struct hodlr_mat_s {
   int leaf_threads = 512;
   int gram_rows = kGramRows;
   int fuse_rows = kFuseRows;                 // phase A of nodes with children up to this many rows: fused kernels
+  int fuse_used = kFuseRows;                 // the threshold the current schedule was planned with
   std::vector<int> mwg_kind;                 // launch kind per record
   std::vector<int> mwg_grid;                 // grid size
   std::vector<int64_t> mwg_off;              // offset into the unit array of its kind
@@ -352,7 +353,7 @@ void launch_solve_t(hodlr_mat m, SolveFactors<TF, TL> F, const WorkUnit* wu, int
     HFDE_LAUNCH((k_expand1<TF, TL>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, F, wu, 0, x, m->ytmp, m->zL,
                        m->partU, lv, m->b);
     if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 1, 1, m->partU, m->zU, lv);
-    HFDE_LAUNCH((k_expand1<TF, TL>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, F, wu, 1, m->ytmp, y, m->zU,
+    HFDE_LAUNCH((k_expand1<TF, TL>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 1, m->ytmp, y, m->zU,
                        (double*)nullptr, lv, m->b);
     (void)ldx;
     (void)ldy;
@@ -466,6 +467,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   size_t steps = 0;
   for (auto& e : evs) steps = std::max(steps, e.size());
   const int fuse_rows = env_int("HODLR_FUSE_ROWS", m->fuse_rows);
+  m->fuse_used = fuse_rows;
   struct TaskSpec { int item, d; int64_t j; int64_t n1, n2; };
   auto add_tasks = [&](const std::vector<TaskSpec>& ts) {
     const int64_t t0 = int64_t(tasks.size());
@@ -800,7 +802,9 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   if (opts->prec < HODLR_FP64 || opts->prec > HODLR_MIXED_BF16) return set_arg(ctx, 4);
   for (int i = 0; i < batch; ++i) {
     const fde_operator& o = ops[i];
-    if (o.n < 1 || o.n > (int64_t(1) << 30) || !(o.alpha >= 1.0 && o.alpha <= 2.0) || !(o.dt > 0.0) ||
+    // the solve kernels address a level's factor block (n x 32 values) with
+    // 32-bit byte offsets
+    if (o.n < 1 || o.n > (int64_t(1) << 23) || !(o.alpha >= 1.0 && o.alpha <= 2.0) || !(o.dt > 0.0) ||
         !(o.dx > 0.0) || !(o.shift > 0.0) || !o.d_plus || !o.d_minus)
       return set_arg(ctx, 2);
   }
@@ -858,7 +862,8 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
     for (int64_t l = 0; l < (int64_t(1) << it.L); ++l) {
       const Node nd = m->nodes[node_index(it, it.L, l)];
       for (int32_t r = 0; r < nd.size; ++r) rowleaf[it.row0 + nd.start + r] = int32_t(l);
-      m->wu_h.push_back(WorkUnit{i, int32_t(l)});
+      m->wu_h.push_back(WorkUnit{i, int32_t(l), nd.start, nd.size, it.row0, it.lvl0, it.n, it.leaf0 + l, it.node0,
+                                 it.L, 0});
     }
     for (int d = 0; d < it.L; ++d)
       for (int64_t j = 0; j < (int64_t(1) << d); ++j) m->nu_h.push_back(NodeUnit{i, d, int32_t(j), 0});
@@ -1024,6 +1029,8 @@ struct FlopSplit {
                         // two pivoted Cholesky ~2 R^3, K ~2 R^3, QRCP ~4 R^2 r, Q 4 R r^2, M_U, M_V ~R r^2 + 2 R^2 r
   double gram = 0.0;    // Gram matrices (k_gram_partial): 2 rows x cols x cols each
   double leaf = 0.0;    // leaves (k_leaf_task): pending update, LU, both inverses
+  double node_rec = 0.0;   // fused phase A, first part (k_node_recompress): Grams, cores, forms of S12, S21
+  double node_pend = 0.0;  // fused phase A, last part (k_node_pending): C, W, pending Grams, core, forms
 };
 
 static FlopSplit factor_flop_split(hodlr_mat m);
@@ -1062,8 +1069,15 @@ static FlopSplit factor_flop_split(hodlr_mat m) {
         const double n1 = double(nd.size / 2), n2 = n - n1;
         const double r = it.r, R = r + pr, r12 = ru[ni], r21 = rl[ni];
         auto core = [](double Rc, double rc) { return 4.0 * Rc * Rc * Rc + 6.0 * Rc * Rc * rc + 5.0 * Rc * rc * rc; };
-        out.core += core(R, r12) + core(R, r21) + core(pr + r12, rp[node_index(it, d + 1, 2 * j + 1)]);
-        out.gram += 4.0 * n * R * R + 2.0 * n1 * r21 * r12 + 4.0 * n2 * (pr + r12) * (pr + r12);
+        const double rpc = rp[node_index(it, d + 1, 2 * j + 1)], Rp = pr + r12;
+        if (std::max(n1, n2) <= double(m->fuse_used)) {
+          out.node_rec += core(R, r12) + core(R, r21) + 4.0 * n * R * R + 2.0 * n * R * (r12 + r21);
+          out.node_pend += 2.0 * n1 * r21 * r12 + 2.0 * n2 * r21 * r12 + core(Rp, rpc) + 4.0 * n2 * Rp * Rp +
+                           4.0 * n2 * Rp * rpc;
+        } else {
+          out.core += core(R, r12) + core(R, r21) + core(Rp, rpc);
+          out.gram += 4.0 * n * R * R + 2.0 * n1 * r21 * r12 + 4.0 * n2 * Rp * Rp;
+        }
         fl += 2 * (2.0 * n * R * R) + 2.0 * n * R * (r12 + r21);              // S12, S21 recompression
         fl += 2.0 * n2 * (pr + r12) * (pr + r12) * 2 + 2.0 * n2 * (pr + r12) * r12;  // pending recompression
         fl += 2.0 * n1 * r12 * r21 + 2.0 * n2 * r21 * r12;                      // C and W
@@ -1112,6 +1126,8 @@ hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info) {
   info->core_flops = fs.core;
   info->gram_flops = fs.gram;
   info->leaf_flops = fs.leaf;
+  info->node_rec_flops = fs.node_rec;
+  info->node_pend_flops = fs.node_pend;
   return HODLR_OK;
 }
 

@@ -87,9 +87,18 @@ struct DevPtrs {
 };
 
 // Work lists of the multi-work-group kernels.
-struct WorkUnit {          // one leaf of one problem
+struct WorkUnit {          // one leaf of one problem, with the geometry the solve kernels read
   int32_t item;
-  int32_t leaf;
+  int32_t leaf;            // leaf index within the problem
+  int32_t start;           // first row of the leaf within the problem
+  int32_t size;            // rows of the leaf
+  int64_t row0;            // the problem's first row in concatenated vectors
+  int64_t lvl0;            // the problem's per-level factor offset (Item.lvl0)
+  int64_t n;               // rows of the problem
+  int64_t gl;              // global leaf index (Item.leaf0 + leaf)
+  int64_t node0;           // the problem's first node (Item.node0)
+  int32_t L;               // split levels of the problem
+  int32_t pad;
 };
 struct NodeUnit {          // one internal node of one problem
   int32_t item;

@@ -214,51 +214,77 @@ __global__ void __launch_bounds__(256) k_expand(DevPtrs P, SolveFactors<TF, TL> 
 
 // ------------------------------------------------ single right-hand side
 // The time-step solves carry one right-hand side.  There each lane owns one
-// row of the leaf, so every basis load is coalesced across the wave and all
-// ranks of a level are loaded at once; the row products are summed across
-// the leaf by a transpose through LDS (stride 65: conflict-free), with four
-// partial sums combined in a fixed order.  Levels are dealt round-robin to the
-// four waves of the work-group.
+// row of the leaf, so every basis load is coalesced across the wave.  The
+// kernels are built to have few dependent memory round trips per
+// work-group: the leaf's geometry comes with its work unit, the ranks of all
+// levels arrive in one load (one level per lane), and the basis columns and
+// leaf-inverse entries are fetched through buffer loads whose range check
+// returns zero without a memory access, so a wave issues every load of a
+// level (or of the leaf block) at once and fetches only columns below the
+// rank and the triangle of the leaf inverse that the product uses.  Row
+// products are summed across the leaf by a transpose through LDS (stride 65:
+// conflict-free) in two halves of 16 columns, with four partial sums combined
+// in a fixed order.  Levels are dealt round-robin to the waves.
 constexpr int kP1Ld = 65;
-constexpr size_t kSolve1Lds = size_t(4) * kRS * kP1Ld * sizeof(double);
+constexpr int kP1Cols = 16;                    // columns per transpose pass
+constexpr size_t kSolve1Lds = size_t(4) * kP1Cols * kP1Ld * sizeof(double);
+constexpr int kOob = 0x7ffffff0;               // byte offset past every buffer: loads return 0
 
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                           int(min<int64_t>(bytes, int64_t(0x7fffffff))), 0x00020000);
+}
+__device__ inline float bload(__amdgpu_buffer_rsrc_t r, int off, const float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline double bload(__amdgpu_buffer_rsrc_t r, int off, const double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline bf16 bload(__amdgpu_buffer_rsrc_t r, int off, const bf16*) {
+  return bf16{__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)};
+}
+
+// rank of the ancestor at depth `lane` of the work unit's leaf (0 for lanes >= L)
+__device__ inline int level_ranks(const int32_t* ranks, const WorkUnit& w, int lane) {
+  return lane < w.L ? ranks[w.node0 + ((int64_t(1) << lane) - 1) + (w.leaf >> (w.L - lane))] : 0;
+}
+
+// Partial projections of y (this lane's row value) onto the basis of every
+// level where the leaf lies in the source child; rk = level_ranks(...).
 template <typename TF>
-__device__ void leaf_project1(const DevPtrs& P, const Item& it, int leaf, const Node& lf, const TF* Bb,
-                              const int32_t* ranks, int src_side, double xv, double* part, int64_t leaves,
-                              double* sm) {
+__device__ void leaf_project1(const WorkUnit& w, const TF* Bb, int rk, int src_side, double yv, double* part,
+                              int64_t leaves, double* sm) {
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int m = lf.size;
-  double* pw = sm + wave * (kRS * kP1Ld);
-  const int64_t gl = it.leaf0 + leaf;
+  const int m = w.size;
+  double* pw = sm + wave * (kP1Cols * kP1Ld);
   int cnt = 0;
-  for (int d = 0; d < it.L; ++d) {
-    const int side = (leaf >> (it.L - d - 1)) & 1;
+  for (int d = 0; d < w.L; ++d) {
+    const int side = (w.leaf >> (w.L - d - 1)) & 1;
     if (side != src_side) continue;
     if ((cnt++ & 3) != wave) continue;
-    const int64_t nidx = node_index(it, d, leaf >> (it.L - d));
-    const int r = ranks[nidx];
-    // columns are loaded in groups of eight up to the rank with no use in
-    // between (all kRS columns are allocated; rows past the leaf read its last
-    // row), so the loads are issued together; the guard is applied after the
-    // conversion
-    const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + min(lane, m - 1);
-    TF raw[kRS] = {};
+    const int r = __builtin_amdgcn_readlane(rk, d);
+    const __amdgpu_buffer_rsrc_t R = buf_rsrc(Bb + w.lvl0 + int64_t(d) * w.n * kRS, w.n * kRS * int64_t(sizeof(TF)));
+    TF raw[kRS];
 #pragma unroll
-    for (int g8 = 0; g8 < kRS / 8; ++g8)      // groups of 8 columns up to the rank (uniform branch)
-      if (8 * g8 < r)
+    for (int q = 0; q < kRS; ++q)
+      raw[q] = bload(R, (q < r && lane < m) ? int((w.start + lane + int64_t(q) * w.n) * sizeof(TF)) : kOob,
+                     (const TF*)nullptr);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) raw[8 * g8 + k] = Bd[int64_t(8 * g8 + k) * it.n];
+    for (int h2 = 0; h2 < kRS / kP1Cols; ++h2) {
+      if (kP1Cols * h2 >= r) break;
 #pragma unroll
-    for (int q = 0; q < kRS; ++q) pw[q * kP1Ld + lane] = (q < r && lane < m) ? cvt(raw[q]) * xv : 0.0;
-    wave_lds_sync();
-    const int q = lane & 31, h = lane >> 5;
-    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < kP1Cols; ++q) pw[q * kP1Ld + lane] = cvt(raw[kP1Cols * h2 + q]) * yv;
+      wave_lds_sync();
+      const int q = lane & (kP1Cols - 1), qq = lane / kP1Cols;     // column, quarter of the rows
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 32; ++k) a4[k & 3] += pw[q * kP1Ld + h * 32 + k];
-    double v = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-    v += __shfl_xor(v, 32);
-    if (h == 0 && q < r) part[(int64_t(d) * leaves + gl) * kRS + q] = v;
-    wave_lds_sync();
+      for (int k = 0; k < 16; ++k) a4[k & 3] += pw[q * kP1Ld + qq * 16 + k];
+      double v = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (qq == 0 && kP1Cols * h2 + q < r) part[(int64_t(d) * leaves + w.gl) * kRS + kP1Cols * h2 + q] = v;
+      wave_lds_sync();
+    }
   }
 }
 
@@ -267,93 +293,87 @@ __global__ void __launch_bounds__(256) k_project1(DevPtrs P, const WorkUnit* wu,
                                                   const double* x, double* part, int64_t leaves) {
   extern __shared__ double sm[];
   const WorkUnit w = wu[blockIdx.x];
-  const Item it = P.items[w.item];
-  const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
   const int lane = threadIdx.x & 63;
-  const double xv = lane < lf.size ? x[it.row0 + lf.start + lane] : 0.0;
-  leaf_project1<TF>(P, it, w.leaf, lf, Bb, which == 0 ? P.rankL : P.rankU, which == 0 ? 0 : 1, xv, part, leaves,
-                    sm);
+  const int rk = level_ranks(which == 0 ? P.rankL : P.rankU, w, lane);
+  const double xv = lane < w.size ? x[w.row0 + w.start + lane] : 0.0;
+  leaf_project1<TF>(w, Bb, rk, which == 0 ? 0 : 1, xv, part, leaves, sm);
 }
 
 // y = F x on one leaf's rows (F = L^{-1} for which = 0, U^{-1} for which = 1):
-// wave 0 applies the leaf block (64 coalesced loads per lane, 16 in flight,
-// four partial sums), waves 1..3 the destination levels round-robin (basis
-// row loads of all ranks at once; z_node broadcast from lane s by readlane).
-// If next_part is set, the rows of y are projected for U^{-1} in the same
-// launch.
+// wave 0 applies the leaf block (only the triangle the product uses is
+// fetched: strictly lower in pivot order for L^{-1}, upper for U^{-1}), waves
+// 1..3 the destination levels round-robin (z_node broadcast from lane s by
+// readlane).  If next_part is set, the rows of y are projected for U^{-1} in
+// the same launch (dynamic LDS kSolve1Lds; none otherwise).
 template <typename TF, typename TL>
 __global__ void __launch_bounds__(256) k_expand1(DevPtrs P, SolveFactors<TF, TL> F, const WorkUnit* wu, int which,
                                                  const double* xin, double* yout, const double* z,
                                                  double* next_part, int64_t leaves, int b) {
   extern __shared__ double sm[];
   __shared__ double vl[64];
+  __shared__ double xp[64];
   __shared__ double yl[4][64];
-  __shared__ int pm[64];
   const WorkUnit w = wu[blockIdx.x];
-  const Item it = P.items[w.item];
-  const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63, row = lane;
-  const int m = lf.size;
-  const int64_t gl = it.leaf0 + w.leaf;
-  if (t < 64) {
-    vl[t] = t < m ? xin[it.row0 + lf.start + t] : 0.0;
-    pm[t] = t < m ? P.perm[gl * b + t] : 0;
-  }
-  __syncthreads();
+  const int m = w.size;
+  // ranks of the next projection, loaded early (used after the expansion)
+  const int rkU = next_part != nullptr ? level_ranks(P.rankU, w, lane) : 0;
   double acc = 0.0;
   if (wave == 0) {
-    const TL* Fi = F.LUinv + gl * int64_t(b) * b + row;
-    double a4[4] = {0.0, 0.0, 0.0, 0.0};
-    if (row < m) {
-      if (which == 0) a4[0] = vl[pm[row]];
-      for (int j0 = 0; j0 < m; j0 += 16) {      // columns j0..j0+15 < b are inside the leaf block
-        TL raw[16];
+    constexpr int kLB = sizeof(TL) == 8 ? 32 : 64;    // leaf columns in flight
+    const __amdgpu_buffer_rsrc_t R = buf_rsrc(F.LUinv + w.gl * int64_t(b) * b, int64_t(b) * b * int64_t(sizeof(TL)));
+    const double xv = row < m ? xin[w.row0 + w.start + row] : 0.0;
+    const int pv = row < m ? P.perm[w.gl * b + row] : 0;
+    vl[row] = xv;
+    wave_lds_sync();
+    xp[row] = which == 0 ? vl[pv] : xv;
+    wave_lds_sync();
+    double a4[4] = {which == 0 && row < m ? xp[row] : 0.0, 0.0, 0.0, 0.0};   // unit diagonal of L^{-1}
+#pragma unroll 1
+    for (int j0 = 0; j0 < 64; j0 += kLB) {
+      TL raw[kLB];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) raw[q] = Fi[(j0 + q) * b];
-        double f[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) f[q] = j0 + q < m ? cvt(raw[q]) : 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int j = j0 + q;
-          const bool use = which == 0 ? (j < row) : (j >= row && j < m);
-          const double xv = which == 0 ? vl[pm[min(j, m - 1)]] : vl[min(j, m - 1)];
-          a4[q & 3] += use ? f[q] * xv : 0.0;
-        }
+      for (int q = 0; q < kLB; ++q) {
+        const int j = j0 + q;
+        const bool use = row < m && j < m && (which == 0 ? j < row : j >= row);
+        raw[q] = bload(R, use ? int((int64_t(j) * b + row) * sizeof(TL)) : kOob, (const TL*)nullptr);
       }
+#pragma unroll
+      for (int q = 0; q < kLB; ++q) a4[q & 3] += cvt(raw[q]) * xp[j0 + q];
     }
     acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   } else {
     const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
+    const int rk = level_ranks(ranks, w, lane);
     const TF* Bb = which == 0 ? F.IL : F.IU;
     const int dst_side = which == 0 ? 1 : 0;
     double a4[4] = {0.0, 0.0, 0.0, 0.0};
     int cnt = 0;
-    for (int d = 0; d < it.L; ++d) {
-      const int side = (w.leaf >> (it.L - d - 1)) & 1;
+    for (int d = 0; d < w.L; ++d) {
+      const int side = (w.leaf >> (w.L - d - 1)) & 1;
       if (side != dst_side) continue;
       if ((cnt++ % 3) != wave - 1) continue;
-      const int64_t nidx = node_index(it, d, w.leaf >> (it.L - d));
-      const int r = ranks[nidx];
-      const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + min(row, m - 1);
-      const double zs = lane < r ? z[nidx * int64_t(kRS) + lane] : 0.0;
-      TF raw[kRS] = {};
+      const int64_t nidx = w.node0 + ((int64_t(1) << d) - 1) + (w.leaf >> (w.L - d));
+      const int r = __builtin_amdgcn_readlane(rk, d);
+      const double zl = lane < kRS ? z[nidx * int64_t(kRS) + lane] : 0.0;
+      const double zs = lane < r ? zl : 0.0;
+      const __amdgpu_buffer_rsrc_t R =
+          buf_rsrc(Bb + w.lvl0 + int64_t(d) * w.n * kRS, w.n * kRS * int64_t(sizeof(TF)));
+      TF raw[kRS];
 #pragma unroll
-      for (int g8 = 0; g8 < kRS / 8; ++g8)
-        if (8 * g8 < r)
+      for (int q = 0; q < kRS; ++q)
+        raw[q] = bload(R, (q < r && row < m) ? int((w.start + row + int64_t(q) * w.n) * sizeof(TF)) : kOob,
+                       (const TF*)nullptr);
 #pragma unroll
-          for (int k = 0; k < 8; ++k) raw[8 * g8 + k] = Bd[int64_t(8 * g8 + k) * it.n];
-#pragma unroll
-      for (int q = 0; q < kRS; ++q) a4[q & 3] += (q < r && row < m) ? cvt(raw[q]) * readlane_d(zs, q) : 0.0;
+      for (int q = 0; q < kRS; ++q) a4[q & 3] += cvt(raw[q]) * readlane_d(zs, q);
     }
     acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   }
   yl[wave][row] = acc;
   __syncthreads();
   const double y = (yl[0][row] + yl[1][row]) + (yl[2][row] + yl[3][row]);
-  if (wave == 0 && row < m) yout[it.row0 + lf.start + row] = y;
-  if (next_part != nullptr)
-    leaf_project1<TF>(P, it, w.leaf, lf, F.IU, P.rankU, 1, row < m ? y : 0.0, next_part, leaves, sm);
+  if (wave == 0 && row < m) yout[w.row0 + w.start + row] = y;
+  if (next_part != nullptr) leaf_project1<TF>(w, F.IU, rkU, 1, row < m ? y : 0.0, next_part, leaves, sm);
 }
 
 // ---------------------------------------------------------------- helpers
