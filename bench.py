@@ -231,16 +231,17 @@ def roofline(res, total_n, prec):
     flop_kernels = {"k_core": mi.core_flops, "k_gram_partial": mi.gram_flops, "k_leaf_task": mi.leaf_flops,
                     "k_node_recompress": mi.node_rec_flops, "k_node_pending": mi.node_pend_flops}
     out = {"kernel": name, "launches": launches, "launch_us": 1e6 * avg_s}
+    traffic = measured_traffic(name, prec)
     if name in flop_kernels:
         factorisations = 1
         per_launch = flop_kernels[name] / max(launches / factorisations, 1)
         achieved = per_launch / avg_s
         out.update(bound="alu", achieved=achieved / 1e12, peak=MI355X_FP64 / 1e12, unit="TFLOP/s",
-                   frac=achieved / MI355X_FP64, traffic=None,
+                   frac=achieved / MI355X_FP64, traffic=traffic,
+                   traffic_unit="HBM bytes per launch (counters scaled by a plain copy)",
                    algorithmic=f"{per_launch:.3e} flop per launch (flop model of this kernel's share of the "
                                f"HODLR LU at the final ranks, {flop_kernels[name]:.3e} flop over {launches} launches)")
     elif name in ("(k_expand1<TF, TL>)", "(k_project1<TF>)") and solves:
-        traffic = measured_traffic(name, prec)
         if name == "(k_project1<TF>)":
             per_launch = off_bytes / 4 + 8.0 * total_n
         else:
@@ -259,15 +260,35 @@ def roofline(res, total_n, prec):
     return out
 
 
+# kernel (as the timing facility names it) -> (counter summary in profiles/, the
+# kernel name recorded there, the sources whose SHA-256 it was measured with)
+TRAFFIC = {
+    "(k_expand1<TF, TL>)": ("k_expand1_var_1d_n65536_traffic.txt", "k_expand1<float, float>",
+                            ["solve.hip", "internal.hpp"]),
+    "k_node_recompress": ("k_node_recompress_var_1d_n65536_traffic.txt", "k_node_recompress",
+                          ["factor_mwg.hip", "factor.hip", "internal.hpp"]),
+    "k_node_pending": ("k_node_pending_var_1d_n65536_traffic.txt", "k_node_pending",
+                       ["factor_mwg.hip", "factor.hip", "internal.hpp"]),
+}
+
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_1804_05522_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(name, prec):
     """HBM bytes per launch of the kernel from the hardware-counter summary in
     profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
-    there is none for this kernel and precision or the kernel's source has
+    there is none for this kernel at FP32 factors or the kernel's sources have
     changed since the counters were taken."""
-    import hashlib
-    if name != "(k_expand1<TF, TL>)" or prec != "fp32":
+    if name not in TRAFFIC or prec != "fp32":
         return None
-    path = os.path.join(ROOT, "profiles", "k_expand1_var_1d_n65536_traffic.txt")
+    fname, kname, files = TRAFFIC[name]
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     fields = {}
@@ -275,9 +296,7 @@ def measured_traffic(name, prec):
         if ":" in line and not line.startswith(" "):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.split("(")[0].strip() if k.strip() == "kernel" else (v.split() or [""])[0]
-    src = os.path.join(ROOT, "paper_1804_05522_amd", "csrc", "solve.hip")
-    if fields.get("kernel") != "k_expand1<float, float>" or \
-            hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+    if fields.get("kernel") != kname or source_hash(files) != fields.get("source_sha256"):
         return None
     return float(fields["traffic_bytes_per_launch"])
 
