@@ -142,6 +142,19 @@ hodlr_status hodlr_default_opts(hodlr_opts* opts);
  * The operators are copied; the caller may free d+/d- after the call.   */
 hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch,
                          const hodlr_opts* opts, hodlr_mat* out);
+
+/* Time-dependent coefficients d+(x, t), d-(x, t) (the paper assumes them
+ * constant in time, Sec. 2.2.1, which lets one LU serve every step; with
+ * coefficients that change, the matrix of eq. (system_FD) changes every
+ * step).  Replaces the d+/d- samples of every problem of m by those of ops
+ * (host array of m's batch size; n, alpha, dt, dx and shift must equal the
+ * values m was built with, else HODLR_EINVAL with argument 3) and rebuilds
+ * the compressed operator in place: truncation tolerances from the new
+ * coefficients, the Hankel compression and the assembly of all blocks and
+ * leaves.  The weights, the exact-residual tables, the tree and the
+ * factorisation schedule are kept.  m must be factored again before it is
+ * solved with (HODLR_ESTATE otherwise). */
+hodlr_status hodlr_update_coefficients(hodlr_ctx ctx, hodlr_mat m, const fde_operator* ops);
 void hodlr_destroy(hodlr_mat m);
 hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info);
 

@@ -196,6 +196,19 @@ def euler_1d(prob, steps=None, refine=3, keep_all=False):
     return (u, out) if keep_all else u
 
 
+def euler_1d_varying(prob, coef, steps=None, refine=3):
+    """Implicit Euler with coefficients that change in time: at step m the
+    matrix of eq. (system_FD) is built from d+(x, t_m), d-(x, t_m) (the new
+    time level, t_m = m dt), so every step has its own dense LU:
+    u^(m) = M(t_m)^{-1}(u^(m-1) + dt f).  coef(t) -> (d_plus, d_minus)."""
+    steps = prob.steps if steps is None else steps
+    u = prob.u0.copy()
+    for m in range(1, steps + 1):
+        dp, dm = coef(m * prob.dt)
+        u = DenseSolver(prob.alpha, prob.n, prob.nu, dp, dm, 1.0, refine).solve(u + prob.dt * prob.f)
+    return u
+
+
 # --------------------------------------------------------------------------
 # Manufactured solution (eq. (frac-der) closed forms)
 # --------------------------------------------------------------------------

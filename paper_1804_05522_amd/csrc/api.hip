@@ -1015,6 +1015,48 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   return HODLR_OK;
 }
 
+hodlr_status hodlr_update_coefficients(hodlr_ctx ctx, hodlr_mat m, const fde_operator* ops) {
+  if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
+  if (!m) return set_arg(ctx, 2);
+  if (!ops) return set_arg(ctx, 3);
+  for (int i = 0; i < m->batch; ++i) {
+    const fde_operator& o = ops[i];
+    const Item& it = m->items[i];
+    const double nu = (o.dt > 0.0 && o.dx > 0.0) ? o.dt / std::pow(o.dx, o.alpha) : -1.0;
+    if (o.n != it.n || o.alpha != it.alpha || o.shift != it.shift || !(std::fabs(nu - it.nu) <= 1e-14 * it.nu) ||
+        !o.d_plus || !o.d_minus)
+      return set_arg(ctx, 3);
+  }
+  hipStream_t s = ctx->stream;
+  DevPtrs& P = m->P;
+  const int batch = m->batch;
+  for (int i = 0; i < batch; ++i) {
+    const Item& it = m->items[i];
+    HIP_TRY(hipMemcpyAsync(P.dplus + it.row0, ops[i].d_plus, it.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(P.dminus + it.row0, ops[i].d_minus, it.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipMemsetAsync(P.status, 0, batch * sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P.diag, 0, 4 * batch * sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P.rankL, 0, m->total_nodes * sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P.rankU, 0, m->total_nodes * sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P.rankP, 0, m->total_nodes * sizeof(int32_t), s));
+  HFDE_LAUNCH(k_hankel_aca, dim3(batch), dim3(512), 0, s, P, m->opts.tol);
+  for (int i = 0; i < batch; ++i) {
+    const Item& it = m->items[i];
+    if (it.L > 0)
+      HFDE_LAUNCH(k_assemble_bases, dim3(unsigned((it.n + 255) / 256), it.L), dim3(256), 0, s, P, i);
+    HFDE_LAUNCH(k_assemble_leaves, dim3(unsigned(int64_t(1) << it.L)), dim3(256), 0, s, P, i, m->b);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(m->items.data(), P.items, batch * sizeof(Item), hipMemcpyDeviceToHost));
+  m->max_rank_A = 0;
+  for (const Item& it : m->items) m->max_rank_A = std::max(m->max_rank_A, it.r);
+  m->factored = false;
+  return HODLR_OK;
+}
+
 // Algorithmic FP64 flops of the factorisation of Sec. 3.5 as carried out
 // (ranks read back from the device): per internal node the two
 // recompressions of the off-diagonal Schur blocks and the one of the pending

@@ -428,7 +428,7 @@ __global__ void k_convert<bf16>(const double* src, bf16* dst, int64_t count) {
 }
 
 // y = M_H x for the compressed operator itself (leaves dense + off-diagonal
-// blocks of every level), one leaf per work unit; used to check the build.
+// blocks of every level), one leaf per work unit; used to check the compression.
 __global__ void __launch_bounds__(64) k_hmatvec_A_project(DevPtrs P, const WorkUnit* wu, const double* x,
                                                           int64_t ldx, int nc, double* part, int Lmax) {
   // partial projections for both the lower (src c1, basis XR) and upper

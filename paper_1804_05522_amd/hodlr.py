@@ -25,7 +25,7 @@ EXPORTS = [
     "fde2d_plan_create", "fde2d_plan_destroy", "fde2d_plan_shifts", "fde2d_sylvester_step",
     "hodlr_ctx_set_timing", "hodlr_ctx_timing_count", "hodlr_ctx_timing_entry", "hodlr_ctx_timing_reset",
     "fde2d_sylvester_step_guess", "fde2d_field_from_lr", "fde2d_compress_field", "hodlr_autotune",
-    "hodlr_set_tuning",
+    "hodlr_set_tuning", "hodlr_update_coefficients",
     "fde_net_param_count", "fde_net_create", "fde_net_destroy", "fde_net_set_params", "fde_net_get_params",
     "fde_net_get_grads", "fde_net_forward", "fde_net_train_step",
 ]
@@ -98,6 +98,7 @@ def lib():
         L.hodlr_time_steps.argtypes = [vp, vp, vp, vp, dbl, i32, C.POINTER(HodlrInfo)]
         L.hodlr_autotune.argtypes = [vp, vp, C.POINTER(HodlrTuning)]
         L.hodlr_set_tuning.argtypes = [vp, vp, C.POINTER(HodlrTuning)]
+        L.hodlr_update_coefficients.argtypes = [vp, vp, C.POINTER(FdeOperator)]
         L.hodlr_ctx_set_timing.argtypes = [vp, i32]
         L.hodlr_ctx_timing_count.argtypes = [vp]
         L.hodlr_ctx_timing_entry.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(i64), C.POINTER(dbl)]
@@ -200,23 +201,33 @@ def default_opts(**kw) -> HodlrOpts:
 class HodlrMatrix:
     """A batch of HODLR-compressed operators M = s I + nu (D+ T + D- T^T)."""
 
-    def __init__(self, ctx: Context, ops, opts: HodlrOpts):
-        """ops: list of dicts n, alpha, dt, dx, shift, d_plus, d_minus (torch CUDA float64)."""
-        self.ctx = ctx
-        self._keep = []
+    @staticmethod
+    def _op_array(ops):
         arr = (FdeOperator * len(ops))()
         for i, o in enumerate(ops):
             dp, dm = o["d_plus"], o["d_minus"]
-            self._keep += [dp, dm]
             arr[i] = FdeOperator(int(o["n"]), float(o["alpha"]), float(o["dt"]), float(o["dx"]),
                                  float(o.get("shift", 1.0)), C.c_void_p(dp.data_ptr()),
                                  C.c_void_p(dm.data_ptr()))
+        return arr
+
+    def __init__(self, ctx: Context, ops, opts: HodlrOpts):
+        """ops: list of dicts n, alpha, dt, dx, shift, d_plus, d_minus (torch CUDA float64)."""
+        self.ctx = ctx
+        arr = self._op_array(ops)
         self.h = C.c_void_p()
         self.opts = opts
         self.sizes = [int(o["n"]) for o in ops]
         self.total_n = sum(self.sizes)
         check(lib().hodlr_build(ctx.h, arr, len(ops), C.byref(opts), C.byref(self.h)), "hodlr_build", ctx.h)
-        self._keep = []
+
+    def update_coefficients(self, ops):
+        """New d+/d- samples (same n, alpha, dt, dx, shift): rebuild the
+        compressed operator in place; factor again before solving."""
+        if len(ops) != len(self.sizes):
+            raise ValueError("one operator per problem of the batch")
+        check(lib().hodlr_update_coefficients(self.ctx.h, self.h, self._op_array(ops)),
+              "hodlr_update_coefficients", self.ctx.h)
 
     def info(self) -> HodlrMatInfo:
         i = HodlrMatInfo()

@@ -269,3 +269,33 @@ def test_fused_and_split_node_steps_agree(H, ctx):
             off += p.n
     for s in sols[1:]:
         assert np.linalg.norm(s - sols[0]) <= 1e-9 * np.linalg.norm(sols[0])
+
+
+def test_time_dependent_coefficients(H, ctx):
+    """Coefficients d+(x, t), d-(x, t) that change every step: the compressed
+    operator is rebuilt in place and factored again each step (a ragged batch
+    of two problems), and the trajectory matches the oracle's per-step dense
+    solves.  Solving between the update and the new factorisation is refused."""
+    probs = [var_problem(1500, 1.4, dt=1 / 32), var_problem(900, 1.7, dt=1 / 32, seed=1)]
+    steps = 6
+    A = build(H, ctx, probs, tol=1e-10, refine_max=3, rtol=1e-12)
+    u = dev(np.concatenate([p.u0 for p in probs]))
+    for m in range(1, steps + 1):
+        coefs = [W.timedep_coefficients(p, m * p.dt) for p in probs]
+        A.update_coefficients([H.operator_dict(p.n, p.alpha, p.dt, p.h, dev(dp), dev(dm), 1.0)
+                               for p, (dp, dm) in zip(probs, coefs)])
+        if m == 1:
+            with pytest.raises(H.HodlrError):
+                A.solve(u.clone())
+        A.factor()
+        A.solve(u, allow=(0, 2))          # f = 0: the right-hand side is u^(m-1)
+    us = u.cpu().numpy()
+    off = 0
+    for p in probs:
+        ref = O.euler_1d_varying(p, lambda t, p=p: W.timedep_coefficients(p, t), steps=steps)
+        err = np.linalg.norm(us[off:off + p.n] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-9, (p.n, err)
+        off += p.n
+    with pytest.raises(H.HodlrError):      # n must not change
+        A.update_coefficients([H.operator_dict(p.n + 1, p.alpha, p.dt, p.h, dev(np.ones(p.n + 1)),
+                                               dev(np.ones(p.n + 1)), 1.0) for p in probs])

@@ -226,3 +226,31 @@ def test_lower_blocks_are_restrictions_of_top_block():
         if r0 > c0:   # lower block, rows [r0,r1) cols [c0,c1), touching the diagonal at r0=c1
             m2, m1 = r1 - r0, c1 - c0
             np.testing.assert_array_equal(T[r0:r1, c0:c1], top[:m2, n1 - m1:])
+
+
+# ------------------------------------------------ time-dependent coefficients
+def test_varying_coefficients_constant_in_time_equal_euler():
+    """Coefficients that do not change in time reproduce the one-LU stepper."""
+    n = 150
+    x, h = W.grid(n)
+    p = W.Problem1D(n, 1.6, 1 / 16, 5, h, x, 1 + x * x, 1 + (1 - x) ** 2, W.bump(x), np.cos(3 * x))
+    u1 = O.euler_1d(p)
+    u2 = O.euler_1d_varying(p, lambda t: (p.d_plus, p.d_minus))
+    np.testing.assert_allclose(u2, u1, rtol=1e-15, atol=0)
+
+
+def test_varying_coefficients_alpha2_eigenmode_closed_form():
+    """alpha = 2 with d+ = d- = c(t): M(t) = I + 2 nu c(t) tridiag(-1, 2, -1),
+    whose eigenvectors sin(j pi x_i) do not depend on t, so the discrete
+    solution from u0 = sin(pi x) is u0 times prod_m 1 / (1 + 2 nu c(t_m) lambda_1)
+    with lambda_1 = 4 sin^2(pi h / 2)."""
+    n, dt, steps = 127, 0.01, 6
+    x, h = W.grid(n)
+    v = np.sin(np.pi * x)
+    one = np.ones(n)
+    p = W.Problem1D(n, 2.0, dt, steps, h, x, one, one, v.copy(), np.zeros(n))
+    c = lambda t: 1.0 + 0.5 * math.sin(3.0 * t)
+    u = O.euler_1d_varying(p, lambda t: (c(t) * one, c(t) * one))
+    lam = 4.0 * math.sin(math.pi * h / 2) ** 2
+    fac = np.prod([1.0 / (1.0 + 2.0 * p.nu * c(m * dt) * lam) for m in range(1, steps + 1)])
+    np.testing.assert_allclose(u, fac * v, rtol=1e-11, atol=1e-14)

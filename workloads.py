@@ -8,8 +8,8 @@ arithmetic: no Grunwald-Letnikov weights, no matrices, no solves.
 Grid convention (Sec. 2.2.1, eq. (part)): N interior points x_i = L + i*h,
 i = 1..N, h = (R - L)/(N + 1), absorbing boundary (u = 0 outside (L, R)).
 
-Workload recipes (sizes follow the five workload configurations the build is
-measured on; unstated inputs use the readings listed in the design doc):
+Workload recipes (the shapes of the paper's experiments; inputs the paper
+does not state are the choices written out below):
 
 * ``plain_1d``   N=1024, alpha=1.5, d+=d-=1, dt=1/16, 16 steps,
                  u0=x^2(1-x)^2, f=0.
@@ -77,6 +77,14 @@ class Problem1D:
     @property
     def nu(self) -> float:
         return self.dt / self.h ** self.alpha
+
+
+def timedep_coefficients(prob: Problem1D, t: float, amp: float = 0.25):
+    """Time-dependent coefficients for a 1D problem: its d+(x), d-(x) scaled
+    by 1 + amp sin(2 pi t) and 1 + amp cos(2 pi t) (both stay positive for
+    amp < 1).  Returns (d_plus, d_minus) at time t."""
+    return (prob.d_plus * (1.0 + amp * math.sin(2.0 * math.pi * t)),
+            prob.d_minus * (1.0 + amp * math.cos(2.0 * math.pi * t)))
 
 
 def plain_1d(n: int = 1024, alpha: float = 1.5, dt: float = 1.0 / 16,
