@@ -179,8 +179,8 @@ hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info);
  * runs) in a coordinate search over: the largest child size (rows) of a node
  * whose phase A runs as fused single-work-group kernels (0, 128, 256, 512,
  * 1024; 0 = never), rows per Gram partial of the other nodes (128, 256, 512),
- * and the work-group sizes of the recompression cores and of the leaves (256
- * or 512 threads).  Keeps the fastest for m and for every matrix of the same
+ * and the work-group size of the leaves (256 or 512 threads; the
+ * recompression cores always run with 256).  Keeps the fastest for m and for every matrix of the same
  * tree signature (batch, total rows, depth, leaf size) built later in the
  * process.  The trial runs overwrite m's factors: call hodlr_factor afterwards.
  * best (may be NULL): the chosen shapes and their factorisation time. */
@@ -193,8 +193,8 @@ typedef struct {
 } hodlr_tuning;
 hodlr_status hodlr_autotune(hodlr_ctx ctx, hodlr_mat m, hodlr_tuning* best);
 
-/* Sets m's factorisation launch shapes (core_threads, leaf_threads: 256 or
- * 512; gram_rows: 32 .. 65536, a multiple of 32; fuse_rows >= 0; factor_ms is
+/* Sets m's factorisation launch shapes (core_threads: 256; leaf_threads: 256
+ * or 512; gram_rows: 32 .. 65536, a multiple of 32; fuse_rows >= 0; factor_ms is
  * ignored), for instance ones found by hodlr_autotune on another matrix.  Any
  * other value: HODLR_EINVAL (argument 3).  The factors computed with any valid
  * shape agree up to the rounding order of the Gram sums. */

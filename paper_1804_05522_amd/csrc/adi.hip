@@ -124,8 +124,8 @@ __global__ void __launch_bounds__(256) k_lr_gram(const LrJob* jobs, const LrUnit
     for (int b = 0; b < 4; ++b) out[(ti + a) + (tj + b) * kMaxCat] = acc[a][b];
 }
 
-__global__ void __launch_bounds__(kWG) k_lr_core(const LrJob* jobs, const double* G, double* Mbuf) {
-  extern __shared__ double Lds[];
+__global__ void __launch_bounds__(kCoreWG) k_lr_core(const LrJob* jobs, const double* G, double* Mbuf) {
+  extern __shared__ __align__(16) double Lds[];
   const LrJob jb = jobs[blockIdx.x];
   const Cat3V X = resolve(jb.X);
   const int R = X.cols();

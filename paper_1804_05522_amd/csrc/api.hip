@@ -182,7 +182,7 @@ struct hodlr_mat_s {
   bf16* IU16 = nullptr;
   // multi-work-group factorisation schedule
   bool mwg_planned = false;
-  int core_threads = 512;                    // launch shapes of the factorisation (tunable)
+  int core_threads = kCoreWG;                // launch shapes of the factorisation (tunable)
   int leaf_threads = 512;
   int gram_rows = kGramRows;
   int fuse_rows = kFuseRows;                 // phase A of nodes with children up to this many rows: fused kernels
@@ -543,7 +543,10 @@ static hodlr_status plan_mwg(hodlr_mat m) {
     punits.insert(punits.end(), nodeu.begin(), nodeu.end());
     max_ppart = std::max(max_ppart, leafu.size());
     max_pz = std::max(max_pz, nodeu.size());
-    rec(KL_SPP, int(leafu.size()), lu0, j0i);
+    // subtrees that are single leaves have no levels to project onto
+    bool levels = false;
+    for (int64_t q = j0i; q < int64_t(jobs.size()); ++q) levels = levels || jobs[q].d0 < m->items[jobs[q].item].L;
+    if (levels) rec(KL_SPP, int(leafu.size()), lu0, j0i);
     if (!nodeu.empty()) rec(KL_SPR, int(nodeu.size()), nu0, j0i);
     rec(KL_SPE, int(leafu.size()), lu0, j0i);
   };
@@ -635,7 +638,7 @@ static void enqueue_mwg(hodlr_mat m, hipStream_t s) {
   // block sizes of the latency-bound single-group kernels (512 measured fastest);
   // the leaf kernel splits its dot products over blockDim/128 threads, so it needs >= 128
   auto pick = [](int v) { return v >= 512 ? 512 : (v >= 256 ? 256 : 128); };
-  const int core_threads = std::max(256, pick(env_int("HODLR_CORE_THREADS", m->core_threads)));
+  const int core_threads = kCoreWG;   // fixed by the cores' launch bounds (register-held columns)
   const int leaf_threads = std::max(256, pick(env_int("HODLR_LEAF_THREADS", m->leaf_threads)));
   const int Lmax = std::max(1, m->Lmax);
   for (size_t q = 0; q < m->mwg_kind.size(); ++q) {
@@ -1215,7 +1218,7 @@ hodlr_status hodlr_toeplitz_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, 
 hodlr_status hodlr_set_tuning(hodlr_ctx ctx, hodlr_mat m, const hodlr_tuning* t) {
   if (!ctx) return HODLR_EINVAL;
   if (!m) return set_arg(ctx, 2);
-  if (!t || (t->core_threads != 256 && t->core_threads != 512) || (t->leaf_threads != 256 && t->leaf_threads != 512) ||
+  if (!t || t->core_threads != kCoreWG || (t->leaf_threads != 256 && t->leaf_threads != 512) ||
       t->gram_rows < 32 || t->gram_rows > 65536 || t->gram_rows % 32 != 0 || t->fuse_rows < 0)
     return set_arg(ctx, 3);
   if (t->gram_rows != m->gram_rows || t->fuse_rows != m->fuse_rows) {
@@ -1269,7 +1272,7 @@ hodlr_status hodlr_autotune(hodlr_ctx ctx, hodlr_mat m, hodlr_tuning* best) {
   };
   // coordinate search: fused-node threshold, then Gram chunk rows, then the
   // work-group sizes of the cores and leaves
-  TuneVal bestv{m->core_threads, m->leaf_threads, m->gram_rows, m->fuse_rows};
+  TuneVal bestv{kCoreWG, m->leaf_threads, m->gram_rows, m->fuse_rows};
   double best_ms = 1e300;
   auto consider = [&](TuneVal v) -> hodlr_status {
     double ms = 0.0;
@@ -1284,10 +1287,8 @@ hodlr_status hodlr_autotune(hodlr_ctx ctx, hodlr_mat m, hodlr_tuning* best) {
   for (int g : {128, 256, 512})
     if (g != bestv.gram_rows) TRY(consider(TuneVal{bestv.core_threads, bestv.leaf_threads, g, bestv.fuse_rows}));
   const TuneVal base = bestv;
-  for (int ct : {256, 512})
-    for (int lt : {256, 512})
-      if (ct != base.core_threads || lt != base.leaf_threads)
-        TRY(consider(TuneVal{ct, lt, base.gram_rows, base.fuse_rows}));
+  for (int lt : {256, 512})
+    if (lt != base.leaf_threads) TRY(consider(TuneVal{kCoreWG, lt, base.gram_rows, base.fuse_rows}));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   TRY(replan(bestv.gram_rows, bestv.fuse_rows));

@@ -123,7 +123,7 @@ hodlr_status run_lr(fde2d_plan P, const LrJob& job, int slot, bool recompress, h
     HFDE_LAUNCH(k_lr_frob, dim3(1), dim3(256), 0, s, P->jobs + slot, P->grams, P->frob + slot);
     return HODLR_OK;
   }
-  HFDE_LAUNCH(k_lr_core, dim3(1), dim3(kWG), kFactorLdsBytes, s, P->jobs + slot, P->grams, P->mbuf);
+  HFDE_LAUNCH(k_lr_core, dim3(1), dim3(kCoreWG), kFactorLdsBytes, s, P->jobs + slot, P->grams, P->mbuf);
   std::vector<LrUnit> fu;
   for (int side = 0; side < 2; ++side) {
     const int64_t rows = side == 0 ? jb.rows_x : jb.rows_y;

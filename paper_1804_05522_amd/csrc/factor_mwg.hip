@@ -317,9 +317,9 @@ __device__ RecompressOut wg_recompress_core(const double* GAg, const double* GBg
 
 // Core unit: which recompression of a task (0: S12 -> rankU, 1: S21 -> rankL,
 // 2: pending of c2 -> rankP[c2]); grams at G[task*9 + type].
-__global__ void __launch_bounds__(kWG) k_core(DevPtrs P, const NodeTask* tasks, const int2* core_units,
+__global__ void __launch_bounds__(kCoreWG) k_core(DevPtrs P, const NodeTask* tasks, const int2* core_units,
                                               const double* G, double* Mbuf, int rmax) {
-  extern __shared__ double Lds[];
+  extern __shared__ __align__(16) double Lds[];
   const int2 cu = core_units[blockIdx.x];
   const NodeTask tk = tasks[cu.x];
   const int which = cu.y;
@@ -463,7 +463,7 @@ __device__ inline void record_rank(const DevPtrs& P, const Item& it, int item, i
 // Phase A, first part, of one node: unit 2k + w recompresses S12 (w = 0:
 // U12' -> T1(c1), V12' -> FU(c2)) or S21 (w = 1: U21' -> FL(c2),
 // V21' -> T2(c1)) of task k.
-__global__ void __launch_bounds__(kWG) k_node_recompress(DevPtrs P, const NodeTask* tasks, int rmax) {
+__global__ void __launch_bounds__(kCoreWG) k_node_recompress(DevPtrs P, const NodeTask* tasks, int rmax) {
   extern __shared__ __align__(16) double Lf[];
   const NodeTask tk = tasks[blockIdx.x >> 1];
   const int which = blockIdx.x & 1;
@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(kWG) k_node_recompress(DevPtrs P, const NodeTa
 // Phase A, last part, of one node (after the products U~12, V~21):
 // C = V~21^T U~12, W = U21' C -> T1(c2), then the recompression of the
 // pending update [P(c2), W][Q(c2), V12']^T of c2 -> PP, PQ at depth d + 1.
-__global__ void __launch_bounds__(kWG) k_node_pending(DevPtrs P, const NodeTask* tasks) {
+__global__ void __launch_bounds__(kCoreWG) k_node_pending(DevPtrs P, const NodeTask* tasks) {
   extern __shared__ __align__(16) double Lf[];
   const NodeTask tk = tasks[blockIdx.x];
   const Item it = P.items[tk.item];
@@ -795,7 +795,7 @@ __global__ void __launch_bounds__(256) k_sp_expand(DevPtrs P, const ProdJob* job
 // --------------------------------------------------------------- leaves
 // One leaf per unit: the leaf's pending update comes from pend_src.
 __global__ void __launch_bounds__(kWG) k_leaf_task(DevPtrs P, const NodeTask* tasks, int b) {
-  extern __shared__ double Lds[];
+  extern __shared__ __align__(16) double Lds[];
   const NodeTask tk = tasks[blockIdx.x];
   const Item it = P.items[tk.item];
   const int ps = pend_src(tk.d, tk.j);

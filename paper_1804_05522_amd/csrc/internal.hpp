@@ -9,6 +9,9 @@
 namespace hfde {
 
 constexpr int kWG = 512;          // threads per work-group of the per-problem kernels
+constexpr int kCoreWG = 256;      // threads of the recompression-core kernels: one wave per SIMD, so a
+                                  // wave may hold 512 registers (a pivoted-Cholesky column of 64 doubles
+                                  // stays in registers)
 constexpr int kRS = 32;           // column stride of every off-diagonal factor array (max rank)
 constexpr int kMaxLeaf = 64;      // largest leaf size b
 constexpr int kLdsLeaf = kMaxLeaf + 1;   // padded leading dimension of leaf tiles in LDS

@@ -246,7 +246,7 @@ class HodlrMatrix:
         check(lib().hodlr_autotune(self.ctx.h, self.h, C.byref(t)), "hodlr_autotune", self.ctx.h)
         return t
 
-    def set_tuning(self, core_threads=512, leaf_threads=512, gram_rows=256, fuse_rows=256):
+    def set_tuning(self, core_threads=256, leaf_threads=512, gram_rows=256, fuse_rows=256):
         """Fix the factorisation's launch shapes (see hodlr_set_tuning)."""
         t = HodlrTuning(core_threads, leaf_threads, gram_rows, fuse_rows, 0.0)
         check(lib().hodlr_set_tuning(self.ctx.h, self.h, C.byref(t)), "hodlr_set_tuning", self.ctx.h)
