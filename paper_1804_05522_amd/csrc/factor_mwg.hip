@@ -651,8 +651,16 @@ __global__ void __launch_bounds__(256) k_sp_reduce(DevPtrs P, const ProdJob* job
     double acc = 0.0;
     if (g < groups) {
       const int s = e % r, c = e / r;
-      for (int64_t l = g; l < span; l += groups)
-        acc += part[((unit_first + l) * Lmax + d) * kRS * kPNC + s + c * kRS];
+      const double* pp = part + (unit_first * Lmax + d) * kRS * kPNC + s + c * kRS;
+      const int64_t stride = int64_t(Lmax) * kRS * kPNC;
+      double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // eight loads in flight
+      int64_t l = g;
+      for (; l + 7 * groups < span; l += 8 * groups) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a8[q] += pp[(l + q * groups) * stride];
+      }
+      for (; l < span; l += groups) a8[0] += pp[l * stride];
+      acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     }
     red[t] = acc;
     __syncthreads();

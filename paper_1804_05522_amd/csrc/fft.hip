@@ -93,19 +93,42 @@ __device__ inline double exact_row(const DevPtrs& P, const Item& it, const doubl
   const double* g = P.g + it.g0;
   const int64_t n = it.n;
   const int w = it.band;
-  dd sp{0.0, 0.0}, sm{0.0, 0.0};
   // (T x)_i = -sum_{j <= i+1} g_{i-j+1} x_j ;  near: i - j in [-1, w]
-  for (int k = -1; k <= w; ++k) {
-    const int64_t j = i - k;
-    if (j < 0 || j >= n) continue;
-    sp = dd_add(sp, dd_prod(-g[k + 1], x[j]));
-  }
   // (T^T x)_i = -sum_{j >= i-1} g_{j-i+1} x_j ;  near: j - i in [-1, w]
-  for (int k = -1; k <= w; ++k) {
-    const int64_t j = i + k;
-    if (j < 0 || j >= n) continue;
-    sm = dd_add(sm, dd_prod(-g[k + 1], x[j]));
+  // Each sum runs in four interleaved double-double accumulators (terms
+  // k = q mod 4), combined at the end: independent chains keep the FP64
+  // pipeline busy.  Rows whose whole band lies inside the problem skip the
+  // range checks.
+  dd ap[4], am[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ap[q] = am[q] = dd{0.0, 0.0};
+  if (i - w >= 0 && i + w < n && i + 1 < n && i >= 1) {
+    for (int k0 = -1; k0 <= w; k0 += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + q;
+        if (k <= w) {
+          const double gk = -g[k + 1];
+          ap[q] = dd_add(ap[q], dd_prod(gk, x[i - k]));
+          am[q] = dd_add(am[q], dd_prod(gk, x[i + k]));
+        }
+      }
+    }
+  } else {
+    for (int k0 = -1; k0 <= w; k0 += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + q;
+        if (k <= w) {
+          const double gk = -g[k + 1];
+          if (i - k >= 0 && i - k < n) ap[q] = dd_add(ap[q], dd_prod(gk, x[i - k]));
+          if (i + k >= 0 && i + k < n) am[q] = dd_add(am[q], dd_prod(gk, x[i + k]));
+        }
+      }
+    }
   }
+  dd sp = dd_add(dd_add(ap[0], ap[1]), dd_add(ap[2], ap[3]));
+  dd sm = dd_add(dd_add(am[0], am[1]), dd_add(am[2], am[3]));
   sp = dd_add(sp, dd{far_re, 0.0});
   sm = dd_add(sm, dd{far_im, 0.0});
   const int64_t gi = it.row0 + i;

@@ -112,7 +112,16 @@ __global__ void __launch_bounds__(256) k_reduce(DevPtrs P, const NodeUnit* nu, i
     if (g < groups) {
       const int s = e % r, c = e / r;
       const double* pp = part + (int64_t(u.level) * leaves + first) * int64_t(kRS) * nc + s + c * kRS;
-      for (int64_t l = g; l < span; l += groups) acc += pp[l * int64_t(kRS) * nc];
+      const int64_t stride = int64_t(kRS) * nc;
+      // eight independent partial sums: eight loads in flight per thread
+      double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int64_t l = g;
+      for (; l + 7 * groups < span; l += 8 * groups) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a8[q] += pp[(l + q * groups) * stride];
+      }
+      for (; l < span; l += groups) a8[0] += pp[l * stride];
+      acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     }
     red[t] = acc;
     __syncthreads();
