@@ -439,13 +439,22 @@ static hodlr_status plan_mwg(hodlr_mat m) {
     m->mwg_off.push_back(off);
     m->mwg_off2.push_back(off2);
   };
-  struct Ev { int type, d; int64_t j; };   // type 0: leaf, 1: phase A, 2: phase B
+  // Events of a problem's post-order walk.  type 0: leaf; 3: recompression
+  // of the off-diagonal blocks S12, S21 (with the pending update) of every
+  // internal node on the left spine that starts at (d, j): a node's blocks
+  // and pending update are known once the spine's head has its pending
+  // update (a left child inherits its parent's), so the spine is recompressed
+  // in one step before its leftmost leaf; 1: phase A after the left child
+  // (subtree products, C, W and the pending update of the right child, whose
+  // spine follows); 2: phase B after the right child.
+  struct Ev { int type, d; int64_t j; };
   std::vector<std::vector<Ev>> evs(B);
   for (int i = 0; i < B; ++i) {
     const int L = m->items[i].L;
     std::vector<int> state(L + 2, 0);
     int d = 0;
     int64_t j = 0;
+    if (L > 0) evs[i].push_back(Ev{3, 0, 0});
     for (;;) {
       if (d == L) {
         evs[i].push_back(Ev{0, d, j});
@@ -456,6 +465,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
       if (state[d] == 0) { state[d] = 1; state[d + 1] = 0; ++d; j = 2 * j; continue; }
       if (state[d] == 1) {
         evs[i].push_back(Ev{1, d, j});
+        if (d + 1 < L) evs[i].push_back(Ev{3, d + 1, 2 * j + 1});
         state[d] = 2; state[d + 1] = 0; ++d; j = 2 * j + 1;
         continue;
       }
@@ -469,7 +479,9 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   const int fuse_rows = env_int("HODLR_FUSE_ROWS", m->fuse_rows);
   m->fuse_used = fuse_rows;
   struct TaskSpec { int item, d; int64_t j; int64_t n1, n2; };
+  size_t max_step_tasks = 1;
   auto add_tasks = [&](const std::vector<TaskSpec>& ts) {
+    max_step_tasks = std::max(max_step_tasks, ts.size());
     const int64_t t0 = int64_t(tasks.size());
     for (size_t k = 0; k < ts.size(); ++k) tasks.push_back(NodeTask{ts[k].item, ts[k].d, int32_t(ts[k].j), int32_t(k)});
     return t0;
@@ -551,36 +563,61 @@ static hodlr_status plan_mwg(hodlr_mat m) {
     rec(KL_SPE, int(leafu.size()), lu0, j0i);
   };
   for (size_t g = 0; g < steps; ++g) {
-    std::vector<TaskSpec> lt, at, bt;
+    std::vector<TaskSpec> lt, at, bt, st;
     for (int i = 0; i < B; ++i) {
       if (g >= evs[i].size()) continue;
       const Ev e = evs[i][g];
+      if (e.type == 3) {                 // every internal node of the spine
+        const int L = m->items[i].L;
+        for (int dd = e.d; dd < L; ++dd) {
+          const int64_t jj = e.j << (dd - e.d);
+          const Node nd = m->nodes[node_index(m->items[i], dd, jj)];
+          st.push_back(TaskSpec{i, dd, jj, nd.size / 2, nd.size - nd.size / 2});
+        }
+        continue;
+      }
       const Node nd = m->nodes[node_index(m->items[i], e.d, e.j)];
       TaskSpec t{i, e.d, e.j, nd.size / 2, nd.size - nd.size / 2};
       (e.type == 0 ? lt : (e.type == 1 ? at : bt)).push_back(t);
     }
+    // nodes whose children fit the fused single-work-group kernels, and the rest
+    auto split = [&](const std::vector<TaskSpec>& ts, std::vector<TaskSpec>& small, std::vector<TaskSpec>& big) {
+      for (const TaskSpec& t : ts) (std::max(t.n1, t.n2) <= fuse_rows ? small : big).push_back(t);
+    };
     if (!lt.empty()) {
       const int64_t t0 = add_tasks(lt);
       rec(KL_LEAF, int(lt.size()), t0, t0);
     }
-    bool fuse = !at.empty();
-    for (const TaskSpec& t : at) fuse = fuse && std::max(t.n1, t.n2) <= fuse_rows;
-    if (fuse) {
-      const int64_t t0 = add_tasks(at);
-      rec(KL_NODE_REC, int(2 * at.size()), t0, t0);
+    if (!st.empty()) {
+      std::vector<TaskSpec> small, big;
+      split(st, small, big);
+      if (!small.empty()) {
+        const int64_t t0 = add_tasks(small);
+        rec(KL_NODE_REC, int(2 * small.size()), t0, t0);
+      }
+      if (!big.empty()) {
+        const int64_t t0 = add_tasks(big);
+        add_grams(t0, big, {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {3, 3, 3}});
+        add_core(t0, big.size(), {0, 1});
+        add_form(t0, big, {0, 1, 2, 3});
+      }
+    }
+    if (!at.empty()) {
       add_prods(at, {{0, 0, 0, A_T1, A_FU, 0, 1.0}, {0, 1, 1, A_T2, A_FL, 1, 1.0}});
-      rec(KL_NODE_PEND, int(at.size()), t0, t0);
-    } else if (!at.empty()) {
-      const int64_t t0 = add_tasks(at);
-      add_grams(t0, at, {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {3, 3, 3}});
-      add_core(t0, at.size(), {0, 1});
-      add_form(t0, at, {0, 1, 2, 3});
-      add_prods(at, {{0, 0, 0, A_T1, A_FU, 0, 1.0}, {0, 1, 1, A_T2, A_FL, 1, 1.0}});
-      add_grams(t0, at, {{4, 7, 4}});
-      add_form(t0, at, {4});
-      add_grams(t0, at, {{5, 5, 5}, {6, 6, 6}});
-      add_core(t0, at.size(), {2});
-      add_form(t0, at, {5, 6});
+      std::vector<TaskSpec> small, big;
+      split(at, small, big);
+      if (!small.empty()) {
+        const int64_t t0 = add_tasks(small);
+        rec(KL_NODE_PEND, int(small.size()), t0, t0);
+      }
+      if (!big.empty()) {
+        const int64_t t0 = add_tasks(big);
+        add_grams(t0, big, {{4, 7, 4}});
+        add_form(t0, big, {4});
+        add_grams(t0, big, {{5, 5, 5}, {6, 6, 6}});
+        add_core(t0, big.size(), {2});
+        add_form(t0, big, {5, 6});
+      }
     }
     if (!bt.empty())
       add_prods(bt, {{1, 0, 0, A_FL, A_IL, 1, -1.0}, {0, 0, 1, A_FL, A_IL, 1, 1.0},
@@ -595,8 +632,8 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   TRY(dalloc(m, &m->d_jobs, jobs.size()));
   TRY(dalloc(m, &m->d_punits, punits.size()));
   TRY(dalloc(m, &m->d_gpart, max_gpart * kG2));
-  TRY(dalloc(m, &m->d_G, size_t(B) * 9 * kG2));
-  TRY(dalloc(m, &m->d_M, size_t(B) * 3 * 2 * kMaxCat * kRS));
+  TRY(dalloc(m, &m->d_G, max_step_tasks * 9 * kG2));
+  TRY(dalloc(m, &m->d_M, max_step_tasks * 3 * 2 * kMaxCat * kRS));
   TRY(dalloc(m, &m->d_ppart, max_ppart * Lmax * kRS * kPNC));
   TRY(dalloc(m, &m->d_pz, max_pz * kRS * kPNC));
   auto up = [](void* dst, const void* src, size_t bytes) -> hodlr_status {
