@@ -199,6 +199,10 @@ struct hodlr_mat_s {
   ProdJob* d_jobs = nullptr;
   ProdUnit* d_punits = nullptr;
   double* d_gpart = nullptr;
+  double* d_gpart_side = nullptr;            // Gram partials of the second stream's recompressions
+  std::vector<char> mwg_side;                // record runs on the second stream
+  hipStream_t side = nullptr;                // second stream of the factorisation (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* d_G = nullptr;
   double* d_M = nullptr;
   double* d_ppart = nullptr;
@@ -415,7 +419,8 @@ void launch_axpby(int64_t nrows, int nc, double a, const double* x, int64_t ldx,
 // ------------------------------------------------------------------
 // Multi-work-group factorisation: host schedule (post-order, lock-step
 // over the problems of the batch, which must share one tree shape).
-enum MwgKind { KL_LEAF = 0, KL_GRAM, KL_REDUCE, KL_CORE, KL_FORM, KL_SPP, KL_SPR, KL_SPE, KL_NODE_REC, KL_NODE_PEND };
+enum MwgKind { KL_LEAF = 0, KL_GRAM, KL_REDUCE, KL_CORE, KL_FORM, KL_SPP, KL_SPR, KL_SPE, KL_NODE_REC, KL_NODE_PEND,
+               KL_FORK, KL_JOIN_MARK, KL_JOIN_WAIT };
 
 static int env_int(const char* name, int dflt) {
   const char* v = getenv(name);
@@ -433,7 +438,9 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   std::vector<ProdJob> jobs;
   std::vector<ProdUnit> punits;
   size_t max_gpart = 1, max_ppart = 1, max_pz = 1;
+  bool on_side = false;                      // records go to the second stream
   auto rec = [&](int kind, int grid, int64_t off, int64_t off2) {
+    m->mwg_side.push_back(on_side ? 1 : 0);
     m->mwg_kind.push_back(kind);
     m->mwg_grid.push_back(grid);
     m->mwg_off.push_back(off);
@@ -478,6 +485,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   for (auto& e : evs) steps = std::max(steps, e.size());
   const int fuse_rows = env_int("HODLR_FUSE_ROWS", m->fuse_rows);
   m->fuse_used = fuse_rows;
+  bool side_open = false;
   struct TaskSpec { int item, d; int64_t j; int64_t n1, n2; };
   size_t max_step_tasks = 1;
   auto add_tasks = [&](const std::vector<TaskSpec>& ts) {
@@ -589,6 +597,10 @@ static hodlr_status plan_mwg(hodlr_mat m) {
       rec(KL_LEAF, int(lt.size()), t0, t0);
     }
     if (!st.empty()) {
+      // the spine's recompressions run on the second stream, concurrently with
+      // the leaves that follow; phase A waits for them (join)
+      rec(KL_FORK, 1, 0, 0);
+      on_side = true;
       std::vector<TaskSpec> small, big;
       split(st, small, big);
       if (!small.empty()) {
@@ -601,8 +613,13 @@ static hodlr_status plan_mwg(hodlr_mat m) {
         add_core(t0, big.size(), {0, 1});
         add_form(t0, big, {0, 1, 2, 3});
       }
+      rec(KL_JOIN_MARK, 1, 0, 0);
+      on_side = false;
+      side_open = true;
     }
     if (!at.empty()) {
+      if (side_open) rec(KL_JOIN_WAIT, 1, 0, 0);
+      side_open = false;
       add_prods(at, {{0, 0, 0, A_T1, A_FU, 0, 1.0}, {0, 1, 1, A_T2, A_FL, 1, 1.0}});
       std::vector<TaskSpec> small, big;
       split(at, small, big);
@@ -623,6 +640,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
       add_prods(bt, {{1, 0, 0, A_FL, A_IL, 1, -1.0}, {0, 0, 1, A_FL, A_IL, 1, 1.0},
                      {0, 1, 0, A_FU, A_IU, 0, -1.0}, {1, 1, 1, A_FU, A_IU, 0, 1.0}});
   }
+  if (side_open) rec(KL_JOIN_WAIT, 1, 0, 0);
   const int Lmax = std::max(1, m->Lmax);
   TRY(dalloc(m, &m->d_tasks, tasks.size()));
   TRY(dalloc(m, &m->d_gram, grams.size()));
@@ -632,6 +650,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   TRY(dalloc(m, &m->d_jobs, jobs.size()));
   TRY(dalloc(m, &m->d_punits, punits.size()));
   TRY(dalloc(m, &m->d_gpart, max_gpart * kG2));
+  TRY(dalloc(m, &m->d_gpart_side, max_gpart * kG2));
   TRY(dalloc(m, &m->d_G, max_step_tasks * 9 * kG2));
   TRY(dalloc(m, &m->d_M, max_step_tasks * 3 * 2 * kMaxCat * kRS));
   TRY(dalloc(m, &m->d_ppart, max_ppart * Lmax * kRS * kPNC));
@@ -678,20 +697,44 @@ static void enqueue_mwg(hodlr_mat m, hipStream_t s) {
   const int core_threads = kCoreWG;   // fixed by the cores' launch bounds (register-held columns)
   const int leaf_threads = std::max(256, pick(env_int("HODLR_LEAF_THREADS", m->leaf_threads)));
   const int Lmax = std::max(1, m->Lmax);
+  // second stream for the spine recompressions; timed runs (events on the
+  // context's stream around every launch) keep everything on one stream
+  bool two = g_timer == nullptr;
+  if (two && !m->side) {
+    two = hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) == hipSuccess &&
+          hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming) == hipSuccess &&
+          hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming) == hipSuccess;
+  }
+  const hipStream_t main_s = s;
   for (size_t q = 0; q < m->mwg_kind.size(); ++q) {
     const int g = m->mwg_grid[q];
     if (g <= 0) continue;
     const int64_t off = m->mwg_off[q], off2 = m->mwg_off2[q];
+    const bool on_side = m->mwg_side[q] != 0;
+    s = (two && on_side) ? m->side : main_s;
+    double* gpart = on_side ? m->d_gpart_side : m->d_gpart;
     switch (m->mwg_kind[q]) {
+      case KL_FORK:
+        if (two) {
+          (void)hipEventRecord(m->ev_fork, main_s);
+          (void)hipStreamWaitEvent(m->side, m->ev_fork, 0);
+        }
+        break;
+      case KL_JOIN_MARK:
+        if (two) (void)hipEventRecord(m->ev_join, m->side);
+        break;
+      case KL_JOIN_WAIT:
+        if (two) (void)hipStreamWaitEvent(main_s, m->ev_join, 0);
+        break;
       case KL_LEAF:
         HFDE_LAUNCH(k_leaf_task, dim3(g), dim3(leaf_threads), kFactorLdsBytes, s, P, m->d_tasks + off, m->b);
         break;
       case KL_GRAM:
-        HFDE_LAUNCH(k_gram_partial, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_gram + off, m->d_gpart,
+        HFDE_LAUNCH(k_gram_partial, dim3(g), dim3(256), 0, s, P, m->d_tasks + off2, m->d_gram + off, gpart,
                     m->gram_rows);
         break;
       case KL_REDUCE:
-        HFDE_LAUNCH(k_gram_reduce, dim3(g), dim3(256), 0, s, m->d_red + off, m->d_gpart, m->d_G);
+        HFDE_LAUNCH(k_gram_reduce, dim3(g), dim3(256), 0, s, m->d_red + off, gpart, m->d_G);
         break;
       case KL_CORE:
         HFDE_LAUNCH(k_core, dim3(g), dim3(core_threads), kFactorLdsBytes, s, P, m->d_tasks + off2, m->d_core + off, m->d_G,
@@ -787,6 +830,12 @@ hodlr_status hodlr_default_opts(hodlr_opts* o) {
 void hodlr_destroy(hodlr_mat m) {
   if (!m) return;
   if (m->step_graph) (void)hipGraphExecDestroy(m->step_graph);
+  if (m->side) {
+    (void)hipStreamSynchronize(m->side);
+    (void)hipStreamDestroy(m->side);
+  }
+  if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+  if (m->ev_join) (void)hipEventDestroy(m->ev_join);
   for (void* p : m->allocs) (void)hipFree(p);
   delete m;
 }
@@ -1263,6 +1312,7 @@ hodlr_status hodlr_set_tuning(hodlr_ctx ctx, hodlr_mat m, const hodlr_tuning* t)
     m->fuse_rows = t->fuse_rows;
     m->mwg_planned = false;
     m->mwg_kind.clear();
+    m->mwg_side.clear();
     m->mwg_grid.clear();
     m->mwg_off.clear();
     m->mwg_off2.clear();
@@ -1285,6 +1335,7 @@ hodlr_status hodlr_autotune(hodlr_ctx ctx, hodlr_mat m, hodlr_tuning* best) {
     m->fuse_rows = f;
     m->mwg_planned = false;
     m->mwg_kind.clear();
+    m->mwg_side.clear();
     m->mwg_grid.clear();
     m->mwg_off.clear();
     m->mwg_off2.clear();
