@@ -1025,7 +1025,7 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
       for (int i : m->big_items) {
         const int lg = m->items[i].fftlog;
         const int l2 = lg / 2, l1 = lg - l2;
-        int T = std::min(4, 8192 >> l1);
+        int T = std::min(kFftTileMax, kFftLds >> l1);
         m->fft4_lds = std::max(m->fft4_lds, size_t(T) * (size_t(1) << l1) * sizeof(double2));
         for (int t = 0; t < (1 << l1) / T; ++t) u1.push_back(FftUnit{i, c, t, 0});
         for (int t = 0; t < (1 << l2) / T; ++t) u2.push_back(FftUnit{i, c, t, 0});

@@ -95,13 +95,23 @@ __device__ inline double exact_row(const DevPtrs& P, const Item& it, const doubl
   const int w = it.band;
   // (T x)_i = -sum_{j <= i+1} g_{i-j+1} x_j ;  near: i - j in [-1, w]
   // (T^T x)_i = -sum_{j >= i-1} g_{j-i+1} x_j ;  near: j - i in [-1, w]
-  // Each sum runs in four interleaved double-double accumulators (terms
-  // k = q mod 4), combined at the end: independent chains keep the FP64
-  // pipeline busy.  Rows whose whole band lies inside the problem skip the
-  // range checks.
-  dd ap[4], am[4];
+  // Compensated dot products (Ogita, Rump and Oishi, "Accurate sum and dot
+  // product", 2005, algorithm Dot2): the running sum advances by error-free
+  // additions and the rounding errors of the sums and products collect in a
+  // second double, which gives the accuracy of twice the working precision.
+  // Each sum runs in four interleaved chains (terms k = q mod 4) that are
+  // combined in double-double at the end; rows whose whole band lies inside
+  // the problem skip the range checks.
+  double ps[4], pc[4], ms[4], mc[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) ap[q] = am[q] = dd{0.0, 0.0};
+  for (int q = 0; q < 4; ++q) ps[q] = pc[q] = ms[q] = mc[q] = 0.0;
+  auto acc = [](double& sum, double& err, double a, double b) {
+    const double p = a * b;
+    const double e = fma(a, b, -p);
+    const dd t = two_sum(sum, p);
+    sum = t.hi;
+    err += t.lo + e;
+  };
   if (i - w >= 0 && i + w < n && i + 1 < n && i >= 1) {
     for (int k0 = -1; k0 <= w; k0 += 4) {
 #pragma unroll
@@ -109,8 +119,8 @@ __device__ inline double exact_row(const DevPtrs& P, const Item& it, const doubl
         const int k = k0 + q;
         if (k <= w) {
           const double gk = -g[k + 1];
-          ap[q] = dd_add(ap[q], dd_prod(gk, x[i - k]));
-          am[q] = dd_add(am[q], dd_prod(gk, x[i + k]));
+          acc(ps[q], pc[q], gk, x[i - k]);
+          acc(ms[q], mc[q], gk, x[i + k]);
         }
       }
     }
@@ -121,14 +131,16 @@ __device__ inline double exact_row(const DevPtrs& P, const Item& it, const doubl
         const int k = k0 + q;
         if (k <= w) {
           const double gk = -g[k + 1];
-          if (i - k >= 0 && i - k < n) ap[q] = dd_add(ap[q], dd_prod(gk, x[i - k]));
-          if (i + k >= 0 && i + k < n) am[q] = dd_add(am[q], dd_prod(gk, x[i + k]));
+          if (i - k >= 0 && i - k < n) acc(ps[q], pc[q], gk, x[i - k]);
+          if (i + k >= 0 && i + k < n) acc(ms[q], mc[q], gk, x[i + k]);
         }
       }
     }
   }
-  dd sp = dd_add(dd_add(ap[0], ap[1]), dd_add(ap[2], ap[3]));
-  dd sm = dd_add(dd_add(am[0], am[1]), dd_add(am[2], am[3]));
+  dd sp = dd_add(dd_add(two_sum(ps[0], pc[0]), two_sum(ps[1], pc[1])),
+                 dd_add(two_sum(ps[2], pc[2]), two_sum(ps[3], pc[3])));
+  dd sm = dd_add(dd_add(two_sum(ms[0], mc[0]), two_sum(ms[1], mc[1])),
+                 dd_add(two_sum(ms[2], mc[2]), two_sum(ms[3], mc[3])));
   sp = dd_add(sp, dd{far_re, 0.0});
   sm = dd_add(sm, dd{far_im, 0.0});
   const int64_t gi = it.row0 + i;
@@ -220,11 +232,16 @@ __global__ void __launch_bounds__(kFftWG) k_fft_small(DevPtrs P, const FftUnit* 
 }
 
 // Four-step split: M = M1 * M2, n = n1 + M1 n2, k = k2 + M2 k1.
+// Columns per work-group of a four-step pass: fewer columns give more
+// work-groups per pass (the passes are latency-bound at these lengths), more
+// give longer contiguous segments (tile x 16 bytes).
+constexpr int kFftTileMax = 2;
+
 __device__ inline void four_step_dims(int logM, int& l1, int& l2, int& tile) {
   l2 = logM / 2;
   l1 = logM - l2;
   tile = kFftLds >> l1;
-  if (tile > 4) tile = 4;   // 64-byte contiguous segments, many work-groups per pass
+  if (tile > kFftTileMax) tile = kFftTileMax;
 }
 
 // Pass 1: transforms over n2 (length M2) for `tile` adjacent n1, then the
