@@ -37,6 +37,14 @@ struct Cat3V {          // resolved on the device
   int c[3];
   double s[3];
   __device__ inline int cols() const { return c[0] + c[1] + c[2]; }
+  __device__ inline const double* colp(int col, double& scale) const {
+    const int g = col < c[0] ? 0 : (col < c[0] + c[1] ? 1 : 2);
+    const int cc = col - (g > 0 ? c[0] : 0) - (g > 1 ? c[1] : 0);
+    const double* base = g == 0 ? p[0] : (g == 1 ? p[1] : p[2]);
+    const int64_t l = g == 0 ? ld[0] : (g == 1 ? ld[1] : ld[2]);
+    scale = g == 0 ? s[0] : (g == 1 ? s[1] : s[2]);
+    return base + int64_t(cc) * l;
+  }
   __device__ inline double at(int64_t row, int col) const {
     if (col < c[0]) return s[0] * p[0][row + int64_t(col) * ld[0]];
     col -= c[0];
@@ -77,51 +85,18 @@ struct LrUnit {
   int32_t out;              // partial slot
 };
 
-constexpr int kLrRows = 1024;
-constexpr int kLrSub = 32;
+constexpr int kLrRows = 256;     // rows per Gram partial (one work-group on the matrix cores)
 
 __global__ void __launch_bounds__(256) k_lr_gram(const LrJob* jobs, const LrUnit* units, double* partial) {
-  __shared__ double xs[kLrSub * kMaxCat];
+  __shared__ __align__(16) double st[kMaxCat * kStLd];
   const LrUnit u = units[blockIdx.x];
   const LrJob jb = jobs[u.job];
   const Cat3V A = resolve(u.which == 0 ? jb.X : jb.Y);
   const int64_t rows = u.which == 0 ? jb.rows_x : jb.rows_y;
-  const int M = A.cols();
-  const int t = threadIdx.x;
-  const int ti = (t % 16) * 4, tj = (t / 16) * 4;
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  const int64_t r0 = int64_t(u.chunk) * kLrRows, r1 = min<int64_t>(rows, r0 + kLrRows);
-  for (int64_t s0 = r0; s0 < r1; s0 += kLrSub) {
-    const int sr = int(min<int64_t>(kLrSub, r1 - s0));
-    __syncthreads();
-    for (int e = t; e < kLrSub * kMaxCat; e += 256) {
-      const int i = e % kLrSub, c = e / kLrSub;
-      xs[e] = (i < sr && c < M) ? A.at(s0 + i, c) : 0.0;
-    }
-    __syncthreads();
-    if (ti < M && tj < M) {
-      for (int i = 0; i < sr; ++i) {
-        double xv[4], yv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) xv[a] = xs[i + (ti + a) * kLrSub];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) yv[b] = xs[i + (tj + b) * kLrSub];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] += xv[a] * yv[b];
-      }
-    }
-  }
-  double* out = partial + int64_t(u.out) * kG2;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) out[(ti + a) + (tj + b) * kMaxCat] = acc[a][b];
+  const int64_t r0 = int64_t(u.chunk) * kLrRows;
+  const int64_t cnt = max<int64_t>(0, min<int64_t>(rows, r0 + kLrRows) - r0);
+  // symmetric Gram A^T A of the chunk on the FP64 matrix cores (64 x 64, zero padded)
+  wg_gram_mfma<false>(A, A, r0, cnt, cnt, true, partial + int64_t(u.out) * kG2, nullptr, kMaxCat, true, st, st);
 }
 
 __global__ void __launch_bounds__(kCoreWG) k_lr_core(const LrJob* jobs, const double* G, double* Mbuf) {

@@ -64,6 +64,12 @@ struct Cat {
     return col < c1 ? s1 * p1[row + int64_t(col) * ld1] : s2 * p2[row + int64_t(col - c1) * ld2];
   }
   __device__ inline int cols() const { return c1 + c2; }
+  // base of column col (its row 0) and the column's scale
+  __device__ inline const double* colp(int col, double& scale) const {
+    const bool first = col < c1;
+    scale = first ? s1 : s2;
+    return first ? p1 + int64_t(col) * ld1 : p2 + int64_t(col - c1) * ld2;
+  }
 };
 
 __device__ inline Cat cat1(const double* p, int64_t ld, int c) {

@@ -146,8 +146,8 @@ __device__ inline void sym_tile(int s, int& ti, int& tj) {
 // output tiles w, w + waves, ... (upper triangle only for a symmetric Gram,
 // mirrored on output).  out: ld ldo; zero_rest: zeros over the rest of the
 // 64 x 64 block.  Work-groups of 256 or 512 threads.
-template <bool kTwo>
-__device__ void wg_gram_mfma(const Cat& S0, const Cat& S1, int64_t row0, int64_t rows0, int64_t rows1, bool same,
+template <bool kTwo, typename Op>
+__device__ void wg_gram_mfma(const Op& S0, const Op& S1, int64_t row0, int64_t rows0, int64_t rows1, bool same,
                              double* out0, double* out1, int ldo, bool zero_rest, double* st0, double* st1) {
   const int nt = blockDim.x, t = threadIdx.x;
   const int l = t & 63, wave = t >> 6, waves = nt >> 6;
@@ -168,12 +168,9 @@ __device__ void wg_gram_mfma(const Cat& S0, const Cat& S1, int64_t row0, int64_t
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     const int c = sc + cstep * q;
-    const bool a1 = c < S0.c1, b1 = c < S1.c1;
-    q0[q] = c < c0 ? (a1 ? S0.p1 + int64_t(c) * S0.ld1 : S0.p2 + int64_t(c - S0.c1) * S0.ld2) + row0 : nullptr;
-    q1[q] = (stage1 && c < c1) ? (b1 ? S1.p1 + int64_t(c) * S1.ld1 : S1.p2 + int64_t(c - S1.c1) * S1.ld2) + row0
-                               : nullptr;
-    f0[q] = a1 ? S0.s1 : S0.s2;
-    f1[q] = b1 ? S1.s1 : S1.s2;
+    f0[q] = f1[q] = 0.0;
+    q0[q] = c < c0 ? S0.colp(c, f0[q]) + row0 : nullptr;
+    q1[q] = (stage1 && c < c1) ? S1.colp(c, f1[q]) + row0 : nullptr;
   }
   double v0[kQ], v1[kQ];
 #pragma unroll
