@@ -186,7 +186,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args, probs)
+        cpu = cpu_baseline(args, probs, K)
 
     if args.workload == "var_1d":
         metric = "HODLR solve steps/s (1D N=65536) at rel.err 1e-10"
@@ -471,7 +471,7 @@ def measured_traffic(name, prec):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(args, probs):
+def cpu_baseline(args, probs, K):
     """The oracle as it stands (dense LU + double-double refined steps) on a
     bounded sample: N = 4096 of the same workload, both alphas, 8 steps; the
     whole-workload rate is extrapolated with the oracle's own cost model
@@ -498,12 +498,12 @@ def cpu_baseline(args, probs):
         t_lu += t1 - t0
         t_step += (t2 - t1) / steps0
     scale = args.n / n0
-    t_full = t_lu * scale ** 3 + args.euler_steps * t_step * scale ** 2
-    return {"value": len(probs) * args.euler_steps / t_full, "unit": "problem-steps/s", "cores": cores,
+    t_full = t_lu * scale ** 3 + K * t_step * scale ** 2
+    return {"value": len(probs) * K / t_full, "unit": "problem-steps/s", "cores": cores,
             "kind": "oracle",
             "sample": f"N={n0}, alpha=1.2 and 1.8, dense LU + {steps0} double-double refined steps "
                       f"(LU {t_lu:.2f} s, {1e3 * t_step:.1f} ms/step for both); extrapolated to N={args.n}, "
-                      f"{args.euler_steps} steps with LU ~ N^3 and a step ~ N^2",
+                      f"{K} steps with LU ~ N^3 and a step ~ N^2",
             "sample_problem_steps_per_s": len(probs) / t_step}
 
 

@@ -30,6 +30,31 @@ __device__ inline double cvt(double v) { return v; }
 __device__ inline double cvt(float v) { return double(v); }
 __device__ inline double cvt(bf16 v) { return double(__uint_as_float(uint32_t(v.v) << 16)); }
 
+// Buffer loads whose range check returns zero without a memory access: a
+// wave can issue every load of a block at once and fetch only the entries a
+// product uses.
+constexpr int kOob = 0x7ffffff0;               // byte offset past every buffer: loads return 0
+
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                           int(min<int64_t>(bytes, int64_t(0x7fffffff))), 0x00020000);
+}
+__device__ inline float bload(__amdgpu_buffer_rsrc_t r, int off, const float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline double bload(__amdgpu_buffer_rsrc_t r, int off, const double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline bf16 bload(__amdgpu_buffer_rsrc_t r, int off, const bf16*) {
+  return bf16{__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)};
+}
+
+// rank of the ancestor at depth `lane` of the work unit's leaf (0 for lanes >= L)
+__device__ inline int level_ranks(const int32_t* ranks, const WorkUnit& w, int lane) {
+  return lane < w.L ? ranks[w.node0 + ((int64_t(1) << lane) - 1) + (w.leaf >> (w.L - lane))] : 0;
+}
+
+
 
 // Partial projections of the leaf's rows v (LDS, m x nc, ld 64) onto the
 // basis B of every level where the leaf lies in the source child.  The 256
@@ -45,22 +70,34 @@ __device__ void leaf_project(const DevPtrs& P, const Item& it, int leaf, const N
   const int slot = t >> 5, s = t & 31;
   const int m = lf.size;
   const int64_t gl = it.leaf0 + leaf;
+  // rows in flight: with many columns each entry feeds NC FMAs, so fewer suffice
+  constexpr int kRB = NC == 1 ? (sizeof(TF) == 8 ? 32 : 64) : (sizeof(TF) == 8 ? 8 : 16);
   for (int d = slot; d < it.L; d += 8) {
     const int side = (leaf >> (it.L - d - 1)) & 1;
     if (side != src_side) continue;
     const int64_t nidx = node_index(it, d, leaf >> (it.L - d));
     const int r = ranks[nidx];
-    if (s >= r) continue;
-    const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + int64_t(s) * it.n;
+    const __amdgpu_buffer_rsrc_t R = buf_rsrc(Bb + it.lvl0 + int64_t(d) * it.n * kRS, it.n * kRS * int64_t(sizeof(TF)));
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int i = 0; i < m; ++i) {
-      const double bv = ld(Bd + i);
+#pragma unroll 1
+    for (int i0 = 0; i0 < 64; i0 += kRB) {
+      TF raw[kRB];
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (c < nc) acc[c] += bv * vl[i + c * 64];
+      for (int q = 0; q < kRB; ++q) {
+        const int i = i0 + q;
+        raw[q] = bload(R, (s < r && i < m) ? int((lf.start + i + int64_t(s) * it.n) * sizeof(TF)) : kOob,
+                       (const TF*)nullptr);
+      }
+#pragma unroll
+      for (int q = 0; q < kRB; ++q) {
+        const double bv = cvt(raw[q]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += bv * vl[i0 + q + c * 64];
+      }
     }
+    if (s >= r) continue;
     double* pout = part + (int64_t(d) * leaves + gl) * int64_t(kRS) * nc + s;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -79,9 +116,9 @@ __global__ void __launch_bounds__(256) k_project(DevPtrs P, const WorkUnit* wu, 
   const int t = threadIdx.x;
   const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
   const int src_side = which == 0 ? 0 : 1;
-  for (int e = t; e < lf.size * nc; e += blockDim.x) {
-    const int i = e % lf.size, c = e / lf.size;
-    vl[i + c * 64] = x[it.row0 + lf.start + i + c * ldx];
+  for (int e = t; e < 64 * NC; e += blockDim.x) {    // rows past the leaf and columns past nc are zero
+    const int i = e % 64, c = e / 64;
+    vl[e] = (i < lf.size && c < nc) ? x[it.row0 + lf.start + i + c * ldx] : 0.0;
   }
   __syncthreads();
   leaf_project<TF, NC>(P, it, w.leaf, lf, Bb, ranks, src_side, vl, nc, part, leaves);
@@ -147,6 +184,7 @@ __global__ void __launch_bounds__(256) k_expand(DevPtrs P, SolveFactors<TF, TL> 
                                                 int nc, const double* z, double* next_part, int64_t leaves, int b) {
   __shared__ double vl[64 * NC];
   __shared__ double yl[4][64 * NC];
+  __shared__ double zl[3][kRS * NC];                 // z of a level node, row-major (q, c)
   __shared__ int pm[64];
   const WorkUnit w = wu[blockIdx.x];
   const Item it = P.items[w.item];
@@ -155,55 +193,77 @@ __global__ void __launch_bounds__(256) k_expand(DevPtrs P, SolveFactors<TF, TL> 
   const int slot = t >> 6, row = t & 63;
   const int m = lf.size;
   const int64_t gl = it.leaf0 + w.leaf;
-  const TL* Fi = F.LUinv + gl * int64_t(b) * b;
   const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
   const TF* Bb = which == 0 ? F.IL : F.IU;
   const int dst_side = which == 0 ? 1 : 0;
-  for (int e = t; e < m * nc; e += blockDim.x) {
-    const int i = e % m, c = e / m;
-    vl[i + c * 64] = xin[it.row0 + lf.start + i + c * ldx];
+  for (int e = t; e < 64 * NC; e += blockDim.x) {    // rows past the leaf and columns past nc are zero
+    const int i = e % 64, c = e / 64;
+    vl[e] = (i < m && c < nc) ? xin[it.row0 + lf.start + i + c * ldx] : 0.0;
   }
-  if (t < m) pm[t] = P.perm[gl * b + t];
+  if (t < 64) pm[t] = t < m ? P.perm[gl * b + t] : 0;
+  const int rk = level_ranks(ranks, w, row);
   __syncthreads();
   double acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-  if (row < m) {
-    if (slot == 0) {
-      if (which == 0) {
+  if (slot == 0) {
+    // leaf block: only the triangle the product uses is fetched, all columns at once
+    constexpr int kLB = 8;
+    const __amdgpu_buffer_rsrc_t R = buf_rsrc(F.LUinv + gl * int64_t(b) * b, int64_t(b) * b * int64_t(sizeof(TL)));
+    if (which == 0 && row < m) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (c < nc) acc[c] = vl[pm[row] + c * 64];
-        for (int j = 0; j < row; ++j) {
-          const double f = ld(Fi + row + j * b);
-          const int pj = pm[j];
+      for (int c = 0; c < NC; ++c) acc[c] = vl[pm[row] + c * 64];     // unit diagonal of L^{-1}
+    }
+#pragma unroll 1
+    for (int j0 = 0; j0 < 64; j0 += kLB) {
+      TL raw[kLB];
 #pragma unroll
-          for (int c = 0; c < NC; ++c)
-            if (c < nc) acc[c] += f * vl[pj + c * 64];
-        }
-      } else {
-        for (int j = row; j < m; ++j) {
-          const double f = ld(Fi + row + j * b);
+      for (int q = 0; q < kLB; ++q) {
+        const int j = j0 + q;
+        const bool use = row < m && j < m && (which == 0 ? j < row : j >= row);
+        raw[q] = bload(R, use ? int((int64_t(j) * b + row) * sizeof(TL)) : kOob, (const TL*)nullptr);
+      }
 #pragma unroll
-          for (int c = 0; c < NC; ++c)
-            if (c < nc) acc[c] += f * vl[j + c * 64];
+      for (int q = 0; q < kLB; ++q) {
+        const double f = cvt(raw[q]);
+        const int src = which == 0 ? pm[j0 + q] : j0 + q;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += f * vl[src + c * 64];
+      }
+    }
+  } else {
+    double* zw = zl[slot - 1];
+    int cnt = 0;
+    for (int d = 0; d < it.L; ++d) {
+      const int side = (w.leaf >> (it.L - d - 1)) & 1;
+      if (side != dst_side) continue;
+      if ((cnt++ % 3) != slot - 1) continue;
+      const int64_t nidx = node_index(it, d, w.leaf >> (it.L - d));
+      const int r = __builtin_amdgcn_readlane(rk, d);
+      const __amdgpu_buffer_rsrc_t R =
+          buf_rsrc(Bb + it.lvl0 + int64_t(d) * it.n * kRS, it.n * kRS * int64_t(sizeof(TF)));
+      const double* zn = z + nidx * int64_t(kRS) * nc;
+      for (int e = row; e < kRS * NC; e += 64) {
+        const int q = e / NC, c = e % NC;
+        zw[e] = (q < r && c < nc) ? zn[q + c * kRS] : 0.0;
+      }
+      wave_lds_sync();
+      constexpr int kQB = 8;
+#pragma unroll 1
+      for (int q0 = 0; q0 < r; q0 += kQB) {
+        TF raw[kQB];
+#pragma unroll
+        for (int q = 0; q < kQB; ++q)
+          raw[q] = bload(R, (q0 + q < r && row < m) ? int((lf.start + row + int64_t(q0 + q) * it.n) * sizeof(TF))
+                                                     : kOob, (const TF*)nullptr);
+#pragma unroll
+        for (int q = 0; q < kQB; ++q) {
+          const double bv = cvt(raw[q]);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[c] += bv * zw[(q0 + q) * NC + c];
         }
       }
-    } else {
-      for (int d = slot - 1; d < it.L; d += 3) {
-        const int side = (w.leaf >> (it.L - d - 1)) & 1;
-        if (side != dst_side) continue;
-        const int64_t nidx = node_index(it, d, w.leaf >> (it.L - d));
-        const int r = ranks[nidx];
-        const TF* Bd = Bb + it.lvl0 + int64_t(d) * it.n * kRS + lf.start + row;
-        const double* zn = z + nidx * int64_t(kRS) * nc;
-        for (int s = 0; s < r; ++s) {
-          const double bv = ld(Bd + int64_t(s) * it.n);
-#pragma unroll
-          for (int c = 0; c < NC; ++c)
-            if (c < nc) acc[c] += bv * zn[s + c * kRS];
-        }
-      }
+      wave_lds_sync();
     }
   }
 #pragma unroll
@@ -237,27 +297,6 @@ __global__ void __launch_bounds__(256) k_expand(DevPtrs P, SolveFactors<TF, TL> 
 constexpr int kP1Ld = 65;
 constexpr int kP1Cols = 16;                    // columns per transpose pass
 constexpr size_t kSolve1Lds = size_t(4) * kP1Cols * kP1Ld * sizeof(double);
-constexpr int kOob = 0x7ffffff0;               // byte offset past every buffer: loads return 0
-
-__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int64_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
-                                           int(min<int64_t>(bytes, int64_t(0x7fffffff))), 0x00020000);
-}
-__device__ inline float bload(__amdgpu_buffer_rsrc_t r, int off, const float*) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-__device__ inline double bload(__amdgpu_buffer_rsrc_t r, int off, const double*) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ inline bf16 bload(__amdgpu_buffer_rsrc_t r, int off, const bf16*) {
-  return bf16{__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)};
-}
-
-// rank of the ancestor at depth `lane` of the work unit's leaf (0 for lanes >= L)
-__device__ inline int level_ranks(const int32_t* ranks, const WorkUnit& w, int lane) {
-  return lane < w.L ? ranks[w.node0 + ((int64_t(1) << lane) - 1) + (w.leaf >> (w.L - lane))] : 0;
-}
-
 // Partial projections of y (this lane's row value) onto the basis of every
 // level where the leaf lies in the source child; rk = level_ranks(...).
 template <typename TF>
