@@ -118,18 +118,27 @@ __device__ inline void g2l_pad(const double* src, int64_t lsrc, double* dst, int
   }
 }
 
-// sum_{q = lo}^{hi - 1} A[q SA] B[q SB] over LDS operands (constant strides, so
-// that the loads of a batch use immediate offsets from one base address):
-// eight loads of each operand are issued before their products are added into
-// four partial sums (q mod 4), combined at the end in a fixed order.  Reads up
-// to seven entries past hi (inside the work-group's LDS; their products are
-// discarded).
+// LDS views.  A generic pointer into the work-group's LDS is converted once;
+// indexing through the view is then 32-bit, and loads at constant strides
+// from one base take immediate offsets (pairs of them in one instruction).
+typedef __attribute__((address_space(3))) double ldsd;
+typedef __attribute__((address_space(3))) int ldsi;
+__device__ inline ldsd* lds_view(double* p) { return (ldsd*)p; }
+__device__ inline const ldsd* lds_view(const double* p) { return (const ldsd*)p; }
+__device__ inline ldsi* lds_view(int* p) { return (ldsi*)p; }
+
+// sum_{q = lo}^{hi - 1} A[q SA] B[q SB] over LDS operands (constant strides):
+// full batches of eight loads of each operand are issued before their fused
+// products go into four partial sums (q mod 4), combined at the end in a
+// fixed order; the last partial batch reads up to seven entries past hi
+// (inside the work-group's LDS) and discards their products.
 template <int SA, int SB>
-__device__ inline double lds_dot(const double* A, const double* B, int lo, int hi) {
+__device__ inline double lds_dot(const ldsd* A, const ldsd* B, int lo, int hi) {
   double s4[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int q0 = lo; q0 < hi; q0 += 8) {
-    const double* a = A + q0 * SA;
-    const double* b = B + q0 * SB;
+  int q0 = lo;
+  for (; q0 + 8 <= hi; q0 += 8) {
+    const ldsd* a = A + q0 * SA;
+    const ldsd* b = B + q0 * SB;
     double x[8], y[8];
 #pragma unroll
     for (int w = 0; w < 8; ++w) {
@@ -137,9 +146,25 @@ __device__ inline double lds_dot(const double* A, const double* B, int lo, int h
       y[w] = b[w * SB];
     }
 #pragma unroll
-    for (int w = 0; w < 8; ++w) s4[w & 3] += (q0 + w < hi) ? x[w] * y[w] : 0.0;
+    for (int w = 0; w < 8; ++w) s4[w & 3] = fma(x[w], y[w], s4[w & 3]);
+  }
+  if (q0 < hi) {
+    const ldsd* a = A + q0 * SA;
+    const ldsd* b = B + q0 * SB;
+    double x[8], y[8];
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      x[w] = a[w * SA];
+      y[w] = b[w * SB];
+    }
+#pragma unroll
+    for (int w = 0; w < 8; ++w) s4[w & 3] = (q0 + w < hi) ? fma(x[w], y[w], s4[w & 3]) : s4[w & 3];
   }
   return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+}
+template <int SA, int SB>
+__device__ inline double lds_dot(const double* A, const double* B, int lo, int hi) {
+  return lds_dot<SA, SB>(lds_view(A), lds_view(B), lo, hi);
 }
 
 __device__ inline void wg_sync() {
@@ -294,8 +319,11 @@ __device__ inline int pivot_lane(unsigned key) { return 63 - int(wave_max_u32(ke
 // the new column left-looking from the columns already made.  Stops when the
 // largest remaining diagonal entry falls below delta * (largest initial one).
 // G is read only.
-__device__ int wave_pchol(const double* G, int R, double* Lc, double delta) {
+__device__ int wave_pchol(const double* Gg, int R, double* Lg, double delta) {
+  const ldsd* G = lds_view(Gg);
+  ldsd* Lc = lds_view(Lg);
   const int lane = threadIdx.x & 63;
+  const int rl = lane < R ? lane : 0;          // lanes past R read row 0 and write zeros
   double dv = lane < R ? G[lane + lane * kLdG] : 0.0;
   bool done = lane >= R;
   double dmax0 = 0.0;
@@ -306,12 +334,12 @@ __device__ int wave_pchol(const double* G, int R, double* Lc, double delta) {
     if (k == 0) dmax0 = dp;
     if (!(dp > delta * dmax0) || !(dp > 0.0)) break;
     const double piv = sqrt(dp);
-    double sum = lane < R ? G[lane + p * kLdG] : 0.0;
-    sum -= lds_dot<kLdG, kLdG>(Lc + lane, Lc + p, 0, k);
-    double c = sum / piv;
+    const double rpiv = 1.0 / piv;             // independent of the dot below
+    const double sum = G[rl + p * kLdG] - lds_dot<kLdG, kLdG>(Lc + rl, Lc + p, 0, k);
+    double c = sum * rpiv;
     if (lane == p) c = piv;
     if (done) c = 0.0;
-    if (lane < R) Lc[lane + k * kLdG] = c;
+    Lc[lane + k * kLdG] = c;
     if (lane == p) done = true;
     else if (!done) dv -= c * c;
     wave_lds_sync();
@@ -331,13 +359,16 @@ __device__ int wave_pchol(const double* G, int R, double* Lc, double delta) {
 // row s; tv[s] is its scalar.  Two work-group barriers per step: one to add
 // up the column norms (and publish row s), one to add up the reflector dots.
 // scr: 576 doubles of LDS scratch.
-__device__ int wg_qrcp(double* K, int kA, int kB, double tau, int* perm, double* tv, double* scr) {
+__device__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int* permg, double* tvg, double* scr) {
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const bool mine = wave < 4;
   const int r0 = (mine ? wave : 0) * 16;
-  double* s_nb = scr;              // 4 x 64 partial norms
-  double* s_db = scr + 256;        // 4 x 64 partial dots
-  double* s_row = scr + 512;       // row s
+  ldsd* K = lds_view(Kg);
+  ldsi* perm = lds_view(permg);
+  ldsd* tv = lds_view(tvg);
+  ldsd* s_nb = lds_view(scr);          // 4 x 64 partial norms
+  ldsd* s_db = s_nb + 256;             // 4 x 64 partial dots
+  ldsd* s_row = s_nb + 512;            // row s
   double kr[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) kr[k] = (mine && r0 + k < kA && lane < kB) ? K[r0 + k + lane * kLdG] : 0.0;
@@ -424,17 +455,20 @@ __device__ int wg_qrcp(double* K, int kA, int kB, double tau, int* perm, double*
 // implicit), by waves 0..3 (blockDim >= 256): lane c forms column c, wave w
 // keeps rows 16w..16w+15 in registers; one barrier per reflector to add up
 // the four partial dots.  scr: 512 doubles of LDS scratch.
-__device__ void wg_form_q(const double* Vp, int kA, int r, const double* tv, double* Q, double* scr) {
+__device__ void wg_form_q(const double* Vg, int kA, int r, const double* tvg, double* Qg, double* scr) {
   const int t = threadIdx.x, wave = t >> 6, c = t & 63;
   const bool mine = wave < 4;
   const int r0 = (mine ? wave : 0) * 16;
-  double (*s_pd)[4 * 64] = reinterpret_cast<double (*)[4 * 64]>(scr);   // 2 x 4 x 64 partial dots
+  const ldsd* Vp = lds_view(Vg);
+  const ldsd* tv = lds_view(tvg);
+  ldsd* Q = lds_view(Qg);
+  ldsd* s_pd0 = lds_view(scr);         // 2 x 4 x 64 partial dots
   double q[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) q[k] = (r0 + k == c) ? 1.0 : 0.0;
   for (int s = r - 1; s >= 0; --s) {
     double v[16];
-    const double* vs = Vp + s * kLdG + r0;
+    const ldsd* vs = Vp + s * kLdG + r0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = vs[k];
 #pragma unroll
@@ -442,9 +476,9 @@ __device__ void wg_form_q(const double* Vp, int kA, int r, const double* tv, dou
     double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 16; ++k) d4[k & 3] += v[k] * q[k];
-    if (mine) s_pd[s & 1][wave * 64 + c] = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+    if (mine) s_pd0[(s & 1) * 256 + wave * 64 + c] = (d4[0] + d4[1]) + (d4[2] + d4[3]);
     __syncthreads();
-    const double* pd = s_pd[s & 1];
+    const ldsd* pd = s_pd0 + (s & 1) * 256;
     const double w = tv[s] * (((pd[c] + pd[64 + c]) + pd[128 + c]) + pd[192 + c]);
 #pragma unroll
     for (int k = 0; k < 16; ++k) q[k] -= w * v[k];
@@ -470,40 +504,44 @@ struct RecompressOut {
 // lds::LB, so that U' = A M_U, V' = B M_V and U' V'^T = A B^T up to the
 // discarded trailing block of K.  Waves 0 and 1 factor the two Grams
 // concurrently; wave 0 runs the QR; the rest is work-group parallel.
-__device__ RecompressOut wg_core_grams(double* L, int R, double tau, int rmax) {
+__device__ RecompressOut wg_core_grams(double* Lg, int R, double tau, int rmax) {
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
   RecompressOut out{0, false};
-  double* G = L + lds::G;
-  double* LA = L + lds::LA;
-  double* LB = L + lds::LB;
-  double* KC = L + lds::KC;
-  double* red = L + lds::RED;
-  double* vec = L + lds::VEC;     // [0,64) dA  [64,128) dB  [128,192) D  [256,320) tv
-  int* perm = reinterpret_cast<int*>(L + lds::IVEC) + 64;
+  ldsd* L = lds_view(Lg);
+  ldsd* G = L + lds::G;
+  ldsd* LA = L + lds::LA;
+  ldsd* LB = L + lds::LB;
+  ldsd* KC = L + lds::KC;
+  ldsd* red = L + lds::RED;
+  ldsd* vec = L + lds::VEC;     // [0,64) dA [64,128) dB [128,192) D [192,256) 1/D [256,320) tv [320,384) 1/R(j,j)
+  int* permg = reinterpret_cast<int*>(Lg + lds::IVEC) + 64;
+  const ldsi* perm = lds_view(permg);
   __shared__ int s_k[3];
   for (int j = t; j < R; j += blockDim.x) {
     const double a = G[j + j * kLdG], b = KC[j + j * kLdG];
     // (b / a)^(1/4) from the two fourth roots: no overflow for tiny a
-    vec[128 + j] = (a > 0.0 && b > 0.0) ? sqrt(sqrt(b)) / sqrt(sqrt(a)) : 1.0;
+    const bool both = a > 0.0 && b > 0.0;
+    const double qa = sqrt(sqrt(a)), qb = sqrt(sqrt(b));
+    vec[128 + j] = both ? qb / qa : 1.0;
+    vec[192 + j] = both ? qa / qb : 1.0;
     vec[j] = a;
     vec[64 + j] = b;
   }
   wg_sync();
   for (int e = t; e < R * R; e += blockDim.x) {
     const int i = e % R, j = e / R;
-    const double di = vec[128 + i], dj = vec[128 + j];
     const bool zi = !(vec[i] > 0.0 && vec[64 + i] > 0.0), zj = !(vec[j] > 0.0 && vec[64 + j] > 0.0);
-    G[i + j * kLdG] = (zi || zj) ? 0.0 : G[i + j * kLdG] * di * dj;
-    KC[i + j * kLdG] = (zi || zj) ? 0.0 : KC[i + j * kLdG] / (di * dj);
+    G[i + j * kLdG] = (zi || zj) ? 0.0 : G[i + j * kLdG] * (vec[128 + i] * vec[128 + j]);
+    KC[i + j * kLdG] = (zi || zj) ? 0.0 : KC[i + j * kLdG] * (vec[192 + i] * vec[192 + j]);
   }
   wg_sync();
   const double delta = 1e-15 * R;
   if (wave == 0) {
-    const int k = wave_pchol(G, R, LA, delta);
+    const int k = wave_pchol(Lg + lds::G, R, Lg + lds::LA, delta);
     if (lane == 0) s_k[0] = k;
   } else if (wave == 1) {
-    const int k = wave_pchol(KC, R, LB, delta);
+    const int k = wave_pchol(Lg + lds::KC, R, Lg + lds::LB, delta);
     if (lane == 0) s_k[1] = k;
   }
   wg_sync();
@@ -514,14 +552,15 @@ __device__ RecompressOut wg_core_grams(double* L, int R, double tau, int rmax) {
     KC[i + j * kLdG] = lds_dot<1, 1>(LA + i * kLdG, LB + j * kLdG, 0, R);
   }
   wg_sync();
-  const int rq = wg_qrcp(KC, kA, kB, tau, perm, vec + 256, red);   // RED is free until M_U
+  const int rq = wg_qrcp(Lg + lds::KC, kA, kB, tau, permg, Lg + lds::VEC + 256, Lg + lds::RED);   // RED is free until M_U
   const int rr = rq < rmax ? rq : rmax;
   for (int e = t; e < kA * rr; e += blockDim.x) {   // R factor and vectors in pivot order
     const int i = e % kA, c = e / kA;
     G[i + c * kLdG] = KC[i + perm[c] * kLdG];
   }
   wg_sync();
-  wg_form_q(G, kA, rr, vec + 256, KC, red);
+  for (int j = t; j < rr; j += blockDim.x) vec[320 + j] = 1.0 / G[j + j * kLdG];
+  wg_form_q(Lg + lds::G, kA, rr, Lg + lds::VEC + 256, Lg + lds::KC, Lg + lds::RED);   // ends with a barrier
   if (t == 0) s_k[2] = rq;
   wg_sync();
   int r = s_k[2];
@@ -534,14 +573,14 @@ __device__ RecompressOut wg_core_grams(double* L, int R, double tau, int rmax) {
   for (int i = t; i < R; i += blockDim.x) {
     for (int j = 0; j < r; ++j) {
       const double x = LB[i + perm[j] * kLdG] - lds_dot<kMaxCat, 1>(red + i, G + j * kLdG, 0, j);
-      red[i + j * kMaxCat] = x / G[j + j * kLdG];
+      red[i + j * kMaxCat] = x * vec[320 + j];
     }
     for (int j = 0; j < r; ++j) red[i + j * kMaxCat] *= vec[128 + i];
   }
   wg_sync();
   for (int e = t; e < R * r; e += blockDim.x) {
     const int i = e % R, j = e / R;
-    LB[i + j * kLdG] = lds_dot<kLdG, 1>(LA + i, KC + j * kLdG, 0, kA) / vec[128 + i];
+    LB[i + j * kLdG] = lds_dot<kLdG, 1>(LA + i, KC + j * kLdG, 0, kA) * vec[192 + i];
   }
   wg_sync();
   return out;
