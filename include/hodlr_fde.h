@@ -61,7 +61,7 @@ typedef struct fde2d_plan_s* fde2d_plan;
  * shift = 1/2 (+ an ADI shift) for the coefficients of the 2D Sylvester
  * step (eq. (sylv-timestepping)). */
 typedef struct {
-  int64_t n;              /* interior grid points, 1 <= N <= 2^23 (eq. (part)) */
+  int64_t n;              /* interior grid points, 1 <= N < 2^23 (eq. (part)) */
   double alpha;           /* fractional order, 1 <= alpha <= 2 */
   double dt, dx;          /* time step and grid spacing; nu = dt/dx^alpha */
   double shift;           /* identity shift s > 0 */

@@ -891,9 +891,10 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   if (opts->prec < HODLR_FP64 || opts->prec > HODLR_MIXED_BF16) return set_arg(ctx, 4);
   for (int i = 0; i < batch; ++i) {
     const fde_operator& o = ops[i];
-    // the solve kernels address a level's factor block (n x 32 values) with
-    // 32-bit byte offsets
-    if (o.n < 1 || o.n > (int64_t(1) << 23) || !(o.alpha >= 1.0 && o.alpha <= 2.0) || !(o.dt > 0.0) ||
+    // the solve and product kernels address a level's factor block (n x 32
+    // values) with 32-bit byte offsets that must stay below the out-of-range
+    // sentinel kOob, so n x 32 x 8 < 2^31 - 16
+    if (o.n < 1 || o.n >= (int64_t(1) << 23) || !(o.alpha >= 1.0 && o.alpha <= 2.0) || !(o.dt > 0.0) ||
         !(o.dx > 0.0) || !(o.shift > 0.0) || !o.d_plus || !o.d_minus)
       return set_arg(ctx, 2);
   }

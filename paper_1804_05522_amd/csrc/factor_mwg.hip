@@ -562,7 +562,7 @@ constexpr int kPNC = kRS;   // columns of a subtree product
 constexpr int kSpWaves = 4;          // waves of the subtree-product kernels (256 threads)
 constexpr int kSpLd = 65;            // LDS stride of staged 64-row blocks
 constexpr size_t kSpProjLds = size_t(64 * kPNC + kSpWaves * kSpLd * kRS) * sizeof(double);
-constexpr size_t kSpExpLds = size_t(64 * kPNC + 64 * kSpLd + (kSpWaves - 1) * (kSpLd * kRS + kRS * kPNC)) * sizeof(double);
+constexpr size_t kSpExpLds = size_t(64 * kPNC + 64 * kSpLd + 64 * kPNC) * sizeof(double);
 
 // Partial projections B_d(leaf rows)^T X(leaf rows) for every subtree level d
 // where the leaf is on the source side.  The source levels are dealt
@@ -671,19 +671,27 @@ __global__ void __launch_bounds__(256) k_sp_reduce(DevPtrs P, const ProdJob* job
   }
 }
 
-// Y rows of the leaf = sign * (leaf op X + sum over destination levels B_d z_d).
-// All operands of the leaf op (X rows, the leaf's inverse factors, pivots)
-// are staged in one round trip; wave 0 applies the leaf op while waves 1..3
-// take the destination levels round-robin (a wave stages z_d in its LDS slice
-// and keeps its lane's row of B_d in registers); the four partial sums are
-// added in a fixed order.
+// Y rows of the leaf = sign * (leaf op X + sum over destination levels B_d z_d)
+// on the FP64 matrix cores.  Wave w owns rows 16w..16w+15 of the leaf and
+// both 16-column tiles of the (at most 32) columns.  The leaf op is sixteen
+// k-steps of four rows over the staged X rows and inverse factors (the unit
+// diagonal of L^{-1} and the triangles taken by masks); each destination
+// level adds ceil(r/4) k-steps whose operands, the leaf's rows of B_d and the
+// node's z_d, come from range-checked buffer loads, the next level's issued
+// before the current level is multiplied.  P L^{-T} x permutes the rows of
+// the leaf op's product, which is therefore staged in LDS and gathered before
+// the levels are added.
+struct SpLevel {
+  double a[kRS / 4], z0[kRS / 4], z1[kRS / 4];
+  int steps;
+};
+
 __global__ void __launch_bounds__(256) k_sp_expand(DevPtrs P, const ProdJob* jobs, const ProdUnit* units,
                                                    const double* z, int b) {
   extern __shared__ double sm[];
-  double* xl = sm;                                   // 64 x kPNC
-  double* Fl = xl + 64 * kPNC;                       // 64 x 64, ld kSpLd
-  double* ww = Fl + 64 * kSpLd;                      // per level wave: B rows (64 x kRS, ld kSpLd), z_d
-  constexpr int kSlice = kSpLd * kRS + kRS * kPNC;   // then its partial sum (64 x kPNC) over the B rows
+  double* xl = sm;                                   // 64 x kPNC, ld 64, zero past the leaf and nc
+  double* Fl = xl + 64 * kPNC;                       // 64 x 64, ld kSpLd, zero past the leaf
+  double* yl = Fl + 64 * kSpLd;                      // 64 x kPNC, ld 64
   __shared__ int pm[64], pmi[64];
   const ProdUnit u = units[blockIdx.x];
   const ProdJob jb = jobs[u.job];
@@ -693,107 +701,100 @@ __global__ void __launch_bounds__(256) k_sp_expand(DevPtrs P, const ProdJob* job
   const int m = lf.size, nc = prod_cols(P, it, jb);
   const double* X = lvl_ptr(arr_base(P, jb.xarr), it, jb.xlev) + lf.start;
   double* Y = lvl_ptr(arr_base(P, jb.yarr), it, jb.ylev) + lf.start;
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int t = threadIdx.x, wave = t >> 6, l = t & 63;
+  const int li = l & 15, lk = l >> 4;
   const int64_t gl = it.leaf0 + leaf;
-  const double* Fi = P.LUinv + gl * int64_t(b) * b;
   g2l_pad(X, it.n, xl, 64, m, nc, 64, kPNC);
-  g2l(Fi, b, Fl, kSpLd, m, m);
-  if (t < m) {
-    pm[t] = P.perm[gl * b + t];
-    pmi[t] = P.perminv[gl * b + t];
+  g2l_pad(P.LUinv + gl * int64_t(b) * b, b, Fl, kSpLd, m, m, 64, 64);
+  if (t < 64) {
+    pm[t] = t < m ? P.perm[gl * b + t] : t;
+    pmi[t] = t < m ? P.perminv[gl * b + t] : t;
   }
   __syncthreads();
-  const int row = lane;
-  double acc[kPNC];
+  const bool two = nc > 16;
+  // 0: L^{-1} P^T x   1: P L^{-T} x   2: U^{-1} x   3: U^{-T} x
+  const int var = 2 * jb.which + jb.trans;
+  const int i = wave * 16 + li;                      // row of this lane's leaf-op operand
+  const double* fa = (var & 1) ? Fl + i * kSpLd : Fl + i;
+  const int fs = (var & 1) ? 1 : kSpLd;
+  hfde_d4 acc0{0.0, 0.0, 0.0, 0.0}, acc1{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int c = 0; c < kPNC; ++c) acc[c] = 0.0;
-  if (wave == 0) {
-    if (row < m) {
-      if (jb.which == 0 && !jb.trans) {            // L^{-1} P^T x
+  for (int s4 = 0; s4 < 16; ++s4) {
+    const int k = 4 * s4 + lk;
+    const bool tri = var == 0 ? k < i : (var == 1 ? k > i : (var == 2 ? k >= i : k <= i));
+    const double a = tri ? fa[k * fs] : ((var < 2 && k == i) ? 1.0 : 0.0);
+    const int xr = var == 0 ? pm[k] : k;
+    acc0 = mfma64(a, xl[xr + li * 64], acc0);
+    if (two) acc1 = mfma64(a, xl[xr + (16 + li) * 64], acc1);
+  }
+  if (var == 1) {                                    // rows of L^{-T} x in pivot order: gather
 #pragma unroll
-        for (int c = 0; c < kPNC; ++c) acc[c] = xl[pm[row] + c * 64];
-        for (int jj = 0; jj < row; ++jj) {
-          const double f = Fl[row + jj * kSpLd];
-          const int pj = pm[jj];
-#pragma unroll
-          for (int c = 0; c < kPNC; ++c) acc[c] += f * xl[pj + c * 64];
-        }
-      } else if (jb.which == 0) {                   // P L^{-T} x
-        const int q = pmi[row];
-#pragma unroll
-        for (int c = 0; c < kPNC; ++c) acc[c] = xl[q + c * 64];
-        for (int jj = q + 1; jj < m; ++jj) {
-          const double f = Fl[jj + q * kSpLd];
-#pragma unroll
-          for (int c = 0; c < kPNC; ++c) acc[c] += f * xl[jj + c * 64];
-        }
-      } else if (!jb.trans) {                       // U^{-1} x
-        for (int jj = row; jj < m; ++jj) {
-          const double f = Fl[row + jj * kSpLd];
-#pragma unroll
-          for (int c = 0; c < kPNC; ++c) acc[c] += f * xl[jj + c * 64];
-        }
-      } else {                                      // U^{-T} x
-        for (int jj = 0; jj <= row; ++jj) {
-          const double f = Fl[jj + row * kSpLd];
-#pragma unroll
-          for (int c = 0; c < kPNC; ++c) acc[c] += f * xl[jj + c * 64];
-        }
-      }
+    for (int v = 0; v < 4; ++v) {
+      yl[wave * 16 + 4 * v + lk + li * 64] = acc0[v];
+      yl[wave * 16 + 4 * v + lk + (16 + li) * 64] = acc1[v];
     }
-  } else {
-    const bool src_c1 = (jb.which == 0) ? !jb.trans : jb.trans;
-    const double* Bb = jb.which == 0 ? P.IL : P.IU;
-    const int32_t* ranks = jb.which == 0 ? P.rankL : P.rankU;
-    double* Bl = ww + (wave - 1) * kSlice;
-    double* zl = Bl + kSpLd * kRS;
-    int cnt = 0;
-    for (int d = jb.d0; d < it.L; ++d) {
-      const int side = (leaf >> (it.L - d - 1)) & 1;
-      if (side != (src_c1 ? 1 : 0)) continue;
-      if ((cnt++ % (kSpWaves - 1)) != wave - 1) continue;
-      const int64_t jn = leaf >> (it.L - d);
-      const int r = ranks[node_index(it, d, jn)];
-      const int64_t slot = ((int64_t(1) << (d - jb.d0)) - 1) + (jn - (int64_t(jb.j0) << (d - jb.d0)));
-      const double* zn = z + (int64_t(jb.node0) + slot) * kRS * kPNC;
-      const double* Bd = lvl_ptr(const_cast<double*>(Bb), it, d) + lf.start + row;
-      {
-        double bv[kRS];
+    __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kRS; ++q) bv[q] = (q < r && row < m) ? Bd[int64_t(q) * it.n] : 0.0;
-        double zv[kRS * kPNC / 64];
-#pragma unroll
-        for (int k = 0; k < kRS * kPNC / 64; ++k) {
-          const int e = lane + 64 * k, q = e % kRS, c = e / kRS;
-          zv[k] = (q < r && c < nc) ? zn[q + c * kRS] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < kRS; ++q) Bl[row + q * kSpLd] = bv[q];
-#pragma unroll
-        for (int k = 0; k < kRS * kPNC / 64; ++k) zl[lane + 64 * k] = zv[k];
-      }
-      wave_lds_sync();
-      for (int q = 0; q < r; ++q) {
-        const double bq = Bl[row + q * kSpLd];
-#pragma unroll
-        for (int c = 0; c < kPNC; ++c) acc[c] += bq * zl[q + c * kRS];
-      }
-      wave_lds_sync();
+    for (int v = 0; v < 4; ++v) {
+      const int q = pmi[wave * 16 + 4 * v + lk];
+      acc0[v] = yl[q + li * 64];
+      acc1[v] = yl[q + (16 + li) * 64];
     }
-    double* yo = Bl;                                 // 64 x kPNC partial over this wave's levels
+    __syncthreads();
+  }
+  // destination levels
+  const bool src_c1 = (jb.which == 0) ? !jb.trans : jb.trans;
+  const int dst_side = src_c1 ? 1 : 0;
+  const double* Bb = jb.which == 0 ? P.IL : P.IU;
+  const int32_t* ranks = jb.which == 0 ? P.rankL : P.rankU;
+  auto next_level = [&](int d) {
+    for (++d; d < it.L; ++d)
+      if (((leaf >> (it.L - d - 1)) & 1) == dst_side) break;
+    return d;
+  };
+  auto fetch = [&](int d, SpLevel& o) {
+    const int64_t jn = leaf >> (it.L - d);
+    const int r = ranks[node_index(it, d, jn)];
+    const int64_t slot = ((int64_t(1) << (d - jb.d0)) - 1) + (jn - (int64_t(jb.j0) << (d - jb.d0)));
+    const __amdgpu_buffer_rsrc_t RB =
+        buf_rsrc(lvl_ptr(const_cast<double*>(Bb), it, d), it.n * kRS * int64_t(sizeof(double)));
+    const __amdgpu_buffer_rsrc_t RZ =
+        buf_rsrc(z + (int64_t(jb.node0) + slot) * kRS * kPNC, int64_t(kRS) * kPNC * sizeof(double));
+    o.steps = (r + 3) >> 2;
 #pragma unroll
-    for (int c = 0; c < kPNC; ++c) yo[row + c * 64] = acc[c];
+    for (int s4 = 0; s4 < kRS / 4; ++s4) {
+      const int q = 4 * s4 + lk;
+      o.a[s4] = bload(RB, (q < r && i < m) ? int((lf.start + i + int64_t(q) * it.n) * sizeof(double)) : kOob,
+                      (const double*)nullptr);
+      o.z0[s4] = bload(RZ, (q < r && li < nc) ? int((q + li * kRS) * sizeof(double)) : kOob, (const double*)nullptr);
+      o.z1[s4] = bload(RZ, (q < r && 16 + li < nc) ? int((q + (16 + li) * kRS) * sizeof(double)) : kOob,
+                       (const double*)nullptr);
+    }
+  };
+  int d = next_level(jb.d0 - 1);
+  SpLevel cur, nxt;
+  if (d < it.L) fetch(d, cur);
+  while (d < it.L) {
+    const int dn = next_level(d);
+    if (dn < it.L) fetch(dn, nxt);
+#pragma unroll
+    for (int s4 = 0; s4 < kRS / 4; ++s4)
+      if (s4 < cur.steps) {
+        acc0 = mfma64(cur.a[s4], cur.z0[s4], acc0);
+        if (two) acc1 = mfma64(cur.a[s4], cur.z1[s4], acc1);
+      }
+    cur = nxt;
+    d = dn;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    yl[wave * 16 + 4 * v + lk + li * 64] = jb.sign * acc0[v];
+    yl[wave * 16 + 4 * v + lk + (16 + li) * 64] = jb.sign * acc1[v];
   }
   __syncthreads();
-  if (wave == 0 && row < m) {
-#pragma unroll
-    for (int c = 0; c < kPNC; ++c)
-      if (c < nc) {
-        double v = acc[c];
-#pragma unroll
-        for (int w = 0; w < kSpWaves - 1; ++w) v += ww[w * kSlice + row + c * 64];
-        Y[row + int64_t(c) * it.n] = jb.sign * v;
-      }
+  for (int e = t; e < m * nc; e += blockDim.x) {
+    const int r0 = e % m, c = e / m;
+    Y[r0 + int64_t(c) * it.n] = yl[r0 + c * 64];
   }
 }
 

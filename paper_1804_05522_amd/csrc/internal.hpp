@@ -134,4 +134,23 @@ __device__ inline double* lvl_ptr(double* base, const Item& it, int d) {
   return base + it.lvl0 + int64_t(d) * it.n * kRS;
 }
 
+// Buffer loads whose range check returns zero without a memory access: a
+// wave can issue every load of a block at once and fetch only the entries a
+// product uses.
+constexpr int kOob = 0x7ffffff0;               // byte offset past every buffer: loads return 0
+
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                           int(min<int64_t>(bytes, int64_t(0x7fffffff))), 0x00020000);
+}
+__device__ inline float bload(__amdgpu_buffer_rsrc_t r, int off, const float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline double bload(__amdgpu_buffer_rsrc_t r, int off, const double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline bf16 bload(__amdgpu_buffer_rsrc_t r, int off, const bf16*) {
+  return bf16{__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)};
+}
+
 }  // namespace hfde

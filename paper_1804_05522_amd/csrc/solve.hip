@@ -30,25 +30,6 @@ __device__ inline double cvt(double v) { return v; }
 __device__ inline double cvt(float v) { return double(v); }
 __device__ inline double cvt(bf16 v) { return double(__uint_as_float(uint32_t(v.v) << 16)); }
 
-// Buffer loads whose range check returns zero without a memory access: a
-// wave can issue every load of a block at once and fetch only the entries a
-// product uses.
-constexpr int kOob = 0x7ffffff0;               // byte offset past every buffer: loads return 0
-
-__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int64_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
-                                           int(min<int64_t>(bytes, int64_t(0x7fffffff))), 0x00020000);
-}
-__device__ inline float bload(__amdgpu_buffer_rsrc_t r, int off, const float*) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-__device__ inline double bload(__amdgpu_buffer_rsrc_t r, int off, const double*) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ inline bf16 bload(__amdgpu_buffer_rsrc_t r, int off, const bf16*) {
-  return bf16{__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)};
-}
-
 // rank of the ancestor at depth `lane` of the work unit's leaf (0 for lanes >= L)
 __device__ inline int level_ranks(const int32_t* ranks, const WorkUnit& w, int lane) {
   return lane < w.L ? ranks[w.node0 + ((int64_t(1) << lane) - 1) + (w.leaf >> (w.L - lane))] : 0;

@@ -140,19 +140,27 @@ def test_learned_warm_start(H, setup):
     assert all(w <= c for w, c in zip(adi_warm, adi_cold)), (adi_warm, adi_cold)
 
 
-def test_exact_guess_cuts_adi_steps(setup):
-    """With the solution itself as the guess the exact residual is at the
-    level of the solver's tolerance: a few blocks of four shifts correct and
-    confirm it, against a full sweep plus a confirming block from the zero
-    guess."""
-    _, P, zero, trajs = setup
+def test_exact_guess_cuts_adi_steps(H, setup):
+    """With the solution itself as the guess (the step solved by a plan at a
+    thousandfold tighter tolerance, so that its residual lies well below the
+    stopping level) a block or two of four shifts confirm it, against a full
+    sweep plus a confirming block from the zero guess."""
+    ctx, P, zero, trajs = setup
     p, lrs, _, adi_cold = trajs[1]
-    for k in range(2):
-        out = newout()
-        r, info = P.step(lrs[k], zero, p.dt, out, allow=(0, 2), guess=lrs[k + 1], guess_rank=lrs[k + 1][0].shape[0])
-        assert info.used_fallback == 0
-        assert info.refine_iters <= 12 and info.refine_iters < adi_cold[k], (info.refine_iters, adi_cold[k])
-        assert rel(dense((out[0][:r], out[1][:r])), dense(lrs[k + 1])) <= 1e-7
+    opx = H.operator_dict(N, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5)
+    opy = H.operator_dict(N, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5)
+    Pt = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-14, prec="fp64", leaf=64), tol=1e-11)
+    try:
+        for k in range(2):
+            ex = newout()
+            re, _ = Pt.step(lrs[k], zero, p.dt, ex, allow=(0, 2))
+            out = newout()
+            r, info = P.step(lrs[k], zero, p.dt, out, allow=(0, 2), guess=(ex[0][:re], ex[1][:re]), guess_rank=re)
+            assert info.used_fallback == 0
+            assert info.refine_iters <= 8 and info.refine_iters < adi_cold[k], (info.refine_iters, adi_cold[k])
+            assert rel(dense((out[0][:r], out[1][:r])), dense(lrs[k + 1])) <= 1e-7
+    finally:
+        Pt.close()
 
 
 def test_bad_guess_falls_back_to_plain_solve(H, setup):
