@@ -359,10 +359,11 @@ __device__ int wave_pchol(const double* Gg, int R, double* Lg, double delta) {
 // row s; tv[s] is its scalar.  Two work-group barriers per step: one to add
 // up the column norms (and publish row s), one to add up the reflector dots.
 // scr: 576 doubles of LDS scratch.
-__device__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int* permg, double* tvg, double* scr) {
+__device__ __noinline__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int* permg, double* tvg, double* scr) {
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const bool mine = wave < 4;
-  const int r0 = (mine ? wave : 0) * 16;
+  const int wv = mine ? wave : 0;
+  const int r0 = wv * 16;
   ldsd* K = lds_view(Kg);
   ldsi* perm = lds_view(permg);
   ldsd* tv = lds_view(tvg);
@@ -377,67 +378,83 @@ __device__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int* permg, doubl
   {
     double p4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) p4[k & 3] += kr[k] * kr[k];
+    for (int k = 0; k < 16; ++k) p4[k & 3] = fma(kr[k], kr[k], p4[k & 3]);
     pn = (p4[0] + p4[1]) + (p4[2] + p4[3]);
   }
   const int kmax = kA < kB ? kA : kB;
-  int s = 0;
-  for (; s < kmax; ++s) {
-    if (mine) {
-      s_nb[wave * 64 + lane] = pn;
-      if (wave == (s >> 4)) {
-        double x = 0.0;
+  int steps = 0;
+  bool go = kmax > 0;
+  // Step s = 16 jp + jj: the unrolled jj makes row s a fixed register of
+  // wave jp, and a wave's rows lie wholly above, at or below row s.
+  for (int jp = 0; jp < 4 && go; ++jp) {
+    const bool w_eq = wv == jp, w_gt = wv > jp;
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (r0 + k == s) x = kr[k];
-        s_row[lane] = x;
+    for (int jj = 0; jj < 16; ++jj) {      // no early exit, so that the loop unrolls
+      const int s = jp * 16 + jj;
+      if (s >= kmax) go = false;
+      if (!go) continue;
+      if (mine) {
+        s_nb[wv * 64 + lane] = pn;
+        if (w_eq) s_row[lane] = kr[jj];
       }
-    }
-    __syncthreads();
-    const double n2 = ((s_nb[lane] + s_nb[64 + lane]) + s_nb[128 + lane]) + s_nb[192 + lane];
-    const double tot = wave_sum_fixed(done ? 0.0 : n2);
-    if (tot <= tau * tau) break;                 // same value in every wave
-    const int p = pivot_lane(pivot_key(n2, !done, lane));
-    const double nrm = sqrt(readlane_d(n2, p));
-    const double x0 = s_row[p];
-    double beta = 0.0, tq = 0.0, sc = 0.0;
-    if (nrm > 0.0) {
-      beta = x0 >= 0 ? -nrm : nrm;
-      tq = (beta - x0) / beta;
-      sc = 1.0 / (x0 - beta);
-    }
-    double v[16];
-    double d4[4] = {0.0, 0.0, 0.0, 0.0};
+      __syncthreads();
+      const double n2 = ((s_nb[lane] + s_nb[64 + lane]) + s_nb[128 + lane]) + s_nb[192 + lane];
+      const double xs = s_row[lane];
+      const double tot = wave_sum_fixed(done ? 0.0 : n2);
+      if (tot <= tau * tau) {                    // same value in every wave
+        go = false;
+        continue;
+      }
+      const int p = pivot_lane(pivot_key(n2, !done, lane));
+      const double nrm = sqrt(readlane_d(n2, p));
+      const double x0 = readlane_d(xs, p);
+      double beta = 0.0, tq = 0.0, sc = 0.0;
+      if (nrm > 0.0) {
+        beta = x0 >= 0 ? -nrm : nrm;
+        const double rb = 1.0 / beta, rd = 1.0 / (x0 - beta);   // independent
+        tq = (beta - x0) * rb;
+        sc = rd;
+      }
+      double v[16];
+      double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const double pk = readlane_d(kr[k], p);
-      v[k] = (r0 + k > s) ? pk * sc : ((r0 + k == s) ? 1.0 : 0.0);
-      d4[k & 3] += v[k] * kr[k];
-    }
-    const double pd = (d4[0] + d4[1]) + (d4[2] + d4[3]);
-    if (mine) s_db[wave * 64 + lane] = pd;
-    if (t == 0) {
-      perm[s] = p;
-      tv[s] = tq;
-    }
-    __syncthreads();
-    const double dot = ((s_db[lane] + s_db[64 + lane]) + s_db[128 + lane]) + s_db[192 + lane];
-    const double wj = tq * dot;
-    if (lane == p) {
+      for (int k = 0; k < 16; ++k) {
+        const double pk = readlane_d(kr[k], p);
+        const bool below = k > jj ? (w_eq || w_gt) : w_gt;     // row r0 + k > s
+        v[k] = below ? pk * sc : ((k == jj && w_eq) ? 1.0 : 0.0);
+        d4[k & 3] = fma(v[k], kr[k], d4[k & 3]);
+      }
+      const double pd = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+      if (mine) s_db[wv * 64 + lane] = pd;
+      if (t == 0) {
+        perm[s] = p;
+        tv[s] = tq;
+      }
+      __syncthreads();
+      const double dot = ((s_db[lane] + s_db[64 + lane]) + s_db[128 + lane]) + s_db[192 + lane];
+      const double wj = tq * dot;
+      if (lane == p) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (r0 + k >= s) kr[k] = (r0 + k == s) ? beta : v[k];
-      done = true;
-    } else if (!done) {
+        for (int k = 0; k < 16; ++k) {
+          const bool at = k == jj && w_eq;
+          const bool below = k > jj ? (w_eq || w_gt) : w_gt;
+          kr[k] = at ? beta : (below ? v[k] : kr[k]);
+        }
+        done = true;
+      } else if (!done) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) kr[k] -= wj * v[k];
-    }
-    {
-      double p4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < 16; ++k) kr[k] = fma(-wj, v[k], kr[k]);
+      }
+      {
+        double p4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (r0 + k > s) p4[k & 3] += kr[k] * kr[k];
-      pn = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+        for (int k = 0; k < 16; ++k) {
+          const bool below = k > jj ? (w_eq || w_gt) : w_gt;
+          p4[k & 3] = below ? fma(kr[k], kr[k], p4[k & 3]) : p4[k & 3];
+        }
+        pn = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+      }
+      ++steps;
     }
   }
   __syncthreads();
@@ -447,7 +464,7 @@ __device__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int* permg, doubl
       if (r0 + k < kA) K[r0 + k + lane * kLdG] = kr[k];
   }
   __syncthreads();
-  return s;
+  return steps;
 }
 
 // Q = H_0 ... H_{r-1} [I_r; 0] (kA x r <= 64 x 32, LDS, ld kLdG) from the
