@@ -847,13 +847,19 @@ __device__ inline bool wg_leaf(const DevPtrs& P, const Item& it, int b, int64_t 
     UI[e] = 0.0;
   }
   wg_sync();
-  // ---- inverses (S now holds L\U in pivot order)
+  // ---- inverses (S now holds L\U in pivot order).  Half of the group
+  // inverts L, the other half U: the 8 x 8 diagonal blocks by substitution
+  // (one column per thread), then the block size doubles and the off-diagonal
+  // block of each pair follows from two products (L: X21 = -X22 (L21 X11),
+  // U: X12 = -X11 (U12 X22)); pairs of 16 and 32 run on the FP64 matrix cores.
   {
     const int half = blockDim.x >> 1;
     const int grp = t / half, loc = t % half;
-    double* X = grp == 0 ? LI : UI;
-    double* T = grp == 0 ? PL : QL;            // s x s products of a level (<= 32 * 32 per pair set)
-    if (loc < 64) {                            // 8 x 8 diagonal blocks, one column per thread
+    const int gw = loc >> 6, nw = half >> 6;         // wave within the half, waves per half
+    const ldsd* S3 = lds_view(S);
+    ldsd* X = lds_view(grp == 0 ? LI : UI);
+    ldsd* T = lds_view(grp == 0 ? PL : QL);         // products of a level (<= 2048 values)
+    if (loc < 64) {                                 // 8 x 8 diagonal blocks, one column per thread
       const int bb = loc >> 3, c = loc & 7, o = bb * 8;
       double x[8];
       if (grp == 0) {
@@ -861,47 +867,91 @@ __device__ inline bool wg_leaf(const DevPtrs& P, const Item& it, int b, int64_t 
         for (int k = 0; k < 8; ++k) {
           double v = (k == c) ? 1.0 : 0.0;
 #pragma unroll
-          for (int q = 0; q < k; ++q) v -= S[(o + k) + (o + q) * kLdsLeaf] * x[q];
+          for (int q = 0; q < k; ++q) v = fma(-S3[(o + k) + (o + q) * kLdsLeaf], x[q], v);
           x[k] = k < c ? 0.0 : v;
         }
       } else {
+        double rd[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) rd[k] = 1.0 / S3[(o + k) + (o + k) * kLdsLeaf];
 #pragma unroll
         for (int k = 7; k >= 0; --k) {
           double v = (k == c) ? 1.0 : 0.0;
 #pragma unroll
-          for (int q = k + 1; q < 8; ++q) v -= S[(o + k) + (o + q) * kLdsLeaf] * x[q];
-          x[k] = k > c ? 0.0 : v / S[(o + k) + (o + k) * kLdsLeaf];
+          for (int q = k + 1; q < 8; ++q) v = fma(-S3[(o + k) + (o + q) * kLdsLeaf], x[q], v);
+          x[k] = k > c ? 0.0 : v * rd[k];
         }
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) X[(o + k) + (o + c) * kLdsLeaf] = x[k];
     }
     wg_sync();
-    for (int sz = 8; sz < 64; sz *= 2) {
-      const int pairs = 64 / (2 * sz), tot = pairs * sz * sz;
-      // T = L21 X11 (lower) or U12 X22 (upper), per pair, sz x sz
-      for (int e = loc; e < tot; e += half) {
-        const int pi = e / (sz * sz), r = e % (sz * sz), i = r % sz, c = r / sz, o = pi * 2 * sz;
-        double v = 0.0;
-        if (grp == 0) {
-          for (int q = c; q < sz; ++q) v += S[(o + sz + i) + (o + q) * kLdsLeaf] * X[(o + q) + (o + c) * kLdsLeaf];
-        } else {
-          for (int q = 0; q <= c; ++q) v += S[(o + i) + (o + sz + q) * kLdsLeaf] * X[(o + sz + q) + (o + sz + c) * kLdsLeaf];
+    // pairs of 8 x 8 blocks: T of pair pi at T + 64 pi, ld 8
+    for (int e = loc; e < 256; e += half) {
+      const int pi = e >> 6, i = e & 7, c = (e >> 3) & 7, o = pi * 16;
+      double v = 0.0;
+      if (grp == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q >= c) v = fma(S3[(o + 8 + i) + (o + q) * kLdsLeaf], X[(o + q) + (o + c) * kLdsLeaf], v);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q <= c) v = fma(S3[(o + i) + (o + 8 + q) * kLdsLeaf], X[(o + 8 + q) + (o + 8 + c) * kLdsLeaf], v);
+      }
+      T[e] = v;
+    }
+    wg_sync();
+    for (int e = loc; e < 256; e += half) {
+      const int pi = e >> 6, i = e & 7, c = (e >> 3) & 7, o = pi * 16;
+      const ldsd* Tp = T + pi * 64;
+      double v = 0.0;
+      if (grp == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q <= i) v = fma(X[(o + 8 + i) + (o + 8 + q) * kLdsLeaf], Tp[q + c * 8], v);
+        X[(o + 8 + i) + (o + c) * kLdsLeaf] = -v;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q >= i) v = fma(X[(o + i) + (o + q) * kLdsLeaf], Tp[q + c * 8], v);
+        X[(o + i) + (o + 8 + c) * kLdsLeaf] = -v;
+      }
+    }
+    wg_sync();
+    // pairs of 16 and 32: 16 x 16 tiles, k-steps of 4; T of pair pi at T + 1024 pi, ld 32
+    const int li = lane & 15, lk = lane >> 4;
+    for (int sz = 16; sz < 64; sz *= 2) {
+      const int nt = sz / 16, tpp = nt * nt, tiles = (64 / (2 * sz)) * tpp, ks = sz / 4;
+      for (int tile = gw; tile < tiles; tile += nw) {          // T = L21 X11 or U12 X22
+        const int pi = tile / tpp, ti = (tile % tpp) % nt, tj = (tile % tpp) / nt, o = pi * 2 * sz;
+        hfde_d4 acc{0.0, 0.0, 0.0, 0.0};
+        for (int s4 = 0; s4 < ks; ++s4) {
+          const int k = 4 * s4 + lk;
+          const double a = grp == 0 ? S3[(o + sz + ti * 16 + li) + (o + k) * kLdsLeaf]
+                                    : S3[(o + ti * 16 + li) + (o + sz + k) * kLdsLeaf];
+          const double bv = grp == 0 ? X[(o + k) + (o + tj * 16 + li) * kLdsLeaf]
+                                     : X[(o + sz + k) + (o + sz + tj * 16 + li) * kLdsLeaf];
+          acc = mfma64(a, bv, acc);
         }
-        T[e] = v;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[pi * 1024 + (ti * 16 + 4 * v + lk) + (tj * 16 + li) * 32] = acc[v];
       }
       wg_sync();
-      // X21 = -X22 T (lower) or X12 = -X11 T (upper)
-      for (int e = loc; e < tot; e += half) {
-        const int pi = e / (sz * sz), r = e % (sz * sz), i = r % sz, c = r / sz, o = pi * 2 * sz;
-        const double* Tp = T + pi * sz * sz;
-        double v = 0.0;
-        if (grp == 0) {
-          for (int q = 0; q <= i; ++q) v += X[(o + sz + i) + (o + sz + q) * kLdsLeaf] * Tp[q + c * sz];
-          X[(o + sz + i) + (o + c) * kLdsLeaf] = -v;
-        } else {
-          for (int q = i; q < sz; ++q) v += X[(o + i) + (o + q) * kLdsLeaf] * Tp[q + c * sz];
-          X[(o + i) + (o + sz + c) * kLdsLeaf] = -v;
+      for (int tile = gw; tile < tiles; tile += nw) {          // X21 = -X22 T or X12 = -X11 T
+        const int pi = tile / tpp, ti = (tile % tpp) % nt, tj = (tile % tpp) / nt, o = pi * 2 * sz;
+        hfde_d4 acc{0.0, 0.0, 0.0, 0.0};
+        for (int s4 = 0; s4 < ks; ++s4) {
+          const int k = 4 * s4 + lk;
+          const double a = grp == 0 ? X[(o + sz + ti * 16 + li) + (o + sz + k) * kLdsLeaf]
+                                    : X[(o + ti * 16 + li) + (o + k) * kLdsLeaf];
+          acc = mfma64(a, T[pi * 1024 + k + (tj * 16 + li) * 32], acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = ti * 16 + 4 * v + lk, col = tj * 16 + li;
+          if (grp == 0) X[(o + sz + row) + (o + col) * kLdsLeaf] = -acc[v];
+          else X[(o + row) + (o + sz + col) * kLdsLeaf] = -acc[v];
         }
       }
       wg_sync();

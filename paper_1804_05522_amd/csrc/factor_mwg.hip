@@ -120,15 +120,8 @@ struct GramUnit {
 };
 
 // ------------------------------------------------ Grams on the matrix cores
-typedef double hfde_d4 __attribute__((ext_vector_type(4)));
 constexpr int kStLd = kGramSub + 1;    // column stride (rows) of a staged window in LDS
 constexpr int kMaxTW = 5;              // Gram tiles per wave (20 tiles over 4 waves)
-
-// FP64 16x16x4 matrix-core product: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; element v of the result of lane l is D[4v + l/16][l%16].
-__device__ inline hfde_d4 mfma64(double a, double b, hfde_d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // (ti, tj), ti <= tj, of upper-triangle tile s in tj-major order
 __device__ inline void sym_tile(int s, int& ti, int& tj) {

@@ -153,4 +153,12 @@ __device__ inline bf16 bload(__amdgpu_buffer_rsrc_t r, int off, const bf16*) {
   return bf16{__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)};
 }
 
+typedef double hfde_d4 __attribute__((ext_vector_type(4)));
+
+// FP64 16x16x4 matrix-core product: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; element v of the result of lane l is D[4v + l/16][l%16].
+__device__ inline hfde_d4 mfma64(double a, double b, hfde_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 }  // namespace hfde
