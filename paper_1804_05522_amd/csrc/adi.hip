@@ -87,10 +87,11 @@ struct LrUnit {
 
 constexpr int kLrRows = 256;     // rows per Gram partial (one work-group on the matrix cores)
 
-__global__ void __launch_bounds__(256) k_lr_gram(const LrJob* jobs, const LrUnit* units, double* partial) {
+// The job descriptor travels as a kernel argument; the unit lists depend only
+// on the job slot and the row counts and stay resident between calls.
+__global__ void __launch_bounds__(256) k_lr_gram(const LrJob jb, const LrUnit* units, double* partial) {
   __shared__ __align__(16) double st[kMaxCat * kStLd];
   const LrUnit u = units[blockIdx.x];
-  const LrJob jb = jobs[u.job];
   const Cat3V A = resolve(u.which == 0 ? jb.X : jb.Y);
   const int64_t rows = u.which == 0 ? jb.rows_x : jb.rows_y;
   const int64_t r0 = int64_t(u.chunk) * kLrRows;
@@ -99,9 +100,8 @@ __global__ void __launch_bounds__(256) k_lr_gram(const LrJob* jobs, const LrUnit
   wg_gram_mfma<false>(A, A, r0, cnt, cnt, true, partial + int64_t(u.out) * kG2, nullptr, kMaxCat, true, st, st);
 }
 
-__global__ void __launch_bounds__(kCoreWG) k_lr_core(const LrJob* jobs, const double* G, double* Mbuf) {
+__global__ void __launch_bounds__(kCoreWG) k_lr_core(const LrJob jb, const double* G, double* Mbuf) {
   extern __shared__ __align__(16) double Lds[];
-  const LrJob jb = jobs[blockIdx.x];
   const Cat3V X = resolve(jb.X);
   const int R = X.cols();
   double* MU = Mbuf + int64_t(jb.mslot) * 2 * kMaxCat * kRS;
@@ -125,10 +125,9 @@ __global__ void __launch_bounds__(kCoreWG) k_lr_core(const LrJob* jobs, const do
 }
 
 // U = X * M_U, V = Y * M_V (row-parallel); units: (job, side, chunk of 256 rows)
-__global__ void __launch_bounds__(256) k_lr_form(const LrJob* jobs, const LrUnit* units, const double* Mbuf) {
+__global__ void __launch_bounds__(256) k_lr_form(const LrJob jb, const LrUnit* units, const double* Mbuf) {
   __shared__ double Ms[kMaxCat * kRS];
   const LrUnit u = units[blockIdx.x];
-  const LrJob jb = jobs[u.job];
   const Cat3V A = resolve(u.which == 0 ? jb.X : jb.Y);
   const int R = A.cols();
   const int r = *jb.rank_out;
@@ -152,9 +151,8 @@ __global__ void __launch_bounds__(256) k_lr_form(const LrJob* jobs, const LrUnit
 }
 
 // ||X Y^T||_F^2 = trace((X^T X)(Y^T Y)) from the two Grams; out[slot] = value.
-__global__ void k_lr_frob(const LrJob* jobs, const double* G, double* out) {
+__global__ void k_lr_frob(const LrJob jb, const double* G, double* out) {
   __shared__ double red[256];
-  const LrJob jb = jobs[blockIdx.x];
   const Cat3V X = resolve(jb.X);
   const int R = X.cols();
   const double* GX = G + int64_t(jb.gx) * kG2;
@@ -167,7 +165,7 @@ __global__ void k_lr_frob(const LrJob* jobs, const double* G, double* out) {
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // G -= w Z, H -= w Y for the fADI residual factors; also stores w Z into the

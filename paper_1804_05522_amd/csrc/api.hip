@@ -242,8 +242,13 @@ struct fde2d_plan_s {
   double* ex_in = nullptr;      // (nx + ny) x 64 for the exact products
   double* ex_out = nullptr;
   int32_t* ranks = nullptr;     // device ranks, see kR_* below
-  LrJob* jobs = nullptr;        // device job slots
-  LrUnit* units = nullptr;
+  hipGraphExec_t blk_graph[2][16] = {};   // sweep blocks of four shift pairs, by solve width (16 / 32 columns)
+  hipGraphExec_t d_graph[16] = {};        // their accumulation chains
+  hipStream_t side = nullptr;             // stream of the accumulation chains
+  hipEvent_t ev_blk = nullptr, ev_done = nullptr;
+  LrUnit* units = nullptr;      // per work slot: gram, reduce and form units
+  int64_t unit_rows[16][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1},
+                              {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
   double* gpart = nullptr;
   double* grams = nullptr;
   double* mbuf = nullptr;

@@ -94,44 +94,60 @@ hodlr_status plan_alloc(fde2d_plan p, T** ptr, size_t count) {
 Grp grp(const double* ptr, int64_t ld, const int32_t* cdev, int cnt, double s) { return Grp{ptr, ld, cdev, cnt, s}; }
 Grp grp_none() { return Grp{nullptr, 0, nullptr, 0, 0.0}; }
 
-// Enqueue one low-rank job (uploaded to device slot `slot`): Grams of both
-// sides, then either the recompression (core + forms) or only the norm.
-hodlr_status run_lr(fde2d_plan P, const LrJob& job, int slot, bool recompress, hipStream_t s, bool upload = true) {
+// Unit lists of work slot `slot` for jobs of rows_x x rows_y factors (gram
+// chunks of both sides, their two reductions, form chunks), uploaded only
+// when the slot's row counts change.
+hodlr_status ensure_units(fde2d_plan P, int slot, int64_t rows_x, int64_t rows_y, hipStream_t s) {
+  if (P->unit_rows[slot][0] == rows_x && P->unit_rows[slot][1] == rows_y) return HODLR_OK;
+  const int cx = int((rows_x + kLrRows - 1) / kLrRows), cy = int((rows_y + kLrRows - 1) / kLrRows);
+  const int fx = int((rows_x + 255) / 256), fy = int((rows_y + 255) / 256);
+  LrUnit* du = P->units + int64_t(slot) * P->slot_units;
+  ReduceUnit* dr = reinterpret_cast<ReduceUnit*>(du + P->cap_gram);
+  LrUnit* dfu = du + P->cap_gram + 2;
+  std::vector<LrUnit> units, fu;
+  std::vector<ReduceUnit> reds;
+  int out = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int chunks = side == 0 ? cx : cy;
+    reds.push_back(ReduceUnit{out, chunks, 2 * slot + side, 0});
+    for (int c = 0; c < chunks; ++c) units.push_back(LrUnit{slot, side, c, out++});
+    for (int c = 0; c < (side == 0 ? fx : fy); ++c) fu.push_back(LrUnit{slot, side, c, 0});
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(du, units.data(), units.size() * sizeof(LrUnit), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dr, reds.data(), reds.size() * sizeof(ReduceUnit), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dfu, fu.data(), fu.size() * sizeof(LrUnit), hipMemcpyHostToDevice));
+  P->unit_rows[slot][0] = rows_x;
+  P->unit_rows[slot][1] = rows_y;
+  return HODLR_OK;
+}
+
+// Enqueue one low-rank job on work slot `slot` (Gram, transfer-matrix and
+// norm storage): Grams of both sides, then either the recompression (core +
+// forms) or only the norm.  The descriptor is a kernel argument; the unit
+// lists of a slot are uploaded when its row counts change, so a call copies
+// nothing from the host.
+hodlr_status run_lr(fde2d_plan P, const LrJob& job, int slot, bool recompress, hipStream_t s) {
   LrJob jb = job;
   jb.gx = 2 * slot;
   jb.gy = 2 * slot + 1;
   jb.mslot = slot;
-  if (upload) HIP_TRY(hipMemcpyAsync(P->jobs + slot, &jb, sizeof(LrJob), hipMemcpyHostToDevice, s));
-  std::vector<LrUnit> units;
-  std::vector<ReduceUnit> reds;
-  int out = 0;
-  for (int side = 0; side < 2; ++side) {
-    const int64_t rows = side == 0 ? jb.rows_x : jb.rows_y;
-    const int chunks = int((rows + kLrRows - 1) / kLrRows);
-    reds.push_back(ReduceUnit{out, chunks, side == 0 ? jb.gx : jb.gy, 0});
-    for (int c = 0; c < chunks; ++c) units.push_back(LrUnit{slot, side, c, out++});
-  }
+  const int cx = int((jb.rows_x + kLrRows - 1) / kLrRows), cy = int((jb.rows_y + kLrRows - 1) / kLrRows);
+  const int fx = int((jb.rows_x + 255) / 256), fy = int((jb.rows_y + 255) / 256);
   // per-slot regions: gram units, reduce units, form units
+  TRY(ensure_units(P, slot, jb.rows_x, jb.rows_y, s));
   LrUnit* du = P->units + int64_t(slot) * P->slot_units;
-  HIP_TRY(hipMemcpyAsync(du, units.data(), units.size() * sizeof(LrUnit), hipMemcpyHostToDevice, s));
   ReduceUnit* dr = reinterpret_cast<ReduceUnit*>(du + P->cap_gram);
-  HIP_TRY(hipMemcpyAsync(dr, reds.data(), reds.size() * sizeof(ReduceUnit), hipMemcpyHostToDevice, s));
+  LrUnit* dfu = du + P->cap_gram + 2;
   double* gp = P->gpart + int64_t(slot) * P->cap_gram * kG2;
-  HFDE_LAUNCH(k_lr_gram, dim3(units.size()), dim3(256), 0, s, P->jobs, du, gp);
-  HFDE_LAUNCH(k_gram_reduce, dim3(reds.size()), dim3(256), 0, s, dr, gp, P->grams);
+  HFDE_LAUNCH(k_lr_gram, dim3(cx + cy), dim3(256), 0, s, jb, du, gp);
+  HFDE_LAUNCH(k_gram_reduce, dim3(2), dim3(256), 0, s, dr, gp, P->grams);
   if (!recompress) {
-    HFDE_LAUNCH(k_lr_frob, dim3(1), dim3(256), 0, s, P->jobs + slot, P->grams, P->frob + slot);
+    HFDE_LAUNCH(k_lr_frob, dim3(1), dim3(256), 0, s, jb, P->grams, P->frob + slot);
     return HODLR_OK;
   }
-  HFDE_LAUNCH(k_lr_core, dim3(1), dim3(kCoreWG), kFactorLdsBytes, s, P->jobs + slot, P->grams, P->mbuf);
-  std::vector<LrUnit> fu;
-  for (int side = 0; side < 2; ++side) {
-    const int64_t rows = side == 0 ? jb.rows_x : jb.rows_y;
-    for (int64_t c = 0; c < (rows + 255) / 256; ++c) fu.push_back(LrUnit{slot, side, int32_t(c), 0});
-  }
-  LrUnit* dfu = du + P->cap_gram + 2;
-  HIP_TRY(hipMemcpyAsync(dfu, fu.data(), fu.size() * sizeof(LrUnit), hipMemcpyHostToDevice, s));
-  HFDE_LAUNCH(k_lr_form, dim3(fu.size()), dim3(256), 0, s, P->jobs, dfu, P->mbuf);
+  HFDE_LAUNCH(k_lr_core, dim3(1), dim3(kCoreWG), kFactorLdsBytes, s, jb, P->grams, P->mbuf);
+  HFDE_LAUNCH(k_lr_form, dim3(fx + fy), dim3(256), 0, s, jb, dfu, P->mbuf);
   return HODLR_OK;
 }
 
@@ -153,29 +169,48 @@ void copy_cols(int64_t rows, const int32_t* rdev, int rfix, const double* src, i
   HFDE_LAUNCH(k_copy_cols, dim3(blocks), dim3(256), 0, s, rows, rdev, rfix, src, lds, dst, ldd, sc);
 }
 
-// One fADI sweep on the right-hand side G H^T (rank r0, in P->G / P->H; they are
-// consumed).  Accumulates the sweep's solution into Zd/Wd; returns the steps
-// taken and the parity holding the result.
-hodlr_status adi_sweep(fde2d_plan P, int r0, double cnorm, int& steps, int& parity, hipStream_t s) {
+// Shift pairs 4b .. min(4b + 4, J) - 1 of a sweep, main chain: solves of nc
+// columns and the residual update G -= w Z, H -= w Y, then the Gram norm of
+// the residual G H^T into frob slot 1.  Every column count is read on the
+// device, so the same launches serve any right-hand-side rank up to nc.
+hodlr_status enqueue_main_block(fde2d_plan P, int b, int nc, hipStream_t s) {
   hodlr_mat m = P->mat;
   const int64_t nx = P->nx, ny = P->ny, tn = m->total_n;
-  const double tol = P->opts.tol;
-  HIP_TRY(hipMemsetAsync(P->ranks + kR_D0, 0, sizeof(int32_t), s));
-  parity = 0;
-  steps = 0;
-  if (r0 == 0) return HODLR_OK;
-  for (int jo = 0; jo < P->J; ++jo) {
+  for (int jo = 4 * b; jo < std::min(4 * b + 4, P->J); ++jo) {
     const int j = P->order[jo];
     const Item& ix = m->items[j];
     const Item& iy = m->items[P->J + j];
     copy_cols(nx, P->ranks + kR_R0, 0, P->G, nx, P->xin + ix.row0, tn, 1.0, s);
     copy_cols(ny, P->ranks + kR_R0, 0, P->H, ny, P->xin + iy.row0, tn, 1.0, s);
     launch_solve_units(m, m->opts.prec, P->pair_wu + P->pwu_off[j], P->pwu_cnt[j], P->pair_nu + P->pnu_off[j],
-                       P->pnu_cnt[j], P->xin, tn, P->xin, tn, r0, s);
+                       P->pnu_cnt[j], P->xin, tn, P->xin, tn, nc, s);
     const double w = P->p[j] + P->q[j];
     HFDE_LAUNCH(k_adi_update, dim3(256), dim3(256), 0, s, nx, ny, P->ranks + kR_R0, w, P->xin + ix.row0, tn,
                        P->xin + iy.row0, tn, P->G, nx, P->H, ny);
-    // D <- recompress([D, w Z_j][W_D, Y_j])
+  }
+  LrJob nj{};
+  nj.X.g[0] = grp(P->G, nx, P->ranks + kR_R0, 0, 1.0);
+  nj.X.g[1] = nj.X.g[2] = grp_none();
+  nj.Y.g[0] = grp(P->H, ny, P->ranks + kR_R0, 0, 1.0);
+  nj.Y.g[1] = nj.Y.g[2] = grp_none();
+  nj.rows_x = nx;
+  nj.rows_y = ny;
+  return run_lr(P, nj, 1, false, s);
+}
+
+// The same shift pairs, accumulation chain: D <- recompress([D, w Z_j][W_D, Y_j]).
+// Z_j, Y_j are the solve outputs in shift j's own rows of the workspace, which
+// no other shift of the sweep touches.
+hodlr_status enqueue_d_block(fde2d_plan P, int b, hipStream_t s) {
+  hodlr_mat m = P->mat;
+  const int64_t nx = P->nx, ny = P->ny, tn = m->total_n;
+  const double tol = P->opts.tol;
+  for (int jo = 4 * b; jo < std::min(4 * b + 4, P->J); ++jo) {
+    const int j = P->order[jo];
+    const int parity = jo & 1;
+    const Item& ix = m->items[j];
+    const Item& iy = m->items[P->J + j];
+    const double w = P->p[j] + P->q[j];
     LrJob jb{};
     jb.X.g[0] = grp(P->Zd[parity], nx, P->ranks + kR_D0 + parity, 0, 1.0);
     jb.X.g[1] = grp(P->xin + ix.row0, tn, P->ranks + kR_R0, 0, w);
@@ -193,24 +228,73 @@ hodlr_status adi_sweep(fde2d_plan P, int r0, double cnorm, int& steps, int& pari
     jb.ldu = nx;
     jb.V = P->Wd[1 - parity];
     jb.ldv = ny;
-    TRY(run_lr(P, jb, 2 + (jo & 1), true, s));
-    parity = 1 - parity;
-    steps = jo + 1;
-    if ((jo % 4 == 3) || jo == P->J - 1) {
-      LrJob nj{};
-      nj.X.g[0] = grp(P->G, nx, P->ranks + kR_R0, 0, 1.0);
-      nj.X.g[1] = nj.X.g[2] = grp_none();
-      nj.Y.g[0] = grp(P->H, ny, P->ranks + kR_R0, 0, 1.0);
-      nj.Y.g[1] = nj.Y.g[2] = grp_none();
-      nj.rows_x = nx;
-      nj.rows_y = ny;
-      TRY(run_lr(P, nj, 1, false, s));
-      double f2 = 0.0;
-      TRY(read_frob(P, 1, &f2, s));
-      if (std::sqrt(std::max(f2, 0.0)) <= tol * cnorm) break;
-    }
+    TRY(run_lr(P, jb, 2 + parity, true, s));
   }
   return HODLR_OK;
+}
+
+// Capture `enqueue` on stream s into ge (once), then replay it.
+template <typename F>
+hodlr_status replay(hipGraphExec_t& ge, hipStream_t s, F&& enqueue) {
+  if (!ge) {
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const hodlr_status st = enqueue();
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (st != HODLR_OK) return st;
+    HIP_TRY(ec);
+    const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(ei);
+  }
+  HIP_TRY(hipGraphLaunch(ge, s));
+  return HODLR_OK;
+}
+
+// One fADI sweep on the right-hand side G H^T (rank r0, in P->G / P->H; they are
+// consumed).  Accumulates the sweep's solution into Zd/Wd; returns the steps
+// taken and the parity holding the result.  The convergence test comes after
+// every block of four shift pairs.  On a stream of its own (and without kernel
+// timing) each block's two chains are HIP graphs captured on first use, and
+// the accumulation chain runs on a second stream one block behind the solves,
+// joined before the sweep returns; otherwise both run in order on one stream.
+hodlr_status adi_sweep(fde2d_plan P, int r0, double cnorm, int& steps, int& parity, hipStream_t s) {
+  const int64_t nx = P->nx, ny = P->ny;
+  const double tol = P->opts.tol;
+  HIP_TRY(hipMemsetAsync(P->ranks + kR_D0, 0, sizeof(int32_t), s));
+  parity = 0;
+  steps = 0;
+  if (r0 == 0) return HODLR_OK;
+  const int wide = r0 > kNCS ? 1 : 0;
+  const int nc = wide ? 2 * kNCS : kNCS;
+  const bool graphs = s != nullptr && g_timer == nullptr && P->side != nullptr;
+  if (graphs)
+    for (int slot = 1; slot <= 3; ++slot) TRY(ensure_units(P, slot, nx, ny, s));
+  const int nb = (P->J + 3) / 4;
+  hodlr_status res = HODLR_OK;
+  for (int b = 0; b < nb; ++b) {
+    if (graphs) {
+      res = replay(P->blk_graph[wide][b], s, [&] { return enqueue_main_block(P, b, nc, s); });
+      if (res != HODLR_OK) break;
+      HIP_TRY(hipEventRecord(P->ev_blk, s));
+      HIP_TRY(hipStreamWaitEvent(P->side, P->ev_blk, 0));
+      res = replay(P->d_graph[b], P->side, [&] { return enqueue_d_block(P, b, P->side); });
+      if (res != HODLR_OK) break;
+    } else {
+      TRY(enqueue_main_block(P, b, nc, s));
+      TRY(enqueue_d_block(P, b, s));
+    }
+    steps = std::min(4 * b + 4, P->J);
+    parity = steps & 1;
+    double f2 = 0.0;
+    res = read_frob(P, 1, &f2, s);
+    if (res != HODLR_OK || std::sqrt(std::max(f2, 0.0)) <= tol * cnorm) break;
+  }
+  if (graphs) {                                  // join the accumulation chain
+    HIP_TRY(hipEventRecord(P->ev_done, P->side));
+    HIP_TRY(hipStreamWaitEvent(s, P->ev_done, 0));
+  }
+  return res;
 }
 
 }  // namespace
@@ -219,6 +303,15 @@ extern "C" {
 
 void fde2d_plan_destroy(fde2d_plan p) {
   if (!p) return;
+  if (p->side) (void)hipStreamSynchronize(p->side);
+  for (auto& row : p->blk_graph)
+    for (hipGraphExec_t& ge : row)
+      if (ge) (void)hipGraphExecDestroy(ge);
+  for (hipGraphExec_t& ge : p->d_graph)
+    if (ge) (void)hipGraphExecDestroy(ge);
+  if (p->ev_blk) (void)hipEventDestroy(p->ev_blk);
+  if (p->ev_done) (void)hipEventDestroy(p->ev_done);
+  if (p->side) (void)hipStreamDestroy(p->side);
   hodlr_destroy(p->mat);
   hodlr_destroy(p->exact);
   for (void* q : p->allocs) (void)hipFree(q);
@@ -249,6 +342,13 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
   fde2d_plan P = new (std::nothrow) fde2d_plan_s;
   if (!P) return HODLR_ENOMEM;
   P->ctx = ctx;
+  // second stream (default priority) for the sweeps' accumulation chain
+  if (s != nullptr && (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
+                       hipEventCreateWithFlags(&P->ev_blk, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&P->ev_done, hipEventDisableTiming) != hipSuccess)) {
+    fde2d_plan_destroy(P);
+    return HODLR_EHIP;
+  }
   P->opts = *opts;
   P->nx = opx->n;
   P->ny = opy->n;
@@ -352,7 +452,7 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
             plan_alloc(P, &P->xin, m->total_n * kMaxCat) == HODLR_OK &&
             plan_alloc(P, &P->ex_in, (nx + ny) * kMaxCat) == HODLR_OK &&
             plan_alloc(P, &P->ex_out, (nx + ny) * kMaxCat) == HODLR_OK && plan_alloc(P, &P->ranks, kR_N) == HODLR_OK &&
-            plan_alloc(P, &P->jobs, 16) == HODLR_OK && plan_alloc(P, &P->units, 16 * P->slot_units) == HODLR_OK &&
+            plan_alloc(P, &P->units, 16 * P->slot_units) == HODLR_OK &&
             plan_alloc(P, &P->gpart, 16 * P->cap_gram * kG2) == HODLR_OK && plan_alloc(P, &P->grams, 32 * kG2) == HODLR_OK &&
             plan_alloc(P, &P->mbuf, 16 * 2 * kMaxCat * kRS) == HODLR_OK && plan_alloc(P, &P->frob, 16) == HODLR_OK;
   for (int k = 0; k < 2 && ok; ++k)

@@ -83,3 +83,43 @@ def test_shift_count_reasonable(H, ctx):
     ps, qs = P.shifts()
     assert 5 <= len(ps) <= 64
     assert all(x > 0 for x in ps + qs)
+
+
+def test_sweep_graphs_replay_like_direct_launches(H):
+    """On a stream of its own the sweep's blocks of four shift pairs are HIP
+    graphs, captured on first use and replayed by later sweeps and steps; on
+    the null stream every kernel is launched directly.  Four steps in a row,
+    with eager work and synchronisations between the replays, give the same
+    factors bit for bit on both paths (same kernels in the same order)."""
+    p = W.fd_2d(n=150, variable=True, dt=1 / 16)
+    stream = torch.cuda.Stream()
+    outs = {}
+    for mode in ("direct", "graph"):
+        if mode == "graph":
+            with torch.cuda.stream(stream):
+                c = H.Context(stream)
+                P = plan_for(H, c, p)
+        else:
+            c = H.Context()
+            P = plan_for(H, c, p)
+        cur = (torch.zeros((0, p.nx), dtype=torch.float64, device="cuda"),
+               torch.zeros((0, p.ny), dtype=torch.float64, device="cuda"))
+        F = lr_dev(p.f.Z, p.f.W)
+        seq = []
+        for k in range(4):
+            with torch.cuda.stream(stream if mode == "graph" else torch.cuda.current_stream()):
+                out = (torch.zeros((32, p.nx), dtype=torch.float64, device="cuda"),
+                       torch.zeros((32, p.ny), dtype=torch.float64, device="cuda"))
+                r, info = P.step(cur, F, p.dt, out, allow=(0, 2))
+                torch.cuda.synchronize()
+                junk = torch.randn(1 << 16, device="cuda").sum()      # eager work between replays
+                torch.cuda.synchronize()
+                assert torch.isfinite(junk)
+                cur = (out[0][:r].clone(), out[1][:r].clone())
+                seq.append((r, info.refine_iters, cur[0].cpu().numpy(), cur[1].cpu().numpy()))
+        P.close()
+        c.close()
+        outs[mode] = seq
+    for k, (a, b) in enumerate(zip(outs["direct"], outs["graph"])):
+        assert a[0] == b[0] and a[1] == b[1], (k, a[:2], b[:2])
+        assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]), k
