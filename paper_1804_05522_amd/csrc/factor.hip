@@ -350,14 +350,20 @@ __device__ int wave_pchol(const double* Gg, int R, double* Lg, double delta) {
 // Householder QR with column pivoting of K (kA x kB <= 64 x 64, LDS, ld
 // kLdG), by waves 0..3 of the work-group (blockDim >= 256; the other waves
 // only take part in the barriers).  Lane j owns column j; wave w keeps rows
-// 16w..16w+15 of every column in registers.  Columns are not moved: perm[s]
-// is the column taken at step s.  Stops when the Frobenius norm of the
-// trailing block is <= tau; the trailing column norms are recomputed from the
-// updated entries at every step (no downdating, so small trailing norms are
-// not lost to cancellation).  On return column perm[s] holds R(0:s, s) in
-// rows 0..s and the Householder vector (unit leading entry implicit) below
-// row s; tv[s] is its scalar.  Two work-group barriers per step: one to add
-// up the column norms (and publish row s), one to add up the reflector dots.
+// 16w..16w+15 of the trailing block in registers, with the rows above the
+// current step held at zero, so that the reflector, its dot products and the
+// update need no row masks.  Each step writes row s of R and the pivot
+// column's Householder vector to K in LDS as they leave the trailing block.
+// Columns are not moved: perm[s] is the column taken at step s.  Stops when
+// the Frobenius norm of the trailing block is <= tau; the trailing column
+// norms are recomputed from the updated entries at every step (no
+// downdating, so small trailing norms are not lost to cancellation).  On
+// return column perm[s] holds R(0:s, s) in rows 0..s and the Householder
+// vector (unit leading entry implicit) below row s; tv[s] is its scalar.
+// Two work-group barriers per step: one to add up the column norms (and
+// publish row s), one to add up the reflector dots.  The step loop is
+// unrolled over the sixteen rows of a wave, so row s is a fixed register of
+// wave s / 16 and every wave's rows lie wholly above, at or below it.
 // scr: 576 doubles of LDS scratch.
 __device__ __noinline__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int* permg, double* tvg, double* scr) {
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -370,22 +376,21 @@ __device__ __noinline__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int*
   ldsd* s_nb = lds_view(scr);          // 4 x 64 partial norms
   ldsd* s_db = s_nb + 256;             // 4 x 64 partial dots
   ldsd* s_row = s_nb + 512;            // row s
-  double kr[16];
+  ldsd* Kc = K + lane * kLdG;          // this lane's column
+  double kt[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) kr[k] = (mine && r0 + k < kA && lane < kB) ? K[r0 + k + lane * kLdG] : 0.0;
+  for (int k = 0; k < 16; ++k) kt[k] = (mine && r0 + k < kA && lane < kB) ? Kc[r0 + k] : 0.0;
   bool done = lane >= kB;
   double pn;
   {
     double p4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) p4[k & 3] = fma(kr[k], kr[k], p4[k & 3]);
+    for (int k = 0; k < 16; ++k) p4[k & 3] = fma(kt[k], kt[k], p4[k & 3]);
     pn = (p4[0] + p4[1]) + (p4[2] + p4[3]);
   }
   const int kmax = kA < kB ? kA : kB;
   int steps = 0;
   bool go = kmax > 0;
-  // Step s = 16 jp + jj: the unrolled jj makes row s a fixed register of
-  // wave jp, and a wave's rows lie wholly above, at or below row s.
   for (int jp = 0; jp < 4 && go; ++jp) {
     const bool w_eq = wv == jp, w_gt = wv > jp;
 #pragma unroll
@@ -395,35 +400,58 @@ __device__ __noinline__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int*
       if (!go) continue;
       if (mine) {
         s_nb[wv * 64 + lane] = pn;
-        if (w_eq) s_row[lane] = kr[jj];
+        if (w_eq) s_row[lane] = kt[jj];
       }
       __syncthreads();
       const double n2 = ((s_nb[lane] + s_nb[64 + lane]) + s_nb[128 + lane]) + s_nb[192 + lane];
       const double xs = s_row[lane];
+      // every lane forms the reflector scalars of its own column while the
+      // wave reductions below find the pivot; the pivot lane's are taken
+      double bl = 0.0, tl = 0.0, sl = 0.0;
+      {
+        const double nl = sqrt(n2);
+        if (nl > 0.0) {
+          bl = xs >= 0 ? -nl : nl;
+          const double rb = 1.0 / bl, rd = 1.0 / (xs - bl);      // independent
+          tl = (bl - xs) * rb;
+          sl = rd;
+        }
+      }
       const double tot = wave_sum_fixed(done ? 0.0 : n2);
       if (tot <= tau * tau) {                    // same value in every wave
         go = false;
         continue;
       }
       const int p = pivot_lane(pivot_key(n2, !done, lane));
-      const double nrm = sqrt(readlane_d(n2, p));
-      const double x0 = readlane_d(xs, p);
-      double beta = 0.0, tq = 0.0, sc = 0.0;
-      if (nrm > 0.0) {
-        beta = x0 >= 0 ? -nrm : nrm;
-        const double rb = 1.0 / beta, rd = 1.0 / (x0 - beta);   // independent
-        tq = (beta - x0) * rb;
-        sc = rd;
+      const double beta = readlane_d(bl, p), tq = readlane_d(tl, p), sc = readlane_d(sl, p);
+      // reflector: the pivot column scaled below row s, 1 at row s, 0 above.
+      // The pivot lane stores it as the column's Householder vector; the
+      // wave's other lanes read it back (broadcast loads).
+      if (mine && lane == p) {
+        if (w_gt) {
+#pragma unroll
+          for (int k = 0; k < 16; ++k) Kc[r0 + k] = kt[k] * sc;
+        } else if (w_eq) {
+#pragma unroll
+          for (int k = jj + 1; k < 16; ++k) Kc[r0 + k] = kt[k] * sc;
+        }
       }
+      wave_lds_sync();
+      const ldsd* Kp = K + p * kLdG + r0;
       double v[16];
+      if (w_gt) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = Kp[k];
+      } else if (w_eq) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = k < jj ? 0.0 : (k == jj ? 1.0 : Kp[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = 0.0;
+      }
       double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const double pk = readlane_d(kr[k], p);
-        const bool below = k > jj ? (w_eq || w_gt) : w_gt;     // row r0 + k > s
-        v[k] = below ? pk * sc : ((k == jj && w_eq) ? 1.0 : 0.0);
-        d4[k & 3] = fma(v[k], kr[k], d4[k & 3]);
-      }
+      for (int k = 0; k < 16; ++k) d4[k & 3] = fma(v[k], kt[k], d4[k & 3]);
       const double pd = (d4[0] + d4[1]) + (d4[2] + d4[3]);
       if (mine) s_db[wv * 64 + lane] = pd;
       if (t == 0) {
@@ -433,35 +461,27 @@ __device__ __noinline__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int*
       __syncthreads();
       const double dot = ((s_db[lane] + s_db[64 + lane]) + s_db[128 + lane]) + s_db[192 + lane];
       const double wj = tq * dot;
-      if (lane == p) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const bool at = k == jj && w_eq;
-          const bool below = k > jj ? (w_eq || w_gt) : w_gt;
-          kr[k] = at ? beta : (below ? v[k] : kr[k]);
-        }
-        done = true;
-      } else if (!done) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) kr[k] = fma(-wj, v[k], kr[k]);
+      for (int k = 0; k < 16; ++k) kt[k] = fma(-wj, v[k], kt[k]);   // done columns: values unused
+      if (w_eq) {                                // row s leaves the trailing block as row s of R
+        if (mine && !done) Kc[s] = lane == p ? beta : kt[jj];
+        kt[jj] = 0.0;
       }
+      if (lane == p) done = true;
       {
         double p4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const bool below = k > jj ? (w_eq || w_gt) : w_gt;
-          p4[k & 3] = below ? fma(kr[k], kr[k], p4[k & 3]) : p4[k & 3];
-        }
+        for (int k = 0; k < 16; ++k) p4[k & 3] = fma(kt[k], kt[k], p4[k & 3]);
         pn = (p4[0] + p4[1]) + (p4[2] + p4[3]);
       }
       ++steps;
     }
   }
-  __syncthreads();
-  if (mine && lane < kB) {
+  // the trailing block of the columns never taken
+  if (mine && !done) {
 #pragma unroll
     for (int k = 0; k < 16; ++k)
-      if (r0 + k < kA) K[r0 + k + lane * kLdG] = kr[k];
+      if (r0 + k >= steps && r0 + k < kA) Kc[r0 + k] = kt[k];
   }
   __syncthreads();
   return steps;
