@@ -360,12 +360,15 @@ __device__ int wave_pchol(const double* Gg, int R, double* Lg, double delta) {
 // downdating, so small trailing norms are not lost to cancellation).  On
 // return column perm[s] holds R(0:s, s) in rows 0..s and the Householder
 // vector (unit leading entry implicit) below row s; tv[s] is its scalar.
-// Two work-group barriers per step: one to add up the column norms (and
-// publish row s), one to add up the reflector dots.  The step loop is
+// At most smax steps are taken (a caller that keeps r columns passes r + 1,
+// which still tells whether the tolerance needs more).  Two work-group
+// barriers per step: one to add up the column norms (and publish row s), one
+// to add up the reflector dots.  The step loop is
 // unrolled over the sixteen rows of a wave, so row s is a fixed register of
 // wave s / 16 and every wave's rows lie wholly above, at or below it.
 // scr: 576 doubles of LDS scratch.
-__device__ __noinline__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int* permg, double* tvg, double* scr) {
+__device__ __noinline__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int smax, int* permg, double* tvg,
+                                    double* scr) {
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const bool mine = wave < 4;
   const int wv = mine ? wave : 0;
@@ -388,7 +391,7 @@ __device__ __noinline__ int wg_qrcp(double* Kg, int kA, int kB, double tau, int*
     for (int k = 0; k < 16; ++k) p4[k & 3] = fma(kt[k], kt[k], p4[k & 3]);
     pn = (p4[0] + p4[1]) + (p4[2] + p4[3]);
   }
-  const int kmax = kA < kB ? kA : kB;
+  const int kmax = min(min(kA, kB), smax);
   int steps = 0;
   bool go = kmax > 0;
   for (int jp = 0; jp < 4 && go; ++jp) {
@@ -589,7 +592,8 @@ __device__ RecompressOut wg_core_grams(double* Lg, int R, double tau, int rmax) 
     KC[i + j * kLdG] = lds_dot<1, 1>(LA + i * kLdG, LB + j * kLdG, 0, R);
   }
   wg_sync();
-  const int rq = wg_qrcp(Lg + lds::KC, kA, kB, tau, permg, Lg + lds::VEC + 256, Lg + lds::RED);   // RED is free until M_U
+  // rmax + 1 steps tell whether the rank exceeds the cap
+  const int rq = wg_qrcp(Lg + lds::KC, kA, kB, tau, rmax + 1, permg, Lg + lds::VEC + 256, Lg + lds::RED);
   const int rr = rq < rmax ? rq : rmax;
   for (int e = t; e < kA * rr; e += blockDim.x) {   // R factor and vectors in pivot order
     const int i = e % kA, c = e / kA;
