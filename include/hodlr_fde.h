@@ -155,6 +155,11 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch,
  * factorisation schedule are kept.  m must be factored again before it is
  * solved with (HODLR_ESTATE otherwise). */
 hodlr_status hodlr_update_coefficients(hodlr_ctx ctx, hodlr_mat m, const fde_operator* ops);
+/* Releases m.  Waits for the device to be idle, then keeps m's device blocks
+ * in a process-wide pool (per device, at most 160 GB) from which a later
+ * matrix that needs blocks of exactly the same sizes takes them; building a
+ * matrix of the same shape again therefore maps no new device memory.  When
+ * an allocation fails the pool is released and the allocation retried. */
 void hodlr_destroy(hodlr_mat m);
 hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info);
 

@@ -13,6 +13,8 @@
 #include <vector>
 #include <map>
 #include <mutex>
+#include <map>
+#include <mutex>
 #include <tuple>
 #include <functional>
 
@@ -146,6 +148,7 @@ struct hodlr_mat_s {
   std::vector<NodeUnit> nu_h;
   DevPtrs P{};
   std::vector<void*> allocs;
+  std::vector<size_t> alloc_bytes;
   size_t bytes_device = 0;
   WorkUnit* wu = nullptr;
   NodeUnit* nu = nullptr;
@@ -274,12 +277,77 @@ hodlr_status set_arg(hodlr_ctx ctx, int idx) {
     }                                                 \
   } while (0)
 
+// Device blocks released by destroyed matrices, per device, handed to later
+// matrices that ask for exactly the same sizes: a loop that builds a matrix
+// of the same shape again and again (a serving loop, a benchmark) then maps
+// no new memory, which for tens of GB costs about a second.  At most kPoolMax
+// bytes are kept; an allocation that fails releases the pool and tries again.
+struct BlockPool {
+  std::mutex mu;
+  std::map<int, std::multimap<size_t, void*>> blocks;   // device -> (bytes, block)
+  std::map<int, size_t> held;
+};
+BlockPool& block_pool() {
+  static BlockPool* p = new BlockPool;   // never destroyed: no HIP calls during process exit
+  return *p;
+}
+constexpr size_t kPoolMax = size_t(160) << 30;
+
+void* pool_take(size_t bytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  BlockPool& P = block_pool();
+  std::lock_guard<std::mutex> g(P.mu);
+  auto& mm = P.blocks[dev];
+  auto it = mm.find(bytes);
+  if (it == mm.end()) return nullptr;
+  void* q = it->second;
+  mm.erase(it);
+  P.held[dev] -= bytes;
+  return q;
+}
+
+void pool_give(void* q, size_t bytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipFree(q);
+    return;
+  }
+  BlockPool& P = block_pool();
+  std::lock_guard<std::mutex> g(P.mu);
+  if (P.held[dev] + bytes > kPoolMax) {
+    (void)hipFree(q);
+    return;
+  }
+  P.blocks[dev].emplace(bytes, q);
+  P.held[dev] += bytes;
+}
+
+void pool_release() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  BlockPool& P = block_pool();
+  std::lock_guard<std::mutex> g(P.mu);
+  for (auto& kv : P.blocks[dev]) (void)hipFree(kv.second);
+  P.blocks[dev].clear();
+  P.held[dev] = 0;
+}
+
 template <typename T>
 hodlr_status dalloc(hodlr_mat m, T** p, size_t count) {
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  void* q = nullptr;
-  if (hipMalloc(&q, bytes) != hipSuccess) return HODLR_ENOMEM;
+  void* q = pool_take(bytes);
+  if (!q && hipMalloc(&q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    pool_release();
+    q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return HODLR_ENOMEM;
+    }
+  }
   m->allocs.push_back(q);
+  m->alloc_bytes.push_back(bytes);
   // HODLR_POISON=1 fills new device memory with NaN bytes, so that a read of
   // memory no kernel has written shows up in the results
   static const bool poison = getenv("HODLR_POISON") && getenv("HODLR_POISON")[0] == '1';
@@ -841,7 +909,9 @@ void hodlr_destroy(hodlr_mat m) {
   }
   if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
   if (m->ev_join) (void)hipEventDestroy(m->ev_join);
-  for (void* p : m->allocs) (void)hipFree(p);
+  // no kernel may still use a block when it goes back to the pool
+  (void)hipDeviceSynchronize();
+  for (size_t i = 0; i < m->allocs.size(); ++i) pool_give(m->allocs[i], m->alloc_bytes[i]);
   delete m;
 }
 

@@ -299,3 +299,31 @@ def test_time_dependent_coefficients(H, ctx):
     with pytest.raises(H.HodlrError):      # n must not change
         A.update_coefficients([H.operator_dict(p.n + 1, p.alpha, p.dt, p.h, dev(np.ones(p.n + 1)),
                                                dev(np.ones(p.n + 1)), 1.0) for p in probs])
+
+
+def test_pooled_blocks_give_identical_results(H, ctx):
+    """A destroyed matrix's device blocks go to the library's pool and a new
+    matrix of the same shape takes them (stale contents included): building,
+    factoring and solving the same problems three times in a row, FP32 and
+    FP64 storage interleaved, gives the same bits every time, and the pooled
+    build holds the same device bytes."""
+    probs = [var_problem(3000, 1.35), var_problem(1500, 1.7, seed=3)]
+    b = np.concatenate([np.sin(3 * p.x) + p.x for p in probs])
+    seen = {}
+    for rep in range(3):
+        for prec in ("fp32", "fp64"):
+            A = build(H, ctx, probs, tol=1e-10, prec=prec, refine_max=2, rtol=1e-12)
+            A.factor()
+            x = dev(b)
+            A.solve(x, allow=(0, 2))
+            got = (x.cpu().numpy(), A.info().bytes_device)
+            A.close()
+            if prec in seen:
+                assert np.array_equal(got[0], seen[prec][0]), (rep, prec)
+                assert got[1] == seen[prec][1]
+            else:
+                seen[prec] = got
+    ref = np.concatenate([O.DenseSolver(p.alpha, p.n, p.nu, p.d_plus, p.d_minus).solve(r)
+                          for p, r in zip(probs, np.split(b, [probs[0].n]))])
+    for prec in ("fp32", "fp64"):
+        assert np.linalg.norm(seen[prec][0] - ref) <= 1e-9 * np.linalg.norm(ref), prec
