@@ -107,7 +107,7 @@ __device__ inline OpRef op_ref(const DevPtrs& P, const Item& it, int d, int64_t 
 
 constexpr int kGramRows = 256;      // default rows per partial (a per-matrix tunable)
 constexpr int kFuseRows = 256;      // default largest child of a node whose phase A runs fused (tunable)
-constexpr int kGramSub = 32;        // rows staged in LDS at a time
+constexpr int kGramSub = 64;        // rows staged in LDS at a time
 constexpr int kGramLd = 66;         // LDS row stride (16-byte aligned rows, spread banks)
 constexpr int kG2 = kMaxCat * kMaxCat;   // one 64 x 64 matrix
 
@@ -153,23 +153,27 @@ __device__ void wg_gram_mfma(const Op& S0, const Op& S1, int64_t row0, int64_t r
   if (!stage1) rows1 = 0;
   const int64_t most = max(rows0, rows1);
   // this thread stages window row si of columns sc + cstep q
+  ldsd* s0 = lds_view(st0);
+  ldsd* s1 = lds_view(st1);
+  // Unscaled columns are staged (the column pointers are recomputed per
+  // window to save registers); the column scales multiply the Gram entries.
   constexpr int kQ = kGramSub * kMaxCat / 256;
   const int si = t % kGramSub, sc = t / kGramSub, cstep = nt / kGramSub;
-  const double* q0[kQ];
-  const double* q1[kQ];
-  double f0[kQ], f1[kQ];
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int c = sc + cstep * q;
-    f0[q] = f1[q] = 0.0;
-    q0[q] = c < c0 ? S0.colp(c, f0[q]) + row0 : nullptr;
-    q1[q] = (stage1 && c < c1) ? S1.colp(c, f1[q]) + row0 : nullptr;
-  }
+  auto colptr = [&](const Op& S, int c) {
+    double f;
+    return S.colp(c, f) + row0;
+  };
+  auto scale = [&](const Op& S, int c) {
+    double f = 0.0;
+    (void)S.colp(c, f);
+    return f;
+  };
   double v0[kQ], v1[kQ];
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    v0[q] = (q0[q] && si < rows0) ? f0[q] * q0[q][si] : 0.0;
-    v1[q] = (q1[q] && si < rows1) ? f1[q] * q1[q][si] : 0.0;
+    const int c = sc + cstep * q;
+    v0[q] = (c < c0 && si < rows0) ? colptr(S0, c)[si] : 0.0;
+    v1[q] = (stage1 && c < c1 && si < rows1) ? colptr(S1, c)[si] : 0.0;
   }
   hfde_d4 acc[kMaxTW];
 #pragma unroll
@@ -180,8 +184,8 @@ __device__ void wg_gram_mfma(const Op& S0, const Op& S1, int64_t row0, int64_t r
     for (int q = 0; q < kQ; ++q) {
       const int c = sc + cstep * q;
       if (c < kMaxCat) {
-        st0[c * kStLd + si] = v0[q];
-        if (stage1) st1[c * kStLd + si] = v1[q];
+        s0[c * kStLd + si] = v0[q];
+        if (stage1) s1[c * kStLd + si] = v1[q];
       }
     }
     __syncthreads();
@@ -189,8 +193,9 @@ __device__ void wg_gram_mfma(const Op& S0, const Op& S1, int64_t row0, int64_t r
       const int64_t nr = w0 + kGramSub + si;
 #pragma unroll
       for (int q = 0; q < kQ; ++q) {
-        v0[q] = (q0[q] && nr < rows0) ? f0[q] * q0[q][nr] : 0.0;
-        v1[q] = (q1[q] && nr < rows1) ? f1[q] * q1[q][nr] : 0.0;
+        const int c = sc + cstep * q;
+        v0[q] = (c < c0 && nr < rows0) ? colptr(S0, c)[nr] : 0.0;
+        v1[q] = (stage1 && c < c1 && nr < rows1) ? colptr(S1, c)[nr] : 0.0;
       }
     }
 #pragma unroll
@@ -202,8 +207,8 @@ __device__ void wg_gram_mfma(const Op& S0, const Op& S1, int64_t row0, int64_t r
         if (g1) sym_tile(tau - T0, ti, tj);
         else if (sym0) sym_tile(tau, ti, tj);
         else { ti = tau % t0; tj = tau / t0; }
-        const double* A = (g1 ? st1 : st0) + (ti * 16 + (l & 15)) * kStLd + (l >> 4);
-        const double* B = (kTwo ? (g1 ? st1 : st0) : (same ? st0 : st1)) + (tj * 16 + (l & 15)) * kStLd + (l >> 4);
+        const ldsd* A = (g1 ? s1 : s0) + (ti * 16 + (l & 15)) * kStLd + (l >> 4);
+        const ldsd* B = (kTwo ? (g1 ? s1 : s0) : (same ? s0 : s1)) + (tj * 16 + (l & 15)) * kStLd + (l >> 4);
 #pragma unroll
         for (int s4 = 0; s4 < kGramSub; s4 += 4) acc[q] = mfma64(A[s4], B[s4], acc[q]);
       }
@@ -229,12 +234,16 @@ __device__ void wg_gram_mfma(const Op& S0, const Op& S1, int64_t row0, int64_t r
       const int M = g1 ? c1 : c0, N = (g1 || sym0) ? M : c1;
       const bool mirror = (g1 || sym0) && ti != tj;
       const int j = tj * 16 + (l & 15);
+      const double fj0 = scale(S0, j), fj1 = scale(S1, j);
+      const double fj = (g1 || !sym0) ? fj1 : fj0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = ti * 16 + 4 * v + (l >> 4);
         if (i < M && j < N) {
-          out[i + j * ldo] = acc[q][v];
-          if (mirror) out[j + i * ldo] = acc[q][v];
+          const double fi0 = scale(S0, i), fi1 = scale(S1, i);
+          const double g = acc[q][v] * ((g1 ? fi1 : fi0) * fj);
+          out[i + j * ldo] = g;
+          if (mirror) out[j + i * ldo] = g;
         }
       }
     }
