@@ -569,8 +569,9 @@ constexpr size_t kSpExpLds = size_t(64 * kPNC + 64 * kSpLd + 64 * kPNC) * sizeof
 // Partial projections B_d(leaf rows)^T X(leaf rows) for every subtree level d
 // where the leaf is on the source side.  The source levels are dealt
 // round-robin to the waves; a wave stages its level's leaf rows of B_d in its
-// own LDS slice (one round trip of r loads per lane) and forms the r x nc
-// block (lane: row s of the block, half of its columns).
+// own LDS slice (one round trip of r loads per lane, zero past the leaf and
+// the rank) and forms the r x nc block as 16 x 16 tiles of FP64 matrix-core
+// k-steps over the 64 staged rows.
 __global__ void __launch_bounds__(256) k_sp_project(DevPtrs P, const ProdJob* jobs, const ProdUnit* units,
                                                     double* part, int Lmax) {
   extern __shared__ double sm[];
@@ -583,12 +584,15 @@ __global__ void __launch_bounds__(256) k_sp_project(DevPtrs P, const ProdJob* jo
   const int m = lf.size, nc = prod_cols(P, it, jb);
   const double* X = lvl_ptr(arr_base(P, jb.xarr), it, jb.xlev) + lf.start;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  double* Bl = sm + 64 * kPNC + wave * kSpLd * kRS;
+  const int li = lane & 15, lk = lane >> 4;
+  ldsd* Bl = lds_view(sm + 64 * kPNC + wave * kSpLd * kRS);
+  const ldsd* xv = lds_view(xl);
   g2l_pad(X, it.n, xl, 64, m, nc, 64, kPNC);
   __syncthreads();
   const bool src_c1 = (jb.which == 0) ? !jb.trans : jb.trans;
   const double* Bb = jb.which == 0 ? P.IL : P.IU;
   const int32_t* ranks = jb.which == 0 ? P.rankL : P.rankU;
+  const int nct = nc > 16 ? 2 : 1;
   int cnt = 0;
   for (int d = jb.d0; d < it.L; ++d) {
     const int side = (leaf >> (it.L - d - 1)) & 1;
@@ -596,28 +600,33 @@ __global__ void __launch_bounds__(256) k_sp_project(DevPtrs P, const ProdJob* jo
     if ((cnt++ % kSpWaves) != wave) continue;
     const int r = ranks[node_index(it, d, leaf >> (it.L - d))];
     const double* Bd = lvl_ptr(const_cast<double*>(Bb), it, d) + lf.start;
-    if (lane < m) {
+    {
       double v[kRS];
 #pragma unroll
-      for (int q = 0; q < kRS; ++q) v[q] = q < r ? Bd[lane + int64_t(q) * it.n] : 0.0;
+      for (int q = 0; q < kRS; ++q) v[q] = (q < r && lane < m) ? Bd[lane + int64_t(q) * it.n] : 0.0;
 #pragma unroll
       for (int q = 0; q < kRS; ++q) Bl[lane + q * kSpLd] = v[q];
     }
     wave_lds_sync();
-    const int srow = lane & 31, cp = lane >> 5;
-    if (srow < r) {
-      double acc[kPNC / 2];
+    double* po = part + (int64_t(blockIdx.x) * Lmax + d) * kRS * kPNC;
+    const int nrt = r > 16 ? 2 : 1;
+    for (int rt = 0; rt < nrt; ++rt) {
+      hfde_d4 a0{0.0, 0.0, 0.0, 0.0}, a1{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < kPNC / 2; ++k) acc[k] = 0.0;
-      for (int i = 0; i < m; ++i) {
-        const double bv = Bl[i + srow * kSpLd];
-#pragma unroll
-        for (int k = 0; k < kPNC / 2; ++k) acc[k] += bv * xl[i + (cp + 2 * k) * 64];
+      for (int s4 = 0; s4 < 16; ++s4) {
+        const int k = 4 * s4 + lk;
+        const double a = Bl[k + (rt * 16 + li) * kSpLd];        // (B_d^T)[row of the block][k]
+        a0 = mfma64(a, xv[k + li * 64], a0);
+        if (nct > 1) a1 = mfma64(a, xv[k + (16 + li) * 64], a1);
       }
-      double* po = part + (int64_t(blockIdx.x) * Lmax + d) * kRS * kPNC + srow;
 #pragma unroll
-      for (int k = 0; k < kPNC / 2; ++k)
-        if (cp + 2 * k < nc) po[(cp + 2 * k) * kRS] = acc[k];
+      for (int v = 0; v < 4; ++v) {
+        const int srow = rt * 16 + 4 * v + lk;
+        if (srow < r) {
+          if (li < nc) po[srow + li * kRS] = a0[v];
+          if (16 + li < nc) po[srow + (16 + li) * kRS] = a1[v];
+        }
+      }
     }
     wave_lds_sync();
   }
