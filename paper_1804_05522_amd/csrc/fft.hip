@@ -88,23 +88,25 @@ __device__ inline dd dd_mul_d(dd a, double b) {
 
 // Output of the exact product for row i: y_i = s x_i + nu (d+ (Tn x + far_re) + d- (Tn^T x + far_im)),
 // or the residual b_i - y_i.  Near band in double-double.
-__device__ inline double exact_row(const DevPtrs& P, const Item& it, const double* x, int64_t i, double far_re,
-                                   double far_im, const double* bvec) {
+// Chain q (terms k = q - 1 + 4t) of the compensated near-band sums of row i:
+//   (T x)_i = -sum_{j <= i+1} g_{i-j+1} x_j ;  near: i - j in [-1, w]
+//   (T^T x)_i = -sum_{j >= i-1} g_{j-i+1} x_j ;  near: j - i in [-1, w]
+// Compensated dot products (Ogita, Rump and Oishi, "Accurate sum and dot
+// product", 2005, algorithm Dot2): the running sum advances by error-free
+// additions and the rounding errors of the sums and products collect in a
+// second double, which gives the accuracy of twice the working precision.
+// Each sum runs in four interleaved chains (terms k = q mod 4) that are
+// combined in double-double at the end; rows whose whole band lies inside
+// the problem skip the range checks.
+struct NearChain {
+  double ps, pc, ms, mc;
+};
+
+__device__ inline NearChain exact_chain(const DevPtrs& P, const Item& it, const double* x, int64_t i, int q) {
   const double* g = P.g + it.g0;
   const int64_t n = it.n;
   const int w = it.band;
-  // (T x)_i = -sum_{j <= i+1} g_{i-j+1} x_j ;  near: i - j in [-1, w]
-  // (T^T x)_i = -sum_{j >= i-1} g_{j-i+1} x_j ;  near: j - i in [-1, w]
-  // Compensated dot products (Ogita, Rump and Oishi, "Accurate sum and dot
-  // product", 2005, algorithm Dot2): the running sum advances by error-free
-  // additions and the rounding errors of the sums and products collect in a
-  // second double, which gives the accuracy of twice the working precision.
-  // Each sum runs in four interleaved chains (terms k = q mod 4) that are
-  // combined in double-double at the end; rows whose whole band lies inside
-  // the problem skip the range checks.
-  double ps[4], pc[4], ms[4], mc[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) ps[q] = pc[q] = ms[q] = mc[q] = 0.0;
+  NearChain c{0.0, 0.0, 0.0, 0.0};
   auto acc = [](double& sum, double& err, double a, double b) {
     const double p = a * b;
     const double e = fma(a, b, -p);
@@ -113,34 +115,29 @@ __device__ inline double exact_row(const DevPtrs& P, const Item& it, const doubl
     err += t.lo + e;
   };
   if (i - w >= 0 && i + w < n && i + 1 < n && i >= 1) {
-    for (int k0 = -1; k0 <= w; k0 += 4) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = k0 + q;
-        if (k <= w) {
-          const double gk = -g[k + 1];
-          acc(ps[q], pc[q], gk, x[i - k]);
-          acc(ms[q], mc[q], gk, x[i + k]);
-        }
-      }
+    for (int k = q - 1; k <= w; k += 4) {
+      const double gk = -g[k + 1];
+      acc(c.ps, c.pc, gk, x[i - k]);
+      acc(c.ms, c.mc, gk, x[i + k]);
     }
   } else {
-    for (int k0 = -1; k0 <= w; k0 += 4) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = k0 + q;
-        if (k <= w) {
-          const double gk = -g[k + 1];
-          if (i - k >= 0 && i - k < n) acc(ps[q], pc[q], gk, x[i - k]);
-          if (i + k >= 0 && i + k < n) acc(ms[q], mc[q], gk, x[i + k]);
-        }
-      }
+    for (int k = q - 1; k <= w; k += 4) {
+      const double gk = -g[k + 1];
+      if (i - k >= 0 && i - k < n) acc(c.ps, c.pc, gk, x[i - k]);
+      if (i + k >= 0 && i + k < n) acc(c.ms, c.mc, gk, x[i + k]);
     }
   }
-  dd sp = dd_add(dd_add(two_sum(ps[0], pc[0]), two_sum(ps[1], pc[1])),
-                 dd_add(two_sum(ps[2], pc[2]), two_sum(ps[3], pc[3])));
-  dd sm = dd_add(dd_add(two_sum(ms[0], mc[0]), two_sum(ms[1], mc[1])),
-                 dd_add(two_sum(ms[2], mc[2]), two_sum(ms[3], mc[3])));
+  return c;
+}
+
+// Row i of M x (or of b - M x) from its four near chains and the far-field
+// values left by the inverse transform.
+__device__ inline double exact_finish(const DevPtrs& P, const Item& it, const double* x, int64_t i, const NearChain* c,
+                                      double far_re, double far_im, const double* bvec) {
+  dd sp = dd_add(dd_add(two_sum(c[0].ps, c[0].pc), two_sum(c[1].ps, c[1].pc)),
+                 dd_add(two_sum(c[2].ps, c[2].pc), two_sum(c[3].ps, c[3].pc)));
+  dd sm = dd_add(dd_add(two_sum(c[0].ms, c[0].mc), two_sum(c[1].ms, c[1].mc)),
+                 dd_add(two_sum(c[2].ms, c[2].mc), two_sum(c[3].ms, c[3].mc)));
   sp = dd_add(sp, dd{far_re, 0.0});
   sm = dd_add(sm, dd{far_im, 0.0});
   const int64_t gi = it.row0 + i;
@@ -152,6 +149,14 @@ __device__ inline double exact_row(const DevPtrs& P, const Item& it, const doubl
     return r.hi + r.lo;
   }
   return y.hi + y.lo;
+}
+
+__device__ inline double exact_row(const DevPtrs& P, const Item& it, const double* x, int64_t i, double far_re,
+                                   double far_im, const double* bvec) {
+  NearChain c[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c[q] = exact_chain(P, it, x, i, q);
+  return exact_finish(P, it, x, i, c, far_re, far_im, bvec);
 }
 
 // ---------------------------------------------------------------- setup
@@ -334,18 +339,35 @@ __global__ void __launch_bounds__(kFftWG) k_fft4_pass2(DevPtrs P, const FftUnit*
 }
 
 // Near-field rows (double-double) plus the far-field values left by the
-// inverse pass 2; one thread per row.
-__global__ void __launch_bounds__(256) k_exact_rows(DevPtrs P, const FftUnit* units, const double* x, int64_t ldx,
-                                                    double* y, int64_t ldy, const double* b, int64_t ldb) {
+// inverse pass 2: four lanes per row, one per near chain (the chains are
+// independent, so the row's sums have four times the lanes to hide their
+// latency), gathered in the row's first lane, which finishes the row.  A unit
+// is 256 rows; the work-group has 1024 threads.
+constexpr int kExactRowsWG = 1024;
+__global__ void __launch_bounds__(kExactRowsWG) k_exact_rows(DevPtrs P, const FftUnit* units, const double* x,
+                                                             int64_t ldx, double* y, int64_t ldy, const double* b,
+                                                             int64_t ldb) {
   const FftUnit u = units[blockIdx.x];
   const Item it = P.items[u.item];
-  const int64_t i = int64_t(u.tile) * blockDim.x + threadIdx.x;
-  if (i >= it.n) return;
+  const int q = threadIdx.x & 3, lane = threadIdx.x & 63;
+  const int64_t i = int64_t(u.tile) * (kExactRowsWG / 4) + (threadIdx.x >> 2);
+  const bool valid = i < it.n;
+  const double* xc = x + it.row0 + int64_t(u.col) * ldx;
+  const NearChain mine = valid ? exact_chain(P, it, xc, i, q) : NearChain{0.0, 0.0, 0.0, 0.0};
+  NearChain c[4];
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2) {
+    const int src = (lane & ~3) + s2;
+    c[s2].ps = __shfl(mine.ps, src);
+    c[s2].pc = __shfl(mine.pc, src);
+    c[s2].ms = __shfl(mine.ms, src);
+    c[s2].mc = __shfl(mine.mc, src);
+  }
+  if (q != 0 || !valid) return;
   const int64_t M = int64_t(1) << it.fftlog;
   const double2 w = P.fws[it.ws0 + int64_t(u.col) * 2 * M + i];
-  const double* xc = x + it.row0 + int64_t(u.col) * ldx;
   const double* bc = b ? b + it.row0 + int64_t(u.col) * ldb : nullptr;
-  y[it.row0 + int64_t(u.col) * ldy + i] = exact_row(P, it, xc, i, w.x, w.y, bc);
+  y[it.row0 + int64_t(u.col) * ldy + i] = exact_finish(P, it, xc, i, c, w.x, w.y, bc);
 }
 
 }  // namespace hfde
