@@ -715,45 +715,9 @@ __global__ void __launch_bounds__(256) k_sp_expand(DevPtrs P, const ProdJob* job
   const int t = threadIdx.x, wave = t >> 6, l = t & 63;
   const int li = l & 15, lk = l >> 4;
   const int64_t gl = it.leaf0 + leaf;
-  g2l_pad(X, it.n, xl, 64, m, nc, 64, kPNC);
-  g2l_pad(P.LUinv + gl * int64_t(b) * b, b, Fl, kSpLd, m, m, 64, 64);
-  if (t < 64) {
-    pm[t] = t < m ? P.perm[gl * b + t] : t;
-    pmi[t] = t < m ? P.perminv[gl * b + t] : t;
-  }
-  __syncthreads();
-  const bool two = nc > 16;
-  // 0: L^{-1} P^T x   1: P L^{-T} x   2: U^{-1} x   3: U^{-T} x
-  const int var = 2 * jb.which + jb.trans;
   const int i = wave * 16 + li;                      // row of this lane's leaf-op operand
-  const double* fa = (var & 1) ? Fl + i * kSpLd : Fl + i;
-  const int fs = (var & 1) ? 1 : kSpLd;
-  hfde_d4 acc0{0.0, 0.0, 0.0, 0.0}, acc1{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int s4 = 0; s4 < 16; ++s4) {
-    const int k = 4 * s4 + lk;
-    const bool tri = var == 0 ? k < i : (var == 1 ? k > i : (var == 2 ? k >= i : k <= i));
-    const double a = tri ? fa[k * fs] : ((var < 2 && k == i) ? 1.0 : 0.0);
-    const int xr = var == 0 ? pm[k] : k;
-    acc0 = mfma64(a, xl[xr + li * 64], acc0);
-    if (two) acc1 = mfma64(a, xl[xr + (16 + li) * 64], acc1);
-  }
-  if (var == 1) {                                    // rows of L^{-T} x in pivot order: gather
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      yl[wave * 16 + 4 * v + lk + li * 64] = acc0[v];
-      yl[wave * 16 + 4 * v + lk + (16 + li) * 64] = acc1[v];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int q = pmi[wave * 16 + 4 * v + lk];
-      acc0[v] = yl[q + li * 64];
-      acc1[v] = yl[q + (16 + li) * 64];
-    }
-    __syncthreads();
-  }
-  // destination levels
+  // destination levels; the first level's operands are fetched while X and
+  // the leaf inverse are staged and the leaf op runs
   const bool src_c1 = (jb.which == 0) ? !jb.trans : jb.trans;
   const int dst_side = src_c1 ? 1 : 0;
   const double* Bb = jb.which == 0 ? P.IL : P.IU;
@@ -785,6 +749,43 @@ __global__ void __launch_bounds__(256) k_sp_expand(DevPtrs P, const ProdJob* job
   int d = next_level(jb.d0 - 1);
   SpLevel cur, nxt;
   if (d < it.L) fetch(d, cur);
+  g2l_pad(X, it.n, xl, 64, m, nc, 64, kPNC);
+  g2l_pad(P.LUinv + gl * int64_t(b) * b, b, Fl, kSpLd, m, m, 64, 64);
+  if (t < 64) {
+    pm[t] = t < m ? P.perm[gl * b + t] : t;
+    pmi[t] = t < m ? P.perminv[gl * b + t] : t;
+  }
+  __syncthreads();
+  const bool two = nc > 16;
+  // 0: L^{-1} P^T x   1: P L^{-T} x   2: U^{-1} x   3: U^{-T} x
+  const int var = 2 * jb.which + jb.trans;
+  const double* fa = (var & 1) ? Fl + i * kSpLd : Fl + i;
+  const int fs = (var & 1) ? 1 : kSpLd;
+  hfde_d4 acc0{0.0, 0.0, 0.0, 0.0}, acc1{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s4 = 0; s4 < 16; ++s4) {
+    const int k = 4 * s4 + lk;
+    const bool tri = var == 0 ? k < i : (var == 1 ? k > i : (var == 2 ? k >= i : k <= i));
+    const double a = tri ? fa[k * fs] : ((var < 2 && k == i) ? 1.0 : 0.0);
+    const int xr = var == 0 ? pm[k] : k;
+    acc0 = mfma64(a, xl[xr + li * 64], acc0);
+    if (two) acc1 = mfma64(a, xl[xr + (16 + li) * 64], acc1);
+  }
+  if (var == 1) {                                    // rows of L^{-T} x in pivot order: gather
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      yl[wave * 16 + 4 * v + lk + li * 64] = acc0[v];
+      yl[wave * 16 + 4 * v + lk + (16 + li) * 64] = acc1[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = pmi[wave * 16 + 4 * v + lk];
+      acc0[v] = yl[q + li * 64];
+      acc1[v] = yl[q + (16 + li) * 64];
+    }
+    __syncthreads();
+  }
   while (d < it.L) {
     const int dn = next_level(d);
     if (dn < it.L) fetch(dn, nxt);
