@@ -237,7 +237,9 @@ struct fde2d_plan_s {
   double* H0 = nullptr;
   double* Zx[2] = {nullptr, nullptr};   // solution factors (ping-pong)
   double* Wx[2] = {nullptr, nullptr};
-  double* Zd[2] = {nullptr, nullptr};   // correction factors
+  double* Zd[2] = {nullptr, nullptr};   // correction factors (even shift pairs of a sweep, then the merge)
+  double* Ze[2] = {nullptr, nullptr};   // correction factors of the odd shift pairs
+  double* We[2] = {nullptr, nullptr};
   double* Wd[2] = {nullptr, nullptr};
   double* R1 = nullptr;         // residual recompression temporaries
   double* R1w = nullptr;
@@ -246,9 +248,9 @@ struct fde2d_plan_s {
   double* ex_out = nullptr;
   int32_t* ranks = nullptr;     // device ranks, see kR_* below
   hipGraphExec_t blk_graph[2][16] = {};   // sweep blocks of four shift pairs, by solve width (16 / 32 columns)
-  hipGraphExec_t d_graph[16] = {};        // their accumulation chains
-  hipStream_t side = nullptr;             // stream of the accumulation chains
-  hipEvent_t ev_blk = nullptr, ev_done = nullptr;
+  hipGraphExec_t d_graph[2][16] = {};     // their accumulation chains (even and odd shift pairs)
+  hipStream_t side[2] = {nullptr, nullptr};   // streams of the two accumulation chains
+  hipEvent_t ev_blk = nullptr, ev_done[2] = {nullptr, nullptr};
   LrUnit* units = nullptr;      // per work slot: gram, reduce and form units
   int64_t unit_rows[16][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1},
                               {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};

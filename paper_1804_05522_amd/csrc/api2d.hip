@@ -7,7 +7,8 @@
 
 namespace {
 
-enum { kR_R0 = 0, kR_D0 = 1, kR_D1 = 2, kR_X0 = 3, kR_X1 = 4, kR_T = 5, kR_C = 6, kR_ZERO = 7, kR_N = 8 };
+enum { kR_R0 = 0, kR_D0 = 1, kR_D1 = 2, kR_X0 = 3, kR_X1 = 4, kR_T = 5, kR_C = 6, kR_ZERO = 7, kR_E0 = 8, kR_E1 = 9,
+       kR_N = 10 };
 
 // ---------- Zolotarev shifts for two real intervals (host, FP64) ----------
 double ellip_K(double k) {           // complete elliptic integral of the first kind, modulus k (AGM)
@@ -198,37 +199,42 @@ hodlr_status enqueue_main_block(fde2d_plan P, int b, int nc, hipStream_t s) {
   return run_lr(P, nj, 1, false, s);
 }
 
-// The same shift pairs, accumulation chain: D <- recompress([D, w Z_j][W_D, Y_j]).
-// Z_j, Y_j are the solve outputs in shift j's own rows of the workspace, which
-// no other shift of the sweep touches.
-hodlr_status enqueue_d_block(fde2d_plan P, int b, hipStream_t s) {
+// The same shift pairs, accumulation chains: D_g <- recompress([D_g, w Z_j][W_g, Y_j])
+// for the pairs jo with jo mod 2 = g (D_0 in Zd/Wd, D_1 in Ze/We, each
+// ping-ponging between its two buffers; work slots 2, 3 and 13, 14).  Z_j,
+// Y_j are the solve outputs in shift j's own rows of the workspace, which no
+// other shift of the sweep touches, so the chains run beside the solves.
+hodlr_status enqueue_d_block(fde2d_plan P, int b, int g, hipStream_t s) {
   hodlr_mat m = P->mat;
   const int64_t nx = P->nx, ny = P->ny, tn = m->total_n;
   const double tol = P->opts.tol;
-  for (int jo = 4 * b; jo < std::min(4 * b + 4, P->J); ++jo) {
+  double* const* Zg = g == 0 ? P->Zd : P->Ze;
+  double* const* Wg = g == 0 ? P->Wd : P->We;
+  const int rk = g == 0 ? kR_D0 : kR_E0;
+  for (int jo = 4 * b + g; jo < std::min(4 * b + 4, P->J); jo += 2) {
     const int j = P->order[jo];
-    const int parity = jo & 1;
+    const int parity = (jo >> 1) & 1;
     const Item& ix = m->items[j];
     const Item& iy = m->items[P->J + j];
     const double w = P->p[j] + P->q[j];
     LrJob jb{};
-    jb.X.g[0] = grp(P->Zd[parity], nx, P->ranks + kR_D0 + parity, 0, 1.0);
+    jb.X.g[0] = grp(Zg[parity], nx, P->ranks + rk + parity, 0, 1.0);
     jb.X.g[1] = grp(P->xin + ix.row0, tn, P->ranks + kR_R0, 0, w);
     jb.X.g[2] = grp_none();
-    jb.Y.g[0] = grp(P->Wd[parity], ny, P->ranks + kR_D0 + parity, 0, 1.0);
+    jb.Y.g[0] = grp(Wg[parity], ny, P->ranks + rk + parity, 0, 1.0);
     jb.Y.g[1] = grp(P->xin + iy.row0, tn, P->ranks + kR_R0, 0, 1.0);
     jb.Y.g[2] = grp_none();
     jb.rows_x = nx;
     jb.rows_y = ny;
-    jb.rank_out = P->ranks + kR_D0 + (1 - parity);
+    jb.rank_out = P->ranks + rk + (1 - parity);
     jb.tau = 0.0;
     jb.tau_rel = 0.1 * tol;
     jb.rmax = kRS;
-    jb.U = P->Zd[1 - parity];
+    jb.U = Zg[1 - parity];
     jb.ldu = nx;
-    jb.V = P->Wd[1 - parity];
+    jb.V = Wg[1 - parity];
     jb.ldv = ny;
-    TRY(run_lr(P, jb, 2 + parity, true, s));
+    TRY(run_lr(P, jb, (g == 0 ? 2 : 13) + parity, true, s));
   }
   return HODLR_OK;
 }
@@ -254,47 +260,79 @@ hodlr_status replay(hipGraphExec_t& ge, hipStream_t s, F&& enqueue) {
 // One fADI sweep on the right-hand side G H^T (rank r0, in P->G / P->H; they are
 // consumed).  Accumulates the sweep's solution into Zd/Wd; returns the steps
 // taken and the parity holding the result.  The convergence test comes after
-// every block of four shift pairs.  On a stream of its own (and without kernel
-// timing) each block's two chains are HIP graphs captured on first use, and
-// the accumulation chain runs on a second stream one block behind the solves,
-// joined before the sweep returns; otherwise both run in order on one stream.
+// every block of four shift pairs.  The solution accumulates in two chains
+// (even and odd shift pairs) that are merged at the end.  On a stream of its
+// own (and without kernel timing) each block's solves and each chain are HIP
+// graphs captured on first use, and the two chains run on two more streams
+// one block behind the solves, joined before the merge; otherwise everything
+// runs in the same order on one stream.
 hodlr_status adi_sweep(fde2d_plan P, int r0, double cnorm, int& steps, int& parity, hipStream_t s) {
   const int64_t nx = P->nx, ny = P->ny;
   const double tol = P->opts.tol;
   HIP_TRY(hipMemsetAsync(P->ranks + kR_D0, 0, sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P->ranks + kR_E0, 0, sizeof(int32_t), s));
   parity = 0;
   steps = 0;
   if (r0 == 0) return HODLR_OK;
   const int wide = r0 > kNCS ? 1 : 0;
   const int nc = wide ? 2 * kNCS : kNCS;
-  const bool graphs = s != nullptr && g_timer == nullptr && P->side != nullptr;
+  const bool graphs = s != nullptr && g_timer == nullptr && P->side[0] != nullptr;
   if (graphs)
-    for (int slot = 1; slot <= 3; ++slot) TRY(ensure_units(P, slot, nx, ny, s));
+    for (int slot : {1, 2, 3, 13, 14}) TRY(ensure_units(P, slot, nx, ny, s));
   const int nb = (P->J + 3) / 4;
   hodlr_status res = HODLR_OK;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = 0; b < nb && res == HODLR_OK; ++b) {
     if (graphs) {
       res = replay(P->blk_graph[wide][b], s, [&] { return enqueue_main_block(P, b, nc, s); });
       if (res != HODLR_OK) break;
       HIP_TRY(hipEventRecord(P->ev_blk, s));
-      HIP_TRY(hipStreamWaitEvent(P->side, P->ev_blk, 0));
-      res = replay(P->d_graph[b], P->side, [&] { return enqueue_d_block(P, b, P->side); });
+      for (int g = 0; g < 2 && res == HODLR_OK; ++g) {
+        if (4 * b + g >= P->J) continue;         // no pair of this chain in the block
+        HIP_TRY(hipStreamWaitEvent(P->side[g], P->ev_blk, 0));
+        res = replay(P->d_graph[g][b], P->side[g], [&] { return enqueue_d_block(P, b, g, P->side[g]); });
+      }
       if (res != HODLR_OK) break;
     } else {
       TRY(enqueue_main_block(P, b, nc, s));
-      TRY(enqueue_d_block(P, b, s));
+      TRY(enqueue_d_block(P, b, 0, s));
+      TRY(enqueue_d_block(P, b, 1, s));
     }
     steps = std::min(4 * b + 4, P->J);
-    parity = steps & 1;
     double f2 = 0.0;
     res = read_frob(P, 1, &f2, s);
     if (res != HODLR_OK || std::sqrt(std::max(f2, 0.0)) <= tol * cnorm) break;
   }
-  if (graphs) {                                  // join the accumulation chain
-    HIP_TRY(hipEventRecord(P->ev_done, P->side));
-    HIP_TRY(hipStreamWaitEvent(s, P->ev_done, 0));
+  if (graphs) {                                  // join the accumulation chains
+    for (int g = 0; g < 2; ++g) {
+      HIP_TRY(hipEventRecord(P->ev_done[g], P->side[g]));
+      HIP_TRY(hipStreamWaitEvent(s, P->ev_done[g], 0));
+    }
   }
-  return res;
+  if (res != HODLR_OK) return res;
+  // chain g took n_g = ceil or floor of steps / 2 pairs; its result is in buffer n_g & 1
+  const int p0 = ((steps + 1) / 2) & 1, p1 = (steps / 2) & 1;
+  parity = p0;
+  if (steps < 2) return HODLR_OK;
+  LrJob mj{};                                    // D <- recompress([D_0, D_1][W_0, W_1])
+  mj.X.g[0] = grp(P->Zd[p0], nx, P->ranks + kR_D0 + p0, 0, 1.0);
+  mj.X.g[1] = grp(P->Ze[p1], nx, P->ranks + kR_E0 + p1, 0, 1.0);
+  mj.X.g[2] = grp_none();
+  mj.Y.g[0] = grp(P->Wd[p0], ny, P->ranks + kR_D0 + p0, 0, 1.0);
+  mj.Y.g[1] = grp(P->We[p1], ny, P->ranks + kR_E0 + p1, 0, 1.0);
+  mj.Y.g[2] = grp_none();
+  mj.rows_x = nx;
+  mj.rows_y = ny;
+  mj.rank_out = P->ranks + kR_D0 + (1 - p0);
+  mj.tau = 0.0;
+  mj.tau_rel = 0.1 * tol;
+  mj.rmax = kRS;
+  mj.U = P->Zd[1 - p0];
+  mj.ldu = nx;
+  mj.V = P->Wd[1 - p0];
+  mj.ldv = ny;
+  TRY(run_lr(P, mj, 15, true, s));
+  parity = 1 - p0;
+  return HODLR_OK;
 }
 
 }  // namespace
@@ -303,15 +341,19 @@ extern "C" {
 
 void fde2d_plan_destroy(fde2d_plan p) {
   if (!p) return;
-  if (p->side) (void)hipStreamSynchronize(p->side);
+  for (hipStream_t sd : p->side)
+    if (sd) (void)hipStreamSynchronize(sd);
   for (auto& row : p->blk_graph)
     for (hipGraphExec_t& ge : row)
       if (ge) (void)hipGraphExecDestroy(ge);
-  for (hipGraphExec_t& ge : p->d_graph)
-    if (ge) (void)hipGraphExecDestroy(ge);
+  for (auto& row : p->d_graph)
+    for (hipGraphExec_t& ge : row)
+      if (ge) (void)hipGraphExecDestroy(ge);
   if (p->ev_blk) (void)hipEventDestroy(p->ev_blk);
-  if (p->ev_done) (void)hipEventDestroy(p->ev_done);
-  if (p->side) (void)hipStreamDestroy(p->side);
+  for (hipEvent_t e : p->ev_done)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t sd : p->side)
+    if (sd) (void)hipStreamDestroy(sd);
   hodlr_destroy(p->mat);
   hodlr_destroy(p->exact);
   for (void* q : p->allocs) (void)hipFree(q);
@@ -342,10 +384,12 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
   fde2d_plan P = new (std::nothrow) fde2d_plan_s;
   if (!P) return HODLR_ENOMEM;
   P->ctx = ctx;
-  // second stream (default priority) for the sweeps' accumulation chain
-  if (s != nullptr && (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
+  // two more streams (default priority) for the sweeps' accumulation chains
+  if (s != nullptr && (hipStreamCreateWithFlags(&P->side[0], hipStreamNonBlocking) != hipSuccess ||
+                       hipStreamCreateWithFlags(&P->side[1], hipStreamNonBlocking) != hipSuccess ||
                        hipEventCreateWithFlags(&P->ev_blk, hipEventDisableTiming) != hipSuccess ||
-                       hipEventCreateWithFlags(&P->ev_done, hipEventDisableTiming) != hipSuccess)) {
+                       hipEventCreateWithFlags(&P->ev_done[0], hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&P->ev_done[1], hipEventDisableTiming) != hipSuccess)) {
     fde2d_plan_destroy(P);
     return HODLR_EHIP;
   }
@@ -457,7 +501,8 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
             plan_alloc(P, &P->mbuf, 16 * 2 * kMaxCat * kRS) == HODLR_OK && plan_alloc(P, &P->frob, 16) == HODLR_OK;
   for (int k = 0; k < 2 && ok; ++k)
     ok = plan_alloc(P, &P->Zx[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wx[k], ny * kRS) == HODLR_OK &&
-         plan_alloc(P, &P->Zd[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wd[k], ny * kRS) == HODLR_OK;
+         plan_alloc(P, &P->Zd[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wd[k], ny * kRS) == HODLR_OK &&
+         plan_alloc(P, &P->Ze[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->We[k], ny * kRS) == HODLR_OK;
   if (!ok) { fde2d_plan_destroy(P); return HODLR_ENOMEM; }
   if (hipMemcpy(P->pair_wu, pw.data(), pw.size() * sizeof(WorkUnit), hipMemcpyHostToDevice) != hipSuccess ||
       (!pn.empty() && hipMemcpy(P->pair_nu, pn.data(), pn.size() * sizeof(NodeUnit), hipMemcpyHostToDevice) != hipSuccess) ||
