@@ -414,6 +414,8 @@ void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int
                          xc, ldx);
       HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, true,
                          xc, ldx, yc, ldy, bc, ldb);
+    }
+    if (m->n_fft_rows) {
       const int per_colr = m->n_fft_rows / kNCF;
       HFDE_LAUNCH(k_exact_rows, dim3(per_colr * cn), dim3(kExactRowsWG), 0, s, m->P, m->fft_row_units, xc, ldx, yc,
                          ldy, bc, ldb);
@@ -1107,6 +1109,10 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
         m->fft4_lds = std::max(m->fft4_lds, size_t(T) * (size_t(1) << l1) * sizeof(double2));
         for (int t = 0; t < (1 << l1) / T; ++t) u1.push_back(FftUnit{i, c, t, 0});
         for (int t = 0; t < (1 << l2) / T; ++t) u2.push_back(FftUnit{i, c, t, 0});
+      }
+    // near-band rows of every item (after either transform path)
+    for (int c = 0; c < kNCF; ++c)
+      for (int i = 0; i < m->batch; ++i) {
         constexpr int kRowsPerUnit = kExactRowsWG / 4;   // rows of one k_exact_rows work-group
         for (int64_t t = 0; t < (m->items[i].n + kRowsPerUnit - 1) / kRowsPerUnit; ++t)
           ur.push_back(FftUnit{i, c, int32_t(t), 0});

@@ -151,14 +151,6 @@ __device__ inline double exact_finish(const DevPtrs& P, const Item& it, const do
   return y.hi + y.lo;
 }
 
-__device__ inline double exact_row(const DevPtrs& P, const Item& it, const double* x, int64_t i, double far_re,
-                                   double far_im, const double* bvec) {
-  NearChain c[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) c[q] = exact_chain(P, it, x, i, q);
-  return exact_finish(P, it, x, i, c, far_re, far_im, bvec);
-}
-
 // ---------------------------------------------------------------- setup
 __global__ void k_twiddles(DevPtrs P, int item) {
   const Item it = P.items[item];
@@ -227,13 +219,14 @@ __global__ void __launch_bounds__(kFftWG) k_fft_small(DevPtrs P, const FftUnit* 
   }
   __syncthreads();
   lds_fft(buf, 1, logM, tw, logM, true);
+  // far-field values for k_exact_rows, which adds the near band
   const double inv = 1.0 / double(M);
-  double* yc = y + it.row0 + int64_t(u.col) * ldy;
-  const double* bc = b ? b + it.row0 + int64_t(u.col) * ldb : nullptr;
+  double2* ws = P.fws + it.ws0 + int64_t(u.col) * 2 * M;
   for (int64_t i = threadIdx.x; i < it.n; i += blockDim.x) {
     const double2 w = buf[i];
-    yc[i] = exact_row(P, it, xc, i, w.x * inv, w.y * inv, bc);
+    ws[i] = make_double2(w.x * inv, w.y * inv);
   }
+  (void)y; (void)ldy; (void)b; (void)ldb;
 }
 
 // Four-step split: M = M1 * M2, n = n1 + M1 n2, k = k2 + M2 k1.
