@@ -251,6 +251,8 @@ struct fde2d_plan_s {
   hipGraphExec_t d_graph[2][16] = {};     // their accumulation chains (even and odd shift pairs)
   hipStream_t side[2] = {nullptr, nullptr};   // streams of the two accumulation chains
   hipEvent_t ev_blk = nullptr, ev_done[2] = {nullptr, nullptr};
+  int32_t* host_ranks = nullptr;          // pinned host memory: ranks (32 ints), then the norm read-back
+  double* host_frob = nullptr;
   LrUnit* units = nullptr;      // per work slot: gram, reduce and form units
   int64_t unit_rows[16][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1},
                               {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};

@@ -152,15 +152,19 @@ hodlr_status run_lr(fde2d_plan P, const LrJob& job, int slot, bool recompress, h
   return HODLR_OK;
 }
 
+// Device-to-host reads of the step's control values go through pinned host
+// memory (an asynchronous copy, then one wait), not through a pageable buffer.
 hodlr_status read_ranks(fde2d_plan P, int32_t* h, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(h, P->ranks, kR_N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(P->host_ranks, P->ranks, kR_N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  memcpy(h, P->host_ranks, kR_N * sizeof(int32_t));
   return HODLR_OK;
 }
 
 hodlr_status read_frob(fde2d_plan P, int slot, double* v, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(v, P->frob + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(P->host_frob, P->frob + slot, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  *v = *P->host_frob;
   return HODLR_OK;
 }
 
@@ -357,6 +361,7 @@ void fde2d_plan_destroy(fde2d_plan p) {
   hodlr_destroy(p->mat);
   hodlr_destroy(p->exact);
   for (void* q : p->allocs) (void)hipFree(q);
+  if (p->host_ranks) (void)hipHostFree(p->host_ranks);
   delete p;
 }
 
@@ -384,6 +389,12 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
   fde2d_plan P = new (std::nothrow) fde2d_plan_s;
   if (!P) return HODLR_ENOMEM;
   P->ctx = ctx;
+  if (hipHostMalloc(reinterpret_cast<void**>(&P->host_ranks), 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    P->host_ranks = nullptr;
+    fde2d_plan_destroy(P);
+    return HODLR_ENOMEM;
+  }
+  P->host_frob = reinterpret_cast<double*>(P->host_ranks + 32);
   // two more streams (default priority) for the sweeps' accumulation chains
   if (s != nullptr && (hipStreamCreateWithFlags(&P->side[0], hipStreamNonBlocking) != hipSuccess ||
                        hipStreamCreateWithFlags(&P->side[1], hipStreamNonBlocking) != hipSuccess ||
