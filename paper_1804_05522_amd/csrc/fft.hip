@@ -102,6 +102,33 @@ struct NearChain {
   double ps, pc, ms, mc;
 };
 
+// X: x or its LDS window; XI(k) reads x[i + k] through it.  G: the weights.
+template <typename XA, typename GA>
+__device__ inline NearChain exact_chain_t(XA xat, GA gat, int64_t i, int64_t n, int w, int q) {
+  NearChain c{0.0, 0.0, 0.0, 0.0};
+  auto acc = [](double& sum, double& err, double a, double b) {
+    const double p = a * b;
+    const double e = fma(a, b, -p);
+    const dd t = two_sum(sum, p);
+    sum = t.hi;
+    err += t.lo + e;
+  };
+  if (i - w >= 0 && i + w < n && i + 1 < n && i >= 1) {
+    for (int k = q - 1; k <= w; k += 4) {
+      const double gk = -gat(k + 1);
+      acc(c.ps, c.pc, gk, xat(-k));
+      acc(c.ms, c.mc, gk, xat(k));
+    }
+  } else {
+    for (int k = q - 1; k <= w; k += 4) {
+      const double gk = -gat(k + 1);
+      if (i - k >= 0 && i - k < n) acc(c.ps, c.pc, gk, xat(-k));
+      if (i + k >= 0 && i + k < n) acc(c.ms, c.mc, gk, xat(k));
+    }
+  }
+  return c;
+}
+
 __device__ inline NearChain exact_chain(const DevPtrs& P, const Item& it, const double* x, int64_t i, int q) {
   const double* g = P.g + it.g0;
   const int64_t n = it.n;
@@ -340,13 +367,29 @@ constexpr int kExactRowsWG = 1024;
 __global__ void __launch_bounds__(kExactRowsWG) k_exact_rows(DevPtrs P, const FftUnit* units, const double* x,
                                                              int64_t ldx, double* y, int64_t ldy, const double* b,
                                                              int64_t ldb) {
+  constexpr int kRows = kExactRowsWG / 4, kPad = 66;     // the band is at most 64 wide
+  __shared__ double xs[kRows + 2 * kPad];
+  __shared__ double gs[kPad + 2];
   const FftUnit u = units[blockIdx.x];
   const Item it = P.items[u.item];
   const int q = threadIdx.x & 3, lane = threadIdx.x & 63;
-  const int64_t i = int64_t(u.tile) * (kExactRowsWG / 4) + (threadIdx.x >> 2);
+  const int64_t i0 = int64_t(u.tile) * kRows;
+  const int64_t i = i0 + (threadIdx.x >> 2);
   const bool valid = i < it.n;
   const double* xc = x + it.row0 + int64_t(u.col) * ldx;
-  const NearChain mine = valid ? exact_chain(P, it, xc, i, q) : NearChain{0.0, 0.0, 0.0, 0.0};
+  // the tile's rows of x with the band on both sides, and the weights, in LDS
+  for (int e = threadIdx.x; e < kRows + 2 * kPad; e += blockDim.x) {
+    const int64_t j = i0 - kPad + e;
+    xs[e] = (j >= 0 && j < it.n) ? xc[j] : 0.0;
+  }
+  const double* g = P.g + it.g0;
+  for (int e = threadIdx.x; e < it.band + 2; e += blockDim.x) gs[e] = g[e];
+  __syncthreads();
+  const ldsd* xw = lds_view(xs) + (kPad + (threadIdx.x >> 2));    // x[i] of this row
+  const ldsd* gw = lds_view(gs);
+  const NearChain mine =
+      valid ? exact_chain_t([&](int k) { return xw[k]; }, [&](int k) { return gw[k]; }, i, it.n, it.band, q)
+            : NearChain{0.0, 0.0, 0.0, 0.0};
   NearChain c[4];
 #pragma unroll
   for (int s2 = 0; s2 < 4; ++s2) {
