@@ -256,6 +256,45 @@ __global__ void __launch_bounds__(kFftWG) k_fft_small(DevPtrs P, const FftUnit* 
   (void)y; (void)ldy; (void)b; (void)ldb;
 }
 
+// As lds_fft, with the m/2 roots e^{-2 pi i j / m} of the transform length
+// staged in LDS (tws), so that no stage waits on global memory.
+constexpr int kTwLds = 1024;           // roots held in LDS (transforms up to 2048 points)
+__device__ void lds_fft_tw(double2* buf, int ntile, int logm, const double2* twsp, bool inverse) {
+  const int m = 1 << logm;
+  const int half_total = ntile * (m >> 1);
+  const ldsd* tws = lds_view(reinterpret_cast<const double*>(twsp));   // re, im interleaved
+  ldsd* b3 = lds_view(reinterpret_cast<double*>(buf));
+  const double sgn = inverse ? -1.0 : 1.0;
+  for (int lh = 0; lh < logm; ++lh) {
+    const int h = 1 << lh;
+    const int shift = logm - lh - 1;          // w = omega_{2h}^k = tws[k << shift]
+    for (int b = threadIdx.x; b < half_total; b += blockDim.x) {
+      const int t = b >> (logm - 1);
+      const int q = b & ((m >> 1) - 1);
+      const int k = q & (h - 1);
+      const int i0 = t * m + ((q >> lh) << (lh + 1)) + k;
+      const int i1 = i0 + h;
+      const double wr = tws[2 * (k << shift)], wi = sgn * tws[2 * (k << shift) + 1];
+      const double ar = b3[2 * i0], ai = b3[2 * i0 + 1];
+      const double br = b3[2 * i1], bi = b3[2 * i1 + 1];
+      const double cr = br * wr - bi * wi, ci = br * wi + bi * wr;
+      b3[2 * i0] = ar + cr;
+      b3[2 * i0 + 1] = ai + ci;
+      b3[2 * i1] = ar - cr;
+      b3[2 * i1 + 1] = ai - ci;
+    }
+    __syncthreads();
+  }
+}
+
+// Transform of `ntile` tiles of length 2^logm in buf: with the roots staged
+// in LDS when they fit, else read from the problem's root table.
+__device__ inline void tile_fft(double2* buf, double2* tws, int ntile, int logm, const double2* tw, int logM,
+                                bool inverse) {
+  if ((1 << logm) / 2 <= kTwLds) lds_fft_tw(buf, ntile, logm, tws, inverse);
+  else lds_fft(buf, ntile, logm, tw, logM, inverse);
+}
+
 // Four-step split: M = M1 * M2, n = n1 + M1 n2, k = k2 + M2 k1.
 // Columns per work-group of a four-step pass: fewer columns give more
 // work-groups per pass (the passes are latency-bound at these lengths), more
@@ -287,6 +326,9 @@ __global__ void __launch_bounds__(kFftWG) k_fft4_pass1(DevPtrs P, const FftUnit*
   const double2* Win = ws + (int64_t(1) << logM);   // second half: W (inverse input)
   const int n1base = u.tile * T;
   const double* xc = x ? x + it.row0 + int64_t(u.col) * ldx : nullptr;
+  __shared__ double2 tws[kTwLds];
+  if (M2 / 2 <= kTwLds)
+    for (int j = threadIdx.x; j < M2 / 2; j += blockDim.x) tws[j] = tw[int64_t(j) << (logM - l2)];
   for (int e = threadIdx.x; e < T * M2; e += blockDim.x) {
     const int t = e % T, n2 = e / T;
     const int64_t nidx = int64_t(n1base + t) + int64_t(M1) * n2;
@@ -301,7 +343,7 @@ __global__ void __launch_bounds__(kFftWG) k_fft4_pass1(DevPtrs P, const FftUnit*
     buf[t * M2 + bitrev(n2, l2)] = v;
   }
   __syncthreads();
-  lds_fft(buf, T, l2, tw, logM, inverse);
+  tile_fft(buf, tws, T, l2, tw, logM, inverse);
   const int64_t Mmask = (int64_t(1) << logM) - 1;
   for (int e = threadIdx.x; e < T * M2; e += blockDim.x) {
     const int t = e % T, k2 = e / T;
@@ -332,12 +374,15 @@ __global__ void __launch_bounds__(kFftWG) k_fft4_pass2(DevPtrs P, const FftUnit*
   const double2* Y = ws;
   double2* Wout = ws + M;
   const int k2base = u.tile * T;
+  __shared__ double2 tws[kTwLds];
+  if (M1 / 2 <= kTwLds)
+    for (int j = threadIdx.x; j < M1 / 2; j += blockDim.x) tws[j] = tw[int64_t(j) << (logM - l1)];
   for (int e = threadIdx.x; e < T * M1; e += blockDim.x) {
     const int n1 = e % M1, t = e / M1;
     buf[t * M1 + bitrev(n1, l1)] = Y[int64_t(k2base + t) * M1 + n1];
   }
   __syncthreads();
-  lds_fft(buf, T, l1, tw, logM, inverse);
+  tile_fft(buf, tws, T, l1, tw, logM, inverse);
   double2* mu = P.mu + it.mu0;
   const double inv = 1.0 / double(M);
   const double* xc = x ? x + it.row0 + int64_t(u.col) * ldx : nullptr;
