@@ -261,27 +261,64 @@ __global__ void __launch_bounds__(kFftWG) k_fft_small(DevPtrs P, const FftUnit* 
 constexpr int kTwLds = 1024;           // roots held in LDS (transforms up to 2048 points)
 __device__ void lds_fft_tw(double2* buf, int ntile, int logm, const double2* twsp, bool inverse) {
   const int m = 1 << logm;
-  const int half_total = ntile * (m >> 1);
   const ldsd* tws = lds_view(reinterpret_cast<const double*>(twsp));   // re, im interleaved
   ldsd* b3 = lds_view(reinterpret_cast<double*>(buf));
   const double sgn = inverse ? -1.0 : 1.0;
-  for (int lh = 0; lh < logm; ++lh) {
+  // (x, y) <- (x + w y, x - w y), w = tws[j] (conjugated for the inverse)
+  auto bfly = [&](double& xr, double& xi, double& yr, double& yi, int j) {
+    const double wr = tws[2 * j], wi = sgn * tws[2 * j + 1];
+    const double cr = yr * wr - yi * wi, ci = yr * wi + yi * wr;
+    yr = xr - cr;
+    yi = xi - ci;
+    xr = xr + cr;
+    xi = xi + ci;
+  };
+  int lh = 0;
+  // stages lh and lh + 1 together: one thread takes the four elements
+  // k, k + h, k + 2h, k + 3h of a block of 4h (the same butterflies as two
+  // radix-2 stages, half the barriers)
+  for (; lh + 1 < logm; lh += 2) {
     const int h = 1 << lh;
-    const int shift = logm - lh - 1;          // w = omega_{2h}^k = tws[k << shift]
+    const int quarter_total = ntile * (m >> 2);
+    for (int b = threadIdx.x; b < quarter_total; b += blockDim.x) {
+      const int t = b >> (logm - 2);
+      const int q = b & ((m >> 2) - 1);
+      const int k = q & (h - 1);
+      const int i0 = t * m + ((q >> lh) << (lh + 2)) + k;
+      double r0 = b3[2 * i0], j0 = b3[2 * i0 + 1];
+      double r1 = b3[2 * (i0 + h)], j1 = b3[2 * (i0 + h) + 1];
+      double r2 = b3[2 * (i0 + 2 * h)], j2 = b3[2 * (i0 + 2 * h) + 1];
+      double r3 = b3[2 * (i0 + 3 * h)], j3 = b3[2 * (i0 + 3 * h) + 1];
+      bfly(r0, j0, r1, j1, k << (logm - lh - 1));            // stage lh, span h
+      bfly(r2, j2, r3, j3, k << (logm - lh - 1));
+      bfly(r0, j0, r2, j2, k << (logm - lh - 2));            // stage lh + 1, span 2h
+      bfly(r1, j1, r3, j3, (k + h) << (logm - lh - 2));
+      b3[2 * i0] = r0;
+      b3[2 * i0 + 1] = j0;
+      b3[2 * (i0 + h)] = r1;
+      b3[2 * (i0 + h) + 1] = j1;
+      b3[2 * (i0 + 2 * h)] = r2;
+      b3[2 * (i0 + 2 * h) + 1] = j2;
+      b3[2 * (i0 + 3 * h)] = r3;
+      b3[2 * (i0 + 3 * h) + 1] = j3;
+    }
+    __syncthreads();
+  }
+  if (lh < logm) {                            // a last radix-2 stage
+    const int h = 1 << lh;
+    const int half_total = ntile * (m >> 1);
     for (int b = threadIdx.x; b < half_total; b += blockDim.x) {
       const int t = b >> (logm - 1);
       const int q = b & ((m >> 1) - 1);
       const int k = q & (h - 1);
       const int i0 = t * m + ((q >> lh) << (lh + 1)) + k;
       const int i1 = i0 + h;
-      const double wr = tws[2 * (k << shift)], wi = sgn * tws[2 * (k << shift) + 1];
-      const double ar = b3[2 * i0], ai = b3[2 * i0 + 1];
-      const double br = b3[2 * i1], bi = b3[2 * i1 + 1];
-      const double cr = br * wr - bi * wi, ci = br * wi + bi * wr;
-      b3[2 * i0] = ar + cr;
-      b3[2 * i0 + 1] = ai + ci;
-      b3[2 * i1] = ar - cr;
-      b3[2 * i1 + 1] = ai - ci;
+      double r0 = b3[2 * i0], j0 = b3[2 * i0 + 1], r1 = b3[2 * i1], j1 = b3[2 * i1 + 1];
+      bfly(r0, j0, r1, j1, k << (logm - lh - 1));
+      b3[2 * i0] = r0;
+      b3[2 * i0 + 1] = j0;
+      b3[2 * i1] = r1;
+      b3[2 * i1 + 1] = j1;
     }
     __syncthreads();
   }
