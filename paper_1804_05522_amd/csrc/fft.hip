@@ -246,12 +246,13 @@ __global__ void __launch_bounds__(kFftWG) k_fft_small(DevPtrs P, const FftUnit* 
   }
   __syncthreads();
   lds_fft(buf, 1, logM, tw, logM, true);
-  // far-field values for k_exact_rows, which adds the near band
+  // far-field values for k_exact_rows, which adds the near band (second half
+  // of the column's scratch, where the four-step path leaves them too)
   const double inv = 1.0 / double(M);
-  double2* ws = P.fws + it.ws0 + int64_t(u.col) * 2 * M;
+  double2* far = P.fws + it.ws0 + int64_t(u.col) * 2 * M + M;
   for (int64_t i = threadIdx.x; i < it.n; i += blockDim.x) {
     const double2 w = buf[i];
-    ws[i] = make_double2(w.x * inv, w.y * inv);
+    far[i] = make_double2(w.x * inv, w.y * inv);
   }
   (void)y; (void)ldy; (void)b; (void)ldb;
 }
@@ -394,7 +395,9 @@ __global__ void __launch_bounds__(kFftWG) k_fft4_pass1(DevPtrs P, const FftUnit*
 // Pass 2: transforms over n1 (length M1) for `tile` adjacent k2; output index
 // k = k2 + M2 k1.  setup: mu; forward matvec: W = mu . X (second half of the
 // scratch); inverse: the far-field products (scaled by 1/M) in natural order
-// into the first half of the scratch, for k_exact_rows.
+// into the second half of the scratch, for k_exact_rows.  Every output goes to
+// the half the pass does not read: an output index k lies in rows of Y that
+// other work-groups of the same launch read.
 __global__ void __launch_bounds__(kFftWG) k_fft4_pass2(DevPtrs P, const FftUnit* units, int mode, bool inverse,
                                                       const double* x, int64_t ldx, double* y, int64_t ldy,
                                                       const double* b, int64_t ldb) {
@@ -434,7 +437,7 @@ __global__ void __launch_bounds__(kFftWG) k_fft4_pass2(DevPtrs P, const FftUnit*
     } else if (!inverse) {
       Wout[k] = cmul(v, mu[k]);
     } else if (k < it.n) {
-      ws[k] = make_double2(v.x * inv, v.y * inv);
+      Wout[k] = make_double2(v.x * inv, v.y * inv);
     }
   }
   (void)xc; (void)yc; (void)bc;
@@ -483,7 +486,7 @@ __global__ void __launch_bounds__(kExactRowsWG) k_exact_rows(DevPtrs P, const Ff
   }
   if (q != 0 || !valid) return;
   const int64_t M = int64_t(1) << it.fftlog;
-  const double2 w = P.fws[it.ws0 + int64_t(u.col) * 2 * M + i];
+  const double2 w = P.fws[it.ws0 + int64_t(u.col) * 2 * M + M + i];   // far field
   const double* bc = b ? b + it.row0 + int64_t(u.col) * ldb : nullptr;
   y[it.row0 + int64_t(u.col) * ldy + i] = exact_finish(P, it, xc, i, c, w.x, w.y, bc);
 }

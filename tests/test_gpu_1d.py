@@ -85,6 +85,38 @@ def test_exact_operator_matches_double_double(H, ctx, n, alpha):
     assert rel < 1e-13, rel
 
 
+def test_exact_operator_many_transforms_in_one_launch(H, ctx):
+    """48 four-step transforms (lengths 2^15 and 2^16) in one batch: the passes
+    launch far more work-groups than are resident at once, so an output that
+    lands in another work-group's input would show.  Repeated products agree
+    bit for bit, every problem's product equals that problem's product alone,
+    and the two shortest match the oracle's double-double residual."""
+    rng = np.random.default_rng(7)
+    ns = [int(v) for v in rng.integers(8200, 32768, 48)]
+    probs = [var_problem(n, 1.1 + 0.8 * k / 47, seed=k) for k, n in enumerate(ns)]
+    A = build(H, ctx, probs)
+    x = rng.standard_normal(sum(ns))
+    ys = []
+    for _ in range(3):
+        y = torch.zeros(sum(ns), dtype=torch.float64, device="cuda")
+        A.toeplitz_matvec(dev(x), y)
+        ys.append(y.cpu().numpy())
+    A.close()
+    assert all(np.array_equal(ys[0], y) for y in ys[1:])
+    off = np.concatenate([[0], np.cumsum(ns)])
+    for k in range(0, 48, 8):
+        B = build(H, ctx, [probs[k]])
+        yk = torch.zeros(ns[k], dtype=torch.float64, device="cuda")
+        B.toeplitz_matvec(dev(x[off[k]:off[k + 1]]), yk)
+        B.close()
+        assert np.array_equal(yk.cpu().numpy(), ys[0][off[k]:off[k + 1]]), k
+    for k in np.argsort(ns)[:2]:
+        p, xk = probs[k], x[off[k]:off[k + 1]]
+        ref = -O.residual_dd(p.alpha, p.nu, 1.0, p.d_plus, p.d_minus, xk, np.zeros(p.n))
+        scale = np.abs(xk).max() * (1 + 4 * p.nu * max(p.d_plus.max(), p.d_minus.max()))
+        assert np.max(np.abs(ys[0][off[k]:off[k + 1]] - ref)) <= 1e-13 * scale, k
+
+
 @pytest.mark.parametrize("n,alpha,refine", [(1, 1.5, 0), (60, 1.5, 0), (1000, 1.2, 0), (1024, 1.5, 0),
                                             (1500, 1.8, 4), (4097, 1.8, 4)])
 def test_factor_solve_fp64(H, ctx, n, alpha, refine):
