@@ -387,6 +387,23 @@ void build_nodes(int64_t n, int L, std::vector<Node>& out) {
   }
 }
 
+// Work-groups go to the eight XCDs round-robin by index, and each XCD has an
+// L2 of its own.  The strided four-step passes read and write short segments
+// whose cache lines neighbouring tiles share, so a unit list is reordered to
+// give every XCD a contiguous run of each column's tiles.
+constexpr int kXcds = 8;
+void xcd_order(std::vector<FftUnit>& u, size_t per_col) {
+  if (per_col == 0) return;
+  std::vector<FftUnit> out(u.size());
+  for (size_t c0 = 0; c0 < u.size(); c0 += per_col) {
+    size_t k = c0;
+    for (size_t x = 0; x < size_t(kXcds); ++x)
+      for (size_t b = c0; b < c0 + per_col; ++b)
+        if (b % kXcds == x) out[b] = u[k++];
+  }
+  u.swap(out);
+}
+
 void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int64_t ldy, const double* b,
                        int64_t ldb, int nc, hipStream_t s) {
   // columns in groups of kNCF
@@ -1119,6 +1136,8 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
         for (int64_t t = 0; t < (m->items[i].n + kRowsPerUnit - 1) / kRowsPerUnit; ++t)
           ur.push_back(FftUnit{i, c, int32_t(t), 0});
       }
+    xcd_order(u1, u1.size() / kNCF);
+    xcd_order(u2, u2.size() / kNCF);
     m->n_fft_small = int(m->small_items.size());
     m->n_fft_p1 = int(u1.size());
     m->n_fft_p2 = int(u2.size());
