@@ -277,6 +277,7 @@ __global__ void __launch_bounds__(256) k_expand(DevPtrs P, SolveFactors<TF, TL> 
 // in a fixed order.  Levels are dealt round-robin to the waves.
 constexpr int kP1Ld = 65;
 constexpr int kP1Cols = 16;                    // columns per transpose pass
+constexpr int kE1Cols = 16;                    // basis columns loaded per batch in k_expand1
 constexpr size_t kSolve1Lds = size_t(4) * kP1Cols * kP1Ld * sizeof(double);
 // Partial projections of y (this lane's row value) onto the basis of every
 // level where the leaf lies in the source child; rk = level_ranks(...).
@@ -293,16 +294,18 @@ __device__ void leaf_project1(const WorkUnit& w, const TF* Bb, int rk, int src_s
     if ((cnt++ & 3) != wave) continue;
     const int r = __builtin_amdgcn_readlane(rk, d);
     const __amdgpu_buffer_rsrc_t R = buf_rsrc(Bb + w.lvl0 + int64_t(d) * w.n * kRS, w.n * kRS * int64_t(sizeof(TF)));
-    TF raw[kRS];
-#pragma unroll
-    for (int q = 0; q < kRS; ++q)
-      raw[q] = bload(R, (q < r && lane < m) ? int((w.start + lane + int64_t(q) * w.n) * sizeof(TF)) : kOob,
-                     (const TF*)nullptr);
 #pragma unroll
     for (int h2 = 0; h2 < kRS / kP1Cols; ++h2) {
       if (kP1Cols * h2 >= r) break;
+      TF raw[kP1Cols];
 #pragma unroll
-      for (int q = 0; q < kP1Cols; ++q) pw[q * kP1Ld + lane] = cvt(raw[kP1Cols * h2 + q]) * yv;
+      for (int q = 0; q < kP1Cols; ++q) {
+        const int qq = kP1Cols * h2 + q;
+        raw[q] = bload(R, (qq < r && lane < m) ? int((w.start + lane + int64_t(qq) * w.n) * sizeof(TF)) : kOob,
+                       (const TF*)nullptr);
+      }
+#pragma unroll
+      for (int q = 0; q < kP1Cols; ++q) pw[q * kP1Ld + lane] = cvt(raw[q]) * yv;
       wave_lds_sync();
       const int q = lane & (kP1Cols - 1), qq = lane / kP1Cols;     // column, quarter of the rows
       double a4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -349,7 +352,7 @@ __global__ void __launch_bounds__(256) k_expand1(DevPtrs P, SolveFactors<TF, TL>
   const int rkU = next_part != nullptr ? level_ranks(P.rankU, w, lane) : 0;
   double acc = 0.0;
   if (wave == 0) {
-    constexpr int kLB = sizeof(TL) == 8 ? 32 : 64;    // leaf columns in flight
+    constexpr int kLB = 16;                           // leaf columns in flight
     const __amdgpu_buffer_rsrc_t R = buf_rsrc(F.LUinv + w.gl * int64_t(b) * b, int64_t(b) * b * int64_t(sizeof(TL)));
     const double xv = row < m ? xin[w.row0 + w.start + row] : 0.0;
     const int pv = row < m ? P.perm[w.gl * b + row] : 0;
@@ -388,13 +391,19 @@ __global__ void __launch_bounds__(256) k_expand1(DevPtrs P, SolveFactors<TF, TL>
       const double zs = lane < r ? zl : 0.0;
       const __amdgpu_buffer_rsrc_t R =
           buf_rsrc(Bb + w.lvl0 + int64_t(d) * w.n * kRS, w.n * kRS * int64_t(sizeof(TF)));
-      TF raw[kRS];
 #pragma unroll
-      for (int q = 0; q < kRS; ++q)
-        raw[q] = bload(R, (q < r && row < m) ? int((w.start + row + int64_t(q) * w.n) * sizeof(TF)) : kOob,
-                       (const TF*)nullptr);
+      for (int h2 = 0; h2 < kRS / kE1Cols; ++h2) {      // columns in batches (fewer registers in flight)
+        if (kE1Cols * h2 >= r) break;
+        TF raw[kE1Cols];
 #pragma unroll
-      for (int q = 0; q < kRS; ++q) a4[q & 3] += cvt(raw[q]) * readlane_d(zs, q);
+        for (int q = 0; q < kE1Cols; ++q) {
+          const int qq = kE1Cols * h2 + q;
+          raw[q] = bload(R, (qq < r && row < m) ? int((w.start + row + int64_t(qq) * w.n) * sizeof(TF)) : kOob,
+                         (const TF*)nullptr);
+        }
+#pragma unroll
+        for (int q = 0; q < kE1Cols; ++q) a4[q & 3] += cvt(raw[q]) * readlane_d(zs, kE1Cols * h2 + q);
+      }
     }
     acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   }
