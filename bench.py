@@ -182,7 +182,8 @@ def main():
 
     problem_steps = len(probs) * K
     value = problem_steps / main_res["job_s"]
-    roof = roofline(main_res, sum(p.n for p in probs), args.prec)
+    counters_apply = args.workload == "var_1d" and args.n == 65536 and K == 256
+    roof = roofline(main_res, sum(p.n for p in probs), args.prec, counters_apply)
 
     cpu = None
     if not args.no_cpu:
@@ -379,7 +380,7 @@ def bench_2d(args, ctx, stream):
     print(json.dumps(out), flush=True)
 
 
-def roofline(res, total_n, prec):
+def roofline(res, total_n, prec, counters_apply=False):
     """Roofline of the kernel with the largest summed duration in the
     instrumented job.  Algorithmic work per launch:
       factorisation kernels (FP64; the cores and leaves on the vector ALU, the
@@ -390,7 +391,9 @@ def roofline(res, total_n, prec):
       single right-hand-side solve kernels (HBM): every factor value is read
         once per solve; the projection reads a quarter of the off-diagonal
         factors, the two expansions the rest and the leaf inverses, plus the
-        vector passes (8 bytes a row in and out)."""
+        vector passes (8 bytes a row in and out).
+    The measured traffic is reported only for the job its counters were taken
+    on (var_1d, N = 65536, FP32 factors): other jobs launch other sizes."""
     ks, mi = res["kstats"], res["info"]
     name, (launches, total_ms) = max(ks.items(), key=lambda kv: kv[1][1])
     avg_s = total_ms / launches / 1e3
@@ -401,7 +404,7 @@ def roofline(res, total_n, prec):
     flop_kernels = {"k_core": mi.core_flops, "k_gram_partial": mi.gram_flops, "k_leaf_task": mi.leaf_flops,
                     "k_node_recompress": mi.node_rec_flops, "k_node_pending": mi.node_pend_flops}
     out = {"kernel": name, "launches": launches, "launch_us": 1e6 * avg_s}
-    traffic = measured_traffic(name, prec)
+    traffic = measured_traffic(name, prec) if counters_apply else None
     if name in flop_kernels:
         factorisations = 1
         per_launch = flop_kernels[name] / max(launches / factorisations, 1)
