@@ -15,6 +15,8 @@ What it computes (all FP64):
 * ``fd_matrix``: M = s I + nu (D+ T + D- T^T), nu = dt/h^alpha
   (eq. (system_FD); s = 1 in 1D, s = 1/2 for the 2D Sylvester coefficients of
   eq. (sylv-timestepping)).
+* ``fd_rows``: selected rows of the same matrix, formed the same way without
+  the whole matrix (for sampled checks at large N).
 * ``fd_matrix_from_scheme``: the same matrix assembled term by term from the
   two shifted Grunwald-Letnikov sums of Sec. 2.2.1 (boundary values dropped),
   an independent construction used to pin ``fd_matrix``.
@@ -71,6 +73,23 @@ def fd_matrix(alpha, n, nu, d_plus, d_minus, shift=1.0) -> np.ndarray:
     M = nu * (np.asarray(d_plus)[:, None] * T + np.asarray(d_minus)[:, None] * T.T)
     M[np.diag_indices(n)] += shift
     return M
+
+
+def fd_rows(alpha, n, nu, d_plus, d_minus, rows, shift=1.0, g=None) -> np.ndarray:
+    """Rows `rows` of M = shift*I + nu*(D+ T + D- T^T), computed as fd_matrix
+    does but without forming M (for large N): row i of T holds -g_{i-j+1}
+    for j <= i+1 and row i of T^T holds -g_{j-i+1} for j >= i-1 (0-based)."""
+    g = gl_weights(alpha, n) if g is None else g
+    j = np.arange(n)
+    out = np.zeros((len(rows), n))
+    for r, i in enumerate(rows):
+        k = i - j + 1
+        t_row = np.where(k >= 0, -g[np.clip(k, 0, n)], 0.0)
+        kt = j - i + 1
+        tt_row = np.where(kt >= 0, -g[np.clip(kt, 0, n)], 0.0)
+        out[r] = nu * (d_plus[i] * t_row + d_minus[i] * tt_row)
+        out[r, i] += shift
+    return out
 
 
 def fd_matrix_from_scheme(alpha, n, nu, d_plus, d_minus, shift=1.0) -> np.ndarray:

@@ -92,6 +92,19 @@ def test_toeplitz_matches_scheme_sums(alpha, n):
     np.testing.assert_allclose(M, Mb, rtol=1e-14, atol=1e-12)
 
 
+def test_fd_rows_equal_rows_of_the_dense_matrix():
+    """Selected rows of M formed without the matrix (for sampled checks at
+    large N) equal the rows of the dense fd_matrix bit for bit, including the
+    first and last rows and the rows next to them."""
+    rng = np.random.default_rng(4)
+    for alpha, n in [(1.3, 1), (1.3, 2), (1.7, 57), (1.05, 200)]:
+        dp, dm = 1 + rng.random(n), 1 + rng.random(n)
+        M = O.fd_matrix(alpha, n, 3.7, dp, dm, shift=0.5)
+        rows = sorted({0, 1, n - 2, n - 1, n // 2} & set(range(n)))
+        R = O.fd_rows(alpha, n, 3.7, dp, dm, rows, shift=0.5)
+        assert np.array_equal(R, M[rows])
+
+
 @pytest.mark.parametrize("alpha", [1.1, 1.5, 1.9])
 @pytest.mark.parametrize("shift", [1.0, 0.5])
 def test_strict_diagonal_dominance(alpha, shift):
