@@ -425,13 +425,13 @@ void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int
     if (m->n_fft_p1) {
       const int per_col1 = m->n_fft_p1 / kNCF, per_col2 = m->n_fft_p2 / kNCF;
       const size_t lds = m->fft4_lds;
-      HFDE_LAUNCH(k_fft4_pass1, dim3(per_col1 * cn), dim3(512), lds, s, m->P, m->fft_p1_units, 1, false,
+      HFDE_LAUNCH(k_fft4_pass1, dim3(per_col1 * cn), dim3(kFft4WG), lds, s, m->P, m->fft_p1_units, 1, false,
                          xc, ldx);
-      HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, false,
+      HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(kFft4WG), lds, s, m->P, m->fft_p2_units, 1, false,
                          xc, ldx, yc, ldy, bc, ldb);
-      HFDE_LAUNCH(k_fft4_pass1, dim3(per_col1 * cn), dim3(512), lds, s, m->P, m->fft_p1_units, 1, true,
+      HFDE_LAUNCH(k_fft4_pass1, dim3(per_col1 * cn), dim3(kFft4WG), lds, s, m->P, m->fft_p1_units, 1, true,
                          xc, ldx);
-      HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(512), lds, s, m->P, m->fft_p2_units, 1, true,
+      HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(kFft4WG), lds, s, m->P, m->fft_p2_units, 1, true,
                          xc, ldx, yc, ldy, bc, ldb);
     }
     if (m->n_fft_rows) {
@@ -1188,9 +1188,9 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   }
   if (m->n_fft_p1) {
     const size_t lds = m->fft4_lds;
-    HFDE_LAUNCH(k_fft4_pass1, dim3(m->n_fft_p1 / kNCF), dim3(512), lds, s, P, m->fft_p1_units, 0, false,
+    HFDE_LAUNCH(k_fft4_pass1, dim3(m->n_fft_p1 / kNCF), dim3(kFft4WG), lds, s, P, m->fft_p1_units, 0, false,
                        (const double*)nullptr, 0);
-    HFDE_LAUNCH(k_fft4_pass2, dim3(m->n_fft_p2 / kNCF), dim3(512), lds, s, P, m->fft_p2_units, 0, false,
+    HFDE_LAUNCH(k_fft4_pass2, dim3(m->n_fft_p2 / kNCF), dim3(kFft4WG), lds, s, P, m->fft_p2_units, 0, false,
                        (const double*)nullptr, 0, (double*)nullptr, 0, (const double*)nullptr, 0);
   }
   HIP_TRY(hipGetLastError());

@@ -25,6 +25,7 @@
 namespace hfde {
 
 constexpr int kFftWG = 512;
+constexpr int kFft4WG = 512;         // threads of a four-step pass work-group
 constexpr int kFftLds = 8192;          // complex values held in LDS
 
 
@@ -349,7 +350,7 @@ __device__ inline void four_step_dims(int logM, int& l1, int& l2, int& tile) {
 // Pass 1: transforms over n2 (length M2) for `tile` adjacent n1, then the
 // twiddle omega_M^{n1 k2}; output Y[k2 * M1 + n1].
 // forward/setup: input c (setup) or x (matvec, real); inverse: input W.
-__global__ void __launch_bounds__(kFftWG) k_fft4_pass1(DevPtrs P, const FftUnit* units, int mode, bool inverse,
+__global__ void __launch_bounds__(kFft4WG) k_fft4_pass1(DevPtrs P, const FftUnit* units, int mode, bool inverse,
                                                       const double* x, int64_t ldx) {
   extern __shared__ double2 buf[];
   const FftUnit u = units[blockIdx.x];
@@ -398,7 +399,7 @@ __global__ void __launch_bounds__(kFftWG) k_fft4_pass1(DevPtrs P, const FftUnit*
 // into the second half of the scratch, for k_exact_rows.  Every output goes to
 // the half the pass does not read: an output index k lies in rows of Y that
 // other work-groups of the same launch read.
-__global__ void __launch_bounds__(kFftWG) k_fft4_pass2(DevPtrs P, const FftUnit* units, int mode, bool inverse,
+__global__ void __launch_bounds__(kFft4WG) k_fft4_pass2(DevPtrs P, const FftUnit* units, int mode, bool inverse,
                                                       const double* x, int64_t ldx, double* y, int64_t ldy,
                                                       const double* b, int64_t ldb) {
   extern __shared__ double2 buf[];
