@@ -801,9 +801,26 @@ __device__ inline bool wg_leaf(const DevPtrs& P, const Item& it, int b, int64_t 
   g2l(P.Aleaf + gl * int64_t(b) * b, b, S, kLdsLeaf, b, b);
   wg_sync();
   if (rp > 0) {
-    for (int e = t; e < m * m; e += blockDim.x) {
-      const int i = e % m, j = e / m;
-      S[i + j * kLdsLeaf] -= lds_dot<kMaxLeaf, kMaxLeaf>(PL + i, QL + j, 0, rp);
+    // S -= PL QL^T on the FP64 matrix cores: 4 x 4 tiles of 16 x 16, k-steps
+    // of 4 over the rp pending columns (zero past rp: those LDS columns are
+    // stale); only the m x m block is written
+    const ldsd* PL3 = lds_view(PL);
+    const ldsd* QL3 = lds_view(QL);
+    const int li = lane & 15, lk = lane >> 4;
+    for (int tile = wave; tile < 16; tile += int(blockDim.x >> 6)) {
+      const int ti = tile & 3, tj = tile >> 2;
+      hfde_d4 acc{0.0, 0.0, 0.0, 0.0};
+      for (int q0 = 0; q0 < rp; q0 += 4) {
+        const int q = q0 + lk;
+        const double a = q < rp ? PL3[(ti * 16 + li) + q * kMaxLeaf] : 0.0;
+        const double bv = q < rp ? QL3[(tj * 16 + li) + q * kMaxLeaf] : 0.0;
+        acc = mfma64(a, bv, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * 16 + 4 * v + lk, col = tj * 16 + li;
+        if (row < m && col < m) S[row + col * kLdsLeaf] -= acc[v];
+      }
     }
     wg_sync();
   }
