@@ -103,7 +103,7 @@ struct NearChain {
   double ps, pc, ms, mc;
 };
 
-// X: x or its LDS window; XI(k) reads x[i + k] through it.  G: the weights.
+// xat(k) reads x[i + k] (through the LDS window of x); gat(k) reads g_k.
 template <typename XA, typename GA>
 __device__ inline NearChain exact_chain_t(XA xat, GA gat, int64_t i, int64_t n, int w, int q) {
   NearChain c{0.0, 0.0, 0.0, 0.0};
@@ -125,34 +125,6 @@ __device__ inline NearChain exact_chain_t(XA xat, GA gat, int64_t i, int64_t n, 
       const double gk = -gat(k + 1);
       if (i - k >= 0 && i - k < n) acc(c.ps, c.pc, gk, xat(-k));
       if (i + k >= 0 && i + k < n) acc(c.ms, c.mc, gk, xat(k));
-    }
-  }
-  return c;
-}
-
-__device__ inline NearChain exact_chain(const DevPtrs& P, const Item& it, const double* x, int64_t i, int q) {
-  const double* g = P.g + it.g0;
-  const int64_t n = it.n;
-  const int w = it.band;
-  NearChain c{0.0, 0.0, 0.0, 0.0};
-  auto acc = [](double& sum, double& err, double a, double b) {
-    const double p = a * b;
-    const double e = fma(a, b, -p);
-    const dd t = two_sum(sum, p);
-    sum = t.hi;
-    err += t.lo + e;
-  };
-  if (i - w >= 0 && i + w < n && i + 1 < n && i >= 1) {
-    for (int k = q - 1; k <= w; k += 4) {
-      const double gk = -g[k + 1];
-      acc(c.ps, c.pc, gk, x[i - k]);
-      acc(c.ms, c.mc, gk, x[i + k]);
-    }
-  } else {
-    for (int k = q - 1; k <= w; k += 4) {
-      const double gk = -g[k + 1];
-      if (i - k >= 0 && i - k < n) acc(c.ps, c.pc, gk, x[i - k]);
-      if (i + k >= 0 && i + k < n) acc(c.ms, c.mc, gk, x[i + k]);
     }
   }
   return c;
