@@ -147,3 +147,47 @@ def test_full_size_sylvester_step_residual(H, ctx, stream):
     nr, nc, nx = np.linalg.norm(R), np.linalg.norm(C), np.linalg.norm(X)
     eta = nr / ((np.linalg.norm(A) + np.linalg.norm(B)) * nx + nc)
     assert eta <= 1e-10, (eta, nr / nc, r, info.refine_iters, info.rel_correction)
+
+
+def test_full_size_batched_step_sampled_rows(H, ctx, stream):
+    """The batched workload (256 ragged problems, N from 2048 to 32768, small
+    and four-step transform lengths in one batch) in the benchmark's
+    configuration: for a spread of problems, sampled rows of the exact product
+    match the oracle's rows of M (within 1e-12 of the row's sum of |M_ij x_j|)
+    and, after one refined FP32 step, the oracle's residual rows are below
+    1e-10 of the row's sum of |M_ij u_j|."""
+    probs = W.batched_1d()
+    ns = np.array([p.n for p in probs])
+    off = np.concatenate([[0], np.cumsum(ns)])
+    total = int(off[-1])
+    pick = sorted({int(np.argmin(ns)), int(np.argmax(ns)), 0, 77, 128, 255})
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal(total)
+    with torch.cuda.stream(stream):
+        ops = [H.operator_dict(p.n, p.alpha, p.dt, p.h, dev(p.d_plus), dev(p.d_minus)) for p in probs]
+        At = H.HodlrMatrix(ctx, ops, H.default_opts(tol=1e-10, prec="fp32"))
+        At.autotune()
+        At.close()
+        A = H.HodlrMatrix(ctx, ops, H.default_opts(tol=1e-10, prec="fp32", refine_max=3, rtol=1e-10))
+        y = torch.zeros(total, dtype=torch.float64, device="cuda")
+        A.toeplitz_matvec(dev(x), y)
+        A.factor(allow=(0, 3))
+        u = dev(np.concatenate([p.u0 for p in probs]))
+        f = dev(np.concatenate([p.f for p in probs]))
+        A.time_steps(u, f, probs[0].dt, 1, allow=(0, 2))
+        stream.synchronize()
+        y = y.cpu().numpy()
+        u = u.cpu().numpy()
+        A.close()
+    for k in pick:
+        p, lo = probs[k], int(off[k])
+        rows = sample_rows(p.n, rng, count=16)
+        R = rows_of(p, rows)
+        xs, us = x[lo:lo + p.n], u[lo:lo + p.n]
+        b = p.u0 + p.dt * p.f
+        for r, i in enumerate(rows):
+            prod = R[r] * xs
+            assert abs(y[lo + i] - math.fsum(prod.tolist())) <= 1e-12 * math.fsum(np.abs(prod).tolist()), (k, i)
+            prod = R[r] * us
+            res = math.fsum([b[i]] + (-prod).tolist())
+            assert abs(res) <= 1e-10 * (math.fsum(np.abs(prod).tolist()) + abs(b[i])), (k, i, res)
