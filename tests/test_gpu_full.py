@@ -191,3 +191,48 @@ def test_full_size_batched_step_sampled_rows(H, ctx, stream):
             prod = R[r] * us
             res = math.fsum([b[i]] + (-prod).tolist())
             assert abs(res) <= 1e-10 * (math.fsum(np.abs(prod).tolist()) + abs(b[i])), (k, i, res)
+
+
+def test_full_size_time_dependent_steps_sampled_rows(H, ctx, stream):
+    """The time-dependent workload at full size, as the benchmark runs it:
+    the 256 ragged problems rebuilt in place for new coefficients, factored
+    and solved with three FP64 refinement sweeps, two steps.  After the second
+    step the oracle's residual rows of M(t_2) (built from the step's own
+    coefficient samples) are below 1e-10 of the row's sum of |M_ij u_j| on
+    sampled rows of a spread of problems."""
+    probs = W.batched_1d()
+    ns = np.array([p.n for p in probs])
+    off = np.concatenate([[0], np.cumsum(ns)])
+    dt = probs[0].dt
+    coefs = [[W.timedep_coefficients(p, m * p.dt) for p in probs] for m in range(3)]
+    with torch.cuda.stream(stream):
+        dco = [[(dev(a), dev(b)) for a, b in c] for c in coefs]
+        ops = [[H.operator_dict(p.n, p.alpha, p.dt, p.h, a, b) for p, (a, b) in zip(probs, c)] for c in dco]
+        A = H.HodlrMatrix(ctx, ops[0], H.default_opts(tol=1e-10, prec="fp32", refine_max=3, rtol=1e-10))
+        u = dev(np.concatenate([p.u0 for p in probs]))
+        f = dev(np.concatenate([p.f for p in probs]))
+        rhs = torch.empty_like(u)
+        prev = None
+        for m in (1, 2):
+            A.update_coefficients(ops[m])
+            A.factor(allow=(0, 3))
+            torch.add(u, f, alpha=dt, out=rhs)
+            A.solve(rhs, allow=(0, 2))
+            stream.synchronize()
+            prev = u.cpu().numpy()
+            u.copy_(rhs)
+        stream.synchronize()
+        u = u.cpu().numpy()
+        A.close()
+    rng = np.random.default_rng(24)
+    for k in sorted({int(np.argmin(ns)), int(np.argmax(ns)), 3, 200}):
+        p, lo = probs[k], int(off[k])
+        dp, dm = coefs[2][k]
+        rows = sample_rows(p.n, rng, count=16)
+        R = O.fd_rows(p.alpha, p.n, p.nu, dp, dm, rows)
+        b = prev[lo:lo + p.n] + dt * p.f
+        us = u[lo:lo + p.n]
+        for r, i in enumerate(rows):
+            prod = R[r] * us
+            res = math.fsum([b[i]] + (-prod).tolist())
+            assert abs(res) <= 1e-10 * (math.fsum(np.abs(prod).tolist()) + abs(b[i])), (k, i, res)
