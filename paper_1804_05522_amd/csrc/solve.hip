@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(256) k_expand1(DevPtrs P, SolveFactors<TF, TL>
   const int rkU = next_part != nullptr ? level_ranks(P.rankU, w, lane) : 0;
   double acc = 0.0;
   if (wave == 0) {
-    constexpr int kLB = 16;                           // leaf columns in flight
+    constexpr int kLB = sizeof(TL) == 8 ? 32 : 64;    // leaf columns in flight
     const __amdgpu_buffer_rsrc_t R = buf_rsrc(F.LUinv + w.gl * int64_t(b) * b, int64_t(b) * b * int64_t(sizeof(TL)));
     const double xv = row < m ? xin[w.row0 + w.start + row] : 0.0;
     const int pv = row < m ? P.perm[w.gl * b + row] : 0;
