@@ -99,3 +99,39 @@ def test_adam_first_step_is_signed_lr():
     opt.step(params, grads)
     np.testing.assert_allclose(params[0][0], [0.9, -1.9, 2.9], rtol=1e-6)
     np.testing.assert_allclose(params[0][1], [-0.1], rtol=1e-6)
+
+
+def test_adam_constant_gradient_every_step():
+    """A constant gradient g makes both bias-corrected moments exact at every
+    step (mhat = g, vhat = g^2), so each of five steps moves every parameter by
+    exactly lr g/(|g| + eps).  A bias correction evaluated at t = 1, or the two
+    decay rates exchanged, breaks this from the second step on."""
+    g = np.array([0.5, -4.0, 1e-3, 7.0])
+    lr, eps = 0.05, 1e-8
+    params = [[np.array([1.0, -2.0, 3.0, 0.0])]]
+    opt = C.Adam(params, lr=lr, eps=eps)
+    for t in range(1, 6):
+        before = params[0][0].copy()
+        opt.step(params, [[g.copy()]])
+        np.testing.assert_allclose(before - params[0][0], lr * g / (np.abs(g) + eps), rtol=1e-12, atol=0)
+
+
+def test_adam_alternating_gradient_closed_form():
+    """Gradients +g, -g, +g, ... : the moments have the geometric-series closed
+    forms m_t = (1-b1) g (-1)^(t+1) (1 - (-b1)^t)/(1 + b1) and v_t = g^2 (1 - b2^t),
+    so vhat = g^2 exactly and mhat = m_t/(1 - b1^t); the parameter after t steps
+    is the sum of the resulting updates.  Checked for t = 1..8 against the
+    recurrence of the optimiser."""
+    b1, b2, lr, eps = 0.9, 0.999, 0.01, 1e-8
+    g = np.array([2.0, -0.25])
+    p0 = np.array([0.3, 0.7])
+    params = [[p0.copy()]]
+    opt = C.Adam(params, lr=lr, b1=b1, b2=b2, eps=eps)
+    expect = p0.copy()
+    for t in range(1, 9):
+        sgn = 1.0 if t % 2 == 1 else -1.0
+        opt.step(params, [[sgn * g]])
+        m_t = (1 - b1) * g * (-1.0) ** (t + 1) * (1 - (-b1) ** t) / (1 + b1)
+        mhat = m_t / (1 - b1 ** t)
+        expect = expect - lr * mhat / (np.abs(g) + eps)
+        np.testing.assert_allclose(params[0][0], expect, rtol=1e-13, atol=1e-15)
