@@ -15,6 +15,8 @@ What it computes (all FP64):
 * ``fd_matrix``: M = s I + nu (D+ T + D- T^T), nu = dt/h^alpha
   (eq. (system_FD); s = 1 in 1D, s = 1/2 for the 2D Sylvester coefficients of
   eq. (sylv-timestepping)).
+* ``fd_matrix_lean``: the same matrix, entry for entry, built column block by
+  column block in Fortran order (for N where temporaries would not fit).
 * ``fd_rows``: selected rows of the same matrix, formed the same way without
   the whole matrix (for sampled checks at large N).
 * ``fd_matrix_from_scheme``: the same matrix assembled term by term from the
@@ -90,6 +92,29 @@ def fd_rows(alpha, n, nu, d_plus, d_minus, rows, shift=1.0, g=None) -> np.ndarra
         out[r] = nu * (d_plus[i] * t_row + d_minus[i] * tt_row)
         out[r, i] += shift
     return out
+
+
+def fd_matrix_lean(alpha, n, nu, d_plus, d_minus, shift=1.0, g=None, block=512) -> np.ndarray:
+    """The matrix of ``fd_matrix``, entry for entry the same expression
+    nu*(d+_i T_ij + d-_i T_ji) (+ shift on the diagonal), written column block
+    by column block into one Fortran-ordered array, so that at large N (65536:
+    34 GB) only the matrix itself is held; LAPACK then factors it in place."""
+    g = gl_weights(alpha, n) if g is None else g
+    dp = np.asarray(d_plus, float)[:, None]
+    dm = np.asarray(d_minus, float)[:, None]
+    M = np.empty((n, n), order="F")
+    i = np.arange(n)[:, None]
+    for c0 in range(0, n, block):
+        j = np.arange(c0, min(n, c0 + block))[None, :]
+        k = i - j + 1                       # T_ij = -g_{i-j+1} where i-j+1 >= 0
+        t = np.where(k >= 0, -g[np.clip(k, 0, n)], 0.0)
+        kt = j - i + 1                      # (T^T)_ij = T_ji = -g_{j-i+1}
+        tt = np.where(kt >= 0, -g[np.clip(kt, 0, n)], 0.0)
+        blk = nu * (dp * t + dm * tt)
+        d = np.arange(j.shape[1])
+        blk[c0 + d, d] += shift
+        M[:, c0:c0 + j.shape[1]] = blk
+    return M
 
 
 def fd_matrix_from_scheme(alpha, n, nu, d_plus, d_minus, shift=1.0) -> np.ndarray:
@@ -183,12 +208,15 @@ def matvec_dense(alpha, nu, shift, d_plus, d_minus, x):
 class DenseSolver:
     """Dense LU of M once (LAPACK getrf), solves with double-double refinement."""
 
-    def __init__(self, alpha, n, nu, d_plus, d_minus, shift=1.0, refine=3):
+    def __init__(self, alpha, n, nu, d_plus, d_minus, shift=1.0, refine=3, lean=False):
         self.alpha, self.n, self.nu, self.shift = alpha, n, nu, shift
         self.d_plus = np.asarray(d_plus, float)
         self.d_minus = np.asarray(d_minus, float)
         self.g = gl_weights(alpha, n + 1)
-        M = fd_matrix(alpha, n, nu, d_plus, d_minus, shift)
+        if lean:   # same matrix, built without temporaries (large N)
+            M = fd_matrix_lean(alpha, n, nu, d_plus, d_minus, shift, g=self.g)
+        else:
+            M = fd_matrix(alpha, n, nu, d_plus, d_minus, shift)
         self.lu = sla.lu_factor(M, overwrite_a=True, check_finite=False)
         self.refine = refine
 

@@ -105,6 +105,24 @@ def test_fd_rows_equal_rows_of_the_dense_matrix():
         assert np.array_equal(R, M[rows])
 
 
+def test_lean_matrix_equals_the_dense_matrix():
+    """The column-block builder used for the stored N = 65536 trajectories
+    gives fd_matrix bit for bit (Fortran order, block edges inside and at the
+    ends of the matrix, the limits alpha = 1 and 2), and its dense LU solve
+    gives the same solution as the plain one."""
+    rng = np.random.default_rng(6)
+    for alpha, n, blk in [(1.3, 1, 64), (2.0, 2, 1), (1.0, 9, 4), (1.7, 130, 64), (1.05, 301, 100)]:
+        dp, dm = 1 + rng.random(n), 1 + rng.random(n)
+        M = O.fd_matrix(alpha, n, 3.7, dp, dm, shift=0.5)
+        L = O.fd_matrix_lean(alpha, n, 3.7, dp, dm, shift=0.5, block=blk)
+        assert L.flags.f_contiguous and np.array_equal(M, L)
+    p = W.var_1d(1.8, n=500)
+    b = p.u0 + p.dt * p.f
+    x1 = O.DenseSolver(p.alpha, p.n, p.nu, p.d_plus, p.d_minus).solve(b)
+    x2 = O.DenseSolver(p.alpha, p.n, p.nu, p.d_plus, p.d_minus, lean=True).solve(b)
+    assert np.array_equal(x1, x2)
+
+
 @pytest.mark.parametrize("alpha", [1.1, 1.5, 1.9])
 @pytest.mark.parametrize("shift", [1.0, 0.5])
 def test_strict_diagonal_dominance(alpha, shift):
