@@ -10,7 +10,9 @@ truncation eps = 1e-10.  Inputs are synthetic (workloads.py).
 One bench "step" is one whole job: build the HODLR operators (weights, ACA
 compression, assembly), factor them (HODLR LU + inverse factors), and run the
 256 time steps, each solved to a relative forward-error estimate <= 1e-10
-(FP64 refinement sweeps with the exact near/far-field Toeplitz residual).
+(FP64 refinement sweeps with the exact near/far-field Toeplitz residual; the
+correction of every step is checked on the device, and the sweep count is the
+smallest with which no step misses the target or falls back to FP64).
 value = problem-steps per second of the whole job (2 problems x 256 steps /
 job time), at the headline precision (FP32 factors by default); the FP64
 factor path is measured the same way for comparison.
@@ -48,6 +50,7 @@ def parse():
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-2d", action="store_true", help="var_1d only: skip the 2D 4096^2 sub-object")
     ap.add_argument("--target", type=float, default=1e-10)
     ap.add_argument("--pmc-job", action="store_true",
                     help="for hardware-counter runs: one job of the workload with 8 time steps at the "
@@ -115,7 +118,7 @@ def main():
         dst.copy_(src)
         stream.synchronize()
         print(json.dumps({"pmc_job": args.prec, "sweeps": PMC_SWEEPS[args.prec], "copy_bytes": nbytes,
-                          "rel_correction_last": info.rel_correction}), flush=True)
+                          "rel_correction_worst_step": info.rel_correction}), flush=True)
         return
 
     # launch shapes of the factorisation, tuned once on this workload's tree
@@ -125,10 +128,13 @@ def main():
     At.close()
 
     def calibrate(prec):
-        """Fewest refinement sweeps per step whose last correction is <= target."""
-        for sweeps in range(0, 9):
+        """Fewest refinement sweeps per step with which every step of the job
+        converges on the device check (worst correction of all steps <= target)
+        without an FP64 fallback."""
+        for sweeps in range(1, 9):
             A, u, info = job(prec, sweeps)
-            ok = sweeps > 0 and info.rel_correction <= args.target and info.rel_correction == info.rel_correction
+            ok = (info.rel_correction <= args.target and info.rel_correction == info.rel_correction
+                  and not info.used_fallback)
             A.close()
             if ok:
                 return sweeps, info
@@ -169,6 +175,7 @@ def main():
         res = dict(prec=prec, sweeps=sweeps, job_s=(t1 - t0) / args.steps,
                    build_ms=float(np.mean([p[0] for p in parts])), factor_ms=float(np.mean([p[1] for p in parts])),
                    steps_ms=float(np.mean([p[2] for p in parts])), rel_correction=info.rel_correction,
+                   used_fallback=info.used_fallback,
                    rel_residual=info.rel_residual, rank_A=mi.max_rank_A, rank_factors=mi.max_rank_factors,
                    kstats=kstats, info=mit)
         A.close()
@@ -190,7 +197,7 @@ def main():
         cpu = cpu_baseline(args, probs, K)
 
     if args.workload == "var_1d":
-        metric = "HODLR solve steps/s (1D N=65536) at rel.err 1e-10"
+        metric = "HODLR solve steps/s (1D N=65536; 2D 4096^2 in fd_2d) at rel.err 1e-10, mixed vs FP64"
         workload = (f"var_1d N={args.n} alpha={{1.2,1.8}} batch=2 euler_steps={K} dt=1/256 leaf=64 eps=1e-10 "
                     f"target={args.target}")
     else:
@@ -216,7 +223,8 @@ def main():
         "phases_ms": {"build": main_res["build_ms"], "factor": main_res["factor_ms"], "time_steps": main_res["steps_ms"]},
         "per_step_us": 1e3 * main_res["steps_ms"] / K,
         "refine_sweeps_per_step": main_res["sweeps"],
-        "rel_correction_last": main_res["rel_correction"],
+        "rel_correction_worst_step": main_res["rel_correction"],
+        "fp64_fallback": bool(main_res["used_fallback"]),
         "rank_A": main_res["rank_A"], "rank_factors": main_res["rank_factors"],
         "roofline": roof,
         "autotuned": {"core_threads": tuned.core_threads, "leaf_threads": tuned.leaf_threads,
@@ -228,6 +236,9 @@ def main():
                             "factor_ms": cmp_res["factor_ms"], "sweeps": cmp_res["sweeps"]}
         out["mixed_vs_fp64"] = {"whole_job": out["fp64_path"]["value"] and value / out["fp64_path"]["value"],
                                 "per_step": cmp_res["steps_ms"] / main_res["steps_ms"]}
+    if args.workload == "var_1d" and not args.no_2d:
+        # the metric's second half: the 2D 4096^2 job, its own timing, roofline and CPU baseline
+        out["fd_2d"] = run_2d(args, ctx, stream, cpu=not args.no_cpu, compare=not args.no_compare)
     print(json.dumps(out), flush=True)
 
 
@@ -301,83 +312,169 @@ def bench_timedep(args, ctx, stream):
     print(json.dumps(out), flush=True)
 
 
-def bench_2d(args, ctx, stream):
+def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, compare=True):
     """2D workload: 4096^2, alpha = (1.3, 1.7), eq. (coeff_es) coefficients,
     rank-4 source, U^0 = 0, dt = 1/64.  One job = plan (shifts, shifted
-    factor sets) + K Sylvester steps at tolerance 1e-10 with the headline
-    factor storage; value = Sylvester steps per second of the whole job."""
+    factor sets) + K Sylvester steps at tolerance 1e-10 (normwise backward
+    error of every step) with the headline factor storage; value = Sylvester
+    steps per second of the whole job.  Returns the result as a dict."""
     import numpy as np
     import torch
 
     import paper_1804_05522_amd as H
     import workloads as W
-    K = args.euler_steps or 64
+    K = args.euler_steps if args.workload == "fd_2d" and args.euler_steps else 64
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    prec = args.prec if prec is None else prec
     n = 4096
     p = W.fd_2d(n=n)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5)
     opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5)
     F = (dev(p.f.Z.T.copy()), dev(p.f.W.T.copy()))
+    outs = [(torch.zeros((64, n), dtype=torch.float64, device="cuda"),
+             torch.zeros((64, n), dtype=torch.float64, device="cuda")) for _ in range(2)]
 
-    def job(timing=None):
+    def job(pr, timing=None, keep=False):
         t0 = time.perf_counter()
-        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec=args.prec), tol=1e-10)
+        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec=pr), tol=1e-10)
         stream.synchronize()
         t1 = time.perf_counter()
         cur = (torch.zeros((0, n), dtype=torch.float64, device="cuda"),) * 2
-        adi, worst = 0, 0.0
-        for _ in range(K):
-            out = (torch.zeros((32, n), dtype=torch.float64, device="cuda"),
-                   torch.zeros((32, n), dtype=torch.float64, device="cuda"))
-            r, info = P.step(cur, F, p.dt, out, allow=(0, 2))
-            cur = (out[0][:r].contiguous(), out[1][:r].contiguous())
+        adi, worst, r = 0, 0.0, 0
+        for k in range(K):
+            out = outs[k % 2]
+            r, info = P.step(cur, F, p.dt, out)
+            cur = (out[0][:r], out[1][:r])
             adi += info.refine_iters
-            worst = max(worst, info.rel_correction)
+            worst = max(worst, info.backward_error)
         stream.synchronize()
         t2 = time.perf_counter()
         J = len(P.shifts()[0])
-        P.close()
         if timing is not None:
             timing.append((t1 - t0, t2 - t1))
+        if keep:
+            return P, J, adi / K, worst, r
+        P.close()
         return J, adi / K, worst, r
 
-    for _ in range(args.warmup):
-        job()
-    parts = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        J, adi, worst, rank = job(parts)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    def measure(pr):
+        for _ in range(warmup):
+            job(pr)
+        parts = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            J, adi, worst, rank = job(pr, parts)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, parts, J, adi, worst, rank
+
+    job_s, parts, J, adi, worst, rank = measure(prec)
+    # live per-launch timing and work counters of one more (untimed) job
     ctx.reset_timing()
     ctx.set_timing(True)
-    job()
+    P, _, _, _, _ = job(prec, keep=True)
     ctx.set_timing(False)
     ks = ctx.timing()
     ctx.reset_timing()
-    name, (launches, total_ms) = max(ks.items(), key=lambda kv: kv[1][1])
-    job_s = (t1 - t0) / args.steps
+    cnt = P.counters()
+    P.close()
     out = {
-        "metric": "HODLR Sylvester steps/s (2D 4096^2) at tol 1e-10",
-        "value": K / job_s, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * job_s, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "factor_storage": {"fp64": "f64", "fp32": "f32", "bf16": "bf16+f32"}[args.prec],
-        "data": "synthetic",
-        "config": {"workload": f"fd_2d {n}x{n} alpha=(1.3,1.7) coeff_es rank-4 source dt=1/64 steps={K} tol=1e-10",
-                   "global_batch": 1, "parallelism": "single GPU"},
+        "metric": "HODLR Sylvester steps/s (2D 4096^2) at backward error 1e-10",
+        "value": K / job_s, "unit": "steps/s", "steps": steps, "warmup": warmup,
+        "ms_per_step": 1e3 * job_s, "higher_is_better": True,
+        "dtype": "f64", "factor_storage": {"fp64": "f64", "fp32": "f32", "bf16": "bf16+f32"}[prec],
+        "config": {"workload": f"fd_2d {n}x{n} alpha=(1.3,1.7) coeff_es rank-4 source dt=1/64 steps={K} tol=1e-10"},
         "phases_ms": {"plan": 1e3 * float(np.mean([q[0] for q in parts])),
                       "time_steps": 1e3 * float(np.mean([q[1] for q in parts]))},
         "per_step_ms": 1e3 * float(np.mean([q[1] for q in parts])) / K,
-        "shift_pairs": J, "adi_steps_per_step": adi, "rel_correction_worst": worst, "solution_rank": rank,
-        "roofline": {"kernel": name, "launches": launches, "launch_us": 1e3 * total_ms / launches,
-                     "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
-                     "algorithmic": "no per-kernel work model for this workload",
-                     "top_kernels_ms": {k: round(v[1], 3) for k, v in
-                                        sorted(ks.items(), key=lambda kv: -kv[1][1])[:8]}},
-        "cpu_baseline": None,
+        "shift_pairs": J, "adi_steps_per_step": adi, "backward_error_worst": worst, "solution_rank": rank,
+        "roofline": roofline_2d(ks, cnt, n),
+        "cpu_baseline": cpu_baseline_2d(K) if cpu else None,
     }
+    if compare and prec != "fp64":
+        job_s64, _, _, _, _, _ = measure("fp64")
+        out["fp64_path"] = {"value": K / job_s64, "ms_per_step": 1e3 * job_s64}
+        out["mixed_vs_fp64"] = job_s64 / job_s
+    return out
+
+
+def bench_2d(args, ctx, stream):
+    """--workload fd_2d: the 2D job alone, as the JSON line."""
+    out = run_2d(args, ctx, stream, cpu=not args.no_cpu, compare=not args.no_compare)
+    out.update({"n_gpus": 1, "scaling": "weak", "vs_baseline": None, "data": "synthetic"})
+    out["config"].update({"global_batch": 1, "parallelism": "single GPU"})
     print(json.dumps(out), flush=True)
+
+
+def roofline_2d(ks, cnt, n):
+    """Roofline of the kernel with the largest summed duration in the
+    instrumented 2D job, from the plan's work counters: the recompression
+    cores (k_lr_core, one work-group each, FP64 vector ALU) by their flop
+    model; the dense residual sums (k_lrs_dense, FP64 matrix cores) by
+    2 nx ny K; the shifted solves' expansions (k_expand, HBM) by the factor
+    values of one operator pair read once per column block (half of them per
+    expansion) plus the 16-column vector blocks read and written."""
+    name, (launches, total_ms) = max(ks.items(), key=lambda kv: kv[1][1])
+    out = {"kernel": name, "launches": launches, "launch_us": 1e3 * total_ms / launches}
+    avg_s = total_ms / launches / 1e3
+    if name == "k_lr_core":
+        per = cnt["core_flops"] / launches
+        out.update(bound="alu", achieved=per / avg_s / 1e12, peak=MI355X_FP64 / 1e12, unit="TFLOP/s",
+                   frac=per / avg_s / MI355X_FP64,
+                   algorithmic=f"{per:.3e} flop per launch (work model of the recompression core, "
+                               f"{cnt['core_flops']:.3e} flop over {launches} launches)")
+    elif name == "k_lrs_dense":
+        per = cnt["dense_flops"] / launches
+        out.update(bound="mfma", achieved=per / avg_s / 1e12, peak=MI355X_FP64 / 1e12, unit="TFLOP/s",
+                   frac=per / avg_s / MI355X_FP64,
+                   algorithmic=f"{per:.3e} flop per launch (2 nx ny K over the residual's K columns)")
+    elif name == "(k_expand<TF, TL, NC>)":
+        per = cnt["solve_bytes"] / cnt["shifts"] / 2 + 2 * 16 * 2 * n * 8.0
+        out.update(bound="hbm", achieved=per / avg_s / 1e9, peak=MI355X_HBM / 1e9, unit="GB/s",
+                   frac=per / avg_s / MI355X_HBM,
+                   algorithmic=f"{per:.3e} bytes per launch (half of one shifted pair's factors, plus vectors)")
+    else:
+        out.update(bound="latency", achieved=None, peak=None, unit=None, frac=None,
+                   algorithmic="no algorithmic model for this kernel")
+    out["traffic"] = None
+    out["top_kernels_ms"] = {k: round(v[1], 3) for k, v in sorted(ks.items(), key=lambda kv: -kv[1][1])[:8]}
+    return out
+
+
+def cpu_baseline_2d(K):
+    """The oracle (dense Bartels-Stewart with cached real Schur forms) on a
+    bounded sample: n = 1024 of the same workload, Schur forms + 2 steps,
+    extrapolated to 4096^2 and K steps with its n^3 cost (Schur forms and the
+    per-step triangular Sylvester solve are both cubic)."""
+    import numpy as np
+    import workloads as W
+    from oracle import fde2d as O2
+    n0, k0 = 1024, 2
+    p = W.fd_2d(n=n0)
+    t0 = time.perf_counter()
+    st = O2.SylvesterStepper(p)
+    t1 = time.perf_counter()
+    U = np.zeros((n0, n0))
+    Fd = p.f.dense()
+    for _ in range(k0):
+        U = st.step(U, Fd)
+    t2 = time.perf_counter()
+    scale = (4096 / n0) ** 3
+    t_full = (t1 - t0) * scale + K * (t2 - t1) / k0 * scale
+    return {"value": K / t_full, "unit": "steps/s", "cores": cpu_threads(), "kind": "oracle",
+            "sample": f"n={n0}, Schur forms {t1 - t0:.2f} s + {k0} Bartels-Stewart steps "
+                      f"({1e3 * (t2 - t1) / k0:.1f} ms/step); extrapolated to 4096^2 and {K} steps by n^3",
+            "sample_steps_per_s": k0 / (t2 - t1)}
+
+
+def cpu_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
+    except Exception:
+        return os.cpu_count()
 
 
 def roofline(res, total_n, prec, counters_apply=False):
@@ -476,38 +573,34 @@ def measured_traffic(name, prec):
 
 def cpu_baseline(args, probs, K):
     """The oracle as it stands (dense LU + double-double refined steps) on a
-    bounded sample: N = 4096 of the same workload, both alphas, 8 steps; the
-    whole-workload rate is extrapolated with the oracle's own cost model
-    (LU ~ N^3, a refined step ~ N^2)."""
-    import numpy as np
+    bounded sample of the same workload: N = 16384, alpha = 1.8, the dense LU
+    and 2 refined steps, timed on all the host's cores; the rate of the whole
+    workload (both alphas, N = 65536, K steps) follows from the oracle's own
+    cost model (LU ~ N^3, a refined step ~ N^2).  The full-size oracle, run
+    once on 8 cores when the stored N = 65536 trajectories were written, took
+    696-728 s for the LU and 25-27 s a refined step, which this model
+    reproduces within a factor of about two."""
     import workloads as W
     from oracle import fde1d as O
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
-    n0, steps0 = 4096, 8
-    t_lu = t_step = 0.0
-    for p in probs:
-        q = W.var_1d(p.alpha, n=n0)
-        t0 = time.perf_counter()
-        S = O.DenseSolver(q.alpha, q.n, q.nu, q.d_plus, q.d_minus)
-        t1 = time.perf_counter()
-        u = q.u0.copy()
-        for _ in range(steps0):
-            u = S.solve(u + q.dt * q.f)
-        t2 = time.perf_counter()
-        t_lu += t1 - t0
-        t_step += (t2 - t1) / steps0
+    n0, steps0 = 16384, 2
+    q = W.var_1d(1.8, n=n0)
+    t0 = time.perf_counter()
+    S = O.DenseSolver(q.alpha, q.n, q.nu, q.d_plus, q.d_minus, lean=True)
+    t1 = time.perf_counter()
+    u = q.u0.copy()
+    for _ in range(steps0):
+        u = S.solve(u + q.dt * q.f)
+    t2 = time.perf_counter()
+    del S
+    t_lu, t_step = t1 - t0, (t2 - t1) / steps0
     scale = args.n / n0
-    t_full = t_lu * scale ** 3 + K * t_step * scale ** 2
-    return {"value": len(probs) * K / t_full, "unit": "problem-steps/s", "cores": cores,
+    t_full = len(probs) * (t_lu * scale ** 3 + K * t_step * scale ** 2)
+    return {"value": len(probs) * K / t_full, "unit": "problem-steps/s", "cores": cpu_threads(),
             "kind": "oracle",
-            "sample": f"N={n0}, alpha=1.2 and 1.8, dense LU + {steps0} double-double refined steps "
-                      f"(LU {t_lu:.2f} s, {1e3 * t_step:.1f} ms/step for both); extrapolated to N={args.n}, "
-                      f"{K} steps with LU ~ N^3 and a step ~ N^2",
-            "sample_problem_steps_per_s": len(probs) / t_step}
+            "sample": f"N={n0}, alpha=1.8: dense LU {t_lu:.1f} s + {steps0} double-double refined steps "
+                      f"({t_step:.2f} s/step); scaled to {len(probs)} problems of N={args.n} and {K} steps "
+                      f"with LU ~ N^3 and a step ~ N^2",
+            "sample_problem_steps_per_s": 1.0 / t_step}
 
 
 if __name__ == "__main__":

@@ -16,9 +16,12 @@
  * - Matrices are column-major, 0-based.  A "batch" is a set of independent
  *   problems whose vectors are concatenated: problem i owns rows
  *   offsets[i] .. offsets[i+1]-1 of every vector argument.
- * - Ownership: the caller owns every buffer it passes.  Handles own the
- *   device memory they allocate (tree plan, compressed operator, factors,
- *   scratch), released by the matching *_destroy.  *_destroy(NULL) is a no-op.
+ * - Ownership: the caller owns every buffer it passes.  A matrix built by
+ *   hodlr_build_ws lives entirely in the caller's workspace (sized by
+ *   hodlr_workspace_size); the library allocates no device memory for it.
+ *   A matrix built by hodlr_build, and the other handles, own the device
+ *   memory they allocate (tree plan, compressed operator, factors, scratch),
+ *   released by the matching *_destroy.  *_destroy(NULL) is a no-op.
  * - Streams: a context wraps one hipStream_t supplied by the caller (NULL =
  *   the legacy default stream); all work is enqueued on it.  One context
  *   must not be used from two host threads at once.
@@ -38,6 +41,8 @@ typedef enum {
   HODLR_EINVAL = -1,     /* bad argument; hodlr_last_arg() names it (1-based) */
   HODLR_ENOMEM = -2,     /* device allocation failed */
   HODLR_EHIP = -3,       /* a HIP runtime call failed */
+  HODLR_EWORKSPACE = -4, /* a matrix in a caller workspace needs more of it (a factorisation
+                            schedule at launch shapes hodlr_workspace_size did not size) */
   HODLR_ESTATE = -5,     /* call out of order (e.g. solve before factor) */
   HODLR_ESINGULAR = 1,   /* zero or non-finite pivot in a leaf LU */
   HODLR_ENOCONV = 2,     /* refinement missed rtol; the FP64 fallback result is returned */
@@ -88,6 +93,9 @@ typedef struct {
   int used_fallback;      /* 1 if any problem fell back to the FP64 factors */
   double rel_correction;  /* max over problems of ||d||_2/||x||_2, d = last refinement correction
                              (estimates the forward error; 0 without refinement) */
+  double backward_error;  /* 2D step: ||R||_F / ((a + b) ||X||_F + ||C||_F), R = C - A X - X B^T, with
+                             a <= ||A||_2, b <= ||B||_2 the largest diagonal entries of A and B, so an upper
+                             bound of the normwise backward error; 0 in 1D */
 } hodlr_info;
 
 typedef struct {
@@ -143,6 +151,30 @@ hodlr_status hodlr_default_opts(hodlr_opts* opts);
 hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch,
                          const hodlr_opts* opts, hodlr_mat* out);
 
+/* Device memory, in bytes, that hodlr_build_ws needs for these operators and
+ * options (ops as for hodlr_build; their d+/d- pointers are not read and may be
+ * NULL): the compressed operator of eq. (system_FD) in HODLR form, its LU and
+ * inverse factors (Sec. 3.5) with the reduced-precision copies opts->prec
+ * asks for, the solve and refinement scratch, and the factorisation schedule
+ * at every launch shape hodlr_autotune tries (or that the process has tuned
+ * for this tree).  Host-only: no device work.  HODLR_EINVAL (argument 1-4)
+ * for arguments hodlr_build would refuse. */
+hodlr_status hodlr_workspace_size(const fde_operator* ops, int batch, const hodlr_opts* opts,
+                                  size_t* bytes);
+
+/* hodlr_build into caller-owned device memory: every device buffer of the
+ * matrix is carved from `workspace` (device, ws_bytes >= hodlr_workspace_size
+ * of the same arguments, any alignment), so no later call on the matrix
+ * allocates device memory either.  The caller keeps the workspace alive until
+ * hodlr_destroy(m) and frees it afterwards; hodlr_destroy releases nothing of
+ * it.  HODLR_EINVAL with hodlr_last_arg() == 6 if ws_bytes is too small, 5 if
+ * workspace is NULL.  Launch shapes set later by hodlr_set_tuning that
+ * hodlr_workspace_size did not size make hodlr_factor return
+ * HODLR_EWORKSPACE. */
+hodlr_status hodlr_build_ws(hodlr_ctx ctx, const fde_operator* ops, int batch,
+                            const hodlr_opts* opts, void* workspace, size_t ws_bytes,
+                            hodlr_mat* out);
+
 /* Time-dependent coefficients d+(x, t), d-(x, t) (the paper assumes them
  * constant in time, Sec. 2.2.1, which lets one LU serve every step; with
  * coefficients that change, the matrix of eq. (system_FD) changes every
@@ -155,11 +187,12 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch,
  * factorisation schedule are kept.  m must be factored again before it is
  * solved with (HODLR_ESTATE otherwise). */
 hodlr_status hodlr_update_coefficients(hodlr_ctx ctx, hodlr_mat m, const fde_operator* ops);
-/* Releases m.  Waits for the device to be idle, then keeps m's device blocks
- * in a process-wide pool (per device, at most 160 GB) from which a later
- * matrix that needs blocks of exactly the same sizes takes them; building a
- * matrix of the same shape again therefore maps no new device memory.  When
- * an allocation fails the pool is released and the allocation retried. */
+/* Releases m.  Waits for the device to be idle, then frees the device memory
+ * hodlr_build allocated for m (a matrix of hodlr_build_ws holds none).  With
+ * the environment variable HODLR_POOL=1 the blocks go to a process-wide pool
+ * instead (per device, at most 160 GB), from which a later matrix that needs
+ * blocks of exactly the same sizes takes them; an allocation that fails then
+ * releases the pool and is retried. */
 void hodlr_destroy(hodlr_mat m);
 hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info);
 
@@ -220,9 +253,17 @@ hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_
  * `steps` times, for every problem of the batch at once (fscale = dt for the
  * scheme of eq. (system_FD) with a time-independent source).  u, f device
  * (concatenated, one column); f may be NULL (f = 0).  The per-step kernel
- * sequence (right-hand side, low-precision solve, refine_max refinement
- * sweeps in the mixed modes) is captured once into a HIP graph and replayed.
- * info->rel_residual reports the last step's ||b - M u||_2/||b||_2. */
+ * sequence (right-hand side, solve at the stored precision, refine_max FP64
+ * refinement sweeps with the exact residual) is captured once into a HIP graph
+ * and replayed.  With refine_max > 0 every step's last correction d is checked
+ * on the device: the steps run in groups of 32, each group from a copy of u and
+ * ending with one read-back of the worst ||d||_2/||u||_2 of its steps; a group
+ * in which any step of any problem missed opts.rtol (or went non-finite) is
+ * restored and redone step by step on the FP64 factors, each step refined until
+ * it converges or stalls (info->used_fallback = 1).  Returns HODLR_ENOCONV
+ * (with or without info) if a step still missed rtol.  info->rel_correction:
+ * the worst ||d||_2/||u||_2 over all steps and problems (0 without refinement);
+ * info->rel_residual: the last step's ||b - M u||_2/||b||_2. */
 hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const double* f,
                               double fscale, int steps, hodlr_info* info);
 
@@ -255,23 +296,58 @@ typedef struct {
  * operator and factored with hopts (prec selects the factor precision). */
 hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
                                const hodlr_opts* hopts, const fde2d_opts* opts, fde2d_plan* out);
+/* Device memory, in bytes, that fde2d_plan_create_ws needs for these
+ * arguments: the shifted factor sets (2J HODLR operators, J fixed from the
+ * spectral intervals as fde2d_plan_create fixes it, which reads the d+/d-
+ * samples), the unshifted A and B for the exact residual, and the sweeps'
+ * low-rank work arrays.  No device memory is allocated. */
+hodlr_status fde2d_plan_workspace_size(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
+                                       const hodlr_opts* hopts, const fde2d_opts* opts, size_t* bytes);
+/* fde2d_plan_create into caller-owned device memory (workspace: device,
+ * ws_bytes >= fde2d_plan_workspace_size of the same arguments, any alignment):
+ * the plan's HODLR batches and work arrays are carved from it and the library
+ * allocates no device memory for the plan.  Keep the workspace alive until
+ * fde2d_plan_destroy.  HODLR_EINVAL with hodlr_last_arg() == 7 if ws_bytes is
+ * too small, 6 if workspace is NULL. */
+hodlr_status fde2d_plan_create_ws(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
+                                  const hodlr_opts* hopts, const fde2d_opts* opts, void* workspace,
+                                  size_t ws_bytes, fde2d_plan* out);
+/* Work counters of a plan, for measurement (a roofline report): values[0] the
+ * algorithmic flops of the low-rank recompression cores run so far (a model of
+ * each core on R concatenated columns with output rank r: 2R^2 + 4R^3/3 +
+ * 4R^2(r+1) + 4R^2 r), values[1] the flops of the dense residual sums
+ * (2 nx ny K for K columns), values[2] the bytes one single-column solve of all
+ * shifted operators reads (hodlr_mat_info.bytes_factors of the shifted batch),
+ * values[3] J, values[4] the largest factor rank; up to count values.  Waits
+ * for the device.  reset != 0 clears the two flop counters. */
+hodlr_status fde2d_plan_counters(fde2d_plan p, double* values, int count, int reset);
 void fde2d_plan_destroy(fde2d_plan p);
 int fde2d_plan_shifts(fde2d_plan p, double* p_shifts, double* q_shifts, int cap);
 
 /* One implicit Euler step of eq. (sylv-timestepping): U_next solves
  *   A X + X B^T = C,  C = U_m + dt F,
- * with every matrix in low-rank form.  U_m, F: inputs (rank 0 allowed; at
- * most 32 columns each).  C is recompressed, then factored ADI sweeps with the
- * plan's shifted HODLR solves run until the fADI residual G_J H_J^T is below
- * opts.tol * ||C||_F; the solution factors are recompressed after every ADI
- * step (relative truncation opts.tol / 10).  The exact residual
- * C - A X - X B^T (exact Toeplitz products) then drives correction sweeps
- * until the correction is below opts.tol * ||X||_F (at most 4).
- * U_next: caller-allocated factors with `capacity` (>= the needed rank, <= 32)
- * columns; on return U_next->rank is the rank used.  info->rel_residual:
- * ||C - A X - X B^T||_F / ||C||_F before the last correction;
- * info->rel_correction: the last correction relative to ||X||_F;
- * info->refine_iters: ADI steps taken in total. */
+ * with every matrix in low-rank form.  U_m: input, at most 64 columns; F: at
+ * most 32 (rank 0 allowed).  C, recompressed, is the right-hand side of a
+ * first factored ADI sweep with the plan's shifted HODLR solves, run until the
+ * fADI residual G_J H_J^T is below opts.tol * ||C||_F; its result (recompressed
+ * at opts.tol / 10) is the main term X_main of the solution.  The residual
+ * R = C - A X - X B^T of the current solution is then formed entry by entry
+ * from the factors (C from the caller's U_m and F, A Z and B W by the exact
+ * Toeplitz products), which resolves ||R||_F to about u times the size of its
+ * terms, and while the normwise backward error info->backward_error exceeds
+ * opts.tol (at most 4 times) a correction sweep solves A D + D B^T = R (R
+ * compressed by a randomized range finder on its factors) and D joins the
+ * correction term X_corr (recompressed so that its truncation changes the
+ * backward error by at most opts.tol / 10).  The two terms are kept apart
+ * because a recompression of a sum resolves its smaller term only to about
+ * sqrt(u) times the larger one.
+ * U_next = [Z_main, Z_corr][W_main, W_corr]^T: caller-allocated factors with
+ * `capacity` (>= the rank used, <= 64) columns; on return U_next->rank is the
+ * rank used.  HODLR_ENOCONV if the backward error is still above opts.tol after
+ * the corrections, HODLR_ERANK if the correction term hit its rank cap.
+ * info->rel_residual: ||R||_F / ||C||_F of the returned solution;
+ * info->rel_correction: the last correction relative to ||X_main||_F;
+ * info->refine_iters: ADI steps taken in total; info->max_rank: U_next->rank. */
 hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* U_m,
                                   const lr_matrix* F, double dt, lr_matrix* U_next,
                                   hodlr_info* info);

@@ -71,6 +71,8 @@ struct LrJob {
   int32_t gx, gy;           // Gram slots (64 x 64) for X^T X and Y^T Y
   int32_t mslot;            // transfer matrices slot (2 x 64 x 32)
   int32_t* rank_out;        // device rank of the result
+  int32_t* capped;          // device bit mask: bit `mslot` set when the rank cap truncated above tau (may be null)
+  double* flops;            // device accumulator of the core's algorithmic flops (may be null)
   double tau;               // absolute truncation tolerance
   double tau_rel;           // relative truncation tolerance (times ||X Y^T||_F)
   int32_t rmax;
@@ -121,7 +123,19 @@ __global__ void __launch_bounds__(kCoreWG) k_lr_core(const LrJob jb, const doubl
   __syncthreads();
   const double tau = fmax(jb.tau, jb.tau_rel * fro);
   RecompressOut res = wg_recompress_core(GX, GY, R, tau, jb.rmax, MU, MU + kMaxCat * kRS, Lds);
-  if (threadIdx.x == 0) *jb.rank_out = res.rank;
+  if (threadIdx.x == 0) {
+    *jb.rank_out = res.rank;
+    if (res.capped && jb.capped) atomicOr(jb.capped, 1 << jb.mslot);
+    if (jb.flops) {
+      // work model of the core on R concatenated columns, output rank r: the
+      // norm from the Grams (2 R^2), two pivoted Cholesky factorisations
+      // (R^3 / 3 each), their product (2 R^3 / 3), QR with column pivoting
+      // stopped after r + 1 steps (4 R^2 (r + 1)), the two transfer matrices
+      // (2 R^2 r each)
+      const double Rd = R, rd = res.rank;
+      atomicAdd(jb.flops, 2.0 * Rd * Rd + 4.0 * Rd * Rd * Rd / 3.0 + 4.0 * Rd * Rd * (rd + 1.0) + 4.0 * Rd * Rd * rd);
+    }
+  }
 }
 
 // U = X * M_U, V = Y * M_V (row-parallel); units: (job, side, chunk of 256 rows)
@@ -190,6 +204,192 @@ __global__ void k_copy_cols(int64_t rows, const int32_t* rdev, int rfix, const d
     const int64_t c = e / rows, i = e % rows;
     dst[i + c * ldd] = s * src[i + c * lds_];
   }
+}
+
+// ---------------------------------------------------- sums of low-rank products
+// S = sum_g s_g P_g Q_g^T (nx x ny) formed entry by entry in FP64: the
+// residual C - A X - X B^T of a 2D step from the factors of C, of A Z_X and
+// Z_X, of Z_X and B W_X.  Formed densely, its entries carry rounding errors
+// of about u times the sizes of the terms, so its norm is accurate even when
+// the terms cancel to 1e-10 of their size; a norm from Gram matrices of the
+// concatenated factors would resolve it only to about sqrt(u).
+constexpr int kLrsMax = 8;
+struct LrsGroup {
+  const double* P;          // nx x c, ld ldp
+  int64_t ldp;
+  const double* Q;          // ny x c, ld ldq
+  int64_t ldq;
+  const int32_t* cdev;      // c from device memory (a rank), or cfix when null
+  int32_t cfix;
+  double s;
+};
+struct LrSum {
+  LrsGroup g[kLrsMax];
+  int ng;
+  int64_t nx, ny;
+};
+
+// 64 x 64 output tiles on the FP64 matrix cores: wave w of the four takes the
+// 32 x 32 quarter (w & 1, w >> 1) as 2 x 2 tiles of 16 x 16, k-steps of four
+// columns through every group.  Writes the tile's sum of squares to
+// part[tile]; the entries themselves are not stored.
+__global__ void __launch_bounds__(256) k_lrs_dense(const LrSum S, double* part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = int64_t(blockIdx.x) * 64 + (wave & 1) * 32;
+  const int64_t c0 = int64_t(blockIdx.y) * 64 + (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  hfde_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = hfde_d4{0.0, 0.0, 0.0, 0.0};
+  for (int gi = 0; gi < S.ng; ++gi) {
+    const LrsGroup G = S.g[gi];
+    const int c = G.cdev ? *G.cdev : G.cfix;
+    for (int k0 = 0; k0 < c; k0 += 4) {
+      const int k = k0 + lk;
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int64_t i = r0 + 16 * t + li, j = c0 + 16 * t + li;
+        av[t] = (k < c && i < S.nx) ? G.s * G.P[i + int64_t(k) * G.ldp] : 0.0;
+        bv[t] = (k < c && j < S.ny) ? G.Q[j + int64_t(k) * G.ldq] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
+    }
+  }
+  double sq = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = r0 + 16 * a + 4 * v + lk, j = c0 + 16 * b + li;
+        const double x = acc[a][b][v];
+        if (i < S.nx && j < S.ny) sq += x * x;
+      }
+  __shared__ double red[256];
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+}
+
+// Products of a sum S = sum_g s_g P_g Q_g^T with a thin matrix, for the
+// randomized compression of S without forming it (the correction right-hand
+// side of a 2D step).  side 0: Y = S Om = sum_g s_g P_g (Q_g^T Om); side 1:
+// Y = S^T Om = sum_g s_g Q_g (P_g^T Om); Om has k <= kLrsK columns.  The
+// inner products are formed in 32-row slices (k_lrs_cross, one slice a
+// work-group, partial sums per slice), summed in slice order
+// (k_lrs_cross_sum), then applied row by row (k_lrs_apply).  Every product
+// has errors of about u times the sizes of the terms, as the dense form.
+constexpr int kLrsK = 32;
+constexpr int kLrsCols = kLrsMax * 64;   // at most 64 columns a group
+constexpr int kLrsSlice = 32;
+
+__device__ inline const double* lrs_inner(const LrsGroup& g, int side, int64_t& ld) {
+  ld = side == 0 ? g.ldq : g.ldp;
+  return side == 0 ? g.Q : g.P;
+}
+
+// part[slice][c][q] = sum over the slice's rows r of F[r][c] Om[r][q], F the
+// concatenated inner factors (Q_g for side 0, P_g for side 1), c < total columns.
+__global__ void __launch_bounds__(256) k_lrs_cross(const LrSum S, int side, const double* Om, int64_t ldo, int k,
+                                                   double* part) {
+  __shared__ double om[kLrsSlice][kLrsK + 1];
+  __shared__ double fv[kLrsSlice][65];
+  const int64_t rows = side == 0 ? S.ny : S.nx;
+  const int64_t r0 = int64_t(blockIdx.x) * kLrsSlice;
+  const int nr = int(min<int64_t>(kLrsSlice, rows - r0));
+  for (int e = threadIdx.x; e < kLrsSlice * kLrsK; e += blockDim.x) {
+    const int r = e % kLrsSlice, q = e / kLrsSlice;
+    om[r][q] = (r < nr && q < k) ? Om[r0 + r + int64_t(q) * ldo] : 0.0;
+  }
+  int cols = 0;
+  for (int gi = 0; gi < S.ng; ++gi) cols += S.g[gi].cdev ? *S.g[gi].cdev : S.g[gi].cfix;
+  double* out = part + int64_t(blockIdx.x) * kLrsCols * kLrsK;
+  int c0 = 0;
+  for (int gi = 0; gi < S.ng; ++gi) {
+    const LrsGroup G = S.g[gi];
+    const int c = G.cdev ? *G.cdev : G.cfix;
+    int64_t ld;
+    const double* F = lrs_inner(G, side, ld);
+    for (int cb = 0; cb < c; cb += 64) {
+      const int cn = min(64, c - cb);
+      __syncthreads();
+      for (int e = threadIdx.x; e < kLrsSlice * 64; e += blockDim.x) {
+        const int r = e % kLrsSlice, cc = e / kLrsSlice;
+        fv[r][cc] = (r < nr && cc < cn) ? F[r0 + r + int64_t(cb + cc) * ld] : 0.0;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < cn * kLrsK; e += blockDim.x) {
+        const int cc = e / kLrsK, q = e % kLrsK;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int r = 0; r < kLrsSlice; ++r) acc = fma(fv[r][cc], om[r][q], acc);
+        out[int64_t(c0 + cb + cc) * kLrsK + q] = acc;
+      }
+    }
+    c0 += c;
+  }
+  (void)cols;
+}
+
+// T[c][q] = sum over slices of part[slice][c][q], in slice order.
+__global__ void __launch_bounds__(256) k_lrs_cross_sum(const double* part, int slices, double* T) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kLrsCols * kLrsK) return;
+  double acc = 0.0;
+  for (int sl = 0; sl < slices; ++sl) acc += part[int64_t(sl) * kLrsCols * kLrsK + e];
+  T[e] = acc;
+}
+
+// Y[i][q] = sum_g s_g sum_c O_g[i][c] T[c0_g + c][q], O the outer factors
+// (P_g for side 0, Q_g for side 1), one thread a row, q < k.
+__global__ void __launch_bounds__(256) k_lrs_apply(const LrSum S, int side, const double* T, int k, double* Y,
+                                                   int64_t ldy) {
+  const int64_t rows = side == 0 ? S.nx : S.ny;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double acc[kLrsK];
+#pragma unroll
+  for (int q = 0; q < kLrsK; ++q) acc[q] = 0.0;
+  int c0 = 0;
+  for (int gi = 0; gi < S.ng; ++gi) {
+    const LrsGroup G = S.g[gi];
+    const int c = G.cdev ? *G.cdev : G.cfix;
+    const double* O = side == 0 ? G.P : G.Q;
+    const int64_t ld = side == 0 ? G.ldp : G.ldq;
+    for (int cc = 0; cc < c; ++cc) {
+      const double o = i < rows ? G.s * O[i + int64_t(cc) * ld] : 0.0;
+      const double* t = T + int64_t(c0 + cc) * kLrsK;
+#pragma unroll
+      for (int q = 0; q < kLrsK; ++q) acc[q] = fma(o, t[q], acc[q]);
+    }
+    c0 += c;
+  }
+  if (i < rows)
+    for (int q = 0; q < k; ++q) Y[i + int64_t(q) * ldy] = acc[q];
+}
+
+// out[0] = sum of the tiles' partial sums, in tile order (one work-group).
+__global__ void __launch_bounds__(256) k_sum_partials(const double* part, int64_t count, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < count; e += 256) acc += part[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // ---------------------------------------------------- dense fields

@@ -164,6 +164,7 @@ struct hodlr_mat_s {
   FftUnit* fft_row_units = nullptr;
   int n_fft_rows = 0;
   size_t fft4_lds = 0;
+  int64_t fws_packed = 0;     // complex values of the packed single-column transform scratch (sum of 2M)
   // solve scratch
   double* partL = nullptr;
   double* partU = nullptr;
@@ -174,9 +175,21 @@ struct hodlr_mat_s {
   double* dbuf = nullptr;
   double* bbuf = nullptr;
   double* norms = nullptr;    // batch x kNCS x 2
+  // per-step convergence check of the time loop
+  double* ukeep = nullptr;    // total_n: u at the start of a run of steps (restored on fallback)
+  double2* step_part = nullptr;   // batch x step_slices partial sums (d^2, u^2)
+  double* step_worst = nullptr;   // batch: worst relative correction of the steps since the last clear
+  double* host_worst = nullptr;   // pinned host copy of step_worst
+  int step_slices = 0;
   bool factored = false;
   int max_rank_factors = 0;
   int max_rank_A = 0;
+  bool capped_A = false;      // the Hankel compression of some problem hit the rank cap above its tolerance
+  // caller-owned device memory (hodlr_build_ws): every buffer is carved from it
+  char* ws = nullptr;
+  size_t ws_bytes = 0, ws_used = 0;
+  size_t ws_sched = 0;        // start of the factorisation schedule's region (re-planned in place)
+  bool sizing = false;        // hodlr_workspace_size: buffers are counted, not allocated
   // low precision copies
   float* IL32 = nullptr;
   float* IU32 = nullptr;
@@ -227,6 +240,7 @@ struct fde2d_plan_s {
   std::vector<int> order;   // application order of the shift pairs (interleaved)
   int64_t nx = 0, ny = 0;
   double shift_x = 0.5, shift_y = 0.5;
+  double bound_x = 1.0, bound_y = 1.0;   // lower bounds of ||A||_2, ||B||_2: the largest diagonal entries
   fde2d_opts opts{};
   std::vector<int> pwu_off, pwu_cnt, pnu_off, pnu_cnt;
   WorkUnit* pair_wu = nullptr;
@@ -235,7 +249,22 @@ struct fde2d_plan_s {
   double* H = nullptr;
   double* G0 = nullptr;         // right-hand side factors of the current sweep
   double* H0 = nullptr;
-  double* Zx[2] = {nullptr, nullptr};   // solution factors (ping-pong)
+  double* Zx[2] = {nullptr, nullptr};   // solution factors, main term (ping-pong)
+  double* Zc[2] = {nullptr, nullptr};   // solution factors, sum of the corrections (ping-pong)
+  double* Wc[2] = {nullptr, nullptr};
+  double* counters = nullptr;   // device: algorithmic flops of the recompression cores (k_lr_core)
+  double lrs_flops = 0.0;       // host: algorithmic flops of the dense residual sums (k_lrs_dense)
+  double* lrs_cpart = nullptr;  // slice partials of the factored sketch products
+  double* lrs_t = nullptr;      // their sums
+  double* lrs_part = nullptr;   // per-tile sums of squares of a dense low-rank sum
+  double* dnorm = nullptr;      // their total
+  double* om = nullptr;         // dense compression: sketch matrix (ny x kSketch)
+  double* sk_y = nullptr;       //   sketch X Om (nx x kSketch)
+  double* sk_q1 = nullptr;      //   first orthonormal basis
+  double* sk_q2 = nullptr;      //   second orthonormal basis
+  double* sk_b = nullptr;       //   X^T Q2 (ny x kSketch)
+  double* eye = nullptr;        //   kSketch x kSketch identity
+  double* sk_junk = nullptr;    //   unused right factor of the orthonormalising passes
   double* Wx[2] = {nullptr, nullptr};
   double* Zd[2] = {nullptr, nullptr};   // correction factors (even shift pairs of a sweep, then the merge)
   double* Ze[2] = {nullptr, nullptr};   // correction factors of the odd shift pairs
@@ -254,6 +283,9 @@ struct fde2d_plan_s {
   int32_t* host_ranks = nullptr;          // pinned host memory: ranks (32 ints), then the norm read-back
   double* host_frob = nullptr;
   LrUnit* units = nullptr;      // per work slot: gram, reduce and form units
+  char* ws = nullptr;            // caller workspace (fde2d_plan_create_ws): plan arrays carved from it
+  size_t ws_bytes = 0, ws_used = 0;
+  bool sizing = false;          // fde2d_plan_workspace_size: arrays counted, not allocated
   int64_t unit_rows[16][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1},
                               {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
   double* gpart = nullptr;
@@ -337,10 +369,30 @@ void pool_release() {
   P.held[dev] = 0;
 }
 
+// The block pool is opt-in (HODLR_POOL=1): by default a destroyed matrix
+// frees its blocks.
+bool pool_enabled() {
+  static const bool on = getenv("HODLR_POOL") && getenv("HODLR_POOL")[0] == '1';
+  return on;
+}
+
 template <typename T>
 hodlr_status dalloc(hodlr_mat m, T** p, size_t count) {
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  void* q = pool_take(bytes);
+  if (m->sizing || m->ws) {
+    const size_t off = (m->ws_used + 255) & ~size_t(255);
+    if (m->sizing) {
+      m->ws_used = off + bytes;
+      *p = nullptr;
+      return HODLR_OK;
+    }
+    if (off + bytes > m->ws_bytes) return HODLR_EWORKSPACE;
+    m->ws_used = off + bytes;
+    m->bytes_device += bytes;
+    *p = reinterpret_cast<T*>(m->ws + off);
+    return HODLR_OK;
+  }
+  void* q = pool_enabled() ? pool_take(bytes) : nullptr;
   if (!q && hipMalloc(&q, bytes) != hipSuccess) {
     (void)hipGetLastError();
     pool_release();
@@ -404,11 +456,15 @@ void xcd_order(std::vector<FftUnit>& u, size_t per_col) {
   u.swap(out);
 }
 
-void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int64_t ldy, const double* b,
-                       int64_t ldb, int nc, hipStream_t s) {
-  // columns in groups of kNCF
-  for (int c0 = 0; c0 < nc; c0 += kNCF) {
-    const int cn = std::min(kNCF, nc - c0);
+// y = M x (+ b - 2 M x when b is given: the residual b - M x) through the
+// near band and the circulant far field.  P supplies the transform scratch:
+// the handle's own (columns in groups of kNCF) or, with P.fws_compact, a
+// packed buffer for one column at a time.
+void launch_fft_matvec_p(hodlr_mat m, const DevPtrs& P, const double* x, int64_t ldx, double* y, int64_t ldy,
+                         const double* b, int64_t ldb, int nc, hipStream_t s) {
+  const int group = P.fws_compact ? 1 : kNCF;
+  for (int c0 = 0; c0 < nc; c0 += group) {
+    const int cn = std::min(group, nc - c0);
     const double* xc = x + int64_t(c0) * ldx;
     double* yc = y + int64_t(c0) * ldy;
     const double* bc = b ? b + int64_t(c0) * ldb : nullptr;
@@ -419,27 +475,32 @@ void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int
       int maxlog = 0;
       for (int i : m->small_items) maxlog = std::max(maxlog, m->items[i].fftlog);
       lds = (size_t(1) << maxlog) * sizeof(double2);
-      HFDE_LAUNCH(k_fft_small, dim3(cnt), dim3(512), lds, s, m->P, m->fft_small_units, 1, xc, ldx, yc,
+      HFDE_LAUNCH(k_fft_small, dim3(cnt), dim3(512), lds, s, P, m->fft_small_units, 1, xc, ldx, yc,
                          ldy, bc, ldb);
     }
     if (m->n_fft_p1) {
       const int per_col1 = m->n_fft_p1 / kNCF, per_col2 = m->n_fft_p2 / kNCF;
       const size_t lds = m->fft4_lds;
-      HFDE_LAUNCH(k_fft4_pass1, dim3(per_col1 * cn), dim3(kFft4WG), lds, s, m->P, m->fft_p1_units, 1, false,
+      HFDE_LAUNCH(k_fft4_pass1, dim3(per_col1 * cn), dim3(kFft4WG), lds, s, P, m->fft_p1_units, 1, false,
                          xc, ldx);
-      HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(kFft4WG), lds, s, m->P, m->fft_p2_units, 1, false,
+      HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(kFft4WG), lds, s, P, m->fft_p2_units, 1, false,
                          xc, ldx, yc, ldy, bc, ldb);
-      HFDE_LAUNCH(k_fft4_pass1, dim3(per_col1 * cn), dim3(kFft4WG), lds, s, m->P, m->fft_p1_units, 1, true,
+      HFDE_LAUNCH(k_fft4_pass1, dim3(per_col1 * cn), dim3(kFft4WG), lds, s, P, m->fft_p1_units, 1, true,
                          xc, ldx);
-      HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(kFft4WG), lds, s, m->P, m->fft_p2_units, 1, true,
+      HFDE_LAUNCH(k_fft4_pass2, dim3(per_col2 * cn), dim3(kFft4WG), lds, s, P, m->fft_p2_units, 1, true,
                          xc, ldx, yc, ldy, bc, ldb);
     }
     if (m->n_fft_rows) {
       const int per_colr = m->n_fft_rows / kNCF;
-      HFDE_LAUNCH(k_exact_rows, dim3(per_colr * cn), dim3(kExactRowsWG), 0, s, m->P, m->fft_row_units, xc, ldx, yc,
+      HFDE_LAUNCH(k_exact_rows, dim3(per_colr * cn), dim3(kExactRowsWG), 0, s, P, m->fft_row_units, xc, ldx, yc,
                          ldy, bc, ldb);
     }
   }
+}
+
+void launch_fft_matvec(hodlr_mat m, const double* x, int64_t ldx, double* y, int64_t ldy, const double* b,
+                       int64_t ldb, int nc, hipStream_t s) {
+  launch_fft_matvec_p(m, m->P, x, ldx, y, ldy, b, ldb, nc, s);
 }
 
 template <typename TF, typename TL, int NC>
@@ -738,6 +799,12 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   }
   if (side_open) rec(KL_JOIN_WAIT, 1, 0, 0);
   const int Lmax = std::max(1, m->Lmax);
+  if (m->ws && !m->sizing) {
+    // a workspace holds one schedule: a new one replaces the last in place,
+    // once no factorisation that reads it can still run
+    if (m->ws_used > m->ws_sched) HIP_TRY(hipDeviceSynchronize());
+    m->ws_used = m->ws_sched;
+  }
   TRY(dalloc(m, &m->d_tasks, tasks.size()));
   TRY(dalloc(m, &m->d_gram, grams.size()));
   TRY(dalloc(m, &m->d_red, reds.size()));
@@ -751,6 +818,7 @@ static hodlr_status plan_mwg(hodlr_mat m) {
   TRY(dalloc(m, &m->d_M, max_step_tasks * 3 * 2 * kMaxCat * kRS));
   TRY(dalloc(m, &m->d_ppart, max_ppart * Lmax * kRS * kPNC));
   TRY(dalloc(m, &m->d_pz, max_pz * kRS * kPNC));
+  if (m->sizing) return HODLR_OK;
   auto up = [](void* dst, const void* src, size_t bytes) -> hodlr_status {
     if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
     return HODLR_OK;
@@ -870,6 +938,7 @@ const char* hodlr_status_string(hodlr_status s) {
     case HODLR_ENOMEM: return "device allocation failed";
     case HODLR_EHIP: return "HIP runtime error";
     case HODLR_ESTATE: return "call out of order";
+    case HODLR_EWORKSPACE: return "caller workspace too small";
     case HODLR_ESINGULAR: return "singular leaf pivot";
     case HODLR_ENOCONV: return "refinement did not converge (FP64 fallback used)";
     case HODLR_ERANK: return "rank cap reached above tolerance";
@@ -934,7 +1003,11 @@ void hodlr_destroy(hodlr_mat m) {
   if (m->ev_join) (void)hipEventDestroy(m->ev_join);
   // no kernel may still use a block when it goes back to the pool
   (void)hipDeviceSynchronize();
-  for (size_t i = 0; i < m->allocs.size(); ++i) pool_give(m->allocs[i], m->alloc_bytes[i]);
+  for (size_t i = 0; i < m->allocs.size(); ++i) {
+    if (pool_enabled()) pool_give(m->allocs[i], m->alloc_bytes[i]);
+    else (void)hipFree(m->allocs[i]);
+  }
+  if (m->host_worst) (void)hipHostFree(m->host_worst);
   delete m;
 }
 
@@ -975,15 +1048,47 @@ static hodlr_status set_lds_limits() {
   return HODLR_OK;
 }
 
-hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, const hodlr_opts* opts,
-                         hodlr_mat* out) {
-  if (!ctx) return HODLR_EINVAL;
-  TimerScope ts_(ctx);
-  TRY(set_lds_limits());
+// Reads the compression's status bits (after the stream has drained): a
+// Hankel compression stopped by the rank cap is remembered and reported by
+// the next hodlr_factor as HODLR_ERANK.
+static hodlr_status read_capped_A(hodlr_mat m) {
+  std::vector<int32_t> st(m->batch);
+  HIP_TRY(hipMemcpy(st.data(), m->P.status, m->batch * sizeof(int32_t), hipMemcpyDeviceToHost));
+  m->capped_A = false;
+  for (int32_t v : st) m->capped_A |= (v & 4) != 0;
+  return HODLR_OK;
+}
+
+// The reduced-precision copies of the solve's factors (FP32 leaf inverses and
+// low-rank factors; BF16 low-rank factors as well for HODLR_MIXED_BF16).
+static hodlr_status alloc_lowprec(hodlr_mat m) {
+  if (m->opts.prec == HODLR_FP64) return HODLR_OK;
+  int64_t nlvl = 0;
+  for (const Item& it : m->items) nlvl += int64_t(it.L + 1) * it.n * kRS;
+  const int64_t nleafv = m->total_leaves * m->b * m->b;
+  TRY(dalloc(m, &m->LUinv32, nleafv));
+  TRY(dalloc(m, &m->IL32, nlvl));
+  TRY(dalloc(m, &m->IU32, nlvl));
+  if (m->opts.prec == HODLR_MIXED_BF16) {
+    TRY(dalloc(m, &m->IL16, nlvl));
+    TRY(dalloc(m, &m->IU16, nlvl));
+  }
+  return HODLR_OK;
+}
+
+// Host plan, device buffers and device construction of a batch of
+// operators.  Three modes: library-allocated (ws == nullptr), carved from a
+// caller's workspace (ws != nullptr), or sizing only (need != nullptr: every
+// buffer is counted, nothing is allocated or launched, and *need receives the
+// workspace the matrix would use, including the factorisation schedule at
+// every launch shape the autotuner tries).
+static hodlr_status build_impl(hodlr_ctx ctx, const fde_operator* ops, int batch, const hodlr_opts* opts,
+                               void* ws, size_t ws_bytes, hodlr_mat* out, size_t* need) {
+  const bool sizing = need != nullptr;
   if (!ops) return set_arg(ctx, 2);
   if (batch < 1) return set_arg(ctx, 3);
   if (!opts) return set_arg(ctx, 4);
-  if (!out) return set_arg(ctx, 5);
+  if (!sizing && !out) return set_arg(ctx, 7);
   if (opts->leaf < 16 || opts->leaf > kMaxLeaf) return set_arg(ctx, 4);
   if (!(opts->tol > 0.0) || opts->max_rank < 1 || opts->max_rank > kRS) return set_arg(ctx, 4);
   if (opts->prec < HODLR_FP64 || opts->prec > HODLR_MIXED_BF16) return set_arg(ctx, 4);
@@ -993,18 +1098,22 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
     // values) with 32-bit byte offsets that must stay below the out-of-range
     // sentinel kOob, so n x 32 x 8 < 2^31 - 16
     if (o.n < 1 || o.n >= (int64_t(1) << 23) || !(o.alpha >= 1.0 && o.alpha <= 2.0) || !(o.dt > 0.0) ||
-        !(o.dx > 0.0) || !(o.shift > 0.0) || !o.d_plus || !o.d_minus)
+        !(o.dx > 0.0) || !(o.shift > 0.0) || (!sizing && (!o.d_plus || !o.d_minus)))
       return set_arg(ctx, 2);
   }
+  if (!sizing) TRY(set_lds_limits());
   hodlr_mat m = new (std::nothrow) hodlr_mat_s;
   if (!m) return HODLR_ENOMEM;
   m->ctx = ctx;
   m->opts = *opts;
   m->batch = batch;
   m->b = opts->leaf;
-  hipStream_t s = ctx->stream;
+  m->sizing = sizing;
+  m->ws = static_cast<char*>(ws);
+  m->ws_bytes = ws_bytes;
+  hipStream_t s = ctx ? ctx->stream : nullptr;
   // ---- plan
-  int64_t row0 = 0, leaf0 = 0, node0 = 0, lvl0 = 0, g0 = 0, w0 = 0, z0 = 0, tw0 = 0, ws0 = 0;
+  int64_t row0 = 0, leaf0 = 0, node0 = 0, lvl0 = 0, g0 = 0, w0 = 0, z0 = 0, tw0 = 0, ws0 = 0, wsc0 = 0;
   for (int i = 0; i < batch; ++i) {
     const fde_operator& o = ops[i];
     Item it{};
@@ -1028,6 +1137,7 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
     it.tw0 = tw0;
     it.mu0 = tw0;   // mu shares the offsets of the twiddle table (separate array)
     it.ws0 = ws0;
+    it.wsc0 = wsc0;
     m->items.push_back(it);
     build_nodes(o.n, it.L, m->nodes);
     row0 += o.n;
@@ -1039,9 +1149,11 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
     z0 += (int64_t(1) << it.L) * kRS * 64;
     tw0 += int64_t(1) << flog;
     ws0 += 2 * (int64_t(1) << flog) * kNCF;
+    wsc0 += 2 * (int64_t(1) << flog);
     m->Lmax = std::max(m->Lmax, it.L);
   }
   m->total_n = row0;
+  m->fws_packed = wsc0;
   m->total_leaves = leaf0;
   m->total_nodes = node0;
   std::vector<int32_t> rowleaf(row0);
@@ -1059,13 +1171,43 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   m->nwu = int(m->wu_h.size());
   m->nnu = int(m->nu_h.size());
   const int b = m->b;
-  // ---- allocate
+  // FFT work lists
+  std::vector<FftUnit> us, u1, u2, ur;
+  for (int i = 0; i < batch; ++i) {
+    if (m->items[i].fftlog <= kFftSmallMax) m->small_items.push_back(i);
+    else m->big_items.push_back(i);
+  }
+  for (int c = 0; c < kNCF; ++c)
+    for (int i : m->small_items) us.push_back(FftUnit{i, c, 0, 0});
+  for (int c = 0; c < kNCF; ++c)
+    for (int i : m->big_items) {
+      const int lg = m->items[i].fftlog;
+      const int l2 = lg / 2, l1 = lg - l2;
+      int T = std::min(kFftTileMax, kFftLds >> l1);
+      m->fft4_lds = std::max(m->fft4_lds, size_t(T) * (size_t(1) << l1) * sizeof(double2));
+      for (int t = 0; t < (1 << l1) / T; ++t) u1.push_back(FftUnit{i, c, t, 0});
+      for (int t = 0; t < (1 << l2) / T; ++t) u2.push_back(FftUnit{i, c, t, 0});
+    }
+  // near-band rows of every item (after either transform path)
+  for (int c = 0; c < kNCF; ++c)
+    for (int i = 0; i < m->batch; ++i) {
+      constexpr int kRowsPerUnit = kExactRowsWG / 4;   // rows of one k_exact_rows work-group
+      for (int64_t t = 0; t < (m->items[i].n + kRowsPerUnit - 1) / kRowsPerUnit; ++t)
+        ur.push_back(FftUnit{i, c, int32_t(t), 0});
+    }
+  xcd_order(u1, u1.size() / kNCF);
+  xcd_order(u2, u2.size() / kNCF);
+  m->n_fft_small = int(m->small_items.size());
+  m->n_fft_p1 = int(u1.size());
+  m->n_fft_p2 = int(u2.size());
+  m->n_fft_rows = int(ur.size());
+  // ---- device buffers
   DevPtrs& P = m->P;
   hodlr_status st;
 #define ALLOC(ptr, cnt)                                   \
   do {                                                    \
     st = dalloc(m, &(ptr), (cnt));                        \
-    if (st != HODLR_OK) { hodlr_destroy(m); return st; }  \
+    if (st != HODLR_OK) { hodlr_destroy(m); return st == HODLR_EWORKSPACE ? set_arg(ctx, 6) : st; } \
   } while (0)
   ALLOC(P.items, batch);
   ALLOC(P.nodes, m->nodes.size());
@@ -1111,52 +1253,78 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   ALLOC(m->dbuf, row0 * kNCS);
   ALLOC(m->bbuf, row0 * kNCS);
   ALLOC(m->norms, batch * kNCS * 4);
-  // FFT work lists
   {
-    std::vector<FftUnit> us, u1, u2, ur;
-    for (int i = 0; i < batch; ++i) {
-      if (m->items[i].fftlog <= kFftSmallMax) m->small_items.push_back(i);
-      else m->big_items.push_back(i);
-    }
-    for (int c = 0; c < kNCF; ++c)
-      for (int i : m->small_items) us.push_back(FftUnit{i, c, 0, 0});
-    for (int c = 0; c < kNCF; ++c)
-      for (int i : m->big_items) {
-        const int lg = m->items[i].fftlog;
-        const int l2 = lg / 2, l1 = lg - l2;
-        int T = std::min(kFftTileMax, kFftLds >> l1);
-        m->fft4_lds = std::max(m->fft4_lds, size_t(T) * (size_t(1) << l1) * sizeof(double2));
-        for (int t = 0; t < (1 << l1) / T; ++t) u1.push_back(FftUnit{i, c, t, 0});
-        for (int t = 0; t < (1 << l2) / T; ++t) u2.push_back(FftUnit{i, c, t, 0});
-      }
-    // near-band rows of every item (after either transform path)
-    for (int c = 0; c < kNCF; ++c)
-      for (int i = 0; i < m->batch; ++i) {
-        constexpr int kRowsPerUnit = kExactRowsWG / 4;   // rows of one k_exact_rows work-group
-        for (int64_t t = 0; t < (m->items[i].n + kRowsPerUnit - 1) / kRowsPerUnit; ++t)
-          ur.push_back(FftUnit{i, c, int32_t(t), 0});
-      }
-    xcd_order(u1, u1.size() / kNCF);
-    xcd_order(u2, u2.size() / kNCF);
-    m->n_fft_small = int(m->small_items.size());
-    m->n_fft_p1 = int(u1.size());
-    m->n_fft_p2 = int(u2.size());
-    m->n_fft_rows = int(ur.size());
-    ALLOC(m->fft_row_units, ur.size());
-    if (!ur.empty()) HIP_TRY(hipMemcpy(m->fft_row_units, ur.data(), ur.size() * sizeof(FftUnit), hipMemcpyHostToDevice));
-    ALLOC(m->fft_small_units, us.size());
-    ALLOC(m->fft_p1_units, u1.size());
-    ALLOC(m->fft_p2_units, u2.size());
-    if (!us.empty()) HIP_TRY(hipMemcpy(m->fft_small_units, us.data(), us.size() * sizeof(FftUnit), hipMemcpyHostToDevice));
-    if (!u1.empty()) HIP_TRY(hipMemcpy(m->fft_p1_units, u1.data(), u1.size() * sizeof(FftUnit), hipMemcpyHostToDevice));
-    if (!u2.empty()) HIP_TRY(hipMemcpy(m->fft_p2_units, u2.data(), u2.size() * sizeof(FftUnit), hipMemcpyHostToDevice));
+    int64_t nmax = 1;
+    for (const Item& it : m->items) nmax = std::max(nmax, it.n);
+    m->step_slices = int((nmax + kStepRows - 1) / kStepRows);
+  }
+  ALLOC(m->ukeep, row0);
+  ALLOC(m->step_part, size_t(batch) * m->step_slices);
+  ALLOC(m->step_worst, batch);
+  ALLOC(m->fft_row_units, ur.size());
+  ALLOC(m->fft_small_units, us.size());
+  ALLOC(m->fft_p1_units, u1.size());
+  ALLOC(m->fft_p2_units, u2.size());
+  if (m->ws || sizing) {
+    // in a workspace the reduced-precision factor copies sit before the
+    // factorisation schedule, which is re-planned in place when the launch
+    // shapes change and so comes last
+    st = alloc_lowprec(m);
+    if (st != HODLR_OK) { hodlr_destroy(m); return st == HODLR_EWORKSPACE ? set_arg(ctx, 6) : st; }
+    m->ws_sched = (m->ws_used + 255) & ~size_t(255);
   }
 #undef ALLOC
-  HIP_TRY(hipMemcpy(P.items, m->items.data(), batch * sizeof(Item), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(P.nodes, m->nodes.data(), m->nodes.size() * sizeof(Node), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(P.rowleaf, rowleaf.data(), row0 * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(m->wu, m->wu_h.data(), m->nwu * sizeof(WorkUnit), hipMemcpyHostToDevice));
-  if (m->nnu) HIP_TRY(hipMemcpy(m->nu, m->nu_h.data(), m->nnu * sizeof(NodeUnit), hipMemcpyHostToDevice));
+  if (sizing) {
+    // the schedule at the shapes the autotuner tries and at the ones this
+    // process has tuned for the tree signature
+    std::vector<std::pair<int, int>> shapes;
+    for (int g : {128, 256, 512})
+      for (int f : {0, 128, 256, 512, 1024}) shapes.emplace_back(g, f);
+    shapes.emplace_back(m->gram_rows, m->fuse_rows);
+    {
+      std::lock_guard<std::mutex> lk(g_tuned_mu);
+      auto f = g_tuned.find(tune_key(m));
+      if (f != g_tuned.end()) shapes.emplace_back(f->second.gram_rows, f->second.fuse_rows);
+    }
+    size_t most = 0;
+    for (auto& gf : shapes) {
+      m->gram_rows = gf.first;
+      m->fuse_rows = gf.second;
+      m->mwg_planned = false;
+      m->mwg_kind.clear();
+      m->mwg_side.clear();
+      m->mwg_grid.clear();
+      m->mwg_off.clear();
+      m->mwg_off2.clear();
+      m->ws_used = m->ws_sched;
+      st = plan_mwg(m);
+      if (st != HODLR_OK) { delete m; return st; }
+      most = std::max(most, m->ws_used - m->ws_sched);
+    }
+    *need = m->ws_sched + most + 256;   // + alignment of the workspace's own start
+    delete m;
+    return HODLR_OK;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&m->host_worst), batch * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    m->host_worst = nullptr;
+    hodlr_destroy(m);
+    return HODLR_ENOMEM;
+  }
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hodlr_status {
+    if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return HODLR_OK;
+  };
+  TRY(up(m->fft_row_units, ur.data(), ur.size() * sizeof(FftUnit)));
+  TRY(up(m->fft_small_units, us.data(), us.size() * sizeof(FftUnit)));
+  TRY(up(m->fft_p1_units, u1.data(), u1.size() * sizeof(FftUnit)));
+  TRY(up(m->fft_p2_units, u2.data(), u2.size() * sizeof(FftUnit)));
+  TRY(up(P.items, m->items.data(), batch * sizeof(Item)));
+  TRY(up(P.nodes, m->nodes.data(), m->nodes.size() * sizeof(Node)));
+  TRY(up(P.rowleaf, rowleaf.data(), row0 * sizeof(int32_t)));
+  TRY(up(m->wu, m->wu_h.data(), m->nwu * sizeof(WorkUnit)));
+  TRY(up(m->nu, m->nu_h.data(), m->nnu * sizeof(NodeUnit)));
   HIP_TRY(hipMemsetAsync(P.status, 0, batch * sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(P.diag, 0, 4 * batch * sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(P.rankL, 0, node0 * sizeof(int32_t), s));
@@ -1170,6 +1338,7 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   // ---- device construction
   HFDE_LAUNCH(k_gl_weights, dim3(batch), dim3(1024), 0, s, P);
   HFDE_LAUNCH(k_hankel_aca, dim3(batch), dim3(512), 0, s, P, opts->tol);
+  HFDE_LAUNCH(k_hankel_truncate, dim3(batch), dim3(256), 0, s, P);
   for (int i = 0; i < batch; ++i) {
     const Item& it = m->items[i];
     if (it.L > 0)
@@ -1197,6 +1366,7 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipMemcpy(m->items.data(), P.items, batch * sizeof(Item), hipMemcpyDeviceToHost));
   for (const Item& it : m->items) m->max_rank_A = std::max(m->max_rank_A, it.r);
+  TRY(read_capped_A(m));
   {  // launch shapes tuned earlier in the process for this tree signature
     std::lock_guard<std::mutex> lk(g_tuned_mu);
     auto f = g_tuned.find(tune_key(m));
@@ -1209,6 +1379,77 @@ hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, cons
   }
   *out = m;
   return HODLR_OK;
+}
+
+hodlr_status hodlr_build(hodlr_ctx ctx, const fde_operator* ops, int batch, const hodlr_opts* opts,
+                         hodlr_mat* out) {
+  if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
+  if (!out) return set_arg(ctx, 5);
+  return build_impl(ctx, ops, batch, opts, nullptr, 0, out, nullptr);
+}
+
+// Workspace sizes already computed in this process, by the arguments that
+// determine them (sizes, leaf, precision and the launch shapes tuned for the
+// tree, if any): the sizing pass plans the factorisation schedule at every
+// shape the autotuner tries, which costs milliseconds of host time for large
+// batches, and a loop that builds matrices of one shape asks again and again.
+static std::map<std::vector<int64_t>, size_t> g_ws_sizes;
+static std::mutex g_ws_mu;
+
+static hodlr_status workspace_size_cached(const fde_operator* ops, int batch, const hodlr_opts* opts,
+                                          size_t* bytes) {
+  if (!ops || batch < 1 || !opts) return build_impl(nullptr, ops, batch, opts, nullptr, 0, nullptr, bytes);
+  std::vector<int64_t> key{batch, opts->leaf, opts->prec, env_int("HODLR_FUSE_ROWS", -1)};
+  int64_t total = 0, Lmax = 0;
+  for (int i = 0; i < batch; ++i) {
+    key.push_back(ops[i].n);
+    total += ops[i].n;
+    Lmax = std::max<int64_t>(Lmax, levels_for(ops[i].n, std::max(1, opts->leaf)));
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto f = g_tuned.find(TuneKey{batch, total, int(Lmax), opts->leaf});
+    key.push_back(f != g_tuned.end() ? f->second.gram_rows : -1);
+    key.push_back(f != g_tuned.end() ? f->second.fuse_rows : -1);
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto f = g_ws_sizes.find(key);
+    if (f != g_ws_sizes.end()) {
+      *bytes = f->second;
+      return HODLR_OK;
+    }
+  }
+  size_t need = 0;
+  const hodlr_status st = build_impl(nullptr, ops, batch, opts, nullptr, 0, nullptr, &need);
+  if (st != HODLR_OK) return st;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  g_ws_sizes[key] = need;
+  *bytes = need;
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_workspace_size(const fde_operator* ops, int batch, const hodlr_opts* opts, size_t* bytes) {
+  if (!bytes) return HODLR_EINVAL;
+  return workspace_size_cached(ops, batch, opts, bytes);
+}
+
+hodlr_status hodlr_build_ws(hodlr_ctx ctx, const fde_operator* ops, int batch, const hodlr_opts* opts,
+                            void* workspace, size_t ws_bytes, hodlr_mat* out) {
+  if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
+  if (!workspace) return set_arg(ctx, 5);
+  if (!out) return set_arg(ctx, 7);
+  size_t need = 0;
+  hodlr_status st = workspace_size_cached(ops, batch, opts, &need);
+  if (st == HODLR_EINVAL) st = build_impl(ctx, ops, batch, opts, nullptr, 0, nullptr, &need);   // names the argument
+  if (st != HODLR_OK) return st;
+  // the workspace's own start may be unaligned: carve from the first 256-byte boundary
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(workspace);
+  const uintptr_t a1 = (a0 + 255) & ~uintptr_t(255);
+  if (ws_bytes < need || ws_bytes < (a1 - a0)) return set_arg(ctx, 6);
+  return build_impl(ctx, ops, batch, opts, reinterpret_cast<void*>(a1), ws_bytes - (a1 - a0), out, nullptr);
 }
 
 hodlr_status hodlr_update_coefficients(hodlr_ctx ctx, hodlr_mat m, const fde_operator* ops) {
@@ -1238,6 +1479,7 @@ hodlr_status hodlr_update_coefficients(hodlr_ctx ctx, hodlr_mat m, const fde_ope
   HIP_TRY(hipMemsetAsync(P.rankU, 0, m->total_nodes * sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(P.rankP, 0, m->total_nodes * sizeof(int32_t), s));
   HFDE_LAUNCH(k_hankel_aca, dim3(batch), dim3(512), 0, s, P, m->opts.tol);
+  HFDE_LAUNCH(k_hankel_truncate, dim3(batch), dim3(256), 0, s, P);
   for (int i = 0; i < batch; ++i) {
     const Item& it = m->items[i];
     if (it.L > 0)
@@ -1249,6 +1491,7 @@ hodlr_status hodlr_update_coefficients(hodlr_ctx ctx, hodlr_mat m, const fde_ope
   HIP_TRY(hipMemcpy(m->items.data(), P.items, batch * sizeof(Item), hipMemcpyDeviceToHost));
   m->max_rank_A = 0;
   for (const Item& it : m->items) m->max_rank_A = std::max(m->max_rank_A, it.r);
+  TRY(read_capped_A(m));
   m->factored = false;
   return HODLR_OK;
 }
@@ -1533,6 +1776,7 @@ hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
     if (stv[i] & 1) res = HODLR_ESINGULAR;
     else if ((stv[i] & 4) && res == HODLR_OK) res = HODLR_ERANK;
   }
+  if (m->capped_A && res == HODLR_OK) res = HODLR_ERANK;
   m->max_rank_factors = maxr;
   m->factored = true;
   // low precision copies
@@ -1542,15 +1786,7 @@ hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
     int64_t nlvl = 0;
     for (const Item& it : m->items) nlvl += int64_t(it.L + 1) * it.n * kRS;
     const int64_t nleafv = m->total_leaves * m->b * m->b;
-    if (!m->LUinv32) {
-      TRY(dalloc(m, &m->LUinv32, nleafv));
-      TRY(dalloc(m, &m->IL32, nlvl));
-      TRY(dalloc(m, &m->IU32, nlvl));
-      if (m->opts.prec == HODLR_MIXED_BF16) {
-        TRY(dalloc(m, &m->IL16, nlvl));
-        TRY(dalloc(m, &m->IU16, nlvl));
-      }
-    }
+    if (!m->LUinv32) TRY(alloc_lowprec(m));
     HFDE_LAUNCH(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.LUinv, m->LUinv32, nleafv);
     HFDE_LAUNCH(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.IL, m->IL32, nlvl);
     HFDE_LAUNCH(k_convert<float>, dim3(4096), dim3(256), 0, s, m->P.IU, m->IU32, nlvl);
@@ -1571,6 +1807,47 @@ hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
   return res;
 }
 
+// x <- M_p^{-1} b (b in m->bbuf, cn columns), then FP64 refinement sweeps
+// r = b - M x (exact), d = M_p^{-1} r, x += d, until ||d|| <= rtol ||x|| for
+// every problem and column (the correction estimates the forward error; the
+// residual of a stiff M floors near u ||M|| ||x||), or the correction stalls
+// (shrinks by less than 10%), or maxsw sweeps.  1: converged, 0: not, negative:
+// a HIP error status.  rel_r, rel_d: worst ||r||/||b|| and ||d||/||x||.
+static int sweep_solve(hodlr_mat m, int p, int maxsw, double* xc, int64_t ld, int cn, hipStream_t s,
+                       double& rel_r, double& rel_d, int& iters) {
+  const int64_t tn = m->total_n;
+  const int nb_off = m->batch * kNCS;
+  double* nrm = m->norms;   // [0]: ||r||^2  [1]: ||b||^2  [2]: ||d||^2  [3]: ||x||^2 (each batch x kNCS)
+  launch_norms(m, m->bbuf, tn, cn, nrm + nb_off, s);
+  launch_solve(m, p, m->bbuf, tn, xc, ld, cn, s);
+  double prev = 1e300;
+  std::vector<double> h(4 * nb_off);
+  rel_r = rel_d = 1e300;
+  for (int sweep = 0; sweep < maxsw; ++sweep) {
+    launch_fft_matvec(m, xc, ld, m->rbuf, tn, m->bbuf, tn, cn, s);
+    launch_solve(m, p, m->rbuf, tn, m->dbuf, tn, cn, s);
+    launch_axpby(tn, cn, 1.0, xc, ld, 1.0, m->dbuf, tn, xc, ld, s);
+    launch_norms(m, m->rbuf, tn, cn, nrm, s);
+    launch_norms(m, m->dbuf, tn, cn, nrm + 2 * nb_off, s);
+    launch_norms(m, xc, ld, cn, nrm + 3 * nb_off, s);
+    if (hipMemcpyAsync(h.data(), nrm, h.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return HODLR_EHIP;
+    rel_r = rel_d = 0.0;
+    for (int q = 0; q < m->batch * cn; ++q) {
+      const double bq = h[nb_off + q], xq = h[3 * nb_off + q];
+      rel_r = std::max(rel_r, bq > 0 ? std::sqrt(h[q] / bq) : 0.0);
+      rel_d = std::max(rel_d, xq > 0 ? std::sqrt(h[2 * nb_off + q] / xq) : 0.0);
+    }
+    iters = std::max(iters, sweep + 1);
+    if (!(rel_d == rel_d)) return 0;   // NaN
+    if (rel_d <= m->opts.rtol) return 1;
+    if (rel_d > 0.9 * prev) return 0;  // stalled or diverging
+    prev = rel_d;
+  }
+  return 0;
+}
+
 hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_t ld, hodlr_info* info) {
   if (!ctx) return HODLR_EINVAL;
   TimerScope ts_(ctx);
@@ -1589,52 +1866,21 @@ hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_
     const int cn = std::min(kNCS, nrhs - c0);
     double* xc = x + int64_t(c0) * ld;
     const int64_t tn = m->total_n;
-    const bool refine = m->opts.refine_max > 0;
-    if (!refine) {
+    if (m->opts.refine_max <= 0) {
       launch_solve(m, prec, xc, ld, xc, ld, cn, s);
       continue;
     }
-    // keep b; x0 = M_low^{-1} b; then sweeps r = b - M x (exact), d = M_low^{-1} r,
-    // x += d, until ||d|| <= rtol ||x|| (the correction estimates the forward
-    // error; the residual of a stiff M floors near u ||M|| ||x||).
+    // keep b, then the refined solve at the stored precision; a low-precision
+    // solve that does not converge is redone from b with the FP64 factors
     HIP_TRY(hipMemcpy2DAsync(m->bbuf, tn * sizeof(double), xc, ld * sizeof(double), tn * sizeof(double), cn,
                              hipMemcpyDeviceToDevice, s));
-    const int nb_off = m->batch * kNCS;
-    double* nrm = m->norms;   // [0]: ||r||^2  [1]: ||b||^2  [2]: ||d||^2  [3]: ||x||^2 (each batch x kNCS)
-    launch_norms(m, m->bbuf, tn, cn, nrm + nb_off, s);
-    auto sweep_loop = [&](int p, int maxsw, double& rel_r, double& rel_d) -> bool {
-      launch_solve(m, p, m->bbuf, tn, xc, ld, cn, s);
-      double prev = 1e300;
-      std::vector<double> h(4 * nb_off);
-      rel_r = rel_d = 1e300;
-      for (int sweep = 0; sweep < maxsw; ++sweep) {
-        launch_fft_matvec(m, xc, ld, m->rbuf, tn, m->bbuf, tn, cn, s);
-        launch_solve(m, p, m->rbuf, tn, m->dbuf, tn, cn, s);
-        launch_axpby(tn, cn, 1.0, xc, ld, 1.0, m->dbuf, tn, xc, ld, s);
-        launch_norms(m, m->rbuf, tn, cn, nrm, s);
-        launch_norms(m, m->dbuf, tn, cn, nrm + 2 * nb_off, s);
-        launch_norms(m, xc, ld, cn, nrm + 3 * nb_off, s);
-        HIP_TRY(hipMemcpyAsync(h.data(), nrm, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        rel_r = rel_d = 0.0;
-        for (int q = 0; q < m->batch * cn; ++q) {
-          const double bq = h[nb_off + q], xq = h[3 * nb_off + q];
-          rel_r = std::max(rel_r, bq > 0 ? std::sqrt(h[q] / bq) : 0.0);
-          rel_d = std::max(rel_d, xq > 0 ? std::sqrt(h[2 * nb_off + q] / xq) : 0.0);
-        }
-        iters = std::max(iters, sweep + 1);
-        if (!(rel_d == rel_d)) return false;   // NaN
-        if (rel_d <= m->opts.rtol) return true;
-        if (rel_d > 0.9 * prev) return false;  // stalled or diverging
-        prev = rel_d;
-      }
-      return false;
-    };
     double rr = 0, rd = 0;
-    bool conv = sweep_loop(prec, m->opts.refine_max, rr, rd);
+    int conv = sweep_solve(m, prec, m->opts.refine_max, xc, ld, cn, s, rr, rd, iters);
+    if (conv < 0) return hodlr_status(conv);
     if (!conv && prec != HODLR_FP64) {
       fallback = true;
-      conv = sweep_loop(HODLR_FP64, std::max(4, m->opts.refine_max), rr, rd);
+      conv = sweep_solve(m, HODLR_FP64, std::max(4, m->opts.refine_max), xc, ld, cn, s, rr, rd, iters);
+      if (conv < 0) return hodlr_status(conv);
     }
     if (!conv) res = HODLR_ENOCONV;
     worst = std::max(worst, rr);
@@ -1655,6 +1901,11 @@ hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_
   return res;
 }
 
+// One implicit Euler step at the stored precision with a fixed number of
+// refinement sweeps: b = u + fscale f, u = M_low^{-1} b, then `sweeps` times
+// r = b - M u (exact), d = M_low^{-1} r, u += d.  With sweeps > 0 the last
+// update also folds the step's ||d||/||u|| into m->step_worst.  No host
+// synchronisation: the sequence is what a time-step graph captures.
 static void record_step(hodlr_mat m, double* u, const double* f, double fscale, int sweeps, hipStream_t s) {
   const int64_t tn = m->total_n;
   const int prec = m->opts.prec;
@@ -1665,9 +1916,19 @@ static void record_step(hodlr_mat m, double* u, const double* f, double fscale, 
   for (int q = 0; q < sweeps; ++q) {
     launch_fft_matvec(m, u, tn, m->rbuf, tn, m->bbuf, tn, 1, s);
     launch_solve(m, prec, m->rbuf, tn, m->dbuf, tn, 1, s);
-    launch_axpby(tn, 1, 1.0, u, tn, 1.0, m->dbuf, tn, u, tn, s);
+    if (q + 1 < sweeps) {
+      launch_axpby(tn, 1, 1.0, u, tn, 1.0, m->dbuf, tn, u, tn, s);
+    } else {
+      HFDE_LAUNCH(k_step_update, dim3(m->step_slices, m->batch), dim3(256), 0, s, m->P, u, m->dbuf,
+                  m->step_part, m->step_slices);
+      HFDE_LAUNCH(k_step_check, dim3(1), dim3(256), 0, s, m->batch, m->step_part, m->step_slices,
+                  m->step_worst);
+    }
   }
 }
+
+// Steps between two convergence checks of the time loop.
+constexpr int kCheckSteps = 32;
 
 hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const double* f, double fscale, int steps,
                               hodlr_info* info) {
@@ -1680,12 +1941,11 @@ hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const doubl
   hipStream_t s = ctx->stream;
   const int64_t tn = m->total_n;
   const int sweeps = m->opts.refine_max;
-  if (s == nullptr || ctx->timing) {
+  const bool direct = (s == nullptr || ctx->timing);
+  if (!direct && (!m->step_graph || m->graph_u != u || m->graph_f != f || m->graph_sweeps != sweeps ||
+                  m->graph_fscale != fscale)) {
     // the legacy null stream cannot be captured, and timed runs bracket every
-    // launch with events: launch the steps directly
-    for (int k = 0; k < steps; ++k) record_step(m, u, f, fscale, sweeps, s);
-  } else if (!m->step_graph || m->graph_u != u || m->graph_f != f || m->graph_sweeps != sweeps ||
-             m->graph_fscale != fscale) {
+    // launch with events: those launch the steps directly
     if (m->step_graph) {
       (void)hipGraphExecDestroy(m->step_graph);
       m->step_graph = nullptr;
@@ -1701,42 +1961,75 @@ hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const doubl
     m->graph_sweeps = sweeps;
     m->graph_fscale = fscale;
   }
-  if (s != nullptr && !ctx->timing)
-    for (int k = 0; k < steps; ++k) HIP_TRY(hipGraphLaunch(m->step_graph, s));
+  // Runs of kCheckSteps steps.  With refinement, each run starts from a copy
+  // of u and ends with one read-back of the worst correction of its steps; a
+  // run in which any step of any problem missed rtol (or went non-finite) is
+  // restored and redone step by step on the FP64 factors, each step refined
+  // until it converges or stalls.
+  const bool check = sweeps > 0;
+  bool fallback = false, unconv = false;
+  double worst_all = 0.0;
+  int iters = sweeps;
+  for (int k0 = 0; k0 < steps; k0 += (check ? kCheckSteps : steps)) {
+    const int kc = check ? std::min(kCheckSteps, steps - k0) : steps;
+    if (check) {
+      HIP_TRY(hipMemcpyAsync(m->ukeep, u, tn * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemsetAsync(m->step_worst, 0, m->batch * sizeof(double), s));
+    }
+    for (int k = 0; k < kc; ++k) {
+      if (direct) record_step(m, u, f, fscale, sweeps, s);
+      else HIP_TRY(hipGraphLaunch(m->step_graph, s));
+    }
+    if (!check) break;
+    HIP_TRY(hipMemcpyAsync(m->host_worst, m->step_worst, m->batch * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double w = 0.0;
+    for (int q = 0; q < m->batch; ++q) w = std::max(w, m->host_worst[q]);
+    if (w <= m->opts.rtol) {
+      worst_all = std::max(worst_all, w);
+      continue;
+    }
+    fallback = true;
+    HIP_TRY(hipMemcpyAsync(u, m->ukeep, tn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < kc; ++k) {
+      if (f) launch_axpby(tn, 1, 1.0, u, tn, fscale, f, tn, m->bbuf, tn, s);
+      else launch_axpby(tn, 1, 1.0, u, tn, 0.0, u, tn, m->bbuf, tn, s);
+      double rr = 0, rd = 0;
+      const int conv = sweep_solve(m, HODLR_FP64, std::max(4, sweeps), u, tn, 1, s, rr, rd, iters);
+      if (conv < 0) return hodlr_status(conv);
+      if (!conv) unconv = true;
+      worst_all = std::max(worst_all, rd);
+    }
+  }
   HIP_TRY(hipGetLastError());
+  const hodlr_status res = unconv ? HODLR_ENOCONV : HODLR_OK;
   if (info) {
     memset(info, 0, sizeof(*info));
-    info->refine_iters = sweeps;
+    info->refine_iters = iters;
     info->max_rank = m->max_rank_factors;
     info->leaf = -1;
     info->row = -1;
+    info->used_fallback = fallback ? 1 : 0;
     // residual of the last step against its right-hand side (still in bbuf)
-    launch_fft_matvec(m, u, tn, m->rbuf, tn, m->bbuf, tn, 1, s);
-    launch_norms(m, m->rbuf, tn, 1, m->norms, s);
-    launch_norms(m, m->bbuf, tn, 1, m->norms + m->batch * kNCS, s);
-    std::vector<double> nr(m->batch), nb(m->batch);
-    HIP_TRY(hipMemcpyAsync(nr.data(), m->norms, nr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(nb.data(), m->norms + m->batch * kNCS, nb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    double rel = 0.0;
-    for (int q = 0; q < m->batch; ++q) rel = std::max(rel, nb[q] > 0 ? std::sqrt(nr[q] / nb[q]) : 0.0);
-    info->rel_residual = rel;
-    info->rel_correction = 0.0;
-    if (sweeps > 0) {
-      // size of the last correction of the last step relative to u
-      launch_norms(m, m->dbuf, tn, 1, m->norms, s);
-      launch_norms(m, u, tn, 1, m->norms + m->batch * kNCS, s);
+    info->rel_residual = 0.0;
+    if (steps > 0) {
+      launch_fft_matvec(m, u, tn, m->rbuf, tn, m->bbuf, tn, 1, s);
+      launch_norms(m, m->rbuf, tn, 1, m->norms, s);
+      launch_norms(m, m->bbuf, tn, 1, m->norms + m->batch * kNCS, s);
+      std::vector<double> nr(m->batch), nb(m->batch);
       HIP_TRY(hipMemcpyAsync(nr.data(), m->norms, nr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(nb.data(), m->norms + m->batch * kNCS, nb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(nb.data(), m->norms + m->batch * kNCS, nb.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      double rd = 0.0;
-      for (int q = 0; q < m->batch; ++q) rd = std::max(rd, nb[q] > 0 ? std::sqrt(nr[q] / nb[q]) : 0.0);
-      info->rel_correction = rd;
+      double rel = 0.0;
+      for (int q = 0; q < m->batch; ++q) rel = std::max(rel, nb[q] > 0 ? std::sqrt(nr[q] / nb[q]) : 0.0);
+      info->rel_residual = rel;
     }
-    info->status = (sweeps > 0 && info->rel_correction > m->opts.rtol) ? HODLR_ENOCONV : HODLR_OK;
-    return hodlr_status(info->status);
+    // worst relative correction over every step of every problem (0 without refinement)
+    info->rel_correction = worst_all;
+    info->status = res;
   }
-  return HODLR_OK;
+  return res;
 }
 
 // ---- 2D (factored ADI): implemented in adi.hip

@@ -8,7 +8,12 @@
 namespace {
 
 enum { kR_R0 = 0, kR_D0 = 1, kR_D1 = 2, kR_X0 = 3, kR_X1 = 4, kR_T = 5, kR_C = 6, kR_ZERO = 7, kR_E0 = 8, kR_E1 = 9,
-       kR_N = 10 };
+       kR_CAP = 10,   // bit mask of the work slots whose recompression hit its rank cap above its tolerance
+       kR_K0 = 11, kR_K1 = 12,   // rank of the correction sum X_corr (ping-pong)
+       kR_Q1 = 13, kR_Q2 = 14,   // ranks of the orthonormalised sketches of a dense compression
+       kR_N = 15 };
+constexpr int kMaxCorrections = 4;   // correction sweeps of a step after the first
+constexpr int kSketch = 32;          // sketch columns of a dense compression
 
 // ---------- Zolotarev shifts for two real intervals (host, FP64) ----------
 double ellip_K(double k) {           // complete elliptic integral of the first kind, modulus k (AGM)
@@ -85,8 +90,16 @@ double zolotarev_bound(double a1, double b1, double a2, double b2, const std::ve
 
 template <typename T>
 hodlr_status plan_alloc(fde2d_plan p, T** ptr, size_t count) {
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  if (p->sizing || p->ws) {
+    const size_t off = (p->ws_used + 255) & ~size_t(255);
+    if (!p->sizing && off + bytes > p->ws_bytes) return HODLR_EWORKSPACE;
+    p->ws_used = off + bytes;
+    *ptr = p->sizing ? nullptr : reinterpret_cast<T*>(p->ws + off);
+    return HODLR_OK;
+  }
   void* q = nullptr;
-  if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return HODLR_ENOMEM;
+  if (hipMalloc(&q, bytes) != hipSuccess) return HODLR_ENOMEM;
   p->allocs.push_back(q);
   *ptr = static_cast<T*>(q);
   return HODLR_OK;
@@ -130,6 +143,7 @@ hodlr_status ensure_units(fde2d_plan P, int slot, int64_t rows_x, int64_t rows_y
 // nothing from the host.
 hodlr_status run_lr(fde2d_plan P, const LrJob& job, int slot, bool recompress, hipStream_t s) {
   LrJob jb = job;
+  jb.flops = P->counters;
   jb.gx = 2 * slot;
   jb.gy = 2 * slot + 1;
   jb.mslot = slot;
@@ -172,6 +186,129 @@ void copy_cols(int64_t rows, const int32_t* rdev, int rfix, const double* src, i
                double sc, hipStream_t s) {
   const int blocks = int(std::min<int64_t>((rows * 64 + 255) / 256, 4096));
   HFDE_LAUNCH(k_copy_cols, dim3(blocks), dim3(256), 0, s, rows, rdev, rfix, src, lds, dst, ldd, sc);
+}
+
+// ||S||_F of a sum of low-rank products formed entry by entry (k_lrs_dense).
+hodlr_status dense_norm(fde2d_plan P, const LrSum& S, double& norm, hipStream_t s) {
+  const dim3 grid(unsigned((P->nx + 63) / 64), unsigned((P->ny + 63) / 64));
+  int K = 0;
+  for (int g = 0; g < S.ng; ++g) K += S.g[g].cfix;    // every caller passes host column counts
+  P->lrs_flops += 2.0 * double(P->nx) * double(P->ny) * K;
+  HFDE_LAUNCH(k_lrs_dense, grid, dim3(256), 0, s, S, P->lrs_part);
+  HFDE_LAUNCH(k_sum_partials, dim3(1), dim3(256), 0, s, P->lrs_part, int64_t(grid.x) * grid.y, P->dnorm);
+  HIP_TRY(hipMemcpyAsync(P->host_frob + 1, P->dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  norm = std::sqrt(std::max(P->host_frob[1], 0.0));
+  return HODLR_OK;
+}
+
+// Low-rank approximation of a sum S = sum_g s_g P_g Q_g^T by a randomized
+// range finder on its factors (S is never formed): Y = S Om with a
+// kSketch-column uniform Om (counter-based generator, seed), two
+// orthonormalising passes (Q1 from Y, Q2 from Q1), B = S^T Q2, then Q2 B^T
+// recompressed at tau_rel ||S||_F and at most rmax columns into (U, V), rank
+// at *rank_out.
+hodlr_status compress_lrsum(fde2d_plan P, const LrSum& S, double tau_rel, uint64_t seed, int rmax, double* U,
+                            int64_t ldu, double* V, int64_t ldv, int32_t* rank_out, hipStream_t s) {
+  const int64_t nx = P->nx, ny = P->ny;
+  constexpr int kSk = kSketch;
+  static_assert(kSk == kLrsK, "sketch width");
+  HFDE_LAUNCH(k_fill_uniform, dim3(256), dim3(256), 0, s, P->om, ny * kSk, seed);
+  const unsigned sy = unsigned((ny + kLrsSlice - 1) / kLrsSlice), sx = unsigned((nx + kLrsSlice - 1) / kLrsSlice);
+  const unsigned tb = unsigned((kLrsCols * kLrsK + 255) / 256);
+  HFDE_LAUNCH(k_lrs_cross, dim3(sy), dim3(256), 0, s, S, 0, P->om, ny, kSk, P->lrs_cpart);
+  HFDE_LAUNCH(k_lrs_cross_sum, dim3(tb), dim3(256), 0, s, P->lrs_cpart, int(sy), P->lrs_t);
+  HFDE_LAUNCH(k_lrs_apply, dim3(unsigned((nx + 255) / 256)), dim3(256), 0, s, S, 0, P->lrs_t, kSk, P->sk_y, nx);
+  HFDE_LAUNCH(k_set_identity, dim3((kSk * kSk + 255) / 256), dim3(256), 0, s, P->eye, kSk, kSk);
+  for (int pass = 0; pass < 2; ++pass) {
+    LrJob oj{};
+    oj.X.g[0] = pass == 0 ? grp(P->sk_y, nx, nullptr, kSk, 1.0) : grp(P->sk_q1, nx, P->ranks + kR_Q1, 0, 1.0);
+    oj.X.g[1] = oj.X.g[2] = grp_none();
+    oj.Y.g[0] = pass == 0 ? grp(P->eye, kSk, nullptr, kSk, 1.0) : grp(P->eye, kSk, P->ranks + kR_Q1, 0, 1.0);
+    oj.Y.g[1] = oj.Y.g[2] = grp_none();
+    oj.rows_x = nx;
+    oj.rows_y = kSk;
+    oj.rank_out = P->ranks + (pass == 0 ? kR_Q1 : kR_Q2);
+    oj.tau = 0.0;
+    oj.tau_rel = 1e-15;
+    oj.rmax = kSk;
+    oj.U = pass == 0 ? P->sk_q1 : P->sk_q2;
+    oj.ldu = nx;
+    oj.V = P->sk_junk;
+    oj.ldv = kSk;
+    TRY(run_lr(P, oj, 10 + pass, true, s));
+  }
+  HFDE_LAUNCH(k_lrs_cross, dim3(sx), dim3(256), 0, s, S, 1, P->sk_q2, nx, kSk, P->lrs_cpart);
+  HFDE_LAUNCH(k_lrs_cross_sum, dim3(tb), dim3(256), 0, s, P->lrs_cpart, int(sx), P->lrs_t);
+  HFDE_LAUNCH(k_lrs_apply, dim3(unsigned((ny + 255) / 256)), dim3(256), 0, s, S, 1, P->lrs_t, kSk, P->sk_b, ny);
+  LrJob tj{};
+  tj.X.g[0] = grp(P->sk_q2, nx, P->ranks + kR_Q2, 0, 1.0);
+  tj.X.g[1] = tj.X.g[2] = grp_none();
+  tj.Y.g[0] = grp(P->sk_b, ny, P->ranks + kR_Q2, 0, 1.0);
+  tj.Y.g[1] = tj.Y.g[2] = grp_none();
+  tj.rows_x = nx;
+  tj.rows_y = ny;
+  tj.rank_out = rank_out;
+  tj.tau = 0.0;
+  tj.tau_rel = tau_rel;
+  tj.rmax = rmax;
+  tj.U = U;
+  tj.ldu = ldu;
+  tj.V = V;
+  tj.ldv = ldv;
+  TRY(run_lr(P, tj, 12, true, s));
+  return HODLR_OK;
+}
+
+// Low-rank approximation of a dense FP32 nx x ny matrix X (ld nx) by a
+// randomized range finder: Y = X Om with a kSketch-column uniform Om
+// (counter-based generator, seed), two orthonormalising passes (Q1 from Y,
+// Q2 from Q1), B = X^T Q2, then Q2 B^T recompressed at tau_rel ||X||_F and at
+// most rmax columns into (U, V), rank at *rank_out.
+hodlr_status compress_dense(fde2d_plan P, const float* X, double tau_rel, uint64_t seed, int rmax, double* U,
+                            int64_t ldu, double* V, int64_t ldv, int32_t* rank_out, hipStream_t s) {
+  const int64_t nx = P->nx, ny = P->ny;
+  constexpr int kSk = kSketch;
+  HFDE_LAUNCH(k_fill_uniform, dim3(256), dim3(256), 0, s, P->om, ny * kSk, seed);
+  HFDE_LAUNCH(k_field_times, dim3(unsigned((nx + 255) / 256)), dim3(256), 0, s, nx, ny, X, P->om, kSk, P->sk_y);
+  HFDE_LAUNCH(k_set_identity, dim3((kSk * kSk + 255) / 256), dim3(256), 0, s, P->eye, kSk, kSk);
+  for (int pass = 0; pass < 2; ++pass) {
+    LrJob oj{};
+    oj.X.g[0] = pass == 0 ? grp(P->sk_y, nx, nullptr, kSk, 1.0) : grp(P->sk_q1, nx, P->ranks + kR_Q1, 0, 1.0);
+    oj.X.g[1] = oj.X.g[2] = grp_none();
+    oj.Y.g[0] = pass == 0 ? grp(P->eye, kSk, nullptr, kSk, 1.0) : grp(P->eye, kSk, P->ranks + kR_Q1, 0, 1.0);
+    oj.Y.g[1] = oj.Y.g[2] = grp_none();
+    oj.rows_x = nx;
+    oj.rows_y = kSk;
+    oj.rank_out = P->ranks + (pass == 0 ? kR_Q1 : kR_Q2);
+    oj.tau = 0.0;
+    oj.tau_rel = 1e-15;
+    oj.rmax = kSk;
+    oj.U = pass == 0 ? P->sk_q1 : P->sk_q2;
+    oj.ldu = nx;
+    oj.V = P->sk_junk;                         // unused right factor (kSk x r)
+    oj.ldv = kSk;
+    TRY(run_lr(P, oj, 10 + pass, true, s));
+  }
+  HFDE_LAUNCH(k_field_t_times, dim3(unsigned((ny + 255) / 256)), dim3(256), 0, s, nx, ny, X, P->sk_q2,
+              P->ranks + kR_Q2, P->sk_b);
+  LrJob tj{};
+  tj.X.g[0] = grp(P->sk_q2, nx, P->ranks + kR_Q2, 0, 1.0);
+  tj.X.g[1] = tj.X.g[2] = grp_none();
+  tj.Y.g[0] = grp(P->sk_b, ny, P->ranks + kR_Q2, 0, 1.0);
+  tj.Y.g[1] = tj.Y.g[2] = grp_none();
+  tj.rows_x = nx;
+  tj.rows_y = ny;
+  tj.rank_out = rank_out;
+  tj.tau = 0.0;
+  tj.tau_rel = tau_rel;
+  tj.rmax = rmax;
+  tj.U = U;
+  tj.ldu = ldu;
+  tj.V = V;
+  tj.ldv = ldv;
+  TRY(run_lr(P, tj, 12, true, s));
+  return HODLR_OK;
 }
 
 // Shift pairs 4b .. min(4b + 4, J) - 1 of a sweep, main chain: solves of nc
@@ -263,16 +400,17 @@ hodlr_status replay(hipGraphExec_t& ge, hipStream_t s, F&& enqueue) {
 
 // One fADI sweep on the right-hand side G H^T (rank r0, in P->G / P->H; they are
 // consumed).  Accumulates the sweep's solution into Zd/Wd; returns the steps
-// taken and the parity holding the result.  The convergence test comes after
-// every block of four shift pairs.  The solution accumulates in two chains
+// taken and the parity holding the result.  The convergence test (fADI
+// residual ||G_J H_J^T||_F <= target) comes after every block of four shift
+// pairs.  The solution accumulates in two chains
 // (even and odd shift pairs) that are merged at the end.  On a stream of its
 // own (and without kernel timing) each block's solves and each chain are HIP
 // graphs captured on first use, and the two chains run on two more streams
 // one block behind the solves, joined before the merge; otherwise everything
 // runs in the same order on one stream.
-hodlr_status adi_sweep(fde2d_plan P, int r0, double cnorm, int& steps, int& parity, hipStream_t s) {
-  const int64_t nx = P->nx, ny = P->ny;
+hodlr_status adi_sweep(fde2d_plan P, int r0, double target, int& steps, int& parity, hipStream_t s) {
   const double tol = P->opts.tol;
+  const int64_t nx = P->nx, ny = P->ny;
   HIP_TRY(hipMemsetAsync(P->ranks + kR_D0, 0, sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(P->ranks + kR_E0, 0, sizeof(int32_t), s));
   parity = 0;
@@ -304,7 +442,7 @@ hodlr_status adi_sweep(fde2d_plan P, int r0, double cnorm, int& steps, int& pari
     steps = std::min(4 * b + 4, P->J);
     double f2 = 0.0;
     res = read_frob(P, 1, &f2, s);
-    if (res != HODLR_OK || std::sqrt(std::max(f2, 0.0)) <= tol * cnorm) break;
+    if (res != HODLR_OK || std::sqrt(std::max(f2, 0.0)) <= target) break;
   }
   if (graphs) {                                  // join the accumulation chains
     for (int g = 0; g < 2; ++g) {
@@ -374,29 +512,36 @@ int fde2d_plan_shifts(fde2d_plan p, double* ps, double* qs, int cap) {
   return p->J;
 }
 
-hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
-                               const hodlr_opts* hopts, const fde2d_opts* opts, fde2d_plan* out) {
-  if (!ctx) return HODLR_EINVAL;
-  TimerScope ts_(ctx);
+// Shifts, shifted factor sets and work arrays of a 2D plan.  Modes as for
+// the 1D build: library-allocated (ws == nullptr), carved from a caller's
+// workspace, or sizing (need != nullptr: J is fixed from the coefficients as
+// in a real plan, the two HODLR batches are sized by hodlr_workspace_size and
+// the plan's own arrays counted; nothing is built).  The workspace holds the
+// shifted batch, then the unshifted one, then the plan's arrays.
+static hodlr_status plan2d_impl(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
+                                const hodlr_opts* hopts, const fde2d_opts* opts, void* ws, size_t ws_bytes,
+                                fde2d_plan* out, size_t* need) {
+  const bool sizing = need != nullptr;
   if (!opx) return set_arg(ctx, 2);
   if (!opy) return set_arg(ctx, 3);
   if (!hopts) return set_arg(ctx, 4);
   if (!opts || !(opts->tol > 0.0) || opts->max_shifts < 1 || opts->max_shifts > 64 || opts->max_rank < 1 ||
       opts->max_rank > kRS)
     return set_arg(ctx, 5);
-  if (!out) return set_arg(ctx, 6);
+  if (!sizing && !out) return set_arg(ctx, ws ? 8 : 6);
   hipStream_t s = ctx->stream;
   fde2d_plan P = new (std::nothrow) fde2d_plan_s;
   if (!P) return HODLR_ENOMEM;
   P->ctx = ctx;
-  if (hipHostMalloc(reinterpret_cast<void**>(&P->host_ranks), 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  P->sizing = sizing;
+  if (!sizing && hipHostMalloc(reinterpret_cast<void**>(&P->host_ranks), 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     P->host_ranks = nullptr;
     fde2d_plan_destroy(P);
     return HODLR_ENOMEM;
   }
   P->host_frob = reinterpret_cast<double*>(P->host_ranks + 32);
   // two more streams (default priority) for the sweeps' accumulation chains
-  if (s != nullptr && (hipStreamCreateWithFlags(&P->side[0], hipStreamNonBlocking) != hipSuccess ||
+  if (!sizing && s != nullptr && (hipStreamCreateWithFlags(&P->side[0], hipStreamNonBlocking) != hipSuccess ||
                        hipStreamCreateWithFlags(&P->side[1], hipStreamNonBlocking) != hipSuccess ||
                        hipEventCreateWithFlags(&P->ev_blk, hipEventDisableTiming) != hipSuccess ||
                        hipEventCreateWithFlags(&P->ev_done[0], hipEventDisableTiming) != hipSuccess ||
@@ -410,7 +555,7 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
   P->shift_x = opx->shift;
   P->shift_y = opy->shift;
   // spectral intervals [s, s + 2 nu alpha max(d+ + d-)]
-  auto upper = [&](const fde_operator* o, double& hi) -> hodlr_status {
+  auto upper = [&](const fde_operator* o, double& hi, double& lo) -> hodlr_status {
     std::vector<double> dp(o->n), dm(o->n);
     HIP_TRY(hipMemcpy(dp.data(), o->d_plus, o->n * sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(dm.data(), o->d_minus, o->n * sizeof(double), hipMemcpyDeviceToHost));
@@ -418,13 +563,16 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
     for (int64_t i = 0; i < o->n; ++i) mx = std::max(mx, dp[i] + dm[i]);
     const double nu = o->dt / std::pow(o->dx, o->alpha);
     hi = o->shift + 2.0 * nu * o->alpha * mx;
+    lo = o->shift + nu * o->alpha * mx;       // the largest diagonal entry: <= the 2-norm
     return HODLR_OK;
   };
-  double b1 = 0, b2 = 0;
-  hodlr_status st = upper(opx, b1);
-  if (st == HODLR_OK) st = upper(opy, b2);
+  double b1 = 0, b2 = 0, l1 = 0, l2 = 0;
+  hodlr_status st = upper(opx, b1, l1);
+  if (st == HODLR_OK) st = upper(opy, b2, l2);
   if (st != HODLR_OK) { fde2d_plan_destroy(P); return st; }
   const double a1 = opx->shift, a2 = opy->shift;
+  P->bound_x = l1;
+  P->bound_y = l2;
   int J = 1;
   for (; J <= opts->max_shifts; ++J) {
     zolotarev_shifts(a1, b1, a2, b2, J, P->p, P->q);
@@ -470,31 +618,62 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
   for (int j = 0; j < J; ++j) { fde_operator o = *opy; o.shift = opy->shift + P->p[j]; ops.push_back(o); }
   hodlr_opts ho = *hopts;
   ho.refine_max = 0;
-  st = hodlr_build(ctx, ops.data(), int(ops.size()), &ho, &P->mat);
-  if (st != HODLR_OK) { fde2d_plan_destroy(P); return st; }
-  hodlr_info fi{};
-  st = hodlr_factor(ctx, P->mat, &fi);
-  if (st != HODLR_OK && st != HODLR_ERANK) { fde2d_plan_destroy(P); return st; }
   fde_operator ex[2] = {*opx, *opy};
-  st = hodlr_build(ctx, ex, 2, &ho, &P->exact);
-  if (st != HODLR_OK) { fde2d_plan_destroy(P); return st; }
-  // per-pair solve unit lists (x_j leaves/nodes, then y_j)
-  hodlr_mat m = P->mat;
-  std::vector<int> wo(m->batch + 1, 0), no(m->batch + 1, 0);
-  for (const WorkUnit& w : m->wu_h) wo[w.item + 1]++;
-  for (const NodeUnit& u : m->nu_h) no[u.item + 1]++;
-  for (int i = 0; i < m->batch; ++i) { wo[i + 1] += wo[i]; no[i + 1] += no[i]; }
+  size_t need_mat = 0, need_ex = 0;
+  if (sizing || ws) {
+    st = hodlr_workspace_size(ops.data(), int(ops.size()), &ho, &need_mat);
+    if (st == HODLR_OK) st = hodlr_workspace_size(ex, 2, &ho, &need_ex);
+    if (st != HODLR_OK) { fde2d_plan_destroy(P); return st; }
+    need_mat = (need_mat + 255) & ~size_t(255);
+    need_ex = (need_ex + 255) & ~size_t(255);
+  }
+  int64_t total_rows = 0;
   std::vector<WorkUnit> pw;
   std::vector<NodeUnit> pn;
-  for (int j = 0; j < J; ++j) {
-    P->pwu_off.push_back(int(pw.size()));
-    P->pnu_off.push_back(int(pn.size()));
-    for (int it : {j, J + j}) {
-      pw.insert(pw.end(), m->wu_h.begin() + wo[it], m->wu_h.begin() + wo[it + 1]);
-      pn.insert(pn.end(), m->nu_h.begin() + no[it], m->nu_h.begin() + no[it + 1]);
+  if (!sizing) {
+    char* wsc = static_cast<char*>(ws);
+    if (ws && ws_bytes < need_mat + need_ex) { fde2d_plan_destroy(P); return set_arg(ctx, 7); }
+    st = ws ? hodlr_build_ws(ctx, ops.data(), int(ops.size()), &ho, wsc, need_mat, &P->mat)
+            : hodlr_build(ctx, ops.data(), int(ops.size()), &ho, &P->mat);
+    if (st != HODLR_OK) { fde2d_plan_destroy(P); return st; }
+    hodlr_info fi{};
+    st = hodlr_factor(ctx, P->mat, &fi);
+    if (st != HODLR_OK && st != HODLR_ERANK) { fde2d_plan_destroy(P); return st; }
+    st = ws ? hodlr_build_ws(ctx, ex, 2, &ho, wsc + need_mat, need_ex, &P->exact)
+            : hodlr_build(ctx, ex, 2, &ho, &P->exact);
+    if (st != HODLR_OK) { fde2d_plan_destroy(P); return st; }
+    if (ws) {
+      P->ws = wsc + need_mat + need_ex;
+      P->ws_bytes = ws_bytes - need_mat - need_ex;
     }
-    P->pwu_cnt.push_back(int(pw.size()) - P->pwu_off.back());
-    P->pnu_cnt.push_back(int(pn.size()) - P->pnu_off.back());
+    // per-pair solve unit lists (x_j leaves/nodes, then y_j)
+    hodlr_mat m = P->mat;
+    total_rows = m->total_n;
+    std::vector<int> wo(m->batch + 1, 0), no(m->batch + 1, 0);
+    for (const WorkUnit& w : m->wu_h) wo[w.item + 1]++;
+    for (const NodeUnit& u : m->nu_h) no[u.item + 1]++;
+    for (int i = 0; i < m->batch; ++i) { wo[i + 1] += wo[i]; no[i + 1] += no[i]; }
+    for (int j = 0; j < J; ++j) {
+      P->pwu_off.push_back(int(pw.size()));
+      P->pnu_off.push_back(int(pn.size()));
+      for (int it : {j, J + j}) {
+        pw.insert(pw.end(), m->wu_h.begin() + wo[it], m->wu_h.begin() + wo[it + 1]);
+        pn.insert(pn.end(), m->nu_h.begin() + no[it], m->nu_h.begin() + no[it + 1]);
+      }
+      P->pwu_cnt.push_back(int(pw.size()) - P->pwu_off.back());
+      P->pnu_cnt.push_back(int(pn.size()) - P->pnu_off.back());
+    }
+  } else {
+    // the unit lists hold one entry per leaf and internal node of every shifted problem
+    int64_t leaves = 0, nodes = 0;
+    for (const fde_operator& o : ops) {
+      const int L = levels_for(o.n, ho.leaf);
+      leaves += int64_t(1) << L;
+      nodes += (int64_t(1) << L) - 1;
+      total_rows += o.n;
+    }
+    pw.resize(size_t(leaves));
+    pn.resize(size_t(nodes));
   }
   const int64_t nx = P->nx, ny = P->ny;
   const int64_t mr = std::max(nx, ny);
@@ -504,20 +683,38 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
             plan_alloc(P, &P->G, nx * kMaxCat) == HODLR_OK && plan_alloc(P, &P->H, ny * kMaxCat) == HODLR_OK &&
             plan_alloc(P, &P->G0, nx * kMaxCat) == HODLR_OK && plan_alloc(P, &P->H0, ny * kMaxCat) == HODLR_OK &&
             plan_alloc(P, &P->R1, nx * kMaxCat) == HODLR_OK && plan_alloc(P, &P->R1w, ny * kMaxCat) == HODLR_OK &&
-            plan_alloc(P, &P->xin, m->total_n * kMaxCat) == HODLR_OK &&
+            plan_alloc(P, &P->xin, total_rows * kMaxCat) == HODLR_OK &&
             plan_alloc(P, &P->ex_in, (nx + ny) * kMaxCat) == HODLR_OK &&
             plan_alloc(P, &P->ex_out, (nx + ny) * kMaxCat) == HODLR_OK && plan_alloc(P, &P->ranks, kR_N) == HODLR_OK &&
             plan_alloc(P, &P->units, 16 * P->slot_units) == HODLR_OK &&
             plan_alloc(P, &P->gpart, 16 * P->cap_gram * kG2) == HODLR_OK && plan_alloc(P, &P->grams, 32 * kG2) == HODLR_OK &&
             plan_alloc(P, &P->mbuf, 16 * 2 * kMaxCat * kRS) == HODLR_OK && plan_alloc(P, &P->frob, 16) == HODLR_OK;
+  ok = ok && plan_alloc(P, &P->counters, 1) == HODLR_OK && plan_alloc(P, &P->lrs_cpart, ((std::max(nx, ny) + kLrsSlice - 1) / kLrsSlice) * kLrsCols * kLrsK) == HODLR_OK &&
+       plan_alloc(P, &P->lrs_t, kLrsCols * kLrsK) == HODLR_OK &&
+       plan_alloc(P, &P->lrs_part, ((nx + 63) / 64) * ((ny + 63) / 64)) == HODLR_OK &&
+       plan_alloc(P, &P->dnorm, 1) == HODLR_OK && plan_alloc(P, &P->om, ny * kSketch) == HODLR_OK &&
+       plan_alloc(P, &P->sk_y, nx * kSketch) == HODLR_OK && plan_alloc(P, &P->sk_q1, nx * kSketch) == HODLR_OK &&
+       plan_alloc(P, &P->sk_q2, nx * kSketch) == HODLR_OK && plan_alloc(P, &P->sk_b, ny * kSketch) == HODLR_OK &&
+       plan_alloc(P, &P->eye, kSketch * kSketch) == HODLR_OK &&
+       plan_alloc(P, &P->sk_junk, kSketch * kSketch) == HODLR_OK;
   for (int k = 0; k < 2 && ok; ++k)
-    ok = plan_alloc(P, &P->Zx[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wx[k], ny * kRS) == HODLR_OK &&
+    ok = plan_alloc(P, &P->Zc[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wc[k], ny * kRS) == HODLR_OK &&
+         plan_alloc(P, &P->Zx[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wx[k], ny * kRS) == HODLR_OK &&
          plan_alloc(P, &P->Zd[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wd[k], ny * kRS) == HODLR_OK &&
          plan_alloc(P, &P->Ze[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->We[k], ny * kRS) == HODLR_OK;
-  if (!ok) { fde2d_plan_destroy(P); return HODLR_ENOMEM; }
+  if (!ok) {
+    fde2d_plan_destroy(P);
+    return ws ? set_arg(ctx, 7) : HODLR_ENOMEM;
+  }
+  if (sizing) {
+    *need = need_mat + need_ex + P->ws_used + 256;   // + alignment of the workspace's own start
+    fde2d_plan_destroy(P);
+    return HODLR_OK;
+  }
   if (hipMemcpy(P->pair_wu, pw.data(), pw.size() * sizeof(WorkUnit), hipMemcpyHostToDevice) != hipSuccess ||
       (!pn.empty() && hipMemcpy(P->pair_nu, pn.data(), pn.size() * sizeof(NodeUnit), hipMemcpyHostToDevice) != hipSuccess) ||
-      hipMemsetAsync(P->ranks, 0, kR_N * sizeof(int32_t), s) != hipSuccess) {
+      hipMemsetAsync(P->ranks, 0, kR_N * sizeof(int32_t), s) != hipSuccess ||
+      hipMemsetAsync(P->counters, 0, sizeof(double), s) != hipSuccess) {
     fde2d_plan_destroy(P);
     return HODLR_EHIP;
   }
@@ -532,169 +729,285 @@ hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde
   return HODLR_OK;
 }
 
+hodlr_status fde2d_plan_create(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
+                               const hodlr_opts* hopts, const fde2d_opts* opts, fde2d_plan* out) {
+  if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
+  return plan2d_impl(ctx, opx, opy, hopts, opts, nullptr, 0, out, nullptr);
+}
+
+hodlr_status fde2d_plan_counters(fde2d_plan P, double* values, int count, int reset) {
+  if (!P || !values || count < 0) return HODLR_EINVAL;
+  double core = 0.0;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(&core, P->counters, sizeof(double), hipMemcpyDeviceToHost));
+  hodlr_mat_info mi{};
+  if (P->mat) TRY(hodlr_get_info(P->mat, &mi));
+  const double v[5] = {core, P->lrs_flops, double(mi.bytes_factors), double(P->J), double(mi.max_rank_factors)};
+  for (int i = 0; i < count && i < 5; ++i) values[i] = v[i];
+  if (reset) {
+    HIP_TRY(hipMemset(P->counters, 0, sizeof(double)));
+    P->lrs_flops = 0.0;
+  }
+  return HODLR_OK;
+}
+
+hodlr_status fde2d_plan_workspace_size(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
+                                       const hodlr_opts* hopts, const fde2d_opts* opts, size_t* bytes) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!bytes) return set_arg(ctx, 6);
+  size_t need = 0;
+  const hodlr_status st = plan2d_impl(ctx, opx, opy, hopts, opts, nullptr, 0, nullptr, &need);
+  if (st != HODLR_OK) return st;
+  *bytes = need;
+  return HODLR_OK;
+}
+
+hodlr_status fde2d_plan_create_ws(hodlr_ctx ctx, const fde_operator* opx, const fde_operator* opy,
+                                  const hodlr_opts* hopts, const fde2d_opts* opts, void* workspace,
+                                  size_t ws_bytes, fde2d_plan* out) {
+  if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
+  if (!workspace) return set_arg(ctx, 6);
+  if (!out) return set_arg(ctx, 8);
+  size_t need = 0;
+  const hodlr_status st = plan2d_impl(ctx, opx, opy, hopts, opts, nullptr, 0, nullptr, &need);
+  if (st != HODLR_OK) return st;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(workspace);
+  const uintptr_t a1 = (a0 + 255) & ~uintptr_t(255);
+  if (ws_bytes < need || ws_bytes < (a1 - a0)) return set_arg(ctx, 7);
+  return plan2d_impl(ctx, opx, opy, hopts, opts, reinterpret_cast<void*>(a1), ws_bytes - (a1 - a0), out, nullptr);
+}
+
 hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* U_m, const lr_matrix* F,
                                         double dt, const lr_matrix* X0, lr_matrix* U_next, hodlr_info* info) {
   if (!ctx) return HODLR_EINVAL;
   TimerScope ts_(ctx);
   if (!P) return set_arg(ctx, 2);
-  if (!U_m || U_m->rank < 0 || U_m->rank > kRS || (U_m->rank > 0 && (!U_m->Z || !U_m->W))) return set_arg(ctx, 3);
+  if (!U_m || U_m->rank < 0 || U_m->rank > kMaxCat || (U_m->rank > 0 && (!U_m->Z || !U_m->W))) return set_arg(ctx, 3);
   if (!F || F->rank < 0 || F->rank > kRS || (F->rank > 0 && (!F->Z || !F->W))) return set_arg(ctx, 4);
-  if (X0 && (X0->rank < 0 || X0->rank > P->opts.max_rank || (X0->rank > 0 && (!X0->Z || !X0->W))))
+  if (X0 && (X0->rank < 0 || X0->rank > kMaxCat || (X0->rank > 0 && (!X0->Z || !X0->W))))
     return set_arg(ctx, 6);
   if (!U_next || !U_next->Z || !U_next->W || U_next->capacity < 1) return set_arg(ctx, 7);
   hipStream_t s = ctx->stream;
   const int64_t nx = P->nx, ny = P->ny;
   const double tol = P->opts.tol;
   int32_t hr[kR_N];
-  // C = [Z_m, dt F_Z][W_m, F_W]^T, recompressed into G0, H0 (and G, H)
-  LrJob cj{};
-  cj.X.g[0] = grp(U_m->Z, U_m->ldz, nullptr, U_m->rank, 1.0);
-  cj.X.g[1] = grp(F->Z, F->ldz, nullptr, F->rank, dt);
-  cj.X.g[2] = grp_none();
-  cj.Y.g[0] = grp(U_m->W, U_m->ldw, nullptr, U_m->rank, 1.0);
-  cj.Y.g[1] = grp(F->W, F->ldw, nullptr, F->rank, 1.0);
-  cj.Y.g[2] = grp_none();
-  cj.rows_x = nx;
-  cj.rows_y = ny;
-  cj.rank_out = P->ranks + kR_C;
-  cj.tau = 0.0;
-  cj.tau_rel = 1e-3 * tol;
-  cj.rmax = kRS;
-  cj.U = P->G0;
-  cj.ldu = nx;
-  cj.V = P->H0;
-  cj.ldv = ny;
-  if (U_m->rank + F->rank > 0) {
-    TRY(run_lr(P, cj, 0, true, s));
-  } else {
-    HIP_TRY(hipMemsetAsync(P->ranks + kR_C, 0, sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P->ranks + kR_CAP, 0, sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P->ranks + kR_X0, 0, 2 * sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(P->ranks + kR_K0, 0, 2 * sizeof(int32_t), s));
+  // Right-hand side of the first sweep: C = [Z_m, dt F_Z][W_m, F_W]^T
+  // recompressed into G0, H0 (a factor U_m wider than kRS first on its own).
+  // The exact C, for the residuals, is the caller's factors themselves.
+  {
+    const lr_matrix* um = U_m;
+    lr_matrix pre{};
+    if (U_m->rank > kRS || U_m->rank + F->rank > kMaxCat) {
+      LrJob pj{};
+      pj.X.g[0] = grp(U_m->Z, U_m->ldz, nullptr, U_m->rank, 1.0);
+      pj.X.g[1] = pj.X.g[2] = grp_none();
+      pj.Y.g[0] = grp(U_m->W, U_m->ldw, nullptr, U_m->rank, 1.0);
+      pj.Y.g[1] = pj.Y.g[2] = grp_none();
+      pj.rows_x = nx;
+      pj.rows_y = ny;
+      pj.rank_out = P->ranks + kR_T;
+      pj.tau = 0.0;
+      pj.tau_rel = 1e-3 * tol;
+      pj.rmax = kRS;
+      pj.U = P->R1;
+      pj.ldu = nx;
+      pj.V = P->R1w;
+      pj.ldv = ny;
+      TRY(run_lr(P, pj, 0, true, s));
+      TRY(read_ranks(P, hr, s));
+      pre.rows = nx;
+      pre.rank = hr[kR_T];
+      pre.ldz = nx;
+      pre.ldw = ny;
+      pre.Z = P->R1;
+      pre.W = P->R1w;
+      um = &pre;
+    }
+    LrJob cj{};
+    cj.X.g[0] = grp(um->Z, um->ldz, nullptr, um->rank, 1.0);
+    cj.X.g[1] = grp(F->Z, F->ldz, nullptr, F->rank, dt);
+    cj.X.g[2] = grp_none();
+    cj.Y.g[0] = grp(um->W, um->ldw, nullptr, um->rank, 1.0);
+    cj.Y.g[1] = grp(F->W, F->ldw, nullptr, F->rank, 1.0);
+    cj.Y.g[2] = grp_none();
+    cj.rows_x = nx;
+    cj.rows_y = ny;
+    cj.rank_out = P->ranks + kR_C;
+    cj.tau = 0.0;
+    cj.tau_rel = 1e-3 * tol;
+    cj.rmax = kRS;
+    cj.U = P->G0;
+    cj.ldu = nx;
+    cj.V = P->H0;
+    cj.ldv = ny;
+    if (um->rank + F->rank > 0) {
+      TRY(run_lr(P, cj, 0, true, s));
+    } else {
+      HIP_TRY(hipMemsetAsync(P->ranks + kR_C, 0, sizeof(int32_t), s));
+    }
   }
   TRY(read_ranks(P, hr, s));
   const int rc = hr[kR_C];
-  // ||C||_F
-  double cn2 = 0.0;
-  if (rc > 0) {
-    LrJob nj{};
-    nj.X.g[0] = grp(P->G0, nx, P->ranks + kR_C, 0, 1.0);
-    nj.X.g[1] = nj.X.g[2] = grp_none();
-    nj.Y.g[0] = grp(P->H0, ny, P->ranks + kR_C, 0, 1.0);
-    nj.Y.g[1] = nj.Y.g[2] = grp_none();
-    nj.rows_x = nx;
-    nj.rows_y = ny;
-    TRY(run_lr(P, nj, 1, false, s));
-    TRY(read_frob(P, 1, &cn2, s));
-  }
-  const double cnorm = std::sqrt(std::max(cn2, 0.0));
-  // R = C - A X - X B^T for X = Zx[xp] Wx[xp]^T (rank rx) with the exact
-  // near/far Toeplitz products, recompressed into G, H (rank at kR_R0);
-  // returns ||R||_F / ||C||_F.
-  auto exact_residual = [&](int xp, int rx, double& rel) -> hodlr_status {
-    copy_cols(nx, nullptr, rx, P->Zx[xp], nx, P->ex_in, nx + ny, 1.0, s);
-    copy_cols(ny, nullptr, rx, P->Wx[xp], ny, P->ex_in + nx, nx + ny, 1.0, s);
-    launch_fft_matvec(P->exact, P->ex_in, nx + ny, P->ex_out, nx + ny, nullptr, 0, rx, s);
-    LrJob r1{};
-    r1.X.g[0] = grp(P->G0, nx, P->ranks + kR_C, 0, 1.0);
-    r1.X.g[1] = grp(P->ex_out, nx + ny, nullptr, rx, -1.0);      // A Z_X
-    r1.X.g[2] = grp_none();
-    r1.Y.g[0] = grp(P->H0, ny, P->ranks + kR_C, 0, 1.0);
-    r1.Y.g[1] = grp(P->Wx[xp], ny, nullptr, rx, 1.0);
-    r1.Y.g[2] = grp_none();
-    r1.rows_x = nx;
-    r1.rows_y = ny;
-    r1.rank_out = P->ranks + kR_T;
-    r1.tau = 1e-3 * tol * cnorm;
-    r1.tau_rel = 0.0;
-    r1.rmax = kRS;
-    r1.U = P->R1;
-    r1.ldu = nx;
-    r1.V = P->R1w;
-    r1.ldv = ny;
-    TRY(run_lr(P, r1, 7, true, s));
-    LrJob r2 = r1;
-    r2.X.g[0] = grp(P->R1, nx, P->ranks + kR_T, 0, 1.0);
-    r2.X.g[1] = grp(P->Zx[xp], nx, nullptr, rx, -1.0);
-    r2.Y.g[0] = grp(P->R1w, ny, P->ranks + kR_T, 0, 1.0);
-    r2.Y.g[1] = grp(P->ex_out + nx, nx + ny, nullptr, rx, 1.0);   // B W_X
-    r2.rank_out = P->ranks + kR_R0;
-    r2.U = P->G;
-    r2.V = P->H;
-    TRY(run_lr(P, r2, 8, true, s));
-    LrJob nj{};
-    nj.X.g[0] = grp(P->G, nx, P->ranks + kR_R0, 0, 1.0);
-    nj.X.g[1] = nj.X.g[2] = grp_none();
-    nj.Y.g[0] = grp(P->H, ny, P->ranks + kR_R0, 0, 1.0);
-    nj.Y.g[1] = nj.Y.g[2] = grp_none();
-    nj.rows_x = nx;
-    nj.rows_y = ny;
-    TRY(run_lr(P, nj, 9, false, s));
-    double r2n = 0.0;
-    TRY(read_frob(P, 9, &r2n, s));
-    rel = cnorm > 0 ? std::sqrt(std::max(r2n, 0.0)) / cnorm : 0.0;
+  // ||C||_F, formed entry by entry from the caller's factors
+  LrSum csum{};
+  csum.nx = nx;
+  csum.ny = ny;
+  csum.g[csum.ng++] = LrsGroup{U_m->Z, U_m->ldz, U_m->W, U_m->ldw, nullptr, U_m->rank, 1.0};
+  csum.g[csum.ng++] = LrsGroup{F->Z, F->ldz, F->W, F->ldw, nullptr, F->rank, dt};
+  double cnorm = 0.0;
+  TRY(dense_norm(P, csum, cnorm, s));
+  // The solution is kept as two low-rank terms: X = X_main + X_corr.  X_main
+  // (Zx/Wx, rank at kR_X0 + parity) is the first sweep's result, or the
+  // caller's guess; X_corr (Zc/Wc, kR_K0 + parity) sums the corrections.  A
+  // recompression of a sum resolves its terms only to about sqrt(u) times its
+  // norm, so the corrections, each a small fraction of X, are summed apart
+  // from X_main; the residual C - A X - X B^T of the sum is formed entry by
+  // entry (dense_norm), which resolves it to about u times its terms.
+  int xpar = 0, kpar = 0, total_steps = 0, sweeps = 0;
+  double rel_res = 1.0, rel_corr = 0.0, eta = 1.0;
+  bool warm = false, fallback = false;
+  // R = C - A X - X B^T for X = X_main + X_corr: its norm relative to
+  // ||C||_F, and the normwise backward error eta (||A||_2, ||B||_2 replaced by
+  // lower bounds, so eta is an upper bound of the true one).
+  LrSum rsum{};
+  double xnorm = 0.0;
+  auto residual = [&](double& rel) -> hodlr_status {
+    TRY(read_ranks(P, hr, s));
+    const int rx = hr[kR_X0 + xpar], rk = hr[kR_K0 + kpar];
+    const int64_t ld = nx + ny;
+    copy_cols(nx, nullptr, rx, P->Zx[xpar], nx, P->ex_in, ld, 1.0, s);
+    copy_cols(ny, nullptr, rx, P->Wx[xpar], ny, P->ex_in + nx, ld, 1.0, s);
+    if (rk > 0) {
+      copy_cols(nx, nullptr, rk, P->Zc[kpar], nx, P->ex_in + rx * ld, ld, 1.0, s);
+      copy_cols(ny, nullptr, rk, P->Wc[kpar], ny, P->ex_in + rx * ld + nx, ld, 1.0, s);
+    }
+    if (rx + rk > 0) launch_fft_matvec(P->exact, P->ex_in, ld, P->ex_out, ld, nullptr, 0, rx + rk, s);
+    LrSum& r = rsum;
+    r = csum;
+    r.g[r.ng++] = LrsGroup{P->ex_out, ld, P->Wx[xpar], ny, nullptr, rx, -1.0};             // A Z_main W_main^T
+    r.g[r.ng++] = LrsGroup{P->Zx[xpar], nx, P->ex_out + nx, ld, nullptr, rx, -1.0};        // Z_main (B W_main)^T
+    r.g[r.ng++] = LrsGroup{P->ex_out + rx * ld, ld, P->Wc[kpar], ny, nullptr, rk, -1.0};   // A Z_corr W_corr^T
+    r.g[r.ng++] = LrsGroup{P->Zc[kpar], nx, P->ex_out + rx * ld + nx, ld, nullptr, rk, -1.0};
+    double rn = 0.0;
+    TRY(dense_norm(P, r, rn, s));
+    // ||X||_F of the main term (Gram trace): the correction term is a small
+    // fraction of it
+    double x2 = 0.0;
+    if (rx > 0) {
+      LrJob xj{};
+      xj.X.g[0] = grp(P->Zx[xpar], nx, P->ranks + kR_X0 + xpar, 0, 1.0);
+      xj.X.g[1] = xj.X.g[2] = grp_none();
+      xj.Y.g[0] = grp(P->Wx[xpar], ny, P->ranks + kR_X0 + xpar, 0, 1.0);
+      xj.Y.g[1] = xj.Y.g[2] = grp_none();
+      xj.rows_x = nx;
+      xj.rows_y = ny;
+      TRY(run_lr(P, xj, 6, false, s));
+      TRY(read_frob(P, 6, &x2, s));
+    }
+    xnorm = std::sqrt(std::max(x2, 0.0));
+    rel = cnorm > 0 ? rn / cnorm : 0.0;
+    const double scale = (P->bound_x + P->bound_y) * xnorm + cnorm;
+    eta = scale > 0 ? rn / scale : 0.0;
     return HODLR_OK;
   };
-  int xpar = 0, total_steps = 0, sweeps = 0;
-  double rel_res = 0.0, rel_corr = 1.0;
-  int r0 = rc;
-  bool warm = false, fallback = false;
+  // the next right-hand side G H^T: R compressed (rank at kR_R0)
+  auto residual_rhs = [&]() -> hodlr_status {
+    return compress_lrsum(P, rsum, 1e-6, 0x5eedULL + uint64_t(total_steps), kRS, P->G, nx, P->H, ny,
+                          P->ranks + kR_R0, s);
+  };
   if (X0 && X0->rank > 0 && rc > 0) {
-    // first guess: X = X0, right-hand side of the first sweep = its exact residual
-    copy_cols(nx, nullptr, X0->rank, X0->Z, X0->ldz, P->Zx[0], nx, 1.0, s);
-    copy_cols(ny, nullptr, X0->rank, X0->W, X0->ldw, P->Wx[0], ny, 1.0, s);
-    const int32_t rk = X0->rank;
-    HIP_TRY(hipMemcpyAsync(P->ranks + kR_X0, &rk, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // first guess: X_main = X0 (recompressed if wider than kRS); the first
+    // sweep solves for its residual
+    if (X0->rank <= kRS) {
+      copy_cols(nx, nullptr, X0->rank, X0->Z, X0->ldz, P->Zx[0], nx, 1.0, s);
+      copy_cols(ny, nullptr, X0->rank, X0->W, X0->ldw, P->Wx[0], ny, 1.0, s);
+      const int32_t rk = X0->rank;
+      HIP_TRY(hipMemcpyAsync(P->ranks + kR_X0, &rk, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    } else {
+      LrJob gj{};
+      gj.X.g[0] = grp(X0->Z, X0->ldz, nullptr, X0->rank, 1.0);
+      gj.X.g[1] = gj.X.g[2] = grp_none();
+      gj.Y.g[0] = grp(X0->W, X0->ldw, nullptr, X0->rank, 1.0);
+      gj.Y.g[1] = gj.Y.g[2] = grp_none();
+      gj.rows_x = nx;
+      gj.rows_y = ny;
+      gj.rank_out = P->ranks + kR_X0;
+      gj.tau = 0.0;
+      gj.tau_rel = 0.1 * tol;
+      gj.rmax = kRS;
+      gj.U = P->Zx[0];
+      gj.ldu = nx;
+      gj.V = P->Wx[0];
+      gj.ldv = ny;
+      TRY(run_lr(P, gj, 4, true, s));
+    }
     double rel0 = 0.0;
-    TRY(exact_residual(0, X0->rank, rel0));
-    TRY(read_ranks(P, hr, s));
+    TRY(residual(rel0));
     // The J shifts reduce a residual by about 0.1 tol, i.e. by
     // (0.1 tol)^(1/J) per shift.  The guess is worth taking only if its
     // residual saves at least one block of four shifts (the sweep tests for
-    // convergence every four), and the residual must be represented to its
-    // tolerance (rank below the cap) for the correction to be the solution's
-    // error.  Otherwise the plain step runs, so a guess never costs ADI steps.
+    // convergence every four).  Otherwise the plain step runs, so a guess
+    // never costs ADI steps.
     const double accept = std::pow(0.1 * tol, 4.0 / std::max(P->J, 4));
-    if (rel0 <= accept && hr[kR_R0] < kRS) {
+    if (rel0 <= accept) {
       warm = true;
       rel_res = rel0;
-      r0 = hr[kR_R0];
     } else {
       fallback = true;          // the guess is no better than zero: plain solve
+      HIP_TRY(hipMemsetAsync(P->ranks + kR_X0, 0, sizeof(int32_t), s));
     }
   }
-  if (!warm) {                  // sweep 0 on C itself
-    copy_cols(nx, P->ranks + kR_C, 0, P->G0, nx, P->G, nx, 1.0, s);
-    copy_cols(ny, P->ranks + kR_C, 0, P->H0, ny, P->H, ny, 1.0, s);
-    HIP_TRY(hipMemcpyAsync(P->ranks + kR_R0, P->ranks + kR_C, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemsetAsync(P->ranks + kR_X0, 0, sizeof(int32_t), s));
-    r0 = rc;
-  }
   hodlr_status res = HODLR_OK;
-  if (!(warm && rel_res <= 1e-3 * tol)) {
-    for (sweeps = 0; sweeps < 5; ++sweeps) {
+  if (rc > 0) {
+    if (!warm) {
+      // sweep 0 on C itself: its result is X_main
+      copy_cols(nx, P->ranks + kR_C, 0, P->G0, nx, P->G, nx, 1.0, s);
+      copy_cols(ny, P->ranks + kR_C, 0, P->H0, ny, P->H, ny, 1.0, s);
+      HIP_TRY(hipMemcpyAsync(P->ranks + kR_R0, P->ranks + kR_C, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+      // With reduced-precision factors each shifted solve carries errors of
+      // about the factors' precision, which the first sweep cannot go below:
+      // it stops there, and the corrections (whose residuals are exact) take
+      // the solution the rest of the way.
+      const int fp = P->mat->opts.prec;
+      const double first = fp == HODLR_FP64 ? tol : std::max(tol, fp == HODLR_MIXED_FP32 ? 1e-6 : 1e-3);
       int steps = 0, dpar = 0;
-      TRY(adi_sweep(P, r0, std::max(cnorm, 1e-300), steps, dpar, s));
+      TRY(adi_sweep(P, rc, first * std::max(cnorm, 1e-300), steps, dpar, s));
       total_steps += steps;
-      // X <- recompress([X, D][W_X, W_D])
       LrJob mj{};
-      mj.X.g[0] = grp(P->Zx[xpar], nx, P->ranks + kR_X0 + xpar, 0, 1.0);
-      mj.X.g[1] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
-      mj.X.g[2] = grp_none();
-      mj.Y.g[0] = grp(P->Wx[xpar], ny, P->ranks + kR_X0 + xpar, 0, 1.0);
-      mj.Y.g[1] = grp(P->Wd[dpar], ny, P->ranks + kR_D0 + dpar, 0, 1.0);
-      mj.Y.g[2] = grp_none();
+      mj.X.g[0] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
+      mj.X.g[1] = mj.X.g[2] = grp_none();
+      mj.Y.g[0] = grp(P->Wd[dpar], ny, P->ranks + kR_D0 + dpar, 0, 1.0);
+      mj.Y.g[1] = mj.Y.g[2] = grp_none();
       mj.rows_x = nx;
       mj.rows_y = ny;
-      mj.rank_out = P->ranks + kR_X0 + (1 - xpar);
+      mj.rank_out = P->ranks + kR_X0;
       mj.tau = 0.0;
       mj.tau_rel = 0.1 * tol;
       mj.rmax = P->opts.max_rank;
-      mj.U = P->Zx[1 - xpar];
+      mj.U = P->Zx[0];
       mj.ldu = nx;
-      mj.V = P->Wx[1 - xpar];
+      mj.V = P->Wx[0];
       mj.ldv = ny;
       TRY(run_lr(P, mj, 4, true, s));
-      xpar = 1 - xpar;
-      // size of the correction relative to X
-      double d2 = 0.0, x2 = 0.0;
+      TRY(residual(rel_res));
+    }
+    // corrections: A D + D B^T = R, X_corr <- X_corr + D, while the normwise
+    // backward error ||R|| / ((||A|| + ||B||) ||X|| + ||C||) exceeds tol
+    for (sweeps = 0; sweeps < kMaxCorrections && eta > tol; ++sweeps) {
+      TRY(residual_rhs());
+      TRY(read_ranks(P, hr, s));
+      const int r0 = hr[kR_R0];
+      if (r0 == 0) break;
+      int steps = 0, dpar = 0;
+      TRY(adi_sweep(P, r0, 0.1 * tol * std::max(cnorm, 1e-300), steps, dpar, s));
+      total_steps += steps;
+      // ||D||_F (Gram trace), the size of the correction
+      double d2 = 0.0;
       {
         LrJob nj{};
         nj.X.g[0] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
@@ -704,35 +1017,52 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
         nj.rows_x = nx;
         nj.rows_y = ny;
         TRY(run_lr(P, nj, 5, false, s));
-        LrJob xj = nj;
-        xj.X.g[0] = grp(P->Zx[xpar], nx, P->ranks + kR_X0 + xpar, 0, 1.0);
-        xj.Y.g[0] = grp(P->Wx[xpar], ny, P->ranks + kR_X0 + xpar, 0, 1.0);
-        TRY(run_lr(P, xj, 6, false, s));
         TRY(read_frob(P, 5, &d2, s));
-        TRY(read_frob(P, 6, &x2, s));
       }
-      rel_corr = x2 > 0 ? std::sqrt(std::max(d2, 0.0) / x2) : 0.0;
-      // a sweep from zero is not a correction; sweeps from a residual are
-      if ((sweeps > 0 || warm) && rel_corr <= tol) break;
-      if (rc == 0) break;
-      TRY(read_ranks(P, hr, s));
-      const int rx = hr[kR_X0 + xpar];
-      if (rx == 0) break;
-      TRY(exact_residual(xpar, rx, rel_res));
-      TRY(read_ranks(P, hr, s));
-      r0 = hr[kR_R0];
-      if (rel_res <= 1e-3 * tol) break;
+      rel_corr = xnorm > 0 ? std::sqrt(std::max(d2, 0.0)) / xnorm : 0.0;
+      // X_corr <- recompress([X_corr, D]).  An error e in X changes the
+      // residual by up to (||A|| + ||B||) e, so the truncation is absolute,
+      // at 0.1 tol of the backward error's scale over (||A|| + ||B||)
+      LrJob kj{};
+      kj.X.g[0] = grp(P->Zc[kpar], nx, P->ranks + kR_K0 + kpar, 0, 1.0);
+      kj.X.g[1] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
+      kj.X.g[2] = grp_none();
+      kj.Y.g[0] = grp(P->Wc[kpar], ny, P->ranks + kR_K0 + kpar, 0, 1.0);
+      kj.Y.g[1] = grp(P->Wd[dpar], ny, P->ranks + kR_D0 + dpar, 0, 1.0);
+      kj.Y.g[2] = grp_none();
+      kj.rows_x = nx;
+      kj.rows_y = ny;
+      kj.rank_out = P->ranks + kR_K0 + (1 - kpar);
+      kj.tau = 0.1 * tol * ((P->bound_x + P->bound_y) * xnorm + cnorm) / (P->bound_x + P->bound_y);
+      kj.tau_rel = 0.0;
+      kj.rmax = kRS;
+      kj.capped = P->ranks + kR_CAP;
+      kj.U = P->Zc[1 - kpar];
+      kj.ldu = nx;
+      kj.V = P->Wc[1 - kpar];
+      kj.ldv = ny;
+      TRY(run_lr(P, kj, 7, true, s));
+      kpar = 1 - kpar;
+      TRY(residual(rel_res));
     }
-    if (sweeps >= 5 && rel_corr > tol) res = HODLR_ENOCONV;
+    if (eta > tol) res = HODLR_ENOCONV;
   } else {
-    rel_corr = 0.0;
+    rel_res = 0.0;
+    eta = 0.0;
   }
   TRY(read_ranks(P, hr, s));
-  const int rx = hr[kR_X0 + xpar];
-  if (rx > U_next->capacity) return set_arg(ctx, 7);
+  const int rx = hr[kR_X0 + xpar], rk = hr[kR_K0 + kpar];
+  if (rx + rk > U_next->capacity) return set_arg(ctx, 7);
   copy_cols(nx, nullptr, rx, P->Zx[xpar], nx, U_next->Z, U_next->ldz, 1.0, s);
   copy_cols(ny, nullptr, rx, P->Wx[xpar], ny, U_next->W, U_next->ldw, 1.0, s);
-  U_next->rank = rx;
+  if (rk > 0) {
+    copy_cols(nx, nullptr, rk, P->Zc[kpar], nx, U_next->Z + rx * U_next->ldz, U_next->ldz, 1.0, s);
+    copy_cols(ny, nullptr, rk, P->Wc[kpar], ny, U_next->W + rx * U_next->ldw, U_next->ldw, 1.0, s);
+  }
+  U_next->rank = rx + rk;
+  if (hr[kR_CAP] && res == HODLR_OK) res = HODLR_ERANK;
+  if (hr[kR_CAP] && getenv("HODLR_VERBOSE"))
+    fprintf(stderr, "hodlr_fde: 2D step: rank cap reached in work slots 0x%x\n", unsigned(hr[kR_CAP]));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   if (info) {
@@ -741,7 +1071,8 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
     info->refine_iters = total_steps;
     info->rel_residual = rel_res;
     info->rel_correction = rel_corr;
-    info->max_rank = rx;
+    info->backward_error = eta;
+    info->max_rank = rx + rk;
     info->leaf = -1;
     info->row = -1;
     info->used_fallback = fallback ? 1 : 0;
@@ -771,51 +1102,8 @@ hodlr_status fde2d_compress_field(hodlr_ctx ctx, fde2d_plan P, const float* X, d
   if (!(tol > 0.0)) return set_arg(ctx, 4);
   if (!out || !out->Z || !out->W || out->capacity < 1) return set_arg(ctx, 6);
   hipStream_t s = ctx->stream;
-  const int64_t nx = P->nx, ny = P->ny;
-  constexpr int kSk = 32;                       // sketch columns
-  // scratch between steps: R1w = Om (ny x 32), R1 = Y (nx x 32), G = Q1, G0 = Q2,
-  // H = B (ny x 32), ex_in = the 32 x 32 identity
-  HFDE_LAUNCH(k_fill_uniform, dim3(256), dim3(256), 0, s, P->R1w, ny * kSk, seed);
-  HFDE_LAUNCH(k_field_times, dim3(unsigned((nx + 255) / 256)), dim3(256), 0, s, nx, ny, X, P->R1w, kSk, P->R1);
-  HFDE_LAUNCH(k_set_identity, dim3((kSk * kSk + 255) / 256), dim3(256), 0, s, P->ex_in, kSk, kSk);
-  // two orthonormalising passes: Q1 Q1'^T = Y I^T, then Q2 from Q1
-  for (int pass = 0; pass < 2; ++pass) {
-    LrJob oj{};
-    oj.X.g[0] = pass == 0 ? grp(P->R1, nx, nullptr, kSk, 1.0) : grp(P->G, nx, P->ranks + kR_T, 0, 1.0);
-    oj.X.g[1] = oj.X.g[2] = grp_none();
-    oj.Y.g[0] = pass == 0 ? grp(P->ex_in, kSk, nullptr, kSk, 1.0) : grp(P->ex_in, kSk, P->ranks + kR_T, 0, 1.0);
-    oj.Y.g[1] = oj.Y.g[2] = grp_none();
-    oj.rows_x = nx;
-    oj.rows_y = kSk;
-    oj.rank_out = P->ranks + (pass == 0 ? kR_T : kR_D0);
-    oj.tau = 0.0;
-    oj.tau_rel = 1e-15;
-    oj.rmax = kSk;
-    oj.U = pass == 0 ? P->G : P->G0;
-    oj.ldu = nx;
-    oj.V = P->R1w + ny * kSk;                   // unused right factor (32 x r)
-    oj.ldv = kSk;
-    TRY(run_lr(P, oj, 10 + pass, true, s));
-  }
-  HFDE_LAUNCH(k_field_t_times, dim3(unsigned((ny + 255) / 256)), dim3(256), 0, s, nx, ny, X, P->G0, P->ranks + kR_D0,
-              P->H);
-  // X ~ Q2 (X^T Q2)^T, truncated at tol ||X||_F
-  LrJob tj{};
-  tj.X.g[0] = grp(P->G0, nx, P->ranks + kR_D0, 0, 1.0);
-  tj.X.g[1] = tj.X.g[2] = grp_none();
-  tj.Y.g[0] = grp(P->H, ny, P->ranks + kR_D0, 0, 1.0);
-  tj.Y.g[1] = tj.Y.g[2] = grp_none();
-  tj.rows_x = nx;
-  tj.rows_y = ny;
-  tj.rank_out = P->ranks + kR_D1;
-  tj.tau = 0.0;
-  tj.tau_rel = tol;
-  tj.rmax = std::min(out->capacity, P->opts.max_rank);
-  tj.U = out->Z;
-  tj.ldu = out->ldz;
-  tj.V = out->W;
-  tj.ldv = out->ldw;
-  TRY(run_lr(P, tj, 12, true, s));
+  TRY(compress_dense(P, X, tol, seed, std::min(out->capacity, P->opts.max_rank), out->Z, out->ldz, out->W, out->ldw,
+                     P->ranks + kR_D1, s));
   int32_t hr[kR_N];
   TRY(read_ranks(P, hr, s));
   out->rank = hr[kR_D1];

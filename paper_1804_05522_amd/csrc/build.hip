@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(512) k_hankel_aca(DevPtrs P, double eps) {
       if (v > vmax) { vmax = v; imax = int(p); }
     }
     block_reduce_max_sum(vmax, imax, vsum, s_v, s_i, s_s);
-    if (vsum <= tolH || vmax <= 0.0) break;
+    if (vsum <= 0.5 * tolH || vmax <= 0.0) break;
     if (k >= kRS - 1) { capped = true; break; }
     const int pv = imax;
     if (t0 < k) wp[t0] = W[pv + int64_t(t0) * nh];
@@ -155,6 +155,147 @@ __global__ void __launch_bounds__(512) k_hankel_aca(DevPtrs P, double eps) {
     itr.tolH = tolH;
     P.diag[4 * blockIdx.x + 3] = k;
     if (capped) P.status[blockIdx.x] |= 4;
+  }
+}
+
+// Truncation of the Hankel factor to the 2-norm eps-rank.  The trace-stopped
+// cross approximation leaves ||H - W W^T||_2 <= trace <= tolH/2 but keeps
+// columns whose directions carry less than that: the eigenvalues of W W^T are
+// those of G = W^T W (k x k).  G is formed in LDS (128-row chunks, fixed
+// summation order), diagonalised by cyclic Jacobi in the parallel round-robin
+// order (16 disjoint rotations a round, rotations skipped once
+// |g_pq| <= 1e-17 sqrt(g_pp g_qq), at most 30 sweeps), and W is replaced by
+// W V_k' for the eigenvectors whose eigenvalues exceed tolH/2, largest first:
+// ||H - W' W'^T||_2 <= tolH/2 + tolH/2 = tolH, the tolerance of the blocks.
+__global__ void __launch_bounds__(256) k_hankel_truncate(DevPtrs P) {
+  Item& itr = P.items[blockIdx.x];
+  const Item it = itr;
+  const int k = it.k;
+  if (k <= 1) return;
+  constexpr int K = kRS;                   // padded order (k <= kRS - 1)
+  constexpr int kCh = 128;
+  __shared__ double A[K][K + 1];
+  __shared__ double V[K][K + 1];
+  __shared__ double chunk[kCh][K + 1];
+  __shared__ double rc[K / 2], rs[K / 2];
+  __shared__ int rp[K / 2], rq[K / 2];
+  __shared__ int any_rot;
+  __shared__ int order[K];
+  const int t = threadIdx.x;
+  const int64_t nh = it.nh;
+  double* W = P.W + it.w0;
+  // G = W^T W: thread t owns entries e = t and t + 256 of the k x k upper triangle
+  int ea[2], eb[2];
+  double acc[2] = {0.0, 0.0};
+  for (int h = 0; h < 2; ++h) {
+    int e = t + 256 * h, a = 0;
+    while (e >= k - a && a < k) { e -= k - a; ++a; }
+    ea[h] = a < k ? a : -1;
+    eb[h] = a < k ? a + e : -1;
+  }
+  for (int64_t r0 = 0; r0 < nh; r0 += kCh) {
+    const int rows = int(min<int64_t>(kCh, nh - r0));
+    for (int e = t; e < kCh * k; e += blockDim.x) {
+      const int r = e % kCh, c = e / kCh;
+      chunk[r][c] = r < rows ? W[r0 + r + int64_t(c) * nh] : 0.0;
+    }
+    __syncthreads();
+    for (int h = 0; h < 2; ++h)
+      if (ea[h] >= 0)
+        for (int r = 0; r < kCh; ++r) acc[h] = fma(chunk[r][ea[h]], chunk[r][eb[h]], acc[h]);
+    __syncthreads();
+  }
+  for (int e = t; e < K * K; e += blockDim.x) {
+    A[e / K][e % K] = 0.0;
+    V[e / K][e % K] = (e / K == e % K) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int h = 0; h < 2; ++h)
+    if (ea[h] >= 0) {
+      A[ea[h]][eb[h]] = acc[h];
+      A[eb[h]][ea[h]] = acc[h];
+    }
+  __syncthreads();
+  // cyclic Jacobi, round-robin pairs: round r pairs (r, K-1) and ((r+i) mod (K-1), (r-i) mod (K-1))
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (t == 0) any_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < K - 1; ++round) {
+      if (t < K / 2) {
+        int p, q;
+        if (t == 0) { p = round; q = K - 1; }
+        else { p = (round + t) % (K - 1); q = (round - t + (K - 1)) % (K - 1); }
+        if (p > q) { const int w = p; p = q; q = w; }
+        const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
+        double c = 1.0, sn = 0.0;
+        if (apq != 0.0 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+          const double th = (aqq - app) / (2.0 * apq);
+          const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(tt * tt + 1.0);
+          sn = tt * c;
+          any_rot = 1;
+        }
+        rp[t] = p; rq[t] = q; rc[t] = c; rs[t] = sn;
+      }
+      __syncthreads();
+      // rows p, q of A <- J^T A
+      for (int e = t; e < (K / 2) * K; e += blockDim.x) {
+        const int pr = e / K, j = e % K;
+        const int p = rp[pr], q = rq[pr];
+        const double c = rc[pr], sn = rs[pr];
+        const double ap = A[p][j], aq = A[q][j];
+        A[p][j] = c * ap - sn * aq;
+        A[q][j] = sn * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q of A and of V <- (.) J
+      for (int e = t; e < (K / 2) * K * 2; e += blockDim.x) {
+        const int which = e / ((K / 2) * K);
+        const int f = e % ((K / 2) * K);
+        const int pr = f / K, i = f % K;
+        const int p = rp[pr], q = rq[pr];
+        const double c = rc[pr], sn = rs[pr];
+        double (*X)[K + 1] = which ? V : A;
+        const double xp = X[i][p], xq = X[i][q];
+        X[i][p] = c * xp - sn * xq;
+        X[i][q] = sn * xp + c * xq;
+      }
+      __syncthreads();
+    }
+    if (!any_rot) break;
+    __syncthreads();
+  }
+  // eigenvalues A[i][i], i < k, in decreasing order (ties by index); keep those above tolH/2
+  if (t < k) {
+    const double li = A[t][t];
+    int pos = 0;
+    for (int j = 0; j < k; ++j) {
+      const double lj = A[j][j];
+      pos += (lj > li || (lj == li && j < t)) ? 1 : 0;
+    }
+    order[pos] = t;
+  }
+  __syncthreads();
+  int kk = 0;
+  for (int j = 0; j < k; ++j) kk += A[j][j] > 0.5 * it.tolH ? 1 : 0;
+  // W <- W V(:, order[0 .. kk-1]) row by row (in place: a row's outputs need only that row)
+  for (int64_t i = t; i < nh; i += blockDim.x) {
+    double row[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) row[c] = c < k ? W[i + int64_t(c) * nh] : 0.0;
+    for (int c = 0; c < kk; ++c) {
+      const int src = order[c];
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) v = fma(row[j], V[j][src], v);
+      W[i + int64_t(c) * nh] = v;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    itr.k = kk;
+    itr.r = (it.r > it.k) ? kk + 1 : 0;
+    P.diag[4 * blockIdx.x + 3] = kk;
   }
 }
 

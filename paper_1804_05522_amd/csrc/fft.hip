@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kFftWG) k_fft_small(DevPtrs P, const FftUnit* 
   // far-field values for k_exact_rows, which adds the near band (second half
   // of the column's scratch, where the four-step path leaves them too)
   const double inv = 1.0 / double(M);
-  double2* far = P.fws + it.ws0 + int64_t(u.col) * 2 * M + M;
+  double2* far = P.fws + fws_off(P, it, u.col) + M;
   for (int64_t i = threadIdx.x; i < it.n; i += blockDim.x) {
     const double2 w = buf[i];
     far[i] = make_double2(w.x * inv, w.y * inv);
@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(kFft4WG) k_fft4_pass1(DevPtrs P, const FftUnit
   four_step_dims(logM, l1, l2, T);
   const int M1 = 1 << l1, M2 = 1 << l2;
   const double2* tw = P.tw + it.tw0;
-  double2* ws = P.fws + it.ws0 + int64_t(u.col) * 2 * (int64_t(1) << logM);
+  double2* ws = P.fws + fws_off(P, it, u.col);
   double2* Y = ws;                               // first half: Y
   const double2* Win = ws + (int64_t(1) << logM);   // second half: W (inverse input)
   const int n1base = u.tile * T;
@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(kFft4WG) k_fft4_pass2(DevPtrs P, const FftUnit
   const int M1 = 1 << l1, M2 = 1 << l2;
   const int64_t M = int64_t(1) << logM;
   const double2* tw = P.tw + it.tw0;
-  double2* ws = P.fws + it.ws0 + int64_t(u.col) * 2 * M;
+  double2* ws = P.fws + fws_off(P, it, u.col);
   const double2* Y = ws;
   double2* Wout = ws + M;
   const int k2base = u.tile * T;
@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(kExactRowsWG) k_exact_rows(DevPtrs P, const Ff
   }
   if (q != 0 || !valid) return;
   const int64_t M = int64_t(1) << it.fftlog;
-  const double2 w = P.fws[it.ws0 + int64_t(u.col) * 2 * M + M + i];   // far field
+  const double2 w = P.fws[fws_off(P, it, u.col) + M + i];   // far field
   const double* bc = b ? b + it.row0 + int64_t(u.col) * ldb : nullptr;
   y[it.row0 + int64_t(u.col) * ldy + i] = exact_finish(P, it, xc, i, c, w.x, w.y, bc);
 }

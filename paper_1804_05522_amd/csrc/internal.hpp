@@ -37,6 +37,8 @@ struct Item {
   int64_t tw0;           // offset (complex) of the twiddles e^{-2 pi i j/M}, j < M
   int64_t mu0;           // offset (complex) of the far-field multipliers, M entries
   int64_t ws0;           // offset (complex) of the FFT scratch, 2*M per column
+  int64_t wsc0;          // offset (complex) of the FFT scratch of column 0 when the problems' scratch
+                         //   is packed (2*M each, one column a launch)
   double alpha, nu, shift;
   double tolH;           // absolute trace tolerance of the Hankel compression
   double tau;            // absolute truncation tolerance eps * (lower bound of ||M||_2)
@@ -87,6 +89,8 @@ struct DevPtrs {
   double2* fws;          // FFT scratch
   int32_t* status;       // per problem: hodlr_status bits
   int32_t* diag;         // per problem: [singular leaf, max rank, erank flag, k]
+  int32_t fws_compact;   // 1: fws holds one column per problem at Item.wsc0 (see fws_off)
+  int32_t pad_;
 };
 
 // Work lists of the multi-work-group kernels.
@@ -128,6 +132,13 @@ struct SolveFactors {
 
 __host__ __device__ inline int64_t node_index(const Item& it, int d, int64_t j) {
   return it.node0 + ((int64_t(1) << d) - 1) + j;
+}
+
+// First complex value of the transform scratch of (problem, column): 2*M
+// values per column at ws0 + col*2M in the handle's own scratch, or, when the
+// scratch is a packed buffer for single-column launches, at wsc0.
+__device__ inline int64_t fws_off(const DevPtrs& P, const Item& it, int col) {
+  return P.fws_compact ? it.wsc0 : it.ws0 + int64_t(col) * 2 * (int64_t(1) << it.fftlog);
 }
 
 __device__ inline double* lvl_ptr(double* base, const Item& it, int d) {

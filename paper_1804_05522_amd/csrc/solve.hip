@@ -443,6 +443,64 @@ __global__ void k_axpby(int64_t nrows, int nc, double a, const double* x, int64_
   }
 }
 
+// Last refinement update of a time step, with the step's convergence check.
+// k_step_update: u += d for every problem (grid: kStepSlices-row slices x
+// batch), and per slice the partial sums of d^2 and of the updated u^2, in a
+// fixed order.  k_step_check (one work-group): per problem, the slices'
+// partials summed in slice order, rel = ||d||_2 / ||u||_2 (a non-finite rel
+// counts as +inf), worst[item] = max(worst[item], rel).  The host clears
+// worst before a run of steps and compares it with the target afterwards.
+constexpr int kStepRows = 2048;   // rows of one k_step_update work-group (256 threads x 8)
+
+__global__ void __launch_bounds__(256) k_step_update(DevPtrs P, double* u, const double* d, double2* part,
+                                                     int slices) {
+  const Item it = P.items[blockIdx.y];
+  const int64_t r0 = int64_t(blockIdx.x) * kStepRows;
+  double sd = 0.0, su = 0.0;
+  if (r0 < it.n) {
+    double* uc = u + it.row0;
+    const double* dc = d + it.row0;
+    const int64_t r1 = min(it.n, r0 + kStepRows);
+#pragma unroll 8
+    for (int q = 0; q < kStepRows / 256; ++q) {
+      const int64_t i = r0 + q * 256 + threadIdx.x;
+      if (i < r1) {
+        const double dv = dc[i];
+        const double uv = uc[i] + dv;
+        uc[i] = uv;
+        sd += dv * dv;
+        su += uv * uv;
+      }
+    }
+  }
+  __shared__ double rd[256], ru[256];
+  rd[threadIdx.x] = sd;
+  ru[threadIdx.x] = su;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      rd[threadIdx.x] += rd[threadIdx.x + off];
+      ru[threadIdx.x] += ru[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[int64_t(blockIdx.y) * slices + blockIdx.x] = make_double2(rd[0], ru[0]);
+}
+
+__global__ void __launch_bounds__(256) k_step_check(int batch, const double2* part, int slices, double* worst) {
+  for (int item = threadIdx.x; item < batch; item += blockDim.x) {
+    double sd = 0.0, su = 0.0;
+    for (int q = 0; q < slices; ++q) {
+      const double2 v = part[int64_t(item) * slices + q];
+      sd += v.x;
+      su += v.y;
+    }
+    double rel = su > 0.0 ? sqrt(sd / su) : (sd > 0.0 ? INFINITY : 0.0);
+    if (!(rel == rel)) rel = INFINITY;
+    worst[item] = fmax(worst[item], rel);
+  }
+}
+
 template <typename TF>
 __global__ void k_convert(const double* src, TF* dst, int64_t count);
 

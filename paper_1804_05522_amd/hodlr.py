@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhodlr_fde.so")
 
-HODLR_OK, HODLR_EINVAL, HODLR_ENOMEM, HODLR_EHIP, HODLR_ESTATE = 0, -1, -2, -3, -5
+HODLR_OK, HODLR_EINVAL, HODLR_ENOMEM, HODLR_EHIP, HODLR_EWORKSPACE, HODLR_ESTATE = 0, -1, -2, -3, -4, -5
 HODLR_ESINGULAR, HODLR_ENOCONV, HODLR_ERANK = 1, 2, 3
 FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16": MIXED_BF16}
@@ -28,6 +28,8 @@ EXPORTS = [
     "hodlr_set_tuning", "hodlr_update_coefficients",
     "fde_net_param_count", "fde_net_create", "fde_net_destroy", "fde_net_set_params", "fde_net_get_params",
     "fde_net_get_grads", "fde_net_forward", "fde_net_train_step",
+    "hodlr_workspace_size", "hodlr_build_ws", "fde2d_plan_workspace_size", "fde2d_plan_create_ws",
+    "fde2d_plan_counters",
 ]
 
 
@@ -44,7 +46,7 @@ class HodlrOpts(C.Structure):
 class HodlrInfo(C.Structure):
     _fields_ = [("status", C.c_int), ("refine_iters", C.c_int), ("rel_residual", C.c_double),
                 ("max_rank", C.c_int), ("leaf", C.c_int), ("row", C.c_int),
-                ("used_fallback", C.c_int), ("rel_correction", C.c_double)]
+                ("used_fallback", C.c_int), ("rel_correction", C.c_double), ("backward_error", C.c_double)]
 
 
 class HodlrMatInfo(C.Structure):
@@ -88,6 +90,10 @@ def lib():
         L.hodlr_status_string.restype = C.c_char_p
         L.hodlr_default_opts.argtypes = [C.POINTER(HodlrOpts)]
         L.hodlr_build.argtypes = [vp, C.POINTER(FdeOperator), i32, C.POINTER(HodlrOpts), C.POINTER(vp)]
+        L.hodlr_workspace_size.argtypes = [C.POINTER(FdeOperator), i32, C.POINTER(HodlrOpts),
+                                           C.POINTER(C.c_size_t)]
+        L.hodlr_build_ws.argtypes = [vp, C.POINTER(FdeOperator), i32, C.POINTER(HodlrOpts), vp, C.c_size_t,
+                                     C.POINTER(vp)]
         L.hodlr_destroy.argtypes = [vp]
         L.hodlr_destroy.restype = None
         L.hodlr_get_info.argtypes = [vp, C.POINTER(HodlrMatInfo)]
@@ -107,6 +113,13 @@ def lib():
         if hasattr(L, "fde2d_plan_create"):
             L.fde2d_plan_create.argtypes = [vp, C.POINTER(FdeOperator), C.POINTER(FdeOperator),
                                             C.POINTER(HodlrOpts), C.POINTER(Fde2dOpts), C.POINTER(vp)]
+            L.fde2d_plan_workspace_size.argtypes = [vp, C.POINTER(FdeOperator), C.POINTER(FdeOperator),
+                                                    C.POINTER(HodlrOpts), C.POINTER(Fde2dOpts),
+                                                    C.POINTER(C.c_size_t)]
+            L.fde2d_plan_create_ws.argtypes = [vp, C.POINTER(FdeOperator), C.POINTER(FdeOperator),
+                                               C.POINTER(HodlrOpts), C.POINTER(Fde2dOpts), vp, C.c_size_t,
+                                               C.POINTER(vp)]
+            L.fde2d_plan_counters.argtypes = [vp, C.POINTER(C.c_double), i32, i32]
             L.fde2d_plan_destroy.argtypes = [vp]
             L.fde2d_plan_destroy.restype = None
             L.fde2d_plan_shifts.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), i32]
@@ -211,15 +224,29 @@ class HodlrMatrix:
                                  C.c_void_p(dm.data_ptr()))
         return arr
 
-    def __init__(self, ctx: Context, ops, opts: HodlrOpts):
-        """ops: list of dicts n, alpha, dt, dx, shift, d_plus, d_minus (torch CUDA float64)."""
+    def __init__(self, ctx: Context, ops, opts: HodlrOpts, workspace: bool = True):
+        """ops: list of dicts n, alpha, dt, dx, shift, d_plus, d_minus (torch CUDA float64).
+        workspace=True: torch allocates the matrix's device memory (hodlr_workspace_size bytes)
+        and the library builds into it (hodlr_build_ws); False: the library allocates
+        (hodlr_build)."""
         self.ctx = ctx
         arr = self._op_array(ops)
         self.h = C.c_void_p()
+        self.ws = None
         self.opts = opts
         self.sizes = [int(o["n"]) for o in ops]
         self.total_n = sum(self.sizes)
-        check(lib().hodlr_build(ctx.h, arr, len(ops), C.byref(opts), C.byref(self.h)), "hodlr_build", ctx.h)
+        if workspace:
+            import torch
+            need = C.c_size_t()
+            check(lib().hodlr_workspace_size(arr, len(ops), C.byref(opts), C.byref(need)), "hodlr_workspace_size")
+            self.ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+            if os.environ.get("HODLR_POISON") == "1":
+                self.ws.fill_(0xFF)    # NaN bytes: a read of memory no kernel wrote shows in the results
+            check(lib().hodlr_build_ws(ctx.h, arr, len(ops), C.byref(opts), C.c_void_p(self.ws.data_ptr()),
+                                       need.value, C.byref(self.h)), "hodlr_build_ws", ctx.h)
+        else:
+            check(lib().hodlr_build(ctx.h, arr, len(ops), C.byref(opts), C.byref(self.h)), "hodlr_build", ctx.h)
 
     def update_coefficients(self, ops):
         """New d+/d- samples (same n, alpha, dt, dx, shift): rebuild the
@@ -278,8 +305,9 @@ class HodlrMatrix:
 
     def close(self):
         if self.h:
-            lib().hodlr_destroy(self.h)
+            lib().hodlr_destroy(self.h)     # waits for the device: the workspace is free afterwards
             self.h = C.c_void_p()
+        self.ws = None
 
     def __del__(self):
         try:
@@ -296,8 +324,11 @@ class Fde2dPlan:
     """Shifted HODLR factor sets for A X + X B^T = C (eq. (sylv-timestepping))."""
 
     def __init__(self, ctx: Context, opx: dict, opy: dict, hopts: HodlrOpts, tol=1e-10, max_shifts=64,
-                 max_rank=32):
+                 max_rank=32, workspace: bool = True):
+        """workspace=True: torch allocates the plan's device memory (fde2d_plan_workspace_size bytes)
+        and the library builds the plan into it (fde2d_plan_create_ws)."""
         self.ctx = ctx
+        self.ws = None
         self.nx, self.ny = int(opx["n"]), int(opy["n"])
         ox = FdeOperator(self.nx, float(opx["alpha"]), float(opx["dt"]), float(opx["dx"]),
                          float(opx.get("shift", 0.5)), C.c_void_p(opx["d_plus"].data_ptr()),
@@ -307,8 +338,26 @@ class Fde2dPlan:
                          C.c_void_p(opy["d_minus"].data_ptr()))
         self.opts = Fde2dOpts(float(tol), int(max_shifts), int(max_rank))
         self.h = C.c_void_p()
-        check(lib().fde2d_plan_create(ctx.h, C.byref(ox), C.byref(oy), C.byref(hopts), C.byref(self.opts),
-                                      C.byref(self.h)), "fde2d_plan_create", ctx.h)
+        if workspace:
+            import torch
+            need = C.c_size_t()
+            check(lib().fde2d_plan_workspace_size(ctx.h, C.byref(ox), C.byref(oy), C.byref(hopts),
+                                                  C.byref(self.opts), C.byref(need)),
+                  "fde2d_plan_workspace_size", ctx.h)
+            self.ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+            check(lib().fde2d_plan_create_ws(ctx.h, C.byref(ox), C.byref(oy), C.byref(hopts), C.byref(self.opts),
+                                             C.c_void_p(self.ws.data_ptr()), need.value, C.byref(self.h)),
+                  "fde2d_plan_create_ws", ctx.h)
+        else:
+            check(lib().fde2d_plan_create(ctx.h, C.byref(ox), C.byref(oy), C.byref(hopts), C.byref(self.opts),
+                                          C.byref(self.h)), "fde2d_plan_create", ctx.h)
+
+    def counters(self, reset=False):
+        """Work counters (fde2d_plan_counters): dict of core_flops, dense_flops,
+        solve_bytes (one column, all shifted operators), shifts, rank."""
+        v = (C.c_double * 5)()
+        check(lib().fde2d_plan_counters(self.h, v, 5, 1 if reset else 0), "fde2d_plan_counters")
+        return dict(core_flops=v[0], dense_flops=v[1], solve_bytes=v[2], shifts=int(v[3]), rank=int(v[4]))
 
     def shifts(self):
         n = lib().fde2d_plan_shifts(self.h, None, None, 0)
@@ -357,8 +406,9 @@ class Fde2dPlan:
 
     def close(self):
         if self.h:
-            lib().fde2d_plan_destroy(self.h)
+            lib().fde2d_plan_destroy(self.h)    # its batches' destruction waits for the device
             self.h = C.c_void_p()
+        self.ws = None
 
     def __del__(self):
         try:

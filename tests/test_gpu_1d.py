@@ -64,6 +64,32 @@ def test_compressed_operator_matches_dense(H, ctx, n, alpha):
     assert err <= bound, (err, bound)
 
 
+@pytest.mark.parametrize("n", [2049, 4096])
+@pytest.mark.parametrize("alpha", [1.2, 1.5, 1.8])
+def test_operator_rank_near_dense_eps_rank(H, ctx, n, alpha):
+    """The off-diagonal rank of the compressed operator (Sec. 3.4.1: blocks
+    truncated at tau = eps ||M||_2, ||M||_2 taken from its lower bound
+    max_i M_ii = 1 + nu alpha max(d+ + d-)) is at most 2 above the dense
+    eps-rank of the top-level blocks at the same tau (dense SVD of the
+    oracle's M), and the compressed operator keeps its accuracy."""
+    p = W.var_1d(alpha, n=n)
+    eps = 1e-10
+    A = build(H, ctx, [p], tol=eps)
+    rA = A.info().max_rank_A
+    M = O.fd_matrix(alpha, n, p.nu, p.d_plus, p.d_minus)
+    tau = eps * (1 + p.nu * alpha * np.max(p.d_plus + p.d_minus))
+    n1 = n // 2
+    dense = max(O.eps_rank(M[n1:, :n1], tau), O.eps_rank(M[:n1, n1:], tau))
+    assert rA <= dense + 2, (rA, dense)
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, 2))
+    y = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+    A.matvec(dev(X.T).contiguous(), y, nrhs=2, ld=n)
+    err = np.linalg.norm(y.cpu().numpy().T - M @ X, 2)
+    assert err <= 20 * eps * np.linalg.norm(M, 2) * np.linalg.norm(X, 2)
+    print(f"n={n} alpha={alpha}: operator rank {rA}, dense eps-rank {dense}")
+
+
 @pytest.mark.parametrize("n", [1, 5, 300, 4096, 5000, 20000])
 @pytest.mark.parametrize("alpha", [1.1, 1.5, 1.9])
 def test_exact_operator_matches_double_double(H, ctx, n, alpha):
@@ -359,3 +385,49 @@ def test_pooled_blocks_give_identical_results(H, ctx):
                           for p, r in zip(probs, np.split(b, [probs[0].n]))])
     for prec in ("fp32", "fp64"):
         assert np.linalg.norm(seen[prec][0] - ref) <= 1e-9 * np.linalg.norm(ref), prec
+
+
+def test_workspace_build_equals_library_allocated(H, ctx):
+    """A batch built with hodlr_build_ws into a torch-allocated workspace (the
+    binding's default) that starts filled with NaN bytes gives the same exact
+    product, factors and refined
+    solution, bit for bit, as one the library allocates (hodlr_build); a
+    workspace one page short of hodlr_workspace_size is refused with
+    HODLR_EINVAL naming argument 6."""
+    import ctypes as C
+    from paper_1804_05522_amd import hodlr as HB
+    probs = [var_problem(3000, 1.5, seed=1), var_problem(777, 1.8, seed=2)]
+    ops = [H.operator_dict(p.n, p.alpha, p.dt, p.h, dev(p.d_plus), dev(p.d_minus)) for p in probs]
+    opts = H.default_opts(tol=1e-10, prec="fp32", refine_max=4, rtol=1e-12)
+    n = sum(p.n for p in probs)
+    rng = np.random.default_rng(5)
+    b = dev(rng.standard_normal(n))
+    outs = []
+    import os
+    for ws in (False, True):
+        os.environ["HODLR_POISON"] = "1" if ws else "0"   # the workspace starts as NaN bytes
+        try:
+            A = H.HodlrMatrix(ctx, ops, opts, workspace=ws)
+        finally:
+            os.environ.pop("HODLR_POISON", None)
+        y = torch.zeros(n, dtype=torch.float64, device="cuda")
+        A.toeplitz_matvec(b, y)
+        A.factor()
+        x = b.clone()
+        info = A.solve(x)
+        torch.cuda.synchronize()
+        assert info.used_fallback == 0
+        outs.append((y.cpu().numpy(), x.cpu().numpy(), A.info().max_rank_factors))
+        A.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+    L = H.lib()
+    arr = H.HodlrMatrix._op_array(ops)
+    need = C.c_size_t()
+    assert L.hodlr_workspace_size(arr, len(ops), C.byref(opts), C.byref(need)) == 0
+    short = torch.empty(need.value - 4096, dtype=torch.uint8, device="cuda")
+    h = C.c_void_p()
+    st = L.hodlr_build_ws(ctx.h, arr, len(ops), C.byref(opts), C.c_void_p(short.data_ptr()), need.value - 4096,
+                          C.byref(h))
+    assert st == HB.HODLR_EINVAL and L.hodlr_last_arg(ctx.h) == 6 and not h.value

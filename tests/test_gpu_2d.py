@@ -46,8 +46,8 @@ def test_sylvester_step_matches_bartels_stewart(H, ctx, n, variable):
     # smooth low-rank previous state (the solutions of these problems are smooth)
     Um = W.LowRank(np.stack([np.sin((k + 1) * np.pi * p.x) for k in range(3)], 1) * 0.1,
                    np.stack([p.y * (1 - p.y) * np.cos(k * np.pi * p.y) for k in range(3)], 1))
-    out = (torch.zeros((32, n), dtype=torch.float64, device="cuda"),
-           torch.zeros((32, n), dtype=torch.float64, device="cuda"))
+    out = (torch.zeros((64, n), dtype=torch.float64, device="cuda"),
+           torch.zeros((64, n), dtype=torch.float64, device="cuda"))
     r, info = P.step(lr_dev(Um.Z, Um.W), lr_dev(p.f.Z, p.f.W), p.dt, out, allow=(0, 2))
     X = out[0][:r].cpu().numpy().T @ out[1][:r].cpu().numpy()
     st = O2.SylvesterStepper(p)
@@ -68,8 +68,8 @@ def test_two_steps_in_a_row(H, ctx):
     U = np.zeros((n, n))
     cur = (torch.zeros((0, n), dtype=torch.float64, device="cuda"),) * 2
     for _ in range(2):
-        out = (torch.zeros((32, n), dtype=torch.float64, device="cuda"),
-               torch.zeros((32, n), dtype=torch.float64, device="cuda"))
+        out = (torch.zeros((64, n), dtype=torch.float64, device="cuda"),
+               torch.zeros((64, n), dtype=torch.float64, device="cuda"))
         r, info = P.step(cur, lr_dev(p.f.Z, p.f.W), p.dt, out, allow=(0, 2))
         cur = (out[0][:r].contiguous(), out[1][:r].contiguous())
         U = st.step(U, p.f.dense())
@@ -108,8 +108,8 @@ def test_sweep_graphs_replay_like_direct_launches(H):
         seq = []
         for k in range(4):
             with torch.cuda.stream(stream if mode == "graph" else torch.cuda.current_stream()):
-                out = (torch.zeros((32, p.nx), dtype=torch.float64, device="cuda"),
-                       torch.zeros((32, p.ny), dtype=torch.float64, device="cuda"))
+                out = (torch.zeros((64, p.nx), dtype=torch.float64, device="cuda"),
+                       torch.zeros((64, p.ny), dtype=torch.float64, device="cuda"))
                 r, info = P.step(cur, F, p.dt, out, allow=(0, 2))
                 torch.cuda.synchronize()
                 junk = torch.randn(1 << 16, device="cuda").sum()      # eager work between replays
@@ -123,3 +123,63 @@ def test_sweep_graphs_replay_like_direct_launches(H):
     for k, (a, b) in enumerate(zip(outs["direct"], outs["graph"])):
         assert a[0] == b[0] and a[1] == b[1], (k, a[:2], b[:2])
         assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]), k
+
+
+def test_workspace_plan_equals_library_allocated(H, ctx):
+    """A plan built into a torch-allocated workspace (fde2d_plan_create_ws, the
+    binding's default; shifted and unshifted batches and the sweeps' arrays all
+    carved from it) takes the same step, bit for bit, as a plan whose memory
+    the library allocates."""
+    n = 150
+    p = W.fd_2d(n=n, variable=True, dt=1 / 16)
+    opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5)
+    opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5)
+    res = []
+    for ws in (False, True):
+        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-12, prec="fp32", leaf=32), tol=1e-10, workspace=ws)
+        out = (torch.zeros((64, n), dtype=torch.float64, device="cuda"),
+               torch.zeros((64, n), dtype=torch.float64, device="cuda"))
+        zero = (torch.zeros((0, n), dtype=torch.float64, device="cuda"),) * 2
+        r, info = P.step(zero, lr_dev(p.f.Z, p.f.W), p.dt, out, allow=(0, 2))
+        torch.cuda.synchronize()
+        res.append((r, out[0][:r].cpu().numpy(), out[1][:r].cpu().numpy(), P.shifts()))
+        P.close()
+    assert res[0][0] == res[1][0] and res[0][3] == res[1][3]
+    assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][2], res[1][2])
+
+
+def test_mid_size_steps_with_the_benchmark_options(H, ctx):
+    """Two steps of the 2D workload at n = 1024 with the benchmark's options
+    (FP32 factors, HODLR tolerance 1e-10, leaf 64, step tolerance 1e-10),
+    against the oracle's Bartels-Stewart trajectory: the relative forward
+    error (Frobenius) and the normwise backward error
+    ||R||_F / ((||A||_2 + ||B||_2) ||X||_F + ||C||_F) of each GPU step, with
+    R = C - A X - X B^T formed densely from the oracle's A and B, are both
+    below 1e-10, and the step reports ||R||_F / ||C||_F as the test finds it."""
+    n = 1024
+    p = W.fd_2d(n=n, variable=True, dt=1 / 64)
+    opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5)
+    opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5)
+    P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec="fp32"), tol=1e-10)
+    st = O2.SylvesterStepper(p)
+    na, nb = np.linalg.norm(st.A, 2), np.linalg.norm(st.B, 2)
+    U = np.zeros((n, n))
+    cur = (torch.zeros((0, n), dtype=torch.float64, device="cuda"),) * 2
+    for k in range(2):
+        out = (torch.zeros((64, n), dtype=torch.float64, device="cuda"),
+               torch.zeros((64, n), dtype=torch.float64, device="cuda"))
+        r, info = P.step(cur, lr_dev(p.f.Z, p.f.W), p.dt, out)
+        X = out[0][:r].cpu().numpy().T @ out[1][:r].cpu().numpy()
+        C = U + p.dt * p.f.dense()
+        U = st.solve(C)
+        err = np.linalg.norm(X - U) / np.linalg.norm(U)
+        R = O2.residual(st.A, st.B, X, C)
+        res = np.linalg.norm(R) / np.linalg.norm(C)
+        eta = np.linalg.norm(R) / ((na + nb) * np.linalg.norm(X) + np.linalg.norm(C))
+        print(f"n={n} step {k + 1}: status {info.status} rank {r} adi {info.refine_iters} "
+              f"rel.err {err:.2e} backward error {eta:.2e} (reported {info.backward_error:.2e}) "
+              f"||R||/||C|| {res:.2e} (reported {info.rel_residual:.2e}) correction {info.rel_correction:.2e}")
+        assert err <= 1e-10 and eta <= 1e-10, (err, eta)
+        assert abs(info.rel_residual - res) <= 0.05 * res + 1e-14, (info.rel_residual, res)
+        cur = (out[0][:r].contiguous(), out[1][:r].contiguous())
+    P.close()

@@ -63,8 +63,8 @@ def setup(H):
 
 
 def newout():
-    return (torch.zeros((32, N), dtype=torch.float64, device="cuda"),
-            torch.zeros((32, N), dtype=torch.float64, device="cuda"))
+    return (torch.zeros((64, N), dtype=torch.float64, device="cuda"),
+            torch.zeros((64, N), dtype=torch.float64, device="cuda"))
 
 
 def dense(lr):
