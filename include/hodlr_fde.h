@@ -207,6 +207,21 @@ hodlr_status hodlr_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y
 hodlr_status hodlr_toeplitz_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y,
                                    int nrhs, int64_t ld);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the product of
+ * hodlr_toeplitz_matvec, same arguments, same results, with its transform
+ * scratch in a static device array of the library (16 MiB per GPU, held until
+ * the process ends) instead of the handle's own scratch; columns go one at a
+ * time.  Allocates nothing.  The matrix must need at most 16 MiB of packed
+ * scratch (2 M complex doubles per problem, M the power of two >= 2n - 1: for
+ * example two problems of 65536 rows, or one of 262144), else HODLR_EINVAL
+ * (argument 2) and a
+ * message on stderr.  All calls on one GPU share its array: calls that overlap
+ * on one GPU (two streams, two host threads) race and must be serialised by
+ * the caller. */
+hodlr_status hodlr_toeplitz_matvec_noalloc(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y,
+                                           int nrhs, int64_t ld);
+
 /* HODLR LU of every operator (Sec. 3.5): block LU with leaf partial pivoting,
  * low-rank Schur-complement updates recompressed to the truncation
  * tolerance, plus the HODLR inverses of both triangular factors. */

@@ -120,6 +120,14 @@ struct TimerScope {
   }
 };
 
+// Transform scratch of hodlr_toeplitz_matvec_noalloc, for callers that cannot
+// allocate device memory: one packed column of 2M complex values per problem
+// (at most kNoallocScratchBytes in all).  Every GPU the library runs on holds
+// its own copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) double2 scratch[kNoallocScratchBytes / sizeof(double2)];
+
 namespace {
 
 constexpr int kNCF = 16;     // columns per FFT launch group
@@ -946,8 +954,33 @@ const char* hodlr_status_string(hodlr_status s) {
   return "unknown status";
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+static hodlr_status scratch_address(void** out) {
+  static std::mutex mu;
+  static void* addr[256] = {};
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 256) return HODLR_EHIP;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      fprintf(stderr, "hodlr_fde: hipGetSymbolAddress(scratch) failed on device %d: %s\n", dev,
+              hipGetErrorString(e));
+      return HODLR_EHIP;
+    }
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return HODLR_OK;
+}
+
 hodlr_status hodlr_ctx_create(hodlr_ctx* ctx, void* hip_stream) {
   if (!ctx) return HODLR_EINVAL;
+  void* sp = nullptr;
+  TRY(scratch_address(&sp));   // the no-allocation entry point's scratch on this device
   hodlr_ctx c = new (std::nothrow) hodlr_ctx_s;
   if (!c) return HODLR_ENOMEM;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -1647,6 +1680,32 @@ hodlr_status hodlr_toeplitz_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, 
   if (ld < m->total_n) return set_arg(ctx, 6);
   if (x == y) return set_arg(ctx, 4);
   launch_fft_matvec(m, x, ld, y, ld, nullptr, 0, nrhs, ctx->stream);
+  HIP_TRY(hipGetLastError());
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_toeplitz_matvec_noalloc(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y, int nrhs,
+                                           int64_t ld) {
+  if (!ctx) return HODLR_EINVAL;
+  TimerScope ts_(ctx);
+  if (!m) return set_arg(ctx, 2);
+  if (!x) return set_arg(ctx, 3);
+  if (!y) return set_arg(ctx, 4);
+  if (nrhs < 1) return set_arg(ctx, 5);
+  if (ld < m->total_n) return set_arg(ctx, 6);
+  if (x == y) return set_arg(ctx, 4);
+  if (size_t(m->fws_packed) * sizeof(double2) > kNoallocScratchBytes) {
+    fprintf(stderr, "hodlr_fde: hodlr_toeplitz_matvec_noalloc: the matrix needs %lld bytes of transform scratch, "
+                    "above the static maximum of %zu\n",
+            (long long)(size_t(m->fws_packed) * sizeof(double2)), kNoallocScratchBytes);
+    return set_arg(ctx, 2);
+  }
+  void* sp = nullptr;
+  TRY(scratch_address(&sp));
+  DevPtrs Ps = m->P;
+  Ps.fws = static_cast<double2*>(sp);
+  Ps.fws_compact = 1;
+  launch_fft_matvec_p(m, Ps, x, ld, y, ld, nullptr, 0, nrhs, ctx->stream);
   HIP_TRY(hipGetLastError());
   return HODLR_OK;
 }

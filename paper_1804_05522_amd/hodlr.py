@@ -27,7 +27,7 @@ EXPORTS = [
     "fde2d_sylvester_step_guess", "fde2d_field_from_lr", "fde2d_compress_field", "hodlr_autotune",
     "hodlr_set_tuning", "hodlr_update_coefficients",
     "fde_net_param_count", "fde_net_create", "fde_net_destroy", "fde_net_set_params", "fde_net_get_params",
-    "fde_net_get_grads", "fde_net_forward", "fde_net_train_step",
+    "fde_net_get_grads", "fde_net_forward", "fde_net_train_step", "hodlr_toeplitz_matvec_noalloc",
     "hodlr_workspace_size", "hodlr_build_ws", "fde2d_plan_workspace_size", "fde2d_plan_create_ws",
     "fde2d_plan_counters",
 ]
@@ -99,6 +99,7 @@ def lib():
         L.hodlr_get_info.argtypes = [vp, C.POINTER(HodlrMatInfo)]
         L.hodlr_matvec.argtypes = [vp, vp, vp, vp, i32, i64]
         L.hodlr_toeplitz_matvec.argtypes = [vp, vp, vp, vp, i32, i64]
+        L.hodlr_toeplitz_matvec_noalloc.argtypes = [vp, vp, vp, vp, i32, i64]
         L.hodlr_factor.argtypes = [vp, vp, C.POINTER(HodlrInfo)]
         L.hodlr_solve.argtypes = [vp, vp, vp, i32, i64, C.POINTER(HodlrInfo)]
         L.hodlr_time_steps.argtypes = [vp, vp, vp, vp, dbl, i32, C.POINTER(HodlrInfo)]
@@ -288,6 +289,12 @@ class HodlrMatrix:
         check(lib().hodlr_toeplitz_matvec(self.ctx.h, self.h, C.c_void_p(x.data_ptr()),
                                           C.c_void_p(y.data_ptr()), nrhs, ld),
               "hodlr_toeplitz_matvec", self.ctx.h)
+
+    def toeplitz_matvec_noalloc(self, x, y, nrhs=1, ld=None):
+        ld = self.total_n if ld is None else ld
+        check(lib().hodlr_toeplitz_matvec_noalloc(self.ctx.h, self.h, C.c_void_p(x.data_ptr()),
+                                                  C.c_void_p(y.data_ptr()), nrhs, ld),
+              "hodlr_toeplitz_matvec_noalloc", self.ctx.h)
 
     def solve(self, x, nrhs=1, ld=None, allow=(HODLR_OK,)) -> HodlrInfo:
         ld = self.total_n if ld is None else ld
