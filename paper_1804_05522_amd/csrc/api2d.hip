@@ -973,8 +973,9 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
       // about the factors' precision, which the first sweep cannot go below:
       // it stops there, and the corrections (whose residuals are exact) take
       // the solution the rest of the way.
+      // The sweeps aim one decade below the tolerance (relative to ||C||).
       const int fp = P->mat->opts.prec;
-      const double first = fp == HODLR_FP64 ? tol : std::max(tol, fp == HODLR_MIXED_FP32 ? 1e-6 : 1e-3);
+      const double first = fp == HODLR_FP64 ? 0.1 * tol : std::max(0.1 * tol, fp == HODLR_MIXED_FP32 ? 1e-6 : 1e-3);
       int steps = 0, dpar = 0;
       TRY(adi_sweep(P, rc, first * std::max(cnorm, 1e-300), steps, dpar, s));
       total_steps += steps;
