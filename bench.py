@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=2, help="timed jobs")
     ap.add_argument("--warmup", type=int, default=1, help="untimed jobs")
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--workload", default="var_1d", choices=["var_1d", "batched_1d", "fd_2d", "timedep_1d"],
+    ap.add_argument("--workload", default="var_1d",
+                    choices=["var_1d", "batched_1d", "fd_2d", "timedep_1d", "learned_2d"],
                     help="var_1d: the headline job (default); batched_1d: 256 ragged problems; "
                          "fd_2d: 4096^2 Sylvester time stepping; timedep_1d: the 256 ragged problems "
                          "with coefficients that change every step (rebuild + factor + solve per step)")
@@ -51,6 +52,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-2d", action="store_true", help="var_1d only: skip the 2D 4096^2 sub-object")
+    ap.add_argument("--gmres", type=int, default=0,
+                    help="1D: refinement sweeps as GMRES-IR cycles of this many iterations (0: plain sweeps)")
     ap.add_argument("--target", type=float, default=1e-10)
     ap.add_argument("--pmc-job", action="store_true",
                     help="for hardware-counter runs: one job of the workload with 8 time steps at the "
@@ -79,6 +82,8 @@ def main():
         return bench_2d(args, ctx, stream)
     if args.workload == "timedep_1d":
         return bench_timedep(args, ctx, stream)
+    if args.workload == "learned_2d":
+        return bench_learned(args, ctx, stream)
     if args.workload == "batched_1d":
         probs = W.batched_1d()
         args.no_cpu = True          # the CPU oracle baseline is taken on the headline job only
@@ -96,7 +101,8 @@ def main():
     def job(prec, sweeps, timing=None, steps=None):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
-        A = H.HodlrMatrix(ctx, ops, H.default_opts(tol=1e-10, prec=prec, refine_max=sweeps, rtol=args.target))
+        A = H.HodlrMatrix(ctx, ops, H.default_opts(tol=1e-10, prec=prec, refine_max=sweeps, rtol=args.target,
+                                                   gmres_m=args.gmres if prec != "fp64" else 0))
         ev[1].record(stream)
         A.factor(allow=(0, 3))
         ev[2].record(stream)
@@ -223,6 +229,7 @@ def main():
         "phases_ms": {"build": main_res["build_ms"], "factor": main_res["factor_ms"], "time_steps": main_res["steps_ms"]},
         "per_step_us": 1e3 * main_res["steps_ms"] / K,
         "refine_sweeps_per_step": main_res["sweeps"],
+        "gmres_iterations_per_sweep": args.gmres,
         "rel_correction_worst_step": main_res["rel_correction"],
         "fp64_fallback": bool(main_res["used_fallback"]),
         "rank_A": main_res["rank_A"], "rank_factors": main_res["rank_factors"],
@@ -405,6 +412,125 @@ def bench_2d(args, ctx, stream):
     out = run_2d(args, ctx, stream, cpu=not args.no_cpu, compare=not args.no_compare)
     out.update({"n_gpus": 1, "scaling": "weak", "vs_baseline": None, "data": "synthetic"})
     out["config"].update({"global_batch": 1, "parallelism": "single GPU"})
+    print(json.dumps(out), flush=True)
+
+
+def bench_learned(args, ctx, stream, pairs=10000, traj_len=50, crops=4, crop=256, held_out=4, eval_steps=8):
+    """Learned warm start at its configuration: 2048^2, alpha = (1.4, 1.6),
+    d = 1, f = 0, dt = 1/64, step tolerance 1e-8.  Training pairs (u_k, u_{k+1})
+    come on the fly from HODLR trajectories (random initial conditions: sums of
+    8 separable Gaussians, FP64 factors): each pair's fields are expanded on the
+    GPU and `crops` random 256^2 crops of it make one Adam step of the BF16
+    network (the library's kernels).  Then, on held-out trajectories, every
+    step is solved cold and warm (the network's prediction of u_{k+1} from the
+    cold u_k, compressed, as the first iterate): the prediction errors, the
+    guesses' residuals rho = ||C - A X0 - X0 B^T|| / ||C|| (the quantity the
+    solver's acceptance test reads), how many guesses were taken, the ADI steps
+    and times of both starts, and the difference between the two solutions."""
+    import numpy as np
+    import torch
+
+    import paper_1804_05522_amd as H
+    import workloads as W
+    n = 2048
+    p0 = W.learned_2d(n=n, seed=0)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    opx = H.operator_dict(n, p0.alpha_x, p0.dt, p0.hx, dev(p0.dxp), dev(p0.dxm), 0.5)
+    opy = H.operator_dict(n, p0.alpha_y, p0.dt, p0.hy, dev(p0.dyp), dev(p0.dym), 0.5)
+    P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-12, prec="fp64"), tol=1e-8)
+    zero = (torch.zeros((0, n), dtype=torch.float64, device="cuda"),) * 2
+    outs = [(torch.zeros((64, n), dtype=torch.float64, device="cuda"),
+             torch.zeros((64, n), dtype=torch.float64, device="cuda")) for _ in range(2)]
+    fields = [torch.zeros((n, n), dtype=torch.float32, device="cuda") for _ in range(2)]
+    rng = np.random.default_rng(7)
+    # He initialisation of the four 3x3 convolutions (1 -> 32 -> 32 -> 32 -> 1),
+    # the last layer small so that the first predictions are about u_k
+    params = []
+    for li, (o, c) in enumerate([(32, 1), (32, 32), (32, 32), (1, 32)]):
+        std = np.sqrt(2.0 / (9 * c)) * (1e-2 if li == 3 else 1.0)
+        params += [rng.normal(0.0, std, (o, c, 3, 3)).ravel(), np.zeros(o)]
+    net = H.ConvNet(ctx, bf16=True, max_pixels=max(crops * crop * crop, n * n))
+    net.set_params(np.concatenate(params).astype(np.float32))
+
+    def start(seed):
+        p = W.learned_2d(n=n, seed=seed)
+        return p, (dev(p.u0.Z.T.copy()), dev(p.u0.W.T.copy()))
+
+    t0 = time.perf_counter()
+    made, seed, losses = 0, 1000, []
+    while made < pairs:
+        p, cur = start(seed)
+        seed += 1
+        P.to_field(cur, fields[0])
+        for k in range(min(traj_len, pairs - made)):
+            out = outs[k % 2]
+            r, _ = P.step(cur, zero, p.dt, out, allow=(0, 2))
+            cur = (out[0][:r], out[1][:r])
+            P.to_field(cur, fields[(k + 1) % 2])
+            a, b = fields[k % 2], fields[(k + 1) % 2]
+            ii = rng.integers(0, n - crop, crops)
+            jj = rng.integers(0, n - crop, crops)
+            u = torch.stack([a[i:i + crop, j:j + crop] for i, j in zip(ii, jj)]).contiguous()
+            tg = torch.stack([b[i:i + crop, j:j + crop] for i, j in zip(ii, jj)]).contiguous()
+            lr = 1e-3 if made < 0.7 * pairs else 2e-4
+            losses.append(net.train_step(u, tg, margin=4, lr=lr))
+            made += 1
+    stream.synchronize()
+    t_train = time.perf_counter() - t0
+    # held-out trajectories: cold and warm steps side by side
+    pred = torch.zeros((1, n, n), dtype=torch.float32, device="cuda")
+    g = (torch.zeros((10, n), dtype=torch.float64, device="cuda"),
+         torch.zeros((10, n), dtype=torch.float64, device="cuda"))
+    warm_out = (torch.zeros((64, n), dtype=torch.float64, device="cuda"),
+                torch.zeros((64, n), dtype=torch.float64, device="cuda"))
+    e_net, e_id, rho, adi_c, adi_w, ms_c, ms_w, diff, used = [], [], [], [], [], [], [], [], 0
+    nxt = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    cw = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    for h in range(held_out):
+        p, cur = start(900 + h)
+        for k in range(eval_steps):
+            P.to_field(cur, fields[0])
+            net.forward(fields[0][None], pred)
+            stream.synchronize()
+            ta = time.perf_counter()
+            r, info_c = P.step(cur, zero, p.dt, outs[0], allow=(0, 2))
+            stream.synchronize()
+            tb = time.perf_counter()
+            rg = P.compress_field(pred[0].contiguous(), 1e-2, g, seed=k + 1)
+            rw, info_w = P.step(cur, zero, p.dt, warm_out, allow=(0, 2), guess=g, guess_rank=rg)
+            stream.synchronize()
+            tc = time.perf_counter()
+            P.to_field((outs[0][0][:r], outs[0][1][:r]), nxt)
+            P.to_field((warm_out[0][:rw], warm_out[1][:rw]), cw)
+            nn_ = float(torch.linalg.norm(nxt))
+            e_net.append(float(torch.linalg.norm(pred[0] - nxt)) / nn_)
+            e_id.append(float(torch.linalg.norm(fields[0] - nxt)) / nn_)
+            diff.append(float(torch.linalg.norm(cw - nxt)) / nn_)
+            used += 0 if info_w.used_fallback else 1
+            adi_c.append(info_c.refine_iters)
+            adi_w.append(info_w.refine_iters)
+            ms_c.append(1e3 * (tb - ta))
+            ms_w.append(1e3 * (tc - tb))
+            rho.append(info_w.guess_residual)
+            cur = (outs[0][0][:r].clone(), outs[0][1][:r].clone())
+    J = len(P.shifts()[0])
+    P.close()
+    net.close()
+    out = {
+        "metric": "learned warm start (2D 2048^2, step tolerance 1e-8): ADI steps warm vs cold",
+        "value": float(np.mean(adi_c)) / max(float(np.mean(adi_w)), 1e-30), "unit": "cold/warm ADI steps",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f64 solves, bf16 network", "data": "synthetic",
+        "config": {"workload": f"learned_2d {n}x{n} alpha=(1.4,1.6) d=1 f=0 dt=1/64 tol=1e-8; {pairs} training "
+                               f"pairs from {seed - 1000} HODLR trajectories, {crops} crops of {crop}^2 a pair"},
+        "train_s": t_train, "loss_first_100": float(np.mean(losses[:100])), "loss_last_100": float(np.mean(losses[-100:])),
+        "held_out_steps": len(adi_c), "guesses_used": used,
+        "prediction_error_net_mean": float(np.mean(e_net)), "prediction_error_identity_mean": float(np.mean(e_id)),
+        "guess_residual_median": float(np.median(rho)), "guess_residual_min": float(np.min(rho)),
+        "acceptance_threshold": (0.1 * 1e-8) ** (4.0 / max(J, 4)), "shift_pairs": J,
+        "adi_cold_mean": float(np.mean(adi_c)), "adi_warm_mean": float(np.mean(adi_w)),
+        "ms_cold_mean": float(np.mean(ms_c)), "ms_warm_mean": float(np.mean(ms_w)),
+        "warm_vs_cold_max_rel_diff": float(np.max(diff)),
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -81,6 +81,9 @@ typedef struct {
   int max_rank;           /* cap on every off-diagonal rank, <= 32 */
   int refine_max;         /* max FP64 refinement sweeps per solve (any precision; 0 = plain solve) */
   double rtol;            /* refinement target ||d||_2 / ||x||_2 for the last correction d */
+  int gmres_m;            /* 0: each refinement sweep is d = M_low^{-1} r, x += d; 1..16: each sweep is a
+                             cycle of gmres_m GMRES iterations on M d = r, right-preconditioned by the solve
+                             with the stored (reduced-precision) factors (GMRES-IR), x += d */
 } hodlr_opts;
 
 typedef struct {
@@ -96,6 +99,8 @@ typedef struct {
   double backward_error;  /* 2D step: ||R||_F / ((a + b) ||X||_F + ||C||_F), R = C - A X - X B^T, with
                              a <= ||A||_2, b <= ||B||_2 the largest diagonal entries of A and B, so an upper
                              bound of the normwise backward error; 0 in 1D */
+  double guess_residual;  /* 2D step with a first guess X0: ||C - A X0 - X0 B^T||_F / ||C||_F, the figure
+                             its acceptance test reads; 0 otherwise */
 } hodlr_info;
 
 typedef struct {

@@ -189,6 +189,11 @@ struct hodlr_mat_s {
   double* step_worst = nullptr;   // batch: worst relative correction of the steps since the last clear
   double* host_worst = nullptr;   // pinned host copy of step_worst
   int step_slices = 0;
+  // GMRES-IR (opts.gmres_m > 0): basis V (total_n x (kGmMax + 1)), preconditioned
+  // vectors Z (total_n x kGmMax), per-problem small arrays
+  double* gmV = nullptr;
+  double* gmZ = nullptr;
+  GmState gms{};
   bool factored = false;
   int max_rank_factors = 0;
   int max_rank_A = 0;
@@ -1022,6 +1027,7 @@ hodlr_status hodlr_default_opts(hodlr_opts* o) {
   o->max_rank = 32;
   o->refine_max = 0;
   o->rtol = 1e-12;
+  o->gmres_m = 0;
   return HODLR_OK;
 }
 
@@ -1125,6 +1131,7 @@ static hodlr_status build_impl(hodlr_ctx ctx, const fde_operator* ops, int batch
   if (opts->leaf < 16 || opts->leaf > kMaxLeaf) return set_arg(ctx, 4);
   if (!(opts->tol > 0.0) || opts->max_rank < 1 || opts->max_rank > kRS) return set_arg(ctx, 4);
   if (opts->prec < HODLR_FP64 || opts->prec > HODLR_MIXED_BF16) return set_arg(ctx, 4);
+  if (opts->gmres_m < 0 || opts->gmres_m > kGmMax) return set_arg(ctx, 4);
   for (int i = 0; i < batch; ++i) {
     const fde_operator& o = ops[i];
     // the solve and product kernels address a level's factor block (n x 32
@@ -1294,6 +1301,21 @@ static hodlr_status build_impl(hodlr_ctx ctx, const fde_operator* ops, int batch
   ALLOC(m->ukeep, row0);
   ALLOC(m->step_part, size_t(batch) * m->step_slices);
   ALLOC(m->step_worst, batch);
+  if (opts->gmres_m > 0) {
+    static_assert(kGmRows == kStepRows, "GMRES row kernels share the step kernels' slices");
+    GmState& G = m->gms;
+    G.slices = m->step_slices;
+    ALLOC(m->gmV, row0 * (kGmMax + 1));
+    ALLOC(m->gmZ, row0 * kGmMax);
+    ALLOC(G.H, size_t(batch) * (kGmMax + 1) * kGmMax);
+    ALLOC(G.g, size_t(batch) * (kGmMax + 1));
+    ALLOC(G.cs, size_t(batch) * kGmMax);
+    ALLOC(G.sn, size_t(batch) * kGmMax);
+    ALLOC(G.y, size_t(batch) * kGmMax);
+    ALLOC(G.h1, size_t(G.slices) * batch * (kGmMax + 1));
+    ALLOC(G.h2, size_t(G.slices) * batch * (kGmMax + 1));
+    ALLOC(G.nrm, size_t(G.slices) * batch);
+  }
   ALLOC(m->fft_row_units, ur.size());
   ALLOC(m->fft_small_units, us.size());
   ALLOC(m->fft_p1_units, u1.size());
@@ -1866,6 +1888,36 @@ hodlr_status hodlr_factor(hodlr_ctx ctx, hodlr_mat m, hodlr_info* info) {
   return res;
 }
 
+// One GMRES-IR cycle for one column: d (into m->dbuf) from gmres_m
+// iterations on M d = b - M x, right-preconditioned by the solve with the
+// factors of precision p; the exact residual and products in FP64.
+static void gmres_cycle(hodlr_mat m, int p, const double* b, const double* x, hipStream_t s) {
+  const int64_t tn = m->total_n;
+  const int M = m->opts.gmres_m, B = m->batch;
+  const dim3 grid(m->step_slices, B), one(unsigned((B + 255) / 256));
+  GmState& G = m->gms;
+  double* V = m->gmV;
+  double* Z = m->gmZ;
+  launch_fft_matvec(m, x, tn, m->rbuf, tn, b, tn, 1, s);                      // r = b - M x
+  HFDE_LAUNCH(k_gm_norm2, grid, dim3(256), 0, s, m->P, m->rbuf, G, B);
+  HFDE_LAUNCH(k_gm_normalize, grid, dim3(256), 0, s, m->P, m->rbuf, V, G, B, -1);
+  for (int j = 0; j < M; ++j) {
+    double* vj = V + int64_t(j) * tn;
+    double* zj = Z + int64_t(j) * tn;
+    launch_solve(m, p, vj, tn, zj, tn, 1, s);                                  // z_j = M_low^{-1} v_j
+    launch_fft_matvec(m, zj, tn, m->dbuf, tn, nullptr, 0, 1, s);               // w = M z_j
+    HFDE_LAUNCH(k_gm_dots, grid, dim3(256), 0, s, m->P, V, tn, j, m->dbuf, G.h1, B);
+    HFDE_LAUNCH(k_gm_subtract, grid, dim3(256), 0, s, m->P, V, tn, j, m->dbuf, G.h1, G, B);
+    HFDE_LAUNCH(k_gm_dots, grid, dim3(256), 0, s, m->P, V, tn, j, m->dbuf, G.h2, B);
+    HFDE_LAUNCH(k_gm_subtract, grid, dim3(256), 0, s, m->P, V, tn, j, m->dbuf, G.h2, G, B);
+    HFDE_LAUNCH(k_gm_norm2, grid, dim3(256), 0, s, m->P, m->dbuf, G, B);
+    HFDE_LAUNCH(k_gm_normalize, grid, dim3(256), 0, s, m->P, m->dbuf, V + int64_t(j + 1) * tn, G, B, j);
+    HFDE_LAUNCH(k_gm_givens, one, dim3(256), 0, s, G, B, j);
+  }
+  HFDE_LAUNCH(k_gm_solve_y, one, dim3(256), 0, s, G, B, M);
+  HFDE_LAUNCH(k_gm_combine, grid, dim3(256), 0, s, m->P, Z, tn, M, G, m->dbuf);  // d = Z y
+}
+
 // x <- M_p^{-1} b (b in m->bbuf, cn columns), then FP64 refinement sweeps
 // r = b - M x (exact), d = M_p^{-1} r, x += d, until ||d|| <= rtol ||x|| for
 // every problem and column (the correction estimates the forward error; the
@@ -1882,9 +1934,14 @@ static int sweep_solve(hodlr_mat m, int p, int maxsw, double* xc, int64_t ld, in
   double prev = 1e300;
   std::vector<double> h(4 * nb_off);
   rel_r = rel_d = 1e300;
+  const bool gm = m->opts.gmres_m > 0 && cn == 1;
   for (int sweep = 0; sweep < maxsw; ++sweep) {
-    launch_fft_matvec(m, xc, ld, m->rbuf, tn, m->bbuf, tn, cn, s);
-    launch_solve(m, p, m->rbuf, tn, m->dbuf, tn, cn, s);
+    if (gm) {
+      gmres_cycle(m, p, m->bbuf, xc, s);                          // d in dbuf, r in rbuf
+    } else {
+      launch_fft_matvec(m, xc, ld, m->rbuf, tn, m->bbuf, tn, cn, s);
+      launch_solve(m, p, m->rbuf, tn, m->dbuf, tn, cn, s);
+    }
     launch_axpby(tn, cn, 1.0, xc, ld, 1.0, m->dbuf, tn, xc, ld, s);
     launch_norms(m, m->rbuf, tn, cn, nrm, s);
     launch_norms(m, m->dbuf, tn, cn, nrm + 2 * nb_off, s);
@@ -1921,8 +1978,10 @@ hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_
   int iters = 0;
   double worst = 0.0, worst_d = 0.0;
   bool fallback = false;
-  for (int c0 = 0; c0 < nrhs; c0 += kNCS) {
-    const int cn = std::min(kNCS, nrhs - c0);
+  // GMRES-IR refines one column at a time, in place in a total_n-row copy
+  const int group = m->opts.gmres_m > 0 && m->opts.refine_max > 0 ? 1 : kNCS;
+  for (int c0 = 0; c0 < nrhs; c0 += group) {
+    const int cn = std::min(group, nrhs - c0);
     double* xc = x + int64_t(c0) * ld;
     const int64_t tn = m->total_n;
     if (m->opts.refine_max <= 0) {
@@ -1962,7 +2021,7 @@ hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_
 
 // One implicit Euler step at the stored precision with a fixed number of
 // refinement sweeps: b = u + fscale f, u = M_low^{-1} b, then `sweeps` times
-// r = b - M u (exact), d = M_low^{-1} r, u += d.  With sweeps > 0 the last
+// r = b - M u (exact), d = M_low^{-1} r (or a GMRES-IR cycle), u += d.  With sweeps > 0 the last
 // update also folds the step's ||d||/||u|| into m->step_worst.  No host
 // synchronisation: the sequence is what a time-step graph captures.
 static void record_step(hodlr_mat m, double* u, const double* f, double fscale, int sweeps, hipStream_t s) {
@@ -1973,8 +2032,12 @@ static void record_step(hodlr_mat m, double* u, const double* f, double fscale, 
   else launch_axpby(tn, 1, 1.0, u, tn, 0.0, u, tn, m->bbuf, tn, s);
   launch_solve(m, prec, m->bbuf, tn, u, tn, 1, s);
   for (int q = 0; q < sweeps; ++q) {
-    launch_fft_matvec(m, u, tn, m->rbuf, tn, m->bbuf, tn, 1, s);
-    launch_solve(m, prec, m->rbuf, tn, m->dbuf, tn, 1, s);
+    if (m->opts.gmres_m > 0) {
+      gmres_cycle(m, prec, m->bbuf, u, s);     // d in dbuf
+    } else {
+      launch_fft_matvec(m, u, tn, m->rbuf, tn, m->bbuf, tn, 1, s);
+      launch_solve(m, prec, m->rbuf, tn, m->dbuf, tn, 1, s);
+    }
     if (q + 1 < sweeps) {
       launch_axpby(tn, 1, 1.0, u, tn, 1.0, m->dbuf, tn, u, tn, s);
     } else {

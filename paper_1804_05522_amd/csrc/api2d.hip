@@ -869,7 +869,7 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
   // from X_main; the residual C - A X - X B^T of the sum is formed entry by
   // entry (dense_norm), which resolves it to about u times its terms.
   int xpar = 0, kpar = 0, total_steps = 0, sweeps = 0;
-  double rel_res = 1.0, rel_corr = 0.0, eta = 1.0;
+  double rel_res = 1.0, rel_corr = 0.0, eta = 1.0, guess_res = 0.0;
   bool warm = false, fallback = false;
   // R = C - A X - X B^T for X = X_main + X_corr: its norm relative to
   // ||C||_F, and the normwise backward error eta (||A||_2, ||B||_2 replaced by
@@ -948,6 +948,7 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
     }
     double rel0 = 0.0;
     TRY(residual(rel0));
+    guess_res = rel0;
     // The J shifts reduce a residual by about 0.1 tol, i.e. by
     // (0.1 tol)^(1/J) per shift.  The guess is worth taking only if its
     // residual saves at least one block of four shifts (the sweep tests for
@@ -1073,6 +1074,7 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
     info->rel_residual = rel_res;
     info->rel_correction = rel_corr;
     info->backward_error = eta;
+    info->guess_residual = guess_res;
     info->max_rank = rx + rk;
     info->leaf = -1;
     info->row = -1;

@@ -6,6 +6,7 @@
 #include "factor.hip"
 #include "factor_mwg.hip"
 #include "solve.hip"
+#include "gmres.hip"
 #include "fft.hip"
 #include "adi.hip"
 #include "convnet.hip"

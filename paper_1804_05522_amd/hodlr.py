@@ -40,13 +40,14 @@ class FdeOperator(C.Structure):
 
 class HodlrOpts(C.Structure):
     _fields_ = [("leaf", C.c_int), ("tol", C.c_double), ("prec", C.c_int), ("max_rank", C.c_int),
-                ("refine_max", C.c_int), ("rtol", C.c_double)]
+                ("refine_max", C.c_int), ("rtol", C.c_double), ("gmres_m", C.c_int)]
 
 
 class HodlrInfo(C.Structure):
     _fields_ = [("status", C.c_int), ("refine_iters", C.c_int), ("rel_residual", C.c_double),
                 ("max_rank", C.c_int), ("leaf", C.c_int), ("row", C.c_int),
-                ("used_fallback", C.c_int), ("rel_correction", C.c_double), ("backward_error", C.c_double)]
+                ("used_fallback", C.c_int), ("rel_correction", C.c_double), ("backward_error", C.c_double),
+                ("guess_residual", C.c_double)]
 
 
 class HodlrMatInfo(C.Structure):
