@@ -475,6 +475,9 @@ def bench_learned(args, ctx, stream, pairs=10000, traj_len=50, crops=4, crop=256
             lr = 1e-3 if made < 0.7 * pairs else 2e-4
             losses.append(net.train_step(u, tg, margin=4, lr=lr))
             made += 1
+            if made % 1000 == 0:
+                print(f"learned_2d: {made} training pairs, loss {np.mean(losses[-100:]):.3e}, "
+                      f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
     stream.synchronize()
     t_train = time.perf_counter() - t0
     # held-out trajectories: cold and warm steps side by side
