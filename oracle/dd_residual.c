@@ -5,6 +5,9 @@
  *
  * r = b - (s I + nu (D+ T + D- T^T)) x, with T the lower Hessenberg Toeplitz
  * matrix of eq. (toeplitz_FD): T_ij = -g_{i-j+1} for j <= i+1, else 0.
+ * With mass_c != 0 the shift term is s (I + mass_c (S + S^T)), S the shift
+ * by one row: the mass matrix of the finite-element scheme (Sec. 2.2.2),
+ * 2/3 on the diagonal and 1/6 beside it, is (2/3)(I + (S + S^T)/4).
  *   (T x)_i   = -sum_{j <= i+1} g_{i-j+1} x_j
  *   (T^T x)_i = -sum_{j >= i-1} g_{j-i+1} x_j
  * Every product is split exactly with fma (TwoProd) and every sum is carried
@@ -49,10 +52,9 @@ static inline dd dd_mul_d(dd a, double b) {
 }
 
 /* sum over j of coefficient g[idx(j)] * x_j in double-double */
-void dd_fd_residual(int64_t n, double nu, double shift, double unused,
+void dd_fd_residual(int64_t n, double nu, double shift, double mass_c,
                     const double* g, const double* dp, const double* dm,
                     const double* x, const double* b, double* r, int threads) {
-  (void)unused;
 #ifdef _OPENMP
   if (threads > 0) omp_set_num_threads(threads);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -70,6 +72,11 @@ void dd_fd_residual(int64_t n, double nu, double shift, double unused,
     t = dd_mul_d(t, nu);
     dd acc = two_sum(b[i], -shift * x[i]);
     acc.lo += fma(-shift, x[i], shift * x[i]);   /* exact remainder of shift*x */
+    if (mass_c != 0.0) {
+      /* - s mass_c (x_{i-1} + x_{i+1}); s mass_c is exact for mass_c = 1/4 */
+      dd nb = two_sum(i > 0 ? x[i - 1] : 0.0, i + 1 < n ? x[i + 1] : 0.0);
+      acc = dd_add(acc, dd_mul_d(nb, -shift * mass_c));
+    }
     acc = dd_add(acc, t);                          /* b - s x + nu(...) since T = -G */
     r[i] = acc.hi + acc.lo;
   }

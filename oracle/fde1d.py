@@ -174,12 +174,14 @@ def build_c() -> str:
     return out
 
 
-def residual_dd(alpha, nu, shift, d_plus, d_minus, x, b, g=None, threads=0):
+def residual_dd(alpha, nu, shift, d_plus, d_minus, x, b, g=None, threads=0, mass_c=0.0):
     """r = b - (shift I + nu (D+ T + D- T^T)) x in double-double, rounded to FP64.
 
     Every product nu*d_i*g_k is formed exactly (TwoProd) and every sum is
     carried in double-double, so the result is the residual of the operator
     whose entries are nu*d*g to ~unit roundoff of r (not of |M||x|).
+    With mass_c != 0 the shift term is shift*(I + mass_c*(S + S^T)) (the
+    finite-element mass matrix, see ``oracle.fe``).
     """
     n = x.size
     if g is None:
@@ -191,7 +193,7 @@ def residual_dd(alpha, nu, shift, d_plus, d_minus, x, b, g=None, threads=0):
     dm = np.ascontiguousarray(d_minus, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
     r = np.empty(n)
-    lib.dd_fd_residual(n, float(nu), float(shift), 0.0, g.ctypes.data, dp.ctypes.data,
+    lib.dd_fd_residual(n, float(nu), float(shift), float(mass_c), g.ctypes.data, dp.ctypes.data,
                        dm.ctypes.data, x.ctypes.data, b.ctypes.data, r.ctypes.data,
                        int(threads))
     return r

@@ -25,6 +25,14 @@ does not state are the choices written out below):
                  64 steps.
 * ``learned_2d`` 2048 x 2048, alpha1=1.4, alpha2=1.6, d+-=1, f=0, dt=1/64,
                  initial conditions = sums of 8 separable Gaussians.
+* ``fe_1d``      finite elements (P1 hats) in 1D: N=4096, alpha=1.3,
+                 d+=d-=1 (constant, as in the paper's finite-element
+                 experiment), dt=1/16, 16 steps, u0=x^2(1-x)^2, 8-Gaussian f.
+* ``fe_2d``      the paper's finite-element experiment (Sec. (ex-fe)):
+                 [0,1]^2, constant coefficients d+-=1, alpha1=1.3,
+                 alpha2=1.7, dt=0.1, f = indicator of H=[3/8,5/8]^2 (rank 1),
+                 u0 = f; N=4096 per direction (the paper runs 512..65536) and
+                 8 steps (the paper does not state its step count).
 """
 from __future__ import annotations
 
@@ -210,3 +218,30 @@ def learned_2d(n: int = 2048, alpha_x: float = 1.4, alpha_y: float = 1.6,
     return Problem2D(n, n, alpha_x, alpha_y, dt, steps, hx, hy, x, y,
                      one, one.copy(), one.copy(), one.copy(), u0, f,
                      name=f"learned_2d_N{n}_s{seed}")
+
+
+def fe_1d(n: int = 4096, alpha: float = 1.3, dt: float = 1.0 / 16,
+          steps: int = 16, seed_offset: int = 6) -> Problem1D:
+    """1D finite-element problem (same fields as the finite-difference ones;
+    d+ = d- = 1)."""
+    x, h = grid(n)
+    rng = np.random.default_rng(BASE_SEED + seed_offset)
+    one = np.ones(n)
+    return Problem1D(n, alpha, dt, steps, h, x, one.copy(), one.copy(),
+                     bump(x), gaussian_source(x, rng), name=f"fe_1d_N{n}_a{alpha}")
+
+
+def fe_2d(n: int = 4096, alpha_x: float = 1.3, alpha_y: float = 1.7,
+          dt: float = 0.1, steps: int = 8) -> Problem2D:
+    """The finite-element experiment: f = 1 on H = [3/8, 5/8]^2, else 0;
+    u(x, y, 0) = f; constant coefficients."""
+    x, hx = grid(n)
+    y, hy = grid(n)
+    one = np.ones(n)
+    ix = ((x >= 3 / 8) & (x <= 5 / 8)).astype(float)[:, None]
+    iy = ((y >= 3 / 8) & (y <= 5 / 8)).astype(float)[:, None]
+    f = LowRank(ix.copy(), iy.copy())
+    u0 = LowRank(ix.copy(), iy.copy())
+    return Problem2D(n, n, alpha_x, alpha_y, dt, steps, hx, hy, x, y,
+                     one, one.copy(), one.copy(), one.copy(), u0, f,
+                     name=f"fe_2d_N{n}")
