@@ -59,19 +59,38 @@ typedef struct hodlr_ctx_s* hodlr_ctx;
 typedef struct hodlr_mat_s* hodlr_mat;
 typedef struct fde2d_plan_s* fde2d_plan;
 
-/* One 1D operator (Sec. 2.2.1, eq. (system_FD)):
+/* Space discretisations of an operator. */
+typedef enum {
+  FDE_FD = 0,   /* shifted Grunwald-Letnikov finite differences (Sec. 2.2.1) */
+  FDE_FE = 1    /* P1 (hat-function) finite elements on the uniform grid (Sec. 2.2.2) */
+} fde_discretization;
+
+/* One 1D operator.
+ * FDE_FD (Sec. 2.2.1, eq. (system_FD)):
  *   M = shift*I + nu*(D+ T_alpha + D- T_alpha^T),   nu = dt / dx^alpha,
  * with T_alpha the lower Hessenberg Toeplitz matrix of Grunwald-Letnikov
- * weights (eq. (toeplitz_FD)).  shift = 1 for the 1D implicit Euler step;
- * shift = 1/2 (+ an ADI shift) for the coefficients of the 2D Sylvester
- * step (eq. (sylv-timestepping)). */
+ * weights (eq. (toeplitz_FD)).
+ * FDE_FE (Sec. 2.2.2, Sec. 3.4.3):
+ *   M = shift*E + nu*(D+ T + D- T^T),   E = tridiag(1/6, 2/3, 1/6),
+ * the Galerkin matrix shift*Mass - dt (D+ K+ + D- K-) of hat functions of
+ * height 1 divided by dx, where K+_ij = <phi_i, d^alpha_+ phi_j> (eq.
+ * (fe-int)) = -dx^(1-alpha) T_ij, T_ij = -w_{i-j+1} with
+ *   w_m = (1/Gamma(4-alpha)) sum_{t=-2..2} c_t (m-1+t)_+^(3-alpha),
+ *   c = (1, -4, 6, -4, 1),
+ * and K- = K+^T.  d+- are applied as row scalings (samples at the nodes):
+ * with constant coefficients, the case of the paper's finite-element
+ * experiment, that is the Galerkin matrix exactly.
+ * shift = 1 for the 1D implicit Euler step; shift = 1/2 (+ an ADI shift)
+ * for the coefficients of the 2D Sylvester step (eq. (sylv-timestepping),
+ * eq. (sylv-timestepping-fe)). */
 typedef struct {
   int64_t n;              /* interior grid points, 1 <= N < 2^23 (eq. (part)) */
   double alpha;           /* fractional order, 1 <= alpha <= 2 */
   double dt, dx;          /* time step and grid spacing; nu = dt/dx^alpha */
-  double shift;           /* identity shift s > 0 */
+  double shift;           /* shift s > 0 of the identity (FD) or of the mass matrix E (FE) */
   const double* d_plus;   /* device, n samples d+(x_i) >= 0 */
   const double* d_minus;  /* device, n samples d-(x_i) >= 0 */
+  int discretization;     /* fde_discretization; 0 (FDE_FD) in a zero-initialised struct */
 } fde_operator;
 
 typedef struct {
@@ -201,14 +220,25 @@ hodlr_status hodlr_update_coefficients(hodlr_ctx ctx, hodlr_mat m, const fde_ope
 void hodlr_destroy(hodlr_mat m);
 hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info);
 
+/* The generator the library computed for problem `item` of the batch:
+ * g_0 .. g_{count-1}, count <= n + 3, copied to host memory `out` (the
+ * call waits for the context's stream).  FDE_FD: the Grunwald-Letnikov
+ * weights of eq. (Grun) by the recursion of Sec. 3.4.2; FDE_FE: the P1
+ * stiffness generator w_m of eq. (fe-int) (see fde_operator), each evaluated
+ * in double-double arithmetic and rounded once.  Errors: HODLR_EINVAL for a
+ * null handle (2), item out of range (3), null out (4), count out of range (5). */
+hodlr_status hodlr_get_weights(hodlr_ctx ctx, hodlr_mat m, int item, double* out, int64_t count);
+
 /* y = M_H x with the compressed HODLR operator (Sec. 3.4.1).  x, y device,
  * concatenated over the batch, nrhs columns with leading dimension ld. */
 hodlr_status hodlr_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y,
                           int nrhs, int64_t ld);
 
 /* y = M x exactly (up to FFT rounding) through circulant embedding of the
- * Toeplitz matrices (the FFT matrix-vector product of Sec. 3.4.2).  Used as
- * the refinement residual.  Same layout as hodlr_matvec. */
+ * Toeplitz matrices (the FFT matrix-vector product of Sec. 3.4.2); the near
+ * band, the shift term and the finite-element mass matrix are summed in
+ * double-double.  Used as the refinement residual.  Same layout as
+ * hodlr_matvec. */
 hodlr_status hodlr_toeplitz_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y,
                                    int nrhs, int64_t ld);
 
@@ -346,7 +376,13 @@ int fde2d_plan_shifts(fde2d_plan p, double* p_shifts, double* q_shifts, int cap)
 
 /* One implicit Euler step of eq. (sylv-timestepping): U_next solves
  *   A X + X B^T = C,  C = U_m + dt F,
- * with every matrix in low-rank form.  U_m: input, at most 64 columns; F: at
+ * with every matrix in low-rank form.  With finite-element operators
+ * (FDE_FE) the step is that of eq. (sylv-timestepping-fe),
+ *   A X E_y + E_x X B^T = C,  C = E_x (U_m + dt F) E_y,
+ * E the mass matrices, solved by the same sweeps in generalized form: the
+ * shifted solves use A + q_j E_x and B + p_j E_y, the fADI residual factors
+ * are updated through E, and no inverse of E is formed; A X, X B^T below read
+ * A X E_y, E_x X B^T and ||A|| + ||B|| reads ||A|| ||E_y|| + ||E_x|| ||B||.  U_m: input, at most 64 columns; F: at
  * most 32 (rank 0 allowed).  C, recompressed, is the right-hand side of a
  * first factored ADI sweep with the plan's shifted HODLR solves, run until the
  * fADI residual G_J H_J^T is below opts.tol * ||C||_F; its result (recompressed
@@ -355,7 +391,10 @@ int fde2d_plan_shifts(fde2d_plan p, double* p_shifts, double* q_shifts, int cap)
  * from the factors (C from the caller's U_m and F, A Z and B W by the exact
  * Toeplitz products), which resolves ||R||_F to about u times the size of its
  * terms, and while the normwise backward error info->backward_error exceeds
- * opts.tol (at most 4 times) a correction sweep solves A D + D B^T = R (R
+ * opts.tol, or (reduced-precision factors) while the forward-error estimate
+ * of iterative refinement |D_k|^2 / (|D_{k-1}| |X_main|) (D_0 = X_main; at
+ * least one correction) exceeds opts.tol (at most 6 times), a correction
+ * sweep solves A D + D B^T = R (R
  * compressed by a randomized range finder on its factors) and D joins the
  * correction term X_corr (recompressed so that its truncation changes the
  * backward error by at most opts.tol / 10).  The two terms are kept apart
@@ -363,8 +402,9 @@ int fde2d_plan_shifts(fde2d_plan p, double* p_shifts, double* q_shifts, int cap)
  * sqrt(u) times the larger one.
  * U_next = [Z_main, Z_corr][W_main, W_corr]^T: caller-allocated factors with
  * `capacity` (>= the rank used, <= 64) columns; on return U_next->rank is the
- * rank used.  HODLR_ENOCONV if the backward error is still above opts.tol after
- * the corrections, HODLR_ERANK if the correction term hit its rank cap.
+ * rank used.  HODLR_ENOCONV if the backward error (or, reduced precision, the
+ * forward-error estimate) is still above opts.tol after the corrections, HODLR_ERANK
+ * if the correction term hit its rank cap.
  * info->rel_residual: ||R||_F / ||C||_F of the returned solution;
  * info->rel_correction: the last correction relative to ||X_main||_F;
  * info->refine_iters: ADI steps taken in total; info->max_rank: U_next->rank. */

@@ -5,4 +5,4 @@ The compute path is the HIP library ``libhodlr_fde.so`` (C ABI declared in
 binding.  torch provides device memory and streams only.
 """
 from .hodlr import (Context, HodlrMatrix, HodlrError, Fde2dPlan, ConvNet, default_opts, lib, operator_dict,  # noqa: F401
-                    FP64, MIXED_FP32, MIXED_BF16, EXPORTS)
+                    FP64, MIXED_FP32, MIXED_BF16, FDE_FD, FDE_FE, EXPORTS)

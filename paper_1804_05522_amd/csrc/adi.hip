@@ -15,9 +15,31 @@
 // host FP64); the shifted factors A + q_j I, B + p_j I are one batched HODLR
 // operator whose problems share the off-diagonal blocks and differ on the
 // leaf diagonals.  X is recompressed after every step (rank <= 64).
+//
+// Finite elements (eq. (sylv-timestepping-fe)): A X E_y + E_x X B^T = C with
+// the mass matrices E.  This is A~ X + X B~^T = C~ for A~ = E_x^{-1} A,
+// B~ = E_y^{-1} B, C~ = E_x^{-1} C E_y^{-1}; running the recurrence above on
+// it and carrying G^ = E_x G~, H^ = E_y H~ instead gives
+//   Z_j = (A + q_j E_x)^{-1} G^_{j-1},  G^_j = G^_{j-1} - (p_j + q_j) E_x Z_j
+// (and the same for Y, H^), with G^_J H^_J^T the residual of the generalized
+// equation: no inverse of E is ever applied, the shifted operators are
+// A + q_j E_x (the shift multiplies the mass matrix), and only the residual
+// update gains a tridiagonal product.
 #include "internal.hpp"
 
 namespace hfde {
+
+// E v at row i of a column of n rows (zero outside), E = mass (I + mc (S + S^T));
+// mc == 0: E = I (the value itself, bit for bit).
+__device__ inline double mass_at(const double* v, int64_t i, int64_t n, double mass, double mc) {
+  if (mc == 0.0) return v[i];
+  const double l = i > 0 ? v[i - 1] : 0.0, r = i + 1 < n ? v[i + 1] : 0.0;
+  return mass * (v[i] + mc * (l + r));
+}
+
+struct MassPair {
+  double mx, cx, my, cy;
+};
 
 // Up to three column groups, counts optionally read from device memory.
 struct Grp {
@@ -182,16 +204,26 @@ __global__ void k_lr_frob(const LrJob jb, const double* G, double* out) {
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
-// G -= w Z, H -= w Y for the fADI residual factors; also stores w Z into the
-// accumulation buffer (X update operand).  Z, Y columns: r (device count).
+// G -= w E_x Z, H -= w E_y Y for the fADI residual factors (E = I for
+// differences).  Z, Y columns: r (device count).
 __global__ void k_adi_update(int64_t nx, int64_t ny, const int32_t* rdev, double w, const double* Z, int64_t ldz,
-                             const double* Y, int64_t ldy, double* G, int64_t ldg, double* H, int64_t ldh) {
+                             const double* Y, int64_t ldy, double* G, int64_t ldg, double* H, int64_t ldh, MassPair E) {
   const int r = *rdev;
   const int64_t tot = (nx + ny) * r;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
     const int64_t c = e / (nx + ny), i = e % (nx + ny);
-    if (i < nx) G[i + c * ldg] -= w * Z[i + c * ldz];
-    else H[(i - nx) + c * ldh] -= w * Y[(i - nx) + c * ldy];
+    if (i < nx) G[i + c * ldg] -= w * mass_at(Z + c * ldz, i, nx, E.mx, E.cx);
+    else H[(i - nx) + c * ldh] -= w * mass_at(Y + c * ldy, i - nx, ny, E.my, E.cy);
+  }
+}
+
+// dst = scale * E src on `cols` columns of `rows` rows (E = mass (I + mc (S + S^T))).
+__global__ void k_mass_cols(int64_t rows, int cols, double mass, double mc, const double* src, int64_t lds_,
+                            double* dst, int64_t ldd, double scale) {
+  const int64_t tot = rows * cols;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = e / rows, i = e % rows;
+    dst[i + c * ldd] = scale * mass_at(src + c * lds_, i, rows, mass, mc);
   }
 }
 

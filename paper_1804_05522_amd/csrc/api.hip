@@ -189,6 +189,7 @@ struct hodlr_mat_s {
   double* step_worst = nullptr;   // batch: worst relative correction of the steps since the last clear
   double* host_worst = nullptr;   // pinned host copy of step_worst
   int step_slices = 0;
+  bool has_mass = false;         // some problem is a finite-element operator (E != I)
   // GMRES-IR (opts.gmres_m > 0): basis V (total_n x (kGmMax + 1)), preconditioned
   // vectors Z (total_n x kGmMax), per-problem small arrays
   double* gmV = nullptr;
@@ -254,6 +255,13 @@ struct fde2d_plan_s {
   int64_t nx = 0, ny = 0;
   double shift_x = 0.5, shift_y = 0.5;
   double bound_x = 1.0, bound_y = 1.0;   // lower bounds of ||A||_2, ||B||_2: the largest diagonal entries
+  // Finite elements: A X E_y + E_x X B^T = C (eq. (sylv-timestepping-fe)),
+  // E = mass (I + mc (S + S^T)); mass = 1, mc = 0 for an identity E.
+  bool fe = false;
+  double mass_x = 1.0, mass_y = 1.0, mc_x = 0.0, mc_y = 0.0;
+  double* cz = nullptr;         // E_x [Z_m, F_Z] and E_y [W_m, F_W] (finite elements), (kMaxCat + kRS) columns
+  double* cw = nullptr;
+  double* ex_mass = nullptr;    // E applied to the exact products' inputs, layout of ex_in
   fde2d_opts opts{};
   std::vector<int> pwu_off, pwu_cnt, pnu_off, pnu_cnt;
   WorkUnit* pair_wu = nullptr;
@@ -1138,7 +1146,8 @@ static hodlr_status build_impl(hodlr_ctx ctx, const fde_operator* ops, int batch
     // values) with 32-bit byte offsets that must stay below the out-of-range
     // sentinel kOob, so n x 32 x 8 < 2^31 - 16
     if (o.n < 1 || o.n >= (int64_t(1) << 23) || !(o.alpha >= 1.0 && o.alpha <= 2.0) || !(o.dt > 0.0) ||
-        !(o.dx > 0.0) || !(o.shift > 0.0) || (!sizing && (!o.d_plus || !o.d_minus)))
+        !(o.dx > 0.0) || !(o.shift > 0.0) || (!sizing && (!o.d_plus || !o.d_minus)) ||
+        (o.discretization != FDE_FD && o.discretization != FDE_FE))
       return set_arg(ctx, 2);
   }
   if (!sizing) TRY(set_lds_limits());
@@ -1170,6 +1179,15 @@ static hodlr_status build_impl(hodlr_ctx ctx, const fde_operator* ops, int batch
     it.alpha = o.alpha;
     it.nu = o.dt / std::pow(o.dx, o.alpha);
     it.shift = o.shift;
+    it.kind = o.discretization;
+    it.mass = o.discretization == FDE_FE ? 2.0 / 3.0 : 1.0;
+    it.mc = o.discretization == FDE_FE ? 0.25 : 0.0;
+    if (o.discretization == FDE_FE) {   // 1/Gamma(4 - alpha) in extended precision, split hi + lo
+      const long double ig = 1.0L / std::tgamma(4.0L - static_cast<long double>(o.alpha));
+      it.fig = static_cast<double>(ig);
+      it.fig_lo = static_cast<double>(ig - static_cast<long double>(it.fig));
+    }
+    m->has_mass |= o.discretization == FDE_FE;
     int flog = 1;
     while ((int64_t(1) << flog) < 2 * o.n - 1) ++flog;
     it.fftlog = flog;
@@ -1517,7 +1535,7 @@ hodlr_status hodlr_update_coefficients(hodlr_ctx ctx, hodlr_mat m, const fde_ope
     const Item& it = m->items[i];
     const double nu = (o.dt > 0.0 && o.dx > 0.0) ? o.dt / std::pow(o.dx, o.alpha) : -1.0;
     if (o.n != it.n || o.alpha != it.alpha || o.shift != it.shift || !(std::fabs(nu - it.nu) <= 1e-14 * it.nu) ||
-        !o.d_plus || !o.d_minus)
+        !o.d_plus || !o.d_minus || o.discretization != it.kind)
       return set_arg(ctx, 3);
   }
   hipStream_t s = ctx->stream;
@@ -1689,6 +1707,20 @@ hodlr_status hodlr_matvec(hodlr_ctx ctx, hodlr_mat m, const double* x, double* y
                        m->b);
   }
   HIP_TRY(hipGetLastError());
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_get_weights(hodlr_ctx ctx, hodlr_mat m, int item, double* out, int64_t count) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!m || m->sizing) return set_arg(ctx, 2);
+  if (item < 0 || item >= m->batch) return set_arg(ctx, 3);
+  if (!out) return set_arg(ctx, 4);
+  const Item& it = m->items[item];
+  if (count < 0 || count > it.n + 3) return set_arg(ctx, 5);
+  if (count == 0) return HODLR_OK;
+  hipStream_t s = ctx->stream;
+  HIP_TRY(hipMemcpyAsync(out, m->P.g + it.g0, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return HODLR_OK;
 }
 
@@ -2024,12 +2056,22 @@ hodlr_status hodlr_solve(hodlr_ctx ctx, hodlr_mat m, double* x, int nrhs, int64_
 // r = b - M u (exact), d = M_low^{-1} r (or a GMRES-IR cycle), u += d.  With sweeps > 0 the last
 // update also folds the step's ||d||/||u|| into m->step_worst.  No host
 // synchronisation: the sequence is what a time-step graph captures.
+// Right-hand side of an implicit Euler step into m->bbuf: b = u + fscale f,
+// or E (u + fscale f) for finite-element problems (E = P1 mass / h; Sec. 2.2.2).
+static void launch_step_rhs(hodlr_mat m, const double* u, const double* f, double fscale, hipStream_t s) {
+  const int64_t tn = m->total_n;
+  if (m->has_mass) {
+    HFDE_LAUNCH(k_step_rhs, dim3(m->step_slices, m->batch), dim3(256), 0, s, m->P, u, f, fscale, m->bbuf);
+    return;
+  }
+  if (f) launch_axpby(tn, 1, 1.0, u, tn, fscale, f, tn, m->bbuf, tn, s);
+  else launch_axpby(tn, 1, 1.0, u, tn, 0.0, u, tn, m->bbuf, tn, s);
+}
+
 static void record_step(hodlr_mat m, double* u, const double* f, double fscale, int sweeps, hipStream_t s) {
   const int64_t tn = m->total_n;
   const int prec = m->opts.prec;
-  // b = u + fscale * f
-  if (f) launch_axpby(tn, 1, 1.0, u, tn, fscale, f, tn, m->bbuf, tn, s);
-  else launch_axpby(tn, 1, 1.0, u, tn, 0.0, u, tn, m->bbuf, tn, s);
+  launch_step_rhs(m, u, f, fscale, s);
   launch_solve(m, prec, m->bbuf, tn, u, tn, 1, s);
   for (int q = 0; q < sweeps; ++q) {
     if (m->opts.gmres_m > 0) {
@@ -2114,8 +2156,7 @@ hodlr_status hodlr_time_steps(hodlr_ctx ctx, hodlr_mat m, double* u, const doubl
     fallback = true;
     HIP_TRY(hipMemcpyAsync(u, m->ukeep, tn * sizeof(double), hipMemcpyDeviceToDevice, s));
     for (int k = 0; k < kc; ++k) {
-      if (f) launch_axpby(tn, 1, 1.0, u, tn, fscale, f, tn, m->bbuf, tn, s);
-      else launch_axpby(tn, 1, 1.0, u, tn, 0.0, u, tn, m->bbuf, tn, s);
+      launch_step_rhs(m, u, f, fscale, s);
       double rr = 0, rd = 0;
       const int conv = sweep_solve(m, HODLR_FP64, std::max(4, sweeps), u, tn, 1, s, rr, rd, iters);
       if (conv < 0) return hodlr_status(conv);

@@ -12,7 +12,7 @@ enum { kR_R0 = 0, kR_D0 = 1, kR_D1 = 2, kR_X0 = 3, kR_X1 = 4, kR_T = 5, kR_C = 6
        kR_K0 = 11, kR_K1 = 12,   // rank of the correction sum X_corr (ping-pong)
        kR_Q1 = 13, kR_Q2 = 14,   // ranks of the orthonormalised sketches of a dense compression
        kR_N = 15 };
-constexpr int kMaxCorrections = 4;   // correction sweeps of a step after the first
+constexpr int kMaxCorrections = 6;   // correction sweeps of a step after the first
 constexpr int kSketch = 32;          // sketch columns of a dense compression
 
 // ---------- Zolotarev shifts for two real intervals (host, FP64) ----------
@@ -188,6 +188,14 @@ void copy_cols(int64_t rows, const int32_t* rdev, int rfix, const double* src, i
   HFDE_LAUNCH(k_copy_cols, dim3(blocks), dim3(256), 0, s, rows, rdev, rfix, src, lds, dst, ldd, sc);
 }
 
+// dst = sc * E src on cols columns (E = mass (I + mc (S + S^T))).
+void mass_cols(int64_t rows, int cols, double mass, double mc, const double* src, int64_t lds, double* dst,
+               int64_t ldd, double sc, hipStream_t s) {
+  if (cols <= 0) return;
+  const int blocks = int(std::min<int64_t>((rows * cols + 255) / 256, 4096));
+  HFDE_LAUNCH(k_mass_cols, dim3(blocks), dim3(256), 0, s, rows, cols, mass, mc, src, lds, dst, ldd, sc);
+}
+
 // ||S||_F of a sum of low-rank products formed entry by entry (k_lrs_dense).
 hodlr_status dense_norm(fde2d_plan P, const LrSum& S, double& norm, hipStream_t s) {
   const dim3 grid(unsigned((P->nx + 63) / 64), unsigned((P->ny + 63) / 64));
@@ -328,7 +336,7 @@ hodlr_status enqueue_main_block(fde2d_plan P, int b, int nc, hipStream_t s) {
                        P->pnu_cnt[j], P->xin, tn, P->xin, tn, nc, s);
     const double w = P->p[j] + P->q[j];
     HFDE_LAUNCH(k_adi_update, dim3(256), dim3(256), 0, s, nx, ny, P->ranks + kR_R0, w, P->xin + ix.row0, tn,
-                       P->xin + iy.row0, tn, P->G, nx, P->H, ny);
+                       P->xin + iy.row0, tn, P->G, nx, P->H, ny, MassPair{P->mass_x, P->mc_x, P->mass_y, P->mc_y});
   }
   LrJob nj{};
   nj.X.g[0] = grp(P->G, nx, P->ranks + kR_R0, 0, 1.0);
@@ -529,6 +537,8 @@ static hodlr_status plan2d_impl(hodlr_ctx ctx, const fde_operator* opx, const fd
       opts->max_rank > kRS)
     return set_arg(ctx, 5);
   if (!sizing && !out) return set_arg(ctx, ws ? 8 : 6);
+  if (opx->discretization != FDE_FD && opx->discretization != FDE_FE) return set_arg(ctx, 2);
+  if (opy->discretization != FDE_FD && opy->discretization != FDE_FE) return set_arg(ctx, 3);
   hipStream_t s = ctx->stream;
   fde2d_plan P = new (std::nothrow) fde2d_plan_s;
   if (!P) return HODLR_ENOMEM;
@@ -554,14 +564,35 @@ static hodlr_status plan2d_impl(hodlr_ctx ctx, const fde_operator* opx, const fd
   P->ny = opy->n;
   P->shift_x = opx->shift;
   P->shift_y = opy->shift;
-  // spectral intervals [s, s + 2 nu alpha max(d+ + d-)]
+  // Spectral intervals [s, hi] of the pencils (A, E_x) and (B, E_y).
+  // Differences (E = I): Gershgorin with sum_k |g_k| = 2 alpha, so
+  // hi = s + 2 nu alpha max(d+ + d-).  Finite elements: a generalized
+  // eigenvalue is s + nu v^H (D+ T + D- T^T) v / v^H E v; the stiffness form
+  // is coercive for constant coefficients (real part >= 0), its magnitude is
+  // at most ||D+ T + D- T^T||_2 |v|^2 <= (max d+ + max d-) sum_m |w_m| |v|^2,
+  // and v^H E v >= |v|^2 / 3 (E's eigenvalues lie in (1/3, 1)).  The weights
+  // are positive from w_3 on and w_0 > 0, w_1 < 0 and sum to zero, so
+  // sum |w_m| = -2 (w_1 + min(w_2, 0)).
   auto upper = [&](const fde_operator* o, double& hi, double& lo) -> hodlr_status {
     std::vector<double> dp(o->n), dm(o->n);
     HIP_TRY(hipMemcpy(dp.data(), o->d_plus, o->n * sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(dm.data(), o->d_minus, o->n * sizeof(double), hipMemcpyDeviceToHost));
-    double mx = 0.0;
-    for (int64_t i = 0; i < o->n; ++i) mx = std::max(mx, dp[i] + dm[i]);
+    double mx = 0.0, mxp = 0.0, mxm = 0.0;
+    for (int64_t i = 0; i < o->n; ++i) {
+      mx = std::max(mx, dp[i] + dm[i]);
+      mxp = std::max(mxp, dp[i]);
+      mxm = std::max(mxm, dm[i]);
+    }
     const double nu = o->dt / std::pow(o->dx, o->alpha);
+    if (o->discretization == FDE_FE) {
+      const double p = 3.0 - o->alpha, ig = 1.0 / std::tgamma(4.0 - o->alpha);
+      const double w1 = (std::pow(2.0, p) - 4.0) * ig;
+      const double w2 = (std::pow(3.0, p) - 4.0 * std::pow(2.0, p) + 6.0) * ig;
+      const double sumabs = -2.0 * (w1 + std::min(w2, 0.0));
+      hi = o->shift + 3.0 * nu * (mxp + mxm) * sumabs;
+      lo = o->shift * (2.0 / 3.0) + nu * (-w1) * mx;   // the largest diagonal entry
+      return HODLR_OK;
+    }
     hi = o->shift + 2.0 * nu * o->alpha * mx;
     lo = o->shift + nu * o->alpha * mx;       // the largest diagonal entry: <= the 2-norm
     return HODLR_OK;
@@ -573,6 +604,8 @@ static hodlr_status plan2d_impl(hodlr_ctx ctx, const fde_operator* opx, const fd
   const double a1 = opx->shift, a2 = opy->shift;
   P->bound_x = l1;
   P->bound_y = l2;
+  if (opx->discretization == FDE_FE) { P->fe = true; P->mass_x = 2.0 / 3.0; P->mc_x = 0.25; }
+  if (opy->discretization == FDE_FE) { P->fe = true; P->mass_y = 2.0 / 3.0; P->mc_y = 0.25; }
   int J = 1;
   for (; J <= opts->max_shifts; ++J) {
     zolotarev_shifts(a1, b1, a2, b2, J, P->p, P->q);
@@ -697,6 +730,10 @@ static hodlr_status plan2d_impl(hodlr_ctx ctx, const fde_operator* opx, const fd
        plan_alloc(P, &P->sk_q2, nx * kSketch) == HODLR_OK && plan_alloc(P, &P->sk_b, ny * kSketch) == HODLR_OK &&
        plan_alloc(P, &P->eye, kSketch * kSketch) == HODLR_OK &&
        plan_alloc(P, &P->sk_junk, kSketch * kSketch) == HODLR_OK;
+  if (P->fe)
+    ok = ok && plan_alloc(P, &P->cz, nx * (kMaxCat + kRS)) == HODLR_OK &&
+         plan_alloc(P, &P->cw, ny * (kMaxCat + kRS)) == HODLR_OK &&
+         plan_alloc(P, &P->ex_mass, (nx + ny) * kMaxCat) == HODLR_OK;
   for (int k = 0; k < 2 && ok; ++k)
     ok = plan_alloc(P, &P->Zc[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wc[k], ny * kRS) == HODLR_OK &&
          plan_alloc(P, &P->Zx[k], nx * kRS) == HODLR_OK && plan_alloc(P, &P->Wx[k], ny * kRS) == HODLR_OK &&
@@ -793,6 +830,19 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
   const int64_t nx = P->nx, ny = P->ny;
   const double tol = P->opts.tol;
   int32_t hr[kR_N];
+  lr_matrix um_e{}, f_e{};
+  if (P->fe) {
+    // Finite elements: C = E_x (U_m + dt F) E_y, so the caller's factors
+    // enter with the mass matrices applied (exact: E is tridiagonal).
+    mass_cols(nx, U_m->rank, P->mass_x, P->mc_x, U_m->Z, U_m->ldz, P->cz, nx, 1.0, s);
+    mass_cols(ny, U_m->rank, P->mass_y, P->mc_y, U_m->W, U_m->ldw, P->cw, ny, 1.0, s);
+    mass_cols(nx, F->rank, P->mass_x, P->mc_x, F->Z, F->ldz, P->cz + kMaxCat * nx, nx, 1.0, s);
+    mass_cols(ny, F->rank, P->mass_y, P->mc_y, F->W, F->ldw, P->cw + kMaxCat * ny, ny, 1.0, s);
+    um_e = lr_matrix{nx, U_m->rank, U_m->rank, nx, ny, P->cz, P->cw};
+    f_e = lr_matrix{nx, F->rank, F->rank, nx, ny, P->cz + kMaxCat * nx, P->cw + kMaxCat * ny};
+    U_m = &um_e;
+    F = &f_e;
+  }
   HIP_TRY(hipMemsetAsync(P->ranks + kR_CAP, 0, sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(P->ranks + kR_X0, 0, 2 * sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(P->ranks + kR_K0, 0, 2 * sizeof(int32_t), s));
@@ -869,6 +919,7 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
   // from X_main; the residual C - A X - X B^T of the sum is formed entry by
   // entry (dense_norm), which resolves it to about u times its terms.
   int xpar = 0, kpar = 0, total_steps = 0, sweeps = 0;
+  const bool verbose = getenv("HODLR_VERBOSE") != nullptr;
   double rel_res = 1.0, rel_corr = 0.0, eta = 1.0, guess_res = 0.0;
   bool warm = false, fallback = false;
   // R = C - A X - X B^T for X = X_main + X_corr: its norm relative to
@@ -889,10 +940,22 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
     if (rx + rk > 0) launch_fft_matvec(P->exact, P->ex_in, ld, P->ex_out, ld, nullptr, 0, rx + rk, s);
     LrSum& r = rsum;
     r = csum;
-    r.g[r.ng++] = LrsGroup{P->ex_out, ld, P->Wx[xpar], ny, nullptr, rx, -1.0};             // A Z_main W_main^T
-    r.g[r.ng++] = LrsGroup{P->Zx[xpar], nx, P->ex_out + nx, ld, nullptr, rx, -1.0};        // Z_main (B W_main)^T
-    r.g[r.ng++] = LrsGroup{P->ex_out + rx * ld, ld, P->Wc[kpar], ny, nullptr, rk, -1.0};   // A Z_corr W_corr^T
-    r.g[r.ng++] = LrsGroup{P->Zc[kpar], nx, P->ex_out + rx * ld + nx, ld, nullptr, rk, -1.0};
+    if (!P->fe) {
+      r.g[r.ng++] = LrsGroup{P->ex_out, ld, P->Wx[xpar], ny, nullptr, rx, -1.0};             // A Z_main W_main^T
+      r.g[r.ng++] = LrsGroup{P->Zx[xpar], nx, P->ex_out + nx, ld, nullptr, rx, -1.0};        // Z_main (B W_main)^T
+      r.g[r.ng++] = LrsGroup{P->ex_out + rx * ld, ld, P->Wc[kpar], ny, nullptr, rk, -1.0};   // A Z_corr W_corr^T
+      r.g[r.ng++] = LrsGroup{P->Zc[kpar], nx, P->ex_out + rx * ld + nx, ld, nullptr, rk, -1.0};
+    } else {
+      // A X E_y + E_x X B^T: (A Z)(E_y W)^T + (E_x Z)(B W)^T for both terms
+      mass_cols(nx, rx + rk, P->mass_x, P->mc_x, P->ex_in, ld, P->ex_mass, ld, 1.0, s);
+      mass_cols(ny, rx + rk, P->mass_y, P->mc_y, P->ex_in + nx, ld, P->ex_mass + nx, ld, 1.0, s);
+      for (int t = 0; t < 2; ++t) {
+        const int64_t c0 = t == 0 ? 0 : rx * ld;
+        const int rc_t = t == 0 ? rx : rk;
+        r.g[r.ng++] = LrsGroup{P->ex_out + c0, ld, P->ex_mass + c0 + nx, ld, nullptr, rc_t, -1.0};
+        r.g[r.ng++] = LrsGroup{P->ex_mass + c0, ld, P->ex_out + c0 + nx, ld, nullptr, rc_t, -1.0};
+      }
+    }
     double rn = 0.0;
     TRY(dense_norm(P, r, rn, s));
     // ||X||_F of the main term (Gram trace): the correction term is a small
@@ -911,7 +974,9 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
     }
     xnorm = std::sqrt(std::max(x2, 0.0));
     rel = cnorm > 0 ? rn / cnorm : 0.0;
-    const double scale = (P->bound_x + P->bound_y) * xnorm + cnorm;
+    // ||A X E_y + E_x X B^T|| <= (||A|| ||E_y|| + ||E_x|| ||B||) ||X||; the
+    // masses' lower bounds are their diagonals (1 for the identity)
+    const double scale = (P->bound_x * P->mass_y + P->mass_x * P->bound_y) * xnorm + cnorm;
     eta = scale > 0 ? rn / scale : 0.0;
     return HODLR_OK;
   };
@@ -997,10 +1062,21 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
       mj.ldv = ny;
       TRY(run_lr(P, mj, 4, true, s));
       TRY(residual(rel_res));
+      if (verbose)
+        fprintf(stderr, "hodlr_fde: 2D step: first sweep: %d ADI steps, backward error %.2e, |R|/|C| %.2e\n",
+                steps, eta, rel_res);
     }
     // corrections: A D + D B^T = R, X_corr <- X_corr + D, while the normwise
-    // backward error ||R|| / ((||A|| + ||B||) ||X|| + ||C||) exceeds tol
-    for (sweeps = 0; sweeps < kMaxCorrections && eta > tol; ++sweeps) {
+    // backward error ||R|| / ((||A|| + ||B||) ||X|| + ||C||) exceeds tol, and
+    // with reduced-precision factors also while the forward error estimate
+    // of iterative refinement exceeds tol: corrections shrink geometrically,
+    // so the error left after D_k is about |D_k| |D_k| / |D_{k-1}| (D_0 = X).
+    // The backward error weighs the residual by ||A|| + ||B||, so errors in
+    // the smooth modes, where A and B are small, can hide below it, and the
+    // low-precision solves leave errors in every mode.
+    const bool mixed = P->mat->opts.prec != HODLR_FP64;
+    double fwd_est = mixed ? HUGE_VAL : 0.0, prev_corr = 1.0;
+    for (sweeps = 0; sweeps < kMaxCorrections && (eta > tol || fwd_est > tol); ++sweeps) {
       TRY(residual_rhs());
       TRY(read_ranks(P, hr, s));
       const int r0 = hr[kR_R0];
@@ -1022,9 +1098,11 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
         TRY(read_frob(P, 5, &d2, s));
       }
       rel_corr = xnorm > 0 ? std::sqrt(std::max(d2, 0.0)) / xnorm : 0.0;
+      if (mixed) fwd_est = rel_corr * std::min(1.0, rel_corr / std::max(prev_corr, 1e-300));
+      prev_corr = rel_corr;
       // X_corr <- recompress([X_corr, D]).  An error e in X changes the
-      // residual by up to (||A|| + ||B||) e, so the truncation is absolute,
-      // at 0.1 tol of the backward error's scale over (||A|| + ||B||)
+      // residual by up to (||A|| ||E_y|| + ||E_x|| ||B||) e, so the truncation
+      // is absolute, at 0.1 tol of the backward error's scale over that norm
       LrJob kj{};
       kj.X.g[0] = grp(P->Zc[kpar], nx, P->ranks + kR_K0 + kpar, 0, 1.0);
       kj.X.g[1] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
@@ -1035,7 +1113,8 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
       kj.rows_x = nx;
       kj.rows_y = ny;
       kj.rank_out = P->ranks + kR_K0 + (1 - kpar);
-      kj.tau = 0.1 * tol * ((P->bound_x + P->bound_y) * xnorm + cnorm) / (P->bound_x + P->bound_y);
+      const double lnorm = P->bound_x * P->mass_y + P->mass_x * P->bound_y;
+      kj.tau = 0.1 * tol * (lnorm * xnorm + cnorm) / lnorm;
       kj.tau_rel = 0.0;
       kj.rmax = kRS;
       kj.capped = P->ranks + kR_CAP;
@@ -1046,8 +1125,11 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
       TRY(run_lr(P, kj, 7, true, s));
       kpar = 1 - kpar;
       TRY(residual(rel_res));
+      if (verbose)
+        fprintf(stderr, "hodlr_fde: 2D step: correction %d: %d ADI steps, |D|/|X| %.2e, forward error estimate "
+                "%.2e, backward error %.2e, |R|/|C| %.2e\n", sweeps + 1, steps, rel_corr, fwd_est, eta, rel_res);
     }
-    if (eta > tol) res = HODLR_ENOCONV;
+    if (eta > tol || fwd_est > tol) res = HODLR_ENOCONV;
   } else {
     rel_res = 0.0;
     eta = 0.0;
@@ -1063,7 +1145,7 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
   }
   U_next->rank = rx + rk;
   if (hr[kR_CAP] && res == HODLR_OK) res = HODLR_ERANK;
-  if (hr[kR_CAP] && getenv("HODLR_VERBOSE"))
+  if (hr[kR_CAP] && verbose)
     fprintf(stderr, "hodlr_fde: 2D step: rank cap reached in work slots 0x%x\n", unsigned(hr[kR_CAP]));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));

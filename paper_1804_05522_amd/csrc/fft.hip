@@ -65,30 +65,38 @@ __device__ inline int bitrev(int v, int logm) {
 }
 
 // --------------------------------------------------------- double-double
+// Each function below turns off floating-point contraction: an error-free
+// transformation computes a rounded product and then its rounding error, and
+// fusing that product into a later sum (which the gfx950 backend does even
+// when the product has other uses) counts the error twice.
 struct dd {
   double hi, lo;
 };
 __device__ inline dd two_sum(double a, double b) {
+  #pragma clang fp contract(off)
   double s = a + b;
   double bb = s - a;
   return dd{s, (a - (s - bb)) + (b - bb)};
 }
 __device__ inline dd dd_add(dd a, dd b) {
+  #pragma clang fp contract(off)
   dd s = two_sum(a.hi, b.hi);
   return two_sum(s.hi, s.lo + a.lo + b.lo);
 }
 __device__ inline dd dd_prod(double a, double b) {
+  #pragma clang fp contract(off)
   double p = a * b;
   return dd{p, fma(a, b, -p)};
 }
 __device__ inline dd dd_mul_d(dd a, double b) {
+  #pragma clang fp contract(off)
   dd p = dd_prod(a.hi, b);
   p.lo += a.lo * b;
   return two_sum(p.hi, p.lo);
 }
 
-// Output of the exact product for row i: y_i = s x_i + nu (d+ (Tn x + far_re) + d- (Tn^T x + far_im)),
-// or the residual b_i - y_i.  Near band in double-double.
+// Output of the exact product for row i: y_i = s (E x)_i + nu (d+ (Tn x + far_re) + d- (Tn^T x + far_im)),
+// or the residual b_i - y_i (E = I, or the P1 mass matrix / h).  Near band in double-double.
 // Chain q (terms k = q - 1 + 4t) of the compensated near-band sums of row i:
 //   (T x)_i = -sum_{j <= i+1} g_{i-j+1} x_j ;  near: i - j in [-1, w]
 //   (T^T x)_i = -sum_{j >= i-1} g_{j-i+1} x_j ;  near: j - i in [-1, w]
@@ -108,6 +116,7 @@ template <typename XA, typename GA>
 __device__ inline NearChain exact_chain_t(XA xat, GA gat, int64_t i, int64_t n, int w, int q) {
   NearChain c{0.0, 0.0, 0.0, 0.0};
   auto acc = [](double& sum, double& err, double a, double b) {
+    #pragma clang fp contract(off)
     const double p = a * b;
     const double e = fma(a, b, -p);
     const dd t = two_sum(sum, p);
@@ -134,6 +143,7 @@ __device__ inline NearChain exact_chain_t(XA xat, GA gat, int64_t i, int64_t n, 
 // values left by the inverse transform.
 __device__ inline double exact_finish(const DevPtrs& P, const Item& it, const double* x, int64_t i, const NearChain* c,
                                       double far_re, double far_im, const double* bvec) {
+  #pragma clang fp contract(off)
   dd sp = dd_add(dd_add(two_sum(c[0].ps, c[0].pc), two_sum(c[1].ps, c[1].pc)),
                  dd_add(two_sum(c[2].ps, c[2].pc), two_sum(c[3].ps, c[3].pc)));
   dd sm = dd_add(dd_add(two_sum(c[0].ms, c[0].mc), two_sum(c[1].ms, c[1].mc)),
@@ -143,7 +153,12 @@ __device__ inline double exact_finish(const DevPtrs& P, const Item& it, const do
   const int64_t gi = it.row0 + i;
   dd tsum = dd_add(dd_mul_d(sp, P.dplus[gi]), dd_mul_d(sm, P.dminus[gi]));
   tsum = dd_mul_d(tsum, it.nu);
-  dd y = dd_add(dd_prod(it.shift, x[i]), tsum);
+  const double se = it.shift * it.mass;
+  dd y = dd_add(dd_prod(se, x[i]), tsum);
+  if (it.mc != 0.0) {   // finite elements: s E x = s (2/3)(x_i + (x_{i-1} + x_{i+1})/4)
+    const dd nb = two_sum(i > 0 ? x[i - 1] : 0.0, i + 1 < it.n ? x[i + 1] : 0.0);
+    y = dd_add(y, dd_mul_d(nb, se * it.mc));
+  }
   if (bvec != nullptr) {
     dd r = dd_add(dd{bvec[i], 0.0}, dd{-y.hi, -y.lo});
     return r.hi + r.lo;

@@ -25,7 +25,7 @@ struct Item {
   int64_t n;
   int64_t row0;          // first row in concatenated vectors
   int L;                 // number of split levels; leaves live at depth L
-  int pad0;
+  int kind;              // discretization: 0 Grunwald-Letnikov differences, 1 P1 finite elements
   int64_t leaf0;         // first leaf in the global leaf arrays (2^L leaves)
   int64_t node0;         // first node in the global node table (2^(L+1)-1 nodes, all depths)
   int64_t lvl0;          // offset (doubles) of this problem's per-level factor block
@@ -40,6 +40,9 @@ struct Item {
   int64_t wsc0;          // offset (complex) of the FFT scratch of column 0 when the problems' scratch
                          //   is packed (2*M each, one column a launch)
   double alpha, nu, shift;
+  double mass;           // diagonal of the matrix that the shift multiplies: 1 (identity) or 2/3 (P1 mass / h)
+  double mc;             // its off-diagonals relative to the diagonal: 0 or 1/4
+  double fig, fig_lo;    // finite elements: 1/Gamma(4 - alpha) as a double-double
   double tolH;           // absolute trace tolerance of the Hankel compression
   double tau;            // absolute truncation tolerance eps * (lower bound of ||M||_2)
   int k;                 // Hankel rank (set on device by the compression)

@@ -487,6 +487,25 @@ __global__ void __launch_bounds__(256) k_step_update(DevPtrs P, double* u, const
   if (threadIdx.x == 0) part[int64_t(blockIdx.y) * slices + blockIdx.x] = make_double2(rd[0], ru[0]);
 }
 
+// b = E (u + fscale f) per problem (f may be null), E = I + mc (S + S^T)
+// scaled by mass: the right-hand side of an implicit Euler step of the
+// finite-element scheme (Sec. 2.2.2).  Grid (slices, problems).
+__global__ void __launch_bounds__(256) k_step_rhs(DevPtrs P, const double* u, const double* f, double fscale,
+                                                  double* b) {
+  const Item it = P.items[blockIdx.y];
+  const int64_t r0 = int64_t(blockIdx.x) * kStepRows;
+  auto v = [&](int64_t i) -> double {
+    if (i < 0 || i >= it.n) return 0.0;
+    return f ? u[it.row0 + i] + fscale * f[it.row0 + i] : u[it.row0 + i];
+  };
+  for (int q = 0; q < kStepRows / 256; ++q) {
+    const int64_t i = r0 + q * 256 + threadIdx.x;
+    if (i >= it.n) break;
+    const double vi = v(i);
+    b[it.row0 + i] = it.mc != 0.0 ? it.mass * (vi + it.mc * (v(i - 1) + v(i + 1))) : vi;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_step_check(int batch, const double2* part, int slices, double* worst) {
   for (int item = threadIdx.x; item < batch; item += blockDim.x) {
     double sd = 0.0, su = 0.0;

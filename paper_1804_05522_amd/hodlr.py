@@ -29,13 +29,24 @@ EXPORTS = [
     "fde_net_param_count", "fde_net_create", "fde_net_destroy", "fde_net_set_params", "fde_net_get_params",
     "fde_net_get_grads", "fde_net_forward", "fde_net_train_step", "hodlr_toeplitz_matvec_noalloc",
     "hodlr_workspace_size", "hodlr_build_ws", "fde2d_plan_workspace_size", "fde2d_plan_create_ws",
-    "fde2d_plan_counters",
+    "fde2d_plan_counters", "hodlr_get_weights",
 ]
+
+
+FDE_FD, FDE_FE = 0, 1        # fde_discretization
 
 
 class FdeOperator(C.Structure):
     _fields_ = [("n", C.c_int64), ("alpha", C.c_double), ("dt", C.c_double), ("dx", C.c_double),
-                ("shift", C.c_double), ("d_plus", C.c_void_p), ("d_minus", C.c_void_p)]
+                ("shift", C.c_double), ("d_plus", C.c_void_p), ("d_minus", C.c_void_p),
+                ("discretization", C.c_int)]
+
+
+def _fde_operator(o, default_shift):
+    """fde_operator from an operator dict (see operator_dict)."""
+    return FdeOperator(int(o["n"]), float(o["alpha"]), float(o["dt"]), float(o["dx"]),
+                       float(o.get("shift", default_shift)), C.c_void_p(o["d_plus"].data_ptr()),
+                       C.c_void_p(o["d_minus"].data_ptr()), int(o.get("discretization", FDE_FD)))
 
 
 class HodlrOpts(C.Structure):
@@ -107,6 +118,7 @@ def lib():
         L.hodlr_autotune.argtypes = [vp, vp, C.POINTER(HodlrTuning)]
         L.hodlr_set_tuning.argtypes = [vp, vp, C.POINTER(HodlrTuning)]
         L.hodlr_update_coefficients.argtypes = [vp, vp, C.POINTER(FdeOperator)]
+        L.hodlr_get_weights.argtypes = [vp, vp, i32, C.POINTER(dbl), i64]
         L.hodlr_ctx_set_timing.argtypes = [vp, i32]
         L.hodlr_ctx_timing_count.argtypes = [vp]
         L.hodlr_ctx_timing_entry.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(i64), C.POINTER(dbl)]
@@ -220,10 +232,7 @@ class HodlrMatrix:
     def _op_array(ops):
         arr = (FdeOperator * len(ops))()
         for i, o in enumerate(ops):
-            dp, dm = o["d_plus"], o["d_minus"]
-            arr[i] = FdeOperator(int(o["n"]), float(o["alpha"]), float(o["dt"]), float(o["dx"]),
-                                 float(o.get("shift", 1.0)), C.c_void_p(dp.data_ptr()),
-                                 C.c_void_p(dm.data_ptr()))
+            arr[i] = _fde_operator(o, 1.0)
         return arr
 
     def __init__(self, ctx: Context, ops, opts: HodlrOpts, workspace: bool = True):
@@ -257,6 +266,15 @@ class HodlrMatrix:
             raise ValueError("one operator per problem of the batch")
         check(lib().hodlr_update_coefficients(self.ctx.h, self.h, self._op_array(ops)),
               "hodlr_update_coefficients", self.ctx.h)
+
+    def weights(self, item: int, count: int):
+        """The generator g_0..g_{count-1} the library computed for problem `item` (numpy)."""
+        import numpy as np
+        out = np.zeros(int(count))
+        check(lib().hodlr_get_weights(self.ctx.h, self.h, int(item),
+                                      out.ctypes.data_as(C.POINTER(C.c_double)), int(count)),
+              "hodlr_get_weights", self.ctx.h)
+        return out
 
     def info(self) -> HodlrMatInfo:
         i = HodlrMatInfo()
@@ -324,8 +342,10 @@ class HodlrMatrix:
             pass
 
 
-def operator_dict(n, alpha, dt, dx, d_plus, d_minus, shift=1.0):
-    return dict(n=n, alpha=alpha, dt=dt, dx=dx, d_plus=d_plus, d_minus=d_minus, shift=shift)
+def operator_dict(n, alpha, dt, dx, d_plus, d_minus, shift=1.0, discretization=FDE_FD):
+    """One operator: FDE_FD (Grunwald-Letnikov differences) or FDE_FE (P1 finite elements)."""
+    return dict(n=n, alpha=alpha, dt=dt, dx=dx, d_plus=d_plus, d_minus=d_minus, shift=shift,
+                discretization=discretization)
 
 
 class Fde2dPlan:
@@ -338,12 +358,8 @@ class Fde2dPlan:
         self.ctx = ctx
         self.ws = None
         self.nx, self.ny = int(opx["n"]), int(opy["n"])
-        ox = FdeOperator(self.nx, float(opx["alpha"]), float(opx["dt"]), float(opx["dx"]),
-                         float(opx.get("shift", 0.5)), C.c_void_p(opx["d_plus"].data_ptr()),
-                         C.c_void_p(opx["d_minus"].data_ptr()))
-        oy = FdeOperator(self.ny, float(opy["alpha"]), float(opy["dt"]), float(opy["dx"]),
-                         float(opy.get("shift", 0.5)), C.c_void_p(opy["d_plus"].data_ptr()),
-                         C.c_void_p(opy["d_minus"].data_ptr()))
+        ox = _fde_operator(opx, 0.5)
+        oy = _fde_operator(opy, 0.5)
         self.opts = Fde2dOpts(float(tol), int(max_shifts), int(max_rank))
         self.h = C.c_void_p()
         if workspace:

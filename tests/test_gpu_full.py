@@ -158,7 +158,8 @@ def test_full_size_sylvester_step_residual(H, ctx, stream):
     print(f"4096^2 step: relative forward error against the oracle {ferr:.2e}")
     assert ferr <= 1e-10, ferr
     print(f"4096^2 step: rank {r}, ADI steps {info.refine_iters}, backward error {eta:.2e} "
-          f"(reported {info.backward_error:.2e}), ||R||/||C|| {nr / nc:.2e} (reported {info.rel_residual:.2e})")
+          f"(reported {info.backward_error:.2e}), ||R||/||C|| {nr / nc:.2e} (reported {info.rel_residual:.2e}), "
+          f"last correction {info.rel_correction:.2e}")
     assert eta <= 1e-10, (eta, nr / nc, r, info.refine_iters, info.rel_correction)
     assert abs(info.rel_residual - nr / nc) <= 0.05 * nr / nc + 1e-14, (info.rel_residual, nr / nc)
 

@@ -172,3 +172,16 @@ def test_2d_step_against_kronecker():
     assert np.max(np.abs(X - Xk)) <= 1e-12 * np.max(np.abs(Xk))
     R = fe.generalized_residual(st.A, st.B, st.Ex, st.Ey, X, st.rhs(U0, F))
     assert np.linalg.norm(R) <= 1e-13 * np.linalg.norm(st.rhs(U0, F))
+
+
+def test_2d_step_refinement():
+    """At a size where the Kronecker system is still solvable (n = 40), the
+    refined step is closer to the Kronecker solution than the plain
+    Bartels-Stewart step, and within a few u of it."""
+    p = W.fe_2d(n=40)
+    st = fe.FeSylvesterStepper(p)
+    U0, F = p.u0.dense(), p.f.dense()
+    Xk = fe.fe_kron_solve(st.A, st.B, st.Ex, st.Ey, st.rhs(U0, F))
+    e0 = np.linalg.norm(st.step(U0, F, refine=0) - Xk)
+    e1 = np.linalg.norm(st.step(U0, F, refine=1) - Xk)
+    assert e1 <= e0 and e1 <= 1e-14 * np.linalg.norm(Xk), (e0, e1)
