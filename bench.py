@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1, help="untimed jobs")
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--workload", default="var_1d",
-                    choices=["var_1d", "batched_1d", "fd_2d", "timedep_1d", "learned_2d"],
+                    choices=["var_1d", "batched_1d", "fd_2d", "fe_2d", "timedep_1d", "learned_2d"],
                     help="var_1d: the headline job (default); batched_1d: 256 ragged problems; "
                          "fd_2d: 4096^2 Sylvester time stepping; timedep_1d: the 256 ragged problems "
                          "with coefficients that change every step (rebuild + factor + solve per step)")
@@ -78,7 +78,7 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     ctx = H.Context(stream)
-    if args.workload == "fd_2d":
+    if args.workload in ("fd_2d", "fe_2d"):
         return bench_2d(args, ctx, stream)
     if args.workload == "timedep_1d":
         return bench_timedep(args, ctx, stream)
@@ -319,27 +319,32 @@ def bench_timedep(args, ctx, stream):
     print(json.dumps(out), flush=True)
 
 
-def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, compare=True):
+def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, compare=True, fe=False):
     """2D workload: 4096^2, alpha = (1.3, 1.7), eq. (coeff_es) coefficients,
-    rank-4 source, U^0 = 0, dt = 1/64.  One job = plan (shifts, shifted
-    factor sets) + K Sylvester steps at tolerance 1e-10 (normwise backward
-    error of every step) with the headline factor storage; value = Sylvester
-    steps per second of the whole job.  Returns the result as a dict."""
+    rank-4 source, U^0 = 0, dt = 1/64 (fe=False), or the paper's
+    finite-element experiment (fe=True: P1 elements, constant coefficients,
+    dt = 0.1, f = U^0 = indicator of [3/8, 5/8]^2, eq. (sylv-timestepping-fe)).
+    One job = plan (shifts, shifted factor sets) + K Sylvester steps at
+    tolerance 1e-10 with the headline factor storage; value = Sylvester steps
+    per second of the whole job.  Returns the result as a dict."""
     import numpy as np
     import torch
 
     import paper_1804_05522_amd as H
     import workloads as W
-    K = args.euler_steps if args.workload == "fd_2d" and args.euler_steps else 64
+    n = 4096
+    p = W.fe_2d(n=n) if fe else W.fd_2d(n=n)
+    K = args.euler_steps if args.workload in ("fd_2d", "fe_2d") and args.euler_steps else (p.steps if fe else 64)
     steps = args.steps if steps is None else steps
     warmup = args.warmup if warmup is None else warmup
     prec = args.prec if prec is None else prec
-    n = 4096
-    p = W.fd_2d(n=n)
+    disc = H.FDE_FE if fe else H.FDE_FD
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-    opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5)
-    opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5)
+    opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5, discretization=disc)
+    opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5, discretization=disc)
     F = (dev(p.f.Z.T.copy()), dev(p.f.W.T.copy()))
+    U0 = (dev(p.u0.Z.T.copy()), dev(p.u0.W.T.copy())) if fe else \
+        (torch.zeros((0, n), dtype=torch.float64, device="cuda"),) * 2
     outs = [(torch.zeros((64, n), dtype=torch.float64, device="cuda"),
              torch.zeros((64, n), dtype=torch.float64, device="cuda")) for _ in range(2)]
 
@@ -348,7 +353,7 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
         P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec=pr), tol=1e-10)
         stream.synchronize()
         t1 = time.perf_counter()
-        cur = (torch.zeros((0, n), dtype=torch.float64, device="cuda"),) * 2
+        cur = U0
         adi, worst, r = 0, 0.0, 0
         for k in range(K):
             out = outs[k % 2]
@@ -387,18 +392,20 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
     ctx.reset_timing()
     cnt = P.counters()
     P.close()
+    wl = (f"fe_2d {n}x{n} P1 elements alpha=(1.3,1.7) d=1 f=u0=indicator of [3/8,5/8]^2 dt=0.1 steps={K} tol=1e-10"
+          if fe else f"fd_2d {n}x{n} alpha=(1.3,1.7) coeff_es rank-4 source dt=1/64 steps={K} tol=1e-10")
     out = {
-        "metric": "HODLR Sylvester steps/s (2D 4096^2) at backward error 1e-10",
+        "metric": "HODLR Sylvester steps/s (2D 4096^2%s) at backward error 1e-10" % (", finite elements" if fe else ""),
         "value": K / job_s, "unit": "steps/s", "steps": steps, "warmup": warmup,
         "ms_per_step": 1e3 * job_s, "higher_is_better": True,
         "dtype": "f64", "factor_storage": {"fp64": "f64", "fp32": "f32", "bf16": "bf16+f32"}[prec],
-        "config": {"workload": f"fd_2d {n}x{n} alpha=(1.3,1.7) coeff_es rank-4 source dt=1/64 steps={K} tol=1e-10"},
+        "config": {"workload": wl},
         "phases_ms": {"plan": 1e3 * float(np.mean([q[0] for q in parts])),
                       "time_steps": 1e3 * float(np.mean([q[1] for q in parts]))},
         "per_step_ms": 1e3 * float(np.mean([q[1] for q in parts])) / K,
         "shift_pairs": J, "adi_steps_per_step": adi, "backward_error_worst": worst, "solution_rank": rank,
         "roofline": roofline_2d(ks, cnt, n),
-        "cpu_baseline": cpu_baseline_2d(K) if cpu else None,
+        "cpu_baseline": cpu_baseline_2d(K, fe) if cpu else None,
     }
     if compare and prec != "fp64":
         job_s64, _, _, _, _, _ = measure("fp64")
@@ -408,8 +415,9 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
 
 
 def bench_2d(args, ctx, stream):
-    """--workload fd_2d: the 2D job alone, as the JSON line."""
-    out = run_2d(args, ctx, stream, cpu=not args.no_cpu, compare=not args.no_compare)
+    """--workload fd_2d / fe_2d: the 2D job alone, as the JSON line."""
+    out = run_2d(args, ctx, stream, cpu=not args.no_cpu, compare=not args.no_compare,
+                 fe=args.workload == "fe_2d")
     out.update({"n_gpus": 1, "scaling": "weak", "vs_baseline": None, "data": "synthetic"})
     out["config"].update({"global_batch": 1, "parallelism": "single GPU"})
     print(json.dumps(out), flush=True)
@@ -572,20 +580,27 @@ def roofline_2d(ks, cnt, n):
     return out
 
 
-def cpu_baseline_2d(K):
-    """The oracle (dense Bartels-Stewart with cached real Schur forms) on a
-    bounded sample: n = 1024 of the same workload, Schur forms + 2 steps,
+def cpu_baseline_2d(K, fe=False):
+    """The oracle (dense Bartels-Stewart with cached real Schur forms; for
+    finite elements on the mass-reduced matrices, with its refinement step) on
+    a bounded sample: n = 1024 of the same workload, Schur forms + 2 steps,
     extrapolated to 4096^2 and K steps with its n^3 cost (Schur forms and the
     per-step triangular Sylvester solve are both cubic)."""
     import numpy as np
     import workloads as W
-    from oracle import fde2d as O2
     n0, k0 = 1024, 2
-    p = W.fd_2d(n=n0)
     t0 = time.perf_counter()
-    st = O2.SylvesterStepper(p)
+    if fe:
+        from oracle import fe as OF
+        p = W.fe_2d(n=n0)
+        st = OF.FeSylvesterStepper(p)
+        U = p.u0.dense()
+    else:
+        from oracle import fde2d as O2
+        p = W.fd_2d(n=n0)
+        st = O2.SylvesterStepper(p)
+        U = np.zeros((n0, n0))
     t1 = time.perf_counter()
-    U = np.zeros((n0, n0))
     Fd = p.f.dense()
     for _ in range(k0):
         U = st.step(U, Fd)
