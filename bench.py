@@ -49,6 +49,7 @@ def parse():
                          "with coefficients that change every step (rebuild + factor + solve per step)")
     ap.add_argument("--euler-steps", type=int, default=None, help="time steps per job (256 / 64 / 64)")
     ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--n2d", type=int, default=4096, help="grid points per direction of fd_2d / fe_2d")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-2d", action="store_true", help="var_1d only: skip the 2D 4096^2 sub-object")
@@ -332,7 +333,7 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
 
     import paper_1804_05522_amd as H
     import workloads as W
-    n = 4096
+    n = args.n2d if args.workload in ("fd_2d", "fe_2d") else 4096
     p = W.fe_2d(n=n) if fe else W.fd_2d(n=n)
     K = args.euler_steps if args.workload in ("fd_2d", "fe_2d") and args.euler_steps else (p.steps if fe else 64)
     steps = args.steps if steps is None else steps
@@ -395,7 +396,7 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
     wl = (f"fe_2d {n}x{n} P1 elements alpha=(1.3,1.7) d=1 f=u0=indicator of [3/8,5/8]^2 dt=0.1 steps={K} tol=1e-10"
           if fe else f"fd_2d {n}x{n} alpha=(1.3,1.7) coeff_es rank-4 source dt=1/64 steps={K} tol=1e-10")
     out = {
-        "metric": "HODLR Sylvester steps/s (2D 4096^2%s) at backward error 1e-10" % (", finite elements" if fe else ""),
+        "metric": "HODLR Sylvester steps/s (2D %d^2%s) at backward error 1e-10" % (n, ", finite elements" if fe else ""),
         "value": K / job_s, "unit": "steps/s", "steps": steps, "warmup": warmup,
         "ms_per_step": 1e3 * job_s, "higher_is_better": True,
         "dtype": "f64", "factor_storage": {"fp64": "f64", "fp32": "f32", "bf16": "bf16+f32"}[prec],
@@ -405,7 +406,7 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
         "per_step_ms": 1e3 * float(np.mean([q[1] for q in parts])) / K,
         "shift_pairs": J, "adi_steps_per_step": adi, "backward_error_worst": worst, "solution_rank": rank,
         "roofline": roofline_2d(ks, cnt, n),
-        "cpu_baseline": cpu_baseline_2d(K, fe) if cpu else None,
+        "cpu_baseline": cpu_baseline_2d(K, fe, n) if cpu else None,
     }
     if compare and prec != "fp64":
         job_s64, _, _, _, _, _ = measure("fp64")
@@ -580,7 +581,7 @@ def roofline_2d(ks, cnt, n):
     return out
 
 
-def cpu_baseline_2d(K, fe=False):
+def cpu_baseline_2d(K, fe=False, n_full=4096):
     """The oracle (dense Bartels-Stewart with cached real Schur forms; for
     finite elements on the mass-reduced matrices, with its refinement step) on
     a bounded sample: n = 1024 of the same workload, Schur forms + 2 steps,
@@ -605,11 +606,11 @@ def cpu_baseline_2d(K, fe=False):
     for _ in range(k0):
         U = st.step(U, Fd)
     t2 = time.perf_counter()
-    scale = (4096 / n0) ** 3
+    scale = (n_full / n0) ** 3
     t_full = (t1 - t0) * scale + K * (t2 - t1) / k0 * scale
     return {"value": K / t_full, "unit": "steps/s", "cores": cpu_threads(), "kind": "oracle",
             "sample": f"n={n0}, Schur forms {t1 - t0:.2f} s + {k0} Bartels-Stewart steps "
-                      f"({1e3 * (t2 - t1) / k0:.1f} ms/step); extrapolated to 4096^2 and {K} steps by n^3",
+                      f"({1e3 * (t2 - t1) / k0:.1f} ms/step); extrapolated to {n_full}^2 and {K} steps by n^3",
             "sample_steps_per_s": k0 / (t2 - t1)}
 
 

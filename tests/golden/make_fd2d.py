@@ -2,13 +2,15 @@
 4096 x 4096 that the full-size GPU test compares against.
 
 Calls only the oracle (Bartels-Stewart with the real Schur forms of the dense
-A and B of eq. (sylv-timestepping)) and the seeded input generators; nothing
+A and B of eq. (sylv-timestepping), plus one step of iterative refinement)
+and the seeded input generators; nothing
 here comes from the GPU path.  The step is U^1 = X with A X + X B^T = dt F
 (U^0 = 0).  X is stored as its SVD truncated where the singular values fall
 below 1e-14 of the largest (Frobenius error below 1e-13 of ||X||_F, far below
 the 1e-10 the test asks for): fd2d_n4096.npz holds U*s (4096 x r) and V.
 
-Usage: python tests/golden/make_fd2d.py   (a few minutes on 8 cores)
+Usage: python tests/golden/make_fd2d.py   (about half an hour: LAPACK's triangular
+Sylvester solver runs on one core, twice)
 """
 from __future__ import annotations
 

@@ -54,6 +54,21 @@ def test_2d_step_equals_kron_implicit_euler():
     np.testing.assert_allclose(st.step(U0, F), u1, rtol=1e-11, atol=1e-13)
 
 
+def test_2d_step_refinement():
+    """At n = 40 (Kronecker system still solvable) the refined step is at
+    least as close to the Kronecker solution as the plain Bartels-Stewart
+    step, and within a few u of it (the 4096^2 golden step uses it)."""
+    p = W.fd_2d(n=40, dt=0.1)
+    st = O2.SylvesterStepper(p)
+    rng = np.random.default_rng(5)
+    U0 = rng.standard_normal((40, 3)) @ rng.standard_normal((3, 40))
+    F = p.f.dense()
+    Xk = O2.kron_solve(st.A, st.B, U0 + p.dt * F)
+    e0 = np.linalg.norm(st.step(U0, F, refine=0) - Xk)
+    e1 = np.linalg.norm(st.step(U0, F, refine=1) - Xk)
+    assert e1 <= e0 and e1 <= 1e-14 * np.linalg.norm(Xk), (e0, e1)
+
+
 # ------------------------------------------------------------- convnet -----
 def test_conv3x3_matches_scipy_correlate():
     rng = np.random.default_rng(3)
