@@ -131,7 +131,8 @@ static __device__ __align__(256) double2 scratch[kNoallocScratchBytes / sizeof(d
 namespace {
 
 constexpr int kNCF = 16;     // columns per FFT launch group
-constexpr int kNCS = 16;     // columns per multi-column solve launch
+constexpr int kNCS = 16;     // columns per column block of a multi-column solve launch
+constexpr int kNCB = 2;      // column blocks per launch (grid y): 32 columns in one set of launches
 constexpr int kFftSmallMax = 13;
 
 struct DevBuf {
@@ -178,7 +179,9 @@ struct hodlr_mat_s {
   double* partU = nullptr;
   double* zL = nullptr;
   double* zU = nullptr;
-  double* ytmp = nullptr;     // total_n x kNCS
+  double* ytmp = nullptr;     // total_n x (kNCS kNCB)
+  int64_t part_block = 0;     // doubles between the column blocks of partL / partU
+  int64_t z_block = 0;        // and of zL / zU
   double* rbuf = nullptr;     // total_n x kNCS
   double* dbuf = nullptr;
   double* bbuf = nullptr;
@@ -531,23 +534,29 @@ void launch_solve_t(hodlr_mat m, SolveFactors<TF, TL> F, const WorkUnit* wu, int
   const int64_t lv = m->total_leaves;
   if (NC == 1) {                        // one right-hand side: row-per-lane kernels
     HFDE_LAUNCH((k_project1<TF>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, wu, 0, IL, x, m->partL, lv);
-    if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 0, 1, m->partL, m->zL, lv);
+    if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 0, 1, m->partL, m->zL, lv, 1,
+                         int64_t(0), int64_t(0));
     HFDE_LAUNCH((k_expand1<TF, TL>), dim3(nwu), dim3(256), kSolve1Lds, s, m->P, F, wu, 0, x, m->ytmp, m->zL,
                        m->partU, lv, m->b);
-    if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 1, 1, m->partU, m->zU, lv);
+    if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 1, 1, m->partU, m->zU, lv, 1,
+                         int64_t(0), int64_t(0));
     HFDE_LAUNCH((k_expand1<TF, TL>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 1, m->ytmp, y, m->zU,
                        (double*)nullptr, lv, m->b);
     (void)ldx;
     (void)ldy;
     return;
   }
-  HFDE_LAUNCH((k_project<TF, NC>), dim3(nwu), dim3(256), 0, s, m->P, wu, 0, IL, x, ldx, nc, m->partL, lv);
-  if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 0, nc, m->partL, m->zL, lv);
-  HFDE_LAUNCH((k_expand<TF, TL, NC>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 0, x, ldx, m->ytmp,
-                     m->total_n, nc, m->zL, m->partU, lv, m->b);
-  if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu), dim3(256), 0, s, m->P, nu, 1, nc, m->partU, m->zU, lv);
-  HFDE_LAUNCH((k_expand<TF, TL, NC>), dim3(nwu), dim3(256), 0, s, m->P, F, wu, 1, m->ytmp, m->total_n, y,
-                     ldy, nc, m->zU, (double*)nullptr, lv, m->b);
+  // nc <= kNCB * NC columns in kNCB column blocks (grid y), each with its own
+  // regions of the partials, node sums and ytmp
+  const unsigned nb = unsigned((nc + NC - 1) / NC);
+  const int64_t ps = m->part_block, zs = m->z_block;
+  HFDE_LAUNCH((k_project<TF, NC>), dim3(nwu, nb), dim3(256), 0, s, m->P, wu, 0, IL, x, ldx, nc, m->partL, lv, ps);
+  if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu, nb), dim3(256), 0, s, m->P, nu, 0, nc, m->partL, m->zL, lv, NC, ps, zs);
+  HFDE_LAUNCH((k_expand<TF, TL, NC>), dim3(nwu, nb), dim3(256), 0, s, m->P, F, wu, 0, x, ldx, m->ytmp,
+                     m->total_n, nc, m->zL, m->partU, lv, m->b, ps, zs);
+  if (nnu) HFDE_LAUNCH(k_reduce, dim3(nnu, nb), dim3(256), 0, s, m->P, nu, 1, nc, m->partU, m->zU, lv, NC, ps, zs);
+  HFDE_LAUNCH((k_expand<TF, TL, NC>), dim3(nwu, nb), dim3(256), 0, s, m->P, F, wu, 1, m->ytmp, m->total_n, y,
+                     ldy, nc, m->zU, (double*)nullptr, lv, m->b, ps, zs);
 }
 
 // y <- M_low^{-1} x at precision `prec` (x and y may alias: the first
@@ -555,8 +564,8 @@ void launch_solve_t(hodlr_mat m, SolveFactors<TF, TL> F, const WorkUnit* wu, int
 // leaves / nodes are listed (all by default).
 void launch_solve_units(hodlr_mat m, int prec, const WorkUnit* wu, int nwu, const NodeUnit* nu, int nnu,
                         const double* x, int64_t ldx, double* y, int64_t ldy, int nc, hipStream_t s) {
-  for (int c0 = 0; c0 < nc; c0 += kNCS) {
-    const int cn = std::min(kNCS, nc - c0);
+  for (int c0 = 0; c0 < nc; c0 += kNCS * kNCB) {
+    const int cn = std::min(kNCS * kNCB, nc - c0);
     const double* xc = x + int64_t(c0) * ldx;
     double* yc = y + int64_t(c0) * ldy;
     if (prec == HODLR_MIXED_FP32) {
@@ -1301,12 +1310,15 @@ static hodlr_status build_impl(hodlr_ctx ctx, const fde_operator* ops, int batch
   ALLOC(P.diag, 4 * batch);
   ALLOC(m->wu, m->nwu);
   ALLOC(m->nu, m->nnu);
+  // the solve's work arrays hold kNCB column blocks of kNCS columns
   const int64_t part_sz = leaf0 * std::max(1, m->Lmax) * kRS * kNCS;
-  ALLOC(m->partL, part_sz);
-  ALLOC(m->partU, part_sz);
-  ALLOC(m->zL, 2 * node0 * kRS * kNCS);   // the operator matvec stores two sides per node
-  ALLOC(m->zU, 2 * node0 * kRS * kNCS);
-  ALLOC(m->ytmp, row0 * kNCS);
+  m->part_block = part_sz;
+  m->z_block = node0 * kRS * kNCS;
+  ALLOC(m->partL, part_sz * kNCB);
+  ALLOC(m->partU, part_sz * kNCB);
+  ALLOC(m->zL, std::max(2, kNCB) * node0 * kRS * kNCS);   // the operator matvec stores two sides per node
+  ALLOC(m->zU, std::max(2, kNCB) * node0 * kRS * kNCS);
+  ALLOC(m->ytmp, row0 * kNCS * kNCB);
   ALLOC(m->rbuf, row0 * kNCS);
   ALLOC(m->dbuf, row0 * kNCS);
   ALLOC(m->bbuf, row0 * kNCS);

@@ -86,11 +86,18 @@ __device__ void leaf_project(const DevPtrs& P, const Item& it, int leaf, const N
   }
 }
 
+// Column blocks: blockIdx.y = cb takes columns [cb NC, min(nc, (cb + 1) NC)) of
+// a launch's nc; its partials and node sums live in their own regions of the
+// work arrays (pstride, zstride apart), laid out as for a launch of its own.
 template <typename TF, int NC>
 __global__ void __launch_bounds__(256) k_project(DevPtrs P, const WorkUnit* wu, int which, const TF* Bb,
                                                  const double* x, int64_t ldx, int nc, double* part,
-                                                 int64_t leaves) {
+                                                 int64_t leaves, int64_t pstride) {
   __shared__ double vl[64 * NC];
+  const int cb = blockIdx.y;
+  x += int64_t(cb) * NC * ldx;
+  part += cb * pstride;
+  nc = min(NC, nc - cb * NC);
   const WorkUnit w = wu[blockIdx.x];
   const Item it = P.items[w.item];
   const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
@@ -109,8 +116,13 @@ __global__ void __launch_bounds__(256) k_project(DevPtrs P, const WorkUnit* wu, 
 // child.  256 threads = groups x (rank, column) entries; each group sums a
 // strided subset of the leaves, groups are combined in a fixed order.
 __global__ void __launch_bounds__(256) k_reduce(DevPtrs P, const NodeUnit* nu, int which, int nc,
-                                                const double* part, double* z, int64_t leaves) {
+                                                const double* part, double* z, int64_t leaves, int ncb,
+                                                int64_t pstride, int64_t zstride) {
   __shared__ double red[256];
+  const int cb = blockIdx.y;                 // column block of ncb columns (see k_project)
+  part += cb * pstride;
+  z += cb * zstride;
+  nc = min(ncb, nc - cb * ncb);
   const NodeUnit u = nu[blockIdx.x];
   const Item it = P.items[u.item];
   const int32_t* ranks = which == 0 ? P.rankL : P.rankU;
@@ -162,11 +174,18 @@ __global__ void __launch_bounds__(256) k_reduce(DevPtrs P, const NodeUnit* nu, i
 template <typename TF, typename TL, int NC>
 __global__ void __launch_bounds__(256) k_expand(DevPtrs P, SolveFactors<TF, TL> F, const WorkUnit* wu, int which,
                                                 const double* xin, int64_t ldx, double* yout, int64_t ldy,
-                                                int nc, const double* z, double* next_part, int64_t leaves, int b) {
+                                                int nc, const double* z, double* next_part, int64_t leaves, int b,
+                                                int64_t pstride, int64_t zstride) {
   __shared__ double vl[64 * NC];
   __shared__ double yl[4][64 * NC];
   __shared__ double zl[3][kRS * NC];                 // z of a level node, row-major (q, c)
   __shared__ int pm[64];
+  const int cb = blockIdx.y;                         // column block (see k_project)
+  xin += int64_t(cb) * NC * ldx;
+  yout += int64_t(cb) * NC * ldy;
+  z += cb * zstride;
+  if (next_part != nullptr) next_part += cb * pstride;
+  nc = min(NC, nc - cb * NC);
   const WorkUnit w = wu[blockIdx.x];
   const Item it = P.items[w.item];
   const Node lf = P.nodes[node_index(it, it.L, w.leaf)];
