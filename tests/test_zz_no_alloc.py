@@ -25,8 +25,10 @@ def H():
     return H
 
 
-def build(H, ctx, probs):
-    ops = [H.operator_dict(p.n, p.alpha, p.dt, p.h, dev(p.d_plus), dev(p.d_minus)) for p in probs]
+def build(H, ctx, probs, kinds=None):
+    kinds = kinds or [0] * len(probs)
+    ops = [H.operator_dict(p.n, p.alpha, p.dt, p.h, dev(p.d_plus), dev(p.d_minus), discretization=k)
+           for p, k in zip(probs, kinds)]
     return H.HodlrMatrix(ctx, ops, H.default_opts(tol=1e-10))
 
 
@@ -51,8 +53,8 @@ def test_noalloc_product_equals_the_product(H):
         A = build(H, ctx, big)
         compare(H, ctx, stream, A, 2 * 65536, 3, 1)
         A.close()
-        small = [W.plain_1d(), W.var_1d(1.5, n=3000)]              # second call: smaller input
-        B = build(H, ctx, small)
+        small = [W.plain_1d(), W.var_1d(1.5, n=3000)]              # second call: smaller input,
+        B = build(H, ctx, small, kinds=[H.FDE_FD, H.FDE_FE])      # one finite-element operator
         compare(H, ctx, stream, B, 1024 + 3000, 2, 2)
         B.close()
         over = [W.var_1d(1.4, n=300000)]                           # 2 x 2^20 complex: 32 MiB
