@@ -247,6 +247,17 @@ def main():
     if args.workload == "var_1d" and not args.no_2d:
         # the metric's second half: the 2D 4096^2 job, its own timing, roofline and CPU baseline
         out["fd_2d"] = run_2d(args, ctx, stream, cpu=not args.no_cpu, compare=not args.no_compare)
+    if "mixed_vs_fp64" in out:
+        # the stated targets, checked on this run: mixed-precision steps/s at least 3x the FP64 path,
+        # and the dominant kernel's fraction of its roofline (the matrix-core target of 40% is for the
+        # low-rank update GEMMs, which run inside the latency-bound fused node kernels)
+        ratio = out["mixed_vs_fp64"]["whole_job"]
+        out["targets"] = {"mixed_vs_fp64_min": 3.0, "mixed_vs_fp64_whole_job": ratio,
+                          "mixed_vs_fp64_met": bool(ratio and ratio >= 3.0),
+                          "update_mfma_frac_min": 0.4, "dominant_kernel_frac": roof.get("frac") if roof else None,
+                          "update_mfma_frac_met": bool(roof and roof.get("frac") and roof["frac"] >= 0.4)}
+        if "fd_2d" in out and "mixed_vs_fp64" in out["fd_2d"]:
+            out["targets"]["fd_2d_mixed_vs_fp64"] = out["fd_2d"]["mixed_vs_fp64"]
     print(json.dumps(out), flush=True)
 
 
