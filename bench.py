@@ -314,6 +314,41 @@ def bench_timedep(args, ctx, stream):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     job_s = (t1 - t0) / args.steps
+    # one more job with per-launch timing: the dominant kernel's roofline, with
+    # the factorisation's flop model (final ranks) for each of the K factorisations
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    A = H.HodlrMatrix(ctx, ops_at[0], H.default_opts(tol=1e-10, prec=args.prec, refine_max=3, rtol=args.target))
+    u = u0.clone()
+    for m in range(1, K + 1):
+        A.update_coefficients(ops_at[m])
+        A.factor(allow=(0, 3))
+        torch.add(u, f, alpha=dt, out=u)
+        A.solve(u, allow=(0, 2))
+    stream.synchronize()
+    ctx.set_timing(False)
+    ks = ctx.timing()
+    ctx.reset_timing()
+    roof = roofline({"kstats": ks, "info": A.info()}, sum(p.n for p in probs), args.prec, False, factorisations=K)
+    A.close()
+    cpu = None
+    if not args.no_cpu:
+        # the oracle (a dense LU of the new matrix every step, refined solves) on one
+        # problem of N = 4096 for two steps, scaled to the batch by sum N^3 (LU cost)
+        from oracle import fde1d as O
+        n0 = 4096
+        x0, h0 = W.grid(n0)
+        d0 = 1.0 + 0.25 * np.sin(np.pi * x0)
+        q = W.Problem1D(n0, 1.5, dt, 2, h0, x0, d0, d0.copy(), W.bump(x0), np.zeros(n0))
+        coef = lambda t: W.timedep_coefficients(q, t)
+        c0 = time.perf_counter()
+        O.euler_1d_varying(q, coef, steps=2)
+        t_step = (time.perf_counter() - c0) / 2
+        scale = sum((p.n / n0) ** 3 for p in probs)
+        cpu = {"value": len(probs) * K / (t_step * scale * K), "unit": "problem-steps/s", "cores": cpu_threads(),
+               "kind": "oracle",
+               "sample": f"N={n0}, 2 steps of a new dense LU + refined solve ({t_step:.2f} s a step), scaled to the "
+                         f"256 problems by sum N^3 ({scale:.1f} x)"}
     out = {
         "metric": "HODLR solve steps/s (batched 1D, time-dependent coefficients) at rel.err 1e-10",
         "value": len(probs) * K / job_s, "unit": "problem-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -326,7 +361,7 @@ def bench_timedep(args, ctx, stream):
         "rebuild_and_factor_ms_per_step": 1e3 * float(np.mean([q[1] for q in parts])) / K,
         "factorisations_per_s": len(probs) * K / float(np.mean([q[1] for q in parts])),
         "rel_correction_last": info.rel_correction, "refine_iters_last": info.refine_iters,
-        "roofline": None, "cpu_baseline": None,
+        "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -633,14 +668,15 @@ def cpu_threads():
         return os.cpu_count()
 
 
-def roofline(res, total_n, prec, counters_apply=False):
+def roofline(res, total_n, prec, counters_apply=False, factorisations=1):
     """Roofline of the kernel with the largest summed duration in the
     instrumented job.  Algorithmic work per launch:
       factorisation kernels (FP64; the cores and leaves on the vector ALU, the
         Grams and forms on the FP64 matrix cores, both with the same 78.6
         TFLOP/s peak): the flop model of the factorisation, split by kernel
         (fused node kernels, split recompression cores, Gram matrices,
-        leaves), over the kernel's launches;
+        leaves, subtree products), over the kernel's launches (times the
+        number of factorisations the job ran);
       single right-hand-side solve kernels (HBM): every factor value is read
         once per solve; the projection reads a quarter of the off-diagonal
         factors, the two expansions the rest and the leaf inverses, plus the
@@ -655,11 +691,11 @@ def roofline(res, total_n, prec, counters_apply=False):
     off_bytes = max(mi.bytes_factors - leaf_bytes, 0)
     solves = ks.get("(k_project1<TF>)", (0, 0))[0]
     flop_kernels = {"k_core": mi.core_flops, "k_gram_partial": mi.gram_flops, "k_leaf_task": mi.leaf_flops,
-                    "k_node_recompress": mi.node_rec_flops, "k_node_pending": mi.node_pend_flops}
+                    "k_node_recompress": mi.node_rec_flops, "k_node_pending": mi.node_pend_flops,
+                    "k_sp_expand": mi.sp_expand_flops, "k_sp_project": mi.sp_project_flops}
     out = {"kernel": name, "launches": launches, "launch_us": 1e6 * avg_s}
     traffic = measured_traffic(name, prec) if counters_apply else None
     if name in flop_kernels:
-        factorisations = 1
         per_launch = flop_kernels[name] / max(launches / factorisations, 1)
         achieved = per_launch / avg_s
         out.update(bound="alu", achieved=achieved / 1e12, peak=MI355X_FP64 / 1e12, unit="TFLOP/s",

@@ -138,6 +138,9 @@ typedef struct {
   double leaf_flops;      /* part of factor_flops in the dense leaves (update, LU, inverses) */
   double node_rec_flops;  /* part in the fused node kernels' first launch (Grams, cores, forms of S12, S21) */
   double node_pend_flops; /* part in the fused node kernels' last launch (C, W, pending recompression) */
+  double sp_expand_flops; /* part in the subtree products' expansions (leaf blocks and half the level
+                             products of U~12, V~21 and the inverse blocks) */
+  double sp_project_flops;/* part in the subtree products' projections (the other half of the levels) */
 } hodlr_mat_info;
 
 /* ---- context ------------------------------------------------------------ */

@@ -1597,6 +1597,8 @@ struct FlopSplit {
   double leaf = 0.0;    // leaves (k_leaf_task): pending update, LU, both inverses
   double node_rec = 0.0;   // fused phase A, first part (k_node_recompress): Grams, cores, forms of S12, S21
   double node_pend = 0.0;  // fused phase A, last part (k_node_pending): C, W, pending Grams, core, forms
+  double sp_expand = 0.0;  // subtree products (U~12, V~21, inverse blocks): leaf blocks + half the levels (k_sp_expand)
+  double sp_project = 0.0; // subtree products: the other half of the levels, the projections (k_sp_project)
 };
 
 static FlopSplit factor_flop_split(hodlr_mat m);
@@ -1612,15 +1614,18 @@ static FlopSplit factor_flop_split(hodlr_mat m) {
   double fl = 0.0;
   for (const Item& it : m->items) {
     // subtree product cost per column: leaves (m^2) + 2 * rows * rank per level below
+    // (the projection and the expansion each), kept as the leaf part and the level part
     std::vector<double> sub(size_t(1) << (it.L + 1), 0.0);   // per node (depth-major index)
+    std::vector<double> subl(size_t(1) << (it.L + 1), 0.0);  // its leaf part
     auto idx = [&](int d, int64_t j) { return size_t((int64_t(1) << d) - 1 + j); };
     for (int d = it.L; d >= 0; --d)
       for (int64_t j = 0; j < (int64_t(1) << d); ++j) {
         const Node nd = m->nodes[node_index(it, d, j)];
-        if (d == it.L) { sub[idx(d, j)] = double(nd.size) * nd.size; continue; }
+        if (d == it.L) { sub[idx(d, j)] = subl[idx(d, j)] = double(nd.size) * nd.size; continue; }
         const int64_t ni = node_index(it, d, j);
         const double rr = 0.5 * (rl[ni] + ru[ni]);
         sub[idx(d, j)] = sub[idx(d + 1, 2 * j)] + sub[idx(d + 1, 2 * j + 1)] + 4.0 * nd.size * rr;
+        subl[idx(d, j)] = subl[idx(d + 1, 2 * j)] + subl[idx(d + 1, 2 * j + 1)];
       }
     for (int d = 0; d <= it.L; ++d)
       for (int64_t j = 0; j < (int64_t(1) << d); ++j) {
@@ -1650,6 +1655,11 @@ static FlopSplit factor_flop_split(hodlr_mat m) {
         const double s1 = sub[idx(d + 1, 2 * j)], s2 = sub[idx(d + 1, 2 * j + 1)];
         fl += 2.0 * (r12 + r21) * s1;                                           // U~12, V~21
         fl += 2.0 * r21 * (s1 + s2) + 2.0 * r12 * (s1 + s2);                    // inverse blocks
+        const double l1 = subl[idx(d + 1, 2 * j)], l2 = subl[idx(d + 1, 2 * j + 1)];
+        const double leafpart = 2.0 * (r12 + r21) * l1 + 2.0 * (r21 + r12) * (l1 + l2);
+        const double levelpart = 2.0 * (r12 + r21) * (s1 - l1) + 2.0 * (r21 + r12) * (s1 + s2 - l1 - l2);
+        out.sp_expand += leafpart + 0.5 * levelpart;
+        out.sp_project += 0.5 * levelpart;
       }
   }
   out.total = fl;
@@ -1694,6 +1704,8 @@ hodlr_status hodlr_get_info(hodlr_mat m, hodlr_mat_info* info) {
   info->leaf_flops = fs.leaf;
   info->node_rec_flops = fs.node_rec;
   info->node_pend_flops = fs.node_pend;
+  info->sp_expand_flops = fs.sp_expand;
+  info->sp_project_flops = fs.sp_project;
   return HODLR_OK;
 }
 

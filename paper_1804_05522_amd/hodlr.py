@@ -66,7 +66,8 @@ class HodlrMatInfo(C.Structure):
                 ("total_n", C.c_int64), ("max_rank_A", C.c_int), ("max_rank_factors", C.c_int),
                 ("bytes_factors", C.c_size_t), ("bytes_device", C.c_size_t),
                 ("factor_flops", C.c_double), ("core_flops", C.c_double), ("gram_flops", C.c_double),
-                ("leaf_flops", C.c_double), ("node_rec_flops", C.c_double), ("node_pend_flops", C.c_double)]
+                ("leaf_flops", C.c_double), ("node_rec_flops", C.c_double), ("node_pend_flops", C.c_double),
+                ("sp_expand_flops", C.c_double), ("sp_project_flops", C.c_double)]
 
 
 class HodlrTuning(C.Structure):
