@@ -217,6 +217,30 @@ __global__ void k_adi_update(int64_t nx, int64_t ny, const int32_t* rdev, double
   }
 }
 
+// The residual update of one shift pair fused with the copy that feeds the
+// next pair's solves: G -= w E_x Z, H -= w E_y Y (as k_adi_update), and the
+// updated columns also go to the next pair's rows of the solve workspace
+// (xg, xh).  Z, Y and xg, xh are rows of different problems of the shifted
+// batch, so nothing read is written.
+__global__ void k_adi_update_copy(int64_t nx, int64_t ny, const int32_t* rdev, double w, const double* Z,
+                                  int64_t ldz, const double* Y, int64_t ldy, double* G, int64_t ldg, double* H,
+                                  int64_t ldh, double* xg, double* xh, int64_t ldxn, MassPair E) {
+  const int r = *rdev;
+  const int64_t tot = (nx + ny) * r;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = e / (nx + ny), i = e % (nx + ny);
+    if (i < nx) {
+      const double v = G[i + c * ldg] - w * mass_at(Z + c * ldz, i, nx, E.mx, E.cx);
+      G[i + c * ldg] = v;
+      xg[i + c * ldxn] = v;
+    } else {
+      const double v = H[(i - nx) + c * ldh] - w * mass_at(Y + c * ldy, i - nx, ny, E.my, E.cy);
+      H[(i - nx) + c * ldh] = v;
+      xh[(i - nx) + c * ldxn] = v;
+    }
+  }
+}
+
 // dst = scale * E src on `cols` columns of `rows` rows (E = mass (I + mc (S + S^T))).
 __global__ void k_mass_cols(int64_t rows, int cols, double mass, double mc, const double* src, int64_t lds_,
                             double* dst, int64_t ldd, double scale) {

@@ -326,17 +326,30 @@ hodlr_status compress_dense(fde2d_plan P, const float* X, double tau_rel, uint64
 hodlr_status enqueue_main_block(fde2d_plan P, int b, int nc, hipStream_t s) {
   hodlr_mat m = P->mat;
   const int64_t nx = P->nx, ny = P->ny, tn = m->total_n;
-  for (int jo = 4 * b; jo < std::min(4 * b + 4, P->J); ++jo) {
+  const MassPair E{P->mass_x, P->mc_x, P->mass_y, P->mc_y};
+  const int jend = std::min(4 * b + 4, P->J);
+  for (int jo = 4 * b; jo < jend; ++jo) {
     const int j = P->order[jo];
     const Item& ix = m->items[j];
     const Item& iy = m->items[P->J + j];
-    copy_cols(nx, P->ranks + kR_R0, 0, P->G, nx, P->xin + ix.row0, tn, 1.0, s);
-    copy_cols(ny, P->ranks + kR_R0, 0, P->H, ny, P->xin + iy.row0, tn, 1.0, s);
+    if (jo == 4 * b) {       // the block's first pair: G, H into its rows of the workspace
+      copy_cols(nx, P->ranks + kR_R0, 0, P->G, nx, P->xin + ix.row0, tn, 1.0, s);
+      copy_cols(ny, P->ranks + kR_R0, 0, P->H, ny, P->xin + iy.row0, tn, 1.0, s);
+    } else {                 // the previous pair's update, writing the new G, H into this pair's rows too
+      const int jp = P->order[jo - 1];
+      const Item& px = m->items[jp];
+      const Item& py = m->items[P->J + jp];
+      HFDE_LAUNCH(k_adi_update_copy, dim3(256), dim3(256), 0, s, nx, ny, P->ranks + kR_R0, P->p[jp] + P->q[jp],
+                  P->xin + px.row0, tn, P->xin + py.row0, tn, P->G, nx, P->H, ny, P->xin + ix.row0,
+                  P->xin + iy.row0, tn, E);
+    }
     launch_solve_units(m, m->opts.prec, P->pair_wu + P->pwu_off[j], P->pwu_cnt[j], P->pair_nu + P->pnu_off[j],
                        P->pnu_cnt[j], P->xin, tn, P->xin, tn, nc, s);
-    const double w = P->p[j] + P->q[j];
-    HFDE_LAUNCH(k_adi_update, dim3(256), dim3(256), 0, s, nx, ny, P->ranks + kR_R0, w, P->xin + ix.row0, tn,
-                       P->xin + iy.row0, tn, P->G, nx, P->H, ny, MassPair{P->mass_x, P->mc_x, P->mass_y, P->mc_y});
+    if (jo + 1 == jend) {    // the block's last pair: its update alone (the block's norm reads G, H)
+      const double w = P->p[j] + P->q[j];
+      HFDE_LAUNCH(k_adi_update, dim3(256), dim3(256), 0, s, nx, ny, P->ranks + kR_R0, w, P->xin + ix.row0, tn,
+                  P->xin + iy.row0, tn, P->G, nx, P->H, ny, E);
+    }
   }
   LrJob nj{};
   nj.X.g[0] = grp(P->G, nx, P->ranks + kR_R0, 0, 1.0);
