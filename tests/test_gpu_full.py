@@ -164,6 +164,47 @@ def test_full_size_sylvester_step_residual(H, ctx, stream):
     assert abs(info.rel_residual - nr / nc) <= 0.05 * nr / nc + 1e-14, (info.rel_residual, nr / nc)
 
 
+def test_full_size_fe_sylvester_step(H, ctx, stream):
+    """One step of the paper's finite-element workload at 4096 x 4096 (P1
+    elements, alpha = (1.3, 1.7), dt = 0.1, U^0 = F = indicator of
+    [3/8, 5/8]^2) with the benchmark's options (FP32 factors, tolerance
+    1e-10), against the oracle's step stored by tests/golden/make_fe2d.py
+    (Bartels-Stewart on the mass-reduced matrices plus one refinement step):
+    relative forward error below 1e-10, and the normwise backward error of the
+    generalized equation, formed from the oracle's dense A and B and the
+    tridiagonal mass matrices (||A||, ||B||, ||E|| replaced by their largest
+    diagonal entries), below 1e-10."""
+    from oracle import fe as OF
+    n = 4096
+    p = W.fe_2d(n=n)
+    with torch.cuda.stream(stream):
+        opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5, discretization=H.FDE_FE)
+        opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5, discretization=H.FDE_FE)
+        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec="fp32"), tol=1e-10)
+        cur = (dev(p.u0.Z.T.copy()), dev(p.u0.W.T.copy()))
+        F = (dev(p.f.Z.T.copy()), dev(p.f.W.T.copy()))
+        out = (torch.zeros((64, n), dtype=torch.float64, device="cuda"),
+               torch.zeros((64, n), dtype=torch.float64, device="cuda"))
+        r, info = P.step(cur, F, p.dt, out)
+        stream.synchronize()
+        Z = out[0][:r].cpu().numpy().T
+        Wf = out[1][:r].cpu().numpy().T
+        P.close()
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fe2d_n4096.npz"))
+    Xref = g["Z"] @ g["W"].T
+    X = Z @ Wf.T
+    ferr = np.linalg.norm(X - Xref) / np.linalg.norm(Xref)
+    A, B, _, _ = OF.fe_sylvester_coefficients(p)
+    C = OF.mass_apply(OF.mass_apply(p.u0.dense() + p.dt * p.f.dense()).T).T
+    R = C - (A @ Z) @ OF.mass_apply(Wf).T - OF.mass_apply(Z) @ (B @ Wf).T     # C - A X E_y - E_x X B^T
+    a, b = np.max(np.diag(A)), np.max(np.diag(B))
+    eta = np.linalg.norm(R) / ((a + b) * (2 / 3) * np.linalg.norm(X) + np.linalg.norm(C))
+    print(f"fe 4096^2 step: rank {r}, ADI steps {info.refine_iters}, forward error {ferr:.2e}, "
+          f"backward error {eta:.2e} (reported {info.backward_error:.2e}), last correction {info.rel_correction:.2e}")
+    assert ferr <= 1e-10, ferr
+    assert eta <= 1e-10, eta
+
+
 def test_full_size_batched_step_sampled_rows(H, ctx, stream):
     """The batched workload (256 ragged problems, N from 2048 to 32768, small
     and four-step transform lengths in one batch) in the benchmark's
