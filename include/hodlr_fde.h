@@ -396,7 +396,8 @@ int fde2d_plan_shifts(fde2d_plan p, double* p_shifts, double* q_shifts, int cap)
  * terms, and while the normwise backward error info->backward_error exceeds
  * opts.tol, or (reduced-precision factors) while the forward-error estimate
  * of iterative refinement |D_k|^2 / (|D_{k-1}| |X_main|) (D_0 = X_main; at
- * least one correction) exceeds opts.tol (at most 6 times), a correction
+ * least one correction; BF16 factors, whose late corrections shrink slowly and
+ * unsteadily: |D_k| / |X_main|) exceeds opts.tol (at most 6 times), a correction
  * sweep solves A D + D B^T = R (R
  * compressed by a randomized range finder on its factors) and D joins the
  * correction term X_corr (recompressed so that its truncation changes the

@@ -1086,8 +1086,12 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
     // so the error left after D_k is about |D_k| |D_k| / |D_{k-1}| (D_0 = X).
     // The backward error weighs the residual by ||A|| + ||B||, so errors in
     // the smooth modes, where A and B are small, can hide below it, and the
-    // low-precision solves leave errors in every mode.
+    // low-precision solves leave errors in every mode.  With BF16 factors the
+    // error of a shifted solve, about u_bf16 kappa(A + q E), nears 1 for the
+    // small shifts: the late corrections shrink by only 0.3-0.5 each and not
+    // steadily, so the ratio undershoots; there the estimate is |D_k| itself.
     const bool mixed = P->mat->opts.prec != HODLR_FP64;
+    const bool slow = P->mat->opts.prec == HODLR_MIXED_BF16;
     double fwd_est = mixed ? HUGE_VAL : 0.0, prev_corr = 1.0;
     for (sweeps = 0; sweeps < kMaxCorrections && (eta > tol || fwd_est > tol); ++sweeps) {
       TRY(residual_rhs());
@@ -1111,7 +1115,8 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
         TRY(read_frob(P, 5, &d2, s));
       }
       rel_corr = xnorm > 0 ? std::sqrt(std::max(d2, 0.0)) / xnorm : 0.0;
-      if (mixed) fwd_est = rel_corr * std::min(1.0, rel_corr / std::max(prev_corr, 1e-300));
+      if (mixed)
+        fwd_est = slow ? rel_corr : rel_corr * std::min(1.0, rel_corr / std::max(prev_corr, 1e-300));
       prev_corr = rel_corr;
       // X_corr <- recompress([X_corr, D]).  An error e in X changes the
       // residual by up to (||A|| ||E_y|| + ||E_x|| ||B||) e, so the truncation

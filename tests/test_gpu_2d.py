@@ -183,3 +183,36 @@ def test_mid_size_steps_with_the_benchmark_options(H, ctx):
         assert abs(info.rel_residual - res) <= 0.05 * res + 1e-14, (info.rel_residual, res)
         cur = (out[0][:r].contiguous(), out[1][:r].contiguous())
     P.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16"])
+def test_bf16_factors_2d(H, ctx, prec):
+    """BF16 factors in the 2D step (the first sweep stops at 1e-3, the
+    corrections with the exact residual do the rest): two steps at n = 512
+    against the oracle's (refined) Bartels-Stewart steps at tol 1e-8, forward
+    error and backward error below it.  The late corrections shrink by only
+    0.3-0.5 each with BF16 factors (the shifted solves' error nears 1 for the
+    small shifts), so the step stops on the size of the last correction; six
+    corrections reach a few 1e-9 here."""
+    n = 512
+    p = W.fd_2d(n=n, variable=True, dt=1 / 64)
+    opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5)
+    opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5)
+    tol = 1e-8
+    P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=tol, prec=prec), tol=tol)
+    st = O2.SylvesterStepper(p)
+    U = np.zeros((n, n))
+    cur = (torch.zeros((0, n), dtype=torch.float64, device="cuda"),) * 2
+    for k in range(2):
+        out = (torch.zeros((64, n), dtype=torch.float64, device="cuda"),
+               torch.zeros((64, n), dtype=torch.float64, device="cuda"))
+        r, info = P.step(cur, lr_dev(p.f.Z, p.f.W), p.dt, out)
+        X = out[0][:r].cpu().numpy().T @ out[1][:r].cpu().numpy()
+        U = st.step(U, p.f.dense())
+        err = np.linalg.norm(X - U) / np.linalg.norm(U)
+        print(f"bf16 n={n} step {k + 1}: adi {info.refine_iters} rel.err {err:.2e} "
+              f"backward error {info.backward_error:.2e} correction {info.rel_correction:.2e}")
+        assert info.status == 0, info.status
+        assert err <= tol and info.backward_error <= tol, (err, info.backward_error)
+        cur = (out[0][:r].contiguous(), out[1][:r].contiguous())
+    P.close()
