@@ -415,6 +415,30 @@ int fde2d_plan_shifts(fde2d_plan p, double* p_shifts, double* q_shifts, int cap)
 hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* U_m,
                                   const lr_matrix* F, double dt, lr_matrix* U_next,
                                   hodlr_info* info);
+/* fde2d_sylvester_step with the extended Krylov subspace method of Sec. 4.3
+ * in place of each fADI sweep (the first solve and every correction): the
+ * orthonormal bases U of EK(A, G) = span{G, A^-1 G, A G, A^-2 G, ...} and V
+ * of EK(B, H), for the right-hand side G H^T of the solve, grow by an operator
+ * block and an inverse block per iteration (two extended block Arnoldi
+ * processes: A, B by the exact Toeplitz products, A^-1, B^-1 by plain HODLR
+ * solves with the unshifted factors of A and B, which the first call
+ * factors with the plan's hopts and keeps); a new block is orthogonalised
+ * against its basis and loses its directions below 1e-10 of its norm
+ * (deflation).  The projected equation (U^T A U) Y + Y (V^T B V)^T =
+ * (U^T G)(V^T H)^T, at most 640 x 640, is solved on the device by factored ADI
+ * with the plan's shift pairs on explicit inverses (LU with partial
+ * pivoting) of the shifted projected matrices, until the residual of U Y V^T
+ * (formed from three orthogonal terms) is at most the solve's target; the
+ * solve's result U Y V^T is then compressed to at most 32 columns.
+ * Arguments, outputs and stopping as fde2d_sylvester_step, except that
+ * info->refine_iters counts extended Krylov iterations.  Finite differences
+ * only: a finite-element plan gives HODLR_EINVAL with hodlr_last_arg() == 2.
+ * A plan made by fde2d_plan_create_ws has no room for the solver's arrays
+ * (HODLR_EWORKSPACE).  The plan's shifted factor sets are not used, only its
+ * shift pairs (for the projected equation). */
+hodlr_status fde2d_sylvester_step_ek(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* U_m,
+                                     const lr_matrix* F, double dt, lr_matrix* U_next,
+                                     hodlr_info* info);
 
 /* As fde2d_sylvester_step, starting from a first guess X0 of the solution
  * (low-rank, rank <= opts.max_rank; NULL or rank 0: no guess).  The exact

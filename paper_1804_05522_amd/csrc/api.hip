@@ -248,6 +248,8 @@ struct hodlr_mat_s {
   double graph_fscale = 0.0;
 };
 
+constexpr int kLrSlots = 22;   // low-rank work slots of a 2D plan (Grams, transfer matrices, unit lists)
+
 struct fde2d_plan_s {
   hodlr_ctx ctx = nullptr;
   hodlr_mat mat = nullptr;      // 2J shifted problems: x_j = A + q_j I (items 0..J-1), y_j = B + p_j I (J..2J-1)
@@ -310,14 +312,52 @@ struct fde2d_plan_s {
   char* ws = nullptr;            // caller workspace (fde2d_plan_create_ws): plan arrays carved from it
   size_t ws_bytes = 0, ws_used = 0;
   bool sizing = false;          // fde2d_plan_workspace_size: arrays counted, not allocated
-  int64_t unit_rows[16][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1},
-                              {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
+  int64_t unit_rows[kLrSlots][2] = {};   // row counts the slot's unit lists were built for (-1: none)
   double* gpart = nullptr;
   double* grams = nullptr;
   double* mbuf = nullptr;
   double* frob = nullptr;
   int cap_gram = 0;             // gram units per job slot
   int slot_units = 0;           // LrUnit entries per job slot
+  // extended Krylov solver (arrays allocated on its first use)
+  bool ek_ready = false;
+  bool use_ek = false;          // the current step solves by extended Krylov instead of fADI sweeps
+  int ek_last[2] = {2, 2};      // iterations the last extended Krylov solves took (first solve, correction)
+  double* ekU = nullptr;        // nx x kEkMax orthonormal basis of the A side
+  double* ekAU = nullptr;       // A times it (exact products)
+  double* ekV = nullptr;        // ny x kEkMax basis of the B side
+  double* ekBV = nullptr;       // B times it
+  double* ekTA = nullptr;       // kEkMax x kEkMax projected U^T A U
+  double* ekTB = nullptr;       // kEkMax x kEkMax projected V^T B V
+  double* ekW = nullptr;        // max(nx, ny) x kRS candidate block
+  double* ekO = nullptr;        // max(nx, ny) x kRS its first orthonormalisation
+  double* ekS = nullptr;        // kEkMax x kRS Gram-Schmidt coefficients
+  double* ekPart = nullptr;     // split-K partial products
+  double* ekShift = nullptr;    // device shifts: q_0 .. q_{J-1}, p_0 .. p_{J-1}
+  double* ekLU = nullptr;       // 2J shifted projected matrices, LU factors
+  double* ekInv = nullptr;      // their inverses
+  int32_t* ekPiv = nullptr;     // 2J x kEkMax pivot rows
+  int32_t* ekFlag = nullptr;    // 2J zero-pivot flags
+  double* ekG[2] = {nullptr, nullptr};   // projected right-hand side factors (kEkMax x kRS, ping-pong)
+  double* ekH[2] = {nullptr, nullptr};
+  double* ekKZ = nullptr;       // kEkMax x (64 kRS) projected fADI factors
+  double* ekKY = nullptr;
+  double* ekY = nullptr;        // kEkMax x kEkMax projected solution
+  double* ekOm = nullptr;       // kEkMax x kEkSk sketch of its columns
+  double* ekYs = nullptr;       // kEkMax x kEkSk: Y Om, then its orthonormal bases, then Y^T Q
+  double* ekQ1 = nullptr;
+  double* ekQ2 = nullptr;
+  double* ekBt = nullptr;
+  double* ekEye = nullptr;      // kEkSk x kEkSk identity
+  double* ekZf = nullptr;       // nx x kRS, ny x kRS: U Q and V Y^T Q
+  double* ekWf = nullptr;
+  double* ekJunk = nullptr;     // kEkSk x kRS unused right factor of the orthonormalising passes
+  double* ekG0 = nullptr;       // kEkMax x kRS projected right-hand side factors U^T G, V^T H
+  double* ekH0 = nullptr;
+  double* ekR = nullptr;        // max(nx, ny) x kEkMax residual blocks (A U Y - U T_A Y, ...)
+  double* ekY1 = nullptr;       // kEkMax x kEkMax products with the projected matrices
+  double* ekRs = nullptr;       // kEkMax x kEkMax projected residual
+  double* ekNrm = nullptr;      // device: sums of squares of the three residual terms
   std::vector<void*> allocs;
 };
 

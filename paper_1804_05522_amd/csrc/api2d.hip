@@ -11,7 +11,9 @@ enum { kR_R0 = 0, kR_D0 = 1, kR_D1 = 2, kR_X0 = 3, kR_X1 = 4, kR_T = 5, kR_C = 6
        kR_CAP = 10,   // bit mask of the work slots whose recompression hit its rank cap above its tolerance
        kR_K0 = 11, kR_K1 = 12,   // rank of the correction sum X_corr (ping-pong)
        kR_Q1 = 13, kR_Q2 = 14,   // ranks of the orthonormalised sketches of a dense compression
-       kR_N = 15 };
+       kR_EK1 = 15, kR_EK2 = 16, // extended Krylov: ranks of a new block's two orthonormalisations
+       kR_EQ1 = 17, kR_EQ2 = 18, // and of the projected solution's range
+       kR_N = 19 };
 constexpr int kMaxCorrections = 6;   // correction sweeps of a step after the first
 constexpr int kSketch = 32;          // sketch columns of a dense compression
 
@@ -498,6 +500,418 @@ hodlr_status adi_sweep(fde2d_plan P, int r0, double target, int& steps, int& par
   return HODLR_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Extended Krylov solver of A D + D B^T = G H^T (Sec. 4.3), in place of an
+// fADI sweep: orthonormal bases U of EK(A, G) = span{G, A^-1 G, A G,
+// A^-2 G, ...} and V of EK(B, H) are grown a block at a time (two extended
+// block Arnoldi processes; the products with A and B are the exact Toeplitz
+// products, the solves the plain HODLR solves with the unshifted factors),
+// the projected equation T_A Y + Y T_B^T = (U^T G)(V^T H)^T is solved, and
+// D = U Y V^T.  A new block is orthogonalised against the basis by two block
+// Gram-Schmidt passes and orthonormalised with its directions below 1e-10 of
+// its norm before the passes dropped (deflation: the block shrinks once the
+// space stops growing in a direction), then projected and orthonormalised
+// once more.  The projected equation is solved by factored ADI with the
+// plan's shift pairs on explicit inverses of T_A + q_j I and T_B + p_j I.
+// The residual of D = U Y V^T splits into three orthogonal terms,
+// (A U - U T_A) Y V^T, U Y (B V - V T_B)^T and U (T_A Y + Y T_B^T - G' H'^T) V^T,
+// whose norms are formed from explicit products (no Gram differences), so the
+// test resolves the residual to about u ||A|| ||D||.
+
+constexpr double kEkDrop = 1e-10;   // deflation level of a new block, relative to its norm
+constexpr int kEkIterMax = 40;
+
+struct EkSide {
+  double* Q;        // n x kEkMax orthonormal basis
+  double* AQ;       // the operator times it
+  double* T;        // kEkMax x kEkMax projected operator Q^T (op Q)
+  int64_t n;
+  int m = 0;        // basis columns
+  int o1 = 0, c1 = 0;   // the operator half's last block (columns o1 .. o1 + c1 - 1)
+  int o2 = 0, c2 = 0;   // the inverse half's last block
+};
+
+// C = alpha op(A) op(B) + beta C (k_ek_gemm), the inner dimension split over
+// work-groups when the output has few tiles.
+hodlr_status ek_gemm(fde2d_plan P, int ta, int tb, int M, int N, int64_t K, double alpha, const double* A,
+                     int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0) return HODLR_OK;
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int64_t kchunk = std::max<int64_t>(K, 1);
+  if (tiles < 128 && K >= 128) {
+    int64_t ns = std::min<int64_t>({(K + 63) / 64, int64_t(kEkSplit), int64_t((256 + tiles - 1) / tiles)});
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, int64_t(kEkMax) * kEkMax / (int64_t(M) * N)));
+    kchunk = ((K + ns - 1) / ns + 15) / 16 * 16;
+  }
+  const int nsplit = int(std::max<int64_t>(1, (K + kchunk - 1) / kchunk));
+  HFDE_LAUNCH(k_ek_gemm, dim3(unsigned((M + 63) / 64), unsigned((N + 63) / 64), unsigned(nsplit)), dim3(256), 0, s,
+              ta, tb, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, P->ekPart);
+  if (nsplit > 1)
+    HFDE_LAUNCH(k_ek_gemm_sum, dim3(unsigned(std::min<int64_t>((int64_t(M) * N + 255) / 256, 1024))), dim3(256), 0,
+                s, M, N, nsplit, P->ekPart, alpha, beta, C, ldc);
+  return HODLR_OK;
+}
+
+// ||X||_F^2 of an m x n block into ekNrm[slot] (device).
+void ek_sumsq(fde2d_plan P, int64_t m, int n, const double* X, int64_t ld, int slot, hipStream_t s) {
+  const unsigned blocks = unsigned(std::max<int64_t>(1, std::min<int64_t>((m * n + 255) / 256, 512)));
+  HFDE_LAUNCH(k_ek_sumsq, dim3(blocks), dim3(256), 0, s, m, std::max(n, 0), X, ld, P->ekPart);
+  HFDE_LAUNCH(k_sum_partials, dim3(1), dim3(256), 0, s, P->ekPart, int64_t(blocks), P->ekNrm + slot);
+}
+
+// Arrays of the solver (first use), the shifts on the device, and the
+// factorisation of the unshifted A and B (the batch of the exact products).
+hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
+  if (P->ek_ready) return HODLR_OK;
+  const int64_t nx = P->nx, ny = P->ny, mr = std::max(nx, ny);
+  const int64_t E2 = int64_t(kEkMax) * kEkMax;
+  const int J = P->J;
+  bool ok = plan_alloc(P, &P->ekU, nx * kEkMax) == HODLR_OK && plan_alloc(P, &P->ekAU, nx * kEkMax) == HODLR_OK &&
+            plan_alloc(P, &P->ekV, ny * kEkMax) == HODLR_OK && plan_alloc(P, &P->ekBV, ny * kEkMax) == HODLR_OK &&
+            plan_alloc(P, &P->ekTA, E2) == HODLR_OK && plan_alloc(P, &P->ekTB, E2) == HODLR_OK &&
+            plan_alloc(P, &P->ekW, mr * kRS) == HODLR_OK && plan_alloc(P, &P->ekO, mr * kRS) == HODLR_OK &&
+            plan_alloc(P, &P->ekS, int64_t(kEkMax) * kRS) == HODLR_OK && plan_alloc(P, &P->ekPart, E2) == HODLR_OK &&
+            plan_alloc(P, &P->ekShift, 2 * J) == HODLR_OK && plan_alloc(P, &P->ekLU, 2 * J * E2) == HODLR_OK &&
+            plan_alloc(P, &P->ekInv, 2 * J * E2) == HODLR_OK &&
+            plan_alloc(P, &P->ekPiv, int64_t(2) * J * kEkMax) == HODLR_OK &&
+            plan_alloc(P, &P->ekFlag, 2 * J) == HODLR_OK;
+  for (int k = 0; k < 2 && ok; ++k)
+    ok = plan_alloc(P, &P->ekG[k], int64_t(kEkMax) * kRS) == HODLR_OK &&
+         plan_alloc(P, &P->ekH[k], int64_t(kEkMax) * kRS) == HODLR_OK;
+  ok = ok && plan_alloc(P, &P->ekKZ, int64_t(kEkMax) * J * kRS) == HODLR_OK &&
+       plan_alloc(P, &P->ekKY, int64_t(kEkMax) * J * kRS) == HODLR_OK && plan_alloc(P, &P->ekY, E2) == HODLR_OK &&
+       plan_alloc(P, &P->ekOm, int64_t(kEkMax) * kEkSk) == HODLR_OK &&
+       plan_alloc(P, &P->ekYs, int64_t(kEkMax) * kEkSk) == HODLR_OK &&
+       plan_alloc(P, &P->ekQ1, int64_t(kEkMax) * kRS) == HODLR_OK &&
+       plan_alloc(P, &P->ekQ2, int64_t(kEkMax) * kRS) == HODLR_OK &&
+       plan_alloc(P, &P->ekBt, int64_t(kEkMax) * kRS) == HODLR_OK &&
+       plan_alloc(P, &P->ekEye, kEkSk * kEkSk) == HODLR_OK && plan_alloc(P, &P->ekZf, nx * kRS) == HODLR_OK &&
+       plan_alloc(P, &P->ekWf, ny * kRS) == HODLR_OK && plan_alloc(P, &P->ekJunk, kEkSk * kRS) == HODLR_OK &&
+       plan_alloc(P, &P->ekG0, int64_t(kEkMax) * kRS) == HODLR_OK &&
+       plan_alloc(P, &P->ekH0, int64_t(kEkMax) * kRS) == HODLR_OK && plan_alloc(P, &P->ekR, mr * kEkMax) == HODLR_OK &&
+       plan_alloc(P, &P->ekY1, E2) == HODLR_OK && plan_alloc(P, &P->ekRs, E2) == HODLR_OK &&
+       plan_alloc(P, &P->ekNrm, 4) == HODLR_OK;
+  if (!ok) return P->ws ? HODLR_EWORKSPACE : HODLR_ENOMEM;
+  std::vector<double> sh(2 * J);
+  for (int j = 0; j < J; ++j) {
+    sh[j] = P->q[j];
+    sh[J + j] = P->p[j];
+  }
+  HIP_TRY(hipMemcpyAsync(P->ekShift, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HFDE_LAUNCH(k_set_identity, dim3((kEkSk * kEkSk + 255) / 256), dim3(256), 0, s, P->ekEye, kEkSk, kEkSk);
+  HFDE_LAUNCH(k_fill_uniform, dim3(64), dim3(256), 0, s, P->ekOm, int64_t(kEkMax) * kEkSk, uint64_t(0xe4e4));
+  HIP_TRY(hipStreamSynchronize(s));
+  hodlr_info fi{};
+  const hodlr_status st = hodlr_factor(P->ctx, P->exact, &fi);
+  if (st != HODLR_OK && st != HODLR_ERANK) return st;
+  P->ek_ready = true;
+  return HODLR_OK;
+}
+
+// Append the c-column candidate block in ekW (ld n) to the side's basis:
+// two block Gram-Schmidt passes, an orthonormalisation that drops the
+// directions below kEkDrop times the block's norm, one more pass and a final
+// orthonormalisation into the basis.  `added` is the number of new columns.
+hodlr_status ek_add(fde2d_plan P, EkSide& S, int c, int& added, hipStream_t s) {
+  added = 0;
+  if (c <= 0 || S.m >= kEkMax) return HODLR_OK;
+  const int64_t n = S.n;
+  int32_t hr[kR_N];
+  double w2 = 0.0;
+  LrJob fj{};
+  fj.X.g[0] = grp(P->ekW, n, nullptr, c, 1.0);
+  fj.X.g[1] = fj.X.g[2] = grp_none();
+  fj.Y.g[0] = grp(P->ekEye, kEkSk, nullptr, c, 1.0);
+  fj.Y.g[1] = fj.Y.g[2] = grp_none();
+  fj.rows_x = n;
+  fj.rows_y = kEkSk;
+  TRY(run_lr(P, fj, 16, false, s));
+  TRY(read_frob(P, 16, &w2, s));
+  for (int pass = 0; pass < 2 && S.m > 0; ++pass) {
+    TRY(ek_gemm(P, 1, 0, S.m, c, n, 1.0, S.Q, n, P->ekW, n, 0.0, P->ekS, kEkMax, s));    // Q^T W
+    TRY(ek_gemm(P, 0, 0, int(n), c, S.m, -1.0, S.Q, n, P->ekS, kEkMax, 1.0, P->ekW, n, s));   // W -= Q (Q^T W)
+  }
+  LrJob oj{};
+  oj.X.g[0] = grp(P->ekW, n, nullptr, c, 1.0);
+  oj.X.g[1] = oj.X.g[2] = grp_none();
+  oj.Y.g[0] = grp(P->ekEye, kEkSk, nullptr, c, 1.0);
+  oj.Y.g[1] = oj.Y.g[2] = grp_none();
+  oj.rows_x = n;
+  oj.rows_y = kEkSk;
+  oj.rank_out = P->ranks + kR_EK1;
+  oj.tau = kEkDrop * std::sqrt(std::max(w2, 0.0));
+  oj.tau_rel = 0.0;
+  oj.rmax = std::min(kRS, kEkMax - S.m);
+  oj.U = P->ekO;
+  oj.ldu = n;
+  oj.V = P->ekJunk;
+  oj.ldv = kEkSk;
+  TRY(run_lr(P, oj, 16, true, s));
+  TRY(read_ranks(P, hr, s));
+  const int r1 = hr[kR_EK1];
+  if (r1 == 0) return HODLR_OK;
+  if (S.m > 0) {
+    TRY(ek_gemm(P, 1, 0, S.m, r1, n, 1.0, S.Q, n, P->ekO, n, 0.0, P->ekS, kEkMax, s));
+    TRY(ek_gemm(P, 0, 0, int(n), r1, S.m, -1.0, S.Q, n, P->ekS, kEkMax, 1.0, P->ekO, n, s));
+  }
+  LrJob qj{};
+  qj.X.g[0] = grp(P->ekO, n, nullptr, r1, 1.0);
+  qj.X.g[1] = qj.X.g[2] = grp_none();
+  qj.Y.g[0] = grp(P->ekEye, kEkSk, nullptr, r1, 1.0);
+  qj.Y.g[1] = qj.Y.g[2] = grp_none();
+  qj.rows_x = n;
+  qj.rows_y = kEkSk;
+  qj.rank_out = P->ranks + kR_EK2;
+  qj.tau = 0.0;
+  qj.tau_rel = 1e-6;
+  qj.rmax = std::min(kRS, kEkMax - S.m);
+  qj.U = S.Q + int64_t(S.m) * n;
+  qj.ldu = n;
+  qj.V = P->ekJunk;
+  qj.ldv = kEkSk;
+  TRY(run_lr(P, qj, 17, true, s));
+  TRY(read_ranks(P, hr, s));
+  added = hr[kR_EK2];
+  S.m += added;
+  return HODLR_OK;
+}
+
+// Products with the operators of the columns a0 .. A.m - 1 and b0 .. B.m - 1
+// (exact Toeplitz products of both sides in one call), and the new rows and
+// columns of T_A and T_B.
+hodlr_status ek_products(fde2d_plan P, EkSide& A, int a0, EkSide& B, int b0, hipStream_t s) {
+  const int64_t nx = P->nx, ny = P->ny, ld = nx + ny;
+  const int ca = A.m - a0, cb = B.m - b0, c = std::max(ca, cb);
+  if (c == 0) return HODLR_OK;
+  copy_cols(nx, nullptr, ca, A.Q + int64_t(a0) * nx, nx, P->ex_in, ld, 1.0, s);
+  copy_cols(ny, nullptr, cb, B.Q + int64_t(b0) * ny, ny, P->ex_in + nx, ld, 1.0, s);
+  launch_fft_matvec(P->exact, P->ex_in, ld, P->ex_out, ld, nullptr, 0, c, s);
+  copy_cols(nx, nullptr, ca, P->ex_out, ld, A.AQ + int64_t(a0) * nx, nx, 1.0, s);
+  copy_cols(ny, nullptr, cb, P->ex_out + nx, ld, B.AQ + int64_t(b0) * ny, ny, 1.0, s);
+  for (int side = 0; side < 2; ++side) {
+    EkSide& S = side == 0 ? A : B;
+    const int m0 = side == 0 ? a0 : b0, m1 = S.m;
+    if (m1 == m0) continue;
+    const int64_t n = S.n;
+    TRY(ek_gemm(P, 1, 0, m1, m1 - m0, n, 1.0, S.Q, n, S.AQ + int64_t(m0) * n, n, 0.0, S.T + int64_t(m0) * kEkMax,
+                kEkMax, s));
+    if (m0 > 0)
+      TRY(ek_gemm(P, 1, 0, m1 - m0, m0, n, 1.0, S.Q + int64_t(m0) * n, n, S.AQ, n, 0.0, S.T + m0, kEkMax, s));
+  }
+  return HODLR_OK;
+}
+
+// The inverse half of an iteration: A^-1 and B^-1 (HODLR solves with the
+// unshifted factors, refined) on the given blocks, appended to the bases.
+hodlr_status ek_inverse_half(fde2d_plan P, EkSide& A, int ao, int ac, EkSide& B, int bo, int bc, hipStream_t s) {
+  const int64_t nx = P->nx, ny = P->ny, ld = nx + ny;
+  const int c = std::max(ac, bc), a0 = A.m, b0 = B.m;
+  int added_a = 0, added_b = 0;
+  if (c > 0) {
+    copy_cols(nx, nullptr, ac, A.Q + int64_t(ao) * nx, nx, P->ex_in, ld, 1.0, s);
+    copy_cols(ny, nullptr, bc, B.Q + int64_t(bo) * ny, ny, P->ex_in + nx, ld, 1.0, s);
+    // x = M^-1 b with the stored factors, then refinement steps x += M^-1 (b - M x)
+    // (exact products): the plain solve's error (about the factors'
+    // precision times the condition) would perturb the inverse half of the basis
+    hodlr_mat mx = P->exact;
+    launch_solve(mx, mx->opts.prec, P->ex_in, ld, P->ex_out, ld, c, s);
+    const int refine = mx->opts.prec == HODLR_MIXED_BF16 ? 2 : 1;
+    double* r = P->ekR;
+    double* d = P->ekR + ld * kRS;
+    for (int k = 0; k < refine; ++k) {
+      launch_fft_matvec(mx, P->ex_out, ld, r, ld, P->ex_in, ld, c, s);          // r = b - M x
+      launch_solve(mx, mx->opts.prec, r, ld, d, ld, c, s);
+      launch_axpby(ld, c, 1.0, d, ld, 1.0, P->ex_out, ld, P->ex_out, ld, s);
+    }
+    copy_cols(nx, nullptr, ac, P->ex_out, ld, P->ekW, nx, 1.0, s);
+    TRY(ek_add(P, A, ac, added_a, s));
+    copy_cols(ny, nullptr, bc, P->ex_out + nx, ld, P->ekW, ny, 1.0, s);
+    TRY(ek_add(P, B, bc, added_b, s));
+  }
+  A.o2 = a0;
+  A.c2 = added_a;
+  B.o2 = b0;
+  B.c2 = added_b;
+  return ek_products(P, A, a0, B, b0, s);
+}
+
+// The projected equation on the current bases: U^T G, V^T H, the LU
+// factors and inverses of the 2J shifted projected matrices, the projected
+// fADI over the shift pairs (K_Z, K_Y), Y = K_Z K_Y^T, and the norm of the
+// residual of U Y V^T (three orthogonal terms).
+hodlr_status ek_projected(fde2d_plan P, const EkSide& A, const EkSide& B, int r0, double& rn, hipStream_t s) {
+  const int64_t nx = P->nx, ny = P->ny;
+  const int mA = A.m, mB = B.m, J = P->J;
+  const int64_t E2 = int64_t(kEkMax) * kEkMax;
+  TRY(ek_gemm(P, 1, 0, mA, r0, nx, 1.0, A.Q, nx, P->G, nx, 0.0, P->ekG0, kEkMax, s));
+  TRY(ek_gemm(P, 1, 0, mB, r0, ny, 1.0, B.Q, ny, P->H, ny, 0.0, P->ekH0, kEkMax, s));
+  HFDE_LAUNCH(k_ek_lu, dim3(2 * J), dim3(kEkWG), 0, s, J, mA, A.T, mB, B.T, int64_t(kEkMax), P->ekShift, P->ekLU,
+              int64_t(kEkMax), E2, P->ekPiv, P->ekFlag);
+  HFDE_LAUNCH(k_ek_lu_inv, dim3(unsigned((std::max(mA, mB) + 15) / 16), unsigned(2 * J)), dim3(256), 0, s, J, mA,
+              mB, P->ekLU, int64_t(kEkMax), E2, P->ekPiv, P->ekInv, int64_t(kEkMax));
+  const unsigned tiles = unsigned((mA + 15) / 16 + (mB + 15) / 16);
+  const double* gin = P->ekG0;
+  const double* hin = P->ekH0;
+  for (int jo = 0; jo < J; ++jo) {
+    const int j = P->order[jo];
+    double* gout = P->ekG[jo & 1];
+    double* hout = P->ekH[jo & 1];
+    HFDE_LAUNCH(k_ek_adi_pair, dim3(tiles), dim3(256), 0, s, mA, mB, r0, P->p[j] + P->q[j], P->ekInv + j * E2,
+                P->ekInv + (J + j) * E2, int64_t(kEkMax), gin, hin, gout, hout, P->ekKZ, P->ekKY, int64_t(kEkMax),
+                jo * r0);
+    gin = gout;
+    hin = hout;
+  }
+  const int K = J * r0;
+  TRY(ek_gemm(P, 0, 1, mA, mB, K, 1.0, P->ekKZ, kEkMax, P->ekKY, kEkMax, 0.0, P->ekY, kEkMax, s));
+  // (A U) Y - U (T_A Y)
+  TRY(ek_gemm(P, 0, 0, mA, mB, mA, 1.0, A.T, kEkMax, P->ekY, kEkMax, 0.0, P->ekY1, kEkMax, s));
+  TRY(ek_gemm(P, 0, 0, int(nx), mB, mA, 1.0, A.AQ, nx, P->ekY, kEkMax, 0.0, P->ekR, nx, s));
+  TRY(ek_gemm(P, 0, 0, int(nx), mB, mA, -1.0, A.Q, nx, P->ekY1, kEkMax, 1.0, P->ekR, nx, s));
+  ek_sumsq(P, nx, mB, P->ekR, nx, 0, s);
+  // (B V) Y^T - V (T_B Y^T)
+  TRY(ek_gemm(P, 0, 1, mB, mA, mB, 1.0, B.T, kEkMax, P->ekY, kEkMax, 0.0, P->ekY1, kEkMax, s));
+  TRY(ek_gemm(P, 0, 1, int(ny), mA, mB, 1.0, B.AQ, ny, P->ekY, kEkMax, 0.0, P->ekR, ny, s));
+  TRY(ek_gemm(P, 0, 0, int(ny), mA, mB, -1.0, B.Q, ny, P->ekY1, kEkMax, 1.0, P->ekR, ny, s));
+  ek_sumsq(P, ny, mA, P->ekR, ny, 1, s);
+  // T_A Y + Y T_B^T - (U^T G)(V^T H)^T
+  TRY(ek_gemm(P, 0, 0, mA, mB, mA, 1.0, A.T, kEkMax, P->ekY, kEkMax, 0.0, P->ekRs, kEkMax, s));
+  TRY(ek_gemm(P, 0, 1, mA, mB, mB, 1.0, P->ekY, kEkMax, B.T, kEkMax, 1.0, P->ekRs, kEkMax, s));
+  TRY(ek_gemm(P, 0, 1, mA, mB, r0, -1.0, P->ekG0, kEkMax, P->ekH0, kEkMax, 1.0, P->ekRs, kEkMax, s));
+  ek_sumsq(P, mA, mB, P->ekRs, kEkMax, 2, s);
+  HIP_TRY(hipMemcpyAsync(P->host_frob + 2, P->ekNrm, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  rn = std::sqrt(std::max(P->host_frob[2] + P->host_frob[3] + P->host_frob[4], 0.0));
+  return HODLR_OK;
+}
+
+// D = U Y V^T as low-rank factors: the range of Y from a kEkSk-column sketch
+// (two orthonormalising passes, at most kRS columns), Z = U Q, W = V Y^T Q,
+// recompressed at tol / 10 into Zd[0] / Wd[0] (rank at kR_D0).
+hodlr_status ek_form(fde2d_plan P, const EkSide& A, const EkSide& B, hipStream_t s) {
+  const int64_t nx = P->nx, ny = P->ny;
+  const int mA = A.m, mB = B.m;
+  TRY(ek_gemm(P, 0, 0, mA, kEkSk, mB, 1.0, P->ekY, kEkMax, P->ekOm, kEkMax, 0.0, P->ekYs, kEkMax, s));
+  for (int pass = 0; pass < 2; ++pass) {
+    LrJob oj{};
+    oj.X.g[0] = pass == 0 ? grp(P->ekYs, kEkMax, nullptr, kEkSk, 1.0) : grp(P->ekQ1, kEkMax, P->ranks + kR_EQ1, 0, 1.0);
+    oj.X.g[1] = oj.X.g[2] = grp_none();
+    oj.Y.g[0] = pass == 0 ? grp(P->ekEye, kEkSk, nullptr, kEkSk, 1.0) : grp(P->ekEye, kEkSk, P->ranks + kR_EQ1, 0, 1.0);
+    oj.Y.g[1] = oj.Y.g[2] = grp_none();
+    oj.rows_x = mA;
+    oj.rows_y = kEkSk;
+    oj.rank_out = P->ranks + (pass == 0 ? kR_EQ1 : kR_EQ2);
+    oj.tau = 0.0;
+    oj.tau_rel = 1e-15;
+    oj.rmax = kRS;
+    oj.U = pass == 0 ? P->ekQ1 : P->ekQ2;
+    oj.ldu = kEkMax;
+    oj.V = P->ekJunk;
+    oj.ldv = kEkSk;
+    TRY(run_lr(P, oj, 18 + pass, true, s));
+  }
+  int32_t hr[kR_N];
+  TRY(read_ranks(P, hr, s));
+  const int cq = hr[kR_EQ2];
+  if (cq == 0) {
+    HIP_TRY(hipMemsetAsync(P->ranks + kR_D0, 0, sizeof(int32_t), s));
+    return HODLR_OK;
+  }
+  TRY(ek_gemm(P, 1, 0, mB, cq, mA, 1.0, P->ekY, kEkMax, P->ekQ2, kEkMax, 0.0, P->ekBt, kEkMax, s));
+  TRY(ek_gemm(P, 0, 0, int(nx), cq, mA, 1.0, A.Q, nx, P->ekQ2, kEkMax, 0.0, P->ekZf, nx, s));
+  TRY(ek_gemm(P, 0, 0, int(ny), cq, mB, 1.0, B.Q, ny, P->ekBt, kEkMax, 0.0, P->ekWf, ny, s));
+  LrJob dj{};
+  dj.X.g[0] = grp(P->ekZf, nx, nullptr, cq, 1.0);
+  dj.X.g[1] = dj.X.g[2] = grp_none();
+  dj.Y.g[0] = grp(P->ekWf, ny, nullptr, cq, 1.0);
+  dj.Y.g[1] = dj.Y.g[2] = grp_none();
+  dj.rows_x = nx;
+  dj.rows_y = ny;
+  dj.rank_out = P->ranks + kR_D0;
+  dj.tau = 0.0;
+  dj.tau_rel = 0.1 * P->opts.tol;
+  dj.rmax = kRS;
+  dj.capped = P->ranks + kR_CAP;
+  dj.U = P->Zd[0];
+  dj.ldu = nx;
+  dj.V = P->Wd[0];
+  dj.ldv = ny;
+  return run_lr(P, dj, 15, true, s);
+}
+
+// Extended Krylov solve of A D + D B^T = G H^T (rank r0 in P->G / P->H),
+// until the residual of U Y V^T is at most target; D in Zd[0] / Wd[0]
+// (parity 0), steps = the iterations (each grows both bases by an operator
+// block and an inverse block).  The projected equation is solved first one
+// iteration before the count the last solve of the same kind (0: a step's
+// first solve, 1: a correction) took, then where the residual's rate of
+// decrease between the last two solves predicts the target (at most eight
+// iterations on), or at the next iteration while there is no rate yet.
+hodlr_status ek_solve(fde2d_plan P, int r0, double target, int kind, int& steps, int& parity, hipStream_t s) {
+  const int64_t nx = P->nx, ny = P->ny;
+  HIP_TRY(hipMemsetAsync(P->ranks + kR_D0, 0, sizeof(int32_t), s));
+  parity = 0;
+  steps = 0;
+  if (r0 == 0) return HODLR_OK;
+  if (r0 > kRS) return HODLR_EINVAL;
+  TRY(ek_prepare(P, s));
+  const bool verbose = getenv("HODLR_VERBOSE") != nullptr;
+  EkSide A{P->ekU, P->ekAU, P->ekTA, nx}, B{P->ekV, P->ekBV, P->ekTB, ny};
+  int added = 0;
+  copy_cols(nx, nullptr, r0, P->G, nx, P->ekW, nx, 1.0, s);
+  TRY(ek_add(P, A, r0, added, s));
+  A.c1 = added;
+  copy_cols(ny, nullptr, r0, P->H, ny, P->ekW, ny, 1.0, s);
+  TRY(ek_add(P, B, r0, added, s));
+  B.c1 = added;
+  TRY(ek_products(P, A, 0, B, 0, s));
+  TRY(ek_inverse_half(P, A, A.o1, A.c1, B, B.o1, B.c1, s));
+  int next = std::max(1, P->ek_last[kind] - 1), prev_it = 0, checks = 0;
+  double prev_rn = -1.0, rn = 0.0;
+  for (int it = 1;; ++it) {
+    const bool full = A.m + 2 * kRS > kEkMax || B.m + 2 * kRS > kEkMax;
+    const bool stuck = A.c1 + A.c2 + B.c1 + B.c2 == 0;
+    const bool last = full || stuck || it >= kEkIterMax;
+    if (it >= next || last) {
+      TRY(ek_projected(P, A, B, r0, rn, s));
+      ++checks;
+      steps = it;
+      if (rn <= target || last) break;
+      int more = 1;
+      if (prev_rn > 0.0 && rn < prev_rn) {
+        const double rate = std::log(rn / prev_rn) / double(it - prev_it);   // log decrease per iteration
+        more = int(std::ceil(std::log(target / rn) / rate));
+        more = std::min(8, std::max(1, more));
+      }
+      prev_rn = rn;
+      prev_it = it;
+      next = it + more;
+    }
+    const int a0 = A.m, b0 = B.m;
+    copy_cols(nx, nullptr, A.c1, A.AQ + int64_t(A.o1) * nx, nx, P->ekW, nx, 1.0, s);
+    TRY(ek_add(P, A, A.c1, added, s));
+    A.o1 = a0;
+    A.c1 = added;
+    copy_cols(ny, nullptr, B.c1, B.AQ + int64_t(B.o1) * ny, ny, P->ekW, ny, 1.0, s);
+    TRY(ek_add(P, B, B.c1, added, s));
+    B.o1 = b0;
+    B.c1 = added;
+    TRY(ek_products(P, A, a0, B, b0, s));
+    TRY(ek_inverse_half(P, A, A.o2, A.c2, B, B.o2, B.c2, s));
+  }
+  P->ek_last[kind] = steps;
+  if (verbose)
+    fprintf(stderr, "hodlr_fde: extended Krylov: %d iterations, bases %d x %d, %d projected solves, residual %.2e "
+            "(target %.2e)\n", steps, A.m, B.m, checks, rn, target);
+  return ek_form(P, A, B, s);
+}
+
+// One solve of the step: an fADI sweep, or the extended Krylov solver.
+hodlr_status step_solve(fde2d_plan P, int r0, double target, int kind, int& steps, int& parity, hipStream_t s) {
+  return P->use_ek ? ek_solve(P, r0, target, kind, steps, parity, s) : adi_sweep(P, r0, target, steps, parity, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -557,6 +971,7 @@ static hodlr_status plan2d_impl(hodlr_ctx ctx, const fde_operator* opx, const fd
   if (!P) return HODLR_ENOMEM;
   P->ctx = ctx;
   P->sizing = sizing;
+  for (auto& u : P->unit_rows) u[0] = u[1] = -1;
   if (!sizing && hipHostMalloc(reinterpret_cast<void**>(&P->host_ranks), 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     P->host_ranks = nullptr;
     fde2d_plan_destroy(P);
@@ -732,9 +1147,11 @@ static hodlr_status plan2d_impl(hodlr_ctx ctx, const fde_operator* opx, const fd
             plan_alloc(P, &P->xin, total_rows * kMaxCat) == HODLR_OK &&
             plan_alloc(P, &P->ex_in, (nx + ny) * kMaxCat) == HODLR_OK &&
             plan_alloc(P, &P->ex_out, (nx + ny) * kMaxCat) == HODLR_OK && plan_alloc(P, &P->ranks, kR_N) == HODLR_OK &&
-            plan_alloc(P, &P->units, 16 * P->slot_units) == HODLR_OK &&
-            plan_alloc(P, &P->gpart, 16 * P->cap_gram * kG2) == HODLR_OK && plan_alloc(P, &P->grams, 32 * kG2) == HODLR_OK &&
-            plan_alloc(P, &P->mbuf, 16 * 2 * kMaxCat * kRS) == HODLR_OK && plan_alloc(P, &P->frob, 16) == HODLR_OK;
+            plan_alloc(P, &P->units, kLrSlots * P->slot_units) == HODLR_OK &&
+            plan_alloc(P, &P->gpart, kLrSlots * P->cap_gram * kG2) == HODLR_OK &&
+            plan_alloc(P, &P->grams, 2 * kLrSlots * kG2) == HODLR_OK &&
+            plan_alloc(P, &P->mbuf, kLrSlots * 2 * kMaxCat * kRS) == HODLR_OK &&
+            plan_alloc(P, &P->frob, kLrSlots) == HODLR_OK;
   ok = ok && plan_alloc(P, &P->counters, 1) == HODLR_OK && plan_alloc(P, &P->lrs_cpart, ((std::max(nx, ny) + kLrsSlice - 1) / kLrsSlice) * kLrsCols * kLrsK) == HODLR_OK &&
        plan_alloc(P, &P->lrs_t, kLrsCols * kLrsK) == HODLR_OK &&
        plan_alloc(P, &P->lrs_part, ((nx + 63) / 64) * ((ny + 63) / 64)) == HODLR_OK &&
@@ -1056,7 +1473,7 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
       const int fp = P->mat->opts.prec;
       const double first = fp == HODLR_FP64 ? 0.1 * tol : std::max(0.1 * tol, fp == HODLR_MIXED_FP32 ? 1e-6 : 1e-3);
       int steps = 0, dpar = 0;
-      TRY(adi_sweep(P, rc, first * std::max(cnorm, 1e-300), steps, dpar, s));
+      TRY(step_solve(P, rc, first * std::max(cnorm, 1e-300), 0, steps, dpar, s));
       total_steps += steps;
       LrJob mj{};
       mj.X.g[0] = grp(P->Zd[dpar], nx, P->ranks + kR_D0 + dpar, 0, 1.0);
@@ -1099,7 +1516,7 @@ hodlr_status fde2d_sylvester_step_guess(hodlr_ctx ctx, fde2d_plan P, const lr_ma
       const int r0 = hr[kR_R0];
       if (r0 == 0) break;
       int steps = 0, dpar = 0;
-      TRY(adi_sweep(P, r0, 0.1 * tol * std::max(cnorm, 1e-300), steps, dpar, s));
+      TRY(step_solve(P, r0, 0.1 * tol * std::max(cnorm, 1e-300), 1, steps, dpar, s));
       total_steps += steps;
       // ||D||_F (Gram trace), the size of the correction
       double d2 = 0.0;
@@ -1218,6 +1635,18 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* 
                                   lr_matrix* U_next, hodlr_info* info) {
   const hodlr_status st = fde2d_sylvester_step_guess(ctx, P, U_m, F, dt, nullptr, U_next, info);
   if (st == HODLR_EINVAL && ctx && ctx->last_arg == 7) ctx->last_arg = 6;
+  return st;
+}
+
+hodlr_status fde2d_sylvester_step_ek(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* U_m, const lr_matrix* F,
+                                     double dt, lr_matrix* U_next, hodlr_info* info) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!P) return set_arg(ctx, 2);
+  if (P->fe) return set_arg(ctx, 2);
+  P->use_ek = true;
+  const hodlr_status st = fde2d_sylvester_step_guess(ctx, P, U_m, F, dt, nullptr, U_next, info);
+  P->use_ek = false;
+  if (st == HODLR_EINVAL && ctx->last_arg == 7) ctx->last_arg = 6;
   return st;
 }
 

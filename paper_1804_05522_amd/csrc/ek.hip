@@ -1,0 +1,360 @@
+// Kernels of the extended Krylov solver of the per-step Sylvester equation
+// (Sec. 4.3): products of the tall basis blocks and of the small projected
+// matrices, batched LU factorisations and inverses of the shifted projected
+// matrices T + s I, and the projected fADI pair update.
+//
+// The projected equation T_A Y + Y T_B^T = G H^T (T_A = U^T A U, T_B =
+// V^T B V, U and V the orthonormal extended Krylov bases) is small (at most
+// kEkMax on a side) and dense; it is solved by factored ADI with the plan's
+// shift pairs on explicit inverses of T_A + q_j I and T_B + p_j I.
+
+constexpr int kEkMax = 640;      // basis columns per side (T_A, T_B at most kEkMax x kEkMax)
+constexpr int kEkPanel = 16;     // panel width of the blocked LU
+constexpr int kEkSk = 40;        // sketch columns of the projected solution's range
+constexpr int kEkSplit = 32;     // largest split of an inner dimension (k_ek_gemm partials)
+constexpr int kEkWG = 1024;      // threads of the LU work-groups
+
+// C = alpha op(A) op(B) + beta C for column-major A, B, C; op(X) = X (t = 0)
+// or X^T (t = 1); C is M x N, the inner dimension K.  Work-group (x, y, z)
+// takes the 64 x 64 output tile (x, y) over the inner indices
+// [z kchunk, min(K, (z + 1) kchunk)): with one split (gridDim.z == 1) it
+// writes C, otherwise its partial tile into part + z M N (M x N, ld M), which
+// k_ek_gemm_sum adds up.  256 threads, 4 x 4 outputs each; 16-deep slices of
+// both operands staged in LDS, loaded along the contiguous index.
+__global__ void __launch_bounds__(256) k_ek_gemm(int ta, int tb, int M, int N, int64_t K, int64_t kchunk,
+                                                 double alpha, const double* A, int64_t lda, const double* B,
+                                                 int64_t ldb, double beta, double* C, int64_t ldc, double* part) {
+  constexpr int kK = 16;
+  __shared__ double As[kK][65];
+  __shared__ double Bs[kK][65];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int64_t k0 = int64_t(blockIdx.z) * kchunk;
+  const int64_t k1 = min(K, k0 + kchunk);
+  double acc[4][4] = {};
+  for (int64_t kk = k0; kk < k1; kk += kK) {
+    for (int l = 0; l < 4; ++l) {
+      const int e = threadIdx.x + 256 * l;
+      int i, k;
+      if (ta == 0) { i = e % 64; k = e / 64; } else { k = e % kK; i = e / kK; }
+      const int64_t kg = kk + k;
+      double v = 0.0;
+      if (i0 + i < M && kg < k1) v = ta == 0 ? A[(i0 + i) + kg * lda] : A[kg + int64_t(i0 + i) * lda];
+      As[k][i] = v;
+      int j, kb;
+      if (tb == 0) { kb = e % kK; j = e / kK; } else { j = e % 64; kb = e / 64; }
+      const int64_t kgb = kk + kb;
+      double w = 0.0;
+      if (j0 + j < N && kgb < k1) w = tb == 0 ? B[kgb + int64_t(j0 + j) * ldb] : B[(j0 + j) + kgb * ldb];
+      Bs[kb][j] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kK; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = As[k][tx + 16 * r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = Bs[k][ty + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
+    }
+    __syncthreads();
+  }
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + tx + 16 * r, j = j0 + ty + 16 * c;
+      if (i >= M || j >= N) continue;
+      if (gridDim.z == 1) {
+        double* cp = C + i + int64_t(j) * ldc;
+        *cp = alpha * acc[r][c] + (beta == 0.0 ? 0.0 : beta * *cp);
+      } else {
+        part[int64_t(blockIdx.z) * M * N + i + int64_t(j) * M] = acc[r][c];
+      }
+    }
+}
+
+// C = alpha sum_z part_z + beta C (M x N).
+__global__ void k_ek_gemm_sum(int M, int N, int nsplit, const double* part, double alpha, double beta, double* C,
+                              int64_t ldc) {
+  const int64_t tot = int64_t(M) * N;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += part[int64_t(z) * tot + e];
+    double* cp = C + (e % M) + (e / M) * ldc;
+    *cp = alpha * s + (beta == 0.0 ? 0.0 : beta * *cp);
+  }
+}
+
+// LU factorisation with partial pivoting (P (T + s_b I) = L U, L unit lower)
+// of the batch's matrices, one work-group per matrix b: T = TA (order mA) for
+// b < J, else TB (order mB), both ld ldt; s_b = shift[b]; the factors
+// overwrite out + b stride (ld ldo), the pivot
+// rows go to
+// piv + b kEkMax, and flag[b] = 1 marks an exactly zero pivot.  Right-looking
+// and blocked: a panel of kEkPanel columns is factored in LDS, its row
+// interchanges are applied to the other columns, the block row of U is
+// solved with the panel's unit lower triangle, and the trailing matrix takes
+// the rank-kEkPanel update.  m <= kEkMax.
+__global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA, int mB, const double* TB,
+                                                 int64_t ldt, const double* shift, double* out, int64_t ldo,
+                                                 int64_t stride, int32_t* piv, int32_t* flag) {
+  constexpr int kP = kEkPanel;
+  constexpr int kW = kEkWG / 64;
+  __shared__ double Pn[kEkMax * kP];         // the panel, rows j0 .. m - 1 (ld = m - j0)
+  __shared__ double red_v[kW];
+  __shared__ int red_i[kW];
+  const int b = blockIdx.x;
+  const int m = b < J ? mA : mB;
+  const double* T = b < J ? TA : TB;
+  double* A = out + int64_t(b) * stride;
+  int32_t* pv = piv + int64_t(b) * kEkMax;
+  const double sh = shift[b];
+  for (int64_t e = threadIdx.x; e < int64_t(m) * m; e += kEkWG) {
+    const int i = int(e % m), j = int(e / m);
+    A[i + int64_t(j) * ldo] = T[i + int64_t(j) * ldt] + (i == j ? sh : 0.0);
+  }
+  if (threadIdx.x == 0) flag[b] = 0;
+  __syncthreads();
+  for (int j0 = 0; j0 < m; j0 += kP) {
+    const int nb = min(kP, m - j0), j1 = j0 + nb, mr = m - j0;
+    for (int e = threadIdx.x; e < mr * nb; e += kEkWG) {
+      const int i = e % mr, c = e / mr;
+      Pn[i + c * mr] = A[(j0 + i) + int64_t(j0 + c) * ldo];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < nb; ++jj) {
+      // pivot: the largest magnitude in panel column jj, rows jj .. mr - 1
+      // (ties to the lowest row), reduced within each wave, then over the four
+      double best = -1.0;
+      int bi = jj;
+      for (int i = jj + threadIdx.x; i < mr; i += kEkWG) {
+        const double v = fabs(Pn[i + jj * mr]);
+        if (v > best) { best = v; bi = i; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double v2 = __shfl_xor(best, o);
+        const int i2 = __shfl_xor(bi, o);
+        if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
+      }
+      if ((threadIdx.x & 63) == 0) {
+        red_v[threadIdx.x >> 6] = best;
+        red_i[threadIdx.x >> 6] = bi;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int w = 1; w < kW; ++w)
+          if (red_v[w] > red_v[0] || (red_v[w] == red_v[0] && red_i[w] < red_i[0])) {
+            red_v[0] = red_v[w];
+            red_i[0] = red_i[w];
+          }
+        pv[j0 + jj] = j0 + red_i[0];
+        if (red_v[0] == 0.0) flag[b] = 1;
+      }
+      __syncthreads();
+      const int p = red_i[0];
+      if (p != jj && threadIdx.x < nb) {
+        const double t = Pn[jj + threadIdx.x * mr];
+        Pn[jj + threadIdx.x * mr] = Pn[p + threadIdx.x * mr];
+        Pn[p + threadIdx.x * mr] = t;
+      }
+      __syncthreads();
+      // a thread owns a row below the pivot: its multiplier, then its update
+      const double d = Pn[jj + jj * mr];
+      const double inv = d != 0.0 ? 1.0 / d : 0.0;
+      for (int i = jj + 1 + threadIdx.x; i < mr; i += kEkWG) {
+        const double l = Pn[i + jj * mr] * inv;
+        Pn[i + jj * mr] = l;
+        for (int c = jj + 1; c < nb; ++c) Pn[i + c * mr] -= l * Pn[jj + c * mr];
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < mr * nb; e += kEkWG) {
+      const int i = e % mr, c = e / mr;
+      A[(j0 + i) + int64_t(j0 + c) * ldo] = Pn[i + c * mr];
+    }
+    // the panel's interchanges on the other columns: a thread owns a column
+    // and applies them in order
+    for (int c = threadIdx.x; c < m - nb; c += kEkWG) {
+      const int col = c < j0 ? c : c + nb;
+      double* ac = A + int64_t(col) * ldo;
+      for (int jj = 0; jj < nb; ++jj) {
+        const int p = pv[j0 + jj];
+        if (p != j0 + jj) {
+          const double t = ac[j0 + jj];
+          ac[j0 + jj] = ac[p];
+          ac[p] = t;
+        }
+      }
+      // block row of U: solve with the panel's unit lower triangle (columns right of the panel)
+      if (col >= j1) {
+        for (int r = 1; r < nb; ++r) {
+          double s = ac[j0 + r];
+          for (int t = 0; t < r; ++t) s -= Pn[r + t * mr] * ac[j0 + t];
+          ac[j0 + r] = s;
+        }
+      }
+    }
+    __syncthreads();
+    // trailing update A22 -= L21 U12 (rows, columns j1 .. m - 1)
+    const int m2 = m - j1;
+    for (int64_t e = threadIdx.x; e < int64_t(m2) * m2; e += kEkWG) {
+      const int i = int(e % m2), c = int(e / m2);
+      const double* uc = A + j0 + int64_t(j1 + c) * ldo;
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < kP; ++t)
+        if (t < nb) s += Pn[(nb + i) + t * mr] * uc[t];
+      A[(j1 + i) + int64_t(j1 + c) * ldo] -= s;
+    }
+    __syncthreads();
+  }
+}
+
+// Columns c0 .. c0 + 15 (c0 = 16 blockIdx.x) of the inverse of matrix
+// b = blockIdx.y (order m = mA for b < J, else mB) from its LU factors
+// (k_ek_lu): X = P e_c, then L^-1, then
+// U^-1, in LDS; written to inv + b stride (ld ldi).  Rows are taken in
+// blocks of 16: the diagonal block by one thread per column, the rows below
+// (above) by the whole work-group.
+__global__ void __launch_bounds__(256) k_ek_lu_inv(int J, int mA, int mB, const double* LU, int64_t ldo,
+                                                   int64_t stride, const int32_t* piv, double* inv, int64_t ldi) {
+  constexpr int kC = 16;
+  __shared__ double X[kEkMax * kC];
+  const int b = blockIdx.y, c0 = blockIdx.x * kC;
+  const int m = b < J ? mA : mB;
+  const int nc = min(kC, m - c0);
+  if (nc <= 0) return;
+  const double* A = LU + int64_t(b) * stride;
+  const int32_t* pv = piv + int64_t(b) * kEkMax;
+  for (int e = threadIdx.x; e < m * kC; e += 256) X[e] = (e % m == c0 + e / m) ? 1.0 : 0.0;
+  __syncthreads();
+  if (threadIdx.x < nc) {
+    double* x = X + threadIdx.x * m;
+    for (int k = 0; k < m; ++k) {
+      const int p = pv[k];
+      if (p != k) {
+        const double t = x[k];
+        x[k] = x[p];
+        x[p] = t;
+      }
+    }
+  }
+  __syncthreads();
+  // L y = x (unit lower), blocks of 16 rows top to bottom
+  for (int r0 = 0; r0 < m; r0 += 16) {
+    const int r1 = min(m, r0 + 16);
+    if (threadIdx.x < nc) {
+      double* x = X + threadIdx.x * m;
+      for (int r = r0 + 1; r < r1; ++r) {
+        double s = x[r];
+        for (int t = r0; t < r; ++t) s -= A[r + int64_t(t) * ldo] * x[t];
+        x[r] = s;
+      }
+    }
+    __syncthreads();
+    const int below = m - r1;
+    for (int e = threadIdx.x; e < below * nc; e += 256) {
+      const int i = r1 + e % below, c = e / below;
+      double* x = X + c * m;
+      double s = 0.0;
+      for (int t = r0; t < r1; ++t) s += A[i + int64_t(t) * ldo] * x[t];
+      x[i] -= s;
+    }
+    __syncthreads();
+  }
+  // U z = y, blocks of 16 rows bottom to top
+  for (int r1 = m; r1 > 0; r1 -= 16) {
+    const int r0 = max(0, r1 - 16);
+    if (threadIdx.x < nc) {
+      double* x = X + threadIdx.x * m;
+      for (int r = r1 - 1; r >= r0; --r) {
+        double s = x[r];
+        for (int t = r + 1; t < r1; ++t) s -= A[r + int64_t(t) * ldo] * x[t];
+        const double d = A[r + int64_t(r) * ldo];
+        x[r] = d != 0.0 ? s / d : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < r0 * nc; e += 256) {
+      const int i = e % r0, c = e / r0;
+      double* x = X + c * m;
+      double s = 0.0;
+      for (int t = r0; t < r1; ++t) s += A[i + int64_t(t) * ldo] * x[t];
+      x[i] -= s;
+    }
+    __syncthreads();
+  }
+  double* out = inv + int64_t(b) * stride;
+  for (int e = threadIdx.x; e < m * nc; e += 256) out[(e % m) + int64_t(c0 + e / m) * ldi] = X[e];
+}
+
+// One shift pair of the projected fADI: Z = (T_A + q I)^-1 G_in and
+// Y = (T_B + p I)^-1 H_in from the explicit inverses IA, IB; K_Z gets w Z and
+// K_Y gets Y (column block `off` of r <= 32 columns), G_out = G_in - w Z,
+// H_out = H_in - w Y (w = p + q).  Work-groups 0 .. tA - 1 take 16-row tiles
+// of the A side, the rest of the B side; in a work-group the 16 rows are
+// lanes and the inner dimension is split over 16 lane groups, whose partial
+// sums meet in LDS.  The inputs are read whole by every tile and the outputs
+// are other buffers, so the tiles are independent.
+__global__ void __launch_bounds__(256) k_ek_adi_pair(int mA, int mB, int r, double w, const double* IA,
+                                                     const double* IB, int64_t ldi, const double* Gin,
+                                                     const double* Hin, double* Gout, double* Hout, double* KZ,
+                                                     double* KY, int64_t ldk, int off) {
+  __shared__ double part[16 * 16 * 33];
+  const int tA = (mA + 15) / 16;
+  const bool sa = int(blockIdx.x) < tA;
+  const int tile = sa ? blockIdx.x : blockIdx.x - tA;
+  const int m = sa ? mA : mB;
+  const double* I = sa ? IA : IB;
+  const double* in = sa ? Gin : Hin;
+  double* outp = sa ? Gout : Hout;
+  double* K = sa ? KZ : KY;
+  const double sc = sa ? w : 1.0;
+  const int rl = threadIdx.x % 16, kg = threadIdx.x / 16;
+  const int i = tile * 16 + rl;
+  double acc[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) acc[c] = 0.0;
+  if (i < m) {
+    for (int k = kg; k < m; k += 16) {
+      const double a = I[i + int64_t(k) * ldi];
+#pragma unroll
+      for (int c = 0; c < 32; ++c)
+        if (c < r) acc[c] += a * in[k + int64_t(c) * kEkMax];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 32; ++c) part[(kg * 16 + rl) * 33 + c] = acc[c];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 16 * 32; e += 256) {
+    const int rr = e % 16, c = e / 16;
+    const int row = tile * 16 + rr;
+    if (row >= m || c >= r) continue;
+    double v = 0.0;
+    for (int g = 0; g < 16; ++g) v += part[(g * 16 + rr) * 33 + c];
+    K[row + int64_t(off + c) * ldk] = sc * v;
+    outp[row + int64_t(c) * kEkMax] = in[row + int64_t(c) * kEkMax] - w * v;
+  }
+}
+
+// Per-work-group sums of squares of an m x n column-major block into part
+// (gridDim.x entries), for ||X||_F.
+__global__ void __launch_bounds__(256) k_ek_sumsq(int64_t m, int n, const double* X, int64_t ld, double* part) {
+  __shared__ double red[256];
+  const int64_t tot = m * n;
+  double s = 0.0;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < tot; e += int64_t(gridDim.x) * 256) {
+    const double v = X[(e % m) + (e / m) * ld];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}

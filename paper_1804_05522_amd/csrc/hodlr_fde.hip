@@ -9,6 +9,7 @@
 #include "gmres.hip"
 #include "fft.hip"
 #include "adi.hip"
+#include "ek.hip"
 #include "convnet.hip"
 #include "api.hip"
 #include "api2d.hip"

@@ -29,7 +29,7 @@ EXPORTS = [
     "fde_net_param_count", "fde_net_create", "fde_net_destroy", "fde_net_set_params", "fde_net_get_params",
     "fde_net_get_grads", "fde_net_forward", "fde_net_train_step", "hodlr_toeplitz_matvec_noalloc",
     "hodlr_workspace_size", "hodlr_build_ws", "fde2d_plan_workspace_size", "fde2d_plan_create_ws",
-    "fde2d_plan_counters", "hodlr_get_weights",
+    "fde2d_plan_counters", "hodlr_get_weights", "fde2d_sylvester_step_ek",
 ]
 
 
@@ -140,6 +140,8 @@ def lib():
             L.fde2d_plan_shifts.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), i32]
             L.fde2d_sylvester_step.argtypes = [vp, vp, C.POINTER(LrMatrix), C.POINTER(LrMatrix), dbl,
                                                C.POINTER(LrMatrix), C.POINTER(HodlrInfo)]
+            L.fde2d_sylvester_step_ek.argtypes = [vp, vp, C.POINTER(LrMatrix), C.POINTER(LrMatrix), dbl,
+                                                  C.POINTER(LrMatrix), C.POINTER(HodlrInfo)]
             L.fde2d_sylvester_step_guess.argtypes = [vp, vp, C.POINTER(LrMatrix), C.POINTER(LrMatrix), dbl,
                                                      C.POINTER(LrMatrix), C.POINTER(LrMatrix), C.POINTER(HodlrInfo)]
             L.fde2d_field_from_lr.argtypes = [vp, vp, C.POINTER(LrMatrix), vp]
@@ -398,14 +400,23 @@ class Fde2dPlan:
                         C.c_void_p(Z.data_ptr() if Z is not None and Z.numel() else 0),
                         C.c_void_p(W.data_ptr() if W is not None and W.numel() else 0))
 
-    def step(self, Um, F, dt, out, allow=(HODLR_OK,), guess=None, guess_rank=None):
+    def step(self, Um, F, dt, out, allow=(HODLR_OK,), guess=None, guess_rank=None, ek=False):
         """Um, F, out, guess: (Z, W) pairs of column-major torch CUDA float64
         tensors stored as (rank, n) row-major (column j = row j); out gives the
         capacity.  guess: optional first guess of the solution (its first
-        guess_rank columns)."""
+        guess_rank columns).  ek: solve by extended Krylov
+        (fde2d_sylvester_step_ek) instead of fADI sweeps."""
         a, f, o = self._lr(Um), self._lr(F), self._lr(out, cap=out[0].shape[0])
         info = HodlrInfo()
-        if guess is None:
+        if ek:
+            if guess is not None:
+                raise ValueError("the extended Krylov step takes no first guess")
+            if self.ws is not None:
+                raise ValueError("the extended Krylov step needs a plan made with workspace=False "
+                                 "(its arrays are allocated by the library on first use)")
+            check(lib().fde2d_sylvester_step_ek(self.ctx.h, self.h, C.byref(a), C.byref(f), float(dt), C.byref(o),
+                                                C.byref(info)), "fde2d_sylvester_step_ek", self.ctx.h, allow)
+        elif guess is None:
             check(lib().fde2d_sylvester_step(self.ctx.h, self.h, C.byref(a), C.byref(f), float(dt), C.byref(o),
                                              C.byref(info)), "fde2d_sylvester_step", self.ctx.h, allow)
         else:

@@ -1,0 +1,138 @@
+"""GPU parity of the extended Krylov per-step Sylvester solver (Sec. 4.3,
+fde2d_sylvester_step_ek) against the oracle's Bartels-Stewart steps, and
+against the fADI solver on the same plan."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fde2d as O2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def lr_dev(Z, W_):
+    return dev(Z.T.copy()), dev(W_.T.copy())
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1804_05522_amd as H
+    H.lib()
+    return H
+
+
+@pytest.fixture(scope="module")
+def ctx(H):
+    return H.Context()
+
+
+def plan_for(H, ctx, p, prec, tol=1e-10, workspace=False):
+    opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5)
+    opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5)
+    return H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=tol, prec=prec), tol=tol, workspace=workspace)
+
+
+def run_steps(P, p, steps, ek=True, allow=(0,)):
+    """Steps from U^0 = 0 with the workload's source; yields (X, info) per step."""
+    cur = (torch.zeros((0, p.nx), dtype=torch.float64, device="cuda"),
+           torch.zeros((0, p.ny), dtype=torch.float64, device="cuda"))
+    F = lr_dev(p.f.Z, p.f.W)
+    for _ in range(steps):
+        out = (torch.zeros((64, p.nx), dtype=torch.float64, device="cuda"),
+               torch.zeros((64, p.ny), dtype=torch.float64, device="cuda"))
+        r, info = P.step(cur, F, p.dt, out, allow=allow, ek=ek)
+        X = out[0][:r].cpu().numpy().T @ out[1][:r].cpu().numpy()
+        yield X, info
+        cur = (out[0][:r].contiguous(), out[1][:r].contiguous())
+
+
+@pytest.mark.parametrize("n,variable,prec", [(40, False, "fp64"), (150, True, "fp64"), (333, True, "fp32"),
+                                             (512, True, "fp32"), (512, True, "bf16")])
+def test_ek_steps_match_bartels_stewart(H, ctx, n, variable, prec):
+    """Three implicit Euler steps of eq. (sylv-timestepping) from U^0 = 0 with
+    the extended Krylov solver, tolerance 1e-10: relative forward error
+    against the oracle's (refined) Bartels-Stewart steps and the normwise
+    backward error below 1e-10, with every precision of the factors (the
+    inverse half of the bases uses refined solves, and the corrections' exact
+    residuals close the gap)."""
+    p = W.fd_2d(n=n, variable=variable, dt=1 / 64)
+    P = plan_for(H, ctx, p, prec)
+    st = O2.SylvesterStepper(p)
+    U = np.zeros((n, n))
+    for k, (X, info) in enumerate(run_steps(P, p, 3)):
+        U = st.step(U, p.f.dense())
+        err = np.linalg.norm(X - U) / np.linalg.norm(U)
+        print(f"ek n={n} {prec} step {k + 1}: iterations {info.refine_iters} rank {info.max_rank} "
+              f"rel.err {err:.2e} backward error {info.backward_error:.2e}")
+        assert err <= 1e-10 and info.backward_error <= 1e-10, (err, info.backward_error)
+    P.close()
+
+
+def test_ek_rectangular_grid(H, ctx):
+    """nx != ny (150 x 97, different coefficients in the two directions):
+    the two bases and projected matrices have their own sizes."""
+    px, py = W.fd_2d(n=150, variable=True, dt=1 / 32), W.fd_2d(n=97, variable=True, dt=1 / 32)
+    p = W.Problem2D(150, 97, px.alpha_x, py.alpha_y, px.dt, 2, px.hx, py.hy, px.x, py.y, px.dxp, px.dxm,
+                    py.dyp, py.dym, W.LowRank(np.zeros((150, 1)), np.zeros((97, 1))),
+                    W.LowRank(px.f.Z, py.f.W))
+    P = plan_for(H, ctx, p, "fp32")
+    st = O2.SylvesterStepper(p)
+    U = np.zeros((150, 97))
+    for X, info in run_steps(P, p, 2):
+        U = st.step(U, p.f.dense())
+        err = np.linalg.norm(X - U) / np.linalg.norm(U)
+        assert err <= 1e-10 and info.backward_error <= 1e-10, (err, info.backward_error)
+    P.close()
+
+
+def test_ek_agrees_with_fadi(H, ctx):
+    """The same plan stepped by both solvers (n = 333, FP32 factors): the two
+    solutions agree to the tolerance, and so do the plan's later fADI steps
+    after extended Krylov ones (the solvers share the plan's work arrays)."""
+    p = W.fd_2d(n=333, variable=True, dt=1 / 64)
+    P = plan_for(H, ctx, p, "fp32")
+    xe = [X for X, _ in run_steps(P, p, 2, ek=True)]
+    xf = [X for X, _ in run_steps(P, p, 2, ek=False)]
+    for a, b in zip(xe, xf):
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 2e-10
+    xe2 = [X for X, _ in run_steps(P, p, 1, ek=True)]
+    assert np.linalg.norm(xe2[0] - xe[0]) / np.linalg.norm(xe[0]) <= 2e-10
+    P.close()
+
+
+def test_ek_error_paths(H, ctx):
+    """A finite-element plan is refused (HODLR_EINVAL, argument 2); a plan in
+    a caller workspace has no room for the solver's arrays (HODLR_EWORKSPACE)
+    and the binding says so before the call."""
+    from paper_1804_05522_amd import hodlr as HM
+    p = W.fd_2d(n=64, variable=False, dt=1 / 16)
+    F = lr_dev(p.f.Z, p.f.W)
+    zero = (torch.zeros((0, 64), dtype=torch.float64, device="cuda"),) * 2
+    out = (torch.zeros((64, 64), dtype=torch.float64, device="cuda"),
+           torch.zeros((64, 64), dtype=torch.float64, device="cuda"))
+    one = dev(np.ones(64))
+    opx = H.operator_dict(64, 1.3, p.dt, p.hx, one, one, 0.5, discretization=H.FDE_FE)
+    opy = H.operator_dict(64, 1.7, p.dt, p.hy, one, one, 0.5, discretization=H.FDE_FE)
+    Pfe = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec="fp64"), tol=1e-10, workspace=False)
+    with pytest.raises(H.HodlrError) as e:
+        Pfe.step(zero, F, p.dt, out, ek=True)
+    assert e.value.status == HM.HODLR_EINVAL and H.lib().hodlr_last_arg(ctx.h) == 2
+    Pfe.close()
+    Pws = plan_for(H, ctx, p, "fp64", workspace=True)
+    with pytest.raises(ValueError):
+        Pws.step(zero, F, p.dt, out, ek=True)
+    a, f, o = Pws._lr(zero), Pws._lr(F), Pws._lr(out, cap=64)
+    info = HM.HodlrInfo()
+    st = H.lib().fde2d_sylvester_step_ek(ctx.h, Pws.h, C.byref(a), C.byref(f), float(p.dt), C.byref(o),
+                                         C.byref(info))
+    assert st == HM.HODLR_EWORKSPACE
+    Pws.close()

@@ -116,7 +116,8 @@ def test_full_size_refined_step_residual(full_1d, stream):
             assert abs(res) <= 1e-10 * scale, (k, i, res, scale)
 
 
-def test_full_size_sylvester_step_residual(H, ctx, stream):
+@pytest.mark.parametrize("ek", [False, True], ids=["fadi", "ek"])
+def test_full_size_sylvester_step_residual(H, ctx, stream, ek):
     """One step of the 4096 x 4096 workload (U^0 = 0, rank-4 source, FP32
     factors, tolerance 1e-10, sweeps replayed from their HIP graphs): the
     oracle's residual R = C - A X - X B^T of the low-rank result X = Z W^T,
@@ -126,18 +127,19 @@ def test_full_size_sylvester_step_residual(H, ctx, stream):
     figure bounds the true backward error from above), the step reports
     ||R||_F / ||C||_F as the test finds it, and the relative forward error
     against the oracle's step (stored by tests/golden/make_fd2d.py) is below
-    1e-10."""
+    1e-10.  The same with the extended Krylov solver (ek) in place of the
+    fADI sweeps."""
     n = 4096
     p = W.fd_2d(n=n)
     with torch.cuda.stream(stream):
         opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5)
         opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5)
         F = (dev(p.f.Z.T.copy()), dev(p.f.W.T.copy()))
-        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec="fp32"), tol=1e-10)
+        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec="fp32"), tol=1e-10, workspace=not ek)
         cur = (torch.zeros((0, n), dtype=torch.float64, device="cuda"),) * 2
         out = (torch.zeros((64, n), dtype=torch.float64, device="cuda"),
                torch.zeros((64, n), dtype=torch.float64, device="cuda"))
-        r, info = P.step(cur, F, p.dt, out)
+        r, info = P.step(cur, F, p.dt, out, ek=ek)
         stream.synchronize()
         Z = out[0][:r].cpu().numpy().T
         Wf = out[1][:r].cpu().numpy().T
