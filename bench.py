@@ -400,22 +400,25 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
 
     ek = getattr(args, "solver", "fadi") == "ek" and not fe
 
-    def job(pr, timing=None, keep=False):
+    def job(pr, timing=None, keep=False, use_ek=None):
+        use_ek = ek if use_ek is None else use_ek
         t0 = time.perf_counter()
-        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec=pr), tol=1e-10, workspace=not ek)
+        # extended Krylov needs no shifted factor sets: its plan keeps one pair
+        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec=pr), tol=1e-10, workspace=not use_ek,
+                        max_shifts=1 if use_ek else 64)
         stream.synchronize()
         t1 = time.perf_counter()
         cur = U0
         adi, worst, r = 0, 0.0, 0
         for k in range(K):
             out = outs[k % 2]
-            r, info = P.step(cur, F, p.dt, out, ek=ek)
+            r, info = P.step(cur, F, p.dt, out, ek=use_ek)
             cur = (out[0][:r], out[1][:r])
             adi += info.refine_iters
             worst = max(worst, info.backward_error)
         stream.synchronize()
         t2 = time.perf_counter()
-        J = len(P.shifts()[0])
+        J = P.counters()["ek_shifts"] if use_ek else len(P.shifts()[0])
         if timing is not None:
             timing.append((t1 - t0, t2 - t1))
         if keep:
@@ -423,14 +426,14 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
         P.close()
         return J, adi / K, worst, r
 
-    def measure(pr):
+    def measure(pr, use_ek=None):
         for _ in range(warmup):
-            job(pr)
+            job(pr, use_ek=use_ek)
         parts = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            J, adi, worst, rank = job(pr, parts)
+            J, adi, worst, rank = job(pr, parts, use_ek=use_ek)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, parts, J, adi, worst, rank
 
@@ -465,6 +468,17 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
         job_s64, _, _, _, _, _ = measure("fp64")
         out["fp64_path"] = {"value": K / job_s64, "ms_per_step": 1e3 * job_s64}
         out["mixed_vs_fp64"] = job_s64 / job_s
+    if compare and not fe:
+        # the other per-step solver on the same job (Sec. 4.3's extended Krylov
+        # beside the shifted-solve fADI, or the reverse)
+        job_o, parts_o, _, it_o, worst_o, _ = measure(prec, use_ek=not ek)
+        out["other_solver"] = {
+            "solver": "fADI (shifted HODLR solves)" if ek else "extended Krylov (unshifted HODLR solves)",
+            "value": K / job_o, "ms_per_step": 1e3 * job_o,
+            "phases_ms": {"plan": 1e3 * float(np.mean([q[0] for q in parts_o])),
+                          "time_steps": 1e3 * float(np.mean([q[1] for q in parts_o]))},
+            ("adi_steps_per_step" if ek else "ek_iterations_per_step"): it_o,
+            "backward_error_worst": worst_o}
     return out
 
 

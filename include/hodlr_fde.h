@@ -371,8 +371,10 @@ hodlr_status fde2d_plan_create_ws(hodlr_ctx ctx, const fde_operator* opx, const 
  * 4R^2(r+1) + 4R^2 r), values[1] the flops of the dense residual sums
  * (2 nx ny K for K columns), values[2] the bytes one single-column solve of all
  * shifted operators reads (hodlr_mat_info.bytes_factors of the shifted batch),
- * values[3] J, values[4] the largest factor rank; up to count values.  Waits
- * for the device.  reset != 0 clears the two flop counters. */
+ * values[3] J, values[4] the largest factor rank, values[5] the shift pairs of
+ * the extended Krylov solver's projected equation (0 before its first use);
+ * up to count values.  Waits for the device.  reset != 0 clears the two flop
+ * counters. */
 hodlr_status fde2d_plan_counters(fde2d_plan p, double* values, int count, int reset);
 void fde2d_plan_destroy(fde2d_plan p);
 int fde2d_plan_shifts(fde2d_plan p, double* p_shifts, double* q_shifts, int cap);
@@ -426,7 +428,7 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* 
  * against its basis and loses its directions below 1e-10 of its norm
  * (deflation).  The projected equation (U^T A U) Y + Y (V^T B V)^T =
  * (U^T G)(V^T H)^T, at most 640 x 640, is solved on the device by factored ADI
- * with the plan's shift pairs on explicit inverses (LU with partial
+ * on explicit inverses (LU with partial
  * pivoting) of the shifted projected matrices, until the residual of U Y V^T
  * (formed from three orthogonal terms) is at most the solve's target; the
  * solve's result U Y V^T is then compressed to at most 32 columns.
@@ -434,8 +436,10 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* 
  * info->refine_iters counts extended Krylov iterations.  Finite differences
  * only: a finite-element plan gives HODLR_EINVAL with hodlr_last_arg() == 2.
  * A plan made by fde2d_plan_create_ws has no room for the solver's arrays
- * (HODLR_EWORKSPACE).  The plan's shifted factor sets are not used, only its
- * shift pairs (for the projected equation). */
+ * (HODLR_EWORKSPACE).  The plan's shifted factor sets are not used: the
+ * projected equation takes its own Zolotarev shift pairs on the plan's
+ * spectral intervals, as many as opts.tol / 10 needs (at most 64), so a plan
+ * made for this entry point alone may set max_shifts = 1. */
 hodlr_status fde2d_sylvester_step_ek(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* U_m,
                                      const lr_matrix* F, double dt, lr_matrix* U_next,
                                      hodlr_info* info);

@@ -97,6 +97,8 @@ struct LrJob {
   double* flops;            // device accumulator of the core's algorithmic flops (may be null)
   double tau;               // absolute truncation tolerance
   double tau_rel;           // relative truncation tolerance (times ||X Y^T||_F)
+  const double* tau_sq;     // if set: also tau_sq_scale * sqrt(*tau_sq) (a squared norm held on the device)
+  double tau_sq_scale;
   int32_t rmax;
   double* U; int64_t ldu;   // form outputs
   double* V; int64_t ldv;
@@ -143,7 +145,8 @@ __global__ void __launch_bounds__(kCoreWG) k_lr_core(const LrJob jb, const doubl
   }
   const double fro = sqrt(fmax(red[0], 0.0));
   __syncthreads();
-  const double tau = fmax(jb.tau, jb.tau_rel * fro);
+  double tau = fmax(jb.tau, jb.tau_rel * fro);
+  if (jb.tau_sq) tau = fmax(tau, jb.tau_sq_scale * sqrt(fmax(*jb.tau_sq, 0.0)));
   RecompressOut res = wg_recompress_core(GX, GY, R, tau, jb.rmax, MU, MU + kMaxCat * kRS, Lds);
   if (threadIdx.x == 0) {
     *jb.rank_out = res.rank;

@@ -323,6 +323,9 @@ struct fde2d_plan_s {
   bool ek_ready = false;
   bool use_ek = false;          // the current step solves by extended Krylov instead of fADI sweeps
   int ek_last[2] = {2, 2};      // iterations the last extended Krylov solves took (first solve, correction)
+  double iv[4] = {0, 0, 0, 0};  // spectral intervals [iv0, iv1] of A, [iv2, iv3] of B (the shifts' problem)
+  int ek_J = 0;                 // shift pairs of the projected fADI (reaching opts.tol / 10 on the intervals)
+  std::vector<double> ek_p, ek_q;
   double* ekU = nullptr;        // nx x kEkMax orthonormal basis of the A side
   double* ekAU = nullptr;       // A times it (exact products)
   double* ekV = nullptr;        // ny x kEkMax basis of the B side

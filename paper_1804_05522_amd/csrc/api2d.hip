@@ -11,9 +11,10 @@ enum { kR_R0 = 0, kR_D0 = 1, kR_D1 = 2, kR_X0 = 3, kR_X1 = 4, kR_T = 5, kR_C = 6
        kR_CAP = 10,   // bit mask of the work slots whose recompression hit its rank cap above its tolerance
        kR_K0 = 11, kR_K1 = 12,   // rank of the correction sum X_corr (ping-pong)
        kR_Q1 = 13, kR_Q2 = 14,   // ranks of the orthonormalised sketches of a dense compression
-       kR_EK1 = 15, kR_EK2 = 16, // extended Krylov: ranks of a new block's two orthonormalisations
-       kR_EQ1 = 17, kR_EQ2 = 18, // and of the projected solution's range
-       kR_N = 19 };
+       kR_EK1 = 15, kR_EK2 = 16, // extended Krylov: ranks of a new A-side block's two orthonormalisations,
+       kR_EQ1 = 17, kR_EQ2 = 18, // of the projected solution's range,
+       kR_EK3 = 19, kR_EK4 = 20, // and of a new B-side block's
+       kR_N = 21 };
 constexpr int kMaxCorrections = 6;   // correction sweeps of a step after the first
 constexpr int kSketch = 32;          // sketch columns of a dense compression
 
@@ -535,7 +536,8 @@ struct EkSide {
 // C = alpha op(A) op(B) + beta C (k_ek_gemm), the inner dimension split over
 // work-groups when the output has few tiles.
 hodlr_status ek_gemm(fde2d_plan P, int ta, int tb, int M, int N, int64_t K, double alpha, const double* A,
-                     int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
+                     int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s,
+                     const int32_t* ndev = nullptr) {
   if (M <= 0 || N <= 0) return HODLR_OK;
   const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
   int64_t kchunk = std::max<int64_t>(K, 1);
@@ -546,10 +548,10 @@ hodlr_status ek_gemm(fde2d_plan P, int ta, int tb, int M, int N, int64_t K, doub
   }
   const int nsplit = int(std::max<int64_t>(1, (K + kchunk - 1) / kchunk));
   HFDE_LAUNCH(k_ek_gemm, dim3(unsigned((M + 63) / 64), unsigned((N + 63) / 64), unsigned(nsplit)), dim3(256), 0, s,
-              ta, tb, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, P->ekPart);
+              ta, tb, M, N, ndev, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, P->ekPart);
   if (nsplit > 1)
     HFDE_LAUNCH(k_ek_gemm_sum, dim3(unsigned(std::min<int64_t>((int64_t(M) * N + 255) / 256, 1024))), dim3(256), 0,
-                s, M, N, nsplit, P->ekPart, alpha, beta, C, ldc);
+                s, M, N, ndev, nsplit, P->ekPart, alpha, beta, C, ldc);
   return HODLR_OK;
 }
 
@@ -566,7 +568,15 @@ hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
   if (P->ek_ready) return HODLR_OK;
   const int64_t nx = P->nx, ny = P->ny, mr = std::max(nx, ny);
   const int64_t E2 = int64_t(kEkMax) * kEkMax;
-  const int J = P->J;
+  // the projected equation's shift pairs: as many as the intervals need for
+  // opts.tol / 10, whatever cap the plan's shifted factor sets have
+  int J = 1;
+  for (; J < 64; ++J) {
+    zolotarev_shifts(P->iv[0], P->iv[1], P->iv[2], P->iv[3], J, P->ek_p, P->ek_q);
+    if (zolotarev_bound(P->iv[0], P->iv[1], P->iv[2], P->iv[3], P->ek_p, P->ek_q) <= 0.1 * P->opts.tol) break;
+  }
+  zolotarev_shifts(P->iv[0], P->iv[1], P->iv[2], P->iv[3], J, P->ek_p, P->ek_q);
+  P->ek_J = J;
   bool ok = plan_alloc(P, &P->ekU, nx * kEkMax) == HODLR_OK && plan_alloc(P, &P->ekAU, nx * kEkMax) == HODLR_OK &&
             plan_alloc(P, &P->ekV, ny * kEkMax) == HODLR_OK && plan_alloc(P, &P->ekBV, ny * kEkMax) == HODLR_OK &&
             plan_alloc(P, &P->ekTA, E2) == HODLR_OK && plan_alloc(P, &P->ekTB, E2) == HODLR_OK &&
@@ -595,8 +605,8 @@ hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
   if (!ok) return P->ws ? HODLR_EWORKSPACE : HODLR_ENOMEM;
   std::vector<double> sh(2 * J);
   for (int j = 0; j < J; ++j) {
-    sh[j] = P->q[j];
-    sh[J + j] = P->p[j];
+    sh[j] = P->ek_q[j];
+    sh[J + j] = P->ek_p[j];
   }
   HIP_TRY(hipMemcpyAsync(P->ekShift, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, s));
   HFDE_LAUNCH(k_set_identity, dim3((kEkSk * kEkSk + 255) / 256), dim3(256), 0, s, P->ekEye, kEkSk, kEkSk);
@@ -609,16 +619,18 @@ hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
   return HODLR_OK;
 }
 
-// Append the c-column candidate block in ekW (ld n) to the side's basis:
-// two block Gram-Schmidt passes, an orthonormalisation that drops the
-// directions below kEkDrop times the block's norm, one more pass and a final
-// orthonormalisation into the basis.  `added` is the number of new columns.
-hodlr_status ek_add(fde2d_plan P, EkSide& S, int c, int& added, hipStream_t s) {
-  added = 0;
-  if (c <= 0 || S.m >= kEkMax) return HODLR_OK;
+// Enqueue the append of the c-column candidate block in ekW (ld n) to the
+// side's basis (side 0: A, 1: B): two block Gram-Schmidt passes, an
+// orthonormalisation that drops the directions below kEkDrop times the
+// block's norm before the passes (read on the device), one more pass and a
+// final orthonormalisation into the basis columns S.m ..; the number of new
+// columns lands in ranks[kR_EK2] (side 0) or ranks[kR_EK4] (side 1).  Nothing
+// waits for the device: ek_add_pair reads both counts.
+hodlr_status ek_add(fde2d_plan P, const EkSide& S, int c, int side, hipStream_t s) {
   const int64_t n = S.n;
-  int32_t hr[kR_N];
-  double w2 = 0.0;
+  const int sl1 = side ? 20 : 16, sl2 = side ? 21 : 17;
+  int32_t* rk1 = P->ranks + (side ? kR_EK3 : kR_EK1);
+  int32_t* rk2 = P->ranks + (side ? kR_EK4 : kR_EK2);
   LrJob fj{};
   fj.X.g[0] = grp(P->ekW, n, nullptr, c, 1.0);
   fj.X.g[1] = fj.X.g[2] = grp_none();
@@ -626,8 +638,7 @@ hodlr_status ek_add(fde2d_plan P, EkSide& S, int c, int& added, hipStream_t s) {
   fj.Y.g[1] = fj.Y.g[2] = grp_none();
   fj.rows_x = n;
   fj.rows_y = kEkSk;
-  TRY(run_lr(P, fj, 16, false, s));
-  TRY(read_frob(P, 16, &w2, s));
+  TRY(run_lr(P, fj, sl1, false, s));                  // ||W||_F^2 into frob[sl1]
   for (int pass = 0; pass < 2 && S.m > 0; ++pass) {
     TRY(ek_gemm(P, 1, 0, S.m, c, n, 1.0, S.Q, n, P->ekW, n, 0.0, P->ekS, kEkMax, s));    // Q^T W
     TRY(ek_gemm(P, 0, 0, int(n), c, S.m, -1.0, S.Q, n, P->ekS, kEkMax, 1.0, P->ekW, n, s));   // W -= Q (Q^T W)
@@ -639,30 +650,29 @@ hodlr_status ek_add(fde2d_plan P, EkSide& S, int c, int& added, hipStream_t s) {
   oj.Y.g[1] = oj.Y.g[2] = grp_none();
   oj.rows_x = n;
   oj.rows_y = kEkSk;
-  oj.rank_out = P->ranks + kR_EK1;
-  oj.tau = kEkDrop * std::sqrt(std::max(w2, 0.0));
+  oj.rank_out = rk1;
+  oj.tau = 0.0;
   oj.tau_rel = 0.0;
+  oj.tau_sq = P->frob + sl1;
+  oj.tau_sq_scale = kEkDrop;
   oj.rmax = std::min(kRS, kEkMax - S.m);
   oj.U = P->ekO;
   oj.ldu = n;
   oj.V = P->ekJunk;
   oj.ldv = kEkSk;
-  TRY(run_lr(P, oj, 16, true, s));
-  TRY(read_ranks(P, hr, s));
-  const int r1 = hr[kR_EK1];
-  if (r1 == 0) return HODLR_OK;
+  TRY(run_lr(P, oj, sl1, true, s));
   if (S.m > 0) {
-    TRY(ek_gemm(P, 1, 0, S.m, r1, n, 1.0, S.Q, n, P->ekO, n, 0.0, P->ekS, kEkMax, s));
-    TRY(ek_gemm(P, 0, 0, int(n), r1, S.m, -1.0, S.Q, n, P->ekS, kEkMax, 1.0, P->ekO, n, s));
+    TRY(ek_gemm(P, 1, 0, S.m, c, n, 1.0, S.Q, n, P->ekO, n, 0.0, P->ekS, kEkMax, s, rk1));
+    TRY(ek_gemm(P, 0, 0, int(n), c, S.m, -1.0, S.Q, n, P->ekS, kEkMax, 1.0, P->ekO, n, s, rk1));
   }
   LrJob qj{};
-  qj.X.g[0] = grp(P->ekO, n, nullptr, r1, 1.0);
+  qj.X.g[0] = grp(P->ekO, n, rk1, 0, 1.0);
   qj.X.g[1] = qj.X.g[2] = grp_none();
-  qj.Y.g[0] = grp(P->ekEye, kEkSk, nullptr, r1, 1.0);
+  qj.Y.g[0] = grp(P->ekEye, kEkSk, rk1, 0, 1.0);
   qj.Y.g[1] = qj.Y.g[2] = grp_none();
   qj.rows_x = n;
   qj.rows_y = kEkSk;
-  qj.rank_out = P->ranks + kR_EK2;
+  qj.rank_out = rk2;
   qj.tau = 0.0;
   qj.tau_rel = 1e-6;
   qj.rmax = std::min(kRS, kEkMax - S.m);
@@ -670,10 +680,30 @@ hodlr_status ek_add(fde2d_plan P, EkSide& S, int c, int& added, hipStream_t s) {
   qj.ldu = n;
   qj.V = P->ekJunk;
   qj.ldv = kEkSk;
-  TRY(run_lr(P, qj, 17, true, s));
+  return run_lr(P, qj, sl2, true, s);
+}
+
+// Append candidate blocks to both bases: A's from srcA (ca columns, ld
+// lda), B's from srcB; one wait for the two new column counts.
+hodlr_status ek_add_pair(fde2d_plan P, EkSide& A, const double* srcA, int64_t lda, int ca, EkSide& B,
+                         const double* srcB, int64_t ldb, int cb, int& added_a, int& added_b, hipStream_t s) {
+  added_a = added_b = 0;
+  const bool da = ca > 0 && A.m < kEkMax, db = cb > 0 && B.m < kEkMax;
+  if (da) {
+    copy_cols(A.n, nullptr, ca, srcA, lda, P->ekW, A.n, 1.0, s);
+    TRY(ek_add(P, A, ca, 0, s));
+  }
+  if (db) {
+    copy_cols(B.n, nullptr, cb, srcB, ldb, P->ekW, B.n, 1.0, s);
+    TRY(ek_add(P, B, cb, 1, s));
+  }
+  if (!da && !db) return HODLR_OK;
+  int32_t hr[kR_N];
   TRY(read_ranks(P, hr, s));
-  added = hr[kR_EK2];
-  S.m += added;
+  if (da) added_a = hr[kR_EK2];
+  if (db) added_b = hr[kR_EK4];
+  A.m += added_a;
+  B.m += added_b;
   return HODLR_OK;
 }
 
@@ -724,10 +754,7 @@ hodlr_status ek_inverse_half(fde2d_plan P, EkSide& A, int ao, int ac, EkSide& B,
       launch_solve(mx, mx->opts.prec, r, ld, d, ld, c, s);
       launch_axpby(ld, c, 1.0, d, ld, 1.0, P->ex_out, ld, P->ex_out, ld, s);
     }
-    copy_cols(nx, nullptr, ac, P->ex_out, ld, P->ekW, nx, 1.0, s);
-    TRY(ek_add(P, A, ac, added_a, s));
-    copy_cols(ny, nullptr, bc, P->ex_out + nx, ld, P->ekW, ny, 1.0, s);
-    TRY(ek_add(P, B, bc, added_b, s));
+    TRY(ek_add_pair(P, A, P->ex_out, ld, ac, B, P->ex_out + nx, ld, bc, added_a, added_b, s));
   }
   A.o2 = a0;
   A.c2 = added_a;
@@ -737,12 +764,12 @@ hodlr_status ek_inverse_half(fde2d_plan P, EkSide& A, int ao, int ac, EkSide& B,
 }
 
 // The projected equation on the current bases: U^T G, V^T H, the LU
-// factors and inverses of the 2J shifted projected matrices, the projected
-// fADI over the shift pairs (K_Z, K_Y), Y = K_Z K_Y^T, and the norm of the
+// factors and inverses of the 2 ek_J shifted projected matrices, the projected
+// fADI over those shift pairs (K_Z, K_Y), Y = K_Z K_Y^T, and the norm of the
 // residual of U Y V^T (three orthogonal terms).
 hodlr_status ek_projected(fde2d_plan P, const EkSide& A, const EkSide& B, int r0, double& rn, hipStream_t s) {
   const int64_t nx = P->nx, ny = P->ny;
-  const int mA = A.m, mB = B.m, J = P->J;
+  const int mA = A.m, mB = B.m, J = P->ek_J;
   const int64_t E2 = int64_t(kEkMax) * kEkMax;
   TRY(ek_gemm(P, 1, 0, mA, r0, nx, 1.0, A.Q, nx, P->G, nx, 0.0, P->ekG0, kEkMax, s));
   TRY(ek_gemm(P, 1, 0, mB, r0, ny, 1.0, B.Q, ny, P->H, ny, 0.0, P->ekH0, kEkMax, s));
@@ -754,10 +781,10 @@ hodlr_status ek_projected(fde2d_plan P, const EkSide& A, const EkSide& B, int r0
   const double* gin = P->ekG0;
   const double* hin = P->ekH0;
   for (int jo = 0; jo < J; ++jo) {
-    const int j = P->order[jo];
+    const int j = jo;
     double* gout = P->ekG[jo & 1];
     double* hout = P->ekH[jo & 1];
-    HFDE_LAUNCH(k_ek_adi_pair, dim3(tiles), dim3(256), 0, s, mA, mB, r0, P->p[j] + P->q[j], P->ekInv + j * E2,
+    HFDE_LAUNCH(k_ek_adi_pair, dim3(tiles), dim3(256), 0, s, mA, mB, r0, P->ek_p[j] + P->ek_q[j], P->ekInv + j * E2,
                 P->ekInv + (J + j) * E2, int64_t(kEkMax), gin, hin, gout, hout, P->ekKZ, P->ekKY, int64_t(kEkMax),
                 jo * r0);
     gin = gout;
@@ -858,13 +885,10 @@ hodlr_status ek_solve(fde2d_plan P, int r0, double target, int kind, int& steps,
   TRY(ek_prepare(P, s));
   const bool verbose = getenv("HODLR_VERBOSE") != nullptr;
   EkSide A{P->ekU, P->ekAU, P->ekTA, nx}, B{P->ekV, P->ekBV, P->ekTB, ny};
-  int added = 0;
-  copy_cols(nx, nullptr, r0, P->G, nx, P->ekW, nx, 1.0, s);
-  TRY(ek_add(P, A, r0, added, s));
-  A.c1 = added;
-  copy_cols(ny, nullptr, r0, P->H, ny, P->ekW, ny, 1.0, s);
-  TRY(ek_add(P, B, r0, added, s));
-  B.c1 = added;
+  int added_a = 0, added_b = 0;
+  TRY(ek_add_pair(P, A, P->G, nx, r0, B, P->H, ny, r0, added_a, added_b, s));
+  A.c1 = added_a;
+  B.c1 = added_b;
   TRY(ek_products(P, A, 0, B, 0, s));
   TRY(ek_inverse_half(P, A, A.o1, A.c1, B, B.o1, B.c1, s));
   int next = std::max(1, P->ek_last[kind] - 1), prev_it = 0, checks = 0;
@@ -889,14 +913,12 @@ hodlr_status ek_solve(fde2d_plan P, int r0, double target, int kind, int& steps,
       next = it + more;
     }
     const int a0 = A.m, b0 = B.m;
-    copy_cols(nx, nullptr, A.c1, A.AQ + int64_t(A.o1) * nx, nx, P->ekW, nx, 1.0, s);
-    TRY(ek_add(P, A, A.c1, added, s));
+    TRY(ek_add_pair(P, A, A.AQ + int64_t(A.o1) * nx, nx, A.c1, B, B.AQ + int64_t(B.o1) * ny, ny, B.c1, added_a,
+                    added_b, s));
     A.o1 = a0;
-    A.c1 = added;
-    copy_cols(ny, nullptr, B.c1, B.AQ + int64_t(B.o1) * ny, ny, P->ekW, ny, 1.0, s);
-    TRY(ek_add(P, B, B.c1, added, s));
+    A.c1 = added_a;
     B.o1 = b0;
-    B.c1 = added;
+    B.c1 = added_b;
     TRY(ek_products(P, A, a0, B, b0, s));
     TRY(ek_inverse_half(P, A, A.o2, A.c2, B, B.o2, B.c2, s));
   }
@@ -1030,6 +1052,10 @@ static hodlr_status plan2d_impl(hodlr_ctx ctx, const fde_operator* opx, const fd
   if (st == HODLR_OK) st = upper(opy, b2, l2);
   if (st != HODLR_OK) { fde2d_plan_destroy(P); return st; }
   const double a1 = opx->shift, a2 = opy->shift;
+  P->iv[0] = a1;
+  P->iv[1] = b1;
+  P->iv[2] = a2;
+  P->iv[3] = b2;
   P->bound_x = l1;
   P->bound_y = l2;
   if (opx->discretization == FDE_FE) { P->fe = true; P->mass_x = 2.0 / 3.0; P->mc_x = 0.25; }
@@ -1210,8 +1236,9 @@ hodlr_status fde2d_plan_counters(fde2d_plan P, double* values, int count, int re
   HIP_TRY(hipMemcpy(&core, P->counters, sizeof(double), hipMemcpyDeviceToHost));
   hodlr_mat_info mi{};
   if (P->mat) TRY(hodlr_get_info(P->mat, &mi));
-  const double v[5] = {core, P->lrs_flops, double(mi.bytes_factors), double(P->J), double(mi.max_rank_factors)};
-  for (int i = 0; i < count && i < 5; ++i) values[i] = v[i];
+  const double v[6] = {core, P->lrs_flops, double(mi.bytes_factors), double(P->J), double(mi.max_rank_factors),
+                       double(P->ek_J)};
+  for (int i = 0; i < count && i < 6; ++i) values[i] = v[i];
   if (reset) {
     HIP_TRY(hipMemset(P->counters, 0, sizeof(double)));
     P->lrs_flops = 0.0;

@@ -15,20 +15,24 @@ constexpr int kEkSplit = 32;     // largest split of an inner dimension (k_ek_ge
 constexpr int kEkWG = 1024;      // threads of the LU work-groups
 
 // C = alpha op(A) op(B) + beta C for column-major A, B, C; op(X) = X (t = 0)
-// or X^T (t = 1); C is M x N, the inner dimension K.  Work-group (x, y, z)
+// or X^T (t = 1); C is M x N (N clipped to *ndev when ndev is set, the grid
+// sized for N), the inner dimension K.  Work-group (x, y, z)
 // takes the 64 x 64 output tile (x, y) over the inner indices
 // [z kchunk, min(K, (z + 1) kchunk)): with one split (gridDim.z == 1) it
 // writes C, otherwise its partial tile into part + z M N (M x N, ld M), which
 // k_ek_gemm_sum adds up.  256 threads, 4 x 4 outputs each; 16-deep slices of
 // both operands staged in LDS, loaded along the contiguous index.
-__global__ void __launch_bounds__(256) k_ek_gemm(int ta, int tb, int M, int N, int64_t K, int64_t kchunk,
-                                                 double alpha, const double* A, int64_t lda, const double* B,
-                                                 int64_t ldb, double beta, double* C, int64_t ldc, double* part) {
+__global__ void __launch_bounds__(256) k_ek_gemm(int ta, int tb, int M, int N, const int32_t* ndev, int64_t K,
+                                                 int64_t kchunk, double alpha, const double* A, int64_t lda,
+                                                 const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                                                 double* part) {
   constexpr int kK = 16;
   __shared__ double As[kK][65];
   __shared__ double Bs[kK][65];
+  if (ndev) N = min(N, *ndev);
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  if (j0 >= N) return;
   const int64_t k0 = int64_t(blockIdx.z) * kchunk;
   const int64_t k1 = min(K, k0 + kchunk);
   double acc[4][4] = {};
@@ -71,14 +75,15 @@ __global__ void __launch_bounds__(256) k_ek_gemm(int ta, int tb, int M, int N, i
         double* cp = C + i + int64_t(j) * ldc;
         *cp = alpha * acc[r][c] + (beta == 0.0 ? 0.0 : beta * *cp);
       } else {
-        part[int64_t(blockIdx.z) * M * N + i + int64_t(j) * M] = acc[r][c];
+        part[int64_t(blockIdx.z) * M * N + i + int64_t(j) * M] = acc[r][c];   // N clipped: same layout as the sum's
       }
     }
 }
 
-// C = alpha sum_z part_z + beta C (M x N).
-__global__ void k_ek_gemm_sum(int M, int N, int nsplit, const double* part, double alpha, double beta, double* C,
-                              int64_t ldc) {
+// C = alpha sum_z part_z + beta C (M x N, N clipped to *ndev when set).
+__global__ void k_ek_gemm_sum(int M, int N, const int32_t* ndev, int nsplit, const double* part, double alpha,
+                              double beta, double* C, int64_t ldc) {
+  if (ndev) N = min(N, *ndev);
   const int64_t tot = int64_t(M) * N;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
     double s = 0.0;
