@@ -509,9 +509,9 @@ hodlr_status adi_sweep(fde2d_plan P, int r0, double target, int& steps, int& par
 // block Arnoldi processes; the products with A and B are the exact Toeplitz
 // products, the solves the plain HODLR solves with the unshifted factors),
 // the projected equation T_A Y + Y T_B^T = (U^T G)(V^T H)^T is solved, and
-// D = U Y V^T.  A new block is orthogonalised against the basis by two block
-// Gram-Schmidt passes and orthonormalised with its directions below 1e-10 of
-// its norm before the passes dropped (deflation: the block shrinks once the
+// D = U Y V^T.  A new block is orthogonalised against the basis by a block
+// Gram-Schmidt pass and orthonormalised with its directions below 1e-10 of
+// its norm before the pass dropped (deflation: the block shrinks once the
 // space stops growing in a direction), then projected and orthonormalised
 // once more.  The projected equation is solved by factored ADI with the
 // plan's shift pairs on explicit inverses of T_A + q_j I and T_B + p_j I.
@@ -620,9 +620,9 @@ hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
 }
 
 // Enqueue the append of the c-column candidate block in ekW (ld n) to the
-// side's basis (side 0: A, 1: B): two block Gram-Schmidt passes, an
+// side's basis (side 0: A, 1: B): a block Gram-Schmidt pass, an
 // orthonormalisation that drops the directions below kEkDrop times the
-// block's norm before the passes (read on the device), one more pass and a
+// block's norm before the pass (read on the device), one more pass and a
 // final orthonormalisation into the basis columns S.m ..; the number of new
 // columns lands in ranks[kR_EK2] (side 0) or ranks[kR_EK4] (side 1).  Nothing
 // waits for the device: ek_add_pair reads both counts.
@@ -639,7 +639,7 @@ hodlr_status ek_add(fde2d_plan P, const EkSide& S, int c, int side, hipStream_t 
   fj.rows_x = n;
   fj.rows_y = kEkSk;
   TRY(run_lr(P, fj, sl1, false, s));                  // ||W||_F^2 into frob[sl1]
-  for (int pass = 0; pass < 2 && S.m > 0; ++pass) {
+  if (S.m > 0) {
     TRY(ek_gemm(P, 1, 0, S.m, c, n, 1.0, S.Q, n, P->ekW, n, 0.0, P->ekS, kEkMax, s));    // Q^T W
     TRY(ek_gemm(P, 0, 0, int(n), c, S.m, -1.0, S.Q, n, P->ekS, kEkMax, 1.0, P->ekW, n, s));   // W -= Q (Q^T W)
   }

@@ -309,6 +309,7 @@ __global__ void __launch_bounds__(256) k_ek_adi_pair(int mA, int mB, int r, doub
                                                      const double* Hin, double* Gout, double* Hout, double* KZ,
                                                      double* KY, int64_t ldk, int off) {
   __shared__ double part[16 * 16 * 33];
+  __shared__ double rin[64 * 33];             // a 64-row slice of the right-hand side
   const int tA = (mA + 15) / 16;
   const bool sa = int(blockIdx.x) < tA;
   const int tile = sa ? blockIdx.x : blockIdx.x - tA;
@@ -323,13 +324,21 @@ __global__ void __launch_bounds__(256) k_ek_adi_pair(int mA, int mB, int r, doub
   double acc[32];
 #pragma unroll
   for (int c = 0; c < 32; ++c) acc[c] = 0.0;
-  if (i < m) {
-    for (int k = kg; k < m; k += 16) {
-      const double a = I[i + int64_t(k) * ldi];
-#pragma unroll
-      for (int c = 0; c < 32; ++c)
-        if (c < r) acc[c] += a * in[k + int64_t(c) * kEkMax];
+  for (int k0 = 0; k0 < m; k0 += 64) {
+    const int kn = min(64, m - k0);
+    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+      const int k = e % 64, c = e / 64;
+      rin[k * 33 + c] = (k < kn && c < r) ? in[(k0 + k) + int64_t(c) * kEkMax] : 0.0;
     }
+    __syncthreads();
+    if (i < m) {
+      for (int k = kg; k < kn; k += 16) {
+        const double a = I[i + int64_t(k0 + k) * ldi];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) acc[c] += a * rin[k * 33 + c];
+      }
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int c = 0; c < 32; ++c) part[(kg * 16 + rl) * 33 + c] = acc[c];
