@@ -51,8 +51,8 @@ def parse():
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--n2d", type=int, default=4096, help="grid points per direction of fd_2d / fe_2d")
     ap.add_argument("--solver", default="fadi", choices=["fadi", "ek"],
-                    help="fd_2d: per-step Sylvester solver (factored ADI with shifted HODLR solves, or extended "
-                         "Krylov with the unshifted ones)")
+                    help="fd_2d / fe_2d: per-step Sylvester solver (factored ADI with shifted HODLR solves, or "
+                         "extended Krylov with the unshifted ones)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-2d", action="store_true", help="var_1d only: skip the 2D 4096^2 sub-object")
@@ -398,7 +398,7 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
     outs = [(torch.zeros((64, n), dtype=torch.float64, device="cuda"),
              torch.zeros((64, n), dtype=torch.float64, device="cuda")) for _ in range(2)]
 
-    ek = getattr(args, "solver", "fadi") == "ek" and not fe
+    ek = getattr(args, "solver", "fadi") == "ek"
 
     def job(pr, timing=None, keep=False, use_ek=None):
         use_ek = ek if use_ek is None else use_ek
@@ -468,7 +468,7 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
         job_s64, _, _, _, _, _ = measure("fp64")
         out["fp64_path"] = {"value": K / job_s64, "ms_per_step": 1e3 * job_s64}
         out["mixed_vs_fp64"] = job_s64 / job_s
-    if compare and not fe:
+    if compare:
         # the other per-step solver on the same job (Sec. 4.3's extended Krylov
         # beside the shifted-solve fADI, or the reverse)
         job_o, parts_o, _, it_o, worst_o, _ = measure(prec, use_ek=not ek)

@@ -432,9 +432,11 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* 
  * pivoting) of the shifted projected matrices, until the residual of U Y V^T
  * (formed from three orthogonal terms) is at most the solve's target; the
  * solve's result U Y V^T is then compressed to at most 32 columns.
- * Arguments, outputs and stopping as fde2d_sylvester_step, except that
- * info->refine_iters counts extended Krylov iterations.  Finite differences
- * only: a finite-element plan gives HODLR_EINVAL with hodlr_last_arg() == 2.
+ * Finite elements: the same on E_x^-1 A D + D (E_y^-1 B)^T = (E_x^-1 G)(E_y^-1 H)^T
+ * (the operator products followed by tridiagonal mass solves, the inverses
+ * as A^-1 E; its residual bounds the generalized one, E's eigenvalues being
+ * below 1).  Arguments, outputs and stopping as fde2d_sylvester_step, except
+ * that info->refine_iters counts extended Krylov iterations.
  * A plan made by fde2d_plan_create_ws has no room for the solver's arrays
  * (HODLR_EWORKSPACE).  The plan's shifted factor sets are not used: the
  * projected equation takes its own Zolotarev shift pairs on the plan's

@@ -361,6 +361,10 @@ struct fde2d_plan_s {
   double* ekY1 = nullptr;       // kEkMax x kEkMax products with the projected matrices
   double* ekRs = nullptr;       // kEkMax x kEkMax projected residual
   double* ekNrm = nullptr;      // device: sums of squares of the three residual terms
+  double* ekPivX = nullptr;     // finite elements: pivots of the mass matrices' tridiagonal LU (nx, ny)
+  double* ekPivY = nullptr;
+  double* ekGt = nullptr;       // finite elements: E_x^-1 G, E_y^-1 H (kRS columns)
+  double* ekHt = nullptr;
   std::vector<void*> allocs;
 };
 

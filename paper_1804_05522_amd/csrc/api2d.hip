@@ -601,8 +601,18 @@ hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
        plan_alloc(P, &P->ekG0, int64_t(kEkMax) * kRS) == HODLR_OK &&
        plan_alloc(P, &P->ekH0, int64_t(kEkMax) * kRS) == HODLR_OK && plan_alloc(P, &P->ekR, mr * kEkMax) == HODLR_OK &&
        plan_alloc(P, &P->ekY1, E2) == HODLR_OK && plan_alloc(P, &P->ekRs, E2) == HODLR_OK &&
-       plan_alloc(P, &P->ekNrm, 4) == HODLR_OK;
+       plan_alloc(P, &P->ekNrm, 4) == HODLR_OK && plan_alloc(P, &P->ekPivX, nx) == HODLR_OK &&
+       plan_alloc(P, &P->ekPivY, ny) == HODLR_OK && plan_alloc(P, &P->ekGt, nx * kRS) == HODLR_OK &&
+       plan_alloc(P, &P->ekHt, ny * kRS) == HODLR_OK;
   if (!ok) return P->ws ? HODLR_EWORKSPACE : HODLR_ENOMEM;
+  // pivots of the mass matrices' tridiagonal LU: m_0 = 1, m_i = 1 - mc^2 / m_{i-1}
+  for (int side = 0; side < 2; ++side) {
+    const double mc = side == 0 ? P->mc_x : P->mc_y;
+    const int64_t n = side == 0 ? nx : ny;
+    std::vector<double> piv(n, 1.0);
+    for (int64_t i = 1; i < n; ++i) piv[i] = 1.0 - mc * mc / piv[i - 1];
+    HIP_TRY(hipMemcpy(side == 0 ? P->ekPivX : P->ekPivY, piv.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  }
   std::vector<double> sh(2 * J);
   for (int j = 0; j < J; ++j) {
     sh[j] = P->ek_q[j];
@@ -617,6 +627,14 @@ hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
   if (st != HODLR_OK && st != HODLR_ERANK) return st;
   P->ek_ready = true;
   return HODLR_OK;
+}
+
+// X <- E^-1 X on `cols` columns of one side (0: x, 1: y); nothing for an identity E.
+void ek_mass_solve(fde2d_plan P, int side, int cols, double* X, int64_t ld, hipStream_t s) {
+  const double mass = side == 0 ? P->mass_x : P->mass_y, mc = side == 0 ? P->mc_x : P->mc_y;
+  if (cols <= 0 || (mc == 0.0 && mass == 1.0)) return;
+  HFDE_LAUNCH(k_ek_mass_solve, dim3(1), dim3(64), 0, s, side == 0 ? P->nx : P->ny, cols, mass, mc,
+              side == 0 ? P->ekPivX : P->ekPivY, X, ld);
 }
 
 // Enqueue the append of the c-column candidate block in ekW (ld n) to the
@@ -717,6 +735,8 @@ hodlr_status ek_products(fde2d_plan P, EkSide& A, int a0, EkSide& B, int b0, hip
   copy_cols(nx, nullptr, ca, A.Q + int64_t(a0) * nx, nx, P->ex_in, ld, 1.0, s);
   copy_cols(ny, nullptr, cb, B.Q + int64_t(b0) * ny, ny, P->ex_in + nx, ld, 1.0, s);
   launch_fft_matvec(P->exact, P->ex_in, ld, P->ex_out, ld, nullptr, 0, c, s);
+  ek_mass_solve(P, 0, ca, P->ex_out, ld, s);            // finite elements: E_x^-1 A, E_y^-1 B
+  ek_mass_solve(P, 1, cb, P->ex_out + nx, ld, s);
   copy_cols(nx, nullptr, ca, P->ex_out, ld, A.AQ + int64_t(a0) * nx, nx, 1.0, s);
   copy_cols(ny, nullptr, cb, P->ex_out + nx, ld, B.AQ + int64_t(b0) * ny, ny, 1.0, s);
   for (int side = 0; side < 2; ++side) {
@@ -739,8 +759,9 @@ hodlr_status ek_inverse_half(fde2d_plan P, EkSide& A, int ao, int ac, EkSide& B,
   const int c = std::max(ac, bc), a0 = A.m, b0 = B.m;
   int added_a = 0, added_b = 0;
   if (c > 0) {
-    copy_cols(nx, nullptr, ac, A.Q + int64_t(ao) * nx, nx, P->ex_in, ld, 1.0, s);
-    copy_cols(ny, nullptr, bc, B.Q + int64_t(bo) * ny, ny, P->ex_in + nx, ld, 1.0, s);
+    // b = E v (finite elements: (E^-1 A)^-1 = A^-1 E)
+    mass_cols(nx, ac, P->mass_x, P->mc_x, A.Q + int64_t(ao) * nx, nx, P->ex_in, ld, 1.0, s);
+    mass_cols(ny, bc, P->mass_y, P->mc_y, B.Q + int64_t(bo) * ny, ny, P->ex_in + nx, ld, 1.0, s);
     // x = M^-1 b with the stored factors, then refinement steps x += M^-1 (b - M x)
     // (exact products): the plain solve's error (about the factors'
     // precision times the condition) would perturb the inverse half of the basis
@@ -767,12 +788,13 @@ hodlr_status ek_inverse_half(fde2d_plan P, EkSide& A, int ao, int ac, EkSide& B,
 // factors and inverses of the 2 ek_J shifted projected matrices, the projected
 // fADI over those shift pairs (K_Z, K_Y), Y = K_Z K_Y^T, and the norm of the
 // residual of U Y V^T (three orthogonal terms).
-hodlr_status ek_projected(fde2d_plan P, const EkSide& A, const EkSide& B, int r0, double& rn, hipStream_t s) {
+hodlr_status ek_projected(fde2d_plan P, const EkSide& A, const EkSide& B, const double* G, const double* H, int r0,
+                          double& rn, hipStream_t s) {
   const int64_t nx = P->nx, ny = P->ny;
   const int mA = A.m, mB = B.m, J = P->ek_J;
   const int64_t E2 = int64_t(kEkMax) * kEkMax;
-  TRY(ek_gemm(P, 1, 0, mA, r0, nx, 1.0, A.Q, nx, P->G, nx, 0.0, P->ekG0, kEkMax, s));
-  TRY(ek_gemm(P, 1, 0, mB, r0, ny, 1.0, B.Q, ny, P->H, ny, 0.0, P->ekH0, kEkMax, s));
+  TRY(ek_gemm(P, 1, 0, mA, r0, nx, 1.0, A.Q, nx, G, nx, 0.0, P->ekG0, kEkMax, s));
+  TRY(ek_gemm(P, 1, 0, mB, r0, ny, 1.0, B.Q, ny, H, ny, 0.0, P->ekH0, kEkMax, s));
   HFDE_LAUNCH(k_ek_lu, dim3(2 * J), dim3(kEkWG), 0, s, J, mA, A.T, mB, B.T, int64_t(kEkMax), P->ekShift, P->ekLU,
               int64_t(kEkMax), E2, P->ekPiv, P->ekFlag);
   HFDE_LAUNCH(k_ek_lu_inv, dim3(unsigned((std::max(mA, mB) + 15) / 16), unsigned(2 * J)), dim3(256), 0, s, J, mA,
@@ -885,8 +907,19 @@ hodlr_status ek_solve(fde2d_plan P, int r0, double target, int kind, int& steps,
   TRY(ek_prepare(P, s));
   const bool verbose = getenv("HODLR_VERBOSE") != nullptr;
   EkSide A{P->ekU, P->ekAU, P->ekTA, nx}, B{P->ekV, P->ekBV, P->ekTB, ny};
+  // finite elements: the equation E_x^-1 A D + D (E_y^-1 B)^T = (E_x^-1 G)(E_y^-1 H)^T
+  const double* G = P->G;
+  const double* H = P->H;
+  if (P->fe) {
+    copy_cols(nx, nullptr, r0, P->G, nx, P->ekGt, nx, 1.0, s);
+    copy_cols(ny, nullptr, r0, P->H, ny, P->ekHt, ny, 1.0, s);
+    ek_mass_solve(P, 0, r0, P->ekGt, nx, s);
+    ek_mass_solve(P, 1, r0, P->ekHt, ny, s);
+    G = P->ekGt;
+    H = P->ekHt;
+  }
   int added_a = 0, added_b = 0;
-  TRY(ek_add_pair(P, A, P->G, nx, r0, B, P->H, ny, r0, added_a, added_b, s));
+  TRY(ek_add_pair(P, A, G, nx, r0, B, H, ny, r0, added_a, added_b, s));
   A.c1 = added_a;
   B.c1 = added_b;
   TRY(ek_products(P, A, 0, B, 0, s));
@@ -898,7 +931,7 @@ hodlr_status ek_solve(fde2d_plan P, int r0, double target, int kind, int& steps,
     const bool stuck = A.c1 + A.c2 + B.c1 + B.c2 == 0;
     const bool last = full || stuck || it >= kEkIterMax;
     if (it >= next || last) {
-      TRY(ek_projected(P, A, B, r0, rn, s));
+      TRY(ek_projected(P, A, B, G, H, r0, rn, s));
       ++checks;
       steps = it;
       if (rn <= target || last) break;
@@ -1669,7 +1702,6 @@ hodlr_status fde2d_sylvester_step_ek(hodlr_ctx ctx, fde2d_plan P, const lr_matri
                                      double dt, lr_matrix* U_next, hodlr_info* info) {
   if (!ctx) return HODLR_EINVAL;
   if (!P) return set_arg(ctx, 2);
-  if (P->fe) return set_arg(ctx, 2);
   P->use_ek = true;
   const hodlr_status st = fde2d_sylvester_step_guess(ctx, P, U_m, F, dt, nullptr, U_next, info);
   P->use_ek = false;

@@ -372,3 +372,28 @@ __global__ void __launch_bounds__(256) k_ek_sumsq(int64_t m, int n, const double
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
+
+// X <- E^-1 X in place on `cols` columns of `rows` rows (ld): E = mass
+// (I + mc (S + S^T)), the finite-element mass matrix, symmetric positive
+// definite and diagonally dominant (mc = 1/4), by the tridiagonal LU
+// recurrence with the pivots piv (m_0 = 1, m_i = 1 - mc^2 / m_{i-1}, formed
+// once on the host), one thread a column.
+__global__ void k_ek_mass_solve(int64_t rows, int cols, double mass, double mc, const double* piv, double* X,
+                                int64_t ld) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double* x = X + int64_t(c) * ld;
+  const double s = 1.0 / mass;
+  double y = x[0] * s;
+  x[0] = y;
+  for (int64_t i = 1; i < rows; ++i) {
+    y = x[i] * s - (mc / piv[i - 1]) * y;
+    x[i] = y;
+  }
+  double xv = y / piv[rows - 1];
+  x[rows - 1] = xv;
+  for (int64_t i = rows - 2; i >= 0; --i) {
+    xv = (x[i] - mc * xv) / piv[i];
+    x[i] = xv;
+  }
+}

@@ -110,23 +110,15 @@ def test_ek_agrees_with_fadi(H, ctx):
 
 
 def test_ek_error_paths(H, ctx):
-    """A finite-element plan is refused (HODLR_EINVAL, argument 2); a plan in
-    a caller workspace has no room for the solver's arrays (HODLR_EWORKSPACE)
-    and the binding says so before the call."""
+    """A plan in a caller workspace has no room for the solver's arrays
+    (HODLR_EWORKSPACE) and the binding says so before the call; a null plan
+    is argument 2."""
     from paper_1804_05522_amd import hodlr as HM
     p = W.fd_2d(n=64, variable=False, dt=1 / 16)
     F = lr_dev(p.f.Z, p.f.W)
     zero = (torch.zeros((0, 64), dtype=torch.float64, device="cuda"),) * 2
     out = (torch.zeros((64, 64), dtype=torch.float64, device="cuda"),
            torch.zeros((64, 64), dtype=torch.float64, device="cuda"))
-    one = dev(np.ones(64))
-    opx = H.operator_dict(64, 1.3, p.dt, p.hx, one, one, 0.5, discretization=H.FDE_FE)
-    opy = H.operator_dict(64, 1.7, p.dt, p.hy, one, one, 0.5, discretization=H.FDE_FE)
-    Pfe = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec="fp64"), tol=1e-10, workspace=False)
-    with pytest.raises(H.HodlrError) as e:
-        Pfe.step(zero, F, p.dt, out, ek=True)
-    assert e.value.status == HM.HODLR_EINVAL and H.lib().hodlr_last_arg(ctx.h) == 2
-    Pfe.close()
     Pws = plan_for(H, ctx, p, "fp64", workspace=True)
     with pytest.raises(ValueError):
         Pws.step(zero, F, p.dt, out, ek=True)
@@ -135,4 +127,7 @@ def test_ek_error_paths(H, ctx):
     st = H.lib().fde2d_sylvester_step_ek(ctx.h, Pws.h, C.byref(a), C.byref(f), float(p.dt), C.byref(o),
                                          C.byref(info))
     assert st == HM.HODLR_EWORKSPACE
+    st = H.lib().fde2d_sylvester_step_ek(ctx.h, None, C.byref(a), C.byref(f), float(p.dt), C.byref(o),
+                                         C.byref(info))
+    assert st == HM.HODLR_EINVAL and H.lib().hodlr_last_arg(ctx.h) == 2
     Pws.close()

@@ -166,7 +166,8 @@ def test_full_size_sylvester_step_residual(H, ctx, stream, ek):
     assert abs(info.rel_residual - nr / nc) <= 0.05 * nr / nc + 1e-14, (info.rel_residual, nr / nc)
 
 
-def test_full_size_fe_sylvester_step(H, ctx, stream):
+@pytest.mark.parametrize("ek", [False, True], ids=["fadi", "ek"])
+def test_full_size_fe_sylvester_step(H, ctx, stream, ek):
     """One step of the paper's finite-element workload at 4096 x 4096 (P1
     elements, alpha = (1.3, 1.7), dt = 0.1, U^0 = F = indicator of
     [3/8, 5/8]^2) with the benchmark's options (FP32 factors, tolerance
@@ -175,19 +176,20 @@ def test_full_size_fe_sylvester_step(H, ctx, stream):
     relative forward error below 1e-10, and the normwise backward error of the
     generalized equation, formed from the oracle's dense A and B and the
     tridiagonal mass matrices (||A||, ||B||, ||E|| replaced by their largest
-    diagonal entries), below 1e-10."""
+    diagonal entries), below 1e-10.  The same with the extended Krylov
+    solver (ek) on the pencils."""
     from oracle import fe as OF
     n = 4096
     p = W.fe_2d(n=n)
     with torch.cuda.stream(stream):
         opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5, discretization=H.FDE_FE)
         opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5, discretization=H.FDE_FE)
-        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec="fp32"), tol=1e-10)
+        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec="fp32"), tol=1e-10, workspace=not ek)
         cur = (dev(p.u0.Z.T.copy()), dev(p.u0.W.T.copy()))
         F = (dev(p.f.Z.T.copy()), dev(p.f.W.T.copy()))
         out = (torch.zeros((64, n), dtype=torch.float64, device="cuda"),
                torch.zeros((64, n), dtype=torch.float64, device="cuda"))
-        r, info = P.step(cur, F, p.dt, out)
+        r, info = P.step(cur, F, p.dt, out, ek=ek)
         stream.synchronize()
         Z = out[0][:r].cpu().numpy().T
         Wf = out[1][:r].cpu().numpy().T
