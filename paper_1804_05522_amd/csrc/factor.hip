@@ -1014,7 +1014,7 @@ __device__ inline bool wg_leaf(const DevPtrs& P, const Item& it, int b, int64_t 
   return ok;
 }
 
-// ------------------------------------------------------------ driver
+// ------------------------------------ whole factorisation, one work-group per problem
 __global__ void __launch_bounds__(kWG) k_factor(DevPtrs P, int b, int rmax) {
   extern __shared__ __align__(16) double Lds[];
   const int item = blockIdx.x;
