@@ -629,12 +629,18 @@ hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
   return HODLR_OK;
 }
 
-// X <- E^-1 X on `cols` columns of one side (0: x, 1: y); nothing for an identity E.
-void ek_mass_solve(fde2d_plan P, int side, int cols, double* X, int64_t ld, hipStream_t s) {
+// Y = E^-1 X on `cols` columns of one side (0: x, 1: y); a copy for an identity E.
+void ek_mass_solve(fde2d_plan P, int side, int cols, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                   hipStream_t s) {
   const double mass = side == 0 ? P->mass_x : P->mass_y, mc = side == 0 ? P->mc_x : P->mc_y;
-  if (cols <= 0 || (mc == 0.0 && mass == 1.0)) return;
-  HFDE_LAUNCH(k_ek_mass_solve, dim3(1), dim3(64), 0, s, side == 0 ? P->nx : P->ny, cols, mass, mc,
-              side == 0 ? P->ekPivX : P->ekPivY, X, ld);
+  const int64_t n = side == 0 ? P->nx : P->ny;
+  if (cols <= 0) return;
+  if (mc == 0.0 && mass == 1.0) {
+    copy_cols(n, nullptr, cols, X, ldx, Y, ldy, 1.0, s);
+    return;
+  }
+  HFDE_LAUNCH(k_ek_mass_solve, dim3(unsigned((n + kMsTile - 1) / kMsTile), unsigned(cols)), dim3(256), 0, s, n,
+              mass, mc, side == 0 ? P->ekPivX : P->ekPivY, X, ldx, Y, ldy);
 }
 
 // Enqueue the append of the c-column candidate block in ekW (ld n) to the
@@ -735,10 +741,9 @@ hodlr_status ek_products(fde2d_plan P, EkSide& A, int a0, EkSide& B, int b0, hip
   copy_cols(nx, nullptr, ca, A.Q + int64_t(a0) * nx, nx, P->ex_in, ld, 1.0, s);
   copy_cols(ny, nullptr, cb, B.Q + int64_t(b0) * ny, ny, P->ex_in + nx, ld, 1.0, s);
   launch_fft_matvec(P->exact, P->ex_in, ld, P->ex_out, ld, nullptr, 0, c, s);
-  ek_mass_solve(P, 0, ca, P->ex_out, ld, s);            // finite elements: E_x^-1 A, E_y^-1 B
-  ek_mass_solve(P, 1, cb, P->ex_out + nx, ld, s);
-  copy_cols(nx, nullptr, ca, P->ex_out, ld, A.AQ + int64_t(a0) * nx, nx, 1.0, s);
-  copy_cols(ny, nullptr, cb, P->ex_out + nx, ld, B.AQ + int64_t(b0) * ny, ny, 1.0, s);
+  // finite elements: E_x^-1 A, E_y^-1 B (differences: copies)
+  ek_mass_solve(P, 0, ca, P->ex_out, ld, A.AQ + int64_t(a0) * nx, nx, s);
+  ek_mass_solve(P, 1, cb, P->ex_out + nx, ld, B.AQ + int64_t(b0) * ny, ny, s);
   for (int side = 0; side < 2; ++side) {
     EkSide& S = side == 0 ? A : B;
     const int m0 = side == 0 ? a0 : b0, m1 = S.m;
@@ -911,10 +916,8 @@ hodlr_status ek_solve(fde2d_plan P, int r0, double target, int kind, int& steps,
   const double* G = P->G;
   const double* H = P->H;
   if (P->fe) {
-    copy_cols(nx, nullptr, r0, P->G, nx, P->ekGt, nx, 1.0, s);
-    copy_cols(ny, nullptr, r0, P->H, ny, P->ekHt, ny, 1.0, s);
-    ek_mass_solve(P, 0, r0, P->ekGt, nx, s);
-    ek_mass_solve(P, 1, r0, P->ekHt, ny, s);
+    ek_mass_solve(P, 0, r0, P->G, nx, P->ekGt, nx, s);
+    ek_mass_solve(P, 1, r0, P->H, ny, P->ekHt, ny, s);
     G = P->ekGt;
     H = P->ekHt;
   }

@@ -373,27 +373,50 @@ __global__ void __launch_bounds__(256) k_ek_sumsq(int64_t m, int n, const double
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// X <- E^-1 X in place on `cols` columns of `rows` rows (ld): E = mass
-// (I + mc (S + S^T)), the finite-element mass matrix, symmetric positive
-// definite and diagonally dominant (mc = 1/4), by the tridiagonal LU
-// recurrence with the pivots piv (m_0 = 1, m_i = 1 - mc^2 / m_{i-1}, formed
-// once on the host), one thread a column.
-__global__ void k_ek_mass_solve(int64_t rows, int cols, double mass, double mc, const double* piv, double* X,
-                                int64_t ld) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
-  double* x = X + int64_t(c) * ld;
+// Y = E^-1 X on `cols` columns of `rows` rows (X ld ldx, Y ld ldy, distinct
+// arrays): E = mass (I + mc (S + S^T)), the finite-element mass matrix, by
+// its tridiagonal LU recurrence with the pivots piv (m_0 = 1, m_i = 1 -
+// mc^2 / m_{i-1}, formed once on the host).  The recurrences' multipliers
+// mc / m_i are at most 0.268 (mc = 1/4), so a chunk of rows can start its
+// recurrence kMsWarm rows early from a zero state: the start's influence is
+// below 0.268^48 ~ 4e-28 of the column's largest entry, under rounding.
+// Work-group (x, y): rows [2048 x, 2048 x + 2048) of column y, its right-hand
+// side, pivots and forward values staged in LDS with their halos; a thread
+// per 16-row chunk, forward then backward.
+constexpr int kMsTile = 2048, kMsChunk = 16, kMsWarm = 48;
+__global__ void __launch_bounds__(256) k_ek_mass_solve(int64_t rows, double mass, double mc, const double* piv,
+                                                       const double* X, int64_t ldx, double* Y, int64_t ldy) {
+  __shared__ double bs[kMsTile + 2 * kMsWarm];   // b / mass on rows [lo, hi)
+  __shared__ double ps[kMsTile + 2 * kMsWarm];   // pivots on rows [lo, hi)
+  __shared__ double ys[kMsTile + kMsWarm];       // forward values on rows [t0, hi)
+  const int64_t n = rows;
+  const int64_t t0 = int64_t(blockIdx.x) * kMsTile, t1 = min(n, t0 + kMsTile);
+  const int64_t lo = max<int64_t>(0, t0 - kMsWarm), hi = min(n, t1 + kMsWarm);
+  const double* x = X + int64_t(blockIdx.y) * ldx;
+  double* y = Y + int64_t(blockIdx.y) * ldy;
   const double s = 1.0 / mass;
-  double y = x[0] * s;
-  x[0] = y;
-  for (int64_t i = 1; i < rows; ++i) {
-    y = x[i] * s - (mc / piv[i - 1]) * y;
-    x[i] = y;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    bs[i - lo] = s * x[i];
+    ps[i - lo] = piv[i];
   }
-  double xv = y / piv[rows - 1];
-  x[rows - 1] = xv;
-  for (int64_t i = rows - 2; i >= 0; --i) {
-    xv = (x[i] - mc * xv) / piv[i];
-    x[i] = xv;
+  __syncthreads();
+  const int64_t nf = (hi - t0 + kMsChunk - 1) / kMsChunk;
+  for (int64_t k = threadIdx.x; k < nf; k += blockDim.x) {
+    const int64_t r0 = t0 + k * kMsChunk, r1 = min(hi, r0 + kMsChunk), a = max<int64_t>(0, r0 - kMsWarm);
+    double v = 0.0;
+    for (int64_t i = a; i < r1; ++i) {
+      v = i == a ? bs[i - lo] : bs[i - lo] - (mc / ps[i - 1 - lo]) * v;
+      if (i >= r0) ys[i - t0] = v;
+    }
+  }
+  __syncthreads();
+  const int64_t nb = (t1 - t0 + kMsChunk - 1) / kMsChunk;
+  for (int64_t k = threadIdx.x; k < nb; k += blockDim.x) {
+    const int64_t r0 = t0 + k * kMsChunk, r1 = min(t1, r0 + kMsChunk), e = min(n - 1, r1 - 1 + kMsWarm);
+    double v = 0.0;
+    for (int64_t i = e; i >= r0; --i) {
+      v = i == e ? ys[i - t0] / ps[i - lo] : (ys[i - t0] - mc * v) / ps[i - lo];
+      if (i < r1) y[i] = v;
+    }
   }
 }
