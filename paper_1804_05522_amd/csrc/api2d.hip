@@ -507,14 +507,16 @@ hodlr_status adi_sweep(fde2d_plan P, int r0, double target, int& steps, int& par
 // fADI sweep: orthonormal bases U of EK(A, G) = span{G, A^-1 G, A G,
 // A^-2 G, ...} and V of EK(B, H) are grown a block at a time (two extended
 // block Arnoldi processes; the products with A and B are the exact Toeplitz
-// products, the solves the plain HODLR solves with the unshifted factors),
+// products, the solves HODLR solves with the unshifted factors refined once
+// against the exact product),
 // the projected equation T_A Y + Y T_B^T = (U^T G)(V^T H)^T is solved, and
 // D = U Y V^T.  A new block is orthogonalised against the basis by a block
 // Gram-Schmidt pass and orthonormalised with its directions below 1e-10 of
 // its norm before the pass dropped (deflation: the block shrinks once the
 // space stops growing in a direction), then projected and orthonormalised
-// once more.  The projected equation is solved by factored ADI with the
-// plan's shift pairs on explicit inverses of T_A + q_j I and T_B + p_j I.
+// once more.  The projected equation is solved by factored ADI on explicit
+// inverses of T_A + q_j I and T_B + p_j I, with Zolotarev shift pairs of its
+// own for the plan's spectral intervals.
 // The residual of D = U Y V^T splits into three orthogonal terms,
 // (A U - U T_A) Y V^T, U Y (B V - V T_B)^T and U (T_A Y + Y T_B^T - G' H'^T) V^T,
 // whose norms are formed from explicit products (no Gram differences), so the
