@@ -131,3 +131,37 @@ def test_ek_error_paths(H, ctx):
                                          C.byref(info))
     assert st == HM.HODLR_EINVAL and H.lib().hodlr_last_arg(ctx.h) == 2
     Pws.close()
+
+
+def test_ek_on_a_plan_with_one_shift_pair(H, ctx):
+    """A plan made for the extended Krylov solver alone (max_shifts = 1, as
+    the benchmark's extended Krylov job makes it: one shifted pair factored)
+    steps as well: the projected equation takes its own shift pairs."""
+    p = W.fd_2d(n=333, variable=True, dt=1 / 64)
+    opx = H.operator_dict(p.nx, p.alpha_x, p.dt, p.hx, dev(p.dxp), dev(p.dxm), 0.5)
+    opy = H.operator_dict(p.ny, p.alpha_y, p.dt, p.hy, dev(p.dyp), dev(p.dym), 0.5)
+    P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec="fp32"), tol=1e-10, max_shifts=1,
+                    workspace=False)
+    assert len(P.shifts()[0]) == 1
+    st = O2.SylvesterStepper(p)
+    U = np.zeros((p.nx, p.ny))
+    for X, info in run_steps(P, p, 2):
+        U = st.step(U, p.f.dense())
+        err = np.linalg.norm(X - U) / np.linalg.norm(U)
+        assert err <= 1e-10 and info.backward_error <= 1e-10, (err, info.backward_error)
+    assert P.counters()["ek_shifts"] > 1
+    P.close()
+
+
+def test_ek_zero_right_hand_side(H, ctx):
+    """U_m = 0 and F = 0: the step returns the zero solution (rank 0) without
+    a solve."""
+    p = W.fd_2d(n=150, variable=True, dt=1 / 64)
+    P = plan_for(H, ctx, p, "fp64")
+    zero = (torch.zeros((0, p.nx), dtype=torch.float64, device="cuda"),
+            torch.zeros((0, p.ny), dtype=torch.float64, device="cuda"))
+    out = (torch.zeros((64, p.nx), dtype=torch.float64, device="cuda"),
+           torch.zeros((64, p.ny), dtype=torch.float64, device="cuda"))
+    r, info = P.step(zero, zero, p.dt, out, ek=True)
+    assert r == 0 and info.status == 0 and info.refine_iters == 0
+    P.close()
