@@ -404,7 +404,7 @@ def run_2d(args, ctx, stream, steps=None, warmup=None, prec=None, cpu=True, comp
         use_ek = ek if use_ek is None else use_ek
         t0 = time.perf_counter()
         # extended Krylov needs no shifted factor sets: its plan keeps one pair
-        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec=pr), tol=1e-10, workspace=not use_ek,
+        P = H.Fde2dPlan(ctx, opx, opy, H.default_opts(tol=1e-10, prec=pr), tol=1e-10,
                         max_shifts=1 if use_ek else 64)
         stream.synchronize()
         t1 = time.perf_counter()

@@ -437,14 +437,28 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* 
  * as A^-1 E; its residual bounds the generalized one, E's eigenvalues being
  * below 1).  Arguments, outputs and stopping as fde2d_sylvester_step, except
  * that info->refine_iters counts extended Krylov iterations.
- * A plan made by fde2d_plan_create_ws has no room for the solver's arrays
- * (HODLR_EWORKSPACE).  The plan's shifted factor sets are not used: the
+ * The solver's arrays (bases, projected matrices and their 2 x J shifted
+ * inverses, at most 640 x 640 each) are allocated on the first call; a plan
+ * made by fde2d_plan_create_ws takes them from the workspace given by
+ * fde2d_ek_attach_workspace instead, and without one returns
+ * HODLR_EWORKSPACE.  The plan's shifted factor sets are not used: the
  * projected equation takes its own Zolotarev shift pairs on the plan's
  * spectral intervals, as many as opts.tol / 10 needs (at most 64), so a plan
  * made for this entry point alone may set max_shifts = 1. */
 hodlr_status fde2d_sylvester_step_ek(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* U_m,
                                      const lr_matrix* F, double dt, lr_matrix* U_next,
                                      hodlr_info* info);
+/* Device bytes of the extended Krylov solver's arrays for plan p
+ * (fde2d_sylvester_step_ek), including the alignment slack of a workspace
+ * that fde2d_ek_attach_workspace takes.  Allocates nothing. */
+hodlr_status fde2d_ek_workspace_size(hodlr_ctx ctx, fde2d_plan p, size_t* bytes);
+/* Give a plan made by fde2d_plan_create_ws the caller-owned device memory
+ * for the extended Krylov solver's arrays (workspace: device, ws_bytes >=
+ * fde2d_ek_workspace_size, any alignment; keep it alive until
+ * fde2d_plan_destroy).  Once per plan: HODLR_ESTATE for a plan without a
+ * workspace or with one already attached; HODLR_EINVAL with hodlr_last_arg()
+ * == 4 if ws_bytes is too small, 3 if workspace is NULL. */
+hodlr_status fde2d_ek_attach_workspace(hodlr_ctx ctx, fde2d_plan p, void* workspace, size_t ws_bytes);
 
 /* As fde2d_sylvester_step, starting from a first guess X0 of the solution
  * (low-rank, rank <= opts.max_rank; NULL or rank 0: no guess).  The exact

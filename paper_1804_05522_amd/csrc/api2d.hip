@@ -564,10 +564,10 @@ void ek_sumsq(fde2d_plan P, int64_t m, int n, const double* X, int64_t ld, int s
   HFDE_LAUNCH(k_sum_partials, dim3(1), dim3(256), 0, s, P->ekPart, int64_t(blocks), P->ekNrm + slot);
 }
 
-// Arrays of the solver (first use), the shifts on the device, and the
-// factorisation of the unshifted A and B (the batch of the exact products).
-hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
-  if (P->ek_ready) return HODLR_OK;
+// The solver's shift pairs and arrays: from the library's allocations, from
+// the workspace given by fde2d_ek_attach_workspace, or (P->sizing) only
+// counted in P->ws_used.
+hodlr_status ek_alloc(fde2d_plan P) {
   const int64_t nx = P->nx, ny = P->ny, mr = std::max(nx, ny);
   const int64_t E2 = int64_t(kEkMax) * kEkMax;
   // the projected equation's shift pairs: as many as the intervals need for
@@ -607,6 +607,17 @@ hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
        plan_alloc(P, &P->ekPivY, ny) == HODLR_OK && plan_alloc(P, &P->ekGt, nx * kRS) == HODLR_OK &&
        plan_alloc(P, &P->ekHt, ny * kRS) == HODLR_OK;
   if (!ok) return P->ws ? HODLR_EWORKSPACE : HODLR_ENOMEM;
+  return HODLR_OK;
+}
+
+// Arrays of the solver (first use), the shifts on the device, and the
+// factorisation of the unshifted A and B (the batch of the exact products).
+hodlr_status ek_prepare(fde2d_plan P, hipStream_t s) {
+  if (P->ek_ready) return HODLR_OK;
+  if (P->ws && !P->ek_ws) return HODLR_EWORKSPACE;    // a workspace plan needs fde2d_ek_attach_workspace
+  TRY(ek_alloc(P));
+  const int64_t nx = P->nx, ny = P->ny;
+  const int J = P->ek_J;
   // pivots of the mass matrices' tridiagonal LU: m_0 = 1, m_i = 1 - mc^2 / m_{i-1}
   for (int side = 0; side < 2; ++side) {
     const double mc = side == 0 ? P->mc_x : P->mc_y;
@@ -1701,6 +1712,40 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* 
   const hodlr_status st = fde2d_sylvester_step_guess(ctx, P, U_m, F, dt, nullptr, U_next, info);
   if (st == HODLR_EINVAL && ctx && ctx->last_arg == 7) ctx->last_arg = 6;
   return st;
+}
+
+hodlr_status fde2d_ek_workspace_size(hodlr_ctx ctx, fde2d_plan P, size_t* bytes) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!P) return set_arg(ctx, 2);
+  if (!bytes) return set_arg(ctx, 3);
+  // count the solver's arrays as a sizing pass, on a copy of the plan's
+  // fields (the plan's own pointers stay as they are)
+  fde2d_plan_s scratch = *P;
+  scratch.sizing = true;
+  scratch.ws_used = 0;
+  const hodlr_status st = ek_alloc(&scratch);
+  *bytes = scratch.ws_used + 256;                 // + alignment of the workspace's own start
+  scratch.allocs.clear();
+  return st;
+}
+
+hodlr_status fde2d_ek_attach_workspace(hodlr_ctx ctx, fde2d_plan P, void* workspace, size_t ws_bytes) {
+  if (!ctx) return HODLR_EINVAL;
+  if (!P) return set_arg(ctx, 2);
+  if (!P->ws || P->ek_ws) return HODLR_ESTATE;    // only a workspace plan, once
+  if (!workspace) return set_arg(ctx, 3);
+  size_t need = 0;
+  TRY(fde2d_ek_workspace_size(ctx, P, &need));
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(workspace);
+  const uintptr_t a1 = (a0 + 255) & ~uintptr_t(255);
+  if (ws_bytes < need || ws_bytes < a1 - a0) return set_arg(ctx, 4);
+  // the plan's own arrays keep their places; later allocations (the solver's)
+  // are carved from this workspace
+  P->ek_ws = reinterpret_cast<char*>(a1);
+  P->ws = P->ek_ws;
+  P->ws_bytes = ws_bytes - (a1 - a0);
+  P->ws_used = 0;
+  return HODLR_OK;
 }
 
 hodlr_status fde2d_sylvester_step_ek(hodlr_ctx ctx, fde2d_plan P, const lr_matrix* U_m, const lr_matrix* F,

@@ -29,7 +29,8 @@ EXPORTS = [
     "fde_net_param_count", "fde_net_create", "fde_net_destroy", "fde_net_set_params", "fde_net_get_params",
     "fde_net_get_grads", "fde_net_forward", "fde_net_train_step", "hodlr_toeplitz_matvec_noalloc",
     "hodlr_workspace_size", "hodlr_build_ws", "fde2d_plan_workspace_size", "fde2d_plan_create_ws",
-    "fde2d_plan_counters", "hodlr_get_weights", "fde2d_sylvester_step_ek",
+    "fde2d_plan_counters", "hodlr_get_weights", "fde2d_sylvester_step_ek", "fde2d_ek_workspace_size",
+    "fde2d_ek_attach_workspace",
 ]
 
 
@@ -142,6 +143,8 @@ def lib():
                                                C.POINTER(LrMatrix), C.POINTER(HodlrInfo)]
             L.fde2d_sylvester_step_ek.argtypes = [vp, vp, C.POINTER(LrMatrix), C.POINTER(LrMatrix), dbl,
                                                   C.POINTER(LrMatrix), C.POINTER(HodlrInfo)]
+            L.fde2d_ek_workspace_size.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+            L.fde2d_ek_attach_workspace.argtypes = [vp, vp, vp, C.c_size_t]
             L.fde2d_sylvester_step_guess.argtypes = [vp, vp, C.POINTER(LrMatrix), C.POINTER(LrMatrix), dbl,
                                                      C.POINTER(LrMatrix), C.POINTER(LrMatrix), C.POINTER(HodlrInfo)]
             L.fde2d_field_from_lr.argtypes = [vp, vp, C.POINTER(LrMatrix), vp]
@@ -413,9 +416,15 @@ class Fde2dPlan:
         if ek:
             if guess is not None:
                 raise ValueError("the extended Krylov step takes no first guess")
-            if self.ws is not None:
-                raise ValueError("the extended Krylov step needs a plan made with workspace=False "
-                                 "(its arrays are allocated by the library on first use)")
+            if self.ws is not None and getattr(self, "ek_ws", None) is None:
+                # a workspace plan: the solver's arrays in torch-allocated memory too
+                import torch
+                need = C.c_size_t()
+                check(lib().fde2d_ek_workspace_size(self.ctx.h, self.h, C.byref(need)), "fde2d_ek_workspace_size",
+                      self.ctx.h)
+                self.ek_ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+                check(lib().fde2d_ek_attach_workspace(self.ctx.h, self.h, C.c_void_p(self.ek_ws.data_ptr()),
+                                                      need.value), "fde2d_ek_attach_workspace", self.ctx.h)
             check(lib().fde2d_sylvester_step_ek(self.ctx.h, self.h, C.byref(a), C.byref(f), float(dt), C.byref(o),
                                                 C.byref(info)), "fde2d_sylvester_step_ek", self.ctx.h, allow)
         elif guess is None:
@@ -447,6 +456,7 @@ class Fde2dPlan:
             lib().fde2d_plan_destroy(self.h)    # its batches' destruction waits for the device
             self.h = C.c_void_p()
         self.ws = None
+        self.ek_ws = None
 
     def __del__(self):
         try:

@@ -109,28 +109,42 @@ def test_ek_agrees_with_fadi(H, ctx):
     P.close()
 
 
-def test_ek_error_paths(H, ctx):
-    """A plan in a caller workspace has no room for the solver's arrays
-    (HODLR_EWORKSPACE) and the binding says so before the call; a null plan
-    is argument 2."""
+def test_ek_workspace_plans(H, ctx):
+    """A plan in a caller workspace: without an attached workspace for the
+    solver's arrays the step returns HODLR_EWORKSPACE; an undersized
+    attachment is refused (argument 4), a second one is out of order; with
+    the workspace attached (what the binding does on first use) the steps
+    match the library-allocated plan's bit for bit.  A null plan is argument
+    2."""
     from paper_1804_05522_amd import hodlr as HM
-    p = W.fd_2d(n=64, variable=False, dt=1 / 16)
+    p = W.fd_2d(n=150, variable=True, dt=1 / 64)
     F = lr_dev(p.f.Z, p.f.W)
-    zero = (torch.zeros((0, 64), dtype=torch.float64, device="cuda"),) * 2
-    out = (torch.zeros((64, 64), dtype=torch.float64, device="cuda"),
-           torch.zeros((64, 64), dtype=torch.float64, device="cuda"))
-    Pws = plan_for(H, ctx, p, "fp64", workspace=True)
-    with pytest.raises(ValueError):
-        Pws.step(zero, F, p.dt, out, ek=True)
+    zero = (torch.zeros((0, p.nx), dtype=torch.float64, device="cuda"),) * 2
+    out = (torch.zeros((64, p.nx), dtype=torch.float64, device="cuda"),
+           torch.zeros((64, p.ny), dtype=torch.float64, device="cuda"))
+    Pws = plan_for(H, ctx, p, "fp32", workspace=True)
     a, f, o = Pws._lr(zero), Pws._lr(F), Pws._lr(out, cap=64)
     info = HM.HodlrInfo()
     st = H.lib().fde2d_sylvester_step_ek(ctx.h, Pws.h, C.byref(a), C.byref(f), float(p.dt), C.byref(o),
                                          C.byref(info))
     assert st == HM.HODLR_EWORKSPACE
+    need = C.c_size_t()
+    assert H.lib().fde2d_ek_workspace_size(ctx.h, Pws.h, C.byref(need)) == 0 and need.value > 0
+    small = torch.empty(need.value // 2, dtype=torch.uint8, device="cuda")
+    st = H.lib().fde2d_ek_attach_workspace(ctx.h, Pws.h, C.c_void_p(small.data_ptr()), need.value // 2)
+    assert st == HM.HODLR_EINVAL and H.lib().hodlr_last_arg(ctx.h) == 4
+    xw = [X for X, _ in run_steps(Pws, p, 2)]             # the binding attaches a workspace here
+    st = H.lib().fde2d_ek_attach_workspace(ctx.h, Pws.h, C.c_void_p(small.data_ptr()), need.value // 2)
+    assert st == HM.HODLR_ESTATE
+    Pws.close()
+    Pl = plan_for(H, ctx, p, "fp32", workspace=False)
+    xl = [X for X, _ in run_steps(Pl, p, 2)]
+    Pl.close()
+    for u, v in zip(xw, xl):
+        assert np.array_equal(u, v)
     st = H.lib().fde2d_sylvester_step_ek(ctx.h, None, C.byref(a), C.byref(f), float(p.dt), C.byref(o),
                                          C.byref(info))
     assert st == HM.HODLR_EINVAL and H.lib().hodlr_last_arg(ctx.h) == 2
-    Pws.close()
 
 
 def test_ek_on_a_plan_with_one_shift_pair(H, ctx):
