@@ -635,6 +635,12 @@ def roofline_2d(ks, cnt, n):
         out.update(bound="mfma", achieved=per / avg_s / 1e12, peak=MI355X_FP64 / 1e12, unit="TFLOP/s",
                    frac=per / avg_s / MI355X_FP64,
                    algorithmic=f"{per:.3e} flop per launch (2 nx ny K over the residual's K columns)")
+    elif name == "k_ek_gemm":
+        per = cnt["ek_gemm_flops"] / launches
+        out.update(bound="alu", achieved=per / avg_s / 1e12, peak=MI355X_FP64 / 1e12, unit="TFLOP/s",
+                   frac=per / avg_s / MI355X_FP64,
+                   algorithmic=f"{per:.3e} flop per launch (2 M N K over the extended Krylov solver's products, "
+                               f"an upper bound where the width is clipped on the device)")
     elif name == "(k_expand<TF, TL, NC>)":
         per = cnt["solve_bytes"] / cnt["shifts"] / 2 + 2 * 16 * 2 * n * 8.0
         out.update(bound="hbm", achieved=per / avg_s / 1e9, peak=MI355X_HBM / 1e9, unit="GB/s",

@@ -372,9 +372,10 @@ hodlr_status fde2d_plan_create_ws(hodlr_ctx ctx, const fde_operator* opx, const 
  * (2 nx ny K for K columns), values[2] the bytes one single-column solve of all
  * shifted operators reads (hodlr_mat_info.bytes_factors of the shifted batch),
  * values[3] J, values[4] the largest factor rank, values[5] the shift pairs of
- * the extended Krylov solver's projected equation (0 before its first use);
- * up to count values.  Waits for the device.  reset != 0 clears the two flop
- * counters. */
+ * the extended Krylov solver's projected equation (0 before its first use),
+ * values[6] the flops of its dense products (2 M N K per k_ek_gemm launch,
+ * N before clipping to a device-held width, so an upper bound); up to count
+ * values.  Waits for the device.  reset != 0 clears the three flop counters. */
 hodlr_status fde2d_plan_counters(fde2d_plan p, double* values, int count, int reset);
 void fde2d_plan_destroy(fde2d_plan p);
 int fde2d_plan_shifts(fde2d_plan p, double* p_shifts, double* q_shifts, int cap);

@@ -324,6 +324,7 @@ struct fde2d_plan_s {
   bool use_ek = false;          // the current step solves by extended Krylov instead of fADI sweeps
   char* ek_ws = nullptr;        // caller workspace of the solver's arrays (fde2d_ek_attach_workspace)
   int ek_last[2] = {2, 2};      // iterations the last extended Krylov solves took (first solve, correction)
+  double ek_gemm_flops = 0.0;   // host: 2 M N K over the solver's k_ek_gemm launches (N before device clipping)
   double iv[4] = {0, 0, 0, 0};  // spectral intervals [iv0, iv1] of A, [iv2, iv3] of B (the shifts' problem)
   int ek_J = 0;                 // shift pairs of the projected fADI (reaching opts.tol / 10 on the intervals)
   std::vector<double> ek_p, ek_q;

@@ -549,6 +549,7 @@ hodlr_status ek_gemm(fde2d_plan P, int ta, int tb, int M, int N, int64_t K, doub
     kchunk = ((K + ns - 1) / ns + 15) / 16 * 16;
   }
   const int nsplit = int(std::max<int64_t>(1, (K + kchunk - 1) / kchunk));
+  P->ek_gemm_flops += 2.0 * double(M) * double(N) * double(K);
   HFDE_LAUNCH(k_ek_gemm, dim3(unsigned((M + 63) / 64), unsigned((N + 63) / 64), unsigned(nsplit)), dim3(256), 0, s,
               ta, tb, M, N, ndev, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, P->ekPart);
   if (nsplit > 1)
@@ -1285,12 +1286,13 @@ hodlr_status fde2d_plan_counters(fde2d_plan P, double* values, int count, int re
   HIP_TRY(hipMemcpy(&core, P->counters, sizeof(double), hipMemcpyDeviceToHost));
   hodlr_mat_info mi{};
   if (P->mat) TRY(hodlr_get_info(P->mat, &mi));
-  const double v[6] = {core, P->lrs_flops, double(mi.bytes_factors), double(P->J), double(mi.max_rank_factors),
-                       double(P->ek_J)};
-  for (int i = 0; i < count && i < 6; ++i) values[i] = v[i];
+  const double v[7] = {core, P->lrs_flops, double(mi.bytes_factors), double(P->J), double(mi.max_rank_factors),
+                       double(P->ek_J), P->ek_gemm_flops};
+  for (int i = 0; i < count && i < 7; ++i) values[i] = v[i];
   if (reset) {
     HIP_TRY(hipMemset(P->counters, 0, sizeof(double)));
     P->lrs_flops = 0.0;
+    P->ek_gemm_flops = 0.0;
   }
   return HODLR_OK;
 }

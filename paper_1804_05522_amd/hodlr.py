@@ -385,11 +385,11 @@ class Fde2dPlan:
     def counters(self, reset=False):
         """Work counters (fde2d_plan_counters): dict of core_flops, dense_flops,
         solve_bytes (one column, all shifted operators), shifts, rank, ek_shifts
-        (the extended Krylov solver's projected shift pairs)."""
-        v = (C.c_double * 6)()
-        check(lib().fde2d_plan_counters(self.h, v, 6, 1 if reset else 0), "fde2d_plan_counters")
+        (the extended Krylov solver's projected shift pairs), ek_gemm_flops."""
+        v = (C.c_double * 7)()
+        check(lib().fde2d_plan_counters(self.h, v, 7, 1 if reset else 0), "fde2d_plan_counters")
         return dict(core_flops=v[0], dense_flops=v[1], solve_bytes=v[2], shifts=int(v[3]), rank=int(v[4]),
-                    ek_shifts=int(v[5]))
+                    ek_shifts=int(v[5]), ek_gemm_flops=v[6])
 
     def shifts(self):
         n = lib().fde2d_plan_shifts(self.h, None, None, 0)
