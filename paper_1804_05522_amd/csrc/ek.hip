@@ -36,23 +36,33 @@ __global__ void __launch_bounds__(256) k_ek_gemm(int ta, int tb, int M, int N, c
   const int64_t k0 = int64_t(blockIdx.z) * kchunk;
   const int64_t k1 = min(K, k0 + kchunk);
   double acc[4][4] = {};
-  for (int64_t kk = k0; kk < k1; kk += kK) {
+  // the next slice's operands are loaded into registers while the current
+  // slice is multiplied from LDS
+  double va[4], vb[4];
+  auto fetch = [&](int64_t kk) {
+#pragma unroll
     for (int l = 0; l < 4; ++l) {
       const int e = threadIdx.x + 256 * l;
       int i, k;
       if (ta == 0) { i = e % 64; k = e / 64; } else { k = e % kK; i = e / kK; }
       const int64_t kg = kk + k;
-      double v = 0.0;
-      if (i0 + i < M && kg < k1) v = ta == 0 ? A[(i0 + i) + kg * lda] : A[kg + int64_t(i0 + i) * lda];
-      As[k][i] = v;
+      va[l] = (i0 + i < M && kg < k1) ? (ta == 0 ? A[(i0 + i) + kg * lda] : A[kg + int64_t(i0 + i) * lda]) : 0.0;
       int j, kb;
       if (tb == 0) { kb = e % kK; j = e / kK; } else { j = e % 64; kb = e / 64; }
       const int64_t kgb = kk + kb;
-      double w = 0.0;
-      if (j0 + j < N && kgb < k1) w = tb == 0 ? B[kgb + int64_t(j0 + j) * ldb] : B[(j0 + j) + kgb * ldb];
-      Bs[kb][j] = w;
+      vb[l] = (j0 + j < N && kgb < k1) ? (tb == 0 ? B[kgb + int64_t(j0 + j) * ldb] : B[(j0 + j) + kgb * ldb]) : 0.0;
+    }
+  };
+  if (k0 < k1) fetch(k0);
+  for (int64_t kk = k0; kk < k1; kk += kK) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int e = threadIdx.x + 256 * l;
+      if (ta == 0) As[e / 64][e % 64] = va[l]; else As[e % kK][e / kK] = va[l];
+      if (tb == 0) Bs[e % kK][e / kK] = vb[l]; else Bs[e / 64][e % 64] = vb[l];
     }
     __syncthreads();
+    if (kk + kK < k1) fetch(kk + kK);
 #pragma unroll
     for (int k = 0; k < kK; ++k) {
       double a[4], b[4];
