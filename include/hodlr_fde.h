@@ -433,6 +433,7 @@ hodlr_status fde2d_sylvester_step(hodlr_ctx ctx, fde2d_plan p, const lr_matrix* 
  * pivoting) of the shifted projected matrices, until the residual of U Y V^T
  * (formed from three orthogonal terms) is at most the solve's target; the
  * solve's result U Y V^T is then compressed to at most 32 columns.
+ * HODLR_ESINGULAR if a shifted projected matrix has an exactly zero pivot.
  * Finite elements: the same on E_x^-1 A D + D (E_y^-1 B)^T = (E_x^-1 G)(E_y^-1 H)^T
  * (the operator products followed by tridiagonal mass solves, the inverses
  * as A^-1 E; its residual bounds the generalized one, E's eigenvalues being

@@ -849,7 +849,11 @@ hodlr_status ek_projected(fde2d_plan P, const EkSide& A, const EkSide& B, const 
   TRY(ek_gemm(P, 0, 1, mA, mB, r0, -1.0, P->ekG0, kEkMax, P->ekH0, kEkMax, 1.0, P->ekRs, kEkMax, s));
   ek_sumsq(P, mA, mB, P->ekRs, kEkMax, 2, s);
   HIP_TRY(hipMemcpyAsync(P->host_frob + 2, P->ekNrm, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<int32_t> flags(2 * J);
+  HIP_TRY(hipMemcpyAsync(flags.data(), P->ekFlag, flags.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  for (int32_t f : flags)
+    if (f) return HODLR_ESINGULAR;       // a shifted projected matrix had an exactly zero pivot
   rn = std::sqrt(std::max(P->host_frob[2] + P->host_frob[3] + P->host_frob[4], 0.0));
   return HODLR_OK;
 }
