@@ -179,3 +179,23 @@ def test_ek_zero_right_hand_side(H, ctx):
     r, info = P.step(zero, zero, p.dt, out, ek=True)
     assert r == 0 and info.status == 0 and info.refine_iters == 0
     P.close()
+
+
+@pytest.mark.parametrize("ek", [False, True], ids=["fadi", "ek"])
+@pytest.mark.parametrize("alphas", [(1.1, 1.9), (1.9, 1.1), (1.5, 1.5)])
+def test_both_solvers_across_orders(H, ctx, alphas, ek):
+    """Both per-step solvers at the ends of the fractional orders' range
+    (n = 256, eq. (coeff_es) coefficients, FP32 factors, tolerance 1e-10):
+    two steps against the oracle's Bartels-Stewart steps, forward error and
+    backward error below 1e-10."""
+    p = W.fd_2d(n=256, alpha_x=alphas[0], alpha_y=alphas[1], variable=True, dt=1 / 64)
+    P = plan_for(H, ctx, p, "fp32")
+    st = O2.SylvesterStepper(p)
+    U = np.zeros((p.nx, p.ny))
+    for k, (X, info) in enumerate(run_steps(P, p, 2, ek=ek)):
+        U = st.step(U, p.f.dense())
+        err = np.linalg.norm(X - U) / np.linalg.norm(U)
+        print(f"alphas {alphas} {'ek' if ek else 'fadi'} step {k + 1}: rel.err {err:.2e} "
+              f"backward error {info.backward_error:.2e} iterations {info.refine_iters}")
+        assert err <= 1e-10 and info.backward_error <= 1e-10, (err, info.backward_error)
+    P.close()
