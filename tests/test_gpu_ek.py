@@ -199,3 +199,34 @@ def test_both_solvers_across_orders(H, ctx, alphas, ek):
               f"backward error {info.backward_error:.2e} iterations {info.refine_iters}")
         assert err <= 1e-10 and info.backward_error <= 1e-10, (err, info.backward_error)
     P.close()
+
+
+def _grid_problem(nx, ny):
+    """The fd_2d workload on an nx x ny grid (eq. (coeff_es) coefficients in
+    each direction, rank-4 separable source built from the two directions'
+    problems)."""
+    px, py = W.fd_2d(n=nx, variable=True, dt=1 / 64), W.fd_2d(n=ny, variable=True, dt=1 / 64)
+    return W.Problem2D(nx, ny, px.alpha_x, py.alpha_y, px.dt, 2, px.hx, py.hy, px.x, py.y, px.dxp, px.dxm,
+                       py.dyp, py.dym, W.LowRank(np.zeros((nx, 1)), np.zeros((ny, 1))),
+                       W.LowRank(px.f.Z, py.f.W))
+
+
+@pytest.mark.parametrize("ek", [False, True], ids=["fadi", "ek"])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 5), (5, 2), (17, 17), (64, 65)])
+def test_both_solvers_on_tiny_and_ragged_grids(H, ctx, nx, ny, ek):
+    """Grids smaller than the source's rank and than one HODLR leaf, and a
+    ragged pair around the leaf size (64 x 65): two steps of both per-step
+    solvers with FP32 factors against the oracle's Bartels-Stewart steps.
+    With so few rows the extended Krylov bases exhaust the space and stop
+    growing, where the projected equation is the full one."""
+    p = _grid_problem(nx, ny)
+    P = plan_for(H, ctx, p, "fp32")
+    st = O2.SylvesterStepper(p)
+    U = np.zeros((nx, ny))
+    for k, (X, info) in enumerate(run_steps(P, p, 2, ek=ek)):
+        U = st.step(U, p.f.dense())
+        err = np.linalg.norm(X - U) / np.linalg.norm(U)
+        print(f"{nx}x{ny} {'ek' if ek else 'fadi'} step {k + 1}: rel.err {err:.2e} "
+              f"backward error {info.backward_error:.2e} rank {info.max_rank}")
+        assert err <= 1e-10 and info.backward_error <= 1e-10, (err, info.backward_error)
+    P.close()

@@ -390,3 +390,35 @@ def test_2d_fe_both_solvers_across_orders(H, ctx, alphas, ek):
         assert err <= tol and eta <= tol, (err, eta)
         cur = (out[0][:r].contiguous(), out[1][:r].contiguous())
     P.close()
+
+
+@pytest.mark.parametrize("ek", [False, True], ids=["fadi", "ek"])
+@pytest.mark.parametrize("n", [1, 5, 33])
+def test_2d_fe_tiny_grids(H, ctx, n, ek):
+    """The finite-element step on grids of one point, of fewer points than a
+    leaf, and of one point more than the plans' leaf of 32 (two leaves of
+    16 and 17), with both solvers (FP32 factors, tolerance 1e-10): two steps
+    against the oracle's route, forward error and the dense generalized
+    backward error below 1e-10."""
+    tol = 1e-10
+    p = W.fe_2d(n=n)
+    P = fe_plan(H, ctx, p, prec="fp32", tol=tol, hodlr_tol=1e-10)
+    st = OF.FeSylvesterStepper(p)
+    na, nb = np.linalg.norm(st.A, 2), np.linalg.norm(st.B, 2)
+    ne_x, ne_y = np.linalg.norm(st.Ex, 2), np.linalg.norm(st.Ey, 2)
+    U = p.u0.dense()
+    cur = lr_dev(p.u0.Z, p.u0.W)
+    for k in range(2):
+        out = (torch.zeros((64, p.nx), dtype=torch.float64, device="cuda"),
+               torch.zeros((64, p.ny), dtype=torch.float64, device="cuda"))
+        r, info = P.step(cur, lr_dev(p.f.Z, p.f.W), p.dt, out, ek=ek)
+        X = out[0][:r].cpu().numpy().T @ out[1][:r].cpu().numpy()
+        C = st.rhs(U, p.f.dense())
+        U = st.step(U, p.f.dense())
+        err = np.linalg.norm(X - U) / np.linalg.norm(U)
+        R = OF.generalized_residual(st.A, st.B, st.Ex, st.Ey, X, C)
+        eta = np.linalg.norm(R) / ((na * ne_y + ne_x * nb) * np.linalg.norm(X) + np.linalg.norm(C))
+        print(f"fe n={n} {'ek' if ek else 'fadi'} step {k + 1}: rel.err {err:.2e} backward error {eta:.2e} rank {r}")
+        assert err <= tol and eta <= tol, (err, eta)
+        cur = (out[0][:r].contiguous(), out[1][:r].contiguous())
+    P.close()
