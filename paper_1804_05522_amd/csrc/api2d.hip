@@ -816,7 +816,7 @@ hodlr_status ek_projected(fde2d_plan P, const EkSide& A, const EkSide& B, const 
   TRY(ek_gemm(P, 1, 0, mB, r0, ny, 1.0, B.Q, ny, H, ny, 0.0, P->ekH0, kEkMax, s));
   HFDE_LAUNCH(k_ek_lu, dim3(2 * J), dim3(kEkWG), 0, s, J, mA, A.T, mB, B.T, int64_t(kEkMax), P->ekShift, P->ekLU,
               int64_t(kEkMax), E2, P->ekPiv, P->ekFlag);
-  HFDE_LAUNCH(k_ek_lu_inv, dim3(unsigned((std::max(mA, mB) + 15) / 16), unsigned(2 * J)), dim3(256), 0, s, J, mA,
+  HFDE_LAUNCH(k_ek_lu_inv, dim3(unsigned((std::max(mA, mB) + kEkInvCols - 1) / kEkInvCols), unsigned(2 * J)), dim3(256), 0, s, J, mA,
               mB, P->ekLU, int64_t(kEkMax), E2, P->ekPiv, P->ekInv, int64_t(kEkMax));
   const unsigned tiles = unsigned((mA + 15) / 16 + (mB + 15) / 16);
   const double* gin = P->ekG0;

@@ -106,27 +106,33 @@ __global__ void k_ek_gemm_sum(int M, int N, const int32_t* ndev, int nsplit, con
 // LU factorisation with partial pivoting (P (T + s_b I) = L U, L unit lower)
 // of the batch's matrices, one work-group per matrix b: T = TA (order mA) for
 // b < J, else TB (order mB), both ld ldt; s_b = shift[b]; the factors
-// overwrite out + b stride (ld ldo), the pivot
-// rows go to
-// piv + b kEkMax, and flag[b] = 1 marks an exactly zero pivot.  Right-looking
-// and blocked: a panel of kEkPanel columns is factored in LDS, its row
-// interchanges are applied to the other columns, the block row of U is
-// solved with the panel's unit lower triangle, and the trailing matrix takes
-// the rank-kEkPanel update.  m <= kEkMax.
+// overwrite out + b stride (ld ldo), the pivot rows go to piv + b kEkMax, and
+// flag[b] = 1 marks an exactly zero pivot.  Right-looking and blocked: a
+// panel of kEkPanel columns is factored in LDS; its row interchanges, composed
+// into one gather and one scatter, are applied to the other columns; the block
+// row of U is solved with the panel's unit lower triangle in registers (a
+// thread per column) and kept in LDS; the trailing matrix takes the
+// rank-kEkPanel update with the panel's rows in registers (a wave per 64-row
+// chunk, lanes = rows, the block row of U read by broadcast).  m <= kEkMax.
 __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA, int mB, const double* TB,
                                                  int64_t ldt, const double* shift, double* out, int64_t ldo,
                                                  int64_t stride, int32_t* piv, int32_t* flag) {
   constexpr int kP = kEkPanel;
   constexpr int kW = kEkWG / 64;
-  __shared__ double Pn[kEkMax * kP];         // the panel, rows j0 .. m - 1 (ld = m - j0)
+  // the panel (rows j0 .. m - 1, ld m - j0), then the block row of U right of
+  // it (kP x (m - j0 - kP), ld kP)
+  __shared__ double Sm[(2 * kEkMax - kP) * kP];
   __shared__ double red_v[kW];
   __shared__ int red_i[kW];
+  __shared__ int sw_row[2 * kP], sw_src[2 * kP];
+  __shared__ int sw_n;
   const int b = blockIdx.x;
   const int m = b < J ? mA : mB;
   const double* T = b < J ? TA : TB;
   double* A = out + int64_t(b) * stride;
   int32_t* pv = piv + int64_t(b) * kEkMax;
   const double sh = shift[b];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int64_t e = threadIdx.x; e < int64_t(m) * m; e += kEkWG) {
     const int i = int(e % m), j = int(e / m);
     A[i + int64_t(j) * ldo] = T[i + int64_t(j) * ldt] + (i == j ? sh : 0.0);
@@ -135,6 +141,8 @@ __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA
   __syncthreads();
   for (int j0 = 0; j0 < m; j0 += kP) {
     const int nb = min(kP, m - j0), j1 = j0 + nb, mr = m - j0;
+    double* Pn = Sm;
+    double* Us = Sm + mr * kP;
     for (int e = threadIdx.x; e < mr * nb; e += kEkWG) {
       const int i = e % mr, c = e / mr;
       Pn[i + c * mr] = A[(j0 + i) + int64_t(j0 + c) * ldo];
@@ -142,7 +150,7 @@ __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA
     __syncthreads();
     for (int jj = 0; jj < nb; ++jj) {
       // pivot: the largest magnitude in panel column jj, rows jj .. mr - 1
-      // (ties to the lowest row), reduced within each wave, then over the four
+      // (ties to the lowest row), reduced within each wave, then over the waves
       double best = -1.0;
       int bi = jj;
       for (int i = jj + threadIdx.x; i < mr; i += kEkWG) {
@@ -154,19 +162,24 @@ __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA
         const int i2 = __shfl_xor(bi, o);
         if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
       }
-      if ((threadIdx.x & 63) == 0) {
-        red_v[threadIdx.x >> 6] = best;
-        red_i[threadIdx.x >> 6] = bi;
+      if (lane == 0) {
+        red_v[wave] = best;
+        red_i[wave] = bi;
       }
       __syncthreads();
-      if (threadIdx.x == 0) {
-        for (int w = 1; w < kW; ++w)
-          if (red_v[w] > red_v[0] || (red_v[w] == red_v[0] && red_i[w] < red_i[0])) {
-            red_v[0] = red_v[w];
-            red_i[0] = red_i[w];
-          }
-        pv[j0 + jj] = j0 + red_i[0];
-        if (red_v[0] == 0.0) flag[b] = 1;
+      if (wave == 0) {                          // the waves' candidates, reduced by wave 0 (same rule)
+        best = lane < kW ? red_v[lane] : -1.0;
+        bi = lane < kW ? red_i[lane] : mr;
+        for (int o = kW / 2; o > 0; o >>= 1) {
+          const double v2 = __shfl_xor(best, o);
+          const int i2 = __shfl_xor(bi, o);
+          if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
+        }
+        if (lane == 0) {
+          red_i[0] = bi;
+          pv[j0 + jj] = j0 + bi;
+          if (best == 0.0) flag[b] = 1;
+        }
       }
       __syncthreads();
       const int p = red_i[0];
@@ -190,115 +203,218 @@ __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA
       const int i = e % mr, c = e / mr;
       A[(j0 + i) + int64_t(j0 + c) * ldo] = Pn[i + c * mr];
     }
-    // the panel's interchanges on the other columns: a thread owns a column
-    // and applies them in order
+    // the panel's interchanges as one permutation of the rows they touch:
+    // position sw_row[k] receives the row that was at sw_src[k]; the panel's
+    // own rows come first (sw_row[r] = j0 + r for r < nb)
+    if (threadIdx.x == 0) {
+      int n = 0;
+      for (int r = 0; r < nb; ++r) {
+        sw_row[n] = j0 + r;
+        sw_src[n++] = j0 + r;
+      }
+      for (int r = 0; r < nb; ++r) {
+        const int q = pv[j0 + r];
+        bool seen = false;
+        for (int k = 0; k < n; ++k) seen = seen || sw_row[k] == q;
+        if (!seen) {
+          sw_row[n] = q;
+          sw_src[n++] = q;
+        }
+      }
+      for (int r = 0; r < nb; ++r) {
+        const int q = pv[j0 + r];
+        if (q == j0 + r) continue;
+        int kq = 0;
+        for (int k = 0; k < n; ++k)
+          if (sw_row[k] == q) kq = k;
+        const int t = sw_src[r];
+        sw_src[r] = sw_src[kq];
+        sw_src[kq] = t;
+      }
+      sw_n = n;
+    }
+    __syncthreads();
+    const int ns = sw_n;
+    // the other columns, a thread per column: gather the touched rows, scatter
+    // them to their new places; right of the panel also the block row of U,
+    // U12 = L11^-1 (P A)12, formed in registers and kept in LDS
     for (int c = threadIdx.x; c < m - nb; c += kEkWG) {
       const int col = c < j0 ? c : c + nb;
       double* ac = A + int64_t(col) * ldo;
-      for (int jj = 0; jj < nb; ++jj) {
-        const int p = pv[j0 + jj];
-        if (p != j0 + jj) {
-          const double t = ac[j0 + jj];
-          ac[j0 + jj] = ac[p];
-          ac[p] = t;
-        }
-      }
-      // block row of U: solve with the panel's unit lower triangle (columns right of the panel)
+      double v[2 * kP];
+#pragma unroll
+      for (int k = 0; k < 2 * kP; ++k)
+        if (k < ns) v[k] = ac[sw_src[k]];
+#pragma unroll
+      for (int k = 0; k < 2 * kP; ++k)
+        if (k < ns && k >= nb) ac[sw_row[k]] = v[k];
       if (col >= j1) {
-        for (int r = 1; r < nb; ++r) {
-          double s = ac[j0 + r];
-          for (int t = 0; t < r; ++t) s -= Pn[r + t * mr] * ac[j0 + t];
-          ac[j0 + r] = s;
+#pragma unroll
+        for (int r = 1; r < kP; ++r) {
+          if (r >= nb) break;
+          double sacc = v[r];
+#pragma unroll
+          for (int t = 0; t < r; ++t) sacc -= Pn[r + t * mr] * v[t];
+          v[r] = sacc;
         }
       }
+#pragma unroll
+      for (int r = 0; r < kP; ++r)
+        if (r < nb) {
+          ac[j0 + r] = v[r];
+          if (col >= j1) Us[r + (col - j1) * kP] = v[r];
+        }
     }
     __syncthreads();
-    // trailing update A22 -= L21 U12 (rows, columns j1 .. m - 1)
+    // trailing update A22 -= L21 U12 (rows, columns j1 .. m - 1) in tiles of
+    // 64 rows (lanes) x 16 columns dealt round-robin to the waves; a tile's
+    // 16 loads of A are issued together, its rows of L21 come from the panel
     const int m2 = m - j1;
-    for (int64_t e = threadIdx.x; e < int64_t(m2) * m2; e += kEkWG) {
-      const int i = int(e % m2), c = int(e / m2);
-      const double* uc = A + j0 + int64_t(j1 + c) * ldo;
-      double s = 0.0;
+    if (m2 > 0) {
+      constexpr int kTC = 16;
+      const int nch = (m2 + 63) / 64, ncg = (m2 + kTC - 1) / kTC;
+      for (int tile = wave; tile < nch * ncg; tile += kW) {
+        const int i = (tile % nch) * 64 + lane, cb = (tile / nch) * kTC;
+        double l[kP];
 #pragma unroll
-      for (int t = 0; t < kP; ++t)
-        if (t < nb) s += Pn[(nb + i) + t * mr] * uc[t];
-      A[(j1 + i) + int64_t(j1 + c) * ldo] -= s;
+        for (int t = 0; t < kP; ++t) l[t] = (i < m2 && t < nb) ? Pn[(nb + i) + t * mr] : 0.0;
+        double av[kTC];
+#pragma unroll
+        for (int k = 0; k < kTC; ++k)
+          av[k] = (i < m2 && cb + k < m2) ? A[(j1 + i) + int64_t(j1 + cb + k) * ldo] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kTC; ++k) {
+          if (cb + k >= m2) break;
+          const double* uc = Us + (cb + k) * kP;
+          double sacc = 0.0;
+#pragma unroll
+          for (int t = 0; t < kP; ++t)
+            if (t < nb) sacc += l[t] * uc[t];
+          if (i < m2) A[(j1 + i) + int64_t(j1 + cb + k) * ldo] = av[k] - sacc;
+        }
+      }
     }
     __syncthreads();
   }
 }
 
-// Columns c0 .. c0 + 15 (c0 = 16 blockIdx.x) of the inverse of matrix
-// b = blockIdx.y (order m = mA for b < J, else mB) from its LU factors
-// (k_ek_lu): X = P e_c, then L^-1, then
-// U^-1, in LDS; written to inv + b stride (ld ldi).  Rows are taken in
-// blocks of 16: the diagonal block by one thread per column, the rows below
-// (above) by the whole work-group.
+// Columns c0 .. c0 + kEkInvCols - 1 (c0 = kEkInvCols blockIdx.x) of the
+// inverse of matrix b = blockIdx.y (order m = mA for b < J, else mB) from its
+// LU factors (k_ek_lu): X = P e_c, then L^-1, then U^-1, in LDS; written to
+// inv + b stride (ld ldi).  Rows are taken in blocks of 16: the diagonal
+// block is staged in LDS and solved by one thread per column; the rows below
+// (above) it are updated by a thread per row, which loads its 16 entries of
+// the factor once and applies them to every column.  15 columns a work-group
+// keep X and the staged block within half a CU's LDS.
+constexpr int kEkInvCols = 15;
 __global__ void __launch_bounds__(256) k_ek_lu_inv(int J, int mA, int mB, const double* LU, int64_t ldo,
                                                    int64_t stride, const int32_t* piv, double* inv, int64_t ldi) {
-  constexpr int kC = 16;
+  constexpr int kC = kEkInvCols;
   __shared__ double X[kEkMax * kC];
+  __shared__ double Dg[16 * 16];               // the current diagonal block, ld 16
   const int b = blockIdx.y, c0 = blockIdx.x * kC;
   const int m = b < J ? mA : mB;
   const int nc = min(kC, m - c0);
   if (nc <= 0) return;
   const double* A = LU + int64_t(b) * stride;
   const int32_t* pv = piv + int64_t(b) * kEkMax;
-  for (int e = threadIdx.x; e < m * kC; e += 256) X[e] = (e % m == c0 + e / m) ? 1.0 : 0.0;
-  __syncthreads();
+  // X = P e_c: the interchanges move the unit entry of column c; its final
+  // row is tracked through them
+  __shared__ int s_pos[kC];
   if (threadIdx.x < nc) {
-    double* x = X + threadIdx.x * m;
+    int pos = c0 + threadIdx.x;
     for (int k = 0; k < m; ++k) {
       const int p = pv[k];
-      if (p != k) {
-        const double t = x[k];
-        x[k] = x[p];
-        x[p] = t;
-      }
+      if (pos == k) pos = p;
+      else if (pos == p) pos = k;
     }
+    s_pos[threadIdx.x] = pos;
   }
   __syncthreads();
+  for (int e = threadIdx.x; e < m * nc; e += 256) X[e] = (e % m == s_pos[e / m]) ? 1.0 : 0.0;
   // L y = x (unit lower), blocks of 16 rows top to bottom
   for (int r0 = 0; r0 < m; r0 += 16) {
     const int r1 = min(m, r0 + 16);
-    if (threadIdx.x < nc) {
-      double* x = X + threadIdx.x * m;
-      for (int r = r0 + 1; r < r1; ++r) {
-        double s = x[r];
-        for (int t = r0; t < r; ++t) s -= A[r + int64_t(t) * ldo] * x[t];
-        x[r] = s;
-      }
+    {
+      const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
+      if (r0 + i < r1 && r0 + j < r1) Dg[i + 16 * j] = A[(r0 + i) + int64_t(r0 + j) * ldo];
     }
     __syncthreads();
-    const int below = m - r1;
-    for (int e = threadIdx.x; e < below * nc; e += 256) {
-      const int i = r1 + e % below, c = e / below;
-      double* x = X + c * m;
-      double s = 0.0;
-      for (int t = r0; t < r1; ++t) s += A[i + int64_t(t) * ldo] * x[t];
-      x[i] -= s;
+    if (threadIdx.x < nc) {                    // the block's rows of this column in registers
+      double* x = X + threadIdx.x * m;
+      const int nr = r1 - r0;
+      double xr[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) xr[r] = r < nr ? x[r0 + r] : 0.0;
+#pragma unroll
+      for (int r = 1; r < 16; ++r) {
+        if (r >= nr) break;
+        double s = xr[r];
+#pragma unroll
+        for (int t = 0; t < r; ++t) s -= Dg[r + 16 * t] * xr[t];
+        xr[r] = s;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < nr) x[r0 + r] = xr[r];
+    }
+    __syncthreads();
+    for (int i = r1 + threadIdx.x; i < m; i += 256) {
+      double a[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) a[t] = r0 + t < r1 ? A[i + int64_t(r0 + t) * ldo] : 0.0;
+      for (int c = 0; c < nc; ++c) {
+        double* x = X + c * m;
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+          if (r0 + t < r1) s += a[t] * x[r0 + t];
+        x[i] -= s;
+      }
     }
     __syncthreads();
   }
   // U z = y, blocks of 16 rows bottom to top
   for (int r1 = m; r1 > 0; r1 -= 16) {
     const int r0 = max(0, r1 - 16);
-    if (threadIdx.x < nc) {
-      double* x = X + threadIdx.x * m;
-      for (int r = r1 - 1; r >= r0; --r) {
-        double s = x[r];
-        for (int t = r + 1; t < r1; ++t) s -= A[r + int64_t(t) * ldo] * x[t];
-        const double d = A[r + int64_t(r) * ldo];
-        x[r] = d != 0.0 ? s / d : 0.0;
-      }
+    {
+      const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
+      if (r0 + i < r1 && r0 + j < r1) Dg[i + 16 * j] = A[(r0 + i) + int64_t(r0 + j) * ldo];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < r0 * nc; e += 256) {
-      const int i = e % r0, c = e / r0;
-      double* x = X + c * m;
-      double s = 0.0;
-      for (int t = r0; t < r1; ++t) s += A[i + int64_t(t) * ldo] * x[t];
-      x[i] -= s;
+    if (threadIdx.x < nc) {                    // the block's rows of this column in registers
+      double* x = X + threadIdx.x * m;
+      const int nr = r1 - r0;
+      double xr[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) xr[r] = r < nr ? x[r0 + r] : 0.0;
+#pragma unroll
+      for (int r = 15; r >= 0; --r) {
+        if (r >= nr) continue;
+        double s = xr[r];
+#pragma unroll
+        for (int t = r + 1; t < 16; ++t)
+          if (t < nr) s -= Dg[r + 16 * t] * xr[t];
+        const double d = Dg[r + 16 * r];
+        xr[r] = d != 0.0 ? s / d : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < nr) x[r0 + r] = xr[r];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < r0; i += 256) {
+      double a[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) a[t] = r0 + t < r1 ? A[i + int64_t(r0 + t) * ldo] : 0.0;
+      for (int c = 0; c < nc; ++c) {
+        double* x = X + c * m;
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+          if (r0 + t < r1) s += a[t] * x[r0 + t];
+        x[i] -= s;
+      }
     }
     __syncthreads();
   }
