@@ -112,20 +112,21 @@ __global__ void k_ek_gemm_sum(int M, int N, const int32_t* ndev, int nsplit, con
 // into one gather and one scatter, are applied to the other columns; the block
 // row of U is solved with the panel's unit lower triangle in registers (a
 // thread per column) and kept in LDS; the trailing matrix takes the
-// rank-kEkPanel update with the panel's rows in registers (a wave per 64-row
-// chunk, lanes = rows, the block row of U read by broadcast).  m <= kEkMax.
+// rank-kEkPanel update on the FP64 matrix cores.  m <= kEkMax.
 __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA, int mB, const double* TB,
                                                  int64_t ldt, const double* shift, double* out, int64_t ldo,
                                                  int64_t stride, int32_t* piv, int32_t* flag) {
   constexpr int kP = kEkPanel;
   constexpr int kW = kEkWG / 64;
   // the panel (rows j0 .. m - 1, ld m - j0), then the block row of U right of
-  // it (kP x (m - j0 - kP), ld kP)
-  __shared__ double Sm[(2 * kEkMax - kP) * kP];
+  // it, transposed ((m - j0 - kP) x kP, ld m - j0 - kP + 1)
+  __shared__ double Sm[(2 * kEkMax - kP) * kP + kP];
+  __shared__ int s_pv[kP];                   // the panel's pivot rows
   __shared__ double red_v[kW];
   __shared__ int red_i[kW];
+  __shared__ double prow[kP];                // the pivot row of the current step
+  __shared__ int s_p;
   __shared__ int sw_row[2 * kP], sw_src[2 * kP];
-  __shared__ int sw_n;
   const int b = blockIdx.x;
   const int m = b < J ? mA : mB;
   const double* T = b < J ? TA : TB;
@@ -148,54 +149,84 @@ __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA
       Pn[i + c * mr] = A[(j0 + i) + int64_t(j0 + c) * ldo];
     }
     __syncthreads();
-    for (int jj = 0; jj < nb; ++jj) {
-      // pivot: the largest magnitude in panel column jj, rows jj .. mr - 1
-      // (ties to the lowest row), reduced within each wave, then over the waves
-      double best = -1.0;
-      int bi = jj;
-      for (int i = jj + threadIdx.x; i < mr; i += kEkWG) {
-        const double v = fabs(Pn[i + jj * mr]);
-        if (v > best) { best = v; bi = i; }
-      }
-      for (int o = 32; o > 0; o >>= 1) {
+    // pivot steps, two barriers each.  Candidates (largest magnitude in the
+    // step's column, ties to the lowest row) are reduced within each wave,
+    // then by wave 0, which also stages the pivot row; then a thread per row
+    // below the step forms its multiplier and updates its row (the thread of
+    // the pivot's row also carries out the interchange with row jj) and offers
+    // its entry of the next column as the next step's candidate.
+    auto wave_best = [&](double& best, int& bi, int width) {
+      for (int o = width / 2; o > 0; o >>= 1) {
         const double v2 = __shfl_xor(best, o);
         const int i2 = __shfl_xor(bi, o);
         if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
       }
+    };
+    {
+      double best = -1.0;
+      int bi = 0;
+      for (int i = threadIdx.x; i < mr; i += kEkWG) {
+        const double v = fabs(Pn[i]);
+        if (v > best) { best = v; bi = i; }
+      }
+      wave_best(best, bi, 64);
       if (lane == 0) {
         red_v[wave] = best;
         red_i[wave] = bi;
       }
-      __syncthreads();
-      if (wave == 0) {                          // the waves' candidates, reduced by wave 0 (same rule)
-        best = lane < kW ? red_v[lane] : -1.0;
-        bi = lane < kW ? red_i[lane] : mr;
-        for (int o = kW / 2; o > 0; o >>= 1) {
-          const double v2 = __shfl_xor(best, o);
-          const int i2 = __shfl_xor(bi, o);
-          if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
-        }
+    }
+    __syncthreads();
+    for (int jj = 0; jj < nb; ++jj) {
+      if (wave == 0) {
+        double best = lane < kW ? red_v[lane] : -1.0;
+        int bi = lane < kW ? red_i[lane] : mr;
+        wave_best(best, bi, kW);
+        const int p = __shfl(bi, 0);
+        if (lane < nb) prow[lane] = Pn[p + lane * mr];
         if (lane == 0) {
-          red_i[0] = bi;
-          pv[j0 + jj] = j0 + bi;
+          s_p = p;
+          s_pv[jj] = j0 + p;
+          pv[j0 + jj] = j0 + p;
           if (best == 0.0) flag[b] = 1;
         }
       }
       __syncthreads();
-      const int p = red_i[0];
-      if (p != jj && threadIdx.x < nb) {
-        const double t = Pn[jj + threadIdx.x * mr];
-        Pn[jj + threadIdx.x * mr] = Pn[p + threadIdx.x * mr];
-        Pn[p + threadIdx.x * mr] = t;
-      }
-      __syncthreads();
-      // a thread owns a row below the pivot: its multiplier, then its update
-      const double d = Pn[jj + jj * mr];
+      const int p = s_p;
+      const double d = prow[jj];
       const double inv = d != 0.0 ? 1.0 / d : 0.0;
+      double nbest = -1.0;
+      int nbi = jj + 1;
       for (int i = jj + 1 + threadIdx.x; i < mr; i += kEkWG) {
-        const double l = Pn[i + jj * mr] * inv;
-        Pn[i + jj * mr] = l;
-        for (int c = jj + 1; c < nb; ++c) Pn[i + c * mr] -= l * Pn[jj + c * mr];
+        double nv = 0.0;                         // this row's entry of column jj + 1 after the step
+        if (i == p) {
+          // row p takes the old row jj, updated; row jj takes the pivot row
+          const double l = Pn[jj + jj * mr] * inv;
+          for (int c = 0; c < jj; ++c) Pn[p + c * mr] = Pn[jj + c * mr];
+          Pn[p + jj * mr] = l;
+          for (int c = jj + 1; c < nb; ++c) {
+            const double x = Pn[jj + c * mr] - l * prow[c];
+            Pn[p + c * mr] = x;
+            if (c == jj + 1) nv = x;
+          }
+          for (int c = 0; c < nb; ++c) Pn[jj + c * mr] = prow[c];
+        } else {
+          const double l = Pn[i + jj * mr] * inv;
+          Pn[i + jj * mr] = l;
+          for (int c = jj + 1; c < nb; ++c) {
+            const double x = Pn[i + c * mr] - l * prow[c];
+            Pn[i + c * mr] = x;
+            if (c == jj + 1) nv = x;
+          }
+        }
+        if (jj + 1 < nb) {
+          const double v = fabs(nv);
+          if (v > nbest) { nbest = v; nbi = i; }
+        }
+      }
+      wave_best(nbest, nbi, 64);
+      if (lane == 0) {
+        red_v[wave] = nbest;
+        red_i[wave] = nbi;
       }
       __syncthreads();
     }
@@ -203,38 +234,44 @@ __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA
       const int i = e % mr, c = e / mr;
       A[(j0 + i) + int64_t(j0 + c) * ldo] = Pn[i + c * mr];
     }
-    // the panel's interchanges as one permutation of the rows they touch:
-    // position sw_row[k] receives the row that was at sw_src[k]; the panel's
-    // own rows come first (sw_row[r] = j0 + r for r < nb)
-    if (threadIdx.x == 0) {
-      int n = 0;
-      for (int r = 0; r < nb; ++r) {
-        sw_row[n] = j0 + r;
-        sw_src[n++] = j0 + r;
+    // the panel's interchanges as one permutation of the rows they touch,
+    // composed by wave 0 (a lane per row): position sw_row[k] receives the row
+    // that was at sw_src[k] (sw_row[k] < 0: unused); lanes 0 .. nb - 1 are the
+    // panel's own rows, lane nb + r the pivot row of step r when it lies below
+    // the panel and no earlier step chose it
+    if (wave == 0) {
+      auto slot_of = [&](int r) {                // the lane holding the pivot row of step r
+        const int q = s_pv[r];
+        if (q < j1) return q - j0;
+        int f = r;
+        for (int t = r - 1; t >= 0; --t)
+          if (s_pv[t] == q) f = t;
+        return nb + f;
+      };
+      int row = -1;
+      if (lane < nb) {
+        row = j0 + lane;
+      } else if (lane < nb + nb) {
+        const int r = lane - nb;
+        if (s_pv[r] >= j1 && slot_of(r) == lane) row = s_pv[r];
       }
+      int src = row;
       for (int r = 0; r < nb; ++r) {
-        const int q = pv[j0 + r];
-        bool seen = false;
-        for (int k = 0; k < n; ++k) seen = seen || sw_row[k] == q;
-        if (!seen) {
-          sw_row[n] = q;
-          sw_src[n++] = q;
+        const int la = r, lb = slot_of(r);
+        const int sa = __shfl(src, la), sb = __shfl(src, lb);
+        if (la != lb) {
+          if (lane == la) src = sb;
+          else if (lane == lb) src = sa;
         }
       }
-      for (int r = 0; r < nb; ++r) {
-        const int q = pv[j0 + r];
-        if (q == j0 + r) continue;
-        int kq = 0;
-        for (int k = 0; k < n; ++k)
-          if (sw_row[k] == q) kq = k;
-        const int t = sw_src[r];
-        sw_src[r] = sw_src[kq];
-        sw_src[kq] = t;
+      if (lane < 2 * kP) {
+        sw_row[lane] = row;
+        sw_src[lane] = src;
       }
-      sw_n = n;
     }
     __syncthreads();
-    const int ns = sw_n;
+    const int ns = 2 * kP;
+    const int m2 = m - j1, ldu = m2 + 1;
     // the other columns, a thread per column: gather the touched rows, scatter
     // them to their new places; right of the panel also the block row of U,
     // U12 = L11^-1 (P A)12, formed in registers and kept in LDS
@@ -244,10 +281,10 @@ __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA
       double v[2 * kP];
 #pragma unroll
       for (int k = 0; k < 2 * kP; ++k)
-        if (k < ns) v[k] = ac[sw_src[k]];
+        if (k < ns && sw_row[k] >= 0) v[k] = ac[sw_src[k]];
 #pragma unroll
       for (int k = 0; k < 2 * kP; ++k)
-        if (k < ns && k >= nb) ac[sw_row[k]] = v[k];
+        if (k < ns && k >= nb && sw_row[k] >= 0) ac[sw_row[k]] = v[k];
       if (col >= j1) {
 #pragma unroll
         for (int r = 1; r < kP; ++r) {
@@ -262,35 +299,49 @@ __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA
       for (int r = 0; r < kP; ++r)
         if (r < nb) {
           ac[j0 + r] = v[r];
-          if (col >= j1) Us[r + (col - j1) * kP] = v[r];
+          if (col >= j1) Us[(col - j1) + r * ldu] = v[r];
         }
     }
     __syncthreads();
-    // trailing update A22 -= L21 U12 (rows, columns j1 .. m - 1) in tiles of
-    // 64 rows (lanes) x 16 columns dealt round-robin to the waves; a tile's
-    // 16 loads of A are issued together, its rows of L21 come from the panel
-    const int m2 = m - j1;
+    // trailing update A22 -= L21 U12 (rows, columns j1 .. m - 1) on the FP64
+    // matrix cores, as its transpose U12^T L21^T in 16 x 16 tiles dealt
+    // round-robin to the waves: lane (li, lk) holds rows i0 + li of columns
+    // c0 + 4 v + lk of the tile, so each of its four loads and stores covers
+    // 16 contiguous rows of four columns
     if (m2 > 0) {
-      constexpr int kTC = 16;
-      const int nch = (m2 + 63) / 64, ncg = (m2 + kTC - 1) / kTC;
-      for (int tile = wave; tile < nch * ncg; tile += kW) {
-        const int i = (tile % nch) * 64 + lane, cb = (tile / nch) * kTC;
-        double l[kP];
+      const int li = lane & 15, lk = lane >> 4;
+      const int nt = (m2 + 15) / 16;
+      // two tiles a wave at a time: their eight loads are issued together
+      for (int t0 = wave; t0 < nt * nt; t0 += 2 * kW) {
+        double old[2][4];
+        int i0[2], c0[2];
 #pragma unroll
-        for (int t = 0; t < kP; ++t) l[t] = (i < m2 && t < nb) ? Pn[(nb + i) + t * mr] : 0.0;
-        double av[kTC];
+        for (int h = 0; h < 2; ++h) {
+          const int tile = t0 + h * kW;
+          i0[h] = tile < nt * nt ? (tile % nt) * 16 : m2;      // a missing tile is all out of range
+          c0[h] = tile < nt * nt ? (tile / nt) * 16 : m2;
 #pragma unroll
-        for (int k = 0; k < kTC; ++k)
-          av[k] = (i < m2 && cb + k < m2) ? A[(j1 + i) + int64_t(j1 + cb + k) * ldo] : 0.0;
+          for (int v = 0; v < 4; ++v) {
+            const int row = i0[h] + li, col = c0[h] + 4 * v + lk;
+            old[h][v] = (row < m2 && col < m2) ? A[(j1 + row) + int64_t(j1 + col) * ldo] : 0.0;
+          }
+        }
 #pragma unroll
-        for (int k = 0; k < kTC; ++k) {
-          if (cb + k >= m2) break;
-          const double* uc = Us + (cb + k) * kP;
-          double sacc = 0.0;
+        for (int h = 0; h < 2; ++h) {
+          const int row = i0[h] + li;
+          hfde::hfde_d4 acc{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int t = 0; t < kP; ++t)
-            if (t < nb) sacc += l[t] * uc[t];
-          if (i < m2) A[(j1 + i) + int64_t(j1 + cb + k) * ldo] = av[k] - sacc;
+          for (int s4 = 0; s4 < kP / 4; ++s4) {
+            const int k = 4 * s4 + lk;
+            const double a = (k < nb && c0[h] + li < m2) ? Us[(c0[h] + li) + k * ldu] : 0.0;
+            const double bv = (k < nb && row < m2) ? Pn[(nb + row) + k * mr] : 0.0;
+            acc = hfde::mfma64(a, bv, acc);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int col = c0[h] + 4 * v + lk;
+            if (row < m2 && col < m2) A[(j1 + row) + int64_t(j1 + col) * ldo] = old[h][v] - acc[v];
+          }
         }
       }
     }
