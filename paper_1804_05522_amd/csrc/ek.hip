@@ -155,12 +155,17 @@ __global__ void __launch_bounds__(kEkWG) k_ek_lu(int J, int mA, const double* TA
     // below the step forms its multiplier and updates its row (the thread of
     // the pivot's row also carries out the interchange with row jj) and offers
     // its entry of the next column as the next step's candidate.
+    // the wave's largest candidate and, among equal ones, the lowest lane's
+    // (lanes hold at most one row each, in increasing order, so that is the
+    // lowest row); lanes past `width` do not take part
     auto wave_best = [&](double& best, int& bi, int width) {
-      for (int o = width / 2; o > 0; o >>= 1) {
-        const double v2 = __shfl_xor(best, o);
-        const int i2 = __shfl_xor(bi, o);
-        if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
-      }
+      double mx = lane < width ? best : -1.0;
+      for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+      const unsigned long long hit = __ballot(lane < width && best == mx);
+      const int src = hit ? __ffsll((long long)hit) - 1 : 0;
+      bi = __shfl(bi, src);
+      best = hit ? mx : best;
+      best = __shfl(best, src);
     };
     {
       double best = -1.0;
